@@ -1,0 +1,402 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+library routines used as independent references (mpmath, scipy), brute force
+on tiny inputs, identities, and the values the paper prints.
+"""
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.stats as st
+
+import synth
+from oracle import data, evidence, gradients, grid, kernel, krylov, lens, psf, source
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([float(v) for v in line.split()])
+    return np.array(rows)
+
+
+# ---------------------------------------------------------------- grid (a1)
+
+def test_grid_index_brute_force():
+    for n, ss in [(3, 1), (3, 2), (4, 3), (5, 2)]:
+        M = n * ss
+        want = []
+        for fy in range(M):
+            for fx in range(M):
+                want.append((fy // ss) * n + (fx // ss))
+        assert np.array_equal(grid.coarse_of_fine(n, ss), np.array(want))
+
+
+def test_grid_coords_centred_and_spaced():
+    x, y = grid.fine_coords(4, 2, 0.05)
+    M, h = 8, 0.025
+    assert abs(x.mean()) < 1e-15 and abs(y.mean()) < 1e-15
+    assert np.allclose(np.diff(x.reshape(M, M), axis=1), h)
+    assert np.allclose(np.diff(y.reshape(M, M), axis=0), h)
+    # sub-pixel centres sit at ((s + 1/2)/ss - 1/2) pix inside each pixel
+    assert math.isclose(x[0], -(M - 1) / 2 * h)
+
+
+def test_block_mean_adjoint_and_constant():
+    rng = np.random.default_rng(1)
+    f, xv = rng.standard_normal(36), rng.standard_normal(9)
+    assert math.isclose(grid.block_mean(f, 3, 2) @ xv, f @ grid.block_mean_T(xv, 3, 2), rel_tol=1e-13)
+    assert np.allclose(grid.block_mean(np.full(36, 2.5), 3, 2), 2.5)
+
+
+# ---------------------------------------------------------------- lensing (a2)
+
+def test_hyp2f1_series_matches_mpmath():
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        slope = rng.uniform(1.5, 2.5)
+        qq = rng.uniform(0.1, 1.0)
+        ang = rng.uniform(-math.pi, math.pi)
+        z = -(1 - qq) / (1 + qq) * complex(math.cos(2 * ang), math.sin(2 * ang))
+        b, c = (slope - 1) / 2, (5 - slope) / 2
+        got = lens.hyp2f1_one(b, c, np.array([z]))[0]
+        want = complex(mpmath.hyp2f1(1, b, c, z))
+        assert abs(got - want) <= 1e-14 * abs(want)
+
+
+def test_sis_einstein_ring():
+    """Singular isothermal sphere: every point of |xi| = theta_E maps to the origin."""
+    theta_E = 0.6
+    t = np.linspace(0, 2 * np.pi, 64, endpoint=False)
+    px, py = lens.raytrace(theta_E * np.cos(t), theta_E * np.sin(t), (theta_E, 1.0, 0.3, 2.0, 0, 0, 0, 0))
+    assert np.max(np.hypot(px, py)) < 1e-14
+    # and |alpha| = theta_E everywhere (constant deflection magnitude)
+    ax, ay = lens.sple_deflection(np.array([0.1, 2.0]), np.array([-0.3, 1.0]), theta_E, 1.0, 0.3, 2.0, 0, 0)
+    assert np.allclose(np.hypot(ax, ay), theta_E, rtol=1e-15)
+
+
+def test_circular_power_law_mass_enclosed():
+    """q = 1: alpha = R <kappa>(R), the mean convergence inside R from the printed kappa."""
+    for slope in (1.7, 2.0, 2.3):
+        theta_E = 1.1
+        for R in (0.2, 0.9, 2.3):
+            kbar = 2.0 / R ** 2 * si.quad(
+                lambda r: (3 - slope) / 2 * (theta_E / r) ** (slope - 1) * r, 0, R, limit=200)[0]
+            ax, ay = lens.sple_deflection(np.array([R * 0.6]), np.array([R * 0.8]), theta_E, 1.0, 0.0, slope, 0, 0)
+            assert math.isclose(math.hypot(ax[0], ay[0]), R * kbar, rel_tol=1e-9)
+
+
+def test_sie_arctan_closed_form():
+    """slope = 2: 2F1(1, 1/2; 3/2; -w^2) = arctan(w)/w (A&S 15.1.4)."""
+    for q in (0.1, 0.6, 0.8, 0.95):
+        ang = np.linspace(-3, 3, 13)
+        z = -(1 - q) / (1 + q) * np.exp(2j * ang)
+        w = np.sqrt(-z + 0j)
+        want = np.arctan(w) / w
+        got = lens.hyp2f1_one(0.5, 1.5, z)
+        assert np.max(np.abs(got - want)) < 1e-14
+
+
+@pytest.mark.parametrize("slope,q,phi", [(2.2, 0.7, 0.4), (1.85, 0.6, 2.0), (2.0, 0.8, math.radians(30))])
+def test_poisson_and_curl(slope, q, phi):
+    """div alpha = 2 kappa and curl alpha = 0 (FP64 central differences): pins the
+    prefactor, exponent, 2F1 arguments and the rotation back to the sky frame."""
+    theta_E, x0, y0 = 1.1, 0.05, -0.1
+    rng = np.random.default_rng(3)
+    X = rng.uniform(-2, 2, 30)
+    Y = rng.uniform(-2, 2, 30)
+    h = 1e-5
+
+    def a(x, y):
+        return lens.sple_deflection(x, y, theta_E, q, phi, slope, x0, y0)
+
+    axp, _ = a(X + h, Y)
+    axm, _ = a(X - h, Y)
+    _, ayp = a(X, Y + h)
+    _, aym = a(X, Y - h)
+    _, ayxp = a(X + h, Y)
+    _, ayxm = a(X - h, Y)
+    axyp, _ = a(X, Y + h)
+    axym, _ = a(X, Y - h)
+    div = (axp - axm) / (2 * h) + (ayp - aym) / (2 * h)
+    curl = (ayxp - ayxm) / (2 * h) - (axyp - axym) / (2 * h)
+    kap = lens.convergence(X, Y, theta_E, q, phi, slope, x0, y0)
+    assert np.allclose(div / 2, kap, rtol=2e-8)
+    assert np.max(np.abs(curl)) < 1e-7
+
+
+def test_shear_is_linear_about_origin():
+    px, py = lens.raytrace(np.array([0.7]), np.array([-0.4]), (1e-12, 1.0, 0, 2.0, 5.0, 5.0, 0.03, -0.02))
+    # negligible SPLE (tiny theta_E far away), shear only
+    assert math.isclose(px[0], 0.7 - (0.03 * 0.7 - 0.02 * -0.4), rel_tol=1e-9)
+    assert math.isclose(py[0], -0.4 - (-0.02 * 0.7 - 0.03 * -0.4), rel_tol=1e-9)
+
+
+def test_raytrace_jacobian_identities():
+    lp = (1.1, 0.7, 0.4, 2.15, 0.05, -0.1, 0.03, -0.02)
+    X = np.array([0.3, -1.2, 1.7, 0.9])
+    Y = np.array([1.1, 0.4, -0.8, -1.5])
+    J = lens.raytrace_jacobian(X, Y, lp)
+    ax, ay = lens.sple_deflection(X, Y, *lp[:6])
+    # theta_E: alpha_SPLE scales as theta_E^(slope-1)
+    assert np.allclose(J[:, 0, 0], -(lp[3] - 1) / lp[0] * ax, rtol=1e-9)
+    assert np.allclose(J[:, 1, 0], -(lp[3] - 1) / lp[0] * ay, rtol=1e-9)
+    # lens centre: dp/dx0 + dp/dy0 traces give div alpha = 2 kappa
+    kap = lens.convergence(X, Y, *lp[:6])
+    assert np.allclose(J[:, 0, 4] + J[:, 1, 5], 2 * kap, rtol=1e-8)
+    # shear columns are exact
+    assert np.allclose(J[:, 0, 6], -X) and np.allclose(J[:, 1, 6], Y)
+    assert np.allclose(J[:, 0, 7], -Y) and np.allclose(J[:, 1, 7], -X)
+    # q, phi, slope against mpmath high-precision differentiation at one point
+    mpmath.mp.dps = 30
+
+    def p_mp(k, comp):
+        def f(t):
+            v = [mpmath.mpf(x) for x in lp]
+            v[k] = t
+            th, q, phi, s, x0, y0 = v[:6]
+            dx, dy = mpmath.mpf(X[0]) - x0, mpmath.mpf(Y[0]) - y0
+            xp = mpmath.cos(phi) * dx + mpmath.sin(phi) * dy
+            yp = -mpmath.sin(phi) * dx + mpmath.cos(phi) * dy
+            Rx, Ry = mpmath.sqrt(q) * xp, yp / mpmath.sqrt(q)
+            R = mpmath.sqrt(Rx ** 2 + Ry ** 2)
+            e = mpmath.mpc(Rx, Ry) / R
+            F = mpmath.hyp2f1(1, (s - 1) / 2, (5 - s) / 2, -(1 - q) / (1 + q) * e ** 2)
+            a = th * 2 * mpmath.sqrt(q) / (1 + q) * (th / R) ** (s - 2) * F * e
+            axs = mpmath.cos(phi) * a.real - mpmath.sin(phi) * a.imag
+            ays = mpmath.sin(phi) * a.real + mpmath.cos(phi) * a.imag
+            return -(axs if comp == 0 else ays)
+        return float(mpmath.diff(f, mpmath.mpf(lp[k])))
+
+    for k in (1, 2, 3):
+        for comp in (0, 1):
+            assert math.isclose(J[0, comp, k], p_mp(k, comp), rel_tol=1e-8, abs_tol=1e-11)
+
+
+# ---------------------------------------------------------------- source (a3)
+
+def test_sersic_bn_textbook():
+    for n, bn in _golden("sersic_bn.txt"):
+        assert math.isclose(source.sersic_bn(n), bn, rel_tol=2e-6)
+
+
+def test_sersic_half_light_and_gradient():
+    n, Re, peak = 1.5, 0.1, 0.6
+    tot = si.quad(lambda r: source.sersic(r, 0.0, peak, Re, n, 0, 0) * r, 0, 50 * Re, limit=400)[0]
+    half = si.quad(lambda r: source.sersic(r, 0.0, peak, Re, n, 0, 0) * r, 0, Re, limit=400)[0]
+    assert math.isclose(half, tot / 2, rel_tol=1e-8)
+    assert math.isclose(float(source.sersic(0.0, 0.0, peak, Re, n, 0, 0)), peak, rel_tol=1e-14)
+    px, py = np.array([0.03, -0.2]), np.array([0.05, 0.11])
+    g = source.sersic_grad(px, py, peak, Re, n, 0.01, -0.02)
+    h = 1e-6
+    fdx = (source.sersic(px + h, py, peak, Re, n, 0.01, -0.02) - source.sersic(px - h, py, peak, Re, n, 0.01, -0.02)) / (2 * h)
+    fdy = (source.sersic(px, py + h, peak, Re, n, 0.01, -0.02) - source.sersic(px, py - h, peak, Re, n, 0.01, -0.02)) / (2 * h)
+    assert np.allclose(g[:, 0], fdx, rtol=1e-7) and np.allclose(g[:, 1], fdy, rtol=1e-7)
+
+
+# ---------------------------------------------------------------- kernel (a5)
+
+def test_kernel_symmetric_psd_and_mvm():
+    rng = np.random.default_rng(4)
+    px, py = rng.uniform(-0.3, 0.3, 300), rng.uniform(-0.3, 0.3, 300)
+    K = kernel.rbf_matrix(px, py, 0.04, 0.3)
+    assert np.array_equal(K, K.T)
+    assert np.allclose(np.diag(K), 0.09, rtol=0, atol=0)
+    assert np.linalg.eigvalsh(K).min() >= -1e-12 * 0.09 * 300
+    V = rng.standard_normal((300, 5))
+    Y = kernel.kernel_mvm(px, py, V, 0.04, 0.3, block=37)
+    # brute force on one entry with a Python loop
+    i, c = 17, 3
+    s = sum(0.09 * math.exp(-((px[i] - px[j]) ** 2 + (py[i] - py[j]) ** 2) / (2 * 0.04 ** 2)) * V[j, c] for j in range(300))
+    assert math.isclose(Y[i, c], s, rel_tol=1e-12)
+    assert np.allclose(Y, K @ V, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- PSF / B (a4)
+
+def test_psf_taps_and_adjoint():
+    taps = psf.psf_taps(0.1, 0.025)
+    assert math.isclose(taps.sum(), 1.0, rel_tol=1e-15)
+    assert taps.size == 2 * math.ceil(4 * 0.1 / (2 * math.sqrt(2 * math.log(2))) / 0.025) + 1
+    rng = np.random.default_rng(5)
+    for n, ss in [(6, 1), (5, 2)]:
+        f = rng.standard_normal((n * ss) ** 2)
+        xv = rng.standard_normal(n * n)
+        lhs = psf.apply_B(f, n, ss, taps) @ xv
+        rhs = f @ psf.apply_BT(xv, n, ss, taps)
+        assert math.isclose(lhs, rhs, rel_tol=1e-13)
+
+
+def test_psf_brute_force_and_constant():
+    taps = psf.psf_taps(0.1, 0.05)
+    r = (taps.size - 1) // 2
+    rng = np.random.default_rng(6)
+    M = 9
+    img = rng.standard_normal((M, M))
+    out = psf.conv_same(img, taps)
+    for (y, x) in [(0, 0), (4, 4), (8, 2)]:
+        s = 0.0
+        for a in range(-r, r + 1):
+            for b in range(-r, r + 1):
+                if 0 <= y - a < M and 0 <= x - b < M:
+                    s += taps[a + r] * taps[b + r] * img[y - a, x - b]
+        assert math.isclose(out[y, x], s, rel_tol=1e-13)
+    const = psf.conv_same(np.ones((20, 20)), taps)
+    assert np.allclose(const[r:-r, r:-r], 1.0, rtol=1e-14)
+    # no PSF: B is the plain block mean
+    f = rng.standard_normal(36)
+    assert np.allclose(psf.apply_B(f, 3, 2, psf.psf_taps(0.0, 0.025)), grid.block_mean(f, 3, 2))
+
+
+# ---------------------------------------------------------------- evidence (a6-a8)
+
+def _tiny_problem(n=8, ss=2, fwhm=0.1, seed=0, cx=0.0, cy=0.0):
+    w = synth.workload(1)
+    P = evidence.Problem(n, ss, 0.05, w.lens.as_tuple(), (0.6, 0.1, 1.5, 0.02, -0.01), 0.04, 0.3, 0.02, fwhm,
+                         cx, cy)
+    d, _ = data.simulate(P, synth.noise_normals(n * n, 9, seed), gp_normals=synth.gp_normals(P.N, 9, seed))
+    return P, d
+
+
+def test_evidence_matches_scipy_mvn_logpdf():
+    """The sign reading of eq. gp-mll: ln p equals the Gaussian log-density of d."""
+    P, d = _tiny_problem()
+    out = evidence.solve_problem(P, d, want_mean=False)
+    A = out["A"]
+    want = st.multivariate_normal(mean=P.B(out["mu"]), cov=A).logpdf(d)
+    assert math.isclose(out["lnp"], want, rel_tol=1e-12)
+    assert math.isclose(out["logdet"], np.linalg.slogdet(A)[1], rel_tol=1e-12)
+    # A built blockwise equals the dense B K B^T + sigma^2 I
+    Bd = psf.B_matrix(P.n, P.ss, P.taps())
+    Kd = kernel.rbf_matrix(out["px"], out["py"], P.ell, P.amp)
+    assert np.allclose(A, Bd @ Kd @ Bd.T + P.sigma ** 2 * np.eye(P.n_pix), rtol=1e-12, atol=1e-15)
+
+
+def test_sherman_morrison_block_constant():
+    """App. D.1: clumps of Nc perfectly correlated points, K block = alpha^2 u u^T, B = I.
+    (S0 + alpha^2 u u^T)^{-1} = sigma^-2 [I - alpha^2/(sigma^2 + Nc alpha^2) u u^T]."""
+    Nc, nb, a, s = 5, 4, 0.3, 0.02
+    K = np.kron(np.eye(nb), a * a * np.ones((Nc, Nc)))
+    A = K + s * s * np.eye(Nc * nb)
+    d = np.random.default_rng(7).standard_normal(Nc * nb)
+    ev = evidence.exact_evidence(A, d)
+    quad_cf = 0.0
+    for b in range(nb):
+        db = d[b * Nc:(b + 1) * Nc]
+        quad_cf += (db @ db - a * a / (s * s + Nc * a * a) * db.sum() ** 2) / (s * s)
+    logdet_cf = nb * ((Nc - 1) * math.log(s * s) + math.log(s * s + Nc * a * a))
+    assert math.isclose(ev["quad"], quad_cf, rel_tol=1e-12)
+    assert math.isclose(ev["logdet"], logdet_cf, rel_tol=1e-12)
+
+
+def test_vi_objective_forms_and_golden_variance():
+    """App. D.1: the simplified loss equals quad + ln|Omega^2| - ln|Sigma_y| + N ln sigma^2;
+    the variance limit reproduces the theory lines printed in Fig. vigp."""
+    assert math.isclose(evidence.vi_objective(123.4, 1000, 0.3, 0.02),
+                        evidence.vi_objective_full(123.4, 1000, 0.3, 0.02), rel_tol=1e-13)
+    for a1, a2, s, want in _golden("vigp_variance.txt"):
+        got = math.sqrt(evidence.diag_variance_limit([a1, a2], s).sum())
+        assert abs(got - want) < 5e-5
+
+
+def test_posterior_mean_interpolation_limit():
+    """B = I and sigma -> 0: the posterior mean interpolates the data."""
+    P, d = _tiny_problem(n=6, ss=1, fwhm=0.0)
+    P.sigma = 1e-5
+    out = evidence.solve_problem(P, d)
+    assert np.allclose(out["fhat"], d, atol=1e-6)
+
+
+# ---------------------------------------------------------------- Krylov (a6, a7)
+
+def _spd(n=40, seed=8):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-0.2, 0.2, (2, n))
+    return kernel.rbf_matrix(p[0], p[1], 0.1, 1.0) + 0.05 * np.eye(n)
+
+
+def test_cg_equals_direct_solve():
+    A = _spd()
+    b = np.random.default_rng(9).standard_normal((40, 3))
+    res = krylov.cg(lambda X: A @ X, b, tol=1e-12, max_iter=500)
+    assert np.allclose(res["X"], np.linalg.solve(A, b), rtol=1e-9, atol=1e-10)
+    assert np.all(res["relres"] <= 1e-12)
+
+
+def test_cg_tridiagonal_equals_explicit_lanczos():
+    A = _spd()
+    z = synth.rademacher(40, 1, 0)[:, 0]
+    m = 12
+    res = krylov.cg(lambda X: A @ X, z, tol=0.0, fixed_iters=m, n_lanczos=m)
+    d1, o1 = krylov.cg_tridiagonal(res["alphas"][0], res["betas"][0], m)
+    d2, o2 = krylov.lanczos(lambda X: A @ X, z, m)
+    assert np.allclose(d1, d2, rtol=1e-10) and np.allclose(o1, np.abs(o2), rtol=1e-10)
+
+
+def test_slq_all_unit_probes_is_exact():
+    A = _spd(n=30)
+    n = 30
+    E = np.eye(n)
+    res = krylov.cg(lambda X: A @ X, E, tol=0.0, fixed_iters=n, n_lanczos=n)
+    est, _, _ = krylov.slq_logdet(res["alphas"], res["betas"], res["iters"], res["bnorm2"], n, scale=1.0)
+    assert math.isclose(est, np.linalg.slogdet(A)[1], rel_tol=1e-10)
+
+
+def test_slq_rademacher_within_stderr():
+    A = _spd(n=200, seed=10)
+    Z = synth.rademacher(200, 64, 1)
+    res = krylov.cg(lambda X: A @ X, Z, tol=1e-10, max_iter=400, n_lanczos=60)
+    est, se, _ = krylov.slq_logdet(res["alphas"], res["betas"], res["iters"], res["bnorm2"], 60)
+    exact = np.linalg.slogdet(A)[1]
+    assert abs(est - exact) < 4 * se
+    # predicted standard error from the exact off-diagonal of ln A
+    w, V = np.linalg.eigh(A)
+    lnA = (V * np.log(w)) @ V.T
+    pred = math.sqrt(2 * (np.sum(lnA ** 2) - np.sum(np.diag(lnA) ** 2)) / 64)
+    assert 0.6 * pred < se < 1.6 * pred
+
+
+# ---------------------------------------------------------------- gradients (a10)
+
+def test_gradients_analytic_vs_finite_differences():
+    """A crop on the Einstein ring (away from the lens centre, where the central
+    differences of both the stencil and the evidence stay accurate). The step
+    h = 1e-4 leaves a truncation error of order (h/ell)^2 ~ 1e-5 in the ell entry."""
+    P, d = _tiny_problem(n=6, ss=2, cx=0.9, cy=0.5)
+    an = gradients.analytic_gradient(P, d)
+    fl, fv = gradients.fd_gradient(P, d, h=1e-4)
+    for g_an, g_fd in ((an["grad_lnp"], fl), (an["grad_vi"], fv)):
+        scale = np.maximum(np.abs(g_fd), 1e-3 * np.max(np.abs(g_fd)))
+        assert np.max(np.abs(g_an - g_fd) / scale) < 2e-5, (g_an, g_fd)
+
+
+def test_amplitude_gradient_identity():
+    """alpha d ln p/d alpha = u^T B K B^T u - tr(A^{-1} B K B^T) (K is proportional to alpha^2)."""
+    P, d = _tiny_problem(n=5, ss=2)
+    an = gradients.analytic_gradient(P, d)
+    out = evidence.solve_problem(P, d, want_mean=False)
+    BKBt = out["A"] - P.sigma ** 2 * np.eye(P.n_pix)
+    u = out["u"]
+    want = u @ BKBt @ u - np.trace(np.linalg.solve(out["A"], BKBt))
+    assert math.isclose(P.amp * an["grad_lnp"][11], want, rel_tol=1e-9)
+
+
+# ---------------------------------------------------------------- data
+
+def test_rff_draw_covariance_is_rbf():
+    """Empirical covariance of many random-Fourier-feature draws approaches K."""
+    px, py = np.array([0.0, 0.02, 0.05]), np.array([0.0, 0.01, -0.03])
+    draws = []
+    for k in range(3000):
+        om, ph, w = synth.rff_draws(512, 0, sub=k)
+        draws.append(data.gp_draw_rff(px, py, 0.04, 0.3, om, ph, w))
+    cov = np.cov(np.array(draws).T)
+    assert np.allclose(cov, kernel.rbf_matrix(px, py, 0.04, 0.3), atol=0.08 * 0.09)
