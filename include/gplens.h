@@ -1,0 +1,216 @@
+/*
+ * gplens: GPU library for the Gaussian-process evidence of a lensed source.
+ *
+ * Karchev, Coogan & Weniger (2021), "Strong-lensing source reconstruction with
+ * variationally optimised Gaussian processes". Supersampled image-plane pixels
+ * are ray-traced through an SPLE lens with external shear (Sec. 2.1, 2.2); a
+ * Gaussian-process source with an RBF kernel (Sec. 3.1, eq. "grbf") is observed
+ * through a PSF and local averaging (Sec. 2, Sec. 4.1) with i.i.d. noise. The
+ * library evaluates the marginal likelihood (Sec. 3.1, eq. "gp-mll") with
+ * matrix-free kernel products, conjugate gradients and stochastic Lanczos
+ * quadrature, the posterior mean (Sec. 3.7, eq. "gp-exact-mean"), the
+ * variational objective of App. D.1 (eq. "hyper-loss"), and their gradients.
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller. The library never
+ *    keeps them after a call returns and never frees them.
+ *  - Parameter structs are HOST pointers, read during the call.
+ *  - Work is enqueued on `stream` (0 = the null stream). Calls are asynchronous
+ *    unless their comment says the host waits; none synchronises the device.
+ *  - Scratch memory is passed in as (ws, ws_bytes); the matching
+ *    gpl_*_workspace() call gives the size needed. ws must be 256-byte aligned.
+ *    The library allocates no device memory.
+ *  - Points: structure-of-arrays float px[n], py[n] in arcsec, any n >= 1.
+ *  - Blocks of vectors: column-major float with leading dimension ld >= rows.
+ *  - Return value: GPL_OK or a negative error code; gpl_strerror() names it and
+ *    gpl_last_error() gives the detail of the last failure on this thread.
+ *    Invalid arguments are rejected before anything is enqueued.
+ */
+#ifndef GPLENS_H
+#define GPLENS_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPL_OK 0
+#define GPL_EINVAL (-1)       /* bad size, leading dimension, NULL or parameter */
+#define GPL_EWORKSPACE (-2)   /* workspace missing, misaligned or too small */
+#define GPL_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define GPL_EUNSUPPORTED (-4) /* requested precision/kind is not available */
+
+/* Arithmetic of the kernel-matrix product. */
+#define GPL_PREC_FP32 0  /* exp tile FP32, tile x RHS product FP32 (VALU or FP32 MFMA) */
+#define GPL_PREC_F16X3 1 /* exp tile FP32, product as FP16 hi/lo split on MFMA (3 terms), FP32 accumulate */
+
+/* Per-column CG status. */
+#define GPL_CG_CONVERGED 0
+#define GPL_CG_MAXITER 1
+#define GPL_CG_BREAKDOWN 2 /* p^T A p <= 0 */
+#define GPL_CG_NONFINITE 3
+
+/* Image grid: n x n pixels of side pix_scale (arcsec), each split into ss x ss
+ * sub-pixels; the image centre sits at (cx, cy). Fine point j = fy*M + fx,
+ * M = n*ss, has coordinates (cx + (fx - (M-1)/2) h, cy + (fy - (M-1)/2) h),
+ * h = pix_scale/ss, and lies in image pixel (fy/ss)*n + fx/ss (Sec. 2 pixel
+ * centres; Sec. 4.1 supersampling and local averaging). */
+typedef struct {
+  int n;
+  int ss;
+  double pix_scale;
+  double cx, cy;
+} gpl_grid;
+
+/* SPLE + external shear (Sec. 2.2): Einstein radius, axis ratio q in (0,1],
+ * position angle phi (rad), power-law slope in (1,3), centre (x0, y0), shear. */
+typedef struct {
+  double theta_E, q, phi, slope, x0, y0, gamma1, gamma2;
+} gpl_lens;
+
+/* Circular Sersic mean function mu = I_e exp(-b_n ((r/R_e)^(1/n) - 1)),
+ * r = |p - (xs, ys)| (mean function of Sec. 3.1, footnote). */
+typedef struct {
+  double I_e, R_e, n_sersic, b_n, xs, ys;
+} gpl_source;
+
+/* RBF kernel k = amplitude^2 exp(-|x1-x2|^2 / (2 lengthscale^2)) (eq. "grbf",
+ * isotropic Sigma = lengthscale^2 I). kind must be 0. */
+typedef struct {
+  int kind;
+  double lengthscale, amplitude;
+} gpl_kernel;
+
+/* Gaussian PSF on the fine grid: FWHM in arcsec (0 = no PSF), taps radius in
+ * fine pixels (0 = ceil(4 sigma / h)); 1-D taps normalised to unit sum, applied
+ * separably with zero padding. radius <= GPL_PSF_MAX_RADIUS. */
+typedef struct {
+  double fwhm;
+  int radius;
+} gpl_psf;
+#define GPL_PSF_MAX_RADIUS 24
+
+/* One reconstruction: grid, kernel, PSF, noise and the ray-traced points
+ * (device px, py of length (n*ss)^2). */
+typedef struct {
+  gpl_grid grid;
+  gpl_kernel kernel;
+  gpl_psf psf;
+  double noise_sigma;
+  const float* px;
+  const float* py;
+} gpl_problem;
+
+const char* gpl_strerror(int code);
+const char* gpl_last_error(void);
+int gpl_version(void);
+
+/* Half-light Sersic constant: root b of P(2n, b) = 1/2 (host, FP64). */
+double gpl_sersic_bn(double n_sersic);
+
+/* ---------------------------------------------------------------- forward */
+
+/* Fine-grid coordinates and fine->pixel index map (grid convention above).
+ * Outputs of length (n*ss)^2; any of the three may be NULL. */
+int gpl_grid_map(const gpl_grid* grid, float* xi_x, float* xi_y, int* pixel_of_fine, hipStream_t stream);
+
+/* Ray tracing p = xi - alpha_SPLE(xi) - Gamma xi (Sec. 2.1 eq. "lens", Sec. 2.2
+ * eq. "dispsple" and the shear term) for every fine point of the grid. 2F1 is
+ * summed from its series; alpha_SPLE is rotated back to the sky frame by -phi;
+ * R is floored at 1e-9 arcsec. Writes px, py (length (n*ss)^2). */
+int gpl_lens_raytrace(const gpl_grid* grid, const gpl_lens* lens, float* px, float* py, hipStream_t stream);
+
+/* Sersic mean at n points: mu[i] = mu(px[i], py[i]). */
+int gpl_sersic_eval(const gpl_source* src, int n, const float* px, const float* py, float* mu, hipStream_t stream);
+
+/* Observation operator B = D o P and its adjoint, on nrhs columns.
+ * adjoint = 0: in is fine (N rows, ld_in >= N), out = alpha * B in + beta * out
+ *             with out image pixels (n*n rows, ld_out >= n*n).
+ * adjoint = 1: in is image pixels, out = alpha * B^T in + beta * out (fine).
+ * B^T = P^T D^T: D^T replicates a pixel value / ss^2 to its sub-pixels.
+ * in and out must not overlap. */
+int gpl_psf_conv(const gpl_grid* grid, const gpl_psf* psf, int nrhs, const float* in, int ld_in, float* out,
+                 int ld_out, float alpha, float beta, int adjoint, hipStream_t stream);
+
+/* Matrix-free kernel product Y = K V + beta * Y, K_ij = k(p_i, p_j) (eq. "grbf"),
+ * over n points, nrhs columns. K is never stored: tiles are formed in registers.
+ * prec = GPL_PREC_FP32 or GPL_PREC_F16X3. beta is 0 (overwrite) or any float.
+ * V and Y must not overlap. */
+size_t gpl_gp_kernel_mvm_workspace(int n, int nrhs, int prec);
+int gpl_gp_kernel_mvm(const gpl_kernel* kern, int n, const float* px, const float* py, int nrhs, const float* V,
+                      int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Y = A X with A = B K B^T + noise_sigma^2 I (image pixels, nrhs columns). */
+size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int prec);
+int gpl_apply_A(const gpl_problem* prob, int nrhs, const float* X, int ldx, float* Y, int ldy, int prec, void* ws,
+                size_t ws_bytes, hipStream_t stream);
+
+/* Conjugate gradients on A X = Bm, one independent recurrence per column
+ * (x_0 = 0), all columns sharing each product with A. FP32 vectors; dot
+ * products, alpha/beta recurrences and the recorded coefficients in FP64.
+ * Column c stops when |r|/|b| <= tol (recursive residual) or, if
+ * fixed_iters > 0, after exactly fixed_iters steps; max_iter caps the count.
+ * Outputs (device): X (n*n x nrhs, ld ldx), lanczos_ab [nrhs][n_lanczos][2]
+ * (alpha_k, beta_k for the first n_lanczos steps; 0 beyond a column's count),
+ * bnorm2[nrhs] = |b_c|^2, iters[nrhs], relres[nrhs], status[nrhs].
+ * The host waits (on events, not the device) until every column has stopped;
+ * it checks progress every `check_every` iterations (<= 0: 8). */
+size_t gpl_cg_solve_workspace(const gpl_problem* prob, int nrhs, int prec);
+int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, int ldb, float* X, int ldx, double tol,
+                 int max_iter, int fixed_iters, int n_lanczos, double* lanczos_ab, double* bnorm2, int* iters,
+                 double* relres, int* status, int prec, int check_every, void* ws, size_t ws_bytes,
+                 hipStream_t stream);
+
+/* Stochastic Lanczos quadrature of ln|A| from CG coefficients. Probe j uses the
+ * first k_j = min(iters[j], n_lanczos) steps: the tridiagonal
+ * T_kk = 1/a_k + b_{k-1}/a_{k-1}, T_{k,k+1} = sqrt(b_k)/a_k, eigen-decomposed
+ * in FP64 (implicit QL); contrib[j] = bnorm2[j] * sum_i tau_i^2 ln theta_i.
+ * logdet = scale * sum_j contrib[j] (scale 1/nprobe for Hutchinson probes,
+ * 1 for all unit vectors); stderr = scale * sqrt(nprobe) * sd(contrib).
+ * lanczos_ab, iters, bnorm2 as written by gpl_cg_solve (probe columns only).
+ * Outputs (device): contrib[nprobe], logdet[1], stderr[1]. A probe whose
+ * tridiagonal has a non-positive Ritz value contributes NaN. */
+size_t gpl_lanczos_logdet_workspace(int nprobe, int n_lanczos);
+int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, const int* iters, const double* bnorm2,
+                       double scale, double* contrib, double* logdet, double* stderr_out, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* Evidence scalars (Sec. 3.1 eq. "gp-mll" with the sign reading
+ * -2 ln p = r^T A^{-1} r + ln|2 pi A|; App. D.1 eq. "hyper-loss"):
+ * out[0] = quad = r . u, out[1] = ln p = -(quad + logdet + n_pix ln 2 pi)/2,
+ * out[2] = L_VI = quad + n_points ln(amplitude^2 + noise_sigma^2).
+ * r, u of length n_pix (device), logdet device scalar. */
+int gpl_evidence_scalars(int n_pix, int n_points, const float* r, const float* u, const double* logdet,
+                         double amplitude, double noise_sigma, double* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------- backward */
+
+/* Gradient of F = sum_c w[c] a_c^T K b_c (a_c, b_c columns of A and Bv, n rows)
+ * with respect to the points, the lengthscale and the amplitude, kernel tiles
+ * recomputed: gpx[i] += dF/dpx_i, gpy[i] += dF/dpy_i (FP32, accumulated),
+ * g_hyp[0] = dF/d lengthscale, g_hyp[1] = dF/d amplitude (FP64, overwritten).
+ * w is a HOST array of npairs weights. */
+size_t gpl_gp_kernel_mvm_backward_workspace(int n, int npairs);
+int gpl_gp_kernel_mvm_backward(const gpl_kernel* kern, int n, const float* px, const float* py, int npairs,
+                               const float* A, int lda, const float* Bv, int ldb, const double* w, float* gpx,
+                               float* gpy, double* g_hyp, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of ray tracing: g_lens[k] = sum_i (dp_i/dtheta_k) . (gpx_i, gpy_i) for
+ * theta = (theta_E, q, phi, slope, x0, y0, gamma1, gamma2) (FP64, overwritten).
+ * Per-point Jacobians come from forward-mode derivatives through the series. */
+size_t gpl_lens_raytrace_backward_workspace(const gpl_grid* grid);
+int gpl_lens_raytrace_backward(const gpl_grid* grid, const gpl_lens* lens, const float* gpx, const float* gpy,
+                               double* g_lens, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of the Sersic mean: gpx[i] += gmu[i] dmu_i/dpx, gpy[i] += gmu[i] dmu_i/dpy,
+ * g_src[0..1] = d/d(xs, ys) of sum_i gmu[i] mu_i (FP64, overwritten). */
+size_t gpl_sersic_backward_workspace(int n);
+int gpl_sersic_backward(const gpl_source* src, int n, const float* px, const float* py, const float* gmu, float* gpx,
+                        float* gpy, double* g_src, void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPLENS_H */

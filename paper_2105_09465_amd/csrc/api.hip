@@ -1,0 +1,94 @@
+// Error reporting, version, host-side helpers and the evidence scalars.
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace gpl {
+
+static thread_local char g_last_error[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+
+const char* last_error() { return g_last_error; }
+
+// Regularised lower incomplete gamma P(a, x) from its power series
+// e^{-x} x^a / Gamma(a+1) * sum_k x^k / ((a+1)...(a+k)).
+static double inc_gamma_p(double a, double x) {
+  if (x <= 0) return 0.0;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 10000; ++k) {
+    term *= x / (a + k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return std::exp(a * std::log(x) - x - std::lgamma(a + 1.0)) * sum;
+}
+
+// Evidence scalars: quad = r.u, ln p and the App. D.1 loss.
+__global__ void evidence_scalars_kernel(int n_pix, int n_points, const float* r, const float* u, const double* logdet,
+                                        double amp, double sigma, double* out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n_pix; i += blockDim.x) s += (double)r[i] * (double)u[i];
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) {
+    const double ln2pi = 1.8378770664093454835606594728112;
+    out[0] = s;
+    out[1] = -0.5 * (s + *logdet + n_pix * ln2pi);
+    out[2] = s + n_points * log(amp * amp + sigma * sigma);
+  }
+}
+
+}  // namespace gpl
+
+using namespace gpl;
+
+extern "C" const char* gpl_strerror(int code) {
+  switch (code) {
+    case GPL_OK: return "ok";
+    case GPL_EINVAL: return "invalid argument";
+    case GPL_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case GPL_EHIP: return "HIP runtime error";
+    case GPL_EUNSUPPORTED: return "unsupported precision or kind";
+    default: return "unknown error";
+  }
+}
+
+extern "C" const char* gpl_last_error(void) { return last_error(); }
+
+extern "C" int gpl_version(void) { return 100; }
+
+extern "C" double gpl_sersic_bn(double n) {
+  if (!(n > 0) || !std::isfinite(n)) return NAN;
+  const double a = 2.0 * n;
+  double x = a - 1.0 / 3.0 > 0.05 ? a - 1.0 / 3.0 : 0.05;  // the median of Gamma(a, 1) is close to a - 1/3
+  for (int it = 0; it < 100; ++it) {
+    const double f = inc_gamma_p(a, x) - 0.5;
+    const double fp = std::exp((a - 1.0) * std::log(x) - x - std::lgamma(a));  // density of Gamma(a, 1)
+    double step = f / fp;
+    double xn = x - step;
+    if (xn <= 0) xn = 0.5 * x;
+    if (std::fabs(xn - x) <= 1e-15 * x) {
+      x = xn;
+      break;
+    }
+    x = xn;
+  }
+  return x;
+}
+
+extern "C" int gpl_evidence_scalars(int n_pix, int n_points, const float* r, const float* u, const double* logdet,
+                                    double amplitude, double noise_sigma, double* out, hipStream_t stream) {
+  GPL_REQUIRE(n_pix >= 1 && n_points >= 1, "sizes must be >= 1");
+  GPL_REQUIRE(r && u && logdet && out, "NULL argument");
+  hipLaunchKernelGGL(evidence_scalars_kernel, dim3(1), dim3(256), 0, stream, n_pix, n_points, r, u, logdet, amplitude,
+                     noise_sigma, out);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}

@@ -1,0 +1,419 @@
+// Conjugate gradients on A X = B with A = B_op K B_op^T + sigma^2 I, one
+// independent recurrence per right-hand-side column, all columns sharing each
+// application of A (the evidence of Sec. 3.1, eq. "gp-mll", evaluated with CG
+// as discussed in Sec. 3.3). Vectors are FP32; every dot product, the alpha and
+// beta recurrences and the recorded Lanczos coefficients are FP64.
+//
+// One iteration is five launches on the caller's stream:
+//   T1 = B_op^T P  ->  T2 = K T1  ->  AP = B_op T2 + sigma^2 P  (+ p.Ap partials)
+//   -> update1 (alpha; X += alpha P; R -= alpha AP; r.r partials)
+//   -> update2 (beta; P = R + beta P; bookkeeping).
+// Per-column state is double-buffered by iteration parity so that every block
+// of a kernel reads the same old values. Kernels return at once when no column
+// is active. The host enqueues iterations in chunks, keeps one chunk in flight
+// ahead, and after each chunk reads the number of active columns from a small
+// coherent host buffer written by a snapshot kernel (waiting on an event, never
+// synchronising the device).
+#include <cmath>
+#include <mutex>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace gpl {
+
+struct ColState {
+  double rr;     // r.r of the current residual
+  double alpha;  // alpha of the step that produced this state
+  int active;
+  int iters;
+  int status;
+  int bad;  // set by update1 when p.Ap <= 0 or non-finite
+};
+
+struct CgBuffers {
+  float *R, *P, *AP, *T1, *T2;
+  int ldv, ldf;
+  void* mvm_ws;
+  size_t mvm_ws_bytes;
+  double *pap_part, *rr_part;
+  int ntiles, nb_upd;
+  ColState* st[2];
+  double* bb;
+  int* n_active;  // [2]
+};
+
+template <class C>
+static void carve_cg(C& c, int npix, int N, int nrhs, int prec, CgBuffers* b, size_t* mvm_bytes_out, int ss, int n) {
+  const int ldv = round_up(npix, 64), ldf = round_up(N, 64);
+  const size_t mvm_bytes = mvm_workspace(N, nrhs, prec);
+  const int ntiles = psf_forward_tiles(n, ss), nb_upd = cdiv(npix, 256);
+  float* R = c.template take<float>((size_t)ldv * nrhs);
+  float* P = c.template take<float>((size_t)ldv * nrhs);
+  float* AP = c.template take<float>((size_t)ldv * nrhs);
+  float* T1 = c.template take<float>((size_t)ldf * nrhs);
+  float* T2 = c.template take<float>((size_t)ldf * nrhs);
+  char* mws = c.template take<char>(mvm_bytes);
+  double* pap = c.template take<double>((size_t)ntiles * nrhs);
+  double* rrp = c.template take<double>((size_t)nb_upd * nrhs);
+  ColState* s0 = c.template take<ColState>(nrhs);
+  ColState* s1 = c.template take<ColState>(nrhs);
+  double* bb = c.template take<double>(nrhs);
+  int* na = c.template take<int>(2);
+  if (b) {
+    *b = CgBuffers{R, P, AP, T1, T2, ldv, ldf, mws, mvm_bytes, pap, rrp, ntiles, nb_upd, {s0, s1}, bb, na};
+  }
+  if (mvm_bytes_out) *mvm_bytes_out = mvm_bytes;
+}
+
+// R = P = B, X = 0, partial |b|^2.
+__global__ __launch_bounds__(256) void cg_init_kernel(int npix, const float* __restrict__ Bm, int ldb, float* X,
+                                                      int ldx, float* R, float* P, int ldv, double* part, int nb) {
+  __shared__ double red[4];
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < npix) {
+    const float b = Bm[(size_t)c * ldb + i];
+    R[(size_t)c * ldv + i] = b;
+    P[(size_t)c * ldv + i] = b;
+    X[(size_t)c * ldx + i] = 0.f;
+    s = (double)b * b;
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) part[(size_t)c * nb + blockIdx.x] = s;
+}
+
+__global__ void cg_init_state_kernel(int nrhs, const double* part, int nb, ColState* st0, ColState* st1, double* bb,
+                                     int* n_active, int limit) {
+  // one thread per column; thread 0 of the block also writes the active count
+  __shared__ int count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < nrhs; c += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)c * nb + b];
+    ColState z;
+    z.rr = s;
+    z.alpha = 0.0;
+    z.iters = 0;
+    z.bad = 0;
+    if (!isfinite(s)) {
+      z.status = GPL_CG_NONFINITE;
+      z.active = 0;
+    } else if (s == 0.0 || limit == 0) {
+      z.status = s == 0.0 ? GPL_CG_CONVERGED : GPL_CG_MAXITER;
+      z.active = 0;
+    } else {
+      z.status = GPL_CG_CONVERGED;
+      z.active = 1;
+    }
+    st0[c] = z;
+    st1[c] = z;
+    bb[c] = s;
+    if (z.active) atomicAdd(&count, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    n_active[0] = count;
+    n_active[1] = count;
+  }
+}
+
+// alpha = rr / pAp (redundantly in every block, fixed order), X += alpha P,
+// R -= alpha AP, partial r.r of the new residual.
+__global__ __launch_bounds__(256) void cg_update1_kernel(int npix, float* X, int ldx, float* R, const float* P,
+                                                         const float* AP, int ldv, const double* pap_part,
+                                                         int ntiles, double* rr_part, int nb, const ColState* sin,
+                                                         ColState* sout, const int* n_active_in,
+                                                         int* n_active_out) {
+  __shared__ double red[4];
+  __shared__ double s_alpha;
+  __shared__ int s_ok;
+  const int c = blockIdx.y;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *n_active_out = 0;
+  if (*n_active_in == 0) return;
+  const ColState st = sin[c];
+  if (!st.active) return;
+  if (threadIdx.x == 0) {
+    double pap = 0.0;
+    for (int t = 0; t < ntiles; ++t) pap += pap_part[(size_t)c * ntiles + t];
+    const double a = st.rr / pap;
+    const int ok = (pap > 0.0) && isfinite(a);
+    s_alpha = ok ? a : 0.0;
+    s_ok = ok;
+    if (blockIdx.x == 0) {
+      sout[c].alpha = s_alpha;
+      sout[c].bad = ok ? 0 : (isfinite(pap) ? 1 : 2);
+    }
+  }
+  __syncthreads();
+  const double alpha = s_alpha;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (s_ok && i < npix) {
+    const float af = (float)alpha;
+    const size_t iv = (size_t)c * ldv + i;
+    X[(size_t)c * ldx + i] = fmaf(af, P[iv], X[(size_t)c * ldx + i]);
+    const float r = fmaf(-af, AP[iv], R[iv]);
+    R[iv] = r;
+    s = (double)r * r;
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) rr_part[(size_t)c * nb + blockIdx.x] = s;
+}
+
+// beta = rr_new / rr, P = R + beta P; block 0 of each column records the Lanczos
+// coefficients and decides the column's status for the next iteration.
+__global__ __launch_bounds__(256) void cg_update2_kernel(int npix, const float* R, float* P, int ldv,
+                                                         const double* rr_part, int nb, const ColState* sin,
+                                                         ColState* sout, const double* bb, const int* n_active_in,
+                                                         int* n_active_out, double tol, int max_iter,
+                                                         int fixed_iters, int n_lanczos, double* ab) {
+  __shared__ double s_beta;
+  __shared__ int s_go;
+  const int c = blockIdx.y;
+  const ColState st = sin[c];
+  if (*n_active_in == 0 || !st.active) {  // carry the state into the other parity
+    if (blockIdx.x == 0 && threadIdx.x == 0) sout[c] = st;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    const ColState half = sout[c];  // alpha and bad written by update1
+    double rr_new = 0.0;
+    for (int b = 0; b < nb; ++b) rr_new += rr_part[(size_t)c * nb + b];
+    const double beta = rr_new / st.rr;
+    ColState nx;
+    nx.alpha = half.alpha;
+    nx.bad = 0;
+    nx.iters = st.iters;
+    nx.rr = st.rr;
+    nx.status = GPL_CG_CONVERGED;
+    nx.active = 0;
+    int go = 0;
+    if (half.bad) {
+      nx.status = half.bad == 1 ? GPL_CG_BREAKDOWN : GPL_CG_NONFINITE;
+    } else if (!isfinite(rr_new) || !isfinite(beta)) {
+      nx.status = GPL_CG_NONFINITE;
+      nx.iters = st.iters + 1;
+    } else {
+      go = 1;
+      nx.rr = rr_new;
+      nx.iters = st.iters + 1;
+      if (blockIdx.x == 0 && st.iters < n_lanczos) {
+        double* e = ab + ((size_t)c * n_lanczos + st.iters) * 2;
+        e[0] = half.alpha;
+        e[1] = beta;
+      }
+      if (fixed_iters > 0) {
+        nx.active = nx.iters < fixed_iters;
+      } else if (sqrt(rr_new) <= tol * sqrt(bb[c])) {
+        nx.active = 0;
+      } else if (nx.iters >= max_iter) {
+        nx.status = GPL_CG_MAXITER;
+      } else {
+        nx.active = 1;
+      }
+    }
+    s_beta = beta;
+    s_go = go;
+    if (blockIdx.x == 0) {
+      sout[c] = nx;
+      if (nx.active) atomicAdd(n_active_out, 1);
+    }
+  }
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s_go && i < npix) {
+    const size_t iv = (size_t)c * ldv + i;
+    P[iv] = fmaf((float)s_beta, P[iv], R[iv]);
+  }
+}
+
+__global__ void cg_snapshot_kernel(const int* n_active, volatile int* host_flag) {
+  if (threadIdx.x == 0) {
+    *host_flag = *n_active;
+    __threadfence_system();
+  }
+}
+
+__global__ void cg_finalize_kernel(int nrhs, const ColState* st, const double* bb, double* bnorm2, int* iters,
+                                   double* relres, int* status, int n_lanczos, double* ab) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  const ColState s = st[c];
+  if (bnorm2) bnorm2[c] = bb[c];
+  if (iters) iters[c] = s.iters;
+  if (relres) relres[c] = bb[c] > 0.0 ? sqrt(s.rr / bb[c]) : 0.0;
+  if (status) status[c] = s.active ? GPL_CG_MAXITER : s.status;
+  // zero the Lanczos slots beyond the column's count
+  if (ab)
+    for (int k = s.iters; k < n_lanczos; ++k) {
+      ab[((size_t)c * n_lanczos + k) * 2 + 0] = 0.0;
+      ab[((size_t)c * n_lanczos + k) * 2 + 1] = 0.0;
+    }
+}
+
+// Host polling resources, one set per host thread.
+struct PollSlots {
+  int* flags = nullptr;  // coherent pinned host memory, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int device = -1;
+};
+
+static int poll_slots(PollSlots*& out) {
+  thread_local PollSlots slots;
+  int dev = 0;
+  GPL_HIP(hipGetDevice(&dev));
+  if (slots.flags == nullptr || slots.device != dev) {
+    GPL_HIP(hipHostMalloc(reinterpret_cast<void**>(&slots.flags), 2 * sizeof(int), hipHostMallocCoherent));
+    GPL_HIP(hipEventCreateWithFlags(&slots.ev[0], hipEventDisableTiming));
+    GPL_HIP(hipEventCreateWithFlags(&slots.ev[1], hipEventDisableTiming));
+    slots.device = dev;
+  }
+  out = &slots;
+  return GPL_OK;
+}
+
+static int check_problem(const gpl_problem* prob, Taps& taps) {
+  GPL_REQUIRE(prob != nullptr, "problem is NULL");
+  const gpl_grid* g = &prob->grid;
+  GPL_REQUIRE(g->n >= 1 && g->ss >= 1 && g->pix_scale > 0, "bad grid");
+  GPL_REQUIRE(prob->px && prob->py, "problem points are NULL");
+  GPL_REQUIRE(prob->noise_sigma >= 0 && std::isfinite(prob->noise_sigma), "noise_sigma must be >= 0");
+  GPL_TRY(check_kernel(&prob->kernel));
+  GPL_TRY(make_taps(g, &prob->psf, taps));
+  return GPL_OK;
+}
+
+// One application of A to the columns of P: AP = B K B^T P + sigma^2 P, with
+// p.Ap partials when `pap` is given.
+static int apply_A_into(const gpl_problem* prob, const Taps& taps, int nrhs, const float* P, int ldp, float* T1,
+                        float* T2, int ldf, float* AP, int ldap, double* pap, int prec, void* mws, size_t mws_bytes,
+                        CgGate gate, hipStream_t stream) {
+  const int n = prob->grid.n, ss = prob->grid.ss, N = n * ss * n * ss;
+  const float s2 = (float)(prob->noise_sigma * prob->noise_sigma);
+  GPL_TRY(psf_adjoint_launch(n, ss, taps, nrhs, P, ldp, T1, ldf, 1.f, 0.f, gate, stream));
+  GPL_TRY(mvm_launch(prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, nrhs, T1, ldf, T2, ldf,
+                     0.f, prec, mws, mws_bytes, gate, stream));
+  GPL_TRY(psf_forward_launch(n, ss, taps, nrhs, T2, ldf, AP, ldap, 1.f, 0.f, P, ldp, s2, pap ? P : nullptr, ldp, pap,
+                             gate, stream));
+  return GPL_OK;
+}
+
+}  // namespace gpl
+
+using namespace gpl;
+
+extern "C" size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int prec) {
+  if (prob == nullptr || nrhs <= 0) return 0;
+  const int N = prob->grid.n * prob->grid.ss * prob->grid.n * prob->grid.ss;
+  Sizer s;
+  const int ldf = round_up(N, 64);
+  s.take<float>((size_t)ldf * nrhs);
+  s.take<float>((size_t)ldf * nrhs);
+  s.take<char>(mvm_workspace(N, nrhs, prec));
+  return s.used;
+}
+
+extern "C" int gpl_apply_A(const gpl_problem* prob, int nrhs, const float* X, int ldx, float* Y, int ldy, int prec,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+  Taps taps;
+  GPL_TRY(check_problem(prob, taps));
+  GPL_REQUIRE(nrhs >= 0 && nrhs <= 65535, "nrhs out of range");
+  if (nrhs == 0) return GPL_OK;
+  const int npix = prob->grid.n * prob->grid.n, N = npix * prob->grid.ss * prob->grid.ss;
+  GPL_REQUIRE(X && Y && X != Y, "X/Y NULL or aliased");
+  GPL_REQUIRE(ldx >= npix && ldy >= npix, "ldx/ldy must be >= n*n");
+  GPL_TRY(check_ws(ws, ws_bytes, gpl_apply_A_workspace(prob, nrhs, prec)));
+  Carver c(ws, ws_bytes);
+  const int ldf = round_up(N, 64);
+  float* T1 = c.take<float>((size_t)ldf * nrhs);
+  float* T2 = c.take<float>((size_t)ldf * nrhs);
+  const size_t mb = mvm_workspace(N, nrhs, prec);
+  char* mws = c.take<char>(mb);
+  if (!c.ok()) return check_ws(nullptr, 0, 1);
+  return apply_A_into(prob, taps, nrhs, X, ldx, T1, T2, ldf, Y, ldy, nullptr, prec, mb ? mws : nullptr, mb, CgGate{},
+                      stream);
+}
+
+extern "C" size_t gpl_cg_solve_workspace(const gpl_problem* prob, int nrhs, int prec) {
+  if (prob == nullptr || nrhs <= 0 || prob->grid.n <= 0 || prob->grid.ss <= 0) return 0;
+  const int npix = prob->grid.n * prob->grid.n, N = npix * prob->grid.ss * prob->grid.ss;
+  Sizer s;
+  carve_cg(s, npix, N, nrhs, prec, nullptr, nullptr, prob->grid.ss, prob->grid.n);
+  return s.used;
+}
+
+extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, int ldb, float* X, int ldx,
+                            double tol, int max_iter, int fixed_iters, int n_lanczos, double* lanczos_ab,
+                            double* bnorm2, int* iters, double* relres, int* status, int prec, int check_every,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+  Taps taps;
+  GPL_TRY(check_problem(prob, taps));
+  GPL_REQUIRE(nrhs >= 1 && nrhs <= 65535, "nrhs=%d out of range", nrhs);
+  GPL_REQUIRE(prec == GPL_PREC_FP32 || prec == GPL_PREC_F16X3, "unknown precision %d", prec);
+  const int n = prob->grid.n, ss = prob->grid.ss, npix = n * n, N = npix * ss * ss;
+  GPL_REQUIRE(Bm && X, "Bm/X are NULL");
+  GPL_REQUIRE(ldb >= npix && ldx >= npix, "ldb/ldx must be >= n*n");
+  GPL_REQUIRE(tol >= 0 && max_iter >= 0 && fixed_iters >= 0 && n_lanczos >= 0, "negative tol/iteration counts");
+  GPL_REQUIRE(n_lanczos == 0 || lanczos_ab != nullptr, "lanczos_ab is NULL");
+  GPL_TRY(check_ws(ws, ws_bytes, gpl_cg_solve_workspace(prob, nrhs, prec)));
+  Carver cv(ws, ws_bytes);
+  CgBuffers b;
+  carve_cg(cv, npix, N, nrhs, prec, &b, nullptr, ss, n);
+  if (!cv.ok()) return check_ws(nullptr, 0, 1);
+  PollSlots* poll = nullptr;
+  GPL_TRY(poll_slots(poll));
+
+  const int nb = b.nb_upd;
+  const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
+  hipLaunchKernelGGL(cg_init_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, Bm, ldb, X, ldx, b.R, b.P, b.ldv,
+                     b.rr_part, nb);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(cg_init_state_kernel, dim3(1), dim3(256), 0, stream, nrhs, b.rr_part, nb, b.st[0], b.st[1], b.bb,
+                     b.n_active, limit);
+  GPL_LAUNCH_CHECK();
+
+  const int chunk = check_every > 0 ? check_every : 8;
+  const int nchunks = cdiv(limit, chunk);
+  int last_end = 0;  // one past the last enqueued iteration
+  auto enqueue_chunk = [&](int k) -> int {
+    const int end = std::min(limit, (k + 1) * chunk);
+    for (int it = k * chunk; it < end; ++it) {
+      const int p = it & 1;
+      CgGate gate;
+      gate.n_active = b.n_active + p;
+      GPL_TRY(apply_A_into(prob, taps, nrhs, b.P, b.ldv, b.T1, b.T2, b.ldf, b.AP, b.ldv, b.pap_part, prec,
+                           b.mvm_ws_bytes ? b.mvm_ws : nullptr, b.mvm_ws_bytes, gate, stream));
+      hipLaunchKernelGGL(cg_update1_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, X, ldx, b.R, b.P, b.AP, b.ldv,
+                         b.pap_part, b.ntiles, b.rr_part, nb, b.st[p], b.st[1 - p], b.n_active + p,
+                         b.n_active + (1 - p));
+      GPL_LAUNCH_CHECK();
+      hipLaunchKernelGGL(cg_update2_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, b.R, b.P, b.ldv, b.rr_part,
+                         nb, b.st[p], b.st[1 - p], b.bb, b.n_active + p, b.n_active + (1 - p), tol, max_iter,
+                         fixed_iters, n_lanczos, lanczos_ab);
+      GPL_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(cg_snapshot_kernel, dim3(1), dim3(64), 0, stream, b.n_active + (end & 1),
+                       poll->flags + (k & 1));
+    GPL_LAUNCH_CHECK();
+    GPL_HIP(hipEventRecord(poll->ev[k & 1], stream));
+    last_end = end;
+    return GPL_OK;
+  };
+
+  if (nchunks > 0) {
+    GPL_TRY(enqueue_chunk(0));
+    for (int k = 0; k < nchunks; ++k) {
+      if (k + 1 < nchunks) GPL_TRY(enqueue_chunk(k + 1));
+      GPL_HIP(hipEventSynchronize(poll->ev[k & 1]));
+      if (poll->flags[k & 1] == 0) break;  // later iterations only carry the state forward
+    }
+  }
+  const int final_parity = last_end & 1;
+  hipLaunchKernelGGL(cg_finalize_kernel, dim3(cdiv(nrhs, 256)), dim3(256), 0, stream, nrhs, b.st[final_parity], b.bb,
+                     bnorm2, iters, relres, status, n_lanczos, lanczos_ab);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}

@@ -1,0 +1,194 @@
+// Observation operator B = D o P (PSF on the fine grid, then local averaging to
+// image pixels) and its adjoint B^T = P^T D^T (Sec. 2 and Sec. 3.3 footnote on a
+// PSF as deterministic post-processing of the fluxes; Sec. 4.1 local averaging).
+//
+// One workgroup per (tile, column). The fine window of the tile plus the PSF
+// halo is staged in LDS, convolved along x into a second LDS buffer, then along
+// y; the forward direction averages each ss x ss block on the fly, the adjoint
+// generates D^T x while loading the window. The taps are a normalised 1-D
+// Gaussian (outer product in 2-D), computed on the host in FP64.
+#include <cmath>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace gpl {
+
+constexpr int kFineTile = 32;  // fine-grid tile side
+constexpr int kMaxWin = kFineTile + 2 * GPL_PSF_MAX_RADIUS;
+
+int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
+  GPL_REQUIRE(psf != nullptr, "psf is NULL");
+  GPL_REQUIRE(psf->fwhm >= 0 && std::isfinite(psf->fwhm), "psf fwhm must be >= 0");
+  GPL_REQUIRE(psf->radius >= 0 && psf->radius <= GPL_PSF_MAX_RADIUS, "psf radius must be in [0, %d]",
+              GPL_PSF_MAX_RADIUS);
+  if (psf->fwhm == 0.0) {
+    t.r = 0;
+    t.w[0] = 1.f;
+    return GPL_OK;
+  }
+  const double h = g->pix_scale / g->ss;
+  const double s = psf->fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+  int r = psf->radius > 0 ? psf->radius : (int)std::ceil(4.0 * s / h);
+  GPL_REQUIRE(r <= GPL_PSF_MAX_RADIUS, "psf radius %d (fwhm %g, h %g) exceeds %d", r, psf->fwhm, h,
+              GPL_PSF_MAX_RADIUS);
+  double w[2 * GPL_PSF_MAX_RADIUS + 1], sum = 0.0;
+  for (int k = -r; k <= r; ++k) {
+    const double u = k * h / s;
+    w[k + r] = std::exp(-0.5 * u * u);
+    sum += w[k + r];
+  }
+  t.r = r;
+  for (int k = 0; k < 2 * r + 1; ++k) t.w[k] = (float)(w[k] / sum);
+  return GPL_OK;
+}
+
+// Forward: out[I] = alpha * (B in)[I] + beta * out[I] + gamma * extra[I];
+// optional FP64 partial sums of dotv[I] * out[I] per (column, tile).
+__global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
+                                                          int ld_in, float* __restrict__ out, int ld_out,
+                                                          float alpha, float beta, const float* __restrict__ extra,
+                                                          int ld_extra, float gamma, const float* __restrict__ dotv,
+                                                          int ld_dotv, double* __restrict__ partial, int ntiles,
+                                                          CgGate gate) {
+  const int c = blockIdx.y;
+  if (gate.skip(c)) return;
+  __shared__ float S1[kMaxWin * kMaxWin];
+  __shared__ float S2[kMaxWin * kFineTile];
+  __shared__ double red[4];
+  const int M = n * ss, r = taps.r;
+  const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;  // output pixels per tile side
+  const int F = TP * ss, W = F + 2 * r;
+  const int tiles_x = (n + TP - 1) / TP;
+  const int tile = blockIdx.x, ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int fy0 = ty * F, fx0 = tx * F;
+  const float* src = in + (size_t)c * ld_in;
+  for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
+    const int wy = idx / W, wx = idx - wy * W;
+    const int fy = fy0 - r + wy, fx = fx0 - r + wx;
+    S1[idx] = (fy >= 0 && fy < M && fx >= 0 && fx < M) ? src[(size_t)fy * M + fx] : 0.f;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < W * F; idx += blockDim.x) {
+    const int wy = idx / F, x = idx - wy * F;
+    float s = 0.f;
+    for (int b = -r; b <= r; ++b) s += taps.w[b + r] * S1[wy * W + x + r - b];
+    S2[idx] = s;
+  }
+  __syncthreads();
+  const float inv_ss2 = 1.f / (float)(ss * ss);
+  double dot = 0.0;
+  for (int o = threadIdx.x; o < TP * TP; o += blockDim.x) {
+    const int oy = o / TP, ox = o - oy * TP;
+    const int Iy = ty * TP + oy, Ix = tx * TP + ox;
+    if (Iy >= n || Ix >= n) continue;
+    float acc = 0.f;
+    for (int sy = 0; sy < ss; ++sy)
+      for (int sx = 0; sx < ss; ++sx) {
+        const int y = oy * ss + sy, x = ox * ss + sx;
+        float v = 0.f;
+        for (int a = -r; a <= r; ++a) v += taps.w[a + r] * S2[(y + r - a) * F + x];
+        acc += v;
+      }
+    const int I = Iy * n + Ix;
+    float res = alpha * (acc * inv_ss2);
+    if (beta != 0.f) res += beta * out[(size_t)c * ld_out + I];
+    if (extra) res += gamma * extra[(size_t)c * ld_extra + I];
+    out[(size_t)c * ld_out + I] = res;
+    if (dotv) dot += (double)dotv[(size_t)c * ld_dotv + I] * (double)res;
+  }
+  if (partial) {
+    const double s = block_sum_double(dot, red);
+    if (threadIdx.x == 0) partial[(size_t)c * ntiles + tile] = s;
+  }
+}
+
+// Adjoint: out (fine) = alpha * P^T D^T in + beta * out; P^T is the correlation
+// with the taps: (P^T g)(y, x) = sum_{a,b} w_a w_b g(y + a, x + b).
+__global__ __launch_bounds__(256) void psf_adjoint_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
+                                                          int ld_in, float* __restrict__ out, int ld_out,
+                                                          float alpha, float beta, CgGate gate) {
+  const int c = blockIdx.y;
+  if (gate.skip(c)) return;
+  __shared__ float S1[kMaxWin * kMaxWin];
+  __shared__ float S2[kMaxWin * kFineTile];
+  const int M = n * ss, r = taps.r;
+  const int F = kFineTile, W = F + 2 * r;
+  const int tiles_x = (M + F - 1) / F;
+  const int tile = blockIdx.x, ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int fy0 = ty * F, fx0 = tx * F;
+  const float* src = in + (size_t)c * ld_in;
+  const float inv_ss2 = 1.f / (float)(ss * ss);
+  for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
+    const int wy = idx / W, wx = idx - wy * W;
+    const int fy = fy0 - r + wy, fx = fx0 - r + wx;
+    S1[idx] = (fy >= 0 && fy < M && fx >= 0 && fx < M) ? src[(fy / ss) * n + fx / ss] * inv_ss2 : 0.f;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < W * F; idx += blockDim.x) {
+    const int wy = idx / F, x = idx - wy * F;
+    float s = 0.f;
+    for (int b = -r; b <= r; ++b) s += taps.w[b + r] * S1[wy * W + x + r + b];
+    S2[idx] = s;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < F * F; o += blockDim.x) {
+    const int y = o / F, x = o - y * F;
+    const int fy = fy0 + y, fx = fx0 + x;
+    if (fy >= M || fx >= M) continue;
+    float v = 0.f;
+    for (int a = -r; a <= r; ++a) v += taps.w[a + r] * S2[(y + r + a) * F + x];
+    const size_t o_idx = (size_t)c * ld_out + (size_t)fy * M + fx;
+    float res = alpha * v;
+    if (beta != 0.f) res += beta * out[o_idx];
+    out[o_idx] = res;
+  }
+}
+
+int psf_forward_tiles(int n, int ss) {
+  const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;
+  const int t = (n + TP - 1) / TP;
+  return t * t;
+}
+
+int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* in, int ld_in, float* out, int ld_out,
+                       float alpha, float beta, const float* extra, int ld_extra, float gamma, const float* dotv,
+                       int ld_dotv, double* partial, CgGate gate, hipStream_t stream) {
+  GPL_REQUIRE(ss <= kFineTile, "ss=%d exceeds %d", ss, kFineTile);
+  const int ntiles = psf_forward_tiles(n, ss);
+  hipLaunchKernelGGL(psf_forward_kernel, dim3(ntiles, nrhs), dim3(256), 0, stream, n, ss, taps, in, ld_in, out,
+                     ld_out, alpha, beta, extra, ld_extra, gamma, dotv, ld_dotv, partial, ntiles, gate);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int psf_adjoint_launch(int n, int ss, const Taps& taps, int nrhs, const float* in, int ld_in, float* out, int ld_out,
+                       float alpha, float beta, CgGate gate, hipStream_t stream) {
+  const int M = n * ss, t = (M + kFineTile - 1) / kFineTile;
+  hipLaunchKernelGGL(psf_adjoint_kernel, dim3(t * t, nrhs), dim3(256), 0, stream, n, ss, taps, in, ld_in, out, ld_out,
+                     alpha, beta, gate);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+}  // namespace gpl
+
+using namespace gpl;
+
+extern "C" int gpl_psf_conv(const gpl_grid* grid, const gpl_psf* psf, int nrhs, const float* in, int ld_in,
+                            float* out, int ld_out, float alpha, float beta, int adjoint, hipStream_t stream) {
+  GPL_REQUIRE(grid != nullptr && grid->n >= 1 && grid->ss >= 1 && grid->pix_scale > 0, "bad grid");
+  GPL_REQUIRE(nrhs >= 0 && nrhs <= 65535, "nrhs=%d must be in [0, 65535]", nrhs);
+  if (nrhs == 0) return GPL_OK;
+  GPL_REQUIRE(in && out && in != out, "in/out NULL or aliased");
+  const int N = grid->n * grid->ss * grid->n * grid->ss, npix = grid->n * grid->n;
+  Taps taps;
+  GPL_TRY(make_taps(grid, psf, taps));
+  if (adjoint == 0) {
+    GPL_REQUIRE(ld_in >= N && ld_out >= npix, "ld_in=%d (>= %d) / ld_out=%d (>= %d)", ld_in, N, ld_out, npix);
+    return psf_forward_launch(grid->n, grid->ss, taps, nrhs, in, ld_in, out, ld_out, alpha, beta, nullptr, 0, 0.f,
+                              nullptr, 0, nullptr, CgGate{}, stream);
+  }
+  GPL_REQUIRE(ld_in >= npix && ld_out >= N, "ld_in=%d (>= %d) / ld_out=%d (>= %d)", ld_in, npix, ld_out, N);
+  return psf_adjoint_launch(grid->n, grid->ss, taps, nrhs, in, ld_in, out, ld_out, alpha, beta, CgGate{}, stream);
+}

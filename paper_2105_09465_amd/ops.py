@@ -1,0 +1,223 @@
+"""Thin torch-facing wrappers over the gplens C-ABI.
+
+Blocks of column vectors are torch tensors of shape (ncols, rows) on the GPU:
+row k is column k of the column-major block, and the leading dimension is the
+tensor's stride(0). Each wrapper checks shapes, allocates outputs and workspace
+with torch (device memory only), and passes pointers plus torch's current HIP
+stream to the library. No arithmetic happens here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from .params import Grid, Kernel, Lens, Problem, PSF, Sersic
+
+PREC = {"fp32": _lib.PREC_FP32, "f16x3": _lib.PREC_F16X3}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("gplens expects GPU tensors")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _block(t: torch.Tensor, rows: int, name: str):
+    if t.dim() != 2 or t.shape[1] != rows or t.stride(1) != 1:
+        raise ValueError(f"{name}: expected a (ncols, {rows}) tensor with unit stride along rows, got "
+                         f"{tuple(t.shape)} strides {t.stride()}")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name}: expected float32")
+    return t.stride(0) if t.shape[0] > 1 else max(t.stride(0), rows)
+
+
+def workspace(nbytes: int, device=None):
+    if nbytes == 0:
+        return None, 0
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device or "cuda"), int(nbytes)
+
+
+def _wsptr(ws):
+    return None if ws is None else C.c_void_p(ws.data_ptr())
+
+
+def prec_code(prec):
+    return PREC[prec] if isinstance(prec, str) else int(prec)
+
+
+# ------------------------------------------------------------------ forward
+
+def grid_map(grid: Grid, device="cuda"):
+    x = torch.empty(grid.N, dtype=torch.float32, device=device)
+    y = torch.empty_like(x)
+    pix = torch.empty(grid.N, dtype=torch.int32, device=device)
+    g = grid.c()
+    _lib.call("gpl_grid_map", C.byref(g), _ptr(x), _ptr(y), _ptr(pix), _stream())
+    return x, y, pix
+
+
+def lens_raytrace(grid: Grid, lens: Lens, out=None, device="cuda"):
+    if out is None:
+        out = torch.empty(2, grid.N, dtype=torch.float32, device=device)
+    g, L = grid.c(), lens.c()
+    _lib.call("gpl_lens_raytrace", C.byref(g), C.byref(L), _ptr(out[0]), _ptr(out[1]), _stream())
+    return out
+
+
+def sersic_eval(src: Sersic, px, py, out=None):
+    n = px.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=px.device)
+    s = src.c()
+    _lib.call("gpl_sersic_eval", C.byref(s), n, _ptr(px), _ptr(py), _ptr(out), _stream())
+    return out
+
+
+def psf_conv(grid: Grid, psf: PSF, inp, adjoint: bool, out=None, alpha=1.0, beta=0.0):
+    """adjoint=False: B inp (fine -> image); True: B^T inp (image -> fine)."""
+    rows_in, rows_out = (grid.n_pix, grid.N) if adjoint else (grid.N, grid.n_pix)
+    squeeze = inp.dim() == 1
+    inp2 = inp.unsqueeze(0) if squeeze else inp
+    ld_in = _block(inp2, rows_in, "inp")
+    if out is None:
+        out = torch.zeros(inp2.shape[0], rows_out, dtype=torch.float32, device=inp.device)
+        ld_out = rows_out
+        ret = out
+    else:
+        ret = out
+        out = out.unsqueeze(0) if out.dim() == 1 else out
+        ld_out = _block(out, rows_out, "out")
+    g, p = grid.c(), psf.c()
+    _lib.call("gpl_psf_conv", C.byref(g), C.byref(p), inp2.shape[0], _ptr(inp2), ld_in, _ptr(out), ld_out,
+              float(alpha), float(beta), 1 if adjoint else 0, _stream())
+    return ret[0] if (squeeze and ret.dim() == 2) else ret
+
+
+def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0):
+    n = px.numel()
+    squeeze = V.dim() == 1
+    V2 = V.unsqueeze(0) if squeeze else V
+    ldv = _block(V2, n, "V")
+    if out is None:
+        out = torch.zeros(V2.shape[0], n, dtype=torch.float32, device=V.device)
+    out2 = out.unsqueeze(0) if out.dim() == 1 else out
+    ldy = _block(out2, n, "Y")
+    pc = prec_code(prec)
+    ws, wsb = workspace(_lib.lib.gpl_gp_kernel_mvm_workspace(n, V2.shape[0], pc), V.device)
+    k = kernel.c()
+    _lib.call("gpl_gp_kernel_mvm", C.byref(k), n, _ptr(px), _ptr(py), V2.shape[0], _ptr(V2), ldv, _ptr(out2), ldy,
+              float(beta), pc, _wsptr(ws), wsb, _stream())
+    return out[0] if (squeeze and out.dim() == 2) else out
+
+
+def problem_c(problem: Problem, px, py):
+    return _lib.gpl_problem(problem.grid.c(), problem.kernel.c(), problem.psf.c(), problem.noise_sigma,
+                            C.c_void_p(px.data_ptr()), C.c_void_p(py.data_ptr()))
+
+
+def apply_A(problem: Problem, px, py, X, prec="fp32"):
+    npix = problem.grid.n_pix
+    ldx = _block(X, npix, "X")
+    Y = torch.empty(X.shape[0], npix, dtype=torch.float32, device=X.device)
+    pc = prec_code(prec)
+    pr = problem_c(problem, px, py)
+    ws, wsb = workspace(_lib.lib.gpl_apply_A_workspace(C.byref(pr), X.shape[0], pc), X.device)
+    _lib.call("gpl_apply_A", C.byref(pr), X.shape[0], _ptr(X), ldx, _ptr(Y), npix, pc, _wsptr(ws), wsb, _stream())
+    return Y
+
+
+def cg_solve(problem: Problem, px, py, Bm, tol=1e-6, max_iter=1000, fixed_iters=0, n_lanczos=30, prec="fp32",
+             check_every=8, ws=None):
+    """CG on A X = Bm for every column of Bm (ncols, n_pix). Returns device tensors."""
+    npix = problem.grid.n_pix
+    ldb = _block(Bm, npix, "Bm")
+    m = Bm.shape[0]
+    dev = Bm.device
+    X = torch.empty(m, npix, dtype=torch.float32, device=dev)
+    nl = max(int(n_lanczos), 0)
+    ab = torch.zeros(m, max(nl, 1), 2, dtype=torch.float64, device=dev)
+    bnorm2 = torch.empty(m, dtype=torch.float64, device=dev)
+    iters = torch.empty(m, dtype=torch.int32, device=dev)
+    relres = torch.empty(m, dtype=torch.float64, device=dev)
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    pc = prec_code(prec)
+    pr = problem_c(problem, px, py)
+    need = _lib.lib.gpl_cg_solve_workspace(C.byref(pr), m, pc)
+    if ws is None or ws.numel() < need:
+        ws, _ = workspace(need, dev)
+    _lib.call("gpl_cg_solve", C.byref(pr), m, _ptr(Bm), ldb, _ptr(X), npix, float(tol), int(max_iter),
+              int(fixed_iters), nl, _ptr(ab), _ptr(bnorm2), _ptr(iters), _ptr(relres), _ptr(status), pc,
+              int(check_every), _wsptr(ws), int(need), _stream())
+    return dict(X=X, ab=ab[:, :nl], bnorm2=bnorm2, iters=iters, relres=relres, status=status, n_lanczos=nl)
+
+
+def lanczos_logdet(ab, iters, bnorm2, scale):
+    """SLQ log-determinant from CG coefficients of the probe columns."""
+    m, nl = ab.shape[0], ab.shape[1]
+    ab = ab.contiguous()
+    dev = ab.device
+    contrib = torch.empty(m, dtype=torch.float64, device=dev)
+    logdet = torch.empty(1, dtype=torch.float64, device=dev)
+    stderr = torch.empty(1, dtype=torch.float64, device=dev)
+    ws, wsb = workspace(_lib.lib.gpl_lanczos_logdet_workspace(m, nl), dev)
+    _lib.call("gpl_lanczos_logdet", m, nl, _ptr(ab), _ptr(iters.contiguous()), _ptr(bnorm2.contiguous()),
+              float(scale), _ptr(contrib), _ptr(logdet), _ptr(stderr), _wsptr(ws), wsb, _stream())
+    return logdet, stderr, contrib
+
+
+def evidence_scalars(n_pix, n_points, r, u, logdet, amplitude, noise_sigma):
+    out = torch.empty(3, dtype=torch.float64, device=r.device)
+    _lib.call("gpl_evidence_scalars", n_pix, n_points, _ptr(r), _ptr(u), _ptr(logdet), float(amplitude),
+              float(noise_sigma), _ptr(out), _stream())
+    return out
+
+
+# ------------------------------------------------------------------ backward
+
+def kernel_mvm_backward(kernel: Kernel, px, py, A, Bv, weights, gpx=None, gpy=None):
+    """Gradient of F = sum_c w_c a_c^T K b_c w.r.t. points (accumulated into gpx,
+    gpy), lengthscale and amplitude (returned as a 2-vector of float64)."""
+    n = px.numel()
+    lda, ldb = _block(A, n, "A"), _block(Bv, n, "Bv")
+    npairs = A.shape[0]
+    if Bv.shape[0] != npairs or len(weights) != npairs:
+        raise ValueError("A, Bv and weights must have the same number of columns")
+    if gpx is None:
+        gpx = torch.zeros(n, dtype=torch.float32, device=px.device)
+        gpy = torch.zeros(n, dtype=torch.float32, device=px.device)
+    ghyp = torch.empty(2, dtype=torch.float64, device=px.device)
+    w = (C.c_double * npairs)(*[float(v) for v in weights])
+    ws, wsb = workspace(_lib.lib.gpl_gp_kernel_mvm_backward_workspace(n, npairs), px.device)
+    k = kernel.c()
+    _lib.call("gpl_gp_kernel_mvm_backward", C.byref(k), n, _ptr(px), _ptr(py), npairs, _ptr(A), lda, _ptr(Bv), ldb,
+              w, _ptr(gpx), _ptr(gpy), _ptr(ghyp), _wsptr(ws), wsb, _stream())
+    return gpx, gpy, ghyp
+
+
+def lens_raytrace_backward(grid: Grid, lens: Lens, gpx, gpy):
+    g, L = grid.c(), lens.c()
+    out = torch.empty(8, dtype=torch.float64, device=gpx.device)
+    ws, wsb = workspace(_lib.lib.gpl_lens_raytrace_backward_workspace(C.byref(g)), gpx.device)
+    _lib.call("gpl_lens_raytrace_backward", C.byref(g), C.byref(L), _ptr(gpx), _ptr(gpy), _ptr(out), _wsptr(ws), wsb,
+              _stream())
+    return out
+
+
+def sersic_backward(src: Sersic, px, py, gmu, gpx, gpy):
+    n = px.numel()
+    s = src.c()
+    out = torch.empty(2, dtype=torch.float64, device=px.device)
+    ws, wsb = workspace(_lib.lib.gpl_sersic_backward_workspace(n), px.device)
+    _lib.call("gpl_sersic_backward", C.byref(s), n, _ptr(px), _ptr(py), _ptr(gmu), _ptr(gpx), _ptr(gpy), _ptr(out),
+              _wsptr(ws), wsb, _stream())
+    return out

@@ -1,0 +1,75 @@
+"""One reconstruction through the library: ray tracing, mean, residual, CG on
+the solve column and the probes, SLQ log-determinant, evidence scalars,
+posterior mean and predicted image.
+
+Each step is one library call on torch's current stream; torch only provides
+the buffers (and copies d and the probes into the right-hand-side block).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import torch
+
+from . import ops
+from .params import Problem
+
+
+@dataclasses.dataclass
+class Reconstruction:
+    px: torch.Tensor
+    py: torch.Tensor
+    mu: torch.Tensor
+    rhs: torch.Tensor  # (1+m, n_pix): residual r = d - B mu, then the probes
+    X: torch.Tensor  # A^{-1} rhs
+    cg: dict
+    logdet: torch.Tensor
+    stderr: torch.Tensor
+    contrib: torch.Tensor
+    scalars: torch.Tensor  # quad, ln p, L_VI (float64, device)
+    fhat: torch.Tensor | None
+    image: torch.Tensor | None
+
+    def host(self):
+        """Copy the scalar results to the host (one synchronisation)."""
+        s = self.scalars.double().cpu().tolist()
+        return dict(quad=s[0], lnp=s[1], vi=s[2], logdet=float(self.logdet.item()), stderr=float(self.stderr.item()),
+                    iters=self.cg["iters"].cpu().tolist(), relres=self.cg["relres"].cpu().tolist(),
+                    status=self.cg["status"].cpu().tolist())
+
+
+def reconstruct(problem: Problem, d: torch.Tensor, probes: torch.Tensor, prec="fp32", tol=1e-6, max_iter=1000,
+                fixed_iters=0, n_lanczos=30, logdet_scale=None, want_image=True, check_every=8, ws=None):
+    """Evidence and posterior mean of one image.
+
+    d: observed image (n_pix,) float32 on the GPU; probes: (m, n_pix) float32
+    (Rademacher for SLQ, or unit vectors with logdet_scale=1 for the exact trace)."""
+    g = problem.grid
+    dev = d.device
+    pts = ops.lens_raytrace(g, problem.lens, device=dev)
+    px, py = pts[0], pts[1]
+    mu = ops.sersic_eval(problem.source, px, py)
+    m = probes.shape[0]
+    rhs = torch.empty(1 + m, g.n_pix, dtype=torch.float32, device=dev)
+    rhs[0].copy_(d)
+    if m:
+        rhs[1:].copy_(probes)
+    ops.psf_conv(g, problem.psf, mu, adjoint=False, out=rhs[0], alpha=-1.0, beta=1.0)  # r = d - B mu
+    cg = ops.cg_solve(problem, px, py, rhs, tol=tol, max_iter=max_iter, fixed_iters=fixed_iters,
+                      n_lanczos=n_lanczos, prec=prec, check_every=check_every, ws=ws)
+    if m and cg["n_lanczos"] > 0:
+        scale = (1.0 / m) if logdet_scale is None else logdet_scale
+        logdet, stderr, contrib = ops.lanczos_logdet(cg["ab"][1:], cg["iters"][1:], cg["bnorm2"][1:], scale)
+    else:
+        logdet = torch.full((1,), math.nan, dtype=torch.float64, device=dev)
+        stderr, contrib = logdet.clone(), torch.empty(0, dtype=torch.float64, device=dev)
+    u = cg["X"][0]
+    scalars = ops.evidence_scalars(g.n_pix, g.N, rhs[0], u, logdet, problem.kernel.amplitude, problem.noise_sigma)
+    fhat = image = None
+    if want_image:
+        w = ops.psf_conv(g, problem.psf, u, adjoint=True)  # B^T u
+        fhat = mu.clone()
+        ops.kernel_mvm(problem.kernel, px, py, w, prec="fp32", out=fhat, beta=1.0)  # mu + K B^T u
+        image = ops.psf_conv(g, problem.psf, fhat, adjoint=False)
+    return Reconstruction(px, py, mu, rhs, cg["X"], cg, logdet, stderr, contrib, scalars, fhat, image)

@@ -1,0 +1,350 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Sizes span several tiles and a ragged tail; large products are checked on
+sampled rows the oracle computes one by one. Tolerances are stated per test.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import grid as ogrid
+from oracle import kernel as okernel
+from oracle import krylov as okrylov
+from oracle import lens as olens
+from oracle import psf as opsf
+from oracle import source as osource
+from oracle import evidence as oev
+
+from helpers import gpu_problem, observation, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_09465_amd as G
+    return G
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def t64(x):
+    return x.detach().double().cpu().numpy()
+
+
+def cuda32(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+# ------------------------------------------------------------------ a1 grid
+
+@pytest.mark.parametrize("n,ss,cx,cy", [(24, 1, 0.0, 0.0), (37, 2, 0.0, 0.0), (13, 3, 0.9, -0.45), (100, 2, 0, 0)])
+def test_grid_index_bit_exact(G, n, ss, cx, cy):
+    _say("grid", n, ss, cx, cy)
+    x, y, pix = G.ops.grid_map(G.Grid(n, ss, 0.05, cx, cy))
+    torch.cuda.synchronize()
+    assert np.array_equal(pix.cpu().numpy(), ogrid.coarse_of_fine(n, ss))
+    ox, oy = ogrid.fine_coords(n, ss, 0.05, cx, cy)
+    # coordinates: FP32 arithmetic c + (f - (M-1)/2) h32 rounds h, the product and
+    # the sum, so the bound is 2 eps32 times the magnitude of the terms
+    eps32 = np.finfo(np.float32).eps
+    for got, want, c in ((x, ox, cx), (y, oy, cy)):
+        g = got.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(g - want) <= 2 * eps32 * (abs(c) + np.abs(want - c)) + 1e-12)
+
+
+# ------------------------------------------------------------------ a2 ray tracing
+
+def _deflection_check(G, n, ss, lens, cx=0.0, cy=0.0):
+    grid = G.Grid(n, ss, 0.05, cx, cy)
+    xi_x, xi_y, _ = G.ops.grid_map(grid)
+    pts = G.ops.lens_raytrace(grid, G.Lens(*lens))
+    torch.cuda.synchronize()
+    X, Y = t64(xi_x), t64(xi_y)
+    opx, opy = olens.raytrace(X, Y, lens)  # oracle at the same (FP32) image-plane points
+    ax, ay = X - opx, Y - opy
+    amag = np.hypot(ax, ay)
+    gx, gy = t64(pts[0]), t64(pts[1])
+    err = np.hypot(gx - opx, gy - opy)
+    Rx, Ry = olens.elliptical_coords(X, Y, lens[1], lens[2], lens[4], lens[5])
+    keep = np.hypot(Rx, Ry) >= 1e-3 * 0.05 / ss
+    rel = err[keep] / amag[keep]
+    return rel, (~keep).sum()
+
+
+@pytest.mark.parametrize("index,sub", [(0, 0), (1, 0), (1, 1), (1, 2), (1, 3), (2, 0)])
+def test_raytrace_deflection_rel_1e5(G, index, sub):
+    w = synth.workload(index, sub)
+    _say("raytrace", w.name, w.lens)
+    rel, excluded = _deflection_check(G, min(w.n, 100), w.ss, w.lens.as_tuple())
+    print(f"max rel deflection error {rel.max():.2e}; excluded near centre: {excluded}")
+    assert rel.max() <= 1e-5
+
+
+@pytest.mark.parametrize("q", [0.1, 0.3, 0.99, 1.0])
+def test_raytrace_extreme_axis_ratios(G, q):
+    lens = (1.2, q, 0.7, 2.1, 0.03, -0.02, 0.02, 0.01)
+    _say("raytrace q", q)
+    rel, _ = _deflection_check(G, 64, 2, lens)
+    assert rel.max() <= 1e-5
+
+
+def test_sis_einstein_ring_gpu(G):
+    """q = 1, slope = 2, no shear: |p| = ||xi| - theta_E| exactly (points on the ring map to the centre)."""
+    _say("SIS ring")
+    grid = G.Grid(64, 2, 0.05)
+    xi_x, xi_y, _ = G.ops.grid_map(grid)
+    pts = G.ops.lens_raytrace(grid, G.Lens(0.6, 1.0, 0.3, 2.0, 0.0, 0.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    r = np.hypot(t64(xi_x), t64(xi_y))
+    pm = np.hypot(t64(pts[0]), t64(pts[1]))
+    assert np.max(np.abs(pm - np.abs(r - 0.6))) < 1e-6
+
+
+# ------------------------------------------------------------------ a3 mean
+
+def test_sersic_parity(G):
+    _say("sersic")
+    rng = np.random.default_rng(0)
+    px, py = rng.uniform(-2, 2, 5003), rng.uniform(-2, 2, 5003)
+    px[0], py[0] = 0.05, -0.03  # exactly the centre
+    src = (0.6, 0.1, 1.5, 0.05, -0.03)
+    mu = G.ops.sersic_eval(G.Sersic(*src), cuda32(px), cuda32(py))
+    # the kernel works with the FP32 centre; the profile's cusp at r = 0 makes mu
+    # sensitive to that rounding, so the oracle uses the same centre
+    src32 = src[:3] + tuple(float(np.float32(v)) for v in src[3:])
+    want = osource.sersic(px.astype(np.float32).astype(np.float64), py.astype(np.float32).astype(np.float64), *src32)
+    got = t64(mu)
+    assert np.all(np.abs(got - want) <= 2e-6 * np.abs(want) + 1e-30)
+
+
+# ------------------------------------------------------------------ a4 observation operator
+
+@pytest.mark.parametrize("n,ss,fwhm", [(24, 1, 0.1), (37, 2, 0.1), (20, 3, 0.1), (33, 2, 0.0), (50, 1, 0.3)])
+def test_psf_conv_parity_and_adjoint(G, n, ss, fwhm):
+    _say("psf", n, ss, fwhm)
+    rng = np.random.default_rng(n * 10 + ss)
+    N, npix = (n * ss) ** 2, n * n
+    f = rng.standard_normal((3, N)).astype(np.float32)
+    x = rng.standard_normal((3, npix)).astype(np.float32)
+    grid, psf = G.Grid(n, ss, 0.05), G.PSF(fwhm)
+    Bf = G.ops.psf_conv(grid, psf, cuda32(f), adjoint=False)
+    BTx = G.ops.psf_conv(grid, psf, cuda32(x), adjoint=True)
+    torch.cuda.synchronize()
+    taps = opsf.psf_taps(fwhm, 0.05 / ss)
+    want_B = opsf.apply_B(f.astype(np.float64).T, n, ss, taps).T
+    want_BT = opsf.apply_BT(x.astype(np.float64).T, n, ss, taps).T
+    assert np.max(np.abs(t64(Bf) - want_B)) <= 1e-6 * np.max(np.abs(want_B))
+    assert np.max(np.abs(t64(BTx) - want_BT)) <= 1e-6 * np.max(np.abs(want_BT))
+    lhs = np.sum(t64(Bf) * x.astype(np.float64), axis=1)
+    rhs = np.sum(f.astype(np.float64) * t64(BTx), axis=1)
+    assert np.allclose(lhs, rhs, rtol=1e-5, atol=1e-5 * np.abs(lhs).max())
+
+
+def test_psf_conv_alpha_beta(G):
+    _say("psf alpha beta")
+    n, ss = 16, 2
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((1, (n * ss) ** 2)).astype(np.float32)
+    base = rng.standard_normal((1, n * n)).astype(np.float32)
+    out = cuda32(base)
+    G.ops.psf_conv(G.Grid(n, ss, 0.05), G.PSF(0.1), cuda32(f), adjoint=False, out=out, alpha=-2.0, beta=0.5)
+    want = -2.0 * opsf.apply_B(f[0].astype(np.float64), n, ss, opsf.psf_taps(0.1, 0.025)) + 0.5 * base[0]
+    assert np.max(np.abs(t64(out)[0] - want)) < 1e-5
+
+
+# ------------------------------------------------------------------ a5 kernel product
+
+def _mvm_case(G, n, nrhs, prec, spread=0.6, seed=0, rows=None):
+    rng = np.random.default_rng(seed)
+    px = rng.uniform(-spread, spread, n).astype(np.float32)
+    py = rng.uniform(-spread, spread, n).astype(np.float32)
+    V = rng.standard_normal((nrhs, n)).astype(np.float32)
+    Y = G.ops.kernel_mvm(G.Kernel(0.04, 0.3), cuda32(px), cuda32(py), cuda32(V), prec=prec)
+    torch.cuda.synchronize()
+    rows = np.arange(n) if rows is None else rows
+    P64 = (px.astype(np.float64), py.astype(np.float64))
+    want = okernel.kernel_mvm_rows(*P64, rows, V.astype(np.float64).T, 0.04, 0.3)
+    scale = okernel.kernel_abs_mvm_rows(*P64, rows, V.astype(np.float64).T, 0.04, 0.3)
+    got = t64(Y).T[rows]
+    return np.max(np.abs(got - want) / scale)
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (257, 3), (1000, 1), (3001, 17), (4096, 16), (5003, 33)])
+def test_kernel_mvm_fp32_parity(G, n, nrhs):
+    _say("mvm fp32", n, nrhs)
+    err = _mvm_case(G, n, nrhs, "fp32")
+    print(f"max |err| / (|K||V|) = {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_kernel_mvm_fp32_full_size_sampled(G):
+    """N = 40,000 (the 100x100, ss = 2 workload), 17 columns, 300 sampled rows."""
+    _say("mvm fp32 N=40000")
+    rows = np.random.default_rng(1).choice(40000, 300, replace=False)
+    err = _mvm_case(G, 40000, 17, "fp32", spread=1.5, rows=rows)
+    print(f"max |err| / (|K||V|) = {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_kernel_mvm_beta_accumulate(G):
+    _say("mvm beta")
+    rng = np.random.default_rng(5)
+    n = 700
+    px, py = rng.uniform(-0.3, 0.3, (2, n)).astype(np.float32)
+    V = rng.standard_normal((2, n)).astype(np.float32)
+    Y0 = rng.standard_normal((2, n)).astype(np.float32)
+    out = cuda32(Y0)
+    G.ops.kernel_mvm(G.Kernel(0.05, 0.7), cuda32(px), cuda32(py), cuda32(V), out=out, beta=-1.5)
+    want = okernel.kernel_mvm(px.astype(np.float64), py.astype(np.float64), V.T.astype(np.float64), 0.05, 0.7).T \
+        - 1.5 * Y0
+    assert np.max(np.abs(t64(out) - want)) < 1e-4
+
+
+# ------------------------------------------------------------------ a4-a5 operator A
+
+def test_apply_A_parity(G):
+    w = synth.workload(0)
+    _say("apply_A", w.name)
+    prob = gpu_problem(w)
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((5, w.n_pix)).astype(np.float32)
+    Y = G.ops.apply_A(prob, pts[0], pts[1], cuda32(X))
+    torch.cuda.synchronize()
+    P = oracle_problem(w)
+    px, py = t64(pts[0]), t64(pts[1])
+    A = oev.assemble_A(P, px, py)
+    want = (A @ X.astype(np.float64).T).T
+    scale = (np.abs(A) @ np.abs(X.astype(np.float64)).T).T
+    assert np.max(np.abs(t64(Y) - want) / scale) <= 1e-5
+
+
+# ------------------------------------------------------------------ a6-a9 CG, SLQ, evidence
+
+def test_slq_kernel_on_oracle_coefficients(G):
+    """The tridiagonal eigensolver and quadrature alone: GPU vs oracle on the same
+    FP64 CG coefficients (including long tridiagonals)."""
+    _say("slq kernel")
+    w, d, _ = observation(0)
+    P = oracle_problem(w)
+    px, py = P.points()
+    A = oev.assemble_A(P, px, py)
+    Z = synth.rademacher(w.n_pix, 8, 0)
+    for nl in (30, 200):
+        res = okrylov.cg(lambda X: A @ X, Z, tol=1e-9, max_iter=400, n_lanczos=nl)
+        est, se, contrib = okrylov.slq_logdet(res["alphas"], res["betas"], res["iters"], res["bnorm2"], nl)
+        ab = np.stack([res["alphas"], res["betas"]], axis=-1)
+        ld, sd, c = G.ops.lanczos_logdet(torch.as_tensor(ab, device="cuda"),
+                                         torch.as_tensor(res["iters"].astype(np.int32), device="cuda"),
+                                         torch.as_tensor(res["bnorm2"], device="cuda"), 1.0 / 8)
+        assert np.allclose(t64(c), contrib, rtol=1e-10, atol=1e-9)
+        assert math.isclose(ld.item(), est, rel_tol=1e-11)
+        assert math.isclose(sd.item(), se, rel_tol=1e-9)
+
+
+def _oracle_solution(w, d):
+    P = oracle_problem(w)
+    return oev.solve_problem(P, d)
+
+
+def _cg_fp32_replay(A, B, iters):
+    """The CG recurrences with FP32 vectors and products and FP64 scalars."""
+    A32 = A.astype(np.float32)
+    X = np.zeros(B.shape, dtype=np.float32)
+    R = B.astype(np.float32).copy()
+    P = R.copy()
+    rr = np.sum(R.astype(np.float64) ** 2, axis=0)
+    for _ in range(iters):
+        AP = (A32 @ P).astype(np.float32)
+        a = rr / np.sum(P.astype(np.float64) * AP, axis=0)
+        X = (X + a.astype(np.float32) * P).astype(np.float32)
+        R = (R - a.astype(np.float32) * AP).astype(np.float32)
+        rn = np.sum(R.astype(np.float64) ** 2, axis=0)
+        P = (R + (rn / rr).astype(np.float32) * P).astype(np.float32)
+        rr = rn
+    return X
+
+
+def test_cg_fixed_50_iterations_plain_workload(G):
+    """24x24 workload: CG with exactly 50 iterations, as the workload asks, next to
+    the exact Cholesky solution. At condition ~1e4, 50 steps are far from
+    convergence and FP32 rounding moves the iterate by a few per cent from the
+    FP64 recurrence (an FP32 replay of the recurrences shows the same), so the
+    GPU iterate is checked against that replay and the gaps are reported."""
+    w, d, _ = observation(0)
+    _say("cg 50 iterations", w.name)
+    prob = gpu_problem(w)
+    Z = synth.rademacher(w.n_pix, 16, 0)
+    rec = G.reconstruct(prob, cuda32(d), cuda32(Z.T), fixed_iters=50, n_lanczos=30, want_image=False)
+    h = rec.host()
+    assert h["iters"] == [50] * 17
+    ex = _oracle_solution(w, d)
+    A = ex["A"]
+    rhs = np.concatenate([ex["r"][:, None], Z], axis=1)
+    ocg = okrylov.cg(lambda X: A @ X, rhs, fixed_iters=50, n_lanczos=30)
+    X = t64(rec.X).T
+    X32 = _cg_fp32_replay(A, rhs, 50).astype(np.float64)
+    rel32 = np.linalg.norm(X - X32, axis=0) / np.linalg.norm(X32, axis=0)
+    rel64 = np.linalg.norm(X - ocg["X"], axis=0) / np.linalg.norm(ocg["X"], axis=0)
+    q50 = ex["r"] @ ocg["X"][:, 0]
+    print(f"vs FP32 replay {rel32.max():.2e}; vs FP64 CG {rel64.max():.2e}; quad(50) gpu {h['quad']:.4f} "
+          f"fp32-replay {ex['r'] @ X32[:, 0]:.4f} fp64 {q50:.4f} cholesky {ex['quad']:.4f}")
+    assert rel32.max() < 1e-2
+    assert math.isclose(h["quad"], ex["r"] @ X32[:, 0], rel_tol=2e-3)
+    # both runs are 50-step approximations of the same solve: residual norms comparable
+    tr_gpu = np.linalg.norm(rhs - A @ X, axis=0) / np.linalg.norm(rhs, axis=0)
+    tr_64 = np.linalg.norm(rhs - A @ ocg["X"], axis=0) / np.linalg.norm(rhs, axis=0)
+    assert np.all(tr_gpu <= 2.0 * tr_64 + 1e-6)
+
+
+@pytest.mark.parametrize("index,n,ss", [(0, None, None), (1, 40, 2)])
+def test_evidence_converged_vs_cholesky(G, index, n, ss):
+    w, d, _ = observation(index, 0, n, ss)
+    _say("evidence", w.name, w.n, w.ss)
+    prob = gpu_problem(w)
+    m = 16
+    Z = synth.rademacher(w.n_pix, m, index)
+    rec = G.reconstruct(prob, cuda32(d), cuda32(Z.T), tol=1e-6, max_iter=2000, n_lanczos=30)
+    h = rec.host()
+    ex = _oracle_solution(w, d)
+    assert all(s == 0 for s in h["status"]), h["status"]
+    assert max(h["relres"]) <= 1e-6
+    quad_rel = abs(h["quad"] - ex["quad"]) / ex["quad"]
+    ld_err = h["logdet"] - ex["logdet"]
+    print(f"quad rel {quad_rel:.2e}; logdet err {ld_err:.3f} (stderr {h['stderr']:.3f}); "
+          f"lnp gpu {h['lnp']:.4f} exact {ex['lnp']:.4f}; iters {max(h['iters'])}")
+    assert quad_rel <= 1e-5
+    assert abs(ld_err) <= 4 * h["stderr"] + 1e-6 * abs(ex["logdet"])
+    # posterior mean and predicted image
+    fh = t64(rec.fhat)
+    assert np.max(np.abs(fh - ex["fhat"])) <= 1e-4 * np.max(np.abs(ex["fhat"]))
+    im = t64(rec.image)
+    assert np.max(np.abs(im - ex["image"])) <= 1e-4 * np.max(np.abs(ex["image"]))
+    vi_rel = abs(h["vi"] - ex["vi"]) / abs(ex["vi"])
+    assert vi_rel <= 1e-5
+
+
+def test_evidence_exact_trace_mode_1e4(G):
+    """All unit probes and every CG step in the quadrature: the log-determinant is
+    deterministic and ln p must match the Cholesky value to 1e-4 relative."""
+    w, d, _ = observation(0)
+    _say("exact-trace evidence", w.name)
+    prob = gpu_problem(w)
+    E = np.eye(w.n_pix, dtype=np.float32)
+    rec = G.reconstruct(prob, cuda32(d), cuda32(E), tol=1e-7, max_iter=2000, n_lanczos=2000, logdet_scale=1.0,
+                        want_image=False)
+    h = rec.host()
+    ex = _oracle_solution(w, d)
+    rel = abs(h["lnp"] - ex["lnp"]) / abs(ex["lnp"])
+    print(f"lnp gpu {h['lnp']:.6f} exact {ex['lnp']:.6f} rel {rel:.2e}; logdet {h['logdet']:.4f} vs "
+          f"{ex['logdet']:.4f}")
+    assert rel <= 1e-4
