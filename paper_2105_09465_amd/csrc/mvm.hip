@@ -22,6 +22,7 @@
 namespace gpl {
 
 constexpr int kTJ = 256;
+constexpr int kFp32MfmaMinCols = 4;
 
 struct MvmPlan {
   int R;        // rows per lane
@@ -170,9 +171,13 @@ static int valu_launch(float s2, float amp2, int n, const float* px, const float
   return GPL_OK;
 }
 
+// FP32 form: FMA accumulation on the VALU for a few columns, FP32 MFMA beyond.
+static bool fp32_on_mfma(int nrhs) { return nrhs >= kFp32MfmaMinCols; }
+
 size_t mvm_workspace(int n, int nrhs, int prec) {
   if (n <= 0 || nrhs <= 0) return 0;
   if (prec == GPL_PREC_F16X3) return mfma_f16x3_workspace(n, nrhs);
+  if (fp32_on_mfma(nrhs)) return mfma_f32_workspace(n, nrhs);
   return valu_workspace(n, nrhs);
 }
 
@@ -183,6 +188,8 @@ int mvm_launch(double lengthscale, double amplitude, int n, const float* px, con
   const float amp2 = (float)(amplitude * amplitude);
   if (prec == GPL_PREC_F16X3)
     return mfma_f16x3_launch(s2, amp2, n, px, py, nrhs, V, ldv, Y, ldy, beta, ws, ws_bytes, gate, stream);
+  if (fp32_on_mfma(nrhs))
+    return mfma_f32_launch(s2, amp2, n, px, py, nrhs, V, ldv, Y, ldy, beta, ws, ws_bytes, gate, stream);
   return valu_launch(s2, amp2, n, px, py, nrhs, V, ldv, Y, ldy, beta, ws, ws_bytes, gate, stream);
 }
 

@@ -11,4 +11,8 @@ size_t mfma_f16x3_workspace(int n, int nrhs);
 int mfma_f16x3_launch(float s2, float amp2, int n, const float* px, const float* py, int nrhs, const float* V, int ldv,
                       float* Y, int ldy, float beta, void* ws, size_t ws_bytes, CgGate gate, hipStream_t stream);
 
+size_t mfma_f32_workspace(int n, int nrhs);
+int mfma_f32_launch(float s2, float amp2, int n, const float* px, const float* py, int nrhs, const float* V, int ldv,
+                    float* Y, int ldy, float beta, void* ws, size_t ws_bytes, CgGate gate, hipStream_t stream);
+
 }  // namespace gpl

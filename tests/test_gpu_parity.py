@@ -195,6 +195,55 @@ def test_kernel_mvm_fp32_full_size_sampled(G):
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (257, 3), (1000, 4), (3001, 17), (4096, 16), (5003, 33), (2500, 64),
+                                    (1500, 65)])
+def test_kernel_mvm_fp32_mfma_parity(G, n, nrhs):
+    """Several columns take the FP32 MFMA path; same bound as the VALU path."""
+    _say("mvm fp32 (mfma for >= 4 columns)", n, nrhs)
+    err = _mvm_case(G, n, nrhs, "fp32", seed=7)
+    print(f"max |err| / (|K||V|) = {err:.2e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (257, 3), (1000, 1), (3001, 17), (4096, 16), (5003, 33), (2500, 64),
+                                    (1500, 65)])
+def test_kernel_mvm_f16x3_parity(G, n, nrhs):
+    """Precision form: FP16 hi/lo split of the exp tile and of the RHS, three MFMA
+    terms, FP32 accumulation. Bound: 1e-5 of |K||V| per entry, as the FP32 form."""
+    _say("mvm f16x3", n, nrhs)
+    err = _mvm_case(G, n, nrhs, "f16x3", seed=11)
+    print(f"max |err| / (|K||V|) = {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_kernel_mvm_f16x3_full_size_sampled(G):
+    """N = 160,000 (the 200x200, ss = 2 workload), 64 columns, 200 sampled rows."""
+    _say("mvm f16x3 N=160000 x 64")
+    rows = np.random.default_rng(2).choice(160000, 200, replace=False)
+    err = _mvm_case(G, 160000, 64, "f16x3", spread=2.0, rows=rows, seed=3)
+    print(f"max |err| / (|K||V|) = {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_kernel_mvm_f16x3_wide_dynamic_range(G):
+    """RHS columns of very different magnitudes (per-column scaling) and entries
+    spanning many decades within a column."""
+    _say("mvm f16x3 dynamic range")
+    rng = np.random.default_rng(9)
+    n = 3000
+    px = rng.uniform(-0.5, 0.5, n).astype(np.float32)
+    py = rng.uniform(-0.5, 0.5, n).astype(np.float32)
+    V = rng.standard_normal((5, n)) * np.array([1e-12, 1e-3, 1.0, 1e4, 1e20])[:, None]
+    V[2] *= 10.0 ** rng.uniform(-8, 0, n)
+    V = V.astype(np.float32)
+    Y = G.ops.kernel_mvm(G.Kernel(0.04, 0.3), cuda32(px), cuda32(py), cuda32(V), prec="f16x3")
+    torch.cuda.synchronize()
+    P64 = (px.astype(np.float64), py.astype(np.float64))
+    want = okernel.kernel_mvm(*P64, V.astype(np.float64).T, 0.04, 0.3)
+    scale = okernel.kernel_abs_mvm_rows(*P64, np.arange(n), V.astype(np.float64).T, 0.04, 0.3)
+    assert np.max(np.abs(t64(Y).T - want) / scale) <= 1e-5
+
+
 def test_kernel_mvm_beta_accumulate(G):
     _say("mvm beta")
     rng = np.random.default_rng(5)
