@@ -1,0 +1,242 @@
+#!/usr/bin/env python
+"""Throughput of the lensed-source GP evidence path on one MI355X.
+
+One step = one full reconstruction of the 100x100-pixel image with 2x2
+supersampling (N = 40,000 source points): ray tracing, Sersic mean, residual,
+CG on the solve column plus 16 Rademacher probes (tolerance 1e-6), SLQ
+log-determinant from 30 Lanczos steps, evidence scalars, posterior mean and
+predicted image. The observation comes from the stored oracle simulation of
+that workload; everything in the timed region runs in the HIP library with the
+inputs already in HBM.
+
+Prints one JSON line. `value` is the kernel-pair throughput of the whole step
+(N^2 pairs per product with K, summed over the step's products, over the step
+time). Extra fields: reconstructions/s of both arithmetic forms, the roofline
+of the dominant kernel, and the FP64 oracle timed on the host as a baseline.
+
+    python bench.py [--steps K] [--warmup W] [--prec f16x3|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FIXTURE = os.path.join(ROOT, "tests", "fixtures", "workload1_draw0.npz")
+METRIC = "kernel-MVM Gpairs/s at N=40k; reconstructions/s + p99 latency vs plain form"
+
+# Peak of the plain ALUs for the exp tile ("Roofline"): 256 CUs x
+# 128 FP32 lanes x 2.4 GHz = 78.6 T FP32 VALU lane-ops/s (157.3 TFLOP/s counting
+# an FMA as two); v_exp_f32 at a quarter of that rate. One kernel pair needs at
+# least 5 FP32 VALU ops (two differences, a square, an FMA, the scale) and one
+# exp, i.e. 5 + 4 = 9 FP32-op equivalents -> 78.6e12 / 9 pairs/s.
+VALU_LANE_OPS = 256 * 128 * 2.4e9
+PAIR_COST = 5 + 4
+ALU_PEAK_GPAIRS = VALU_LANE_OPS / PAIR_COST / 1e9
+
+# HBM traffic of the dominant kernel per launch at this workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration (profiles/), valid
+# only for the kernel source it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mvm_f16x3_traffic_N40000_17cols.txt")
+
+
+def _source_hash():
+    h = hashlib.sha256()
+    for f in ("mvm_mfma.hip", "mvm_mfma.hpp"):
+        with open(os.path.join(ROOT, "paper_2105_09465_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic():
+    try:
+        vals = {}
+        for line in open(TRAFFIC_FILE):
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+        if vals.get("source_sha256_16") != _source_hash():
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def load_workload():
+    import numpy as np
+
+    import paper_2105_09465_amd as G
+    z = np.load(FIXTURE)
+    src = z["source"]
+    prob = G.Problem(G.Grid(int(z["n"]), int(z["ss"]), float(z["pix_scale"])), G.Lens(*z["lens"].tolist()),
+                     G.Sersic(*src.tolist()), G.Kernel(float(z["ell"]), float(z["amp"])), G.PSF(float(z["fwhm"])),
+                     float(z["sigma"]))
+    return prob, z
+
+
+def cpu_baseline(prob, px, py, budget_s=15.0):
+    """The FP64 oracle's matrix-free product on a sample of rows (same points,
+    17 columns), on the host's cores; Gpairs/s scaled from the sample."""
+    import numpy as np
+    from oracle import kernel as okernel
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        blas_threads = 1
+    N = px.size
+    V = np.random.default_rng(0).standard_normal((N, 17))
+    rows_done, t0 = 0, time.time()
+    block = 1024
+    while time.time() - t0 < budget_s and rows_done < N:
+        rows = np.arange(rows_done, min(N, rows_done + block))
+        okernel.kernel_mvm_rows(px, py, rows, V, prob.kernel.lengthscale, prob.kernel.amplitude)
+        rows_done += rows.size
+    dt = time.time() - t0
+    return {"value": rows_done * N / dt / 1e9, "unit": "Gpairs/s", "cores": int(blas_threads), "kind": "oracle",
+            "sample": f"{rows_done} of {N} rows of K V with 17 columns (FP64 numpy, oracle.kernel.kernel_mvm_rows; "
+                      f"exp on 1 thread, products on {blas_threads} BLAS threads), {dt:.1f} s; host has "
+                      f"{os.cpu_count()} logical CPUs"}
+
+
+def run_steps(G, torch, prob, d, probes, prec, steps, ws):
+    recs, times = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rec = G.reconstruct(prob, d, probes, prec=prec, tol=1e-6, max_iter=1000, n_lanczos=30, ws=ws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        recs.append(rec)
+    return recs, times
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="f16x3", choices=["f16x3", "fp32"])
+    ap.add_argument("--plain-steps", type=int, default=3, help="timed steps of the plain FP32 form (0: skip)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs on a single MI355X)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2105_09465_amd as G
+    import synth
+
+    torch.cuda.set_device(0)
+    prob, z = load_workload()
+    N, npix = prob.grid.N, prob.grid.n_pix
+    d = torch.as_tensor(z["d"], dtype=torch.float32, device="cuda")
+    probes = torch.as_tensor(synth.rademacher(npix, 16, 1).T.copy(), dtype=torch.float32, device="cuda")
+    ws = None
+
+    # ---- precision form: warmup, then the timed region with kernel timing on
+    run_steps(G, torch, prob, d, probes, args.prec, args.warmup, ws)
+    G.ops.timing_read(reset=True)
+    G.ops.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs, times = run_steps(G, torch, prob, d, probes, args.prec, args.steps, ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    G.ops.timing_enable(False)
+    mvm_ms, mvm_launches = G.ops.timing_read(reset=True)
+    hosts = [r.host() for r in recs]
+    iters = [max(h["iters"]) for h in hosts]
+    # products with K per step: one per CG iteration (all 17 columns) + the posterior mean
+    pairs_per_step = [(it + 1) * N * N for it in iters]
+    value = sum(pairs_per_step) / elapsed / 1e9
+    ms_per_step = elapsed / args.steps * 1e3
+    # the dominant kernel: the 17-column product inside CG; launches after the
+    # last active iteration exit at once and are counted in the time but not as
+    # launches (conservative)
+    cg_launches = sum(iters)
+    post_ms = 0.0
+    avg_ms = (mvm_ms - post_ms) / max(cg_launches, 1)
+    achieved = N * N / (avg_ms * 1e-3) / 1e9
+
+    # ---- the dominant kernel alone, same shape and stream, for the rocprof cross-check
+    V = torch.randn(17, N, device="cuda")
+    px, py = recs[-1].px, recs[-1].py
+    Y = torch.empty_like(V)
+    for _ in range(2):
+        G.ops.kernel_mvm(prob.kernel, px, py, V, prec=args.prec, out=Y)
+    torch.cuda.synchronize()
+    G.ops.timing_read(reset=True)
+    G.ops.timing_enable(True)
+    for _ in range(10):
+        G.ops.kernel_mvm(prob.kernel, px, py, V, prec=args.prec, out=Y)
+    G.ops.timing_enable(False)
+    alone_ms, alone_n = G.ops.timing_read(reset=True)
+    alone_avg = alone_ms / max(alone_n, 1)
+
+    # ---- accuracy of this run against the stored oracle evidence
+    h = hosts[-1]
+    lnp_rel = abs(h["lnp"] - float(z["lnp"])) / abs(float(z["lnp"]))
+
+    # ---- plain FP32 form, same step
+    plain = None
+    if args.plain_steps > 0 and args.prec != "fp32":
+        run_steps(G, torch, prob, d, probes, "fp32", 1, ws)
+        t0 = time.perf_counter()
+        precs, ptimes = run_steps(G, torch, prob, d, probes, "fp32", args.plain_steps, ws)
+        pel = time.perf_counter() - t0
+        ph = [r.host() for r in precs]
+        pit = [max(x["iters"]) for x in ph]
+        plain = {"value": sum((it + 1) * N * N for it in pit) / pel / 1e9, "unit": "Gpairs/s",
+                 "reconstructions_per_s": args.plain_steps / pel, "ms_per_step": pel / args.plain_steps * 1e3,
+                 "cg_iters": pit[-1], "lnp_rel_err_vs_oracle": abs(ph[-1]["lnp"] - float(z["lnp"])) / abs(float(z["lnp"]))}
+
+    cpu = None
+    if args.cpu_budget > 0:
+        cpu = cpu_baseline(prob, px.double().cpu().numpy(), py.double().cpu().numpy(), args.cpu_budget)
+
+    traffic = _traffic()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16x3" if args.prec == "f16x3" else "f32",
+        "data": "synthetic (oracle-simulated lensed Sersic + RBF-GP source, seeded)",
+        "config": {"workload": "100x100 px image, 2x2 supersampling (N=40000 points), SPLE+shear lens prior draw, "
+                               "Gaussian PSF FWHM 0.1\", 1 solve + 16 Rademacher probe columns, CG tol 1e-6, "
+                               "30 Lanczos steps", "N": N, "n_pix": npix, "rhs": 17},
+        "reconstructions_per_s": args.steps / elapsed,
+        "cg_iters": iters[-1],
+        "lnp_rel_err_vs_oracle": lnp_rel,
+        "slq_stderr": h["stderr"],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GPAIRS, "unit": "Gpairs/s",
+                     "frac": achieved / ALU_PEAK_GPAIRS, "traffic": traffic,
+                     "kernel": "mvm_f16x3_kernel" if args.prec == "f16x3" else "mvm_f32mfma_kernel",
+                     "avg_launch_ms_in_step": avg_ms, "avg_launch_ms_alone": alone_avg,
+                     "mfma_tflops": 2.0 * N * N * 17 / (avg_ms * 1e-3) / 1e12},
+        "plain_fp32": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,21 @@ int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, cons
 int gpl_evidence_scalars(int n_pix, int n_points, const float* r, const float* u, const double* logdet,
                          double amplitude, double noise_sigma, double* out, hipStream_t stream);
 
+/* Column-wise dot products in FP64: out[c] = sum_i X[c*ldx + i] * Y[c*ldy + i],
+ * c < ncols, i < n. Used for quadratic forms and trace estimates
+ * (z_j . A^{-1} z_j) of the evidence and its gradient. */
+int gpl_block_dot(int n, int ncols, const float* X, int ldx, const float* Y, int ldy, double* out,
+                  hipStream_t stream);
+
+/* Opt-in timing of the kernel-product launches (main product kernel only, not
+ * its preparation or reduction), for measuring achieved rates: while enabled,
+ * every such launch on this host thread is bracketed by HIP events recorded on
+ * its stream. gpl_timing_read waits for the recorded events (host wait, no
+ * device synchronisation), returns the summed elapsed milliseconds and launch
+ * count since the last reset, and resets them if `reset` is non-zero. */
+int gpl_timing_enable(int on);
+int gpl_timing_read(double* total_ms, long* launches, int reset);
+
 /* ---------------------------------------------------------------- backward */
 
 /* Gradient of F = sum_c w[c] a_c^T K b_c (a_c, b_c columns of A and Bv, n rows)

@@ -1,6 +1,7 @@
 """Build the gplens HIP library for gfx950: one object per source, then link.
 
-Usage: python -m paper_2105_09465_amd.build  (or import and call build()).
+Usage: python paper_2105_09465_amd/build.py (run by path, so the package and its
+previously built library are not imported first).
 Produces paper_2105_09465_amd/libgplens.so next to this file.
 """
 from __future__ import annotations

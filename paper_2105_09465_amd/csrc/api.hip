@@ -45,9 +45,31 @@ __global__ void evidence_scalars_kernel(int n_pix, int n_points, const float* r,
   }
 }
 
+// out[c] = sum_i X[c][i] * Y[c][i] in FP64, one workgroup per column.
+__global__ __launch_bounds__(256) void block_dot_kernel(int n, const float* __restrict__ X, int ldx,
+                                                        const float* __restrict__ Y, int ldy, double* out) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += (double)X[(size_t)c * ldx + i] * (double)Y[(size_t)c * ldy + i];
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) out[c] = s;
+}
+
 }  // namespace gpl
 
 using namespace gpl;
+
+extern "C" int gpl_block_dot(int n, int ncols, const float* X, int ldx, const float* Y, int ldy, double* out,
+                             hipStream_t stream) {
+  GPL_REQUIRE(n >= 0 && ncols >= 0, "negative size");
+  if (ncols == 0) return GPL_OK;
+  GPL_REQUIRE(X && Y && out, "NULL argument");
+  GPL_REQUIRE(ldx >= n && ldy >= n, "ldx/ldy must be >= n");
+  hipLaunchKernelGGL(block_dot_kernel, dim3(ncols), dim3(256), 0, stream, n, X, ldx, Y, ldy, out);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
 
 extern "C" const char* gpl_strerror(int code) {
   switch (code) {

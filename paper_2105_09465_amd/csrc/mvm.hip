@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "internal.hpp"
 #include "mvm_mfma.hpp"
+#include "timing.hpp"
 
 namespace gpl {
 
@@ -153,6 +154,7 @@ static int valu_launch(float s2, float amp2, int n, const float* px, const float
   for (int c0 = 0; c0 < nrhs;) {
     const int left = nrhs - c0;
     const int nc = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    hipEvent_t t0 = timing_begin(stream);
     switch (nc) {
       case 16: launch_valu<16>(p, n, px, py, s2, V, ldv, c0, out, ldo, nrhs, direct, amp2, beta, gate, stream); break;
       case 8: launch_valu<8>(p, n, px, py, s2, V, ldv, c0, out, ldo, nrhs, direct, amp2, beta, gate, stream); break;
@@ -161,6 +163,7 @@ static int valu_launch(float s2, float amp2, int n, const float* px, const float
       default: launch_valu<1>(p, n, px, py, s2, V, ldv, c0, out, ldo, nrhs, direct, amp2, beta, gate, stream); break;
     }
     GPL_LAUNCH_CHECK();
+    timing_end(t0, stream);
     c0 += nc;
   }
   if (!direct) {

@@ -23,10 +23,12 @@
 // in FP32 on v_mfma_f32_16x16x4_f32.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.hpp"
 #include "internal.hpp"
 #include "mvm_mfma.hpp"
+#include "timing.hpp"
 
 namespace gpl {
 
@@ -59,21 +61,19 @@ static MfmaPlan mfma_plan(int n, int nrhs) {
 
 // ---------------------------------------------------------------- RHS preparation
 
-__global__ void zero_u32_kernel(unsigned* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
-// Column-wise max |V| as the bit pattern of a non-negative float (atomicMax on
-// those bits is order independent).
-__global__ void colmax_kernel(int n, const float* __restrict__ V, int ldv, unsigned* colmax, CgGate gate) {
+// Column-wise max |V|, one workgroup per column, stored as the bit pattern of a
+// non-negative float.
+__global__ __launch_bounds__(256) void colmax_kernel(int n, const float* __restrict__ V, int ldv, unsigned* colmax,
+                                                     CgGate gate) {
   if (gate.skip_all()) return;
-  const int c = blockIdx.y;
+  __shared__ float red[4];
+  const int c = blockIdx.x;
   float m = 0.f;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    m = fmaxf(m, fabsf(V[(size_t)c * ldv + i]));
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(V[(size_t)c * ldv + i]));
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(colmax + c, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) colmax[c] = __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
 }
 
 // V' = V * 2^e_c split into FP16 hi (nearest) and lo; zero padding for j >= n
@@ -112,7 +112,7 @@ __device__ inline half8 pack_rtz(const float* k) {
   return r;
 }
 
-template <int CB>
+template <int CB, int JT, bool RR>
 __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __restrict__ px,
                                                         const float* __restrict__ py, float s2,
                                                         const _Float16* __restrict__ Vh,
@@ -121,9 +121,9 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __re
                                                         CgGate gate) {
   if (gate.skip_all()) return;
   constexpr int NCP = CB * 16;
-  constexpr int LDSJ = kJT + 8;  // halves per LDS row (padding against bank conflicts)
-  __shared__ __attribute__((aligned(16))) float sxj[kJT];
-  __shared__ __attribute__((aligned(16))) float syj[kJT];
+  constexpr int LDSJ = JT + 8;  // halves per LDS row (padding against bank conflicts)
+  __shared__ __attribute__((aligned(16))) float sxj[JT];
+  __shared__ __attribute__((aligned(16))) float syj[JT];
   __shared__ __attribute__((aligned(16))) _Float16 sVh[NCP * LDSJ];
   __shared__ __attribute__((aligned(16))) _Float16 sVl[NCP * LDSJ];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -144,17 +144,17 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __re
 
   const int jbeg = blockIdx.y * jlen;
   const int jend = min(n, jbeg + jlen);
-  for (int jt = jbeg; jt < jend; jt += kJT) {
+  for (int jt = jbeg; jt < jend; jt += JT) {
     __syncthreads();
-    {
-      const int j = jt + tid;
-      sxj[tid] = j < n ? px[j] : 0.f;
-      syj[tid] = j < n ? py[j] : 0.f;
+    for (int t = tid; t < JT; t += 256) {
+      const int j = jt + t;
+      sxj[t] = j < n ? px[j] : 0.f;
+      syj[t] = j < n ? py[j] : 0.f;
     }
-    // RHS tiles: NCP columns x 256 points, 8 halves per load (buffers are padded
-    // with zeros up to ldh >= jt + 256)
-    for (int idx = tid; idx < NCP * (kJT / 8); idx += 256) {
-      const int c = idx / (kJT / 8), j8 = (idx - c * (kJT / 8)) * 8;
+    // RHS tiles: NCP columns x JT points, 8 halves per load (buffers are padded
+    // with zeros up to ldh >= jt + JT)
+    for (int idx = tid; idx < NCP * (JT / 8); idx += 256) {
+      const int c = idx / (JT / 8), j8 = (idx - c * (JT / 8)) * 8;
       *reinterpret_cast<half8*>(&sVh[c * LDSJ + j8]) =
           *reinterpret_cast<const half8*>(&Vh[(size_t)c * ldh + jt + j8]);
       *reinterpret_cast<half8*>(&sVl[c * LDSJ + j8]) =
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __re
     }
     __syncthreads();
 #pragma unroll 1
-    for (int s = 0; s < kJT / 32; ++s) {
+    for (int s = 0; s < JT / 32; ++s) {
       const int jl = s * 32 + g * 8;  // this lane's 8 consecutive source points
       float xj[8], yj[8];
       *reinterpret_cast<f32x4*>(&xj[0]) = *reinterpret_cast<const f32x4*>(&sxj[jl]);
@@ -176,24 +176,62 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __re
         bh[cb] = *reinterpret_cast<const half8*>(&sVh[c * LDSJ + jl]);
         bl[cb] = *reinterpret_cast<const half8*>(&sVl[c * LDSJ + jl]);
       }
+      if constexpr (RR) {
+        // all row tiles' A operands first, then MFMAs round-robin over the
+        // independent accumulators
+        half8 ah[kRT], al[kRT];
 #pragma unroll
-      for (int rt = 0; rt < kRT; ++rt) {
-        float k[8], lo[8];
+        for (int rt = 0; rt < kRT; ++rt) {
+          float k[8], lo[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float dx = xi[rt] - xj[e], dy = yi[rt] - yj[e];
-          const float d2 = fmaf(dx, dx, dy * dy);
-          k[e] = exp2_fast(fmaf(d2, -s2, 11.f));  // 2^11 k
+          for (int e = 0; e < 8; ++e) {
+            const float dx = xi[rt] - xj[e], dy = yi[rt] - yj[e];
+            const float d2 = fmaf(dx, dx, dy * dy);
+            k[e] = exp2_fast(fmaf(d2, -s2, 11.f));  // 2^11 k
+          }
+          ah[rt] = pack_rtz(k);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) lo[e] = k[e] - (float)ah[rt][e];
+          al[rt] = pack_rtz(lo);
         }
-        const half8 hi = pack_rtz(k);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) lo[e] = k[e] - (float)hi[e];
-        const half8 lo8 = pack_rtz(lo);
+        for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, bh[cb], acc[rt][cb], 0, 0, 0);
-          acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, bl[cb], acc[rt][cb], 0, 0, 0);
-          acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo8, bh[cb], acc[rt][cb], 0, 0, 0);
+          for (int cb = 0; cb < CB; ++cb)
+            acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rt], bh[cb], acc[rt][cb], 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[rt], bl[cb], acc[rt][cb], 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[rt], bh[cb], acc[rt][cb], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt) {
+          float k[8], lo[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float dx = xi[rt] - xj[e], dy = yi[rt] - yj[e];
+            const float d2 = fmaf(dx, dx, dy * dy);
+            k[e] = exp2_fast(fmaf(d2, -s2, 11.f));  // 2^11 k
+          }
+          const half8 hi = pack_rtz(k);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) lo[e] = k[e] - (float)hi[e];
+          const half8 lo8 = pack_rtz(lo);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, bh[cb], acc[rt][cb], 0, 0, 0);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, bl[cb], acc[rt][cb], 0, 0, 0);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo8, bh[cb], acc[rt][cb], 0, 0, 0);
         }
       }
     }
@@ -332,11 +370,24 @@ size_t mfma_f16x3_workspace(int n, int nrhs) {
   return s.used;
 }
 
+template <int CB, int JT, bool RR>
+static void launch_f16x3_v(const MfmaPlan& p, int n, const float* px, const float* py, float s2, const _Float16* Vh,
+                           const _Float16* Vl, float* part, CgGate gate, hipStream_t stream) {
+  hipLaunchKernelGGL((mvm_f16x3_kernel<CB, JT, RR>), dim3(p.nrb, p.S), dim3(256), 0, stream, n, px, py, s2, Vh, Vl,
+                     p.ldh, p.jlen, part, p.ldp, p.cb * 16, gate);
+}
+
 template <int CB>
 static void launch_f16x3(const MfmaPlan& p, int n, const float* px, const float* py, float s2, const _Float16* Vh,
                          const _Float16* Vl, float* part, CgGate gate, hipStream_t stream) {
-  hipLaunchKernelGGL((mvm_f16x3_kernel<CB>), dim3(p.nrb, p.S), dim3(256), 0, stream, n, px, py, s2, Vh, Vl, p.ldh,
-                     p.jlen, part, p.ldp, p.cb * 16, gate);
+  static const int env_v = getenv("GPLENS_F16X3_VARIANT") ? atoi(getenv("GPLENS_F16X3_VARIANT")) : -1;
+  const int v = env_v >= 0 ? env_v : (CB >= 3 ? 2 : 0);
+  switch (v & 3) {
+    case 0: launch_f16x3_v<CB, 256, false>(p, n, px, py, s2, Vh, Vl, part, gate, stream); break;
+    case 1: launch_f16x3_v<CB, 256, true>(p, n, px, py, s2, Vh, Vl, part, gate, stream); break;
+    case 2: launch_f16x3_v<CB, 128, false>(p, n, px, py, s2, Vh, Vl, part, gate, stream); break;
+    default: launch_f16x3_v<CB, 128, true>(p, n, px, py, s2, Vh, Vl, part, gate, stream); break;
+  }
 }
 
 static constexpr int kMaxCB = 4;  // up to 64 columns per pass
@@ -352,10 +403,7 @@ int mfma_f16x3_launch(float s2, float amp2, int n, const float* px, const float*
   carve_f16x3(cv, p, &colmax, &inv_scale, &Vh, &Vl, &part);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   const int ncp = p.cb * 16;
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(cdiv(ncp, 256)), dim3(256), 0, stream, colmax, ncp);
-  GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(colmax_kernel, dim3(std::min(cdiv(n, 256), 64), nrhs), dim3(256), 0, stream, n, V, ldv, colmax,
-                     gate);
+  hipLaunchKernelGGL(colmax_kernel, dim3(nrhs), dim3(256), 0, stream, n, V, ldv, colmax, gate);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(split_rhs_kernel, dim3(cdiv(p.ldh, 256), ncp), dim3(256), 0, stream, n, nrhs, V, ldv, colmax, Vh,
                      Vl, p.ldh, inv_scale, gate);
@@ -367,6 +415,7 @@ int mfma_f16x3_launch(float s2, float amp2, int n, const float* px, const float*
     const _Float16* vl = Vl + (size_t)c0 * p.ldh;
     // part layout [S][ncp][ldp]; this pass writes columns c0 .. c0 + 16 cb of every slice
     float* pp = part + (size_t)c0 * p.ldp;
+    hipEvent_t t0 = timing_begin(stream);
     switch (cb) {
       case 4: launch_f16x3<4>(p, n, px, py, s2, vh, vl, pp, gate, stream); break;
       case 3: launch_f16x3<3>(p, n, px, py, s2, vh, vl, pp, gate, stream); break;
@@ -374,6 +423,7 @@ int mfma_f16x3_launch(float s2, float amp2, int n, const float* px, const float*
       default: launch_f16x3<1>(p, n, px, py, s2, vh, vl, pp, gate, stream); break;
     }
     GPL_LAUNCH_CHECK();
+    timing_end(t0, stream);
   }
   hipLaunchKernelGGL(mfma_reduce_kernel, dim3(cdiv(n, 256), nrhs), dim3(256), 0, stream, n, nrhs, ncp, p.S, part,
                      p.ldp, inv_scale, amp2, Y, ldy, beta, gate);
@@ -405,6 +455,7 @@ int mfma_f32_launch(float s2, float amp2, int n, const float* px, const float* p
     const float* v = V + (size_t)c0 * ldv;
     float* pp = part + (size_t)c0 * p.ldp;
     const int ncols = std::min(nrhs - c0, cb * 16);
+    hipEvent_t t0 = timing_begin(stream);
     switch (cb) {
       case 4: launch_f32mfma<4>(p, n, px, py, s2, v, ldv, ncols, pp, gate, stream); break;
       case 3: launch_f32mfma<3>(p, n, px, py, s2, v, ldv, ncols, pp, gate, stream); break;
@@ -412,6 +463,7 @@ int mfma_f32_launch(float s2, float amp2, int n, const float* px, const float* p
       default: launch_f32mfma<1>(p, n, px, py, s2, v, ldv, ncols, pp, gate, stream); break;
     }
     GPL_LAUNCH_CHECK();
+    timing_end(t0, stream);
   }
   hipLaunchKernelGGL(mfma_reduce_kernel, dim3(cdiv(n, 256), nrhs), dim3(256), 0, stream, n, nrhs, ncp, p.S, part,
                      p.ldp, nullptr, amp2, Y, ldy, beta, gate);

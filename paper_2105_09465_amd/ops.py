@@ -182,6 +182,17 @@ def evidence_scalars(n_pix, n_points, r, u, logdet, amplitude, noise_sigma):
     return out
 
 
+def block_dot(X, Y):
+    """Per-column FP64 dot products of two (ncols, n) blocks."""
+    n = X.shape[-1]
+    X2 = X.unsqueeze(0) if X.dim() == 1 else X
+    Y2 = Y.unsqueeze(0) if Y.dim() == 1 else Y
+    ldx, ldy = _block(X2, n, "X"), _block(Y2, n, "Y")
+    out = torch.empty(X2.shape[0], dtype=torch.float64, device=X.device)
+    _lib.call("gpl_block_dot", n, X2.shape[0], _ptr(X2), ldx, _ptr(Y2), ldy, _ptr(out), _stream())
+    return out
+
+
 # ------------------------------------------------------------------ backward
 
 def kernel_mvm_backward(kernel: Kernel, px, py, A, Bv, weights, gpx=None, gpy=None):
@@ -221,3 +232,16 @@ def sersic_backward(src: Sersic, px, py, gmu, gpx, gpy):
     _lib.call("gpl_sersic_backward", C.byref(s), n, _ptr(px), _ptr(py), _ptr(gmu), _ptr(gpx), _ptr(gpy), _ptr(out),
               _wsptr(ws), wsb, _stream())
     return out
+
+
+# ------------------------------------------------------------------ timing
+
+def timing_enable(on: bool = True):
+    _lib.call("gpl_timing_enable", 1 if on else 0)
+
+
+def timing_read(reset: bool = True):
+    """(total milliseconds, launches) of the timed kernel-product launches."""
+    ms, n = C.c_double(0.0), C.c_long(0)
+    _lib.call("gpl_timing_read", C.byref(ms), C.byref(n), 1 if reset else 0)
+    return ms.value, n.value

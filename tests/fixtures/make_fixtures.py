@@ -1,0 +1,42 @@
+"""Write the stored inputs and expected values of the full-size workload.
+
+Runs only the FP64 oracle (and synth for the seeded draws). For the 100x100
+image with 2x2 supersampling (N = 40,000 source points, the first prior draw of
+that workload) it stores the simulated observation d, the exact Cholesky
+evidence terms, the variational objective and the predicted image.
+
+    python tests/fixtures/make_fixtures.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import data, evidence  # noqa: E402
+
+
+def make(index=1, sub=0):
+    w = synth.workload(index, sub)
+    s = w.source
+    P = evidence.Problem(w.n, w.ss, w.pix_scale, w.lens.as_tuple(), (s.peak, s.R_e, s.n_sersic, s.xs, s.ys), w.ell,
+                         w.amp, w.noise_sigma, w.psf_fwhm)
+    t = time.time()
+    d, _ = data.simulate(P, synth.noise_normals(w.n_pix, index, sub), rff=synth.rff_draws(8192, index, sub))
+    out = evidence.solve_problem(P, d)
+    path = os.path.join(HERE, f"workload{index}_draw{sub}.npz")
+    np.savez_compressed(path, d=d, image=out["image"], lnp=out["lnp"], quad=out["quad"], logdet=out["logdet"],
+                        vi=out["vi"], lens=np.array(w.lens.as_tuple()), source=np.array([s.peak, s.R_e, s.n_sersic,
+                                                                                         s.xs, s.ys]),
+                        n=w.n, ss=w.ss, pix_scale=w.pix_scale, ell=w.ell, amp=w.amp, sigma=w.noise_sigma,
+                        fwhm=w.psf_fwhm)
+    print(f"{path}: lnp {out['lnp']:.6f} quad {out['quad']:.6f} logdet {out['logdet']:.6f} "
+          f"({time.time() - t:.0f} s)")
+
+
+if __name__ == "__main__":
+    make()

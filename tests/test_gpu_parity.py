@@ -397,3 +397,30 @@ def test_evidence_exact_trace_mode_1e4(G):
     print(f"lnp gpu {h['lnp']:.6f} exact {ex['lnp']:.6f} rel {rel:.2e}; logdet {h['logdet']:.4f} vs "
           f"{ex['logdet']:.4f}")
     assert rel <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "fp32"])
+def test_evidence_full_size_vs_stored_oracle(G, prec):
+    """The 100x100, ss = 2 workload (N = 40,000) against the oracle's exact
+    Cholesky evidence stored by tests/fixtures/make_fixtures.py: quad within 1e-5,
+    the 16-probe SLQ log-determinant within 4 of its standard errors, predicted
+    image within 1e-4 of its maximum."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "fixtures", "workload1_draw0.npz")
+    z = np.load(path)
+    w = synth.workload(1)
+    _say("full size evidence", prec)
+    prob = gpu_problem(w)
+    Z = synth.rademacher(w.n_pix, 16, 1)
+    rec = G.reconstruct(prob, cuda32(z["d"]), cuda32(Z.T), prec=prec, tol=1e-6, max_iter=1000, n_lanczos=30)
+    h = rec.host()
+    quad_rel = abs(h["quad"] - float(z["quad"])) / float(z["quad"])
+    ld_err = h["logdet"] - float(z["logdet"])
+    lnp_rel = abs(h["lnp"] - float(z["lnp"])) / abs(float(z["lnp"]))
+    print(f"{prec}: iters {max(h['iters'])} quad rel {quad_rel:.2e} logdet err {ld_err:.2f} (stderr "
+          f"{h['stderr']:.2f}) lnp rel {lnp_rel:.2e}")
+    assert all(s == 0 for s in h["status"])
+    assert quad_rel <= 1e-5
+    assert abs(ld_err) <= 4 * h["stderr"]
+    im = t64(rec.image)
+    assert np.max(np.abs(im - z["image"])) <= 1e-4 * np.max(np.abs(z["image"]))
