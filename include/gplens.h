@@ -225,6 +225,51 @@ size_t gpl_sersic_backward_workspace(int n);
 int gpl_sersic_backward(const gpl_source* src, int n, const float* px, const float* py, const float* gmu, float* gpx,
                         float* gpy, double* g_src, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------- serving
+ * A continuous-batching request loop keeps every admitted reconstruction (a
+ * slot) resident in its own device workspace: points, residual and probe
+ * columns, CG vectors and state, Lanczos coefficients. gpl_serve_step advances
+ * any set of slots by a number of CG iterations; each stage of an iteration is
+ * ONE grouped launch over the tiles of all those slots, so requests of uneven
+ * sizes share the device. Results of a slot do not depend on which other slots
+ * it is batched with (bitwise). Iteration counters are global: iteration k of
+ * the loop uses state parity k & 1, and a slot may join at any k. */
+typedef struct {
+  void* ws;       /* the slot's device workspace (set by init) */
+  void* dev;      /* device address of the slot descriptor inside ws (set by init) */
+  int N, npix, nrhs;
+  unsigned char opaque[1024]; /* host copy of the descriptor (library use) */
+} gpl_serve_slot;
+
+/* Bytes of device workspace of one slot (nrhs <= 32 columns: the solve column
+ * plus nrhs - 1 probes). This is the slot's HBM footprint for admission. */
+size_t gpl_serve_slot_workspace(const gpl_grid* grid, int nrhs, int n_lanczos, int prec);
+
+/* Admit one request into `ws`: ray tracing, Sersic mean, residual d - B mu in
+ * column 0, probes (nrhs - 1 columns, ld ldz) after it, CG initial state. prob
+ * supplies grid, kernel, PSF and noise (its px/py are ignored). Enqueued on
+ * `stream`; d and probes may be reused once the stream has passed this call. */
+int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob, const gpl_lens* lens, const gpl_source* src,
+                        const float* d, const float* probes, int ldz, int nrhs, double tol, int max_iter,
+                        int n_lanczos, int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Advance the slots (host array of nslots <= 64 pointers) by `iters` CG
+ * iterations, the first being global iteration iter0. Slots whose columns have
+ * all stopped do no work. */
+int gpl_serve_step(gpl_serve_slot* const* slots, int nslots, int iters, long iter0, hipStream_t stream);
+
+/* Write each slot's number of still-active columns after global iteration
+ * `iter` - 1 (i.e. at parity iter & 1) to host_active[s], a host buffer the
+ * device can write (pinned, mapped). Read it after the stream passes this call. */
+int gpl_serve_snapshot(gpl_serve_slot* const* slots, int nslots, long iter, int* host_active, hipStream_t stream);
+
+/* Finish a slot whose columns have stopped, `iter` being the global iteration
+ * count reached: out[0..4] = quad, ln p, L_VI, ln|A| (SLQ, scale logdet_scale),
+ * its standard error; iters/relres/status per column (device, nrhs entries);
+ * optionally the posterior mean fhat (N) and the predicted image (n*n). */
+int gpl_serve_slot_finish(gpl_serve_slot* slot, long iter, double logdet_scale, double* out, int* iters,
+                          double* relres, int* status, float* fhat, float* image, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,11 @@ class gpl_problem(C.Structure):
                 ("px", C.c_void_p), ("py", C.c_void_p)]
 
 
+class gpl_serve_slot(C.Structure):
+    _fields_ = [("ws", C.c_void_p), ("dev", C.c_void_p), ("N", C.c_int), ("npix", C.c_int), ("nrhs", C.c_int),
+                ("opaque", C.c_ubyte * 1024)]
+
+
 _P = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -85,6 +90,12 @@ SIGNATURES = {
     "gpl_sersic_backward": (_I, [C.POINTER(gpl_source), _I, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "gpl_block_dot": (_I, [_I, _I, _P, _I, _P, _I, _P, _P]),
     "gpl_timing_enable": (_I, [_I]),
+    "gpl_serve_slot_workspace": (_Z, [C.POINTER(gpl_grid), _I, _I, _I]),
+    "gpl_serve_slot_init": (_I, [C.POINTER(gpl_serve_slot), C.POINTER(gpl_problem), C.POINTER(gpl_lens),
+                                 C.POINTER(gpl_source), _P, _P, _I, _I, _D, _I, _I, _I, _P, _Z, _P]),
+    "gpl_serve_step": (_I, [C.POINTER(C.POINTER(gpl_serve_slot)), _I, _I, C.c_long, _P]),
+    "gpl_serve_snapshot": (_I, [C.POINTER(C.POINTER(gpl_serve_slot)), _I, C.c_long, _P, _P]),
+    "gpl_serve_slot_finish": (_I, [C.POINTER(gpl_serve_slot), C.c_long, _D, _P, _P, _P, _P, _P, _P, _P]),
     "gpl_timing_read": (_I, [C.POINTER(_D), C.POINTER(C.c_long), _I]),
 }
 

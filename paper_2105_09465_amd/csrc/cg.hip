@@ -22,15 +22,6 @@
 
 namespace gpl {
 
-struct ColState {
-  double rr;     // r.r of the current residual
-  double alpha;  // alpha of the step that produced this state
-  int active;
-  int iters;
-  int status;
-  int bad;  // set by update1 when p.Ap <= 0 or non-finite
-};
-
 struct CgBuffers {
   float *R, *P, *AP, *T1, *T2;
   int ldv, ldf;
@@ -122,16 +113,14 @@ __global__ void cg_init_state_kernel(int nrhs, const double* part, int nb, ColSt
 
 // alpha = rr / pAp (redundantly in every block, fixed order), X += alpha P,
 // R -= alpha AP, partial r.r of the new residual.
-__global__ __launch_bounds__(256) void cg_update1_kernel(int npix, float* X, int ldx, float* R, const float* P,
-                                                         const float* AP, int ldv, const double* pap_part,
-                                                         int ntiles, double* rr_part, int nb, const ColState* sin,
-                                                         ColState* sout, const int* n_active_in,
-                                                         int* n_active_out) {
+__device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* X, int ldx, float* R,
+                                                const float* P, const float* AP, int ldv, const double* pap_part,
+                                                int ntiles, double* rr_part, int nb, const ColState* sin,
+                                                ColState* sout, const int* n_active_in, int* n_active_out) {
   __shared__ double red[4];
   __shared__ double s_alpha;
   __shared__ int s_ok;
-  const int c = blockIdx.y;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *n_active_out = 0;
+  if (bx == 0 && c == 0 && threadIdx.x == 0) *n_active_out = 0;
   if (*n_active_in == 0) return;
   const ColState st = sin[c];
   if (!st.active) return;
@@ -142,14 +131,14 @@ __global__ __launch_bounds__(256) void cg_update1_kernel(int npix, float* X, int
     const int ok = (pap > 0.0) && isfinite(a);
     s_alpha = ok ? a : 0.0;
     s_ok = ok;
-    if (blockIdx.x == 0) {
+    if (bx == 0) {
       sout[c].alpha = s_alpha;
       sout[c].bad = ok ? 0 : (isfinite(pap) ? 1 : 2);
     }
   }
   __syncthreads();
   const double alpha = s_alpha;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   double s = 0.0;
   if (s_ok && i < npix) {
     const float af = (float)alpha;
@@ -160,22 +149,30 @@ __global__ __launch_bounds__(256) void cg_update1_kernel(int npix, float* X, int
     s = (double)r * r;
   }
   s = block_sum_double(s, red);
-  if (threadIdx.x == 0) rr_part[(size_t)c * nb + blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_part[(size_t)c * nb + bx] = s;
+}
+
+__global__ __launch_bounds__(256) void cg_update1_kernel(int npix, float* X, int ldx, float* R, const float* P,
+                                                         const float* AP, int ldv, const double* pap_part,
+                                                         int ntiles, double* rr_part, int nb, const ColState* sin,
+                                                         ColState* sout, const int* n_active_in,
+                                                         int* n_active_out) {
+  cg_update1_body(blockIdx.x, blockIdx.y, npix, X, ldx, R, P, AP, ldv, pap_part, ntiles, rr_part, nb, sin, sout,
+                  n_active_in, n_active_out);
 }
 
 // beta = rr_new / rr, P = R + beta P; block 0 of each column records the Lanczos
 // coefficients and decides the column's status for the next iteration.
-__global__ __launch_bounds__(256) void cg_update2_kernel(int npix, const float* R, float* P, int ldv,
-                                                         const double* rr_part, int nb, const ColState* sin,
-                                                         ColState* sout, const double* bb, const int* n_active_in,
-                                                         int* n_active_out, double tol, int max_iter,
-                                                         int fixed_iters, int n_lanczos, double* ab) {
+__device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const float* R, float* P, int ldv,
+                                                const double* rr_part, int nb, const ColState* sin, ColState* sout,
+                                                const double* bb, const int* n_active_in, int* n_active_out,
+                                                double tol, int max_iter, int fixed_iters, int n_lanczos,
+                                                double* ab) {
   __shared__ double s_beta;
   __shared__ int s_go;
-  const int c = blockIdx.y;
   const ColState st = sin[c];
   if (*n_active_in == 0 || !st.active) {  // carry the state into the other parity
-    if (blockIdx.x == 0 && threadIdx.x == 0) sout[c] = st;
+    if (bx == 0 && threadIdx.x == 0) sout[c] = st;
     return;
   }
   if (threadIdx.x == 0) {
@@ -200,7 +197,7 @@ __global__ __launch_bounds__(256) void cg_update2_kernel(int npix, const float* 
       go = 1;
       nx.rr = rr_new;
       nx.iters = st.iters + 1;
-      if (blockIdx.x == 0 && st.iters < n_lanczos) {
+      if (bx == 0 && st.iters < n_lanczos) {
         double* e = ab + ((size_t)c * n_lanczos + st.iters) * 2;
         e[0] = half.alpha;
         e[1] = beta;
@@ -217,17 +214,43 @@ __global__ __launch_bounds__(256) void cg_update2_kernel(int npix, const float* 
     }
     s_beta = beta;
     s_go = go;
-    if (blockIdx.x == 0) {
+    if (bx == 0) {
       sout[c] = nx;
       if (nx.active) atomicAdd(n_active_out, 1);
     }
   }
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   if (s_go && i < npix) {
     const size_t iv = (size_t)c * ldv + i;
     P[iv] = fmaf((float)s_beta, P[iv], R[iv]);
   }
+}
+
+__global__ __launch_bounds__(256) void cg_update2_kernel(int npix, const float* R, float* P, int ldv,
+                                                         const double* rr_part, int nb, const ColState* sin,
+                                                         ColState* sout, const double* bb, const int* n_active_in,
+                                                         int* n_active_out, double tol, int max_iter,
+                                                         int fixed_iters, int n_lanczos, double* ab) {
+  cg_update2_body(blockIdx.x, blockIdx.y, npix, R, P, ldv, rr_part, nb, sin, sout, bb, n_active_in, n_active_out, tol,
+                  max_iter, fixed_iters, n_lanczos, ab);
+}
+
+// ---- grouped launches (serving): workgroup (local % nb, local / nb) of slot s.
+__global__ __launch_bounds__(256) void cg_update1_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  const int local = blockIdx.x - B.off[s];
+  cg_update1_body(local % S.nb_upd, local / S.nb_upd, S.npix, S.X, S.ldv, S.R, S.P, S.AP, S.ldv, S.pap_part,
+                  S.ntiles_fwd, S.rr_part, S.nb_upd, S.st[p], S.st[1 - p], S.n_active + p, S.n_active + (1 - p));
+}
+
+__global__ __launch_bounds__(256) void cg_update2_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  const int local = blockIdx.x - B.off[s];
+  cg_update2_body(local % S.nb_upd, local / S.nb_upd, S.npix, S.R, S.P, S.ldv, S.rr_part, S.nb_upd, S.st[p],
+                  S.st[1 - p], S.bb, S.n_active + p, S.n_active + (1 - p), S.tol, S.max_iter, 0, S.n_lanczos, S.ab);
 }
 
 __global__ void cg_snapshot_kernel(const int* n_active, volatile int* host_flag) {
@@ -252,6 +275,43 @@ __global__ void cg_finalize_kernel(int nrhs, const ColState* st, const double* b
       ab[((size_t)c * n_lanczos + k) * 2 + 0] = 0.0;
       ab[((size_t)c * n_lanczos + k) * 2 + 1] = 0.0;
     }
+}
+
+int cg_update_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                      hipStream_t stream) {
+  SlotBatch B;
+  B.nslots = nslots;
+  B.off[0] = 0;
+  for (int s = 0; s < nslots; ++s) {
+    B.slot[s] = dslots[s];
+    B.off[s + 1] = B.off[s] + hslots[s]->nb_upd * hslots[s]->nrhs;
+  }
+  if (B.off[nslots] == 0) return GPL_OK;
+  hipLaunchKernelGGL(cg_update1_grouped_kernel, dim3(B.off[nslots]), dim3(256), 0, stream, B, p);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(cg_update2_grouped_kernel, dim3(B.off[nslots]), dim3(256), 0, stream, B, p);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int cg_init_launch(int npix, int nrhs, const float* Bm, int ldb, float* X, int ldx, float* R, float* P, int ldv,
+                   double* part, ColState* st0, ColState* st1, double* bb, int* n_active, int limit,
+                   hipStream_t stream) {
+  const int nb = cdiv(npix, 256);
+  hipLaunchKernelGGL(cg_init_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, Bm, ldb, X, ldx, R, P, ldv, part, nb);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(cg_init_state_kernel, dim3(1), dim3(256), 0, stream, nrhs, part, nb, st0, st1, bb, n_active,
+                     limit);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int cg_finalize_launch(int nrhs, const ColState* st, const double* bb, double* bnorm2, int* iters, double* relres,
+                       int* status, int n_lanczos, double* ab, hipStream_t stream) {
+  hipLaunchKernelGGL(cg_finalize_kernel, dim3(cdiv(nrhs, 256)), dim3(256), 0, stream, nrhs, st, bb, bnorm2, iters,
+                     relres, status, n_lanczos, ab);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
 }
 
 // Host polling resources, one set per host thread.

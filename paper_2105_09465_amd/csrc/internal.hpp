@@ -25,6 +25,57 @@ struct CgGate {
   __device__ bool skip_all() const { return n_active && *n_active == 0; }
 };
 
+struct ColState {
+  double rr;     // r.r of the current residual
+  double alpha;  // alpha of the step that produced this state
+  int active;
+  int iters;
+  int status;
+  int bad;  // set by update1 when p.Ap <= 0 or non-finite
+};
+
+// Device-resident descriptor of one request in the serving loop (stored at the
+// start of the request's workspace). Every grouped kernel reads its slot's
+// sizes and buffers from here.
+struct ServeSlotDev {
+  int n, ss, npix, N, nrhs, prec;
+  Taps taps;
+  float sigma2, s2, amp2;
+  const float *px, *py;
+  float *X, *R, *P, *AP, *T1, *T2;
+  int ldv, ldf;
+  unsigned* colmax;
+  float* inv_scale;
+  _Float16 *Vh, *Vl;
+  float* part;
+  int ldh, ldp, S, jlen, nrb;
+  ColState* st[2];
+  double* bb;
+  int* n_active;  // [2]
+  double *pap_part, *rr_part;
+  int ntiles_fwd, ntiles_adj, nb_upd;
+  double* ab;
+  int n_lanczos, max_iter;
+  double tol;
+  double ell, amp, sigma;  // kernel hyperparameters and noise in FP64
+};
+
+constexpr int kMaxServeSlots = 64;
+constexpr int kColmaxBlocks = 32;  // workgroups per column of the column-max pass
+
+// Kernel argument naming the slots of one grouped launch: slot s owns the
+// workgroups [off[s], off[s+1]) of the launch.
+struct SlotBatch {
+  int nslots;
+  int off[kMaxServeSlots + 1];
+  const ServeSlotDev* slot[kMaxServeSlots];
+  __device__ int find(int b) const {
+    int s = 0;
+    while (s + 1 < nslots && off[s + 1] <= b) ++s;
+    return s;
+  }
+};
+
 int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t);
 int psf_forward_tiles(int n, int ss);
 int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* in, int ld_in, float* out, int ld_out,
@@ -40,5 +91,25 @@ int mvm_launch(double lengthscale, double amplitude, int n, const float* px, con
                hipStream_t stream);
 
 int check_kernel(const gpl_kernel* k);
+
+// Grouped launches of one CG iteration's kernels over the slots of a batch
+// (parity p selects the state buffers). Each returns GPL_OK or GPL_EHIP.
+int psf_adjoint_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                        hipStream_t stream);
+int psf_forward_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                        hipStream_t stream);
+int mvm_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                hipStream_t stream);
+int cg_update_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                      hipStream_t stream);
+int cg_init_launch(int npix, int nrhs, const float* Bm, int ldb, float* X, int ldx, float* R, float* P, int ldv,
+                   double* part, ColState* st0, ColState* st1, double* bb, int* n_active, int limit,
+                   hipStream_t stream);
+int cg_finalize_launch(int nrhs, const ColState* st, const double* bb, double* bnorm2, int* iters, double* relres,
+                       int* status, int n_lanczos, double* ab, hipStream_t stream);
+// Sizes of the product workspace of one slot (CB = 2 column blocks).
+void serve_mvm_plan(int N, int* S, int* jlen, int* nrb, int* ldh, int* ldp);
+int psf_adjoint_tiles(int n, int ss);
+size_t valu_mvm_workspace(int n, int nrhs);
 
 }  // namespace gpl

@@ -143,6 +143,8 @@ static size_t valu_workspace(int n, int nrhs) {
   return p.S > 1 ? align_up(sizeof(float) * (size_t)p.S * nrhs * p.ldp) : 0;
 }
 
+size_t valu_mvm_workspace(int n, int nrhs) { return valu_workspace(n, nrhs); }
+
 static int valu_launch(float s2, float amp2, int n, const float* px, const float* py, int nrhs, const float* V,
                        int ldv, float* Y, int ldy, float beta, void* ws, size_t ws_bytes, CgGate gate,
                        hipStream_t stream) {

@@ -61,32 +61,41 @@ static MfmaPlan mfma_plan(int n, int nrhs) {
 
 // ---------------------------------------------------------------- RHS preparation
 
-// Column-wise max |V|, one workgroup per column, stored as the bit pattern of a
-// non-negative float.
-__global__ __launch_bounds__(256) void colmax_kernel(int n, const float* __restrict__ V, int ldv, unsigned* colmax,
-                                                     CgGate gate) {
-  if (gate.skip_all()) return;
+// Column-wise max |V| in two steps without atomics: kColmaxBlocks workgroups per
+// column write partial maxima (as bit patterns of non-negative floats); the
+// split kernel folds them (kColmaxBlocks workgroups per column).
+
+__device__ __forceinline__ void colmax_body(int bx, int c, int n, const float* __restrict__ V, int ldv,
+                                            unsigned* partial) {
   __shared__ float red[4];
-  const int c = blockIdx.x;
   float m = 0.f;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(V[(size_t)c * ldv + i]));
+  for (int i = bx * blockDim.x + threadIdx.x; i < n; i += kColmaxBlocks * blockDim.x)
+    m = fmaxf(m, fabsf(V[(size_t)c * ldv + i]));
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) colmax[c] = __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+  if (threadIdx.x == 0)
+    partial[c * kColmaxBlocks + bx] = __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+}
+
+__global__ __launch_bounds__(256) void colmax_kernel(int n, const float* __restrict__ V, int ldv, unsigned* partial,
+                                                     CgGate gate) {
+  if (gate.skip_all()) return;
+  colmax_body(blockIdx.x, blockIdx.y, n, V, ldv, partial);
 }
 
 // V' = V * 2^e_c split into FP16 hi (nearest) and lo; zero padding for j >= n
 // and c >= nrhs; inv_scale[c] = 2^-e_c / 2^11 folds both scales for the output.
-__global__ void split_rhs_kernel(int n, int nrhs, const float* __restrict__ V, int ldv, const unsigned* colmax,
-                                 _Float16* Vh, _Float16* Vl, int ldh, float* inv_scale, CgGate gate) {
-  if (gate.skip_all()) return;
-  const int c = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void split_rhs_body(int bx, int c, int n, int nrhs, const float* __restrict__ V, int ldv,
+                                               const unsigned* colmax, _Float16* Vh, _Float16* Vl, int ldh,
+                                               float* inv_scale) {
+  const int j = bx * blockDim.x + threadIdx.x;
   if (j >= ldh) return;
   int e = 0;
   if (c < nrhs) {
-    const float mx = __uint_as_float(colmax[c]);
+    unsigned mb = 0u;
+    for (int b = 0; b < kColmaxBlocks; ++b) mb = max(mb, colmax[c * kColmaxBlocks + b]);
+    const float mx = __uint_as_float(mb);
     if (mx > 0.f && isfinite(mx)) e = 14 - ilogbf(mx) - 1;  // mx * 2^e in [2^13, 2^14)
   }
   const float scale = ldexpf(1.f, e);
@@ -96,6 +105,12 @@ __global__ void split_rhs_kernel(int n, int nrhs, const float* __restrict__ V, i
   const _Float16 l = (_Float16)(v - (float)h);
   Vh[(size_t)c * ldh + j] = h;
   Vl[(size_t)c * ldh + j] = l;
+}
+
+__global__ void split_rhs_kernel(int n, int nrhs, const float* __restrict__ V, int ldv, const unsigned* colmax,
+                                 _Float16* Vh, _Float16* Vl, int ldh, float* inv_scale, CgGate gate) {
+  if (gate.skip_all()) return;
+  split_rhs_body(blockIdx.x, blockIdx.y, n, nrhs, V, ldv, colmax, Vh, Vl, ldh, inv_scale);
 }
 
 // ---------------------------------------------------------------- precision form
@@ -113,13 +128,11 @@ __device__ inline half8 pack_rtz(const float* k) {
 }
 
 template <int CB, int JT, bool RR>
-__global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __restrict__ px,
-                                                        const float* __restrict__ py, float s2,
-                                                        const _Float16* __restrict__ Vh,
-                                                        const _Float16* __restrict__ Vl, int ldh, int jlen,
-                                                        float* __restrict__ part, int ldp, int slice_cols,
-                                                        CgGate gate) {
-  if (gate.skip_all()) return;
+__device__ __forceinline__ void mvm_f16x3_body(int bx, int by, int n, const float* __restrict__ px,
+                                               const float* __restrict__ py, float s2,
+                                               const _Float16* __restrict__ Vh, const _Float16* __restrict__ Vl,
+                                               int ldh, int jlen, float* __restrict__ part, int ldp,
+                                               int slice_cols) {
   constexpr int NCP = CB * 16;
   constexpr int LDSJ = JT + 8;  // halves per LDS row (padding against bank conflicts)
   __shared__ __attribute__((aligned(16))) float sxj[JT];
@@ -128,7 +141,7 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __re
   __shared__ __attribute__((aligned(16))) _Float16 sVl[NCP * LDSJ];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ri = lane & 15, g = lane >> 4;
-  const int row_base = blockIdx.x * kRowsWG + wave * (kRT * 16);
+  const int row_base = bx * kRowsWG + wave * (kRT * 16);
   float xi[kRT], yi[kRT];
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
@@ -142,7 +155,7 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __re
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int jbeg = blockIdx.y * jlen;
+  const int jbeg = by * jlen;
   const int jend = min(n, jbeg + jlen);
   for (int jt = jbeg; jt < jend; jt += JT) {
     __syncthreads();
@@ -245,19 +258,28 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __re
       for (int v = 0; v < 4; ++v) {
         const int i = row_base + rt * 16 + g * 4 + v;
         const int c = cb * 16 + ri;
-        if (i < n) part[((size_t)blockIdx.y * slice_cols + c) * ldp + i] = acc[rt][cb][v];
+        if (i < n) part[((size_t)by * slice_cols + c) * ldp + i] = acc[rt][cb][v];
       }
+}
+
+template <int CB, int JT, bool RR>
+__global__ __launch_bounds__(256) void mvm_f16x3_kernel(int n, const float* __restrict__ px,
+                                                        const float* __restrict__ py, float s2,
+                                                        const _Float16* __restrict__ Vh,
+                                                        const _Float16* __restrict__ Vl, int ldh, int jlen,
+                                                        float* __restrict__ part, int ldp, int slice_cols,
+                                                        CgGate gate) {
+  if (gate.skip_all()) return;
+  mvm_f16x3_body<CB, JT, RR>(blockIdx.x, blockIdx.y, n, px, py, s2, Vh, Vl, ldh, jlen, part, ldp, slice_cols);
 }
 
 // ---------------------------------------------------------------- FP32 form on MFMA
 
 template <int CB>
-__global__ __launch_bounds__(256) void mvm_f32mfma_kernel(int n, const float* __restrict__ px,
-                                                          const float* __restrict__ py, float s2,
-                                                          const float* __restrict__ V, int ldv, int nrhs, int jlen,
-                                                          float* __restrict__ part, int ldp, int slice_cols,
-                                                          CgGate gate) {
-  if (gate.skip_all()) return;
+__device__ __forceinline__ void mvm_f32mfma_body(int bx, int by, int n, const float* __restrict__ px,
+                                                 const float* __restrict__ py, float s2, const float* __restrict__ V,
+                                                 int ldv, int nrhs, int jlen, float* __restrict__ part, int ldp,
+                                                 int slice_cols) {
   constexpr int NCP = CB * 16;
   constexpr int LDSJ = kJT + 4;
   __shared__ __attribute__((aligned(16))) float sxj[kJT];
@@ -265,7 +287,7 @@ __global__ __launch_bounds__(256) void mvm_f32mfma_kernel(int n, const float* __
   __shared__ __attribute__((aligned(16))) float sV[NCP * LDSJ];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ri = lane & 15, g = lane >> 4;
-  const int row_base = blockIdx.x * kRowsWG + wave * (kRT * 16);
+  const int row_base = bx * kRowsWG + wave * (kRT * 16);
   float xi[kRT], yi[kRT];
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
@@ -279,7 +301,7 @@ __global__ __launch_bounds__(256) void mvm_f32mfma_kernel(int n, const float* __
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int jbeg = blockIdx.y * jlen;
+  const int jbeg = by * jlen;
   const int jend = min(n, jbeg + jlen);
   for (int jt = jbeg; jt < jend; jt += kJT) {
     __syncthreads();
@@ -326,17 +348,26 @@ __global__ __launch_bounds__(256) void mvm_f32mfma_kernel(int n, const float* __
       for (int v = 0; v < 4; ++v) {
         const int i = row_base + rt * 16 + g * 4 + v;
         const int c = cb * 16 + ri;
-        if (i < n) part[((size_t)blockIdx.y * slice_cols + c) * ldp + i] = acc[rt][cb][v];
+        if (i < n) part[((size_t)by * slice_cols + c) * ldp + i] = acc[rt][cb][v];
       }
 }
 
-// Y[c] = (amp2 * colscale[c]) * sum_s part[s][c] + beta Y[c], slices in order.
-__global__ void mfma_reduce_kernel(int n, int nrhs, int ncp, int S, const float* __restrict__ part, int ldp,
-                                   const float* __restrict__ colscale, float amp2, float* Y, int ldy, float beta,
-                                   CgGate gate) {
+template <int CB>
+__global__ __launch_bounds__(256) void mvm_f32mfma_kernel(int n, const float* __restrict__ px,
+                                                          const float* __restrict__ py, float s2,
+                                                          const float* __restrict__ V, int ldv, int nrhs, int jlen,
+                                                          float* __restrict__ part, int ldp, int slice_cols,
+                                                          CgGate gate) {
   if (gate.skip_all()) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
+  mvm_f32mfma_body<CB>(blockIdx.x, blockIdx.y, n, px, py, s2, V, ldv, nrhs, jlen, part, ldp, slice_cols);
+}
+
+// Y[c] = (amp2 * colscale[c]) * sum_s part[s][c] + beta Y[c], slices in order.
+__device__ __forceinline__ void mfma_reduce_body(int bx, int c, int n, int nrhs, int ncp, int S,
+                                                 const float* __restrict__ part, int ldp,
+                                                 const float* __restrict__ colscale, float amp2, float* Y, int ldy,
+                                                 float beta) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= n || c >= nrhs) return;
   float s = 0.f;
   for (int k = 0; k < S; ++k) s += part[((size_t)k * ncp + c) * ldp + i];
@@ -346,13 +377,64 @@ __global__ void mfma_reduce_kernel(int n, int nrhs, int ncp, int S, const float*
   *y = beta != 0.f ? res + beta * *y : res;
 }
 
+__global__ void mfma_reduce_kernel(int n, int nrhs, int ncp, int S, const float* __restrict__ part, int ldp,
+                                   const float* __restrict__ colscale, float amp2, float* Y, int ldy, float beta,
+                                   CgGate gate) {
+  if (gate.skip_all()) return;
+  mfma_reduce_body(blockIdx.x, blockIdx.y, n, nrhs, ncp, S, part, ldp, colscale, amp2, Y, ldy, beta);
+}
+
+// ---------------------------------------------------------------- grouped launches (serving)
+// One launch per stage over all slots of a batch; each slot uses 2 column
+// blocks (up to 32 right-hand sides) and its own slice plan, so its result does
+// not depend on the other slots.
+
+__global__ __launch_bounds__(256) void colmax_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  if (S.n_active[p] == 0 || S.prec != GPL_PREC_F16X3) return;
+  const int local = blockIdx.x - B.off[s];
+  colmax_body(local % kColmaxBlocks, local / kColmaxBlocks, S.N, S.T1, S.ldf, S.colmax);
+}
+
+__global__ void split_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  if (S.n_active[p] == 0 || S.prec != GPL_PREC_F16X3) return;
+  const int local = blockIdx.x - B.off[s];
+  const int per = (S.ldh + 255) / 256;
+  split_rhs_body(local % per, local / per, S.N, S.nrhs, S.T1, S.ldf, S.colmax, S.Vh, S.Vl, S.ldh, S.inv_scale);
+}
+
+__global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  if (S.n_active[p] == 0) return;
+  const int local = blockIdx.x - B.off[s];
+  const int bx = local % S.nrb, by = local / S.nrb;
+  if (S.prec == GPL_PREC_F16X3)
+    mvm_f16x3_body<2, 256, false>(bx, by, S.N, S.px, S.py, S.s2, S.Vh, S.Vl, S.ldh, S.jlen, S.part, S.ldp, 32);
+  else
+    mvm_f32mfma_body<2>(bx, by, S.N, S.px, S.py, S.s2, S.T1, S.ldf, S.nrhs, S.jlen, S.part, S.ldp, 32);
+}
+
+__global__ void reduce_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  if (S.n_active[p] == 0) return;
+  const int local = blockIdx.x - B.off[s];
+  const int per = (S.N + 255) / 256;
+  mfma_reduce_body(local % per, local / per, S.N, S.nrhs, 32, S.S, S.part, S.ldp,
+                   S.prec == GPL_PREC_F16X3 ? S.inv_scale : nullptr, S.amp2, S.T2, S.ldf, 0.f);
+}
+
 // ---------------------------------------------------------------- host side
 
 template <class C>
 static void carve_f16x3(C& cv, const MfmaPlan& p, unsigned** colmax, float** inv_scale, _Float16** Vh, _Float16** Vl,
                         float** part) {
   const int ncp = p.cb * 16;
-  *colmax = cv.template take<unsigned>(ncp);
+  *colmax = cv.template take<unsigned>((size_t)ncp * kColmaxBlocks);
   *inv_scale = cv.template take<float>(ncp);
   *Vh = cv.template take<_Float16>((size_t)ncp * p.ldh);
   *Vl = cv.template take<_Float16>((size_t)ncp * p.ldh);
@@ -403,7 +485,7 @@ int mfma_f16x3_launch(float s2, float amp2, int n, const float* px, const float*
   carve_f16x3(cv, p, &colmax, &inv_scale, &Vh, &Vl, &part);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   const int ncp = p.cb * 16;
-  hipLaunchKernelGGL(colmax_kernel, dim3(nrhs), dim3(256), 0, stream, n, V, ldv, colmax, gate);
+  hipLaunchKernelGGL(colmax_kernel, dim3(kColmaxBlocks, nrhs), dim3(256), 0, stream, n, V, ldv, colmax, gate);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(split_rhs_kernel, dim3(cdiv(p.ldh, 256), ncp), dim3(256), 0, stream, n, nrhs, V, ldv, colmax, Vh,
                      Vl, p.ldh, inv_scale, gate);
@@ -428,6 +510,48 @@ int mfma_f16x3_launch(float s2, float amp2, int n, const float* px, const float*
   hipLaunchKernelGGL(mfma_reduce_kernel, dim3(cdiv(n, 256), nrhs), dim3(256), 0, stream, n, nrhs, ncp, p.S, part,
                      p.ldp, inv_scale, amp2, Y, ldy, beta, gate);
   GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+void serve_mvm_plan(int N, int* S, int* jlen, int* nrb, int* ldh, int* ldp) {
+  const MfmaPlan p = mfma_plan(N, 32);
+  *S = p.S;
+  *jlen = p.jlen;
+  *nrb = p.nrb;
+  *ldh = p.ldh;
+  *ldp = p.ldp;
+}
+
+static int launch_grouped(void (*kern)(SlotBatch, int), const ServeSlotDev* const* hslots,
+                          const ServeSlotDev* const* dslots, int nslots, int p, int (*blocks)(const ServeSlotDev&),
+                          hipStream_t stream) {
+  SlotBatch B;
+  B.nslots = nslots;
+  B.off[0] = 0;
+  for (int s = 0; s < nslots; ++s) {
+    B.slot[s] = dslots[s];
+    B.off[s + 1] = B.off[s] + blocks(*hslots[s]);
+  }
+  if (B.off[nslots] == 0) return GPL_OK;
+  hipLaunchKernelGGL(kern, dim3(B.off[nslots]), dim3(256), 0, stream, B, p);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int mvm_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                hipStream_t stream) {
+  GPL_TRY(launch_grouped(colmax_grouped_kernel, hslots, dslots, nslots, p,
+                         [](const ServeSlotDev& S) { return S.prec == GPL_PREC_F16X3 ? kColmaxBlocks * S.nrhs : 0; },
+                         stream));
+  GPL_TRY(launch_grouped(split_grouped_kernel, hslots, dslots, nslots, p,
+                         [](const ServeSlotDev& S) { return S.prec == GPL_PREC_F16X3 ? (S.ldh + 255) / 256 * 32 : 0; },
+                         stream));
+  hipEvent_t t0 = timing_begin(stream);
+  GPL_TRY(launch_grouped(mvm_grouped_kernel, hslots, dslots, nslots, p,
+                         [](const ServeSlotDev& S) { return S.nrb * S.S; }, stream));
+  timing_end(t0, stream);
+  GPL_TRY(launch_grouped(reduce_grouped_kernel, hslots, dslots, nslots, p,
+                         [](const ServeSlotDev& S) { return (S.N + 255) / 256 * S.nrhs; }, stream));
   return GPL_OK;
 }
 

@@ -45,14 +45,11 @@ int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
 
 // Forward: out[I] = alpha * (B in)[I] + beta * out[I] + gamma * extra[I];
 // optional FP64 partial sums of dotv[I] * out[I] per (column, tile).
-__global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
-                                                          int ld_in, float* __restrict__ out, int ld_out,
-                                                          float alpha, float beta, const float* __restrict__ extra,
-                                                          int ld_extra, float gamma, const float* __restrict__ dotv,
-                                                          int ld_dotv, double* __restrict__ partial, int ntiles,
-                                                          CgGate gate) {
-  const int c = blockIdx.y;
-  if (gate.skip(c)) return;
+__device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss, const Taps& taps,
+                                                 const float* __restrict__ in, int ld_in, float* __restrict__ out,
+                                                 int ld_out, float alpha, float beta, const float* __restrict__ extra,
+                                                 int ld_extra, float gamma, const float* __restrict__ dotv,
+                                                 int ld_dotv, double* __restrict__ partial, int ntiles) {
   __shared__ float S1[kMaxWin * kMaxWin];
   __shared__ float S2[kMaxWin * kFineTile];
   __shared__ double red[4];
@@ -60,7 +57,7 @@ __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps ta
   const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;  // output pixels per tile side
   const int F = TP * ss, W = F + 2 * r;
   const int tiles_x = (n + TP - 1) / TP;
-  const int tile = blockIdx.x, ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
   for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
@@ -103,19 +100,28 @@ __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps ta
   }
 }
 
+__global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
+                                                          int ld_in, float* __restrict__ out, int ld_out,
+                                                          float alpha, float beta, const float* __restrict__ extra,
+                                                          int ld_extra, float gamma, const float* __restrict__ dotv,
+                                                          int ld_dotv, double* __restrict__ partial, int ntiles,
+                                                          CgGate gate) {
+  if (gate.skip(blockIdx.y)) return;
+  psf_forward_body(blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out, alpha, beta, extra, ld_extra, gamma,
+                   dotv, ld_dotv, partial, ntiles);
+}
+
 // Adjoint: out (fine) = alpha * P^T D^T in + beta * out; P^T is the correlation
 // with the taps: (P^T g)(y, x) = sum_{a,b} w_a w_b g(y + a, x + b).
-__global__ __launch_bounds__(256) void psf_adjoint_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
-                                                          int ld_in, float* __restrict__ out, int ld_out,
-                                                          float alpha, float beta, CgGate gate) {
-  const int c = blockIdx.y;
-  if (gate.skip(c)) return;
+__device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss, const Taps& taps,
+                                                 const float* __restrict__ in, int ld_in, float* __restrict__ out,
+                                                 int ld_out, float alpha, float beta) {
   __shared__ float S1[kMaxWin * kMaxWin];
   __shared__ float S2[kMaxWin * kFineTile];
   const int M = n * ss, r = taps.r;
   const int F = kFineTile, W = F + 2 * r;
   const int tiles_x = (M + F - 1) / F;
-  const int tile = blockIdx.x, ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
   const float inv_ss2 = 1.f / (float)(ss * ss);
@@ -143,6 +149,70 @@ __global__ __launch_bounds__(256) void psf_adjoint_kernel(int n, int ss, Taps ta
     if (beta != 0.f) res += beta * out[o_idx];
     out[o_idx] = res;
   }
+}
+
+__global__ __launch_bounds__(256) void psf_adjoint_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
+                                                          int ld_in, float* __restrict__ out, int ld_out,
+                                                          float alpha, float beta, CgGate gate) {
+  if (gate.skip(blockIdx.y)) return;
+  psf_adjoint_body(blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out, alpha, beta);
+}
+
+// ---- grouped launches (serving): workgroup b of slot s handles (tile, column) =
+// (local % tiles, local / tiles), local = b - off[s].
+
+__global__ __launch_bounds__(256) void psf_adjoint_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  if (S.n_active[p] == 0) return;
+  const int local = blockIdx.x - B.off[s];
+  const int tile = local % S.ntiles_adj, c = local / S.ntiles_adj;
+  if (S.st[p][c].active == 0) return;
+  psf_adjoint_body(tile, c, S.n, S.ss, S.taps, S.P, S.ldv, S.T1, S.ldf, 1.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void psf_forward_grouped_kernel(SlotBatch B, int p) {
+  const int s = B.find(blockIdx.x);
+  const ServeSlotDev& S = *B.slot[s];
+  if (S.n_active[p] == 0) return;
+  const int local = blockIdx.x - B.off[s];
+  const int tile = local % S.ntiles_fwd, c = local / S.ntiles_fwd;
+  if (S.st[p][c].active == 0) return;
+  psf_forward_body(tile, c, S.n, S.ss, S.taps, S.T2, S.ldf, S.AP, S.ldv, 1.f, 0.f, S.P, S.ldv, S.sigma2, S.P, S.ldv,
+                   S.pap_part, S.ntiles_fwd);
+}
+
+int psf_adjoint_tiles(int n, int ss) {
+  const int M = n * ss, t = (M + kFineTile - 1) / kFineTile;
+  return t * t;
+}
+
+static int grouped_launch(void (*kern)(SlotBatch, int), const ServeSlotDev* const* hslots,
+                          const ServeSlotDev* const* dslots, int nslots, int p, int (*tiles_of)(const ServeSlotDev&),
+                          hipStream_t stream) {
+  SlotBatch B;
+  B.nslots = nslots;
+  B.off[0] = 0;
+  for (int s = 0; s < nslots; ++s) {
+    B.slot[s] = dslots[s];
+    B.off[s + 1] = B.off[s] + tiles_of(*hslots[s]);
+  }
+  if (B.off[nslots] == 0) return GPL_OK;
+  hipLaunchKernelGGL(kern, dim3(B.off[nslots]), dim3(256), 0, stream, B, p);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int psf_adjoint_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                        hipStream_t stream) {
+  return grouped_launch(psf_adjoint_grouped_kernel, hslots, dslots, nslots, p,
+                        [](const ServeSlotDev& S) { return S.ntiles_adj * S.nrhs; }, stream);
+}
+
+int psf_forward_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
+                        hipStream_t stream) {
+  return grouped_launch(psf_forward_grouped_kernel, hslots, dslots, nslots, p,
+                        [](const ServeSlotDev& S) { return S.ntiles_fwd * S.nrhs; }, stream);
 }
 
 int psf_forward_tiles(int n, int ss) {

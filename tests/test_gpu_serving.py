@@ -1,0 +1,95 @@
+"""Continuous batching: each request's result is the same alone and in the mix
+(bitwise), equals the single-request path, admission respects the memory budget
+and stalled solves are reported rather than hung."""
+import numpy as np
+import pytest
+
+import synth
+
+from helpers import gpu_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_09465_amd as G
+    return G
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+SIZES = [(24, 1), (40, 2), (32, 1), (48, 2), (28, 2), (36, 1)]
+
+
+def _requests(G, sizes=SIZES, m=16):
+    reqs = []
+    for k, (side, ss) in enumerate(sizes):
+        w = synth.serving_request(side, ss, 1000 + k)
+        prob = gpu_problem(w)
+        d = G.serving.mock_observation(prob, synth.noise_normals(w.n_pix, 4, 1000 + k),
+                                       synth.gp_normals(w.N, 4, 1000 + k))
+        Z = torch.as_tensor(synth.rademacher(w.n_pix, m, 4, 1000 + k).T.copy(), dtype=torch.float32, device="cuda")
+        reqs.append(G.serving.Request(k, 0.0, prob, d, Z))
+    return reqs
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "fp32"])
+def test_alone_equals_mix_bitwise(G, prec):
+    _say("serving alone vs mix", prec)
+    reqs = _requests(G)
+    eng = G.serving.ServingEngine(prec=prec, max_slots=3, chunk=4, want_image=True)
+    mix = {r.rid: r for r in eng.run(reqs, realtime=False)}
+    assert len(mix) == len(reqs)
+    assert eng.stats["max_active"] == 3  # later requests joined while others ran
+    for req in reqs:
+        alone = G.serving.ServingEngine(prec=prec, max_slots=1, chunk=4, want_image=True).run([req], realtime=False)[0]
+        a, b = alone, mix[req.rid]
+        assert (a.quad, a.lnp, a.vi, a.logdet, a.stderr) == (b.quad, b.lnp, b.vi, b.logdet, b.stderr), req.rid
+        assert a.iters == b.iters and a.status == b.status
+        assert torch.equal(a.image, b.image)
+        assert all(s == 0 for s in a.status)
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "fp32"])
+def test_serving_matches_single_request_path(G, prec):
+    _say("serving vs reconstruct()", prec)
+    reqs = _requests(G, SIZES[:3])
+    res = {r.rid: r for r in G.serving.ServingEngine(prec=prec, want_image=True).run(reqs, realtime=False)}
+    for req in reqs:
+        rec = G.reconstruct(req.problem, req.d, req.probes, prec=prec, tol=1e-6, max_iter=1000, n_lanczos=1000)
+        h = rec.host()
+        r = res[req.rid]
+        print(req.rid, h["lnp"], r.lnp, h["iters"][:3], r.iters[:3])
+        assert h["iters"] == r.iters
+        assert h["lnp"] == r.lnp and h["quad"] == r.quad and h["logdet"] == r.logdet
+        assert torch.equal(rec.image, r.image)
+
+
+def test_admission_by_memory_budget(G):
+    _say("serving memory budget")
+    reqs = _requests(G)
+    eng = G.serving.ServingEngine(prec="f16x3")
+    fps = [eng.footprint(r) for r in reqs]
+    budget = max(fps) + min(fps)  # never room for three slots
+    eng = G.serving.ServingEngine(prec="f16x3", hbm_budget=budget)
+    res = eng.run(reqs, realtime=False)
+    assert len(res) == len(reqs)
+    assert eng.stats["max_bytes"] <= budget
+    assert eng.stats["max_active"] <= 2
+    assert eng.stats["deferred_memory"] > 0
+
+
+def test_stalled_solves_reported(G):
+    _say("serving max_iter")
+    reqs = _requests(G, SIZES[:2])
+    res = G.serving.ServingEngine(prec="f16x3", max_iter=5, chunk=4).run(reqs, realtime=False)
+    for r in res:
+        assert max(r.iters) <= 5
+        assert all(s == 1 for s in r.status)  # max_iter reached, reported per column
