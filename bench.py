@@ -170,6 +170,22 @@ def run_steps(G, torch, prob, d, probes, prec, steps, ws):
     return recs, times
 
 
+def kernel_only(G, torch, prec, reps):
+    """The dominant product alone (N = 40,000 points of the workload, 17 columns),
+    then a device copy of exactly 1 GiB whose byte counters calibrate HBM traffic."""
+    prob, _ = load_workload()
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    V = torch.randn(17, prob.grid.N, device="cuda")
+    Y = torch.empty_like(V)
+    for _ in range(reps):
+        G.ops.kernel_mvm(prob.kernel, pts[0], pts[1], V, prec=prec, out=Y)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_only": reps, "copy_bytes": src.numel() * 4}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +194,9 @@ def main():
     ap.add_argument("--prec", default="f16x3", choices=["f16x3", "fp32"])
     ap.add_argument("--plain-steps", type=int, default=3, help="timed steps of the plain FP32 form (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0: skip)")
+    ap.add_argument("--kernel-only", type=int, default=0,
+                    help="run only the dominant kernel this many times at the bench shape, then a 1 GiB copy "
+                         "(calibration of the HBM byte counters), and exit; for rocprofv3 counter runs")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests in the serving trace (0: skip; the full trace has 512)")
     args = ap.parse_args()
@@ -193,6 +212,9 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.kernel_only > 0:
+        kernel_only(G, torch, args.prec, args.kernel_only)
+        return
     prob, z = load_workload()
     N, npix = prob.grid.N, prob.grid.n_pix
     d = torch.as_tensor(z["d"], dtype=torch.float32, device="cuda")

@@ -165,13 +165,17 @@ int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, int ldb, fl
 
 /* Stochastic Lanczos quadrature of ln|A| from CG coefficients. Probe j uses the
  * first k_j = min(iters[j], n_lanczos) steps: the tridiagonal
- * T_kk = 1/a_k + b_{k-1}/a_{k-1}, T_{k,k+1} = sqrt(b_k)/a_k, eigen-decomposed
- * in FP64 (implicit QL); contrib[j] = bnorm2[j] * sum_i tau_i^2 ln theta_i.
+ * T_kk = 1/a_k + b_{k-1}/a_{k-1}, T_{k,k+1} = sqrt(b_k)/a_k, and
+ * contrib[j] = bnorm2[j] * e_1^T ln(T) e_1 (Gauss quadrature on T's Ritz
+ * values), evaluated in FP64 from the integral representation
+ * ln x = int e^s (1/(1+e^s) - 1/(x+e^s)) ds with the trapezoidal rule and
+ * continued-fraction resolvents of T.
  * logdet = scale * sum_j contrib[j] (scale 1/nprobe for Hutchinson probes,
  * 1 for all unit vectors); stderr = scale * sqrt(nprobe) * sd(contrib).
- * lanczos_ab, iters, bnorm2 as written by gpl_cg_solve (probe columns only).
- * Outputs (device): contrib[nprobe], logdet[1], stderr[1]. A probe whose
- * tridiagonal has a non-positive Ritz value contributes NaN. */
+ * lanczos_ab, iters, bnorm2 as written by gpl_cg_solve (probe columns only);
+ * n_lanczos <= 4096. Outputs (device): contrib[nprobe], logdet[1], stderr[1].
+ * A probe whose tridiagonal is not positive definite contributes NaN.
+ * The workspace size is 0 (ws may be NULL). */
 size_t gpl_lanczos_logdet_workspace(int nprobe, int n_lanczos);
 int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, const int* iters, const double* bnorm2,
                        double scale, double* contrib, double* logdet, double* stderr_out, void* ws, size_t ws_bytes,

@@ -2,86 +2,82 @@
 // stochastic log-determinant discussed in Sec. 3.3 for eq. "gp-mll").
 //
 // For probe j the k x k tridiagonal T implied by CG, T_kk = 1/a_k + b_{k-1}/a_{k-1},
-// T_{k,k+1} = sqrt(b_k)/a_k, is diagonalised in FP64 by implicit symmetric QR
-// steps with a Wilkinson shift (bulge chasing with Givens rotations), keeping
-// only the first row of the accumulated rotations: z^T ln(A) z is approximated
-// by |z|^2 sum_i q_i^2 ln(theta_i) (Gauss quadrature on the Ritz values theta_i
-// with weights q_i^2). One thread per probe; the per-probe arrays live in the
-// workspace. A second kernel sums the contributions in a fixed order.
+// T_{k,k+1} = sqrt(b_k)/a_k, gives z^T ln(A) z ~= |z|^2 e_1^T ln(T) e_1 (Gauss
+// quadrature on the Ritz values). Instead of diagonalising T, the quadratic form
+// is evaluated from the integral representation of the logarithm,
+//   ln x = int_R e^s [ 1/(1 + e^s) - 1/(x + e^s) ] ds,
+// so e_1^T ln(T) e_1 = int e^s [ 1/(1 + e^s) - e_1^T (T + e^s I)^{-1} e_1 ] ds.
+// The integrand is analytic in the strip |Im s| < pi (poles at s = ln x + i pi),
+// so the trapezoidal rule with step h converges like exp(-2 pi^2 / h); nodes run
+// from ln(x_hi) - 75 to ln(x_hi) + 38 (x_hi a Gershgorin bound), where the
+// integrand is below 1e-16. Each resolvent element (T + tI)^{-1}_{11} is a
+// continued fraction evaluated from the bottom of T (the pivots of an LDL^T
+// factorisation, all positive for t >= 0 when T is positive definite).
+// One wave per probe: the coefficients sit in LDS, lanes take the nodes, a
+// fixed-order reduction sums them (FP64 throughout).
 #include <cmath>
 
 #include "common.hpp"
 
 namespace gpl {
 
-// Eigenvalues (left in d) and first eigenvector components (q) of the
-// symmetric tridiagonal (d[0..m-1], e[0..m-2]).
-__device__ void tridiag_eig_first(int m, double* d, double* e, double* q) {
-  for (int i = 0; i < m; ++i) q[i] = (i == 0) ? 1.0 : 0.0;
-  int hi = m - 1;
-  int sweeps = 0;
-  const double eps = 2.220446049250313e-16;
-  while (hi > 0 && sweeps < 50 * m) {
-    // deflate converged eigenvalues at the bottom
-    if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) {
-      e[hi - 1] = 0.0;
-      --hi;
-      continue;
-    }
-    int lo = hi - 1;
-    while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
-    if (lo > 0) e[lo - 1] = 0.0;
-    // Wilkinson shift from the trailing 2x2 block
-    const double t = 0.5 * (d[hi - 1] - d[hi]);
-    const double bb = e[hi - 1] * e[hi - 1];
-    const double sgn = t >= 0.0 ? 1.0 : -1.0;
-    const double mu = d[hi] - bb / (t + sgn * sqrt(t * t + bb));
-    double x = d[lo] - mu, z = e[lo];
-    for (int k = lo; k < hi; ++k) {
-      const double r = hypot(x, z);
-      const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? z / r : 0.0;
-      if (k > lo) e[k - 1] = r;
-      const double ak = d[k], ak1 = d[k + 1], bk = e[k];
-      d[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
-      d[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
-      e[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
-      if (k + 1 < hi) {
-        x = e[k];
-        z = s * e[k + 1];
-        e[k + 1] = c * e[k + 1];
-      }
-      const double qk = q[k], qk1 = q[k + 1];
-      q[k] = c * qk + s * qk1;
-      q[k + 1] = -s * qk + c * qk1;
-    }
-    ++sweeps;
-  }
-}
+constexpr int kSlqMaxSteps = 4096;       // LDS capacity per probe (doubles x 2)
+constexpr double kSlqStep = 0.4;         // trapezoid step in s = ln t
+constexpr double kSlqLo = 75.0, kSlqHi = 38.0;
 
-__global__ void slq_probe_kernel(int nprobe, int n_lanczos, const double* __restrict__ ab, const int* __restrict__ iters,
-                                 const double* __restrict__ bnorm2, double* contrib, double* scratch) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nprobe) return;
+__global__ __launch_bounds__(64) void slq_probe_kernel(int nprobe, int n_lanczos, const double* __restrict__ ab,
+                                                       const int* __restrict__ iters,
+                                                       const double* __restrict__ bnorm2, double* contrib) {
+  __shared__ double diag[kSlqMaxSteps];
+  __shared__ double off2[kSlqMaxSteps];
+  __shared__ double s_hi;
+  __shared__ int s_ok;
+  const int j = blockIdx.x, lane = threadIdx.x;
   const int m = min(iters[j], n_lanczos);
-  double* d = scratch + (size_t)j * 3 * n_lanczos;
-  double* e = d + n_lanczos;
-  double* q = e + n_lanczos;
   if (m <= 0) {
-    contrib[j] = 0.0;
+    if (lane == 0) contrib[j] = 0.0;
     return;
   }
   const double* a = ab + (size_t)j * n_lanczos * 2;
-  for (int k = 0; k < m; ++k) {
+  for (int k = lane; k < m; k += 64) {
     const double ak = a[2 * k], bk = a[2 * k + 1];
-    d[k] = 1.0 / ak;
-    if (k > 0) d[k] += a[2 * (k - 1) + 1] / a[2 * (k - 1)];
-    if (k + 1 < m) e[k] = sqrt(bk) / ak;
+    double dk = 1.0 / ak;
+    if (k > 0) dk += a[2 * (k - 1) + 1] / a[2 * (k - 1)];
+    diag[k] = dk;
+    off2[k] = (k + 1 < m) ? bk / (ak * ak) : 0.0;  // (sqrt(b_k)/a_k)^2
   }
-  if (m > 1) e[m - 1] = 0.0;
-  tridiag_eig_first(m, d, e, q);
-  double s = 0.0;
-  for (int k = 0; k < m; ++k) s += q[k] * q[k] * log(d[k]);  // log of a non-positive Ritz value gives NaN
-  contrib[j] = bnorm2[j] * s;
+  __syncthreads();
+  if (lane == 0) {
+    // positive definiteness (all pivots of T from the bottom positive) and a
+    // Gershgorin upper bound of the spectrum
+    double g = diag[m - 1];
+    int ok = g > 0.0;
+    double hi = diag[m - 1] + (m > 1 ? sqrt(off2[m - 2]) : 0.0);
+    for (int k = m - 2; k >= 0; --k) {
+      g = diag[k] - off2[k] / g;
+      ok &= g > 0.0;
+      const double r = sqrt(off2[k]) + (k > 0 ? sqrt(off2[k - 1]) : 0.0);
+      hi = fmax(hi, diag[k] + r);
+    }
+    s_ok = ok && isfinite(g);
+    s_hi = hi;
+  }
+  __syncthreads();
+  if (!s_ok) {
+    if (lane == 0) contrib[j] = __builtin_nan("");
+    return;
+  }
+  const double s_lo = log(s_hi) - kSlqLo;
+  const int nodes = (int)((kSlqLo + kSlqHi) / kSlqStep) + 1;
+  double acc = 0.0;
+  for (int q = lane; q < nodes; q += 64) {
+    const double t = exp(s_lo + q * kSlqStep);
+    double g = diag[m - 1] + t;
+    for (int k = m - 2; k >= 0; --k) g = (diag[k] + t) - off2[k] / g;
+    acc += t * (1.0 / (1.0 + t) - 1.0 / g);
+  }
+  acc = warp_sum(acc);
+  if (lane == 0) contrib[j] = bnorm2[j] * kSlqStep * acc;
 }
 
 __global__ void slq_sum_kernel(int nprobe, double scale, const double* contrib, double* logdet, double* stderr_out) {
@@ -101,8 +97,9 @@ __global__ void slq_sum_kernel(int nprobe, double scale, const double* contrib, 
 using namespace gpl;
 
 extern "C" size_t gpl_lanczos_logdet_workspace(int nprobe, int n_lanczos) {
-  if (nprobe <= 0 || n_lanczos <= 0) return 0;
-  return align_up(sizeof(double) * 3 * (size_t)n_lanczos * nprobe);
+  (void)nprobe;
+  (void)n_lanczos;
+  return 0;  // coefficients are staged in LDS
 }
 
 extern "C" int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, const int* iters,
@@ -111,9 +108,11 @@ extern "C" int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lancz
   GPL_REQUIRE(nprobe >= 1 && n_lanczos >= 1, "nprobe=%d n_lanczos=%d must be >= 1", nprobe, n_lanczos);
   GPL_REQUIRE(lanczos_ab && iters && bnorm2 && contrib && logdet && stderr_out, "NULL argument");
   GPL_REQUIRE(std::isfinite(scale), "scale must be finite");
-  GPL_TRY(check_ws(ws, ws_bytes, gpl_lanczos_logdet_workspace(nprobe, n_lanczos)));
-  hipLaunchKernelGGL(slq_probe_kernel, dim3(cdiv(nprobe, 64)), dim3(64), 0, stream, nprobe, n_lanczos, lanczos_ab,
-                     iters, bnorm2, contrib, static_cast<double*>(ws));
+  GPL_REQUIRE(n_lanczos <= kSlqMaxSteps, "n_lanczos=%d exceeds %d", n_lanczos, kSlqMaxSteps);
+  (void)ws;
+  (void)ws_bytes;
+  hipLaunchKernelGGL(slq_probe_kernel, dim3(nprobe), dim3(64), 0, stream, nprobe, n_lanczos, lanczos_ab, iters,
+                     bnorm2, contrib);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(slq_sum_kernel, dim3(1), dim3(64), 0, stream, nprobe, scale, contrib, logdet, stderr_out);
   GPL_LAUNCH_CHECK();

@@ -77,13 +77,13 @@ def test_admission_by_memory_budget(G):
     reqs = _requests(G)
     eng = G.serving.ServingEngine(prec="f16x3")
     fps = [eng.footprint(r) for r in reqs]
-    budget = max(fps) + min(fps)  # never room for three slots
+    budget = max(fps) + min(fps)  # the largest request never shares the device with another large one
     eng = G.serving.ServingEngine(prec="f16x3", hbm_budget=budget)
     res = eng.run(reqs, realtime=False)
     assert len(res) == len(reqs)
     assert eng.stats["max_bytes"] <= budget
-    assert eng.stats["max_active"] <= 2
     assert eng.stats["deferred_memory"] > 0
+    assert all(all(s == 0 for s in r.status) for r in res)
 
 
 def test_stalled_solves_reported(G):
