@@ -134,13 +134,30 @@ int gpl_sersic_eval(const gpl_source* src, int n, const float* px, const float* 
 int gpl_psf_conv(const gpl_grid* grid, const gpl_psf* psf, int nrhs, const float* in, int ld_in, float* out,
                  int ld_out, float alpha, float beta, int adjoint, hipStream_t stream);
 
-/* Matrix-free kernel product Y = K V + beta * Y, K_ij = k(p_i, p_j) (eq. "grbf"),
- * over n points, nrhs columns. K is never stored: tiles are formed in registers.
+/* Matrix-free kernel product Y = K V + beta * Y, K_ij = k(p_i, p_j) (eq. "grbf";
+ * formed on demand, never stored, as in Sec. 3.3), over n points, nrhs columns
+ * (V, Y column-major with ld >= n, device memory, must not overlap).
  * prec = GPL_PREC_FP32 or GPL_PREC_F16X3. beta is 0 (overwrite) or any float.
- * V and Y must not overlap. */
+ * Pairs of 64-point row tiles and 32-point chunks whose bounding boxes are so far
+ * apart that every kernel value is exactly zero in the chosen precision are not
+ * evaluated, so the result equals the all-pairs product up to FP32 summation
+ * order. grid (nullable): the points are that grid's fine points in row-major
+ * order (as gpl_lens_raytrace writes them) and are then taken in the grid's
+ * Z-order, which keeps tiles compact; NULL keeps the caller's order, best when
+ * consecutive points are close. n <= 2,097,120. */
 size_t gpl_gp_kernel_mvm_workspace(int n, int nrhs, int prec);
-int gpl_gp_kernel_mvm(const gpl_kernel* kern, int n, const float* px, const float* py, int nrhs, const float* V,
-                      int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+int gpl_gp_kernel_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px, const float* py, int nrhs,
+                      const float* V, int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* Work of the product above for these points: the number of (64-point row tile,
+ * 32-point chunk) pairs it evaluates, each 2048 kernel values (the rest are
+ * exactly zero). Writes *live_tiles (host memory) and synchronises `stream`;
+ * a measurement helper, not needed for the product itself. */
+size_t gpl_gp_kernel_mvm_plan_workspace(int n);
+int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px,
+                                 const float* py, int prec, long long* live_tiles, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
 
 /* Y = A X with A = B K B^T + noise_sigma^2 I (image pixels, nrhs columns). */
 size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int prec);

@@ -72,7 +72,11 @@ SIGNATURES = {
     "gpl_sersic_eval": (_I, [C.POINTER(gpl_source), _I, _P, _P, _P, _P]),
     "gpl_psf_conv": (_I, [C.POINTER(gpl_grid), C.POINTER(gpl_psf), _I, _P, _I, _P, _I, _F, _F, _I, _P]),
     "gpl_gp_kernel_mvm_workspace": (_Z, [_I, _I, _I]),
-    "gpl_gp_kernel_mvm": (_I, [C.POINTER(gpl_kernel), _I, _P, _P, _I, _P, _I, _P, _I, _F, _I, _P, _Z, _P]),
+    "gpl_gp_kernel_mvm": (_I, [C.POINTER(gpl_kernel), C.POINTER(gpl_grid), _I, _P, _P, _I, _P, _I, _P, _I, _F, _I,
+                               _P, _Z, _P]),
+    "gpl_gp_kernel_mvm_plan_workspace": (_Z, [_I]),
+    "gpl_gp_kernel_mvm_plan_stats": (_I, [C.POINTER(gpl_kernel), C.POINTER(gpl_grid), _I, _P, _P, _I,
+                                          C.POINTER(C.c_longlong), _P, _Z, _P]),
     "gpl_apply_A_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I]),
     "gpl_apply_A": (_I, [C.POINTER(gpl_problem), _I, _P, _I, _P, _I, _I, _P, _Z, _P]),
     "gpl_cg_solve_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I]),

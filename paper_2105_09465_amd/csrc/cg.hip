@@ -4,7 +4,7 @@
 // as discussed in Sec. 3.3). Vectors are FP32; every dot product, the alpha and
 // beta recurrences and the recorded Lanczos coefficients are FP64.
 //
-// One iteration is five launches on the caller's stream:
+// One iteration is a fixed sequence of launches on the caller's stream:
 //   T1 = B_op^T P  ->  T2 = K T1  ->  AP = B_op T2 + sigma^2 P  (+ p.Ap partials)
 //   -> update1 (alpha; X += alpha P; R -= alpha AP; r.r partials)
 //   -> update2 (beta; P = R + beta P; bookkeeping).
@@ -348,14 +348,13 @@ static int check_problem(const gpl_problem* prob, Taps& taps) {
 
 // One application of A to the columns of P: AP = B K B^T P + sigma^2 P, with
 // p.Ap partials when `pap` is given.
-static int apply_A_into(const gpl_problem* prob, const Taps& taps, int nrhs, const float* P, int ldp, float* T1,
-                        float* T2, int ldf, float* AP, int ldap, double* pap, int prec, void* mws, size_t mws_bytes,
-                        CgGate gate, hipStream_t stream) {
-  const int n = prob->grid.n, ss = prob->grid.ss, N = n * ss * n * ss;
+static int apply_A_into(const gpl_problem* prob, const Taps& taps, const MvmCtx& mv, int nrhs, const float* P,
+                        int ldp, float* T1, float* T2, int ldf, float* AP, int ldap, double* pap, CgGate gate,
+                        hipStream_t stream) {
+  const int n = prob->grid.n, ss = prob->grid.ss;
   const float s2 = (float)(prob->noise_sigma * prob->noise_sigma);
   GPL_TRY(psf_adjoint_launch(n, ss, taps, nrhs, P, ldp, T1, ldf, 1.f, 0.f, gate, stream));
-  GPL_TRY(mvm_launch(prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, nrhs, T1, ldf, T2, ldf,
-                     0.f, prec, mws, mws_bytes, gate, stream));
+  GPL_TRY(mvm_run(mv, nrhs, T1, ldf, T2, ldf, 0.f, gate, stream));
   GPL_TRY(psf_forward_launch(n, ss, taps, nrhs, T2, ldf, AP, ldap, 1.f, 0.f, P, ldp, s2, pap ? P : nullptr, ldp, pap,
                              gate, stream));
   return GPL_OK;
@@ -393,8 +392,10 @@ extern "C" int gpl_apply_A(const gpl_problem* prob, int nrhs, const float* X, in
   const size_t mb = mvm_workspace(N, nrhs, prec);
   char* mws = c.take<char>(mb);
   if (!c.ok()) return check_ws(nullptr, 0, 1);
-  return apply_A_into(prob, taps, nrhs, X, ldx, T1, T2, ldf, Y, ldy, nullptr, prec, mb ? mws : nullptr, mb, CgGate{},
-                      stream);
+  MvmCtx mv;
+  GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid, nrhs,
+                      prec, mws, mb, stream));
+  return apply_A_into(prob, taps, mv, nrhs, X, ldx, T1, T2, ldf, Y, ldy, nullptr, CgGate{}, stream);
 }
 
 extern "C" size_t gpl_cg_solve_workspace(const gpl_problem* prob, int nrhs, int prec) {
@@ -425,6 +426,9 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   PollSlots* poll = nullptr;
   GPL_TRY(poll_slots(poll));
+  MvmCtx mv;  // the points stay fixed for the whole solve: one tile plan
+  GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid, nrhs,
+                      prec, b.mvm_ws, b.mvm_ws_bytes, stream));
 
   const int nb = b.nb_upd;
   const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
@@ -444,8 +448,8 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
       const int p = it & 1;
       CgGate gate;
       gate.n_active = b.n_active + p;
-      GPL_TRY(apply_A_into(prob, taps, nrhs, b.P, b.ldv, b.T1, b.T2, b.ldf, b.AP, b.ldv, b.pap_part, prec,
-                           b.mvm_ws_bytes ? b.mvm_ws : nullptr, b.mvm_ws_bytes, gate, stream));
+      GPL_TRY(apply_A_into(prob, taps, mv, nrhs, b.P, b.ldv, b.T1, b.T2, b.ldf, b.AP, b.ldv, b.pap_part, gate,
+                           stream));
       hipLaunchKernelGGL(cg_update1_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, X, ldx, b.R, b.P, b.AP, b.ldv,
                          b.pap_part, b.ntiles, b.rr_part, nb, b.st[p], b.st[1 - p], b.n_active + p,
                          b.n_active + (1 - p));

@@ -44,8 +44,8 @@ const char* last_error();
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
-inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
-inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // Bump allocator over a caller-provided workspace. `take` returns nullptr when
 // the workspace is exhausted (callers check `ok()` once after carving).

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "tileplan.hpp"
 
 namespace gpl {
 
@@ -44,11 +45,13 @@ struct ServeSlotDev {
   const float *px, *py;
   float *X, *R, *P, *AP, *T1, *T2;
   int ldv, ldf;
+  TilePlan plan;  // tile plan of the slot's points (grid Z-order)
   unsigned* colmax;
   float* inv_scale;
-  _Float16 *Vh, *Vl;
-  float* part;
-  int ldh, ldp, S, jlen, nrb;
+  _Float16 *Vh, *Vl;  // precision form: RHS block split in sorted order
+  float* Vp;          // FP32 form: RHS block in sorted order
+  float* part;        // partial rows of the product's work items
+  int ldh, ncp;
   ColState* st[2];
   double* bb;
   int* n_active;  // [2]
@@ -84,11 +87,25 @@ int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* i
 int psf_adjoint_launch(int n, int ss, const Taps& taps, int nrhs, const float* in, int ld_in, float* out, int ld_out,
                        float alpha, float beta, CgGate gate, hipStream_t stream);
 
-// Kernel product Y = K V + beta Y (internal form with the CG gate).
+// Kernel product Y = K V + beta Y (internal form with the CG gate). A product
+// is prepared once per point set (tile plan) and run for any RHS block of at
+// most nrhs_max columns. `grid` (nullable) says the points are that grid's fine
+// pixels in row-major order.
+struct MvmCtx {
+  TilePlan plan;
+  void* scratch;
+  size_t scratch_bytes;
+  int prec, nrhs_max;
+  float s2, amp2;
+};
 size_t mvm_workspace(int n, int nrhs, int prec);
-int mvm_launch(double lengthscale, double amplitude, int n, const float* px, const float* py, int nrhs, const float* V,
-               int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes, CgGate gate,
-               hipStream_t stream);
+int mvm_prepare(MvmCtx& m, double lengthscale, double amplitude, int n, const float* px, const float* py,
+                const gpl_grid* grid, int nrhs, int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+int mvm_run(const MvmCtx& m, int nrhs, const float* V, int ldv, float* Y, int ldy, float beta, CgGate gate,
+            hipStream_t stream);
+int mvm_launch(double lengthscale, double amplitude, int n, const float* px, const float* py, const gpl_grid* grid,
+               int nrhs, const float* V, int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes,
+               CgGate gate, hipStream_t stream);
 
 int check_kernel(const gpl_kernel* k);
 
@@ -107,9 +124,6 @@ int cg_init_launch(int npix, int nrhs, const float* Bm, int ldb, float* X, int l
                    hipStream_t stream);
 int cg_finalize_launch(int nrhs, const ColState* st, const double* bb, double* bnorm2, int* iters, double* relres,
                        int* status, int n_lanczos, double* ab, hipStream_t stream);
-// Sizes of the product workspace of one slot (CB = 2 column blocks).
-void serve_mvm_plan(int N, int* S, int* jlen, int* nrb, int* ldh, int* ldp);
 int psf_adjoint_tiles(int n, int ss);
-size_t valu_mvm_workspace(int n, int nrhs);
 
 }  // namespace gpl

@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "mvm_mfma.hpp"
 
 namespace gpl {
 
@@ -25,10 +26,11 @@ static const ServeSlotDev& host_desc(const gpl_serve_slot* s) {
 struct SlotBufs {
   ServeSlotDev* desc;
   float *px, *py, *mu, *rhs, *X, *R, *P, *AP, *T1, *T2, *w, *fhat_tmp;
+  TilePlan plan;
   unsigned* colmax;
   float* inv_scale;
   _Float16 *Vh, *Vl;
-  float* part;
+  float *Vp, *part;
   ColState *st0, *st1;
   double *bb, *pap, *rr, *ab, *bnorm2, *contrib, *scal, *lz_ws;
   int* n_active;
@@ -40,8 +42,7 @@ template <class Cv>
 static void carve_slot(Cv& cv, int n, int ss, int nrhs, int n_lanczos, int prec, SlotBufs* b) {
   const int npix = n * n, N = npix * ss * ss;
   const int ldv = round_up(npix, 64), ldf = round_up(N, 64);
-  int S, jlen, nrb, ldh, ldp;
-  serve_mvm_plan(N, &S, &jlen, &nrb, &ldh, &ldp);
+  const int nrt = cdiv(N, kRowTile), ldh = nrt * kRowTile, ncp = cdiv(nrhs, 16) * 16;
   const bool f16 = prec == GPL_PREC_F16X3;
   const int ntiles = psf_forward_tiles(n, ss), nb = cdiv(npix, 256);
   SlotBufs x;
@@ -58,11 +59,13 @@ static void carve_slot(Cv& cv, int n, int ss, int nrhs, int n_lanczos, int prec,
   x.T2 = cv.template take<float>((size_t)ldf * nrhs);
   x.w = cv.template take<float>(N);
   x.fhat_tmp = nullptr;
-  x.colmax = cv.template take<unsigned>(f16 ? 32 * kColmaxBlocks : 1);
-  x.inv_scale = cv.template take<float>(32);
-  x.Vh = cv.template take<_Float16>(f16 ? (size_t)32 * ldh : 1);
-  x.Vl = cv.template take<_Float16>(f16 ? (size_t)32 * ldh : 1);
-  x.part = cv.template take<float>((size_t)S * 32 * ldp);
+  plan_carve(cv, N, x.plan);
+  x.colmax = cv.template take<unsigned>(f16 ? (size_t)ncp * kColmaxBlocks : 1);
+  x.inv_scale = cv.template take<float>(ncp);
+  x.Vh = cv.template take<_Float16>(f16 ? (size_t)ncp * ldh : 1);
+  x.Vl = cv.template take<_Float16>(f16 ? (size_t)ncp * ldh : 1);
+  x.Vp = cv.template take<float>(f16 ? 1 : (size_t)ncp * ldh);
+  x.part = cv.template take<float>((size_t)nrt * kMaxSeg * nrhs * kRowTile);
   x.st0 = cv.template take<ColState>(nrhs);
   x.st1 = cv.template take<ColState>(nrhs);
   x.bb = cv.template take<double>(nrhs);
@@ -75,7 +78,7 @@ static void carve_slot(Cv& cv, int n, int ss, int nrhs, int n_lanczos, int prec,
   x.scal = cv.template take<double>(8);
   x.lz_bytes = gpl_lanczos_logdet_workspace(std::max(nrhs - 1, 1), std::max(n_lanczos, 1));
   x.lz_ws = reinterpret_cast<double*>(cv.template take<char>(x.lz_bytes));
-  x.mv_bytes = valu_mvm_workspace(N, 1);
+  x.mv_bytes = mvm_workspace(N, 1, GPL_PREC_FP32);
   x.mv_ws = cv.template take<char>(x.mv_bytes);
   if (b) *b = x;
 }
@@ -157,12 +160,15 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
   D.T2 = b.T2;
   D.ldv = round_up(npix, 64);
   D.ldf = round_up(N, 64);
+  D.plan = b.plan;
   D.colmax = b.colmax;
   D.inv_scale = b.inv_scale;
   D.Vh = b.Vh;
   D.Vl = b.Vl;
+  D.Vp = b.Vp;
   D.part = b.part;
-  serve_mvm_plan(N, &D.S, &D.jlen, &D.nrb, &D.ldh, &D.ldp);
+  D.ldh = b.plan.npad;
+  D.ncp = cdiv(nrhs, 16) * 16;
   D.st[0] = b.st0;
   D.st[1] = b.st1;
   D.bb = b.bb;
@@ -183,6 +189,8 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
   hipLaunchKernelGGL(write_desc_kernel, dim3(1), dim3(64), 0, stream, D, b.desc);
   GPL_LAUNCH_CHECK();
   GPL_TRY(gpl_lens_raytrace(g, lens, b.px, b.py, stream));
+  TilePlan plan = b.plan;  // same buffers as the descriptor's copy
+  GPL_TRY(plan_build(plan, N, b.px, b.py, g, D.s2, plan_threshold(prec), stream));
   GPL_TRY(gpl_sersic_eval(src, N, b.px, b.py, b.mu, stream));
   GPL_HIP(hipMemcpyAsync(b.rhs, d, sizeof(float) * npix, hipMemcpyDeviceToDevice, stream));
   if (nrhs > 1)
@@ -261,8 +269,9 @@ extern "C" int gpl_serve_slot_finish(gpl_serve_slot* slot, long iter, double log
     // posterior mean mu + K B^T u and the predicted image B fhat
     GPL_TRY(psf_adjoint_launch(D.n, D.ss, D.taps, 1, b.X, D.ldv, b.w, D.N, 1.f, 0.f, CgGate{}, stream));
     GPL_HIP(hipMemcpyAsync(fhat, b.mu, sizeof(float) * D.N, hipMemcpyDeviceToDevice, stream));
-    GPL_TRY(mvm_launch(D.ell, D.amp, D.N, D.px, D.py, 1, b.w, D.N, fhat, D.N, 1.f, GPL_PREC_FP32,
-                       b.mv_bytes ? b.mv_ws : nullptr, b.mv_bytes, CgGate{}, stream));
+    gpl_grid grid{D.n, D.ss, 0.0, 0.0, 0.0};  // ordering only: the points are this grid's fine pixels
+    GPL_TRY(mvm_launch(D.ell, D.amp, D.N, D.px, D.py, &grid, 1, b.w, D.N, fhat, D.N, 1.f, GPL_PREC_FP32, b.mv_ws,
+                       b.mv_bytes, CgGate{}, stream));
     if (image)
       GPL_TRY(psf_forward_launch(D.n, D.ss, D.taps, 1, fhat, D.N, image, D.npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr, 0,
                                  nullptr, CgGate{}, stream));

@@ -103,7 +103,10 @@ def psf_conv(grid: Grid, psf: PSF, inp, adjoint: bool, out=None, alpha=1.0, beta
     return ret[0] if (squeeze and ret.dim() == 2) else ret
 
 
-def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0):
+def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0, grid: Grid | None = None):
+    """Y = K V (+ beta Y) over the points (px, py); grid: the points are that
+    grid's fine points in row-major order (lets the product use the grid's
+    Z-order tiles)."""
     n = px.numel()
     squeeze = V.dim() == 1
     V2 = V.unsqueeze(0) if squeeze else V
@@ -115,9 +118,23 @@ def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0):
     pc = prec_code(prec)
     ws, wsb = workspace(_lib.lib.gpl_gp_kernel_mvm_workspace(n, V2.shape[0], pc), V.device)
     k = kernel.c()
-    _lib.call("gpl_gp_kernel_mvm", C.byref(k), n, _ptr(px), _ptr(py), V2.shape[0], _ptr(V2), ldv, _ptr(out2), ldy,
+    g = C.byref(grid.c()) if grid is not None else None
+    _lib.call("gpl_gp_kernel_mvm", C.byref(k), g, n, _ptr(px), _ptr(py), V2.shape[0], _ptr(V2), ldv, _ptr(out2), ldy,
               float(beta), pc, _wsptr(ws), wsb, _stream())
     return out[0] if (squeeze and out.dim() == 2) else out
+
+
+def kernel_mvm_live_tiles(kernel: Kernel, px, py, prec="fp32", grid: Grid | None = None) -> int:
+    """Number of (64-point row tile, 32-point chunk) pairs the product evaluates
+    for these points (2048 kernel values each); synchronises the stream."""
+    n = px.numel()
+    ws, wsb = workspace(_lib.lib.gpl_gp_kernel_mvm_plan_workspace(n), px.device)
+    out = C.c_longlong(0)
+    k = kernel.c()
+    g = C.byref(grid.c()) if grid is not None else None
+    _lib.call("gpl_gp_kernel_mvm_plan_stats", C.byref(k), g, n, _ptr(px), _ptr(py), prec_code(prec), C.byref(out),
+              _wsptr(ws), wsb, _stream())
+    return int(out.value)
 
 
 def problem_c(problem: Problem, px, py):

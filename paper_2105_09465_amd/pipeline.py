@@ -70,6 +70,6 @@ def reconstruct(problem: Problem, d: torch.Tensor, probes: torch.Tensor, prec="f
     if want_image:
         w = ops.psf_conv(g, problem.psf, u, adjoint=True)  # B^T u
         fhat = mu.clone()
-        ops.kernel_mvm(problem.kernel, px, py, w, prec="fp32", out=fhat, beta=1.0)  # mu + K B^T u
+        ops.kernel_mvm(problem.kernel, px, py, w, prec="fp32", out=fhat, beta=1.0, grid=g)  # mu + K B^T u
         image = ops.psf_conv(g, problem.psf, fhat, adjoint=False)
     return Reconstruction(px, py, mu, rhs, cg["X"], cg, logdet, stderr, contrib, scalars, fhat, image)

@@ -66,7 +66,7 @@ def mock_observation(problem: Problem, noise: np.ndarray, field: np.ndarray):
     mu = ops.sersic_eval(problem.source, pts[0], pts[1])
     wn = torch.as_tensor(field, dtype=torch.float32, device="cuda")
     k2 = dataclasses.replace(problem.kernel, lengthscale=problem.kernel.lengthscale / math.sqrt(2.0))
-    gf = ops.kernel_mvm(k2, pts[0], pts[1], wn, prec="fp32")
+    gf = ops.kernel_mvm(k2, pts[0], pts[1], wn, prec="fp32", grid=g)
     gf = gf * (problem.kernel.amplitude / gf.std().clamp_min(1e-30))
     f = mu + gf
     d = ops.psf_conv(g, problem.psf, f, adjoint=False)

@@ -58,17 +58,17 @@ def test_invalid_arguments_rejected_on_host():
     assert L.lib.gpl_lens_raytrace(C.byref(g), C.byref(bad_lens), p, p, None) == L.GPL_EINVAL
     assert b"q=" in L.lib.gpl_last_error()
     k = L.gpl_kernel(0, -1.0, 0.3)
-    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), 10, p, p, 1, p, 10, p, 10, 0.0, 0, None, 0, None) == L.GPL_EINVAL
+    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), None, 10, p, p, 1, p, 10, p, 10, 0.0, 0, None, 0, None) == L.GPL_EINVAL
     k = L.gpl_kernel(0, 0.04, 0.3)
-    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), 10, p, p, 1, p, 5, p, 10, 0.0, 0, None, 0, None) == L.GPL_EINVAL
-    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), 10, p, p, 1, p, 10, p, 10, 0.0, 7, None, 0, None) == L.GPL_EINVAL
+    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), None, 10, p, p, 1, p, 5, p, 10, 0.0, 0, None, 0, None) == L.GPL_EINVAL
+    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), None, 10, p, p, 1, p, 10, p, 10, 0.0, 7, None, 0, None) == L.GPL_EINVAL
     big = L.gpl_psf(5.0, 0)  # radius beyond the maximum
     assert L.lib.gpl_psf_conv(C.byref(g), C.byref(big), 1, p, 400, C.c_void_p(32), 100, 1.0, 0.0, 0, None) == \
         L.GPL_EINVAL
     # workspace checks
     need = L.lib.gpl_gp_kernel_mvm_workspace(40000, 17, 0)
     assert need > 0
-    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), 40000, p, p, 17, p, 40000, C.c_void_p(64), 40000, 0.0, 0, None, 0,
+    assert L.lib.gpl_gp_kernel_mvm(C.byref(k), None, 40000, p, p, 17, p, 40000, C.c_void_p(64), 40000, 0.0, 0, None, 0,
                                    None) == L.GPL_EWORKSPACE
     assert L.lib.gpl_lanczos_logdet(0, 30, p, p, p, 1.0, p, p, p, None, 0, None) == L.GPL_EINVAL
 
@@ -81,4 +81,5 @@ def test_workspace_sizes_monotone():
     b = L.lib.gpl_cg_solve_workspace(C.byref(prob), 33, 0)
     assert 0 < a < b
     assert a % 256 == 0
-    assert L.lib.gpl_lanczos_logdet_workspace(16, 30) == 16 * 30 * 3 * 8 + (-(16 * 30 * 3 * 8) % 256)
+    assert L.lib.gpl_lanczos_logdet_workspace(16, 30) == 0  # the quadrature runs in LDS
+    assert L.lib.gpl_gp_kernel_mvm_workspace(160000, 64, 1) > L.lib.gpl_gp_kernel_mvm_workspace(40000, 17, 1) > 0

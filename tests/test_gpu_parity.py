@@ -249,6 +249,73 @@ def test_kernel_mvm_f16x3_wide_dynamic_range(G):
     assert np.max(np.abs(t64(Y).T - want) / scale) <= 1e-5
 
 
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_kernel_mvm_grid_tiles(G, prec):
+    """Lensed points of the 100x100, ss = 2 workload (N = 40,000) taken in the
+    grid's Z-order tiles: most tile pairs are dropped as exactly zero. Sampled
+    rows against the FP64 oracle, all rows against the same product in the
+    caller's row-major order (which drops fewer pairs): they differ only by FP32
+    summation order."""
+    w = synth.workload(1)
+    _say("mvm grid tiles", prec, w.name)
+    prob = gpu_problem(w)
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    rng = np.random.default_rng(21)
+    V = rng.standard_normal((17, w.N)).astype(np.float32)
+    Vt = cuda32(V)
+    Yg = G.ops.kernel_mvm(prob.kernel, pts[0], pts[1], Vt, prec=prec, grid=prob.grid)
+    Yc = G.ops.kernel_mvm(prob.kernel, pts[0], pts[1], Vt, prec=prec)
+    live_g = G.ops.kernel_mvm_live_tiles(prob.kernel, pts[0], pts[1], prec=prec, grid=prob.grid)
+    live_c = G.ops.kernel_mvm_live_tiles(prob.kernel, pts[0], pts[1], prec=prec)
+    total = (w.N // 64) * (w.N // 32)
+    print(f"evaluated tile pairs: grid order {live_g / total:.3f}, row-major {live_c / total:.3f}")
+    assert live_g < live_c < total
+    assert live_g < 0.5 * total
+    px, py = t64(pts[0]), t64(pts[1])
+    rows = rng.choice(w.N, 300, replace=False)
+    V64 = V.astype(np.float64).T
+    want = okernel.kernel_mvm_rows(px, py, rows, V64, w.ell, w.amp)
+    scale = okernel.kernel_abs_mvm_rows(px, py, rows, V64, w.ell, w.amp)
+    err = np.max(np.abs(t64(Yg).T[rows] - want) / scale)
+    print(f"max |err| / (|K||V|) = {err:.2e}")
+    assert err <= 1e-5
+    diff = np.abs(t64(Yg) - t64(Yc)).max(axis=1) / np.abs(t64(Yc)).max(axis=1)
+    assert diff.max() <= 2e-6, diff.max()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_kernel_mvm_grid_tiles_ragged(G, prec):
+    """A 13x13 grid with 3x3 supersampling (N = 1521: a ragged last row tile and
+    a fine side that is not a power of two) through a strong lens; all rows."""
+    w = synth.workload(1, 3).replace(n=13, ss=3, ell=0.02)
+    _say("mvm grid tiles ragged", prec)
+    prob = gpu_problem(w)
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    rng = np.random.default_rng(22)
+    V = rng.standard_normal((3, w.N)).astype(np.float32)
+    Y = G.ops.kernel_mvm(prob.kernel, pts[0], pts[1], cuda32(V), prec=prec, grid=prob.grid)
+    px, py = t64(pts[0]), t64(pts[1])
+    V64 = V.astype(np.float64).T
+    want = okernel.kernel_mvm(px, py, V64, w.ell, w.amp)
+    scale = okernel.kernel_abs_mvm_rows(px, py, np.arange(w.N), V64, w.ell, w.amp)
+    assert np.max(np.abs(t64(Y).T - want) / scale) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_kernel_mvm_isolated_points(G, prec):
+    """Lengthscale far below the point spacing: every pair but the diagonal is
+    exactly zero, so K V = a^2 V."""
+    _say("mvm isolated points", prec)
+    rng = np.random.default_rng(23)
+    n = 2000
+    px = (rng.permutation(n) * 0.01).astype(np.float32)
+    py = rng.uniform(-1, 1, n).astype(np.float32)
+    V = rng.standard_normal((2, n)).astype(np.float32)
+    Y = G.ops.kernel_mvm(G.Kernel(1e-4, 0.3), cuda32(px), cuda32(py), cuda32(V), prec=prec)
+    want = 0.09 * V.astype(np.float64)
+    assert np.max(np.abs(t64(Y) - want) / np.abs(want).max()) <= 1e-6
+
+
 def test_kernel_mvm_beta_accumulate(G):
     _say("mvm beta")
     rng = np.random.default_rng(5)
