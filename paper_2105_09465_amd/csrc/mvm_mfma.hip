@@ -6,15 +6,15 @@
 // Work decomposition: the points are taken in the order of a tile plan
 // (tileplan.hpp), which lists for every row tile of 64 points the chunks of 32
 // points that can give a non-zero kernel value; every other pair contributes
-// exact zeros and is not evaluated. A work item is one row tile and one
-// contiguous segment of its chunk list; its workgroup of 4 waves computes the
-// same 64 rows (four 16-row MFMA tiles per wave) over interleaved chunks, with
-// the chunk's coordinates and right-hand-side block loaded straight from global
-// memory into the MFMA B-operand layout, and sums the 4 waves' accumulators in
-// LDS in a fixed order. Items write partial rows; a reduction kernel adds the
-// items of each row tile in order and scatters to the caller's order, so the
-// result is bitwise reproducible. Exact coordinate differences are formed
-// before scaling.
+// exact zeros and is not evaluated. The listed (row tile, chunk) pairs are split
+// evenly over the waves of the launch, each wave taking a contiguous run of them
+// (so the work is balanced however unevenly the live pairs fall on row tiles).
+// A wave computes 64 rows (four 16-row MFMA tiles) at a time, with each chunk's
+// coordinates and right-hand-side block loaded straight from global memory into
+// the MFMA B-operand layout, and writes one block of partial rows per row tile
+// it touches; a reduction kernel adds the partials of each row tile in wave
+// order and scatters to the caller's order, so the result is bitwise
+// reproducible. Exact coordinate differences are formed before scaling.
 //
 // Precision form (GPL_PREC_F16X3): exp tiles computed in FP32 as 2^11 k (the
 // factor enters through the exp2 argument) and split into FP16 hi (the top 11
@@ -40,7 +40,7 @@ typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRT = 4;                      // 16-row MFMA tiles per wave
-constexpr int kWaves = 4;                   // waves per workgroup (one work item)
+constexpr int kWaves = 4;                   // independent waves per workgroup
 constexpr float kKScale = 2048.f;           // 2^11 applied to the FP16 exp tile
 static constexpr int kMaxCB = 4;            // up to 64 columns per pass
 
@@ -121,61 +121,109 @@ __global__ void pack_rhs_kernel(int n, int nrhs, const float* __restrict__ V, in
   pack_rhs_body(blockIdx.x, blockIdx.y, n, nrhs, V, ldv, perm, Vp, ldh);
 }
 
-// ---------------------------------------------------------------- work items
+// ---------------------------------------------------------------- work of one wave
 
-struct Item {
-  int r, beg, end;
+// The units [u0, u1) of wave w (row-tile order), and the first row tile and
+// partial slot they map to.
+struct WaveRange {
+  int u0, u1, r, slot;
 };
 
-// Work item `item` of a plan: row tile item / kMaxSeg and its segment of the
-// chunk list (r = -1 when the item is unused).
-__device__ __forceinline__ Item item_of(int item, const TilePlan& P) {
-  Item it{-1, 0, 0};
-  const int r = item / kMaxSeg, s = item - r * kMaxSeg;
-  if (r >= P.nrt) return it;
-  const int ns = P.nseg[r];
-  if (s >= ns) return it;
-  const int L = P.count[r];
-  it.r = r;
-  it.beg = L * s / ns;  // L < 2^16, s < kMaxSeg: no overflow
-  it.end = L * (s + 1) / ns;
-  return it;
+__device__ __forceinline__ WaveRange wave_range(int w, const TilePlan& P) {
+  const int T = *P.total;
+  WaveRange wr;
+  wr.u0 = wave_unit(w, T, P.nw);
+  wr.u1 = wave_unit(w + 1, T, P.nw);
+  wr.r = P.wrow[w];
+  wr.slot = P.wslot[w];
+  return wr;
 }
 
-// Chunk k of a row tile's list, read through the scalar unit (k is uniform per
-// wave; rows of the list start 4-byte aligned since nch is even).
-__device__ __forceinline__ int chunk_at(const uint16_t* lst, int k) {
-  const uint32_t w = reinterpret_cast<const uint32_t*>(lst)[k >> 1];
-  return (int)((k & 1) ? (w >> 16) : (w & 0xffffu));
-}
-
-// Fixed-order sum of the 4 waves' accumulators of a work item and the write of
-// its partial rows: part[(item * pcols + c0 + c) * 64 + row] for c < ncols.
+// Partial rows of one row tile from one wave: part[(slot * pcols + c0 + c) * 64 + row]
+// for c < ncols (MFMA D layout: column = lane % 16, rows 4 * (lane / 16) + v).
 template <int CB>
-__device__ __forceinline__ void item_store(f32x4 (&acc)[kRT][CB], int item, float* __restrict__ part, int pcols,
-                                           int c0, int ncols) {
-  __shared__ f32x4 red[kWaves - 1][kRT * CB][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (wave > 0) {
-#pragma unroll
-    for (int rt = 0; rt < kRT; ++rt)
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) red[wave - 1][rt * CB + cb][lane] = acc[rt][cb];
-  }
-  __syncthreads();
-  if (wave != 0) return;
-  const int ri = lane & 15, g = lane >> 4;
+__device__ __forceinline__ void store_partial(const f32x4 (&acc)[kRT][CB], int slot, float* __restrict__ part,
+                                              int pcols, int c0, int ncols, int ri, int g) {
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-      f32x4 s = acc[rt][cb];
-#pragma unroll
-      for (int w = 0; w < kWaves - 1; ++w) s += red[w][rt * CB + cb][lane];
-      const int c = cb * 16 + ri;  // D layout: column = lane % 16, rows 4 * (lane / 16) + v
+      const int c = cb * 16 + ri;
       if (c < ncols)
-        *reinterpret_cast<f32x4*>(&part[((size_t)item * pcols + c0 + c) * kRowTile + rt * 16 + g * 4]) = s;
+        *reinterpret_cast<f32x4*>(&part[((size_t)slot * pcols + c0 + c) * kRowTile + rt * 16 + g * 4]) = acc[rt][cb];
     }
+}
+
+// Runs `body(chunk)` for the chunks at positions [kb, ke) of a row tile's list;
+// the chunk indices are read 64 at a time, one per lane, and broadcast with
+// readlane so that the chunk is uniform across the wave.
+template <class F>
+__device__ __forceinline__ void for_chunks(const uint16_t* lst, int kb, int ke, int lane, F&& body) {
+#pragma unroll 1
+  for (int k0 = kb; k0 < ke; k0 += 64) {
+    const int m = min(64, ke - k0);
+    const int vidx = lane < m ? (int)lst[k0 + lane] : 0;
+#pragma unroll 1
+    for (int t = 0; t < m; ++t) body(__builtin_amdgcn_readlane(vidx, t));
+  }
+}
+
+// As for_chunks with two operand buffers: the next chunk's loads are issued
+// before the current chunk is computed (a load past the end repeats the last
+// chunk and is not used).
+template <class Buf, class L, class C>
+__device__ __forceinline__ void for_chunks_pf(const uint16_t* lst, int kb, int ke, int lane, L&& load, C&& compute) {
+#pragma unroll 1
+  for (int k0 = kb; k0 < ke; k0 += 64) {
+    const int m = min(64, ke - k0);
+    const int vidx = lane < m ? (int)lst[k0 + lane] : 0;
+    Buf a, b;
+    load(a, __builtin_amdgcn_readlane(vidx, 0));
+#pragma unroll 1
+    for (int t = 0; t < m; t += 2) {
+      load(b, __builtin_amdgcn_readlane(vidx, min(t + 1, m - 1)));
+      __builtin_amdgcn_sched_barrier(0);  // keep the next chunk's loads ahead of this compute
+      compute(a);
+      if (t + 1 >= m) break;
+      load(a, __builtin_amdgcn_readlane(vidx, min(t + 2, m - 1)));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(b);
+    }
+  }
+}
+
+// One wave's share of a product: for each row tile its units touch, load the
+// tile's 64 row coordinates, accumulate over the tile's chunks in the range, and
+// write the partial rows. `chunk_fn(acc, xi, yi, ch)` accumulates one chunk.
+template <int CB, class F>
+__device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __restrict__ part, int pcols, int c0,
+                                             int ncols, F&& chunk_fn) {
+  const WaveRange wr = wave_range(w, P);
+  if (wr.u0 >= wr.u1) return;
+  const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
+  int u = wr.u0, r = wr.r, slot = wr.slot;
+#pragma unroll 1
+  while (u < wr.u1) {
+    const int off = P.unit_off[r];
+    const int end = min(wr.u1, off + P.count[r]);
+    float xi[kRT], yi[kRT];
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
+      const int i = r * kRowTile + rt * 16 + ri;
+      xi[rt] = P.xs[i];
+      yi[rt] = P.ys[i];
+    }
+    f32x4 acc[kRT][CB];
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    chunk_fn(acc, xi, yi, P.list + (size_t)r * P.nch, u - off, end - off, lane);
+    store_partial<CB>(acc, slot, part, pcols, c0, ncols, ri, g);
+    ++slot;
+    ++r;
+    u = end;
+  }
 }
 
 // ---------------------------------------------------------------- precision form
@@ -211,15 +259,23 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
   const float yj[8] = {c.y0[0], c.y0[1], c.y0[2], c.y0[3], c.y1[0], c.y1[1], c.y1[2], c.y1[3]};
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
-    float hf[8], lf[8];
+    float hf[8], lf[8], dx[8], dy[8], d2[8], k2[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float dx = xi[rt] - xj[e], dy = yi[rt] - yj[e];
-      const float d2 = fmaf(dx, dx, dy * dy);
-      const float k2 = exp2_fast(fmaf(d2, -s2, 11.f));             // 2^11 k
-      hf[e] = __uint_as_float(__float_as_uint(k2) & 0xffffe000u);  // top 11 significant bits
-      lf[e] = k2 - hf[e];
-    }
+    for (int e = 0; e < 8; ++e) dx[e] = xi[rt] - xj[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dy[e] = yi[rt] - yj[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d2[e] = dy[e] * dy[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d2[e] = fmaf(dx[e], dx[e], d2[e]);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d2[e] = fmaf(d2[e], -s2, 11.f);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) k2[e] = exp2_fast(d2[e]);  // 2^11 k
+#pragma unroll
+    for (int e = 0; e < 8; ++e) hf[e] = __uint_as_float(__float_as_uint(k2[e]) & 0xffffe000u);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lf[e] = k2[e] - hf[e];
     half8 hi, lo;
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
@@ -243,117 +299,74 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
 }
 
 template <int CB>
-__device__ __forceinline__ void mvm_f16x3_item(int item, const TilePlan P, float s2, const _Float16* __restrict__ Vh,
+__device__ __forceinline__ void mvm_f16x3_wave(int w, const TilePlan& P, float s2, const _Float16* __restrict__ Vh,
                                                const _Float16* __restrict__ Vl, int ldh, int ncols,
                                                float* __restrict__ part, int pcols, int c0) {
-  const Item it = item_of(item, P);
-  if (it.r < 0) return;
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ri = lane & 15, g = lane >> 4;
-  float xi[kRT], yi[kRT];
-#pragma unroll
-  for (int rt = 0; rt < kRT; ++rt) {
-    const int i = it.r * kRowTile + rt * 16 + ri;
-    xi[rt] = P.xs[i];
-    yi[rt] = P.ys[i];
-  }
-  f32x4 acc[kRT][CB];
-#pragma unroll
-  for (int rt = 0; rt < kRT; ++rt)
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // This wave's chunks are list entries kw, kw + 4, ...; their indices are
-  // read 64 at a time, one per lane, and broadcast with readlane.
-  const uint16_t* lst = P.list + (size_t)it.r * P.nch;
-  const int kw = it.beg + wave;
-  const int nk = kw < it.end ? (it.end - kw + kWaves - 1) / kWaves : 0;
-#pragma unroll 1
-  for (int t0 = 0; t0 < nk; t0 += 64) {
-    const int m = min(64, nk - t0);
-    const int vidx = lane < m ? (int)lst[kw + kWaves * (t0 + lane)] : 0;
-    // two operand buffers: the next chunk's loads are in flight while the
-    // current one is computed (a load past the end repeats the last chunk)
-    F16Chunk<CB> a, b;
-    f16_load(a, P, Vh, Vl, ldh, __builtin_amdgcn_readlane(vidx, 0), ri, g);
-#pragma unroll 1
-    for (int t = 0; t < m; t += 2) {
-      f16_load(b, P, Vh, Vl, ldh, __builtin_amdgcn_readlane(vidx, min(t + 1, m - 1)), ri, g);
-      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the compute
-      f16_compute(acc, a, xi, yi, s2);
-      if (t + 1 >= m) break;
-      f16_load(a, P, Vh, Vl, ldh, __builtin_amdgcn_readlane(vidx, min(t + 2, m - 1)), ri, g);
-      __builtin_amdgcn_sched_barrier(0);
-      f16_compute(acc, b, xi, yi, s2);
-    }
-  }
-  item_store<CB>(acc, item, part, pcols, c0, ncols);
+  const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
+  wave_product<CB>(w, P, part, pcols, c0, ncols,
+                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint16_t* lst,
+                       int kb, int ke, int lane) {
+                     for_chunks_pf<F16Chunk<CB>>(lst, kb, ke, lane,
+                         [&](F16Chunk<CB>& c, int ch) { f16_load(c, P, Vh, Vl, ldh, ch, ri, g); },
+                         [&](const F16Chunk<CB>& c) { f16_compute(acc, c, xi, yi, s2); });
+                   });
 }
 
+// One wave per share of the plan's units; 4 independent waves per workgroup.
 template <int CB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB >= 3 ? 2 : 3))) void mvm_f16x3_kernel(const TilePlan P, float s2, const _Float16* __restrict__ Vh,
+__global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, float s2, const _Float16* __restrict__ Vh,
                                                         const _Float16* __restrict__ Vl, int ldh, int ncols,
                                                         float* __restrict__ part, int pcols, int c0, CgGate gate) {
   if (gate.skip_all()) return;
-  mvm_f16x3_item<CB>(blockIdx.x, P, s2, Vh, Vl, ldh, ncols, part, pcols, c0);
+  const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  mvm_f16x3_wave<CB>(w, P, s2, Vh, Vl, ldh, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- FP32 form
 
 template <int CB>
-__device__ __forceinline__ void mvm_f32_item(int item, const TilePlan P, float s2, const float* __restrict__ Vp,
-                                             int ldh, int ncols, float* __restrict__ part, int pcols, int c0) {
-  const Item it = item_of(item, P);
-  if (it.r < 0) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ri = lane & 15, g = lane >> 4;
-  float xi[kRT], yi[kRT];
+__device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT],
+                                          const TilePlan& P, float s2, const float* __restrict__ Vp, int ldh, int ch,
+                                          int ri, int g) {
+  // two groups of 16 points; in each, this lane's 4 consecutive points
+  const int jc = ch * kChunk + g * 4;
+  float xj[8], yj[8];
+  *reinterpret_cast<f32x4*>(&xj[0]) = *reinterpret_cast<const f32x4*>(&P.xs[jc]);
+  *reinterpret_cast<f32x4*>(&xj[4]) = *reinterpret_cast<const f32x4*>(&P.xs[jc + 16]);
+  *reinterpret_cast<f32x4*>(&yj[0]) = *reinterpret_cast<const f32x4*>(&P.ys[jc]);
+  *reinterpret_cast<f32x4*>(&yj[4]) = *reinterpret_cast<const f32x4*>(&P.ys[jc + 16]);
+  f32x4 b[CB][2];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      b[cb][h] = *reinterpret_cast<const f32x4*>(&Vp[(size_t)(cb * 16 + ri) * ldh + jc + 16 * h]);
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
-    const int i = it.r * kRowTile + rt * 16 + ri;
-    xi[rt] = P.xs[i];
-    yi[rt] = P.ys[i];
-  }
-  f32x4 acc[kRT][CB];
+    float kv[8];
 #pragma unroll
-  for (int rt = 0; rt < kRT; ++rt)
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const uint16_t* lst = P.list + (size_t)it.r * P.nch;
-#pragma unroll 1
-  for (int k = it.beg + wave; k < it.end; k += kWaves) {
-    // two groups of 16 points; in each, this lane's 4 consecutive points
-    const int jc = (int)lst[k] * kChunk + g * 4;
-    float xj[8], yj[8];
-    *reinterpret_cast<f32x4*>(&xj[0]) = *reinterpret_cast<const f32x4*>(&P.xs[jc]);
-    *reinterpret_cast<f32x4*>(&xj[4]) = *reinterpret_cast<const f32x4*>(&P.xs[jc + 16]);
-    *reinterpret_cast<f32x4*>(&yj[0]) = *reinterpret_cast<const f32x4*>(&P.ys[jc]);
-    *reinterpret_cast<f32x4*>(&yj[4]) = *reinterpret_cast<const f32x4*>(&P.ys[jc + 16]);
-    f32x4 b[CB][2];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int c = cb * 16 + ri;
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        b[cb][h] = c < ncols ? *reinterpret_cast<const f32x4*>(&Vp[(size_t)c * ldh + jc + 16 * h])
-                             : f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int e = 0; e < 8; ++e) {
+      const float dx = xi[rt] - xj[e], dy = yi[rt] - yj[e];
+      const float d2 = fmaf(dx, dx, dy * dy);
+      kv[e] = exp2_fast(-(d2 * s2));
     }
 #pragma unroll
-    for (int rt = 0; rt < kRT; ++rt) {
-      float kv[8];
+    for (int e = 0; e < 8; ++e)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float dx = xi[rt] - xj[e], dy = yi[rt] - yj[e];
-        const float d2 = fmaf(dx, dx, dy * dy);
-        kv[e] = exp2_fast(-(d2 * s2));
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-          acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[e], b[cb][e >> 2][e & 3], acc[rt][cb], 0, 0, 0);
-    }
+      for (int cb = 0; cb < CB; ++cb)
+        acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[e], b[cb][e >> 2][e & 3], acc[rt][cb], 0, 0, 0);
   }
-  item_store<CB>(acc, item, part, pcols, c0, ncols);
+}
+
+template <int CB>
+__device__ __forceinline__ void mvm_f32_wave(int w, const TilePlan& P, float s2, const float* __restrict__ Vp,
+                                             int ldh, int ncols, float* __restrict__ part, int pcols, int c0) {
+  const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
+  wave_product<CB>(w, P, part, pcols, c0, ncols,
+                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint16_t* lst,
+                       int kb, int ke, int lane) {
+                     for_chunks(lst, kb, ke, lane, [&](int ch) { f32_chunk<CB>(acc, xi, yi, P, s2, Vp, ldh, ch, ri, g); });
+                   });
 }
 
 template <int CB>
@@ -361,22 +374,27 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(const TilePlan P, float s2
                                                       int ldh, int ncols, float* __restrict__ part, int pcols, int c0,
                                                       CgGate gate) {
   if (gate.skip_all()) return;
-  mvm_f32_item<CB>(blockIdx.x, P, s2, Vp, ldh, ncols, part, pcols, c0);
+  const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  mvm_f32_wave<CB>(w, P, s2, Vp, ldh, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- reduction
 
-// Y[c][perm[j]] = (amp2 * colscale[c]) * sum_s part[r, s][c][row] + beta Y, the
-// items of row tile r = j / 64 in order.
+// Y[c][perm[j]] = (amp2 * colscale[c]) * sum_w part[slot(w, r)][c][row] + beta Y,
+// over the waves w that hold units of row tile r = j / 64, in wave order.
 __device__ __forceinline__ void reduce_body(int bx, int c, const TilePlan& P, int nrhs, const float* __restrict__ part,
                                             int pcols, const float* __restrict__ colscale, float amp2, float* Y,
                                             int ldy, float beta) {
   const int j = bx * blockDim.x + threadIdx.x;
   if (j >= P.n || c >= nrhs) return;
   const int r = j / kRowTile, row = j - r * kRowTile;
-  const int ns = P.nseg[r];
+  const int2 wv = P.rwave[r];
   float s = 0.f;
-  for (int q = 0; q < ns; ++q) s += part[((size_t)(r * kMaxSeg + q) * pcols + c) * kRowTile + row];
+  for (int w = wv.x; w <= wv.y; ++w) {
+    const int r0 = P.wrow[w];
+    if (r0 < 0) continue;  // a wave without units
+    s += part[((size_t)(P.wslot[w] + r - r0) * pcols + c) * kRowTile + row];
+  }
   const float f = colscale ? amp2 * colscale[c] : amp2;
   float* y = Y + (size_t)c * ldy + (P.perm ? P.perm[j] : j);
   const float res = f * s;
@@ -393,7 +411,7 @@ __global__ void reduce_kernel(const TilePlan P, int nrhs, const float* __restric
 // ---------------------------------------------------------------- workspace
 
 // Buffers of one product: RHS block in sorted order (FP16 hi/lo or FP32), the
-// column scales and the partial rows of every work item.
+// column scales and the partial rows of the waves.
 struct ProdBufs {
   unsigned* colmax;
   float* inv_scale;
@@ -414,7 +432,7 @@ static void carve_prod(C& cv, int n, int nrhs, int prec, ProdBufs& b) {
   b.Vh = f16 ? cv.template take<_Float16>((size_t)b.ncp * b.ldh) : nullptr;
   b.Vl = f16 ? cv.template take<_Float16>((size_t)b.ncp * b.ldh) : nullptr;
   b.Vp = f16 ? nullptr : cv.template take<float>((size_t)b.ncp * b.ldh);
-  b.part = cv.template take<float>((size_t)nrt * kMaxSeg * nrhs * kRowTile);
+  b.part = cv.template take<float>((size_t)plan_slots(n) * nrhs * kRowTile);
 }
 
 size_t mfma_workspace(int n, int nrhs, int prec) {
@@ -432,14 +450,14 @@ float plan_threshold(int prec) { return prec == GPL_PREC_F16X3 ? kSkipF16x3 : kS
 template <int CB>
 static void launch_f16x3(const TilePlan& P, float s2, const _Float16* Vh, const _Float16* Vl, int ldh, int ncols,
                          float* part, int pcols, int c0, CgGate gate, hipStream_t stream) {
-  hipLaunchKernelGGL((mvm_f16x3_kernel<CB>), dim3(P.nrt * kMaxSeg), dim3(256), 0, stream, P, s2, Vh, Vl, ldh, ncols,
+  hipLaunchKernelGGL((mvm_f16x3_kernel<CB>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ldh, ncols,
                      part, pcols, c0, gate);
 }
 
 template <int CB>
 static void launch_f32(const TilePlan& P, float s2, const float* Vp, int ldh, int ncols, float* part, int pcols,
                        int c0, CgGate gate, hipStream_t stream) {
-  hipLaunchKernelGGL((mvm_f32_kernel<CB>), dim3(P.nrt * kMaxSeg), dim3(256), 0, stream, P, s2, Vp, ldh, ncols, part,
+  hipLaunchKernelGGL((mvm_f32_kernel<CB>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vp, ldh, ncols, part,
                      pcols, c0, gate);
 }
 
@@ -524,17 +542,17 @@ __global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
   const int s = B.find(blockIdx.x);
   const ServeSlotDev& S = *B.slot[s];
   if (S.n_active[p] == 0) return;
-  const int item = blockIdx.x - B.off[s];
+  const int w = (blockIdx.x - B.off[s]) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (S.prec == GPL_PREC_F16X3) {
     if (S.nrhs > 16)
-      mvm_f16x3_item<2>(item, S.plan, S.s2, S.Vh, S.Vl, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f16x3_wave<2>(w, S.plan, S.s2, S.Vh, S.Vl, S.ldh, S.nrhs, S.part, S.nrhs, 0);
     else
-      mvm_f16x3_item<1>(item, S.plan, S.s2, S.Vh, S.Vl, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f16x3_wave<1>(w, S.plan, S.s2, S.Vh, S.Vl, S.ldh, S.nrhs, S.part, S.nrhs, 0);
   } else {
     if (S.nrhs > 16)
-      mvm_f32_item<2>(item, S.plan, S.s2, S.Vp, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f32_wave<2>(w, S.plan, S.s2, S.Vp, S.ldh, S.nrhs, S.part, S.nrhs, 0);
     else
-      mvm_f32_item<1>(item, S.plan, S.s2, S.Vp, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f32_wave<1>(w, S.plan, S.s2, S.Vp, S.ldh, S.nrhs, S.part, S.nrhs, 0);
   }
 }
 
@@ -573,7 +591,7 @@ int mvm_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* ds
                          [](const ServeSlotDev& S) { return cdiv(S.ldh, 256) * S.ncp; }, stream));
   hipEvent_t t0 = timing_begin(stream);
   GPL_TRY(launch_grouped(mvm_grouped_kernel, hslots, dslots, nslots, p,
-                         [](const ServeSlotDev& S) { return S.plan.nrt * kMaxSeg; }, stream));
+                         [](const ServeSlotDev& S) { return S.plan.nw / kWaves; }, stream));
   timing_end(t0, stream);
   GPL_TRY(launch_grouped(reduce_grouped_kernel, hslots, dslots, nslots, p,
                          [](const ServeSlotDev& S) { return cdiv(S.N, 256) * S.nrhs; }, stream));

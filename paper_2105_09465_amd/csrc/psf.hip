@@ -52,8 +52,10 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
                                                  int ld_dotv, double* __restrict__ partial, int ntiles) {
   __shared__ float S1[kMaxWin * kMaxWin];
   __shared__ float S2[kMaxWin * kFineTile];
+  __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
   __shared__ double red[4];
   const int M = n * ss, r = taps.r;
+  if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
   const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;  // output pixels per tile side
   const int F = TP * ss, W = F + 2 * r;
   const int tiles_x = (n + TP - 1) / TP;
@@ -69,7 +71,7 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
   for (int idx = threadIdx.x; idx < W * F; idx += blockDim.x) {
     const int wy = idx / F, x = idx - wy * F;
     float s = 0.f;
-    for (int b = -r; b <= r; ++b) s += taps.w[b + r] * S1[wy * W + x + r - b];
+    for (int b = -r; b <= r; ++b) s += tw[b + r] * S1[wy * W + x + r - b];
     S2[idx] = s;
   }
   __syncthreads();
@@ -84,7 +86,7 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
       for (int sx = 0; sx < ss; ++sx) {
         const int y = oy * ss + sy, x = ox * ss + sx;
         float v = 0.f;
-        for (int a = -r; a <= r; ++a) v += taps.w[a + r] * S2[(y + r - a) * F + x];
+        for (int a = -r; a <= r; ++a) v += tw[a + r] * S2[(y + r - a) * F + x];
         acc += v;
       }
     const int I = Iy * n + Ix;
@@ -118,8 +120,10 @@ __device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss,
                                                  int ld_out, float alpha, float beta) {
   __shared__ float S1[kMaxWin * kMaxWin];
   __shared__ float S2[kMaxWin * kFineTile];
+  __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
   const int M = n * ss, r = taps.r;
   const int F = kFineTile, W = F + 2 * r;
+  if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
   const int tiles_x = (M + F - 1) / F;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
@@ -134,7 +138,7 @@ __device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss,
   for (int idx = threadIdx.x; idx < W * F; idx += blockDim.x) {
     const int wy = idx / F, x = idx - wy * F;
     float s = 0.f;
-    for (int b = -r; b <= r; ++b) s += taps.w[b + r] * S1[wy * W + x + r + b];
+    for (int b = -r; b <= r; ++b) s += tw[b + r] * S1[wy * W + x + r + b];
     S2[idx] = s;
   }
   __syncthreads();
@@ -143,7 +147,7 @@ __device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss,
     const int fy = fy0 + y, fx = fx0 + x;
     if (fy >= M || fx >= M) continue;
     float v = 0.f;
-    for (int a = -r; a <= r; ++a) v += taps.w[a + r] * S2[(y + r + a) * F + x];
+    for (int a = -r; a <= r; ++a) v += tw[a + r] * S2[(y + r + a) * F + x];
     const size_t o_idx = (size_t)c * ld_out + (size_t)fy * M + fx;
     float res = alpha * v;
     if (beta != 0.f) res += beta * out[o_idx];

@@ -65,7 +65,7 @@ static void carve_slot(Cv& cv, int n, int ss, int nrhs, int n_lanczos, int prec,
   x.Vh = cv.template take<_Float16>(f16 ? (size_t)ncp * ldh : 1);
   x.Vl = cv.template take<_Float16>(f16 ? (size_t)ncp * ldh : 1);
   x.Vp = cv.template take<float>(f16 ? 1 : (size_t)ncp * ldh);
-  x.part = cv.template take<float>((size_t)nrt * kMaxSeg * nrhs * kRowTile);
+  x.part = cv.template take<float>((size_t)plan_slots(N) * nrhs * kRowTile);
   x.st0 = cv.template take<ColState>(nrhs);
   x.st1 = cv.template take<ColState>(nrhs);
   x.bb = cv.template take<double>(nrhs);

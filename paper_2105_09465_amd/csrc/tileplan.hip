@@ -59,7 +59,7 @@ __global__ void plan_boxes_kernel(int n, int nch, const float* __restrict__ xs, 
 
 // One wave per row tile: ascending list of live chunks by ballot compaction.
 __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const float4* __restrict__ cbox, float s2,
-                                                        float threshold, int* count, int* nseg, uint16_t* list) {
+                                                        float threshold, int* count, uint16_t* list) {
   const int r = blockIdx.x;
   if (r >= nrt) return;
   const int lane = threadIdx.x;
@@ -80,10 +80,82 @@ __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const 
     if (live) out[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint16_t)c;
     base += __popcll(mask);
   }
-  if (lane == 0) {
-    count[r] = base;
-    nseg[r] = min(kMaxSeg, max(1, cdiv(base, kSegChunks)));
+  if (lane == 0) count[r] = base;
+}
+
+// Exclusive prefix sum of n ints in one workgroup of 1024 threads (in place
+// allowed); the sum goes to *sum.
+__global__ __launch_bounds__(1024) void plan_scan_kernel(int n, const int* in, int* out, int* sum) {
+  __shared__ int wsum[16];
+  __shared__ int carry_s;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) carry_s = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + tid;
+    const int v = i < n ? in[i] : 0;
+    int x = v;  // inclusive scan within the wave
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int before = carry_s;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    if (i < n) out[i] = before + x - v;
+    __syncthreads();
+    if (tid == 1023) carry_s = before + x;
+    __syncthreads();
   }
+  if (tid == 0) *sum = carry_s;
+}
+
+// Largest row tile r with unit_off[r] <= u.
+__device__ __forceinline__ int row_of_unit(const int* unit_off, int nrt, int u) {
+  int lo = 0, hi = nrt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (unit_off[mid] <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Largest wave w with wave_unit(w) <= u (the wave whose range holds unit u).
+__device__ __forceinline__ int wave_of_unit(int u, int T, int nw) {
+  int lo = 0, hi = nw - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wave_unit(mid, T, nw) <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per wave: first row tile and number of row tiles its units touch (the count
+// goes to nrows[w], scanned into partial slots afterwards).
+__global__ void plan_waves_kernel(int nrt, int nw, const int* unit_off, const int* total, int* wrow, int* nrows) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const int T = *total;
+  const int u0 = wave_unit(w, T, nw), u1 = wave_unit(w + 1, T, nw);
+  if (u0 >= u1) {
+    wrow[w] = -1;
+    nrows[w] = 0;
+    return;
+  }
+  const int r0 = row_of_unit(unit_off, nrt, u0), r1 = row_of_unit(unit_off, nrt, u1 - 1);
+  wrow[w] = r0;
+  nrows[w] = r1 - r0 + 1;
+}
+
+// Per row tile: first and last wave holding its units.
+__global__ void plan_rowwaves_kernel(int nrt, int nw, const int* unit_off, const int* count, const int* total,
+                                     int2* rwave) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrt) return;
+  const int T = *total;
+  const int a = unit_off[r], c = count[r];
+  rwave[r] = c > 0 ? make_int2(wave_of_unit(a, T, nw), wave_of_unit(a + c - 1, T, nw)) : make_int2(0, -1);
 }
 
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
@@ -96,14 +168,24 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
     GPL_REQUIRE(m > 0 && (long)m * m == n, "grid does not match n=%d", n);
   }
   int* perm = const_cast<int*>(p.perm);
-  if (!grid) p.perm = nullptr;
+  if (!grid) p.perm = nullptr;  // identity: the buffer stays unused
   hipLaunchKernelGGL(plan_points_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, n, p.npad, px, py, m,
                      grid ? perm : nullptr, p.xs, p.ys);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_boxes_kernel, dim3(cdiv(p.nch, 256)), dim3(256), 0, stream, n, p.nch, p.xs, p.ys, p.cbox);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_lists_kernel, dim3(p.nrt), dim3(64), 0, stream, p.nrt, p.nch, p.cbox, s2, threshold,
-                     p.count, p.nseg, p.list);
+                     p.count, p.list);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, p.nrt, p.count, p.unit_off, p.total);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_waves_kernel, dim3(cdiv(p.nw, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.unit_off, p.total,
+                     p.wrow, p.wslot);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, p.nw, p.wslot, p.wslot, p.wslot + p.nw);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_rowwaves_kernel, dim3(cdiv(p.nrt, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.unit_off,
+                     p.count, p.total, p.rwave);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

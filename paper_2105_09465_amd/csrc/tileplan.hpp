@@ -20,8 +20,7 @@ namespace gpl {
 
 constexpr int kRowTile = 64;     // rows per wave (four 16-row MFMA tiles)
 constexpr int kChunk = 32;       // source points per chunk
-constexpr int kSegChunks = 32;   // chunks per work item that trigger one more item
-constexpr int kMaxSeg = 8;       // work items per row tile
+constexpr int kMaxPlanWaves = 4096;    // waves of one product launch (4 per SIMD)
 constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
 
 // Skip thresholds on s2 g^2 (exp2 arguments: 11 - s2 d^2 <= -25 leaves the FP16
@@ -30,18 +29,37 @@ constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
 constexpr float kSkipF16x3 = 36.f;
 constexpr float kSkipFp32 = 152.f;
 
+// The evaluated work is a sequence of units, the live (row tile, chunk) pairs in
+// row-tile order. A product launch of nw waves gives wave w the contiguous
+// units [w T / nw, (w + 1) T / nw) (T units in all), so every wave gets the same
+// work; a wave writes one partial row block per row tile it touches, into
+// consecutive slots starting at wslot[w], and the partials of a row tile are
+// summed in wave order.
 struct TilePlan {
   int n;     // points
   int nrt;   // row tiles = ceil(n / 64)
   int nch;   // chunks = 2 nrt
   int npad;  // 64 nrt
+  int nw;    // waves of a product launch (multiple of 4)
   const int* perm;  // sorted position -> caller index; nullptr = identity
   float *xs, *ys;   // [npad] points in sorted order, zero padded
   float4* cbox;     // [nch] (xmin, xmax, ymin, ymax); empty chunks have xmin = +inf
-  int* count;       // [nrt] live chunks of each row tile
-  int* nseg;        // [nrt] work items of each row tile, in [1, kMaxSeg]
+  int* count;       // [nrt] live chunks of each row tile (>= 1)
   uint16_t* list;   // [nrt][nch] live chunks of each row tile, ascending
+  int* unit_off;    // [nrt] first unit of each row tile (exclusive prefix of count)
+  int* total;       // [1] T
+  int* wrow;        // [nw] row tile of each wave's first unit (-1: no units)
+  int* wslot;       // [nw + 1] first partial slot of each wave
+  int2* rwave;      // [nrt] first and last wave holding units of each row tile
 };
+
+// Waves of a product launch for n points, and partial slots it may write.
+__host__ __device__ inline int plan_waves(int n) {
+  const int nrt = (n + kRowTile - 1) / kRowTile;
+  const int w = nrt * 8 < kMaxPlanWaves ? nrt * 8 : kMaxPlanWaves;
+  return (w + 3) / 4 * 4;
+}
+__host__ __device__ inline int plan_slots(int n) { return plan_waves(n) + (n + kRowTile - 1) / kRowTile; }
 
 // Bytes of the plan buffers for n points (0 for n <= 0).
 size_t plan_workspace(int n);
@@ -52,15 +70,18 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.nrt = cdiv(n, kRowTile);
   p.nch = 2 * p.nrt;
   p.npad = p.nrt * kRowTile;
-  p.perm = nullptr;
-  int* perm = cv.template take<int>((size_t)p.npad);
-  p.perm = perm;
+  p.nw = plan_waves(n);
+  p.perm = cv.template take<int>((size_t)p.npad);
   p.xs = cv.template take<float>((size_t)p.npad);
   p.ys = cv.template take<float>((size_t)p.npad);
   p.cbox = cv.template take<float4>((size_t)p.nch);
   p.count = cv.template take<int>((size_t)p.nrt);
-  p.nseg = cv.template take<int>((size_t)p.nrt);
   p.list = cv.template take<uint16_t>((size_t)p.nrt * p.nch);
+  p.unit_off = cv.template take<int>((size_t)p.nrt);
+  p.total = cv.template take<int>(1);
+  p.wrow = cv.template take<int>((size_t)p.nw);
+  p.wslot = cv.template take<int>((size_t)p.nw + 1);
+  p.rwave = cv.template take<int2>((size_t)p.nrt);
 }
 
 // Build the plan on `stream`. With `grid` the points are the fine grid of that
@@ -69,6 +90,9 @@ void plan_carve(C& cv, int n, TilePlan& p) {
 // `threshold` one of kSkipF16x3 / kSkipFp32.
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
                hipStream_t stream);
+
+// Device: first unit of wave w of nw over T units.
+__device__ __forceinline__ int wave_unit(int w, int T, int nw) { return (int)((long long)w * T / nw); }
 
 // Device: Z-order rank of fine pixel (fx, fy) among the pixels of an m x m grid.
 __device__ __forceinline__ int zorder_rank(int fx, int fy, int m) {
