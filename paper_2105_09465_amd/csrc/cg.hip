@@ -5,9 +5,11 @@
 // beta recurrences and the recorded Lanczos coefficients are FP64.
 //
 // One iteration is a fixed sequence of launches on the caller's stream:
-//   T1 = B_op^T P  ->  T2 = K T1  ->  AP = B_op T2 + sigma^2 P  (+ p.Ap partials)
+//   B_op^T P (written straight into the kernel product's RHS buffers)
+//   -> T2 = K B_op^T P  ->  AP = B_op T2 + sigma^2 P  (+ p.Ap partials)
 //   -> update1 (alpha; X += alpha P; R -= alpha AP; r.r partials)
-//   -> update2 (beta; P = R + beta P; bookkeeping).
+//   -> update2 (beta; P = R + beta P; bookkeeping; partial max |P| for the
+//      column scales of the precision form).
 // Per-column state is double-buffered by iteration parity so that every block
 // of a kernel reads the same old values. Kernels return at once when no column
 // is active. The host enqueues iterations in chunks, keeps one chunk in flight
@@ -23,7 +25,7 @@
 namespace gpl {
 
 struct CgBuffers {
-  float *R, *P, *AP, *T1, *T2;
+  float *R, *P, *AP, *T2;
   int ldv, ldf;
   void* mvm_ws;
   size_t mvm_ws_bytes;
@@ -32,6 +34,7 @@ struct CgBuffers {
   ColState* st[2];
   double* bb;
   int* n_active;  // [2]
+  unsigned* pmax;  // [nrhs][nb_upd] partial max |P| (float bits)
 };
 
 template <class C>
@@ -42,7 +45,6 @@ static void carve_cg(C& c, int npix, int N, int nrhs, int prec, CgBuffers* b, si
   float* R = c.template take<float>((size_t)ldv * nrhs);
   float* P = c.template take<float>((size_t)ldv * nrhs);
   float* AP = c.template take<float>((size_t)ldv * nrhs);
-  float* T1 = c.template take<float>((size_t)ldf * nrhs);
   float* T2 = c.template take<float>((size_t)ldf * nrhs);
   char* mws = c.template take<char>(mvm_bytes);
   double* pap = c.template take<double>((size_t)ntiles * nrhs);
@@ -51,28 +53,49 @@ static void carve_cg(C& c, int npix, int N, int nrhs, int prec, CgBuffers* b, si
   ColState* s1 = c.template take<ColState>(nrhs);
   double* bb = c.template take<double>(nrhs);
   int* na = c.template take<int>(2);
+  unsigned* pm = c.template take<unsigned>((size_t)nb_upd * nrhs);
   if (b) {
-    *b = CgBuffers{R, P, AP, T1, T2, ldv, ldf, mws, mvm_bytes, pap, rrp, ntiles, nb_upd, {s0, s1}, bb, na};
+    *b = CgBuffers{R, P, AP, T2, ldv, ldf, mws, mvm_bytes, pap, rrp, ntiles, nb_upd, {s0, s1}, bb, na, pm};
   }
   if (mvm_bytes_out) *mvm_bytes_out = mvm_bytes;
 }
 
-// R = P = B, X = 0, partial |b|^2.
+// Block maximum of v >= 0 (result in thread 0).
+__device__ __forceinline__ float block_max(float v, float* smem) {
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) smem[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float m = 0.f;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, smem[w]);
+  return m;
+}
+
+// R = P = B, X = 0, partial |b|^2 and partial max |P|.
 __global__ __launch_bounds__(256) void cg_init_kernel(int npix, const float* __restrict__ Bm, int ldb, float* X,
-                                                      int ldx, float* R, float* P, int ldv, double* part, int nb) {
+                                                      int ldx, float* R, float* P, int ldv, double* part, int nb,
+                                                      unsigned* pmax) {
   __shared__ double red[4];
+  __shared__ float redm[4];
   const int c = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double s = 0.0;
+  float m = 0.f;
   if (i < npix) {
     const float b = Bm[(size_t)c * ldb + i];
     R[(size_t)c * ldv + i] = b;
     P[(size_t)c * ldv + i] = b;
     X[(size_t)c * ldx + i] = 0.f;
     s = (double)b * b;
+    m = fabsf(b);
   }
   s = block_sum_double(s, red);
-  if (threadIdx.x == 0) part[(size_t)c * nb + blockIdx.x] = s;
+  m = block_max(m, redm);
+  if (threadIdx.x == 0) {
+    part[(size_t)c * nb + blockIdx.x] = s;
+    pmax[(size_t)c * nb + blockIdx.x] = __float_as_uint(m);
+  }
 }
 
 __global__ void cg_init_state_kernel(int nrhs, const double* part, int nb, ColState* st0, ColState* st1, double* bb,
@@ -167,9 +190,10 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
                                                 const double* rr_part, int nb, const ColState* sin, ColState* sout,
                                                 const double* bb, const int* n_active_in, int* n_active_out,
                                                 double tol, int max_iter, int fixed_iters, int n_lanczos,
-                                                double* ab) {
+                                                double* ab, unsigned* pmax) {
   __shared__ double s_beta;
   __shared__ int s_go;
+  __shared__ float redm[4];
   const ColState st = sin[c];
   if (*n_active_in == 0 || !st.active) {  // carry the state into the other parity
     if (bx == 0 && threadIdx.x == 0) sout[c] = st;
@@ -220,20 +244,27 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
     }
   }
   __syncthreads();
+  if (!s_go) return;
   const int i = bx * blockDim.x + threadIdx.x;
-  if (s_go && i < npix) {
+  float m = 0.f;
+  if (i < npix) {
     const size_t iv = (size_t)c * ldv + i;
-    P[iv] = fmaf((float)s_beta, P[iv], R[iv]);
+    const float pn = fmaf((float)s_beta, P[iv], R[iv]);
+    P[iv] = pn;
+    m = fabsf(pn);
   }
+  m = block_max(m, redm);
+  if (threadIdx.x == 0) pmax[(size_t)c * nb + bx] = __float_as_uint(m);
 }
 
 __global__ __launch_bounds__(256) void cg_update2_kernel(int npix, const float* R, float* P, int ldv,
                                                          const double* rr_part, int nb, const ColState* sin,
                                                          ColState* sout, const double* bb, const int* n_active_in,
                                                          int* n_active_out, double tol, int max_iter,
-                                                         int fixed_iters, int n_lanczos, double* ab) {
+                                                         int fixed_iters, int n_lanczos, double* ab,
+                                                         unsigned* pmax) {
   cg_update2_body(blockIdx.x, blockIdx.y, npix, R, P, ldv, rr_part, nb, sin, sout, bb, n_active_in, n_active_out, tol,
-                  max_iter, fixed_iters, n_lanczos, ab);
+                  max_iter, fixed_iters, n_lanczos, ab, pmax);
 }
 
 // ---- grouped launches (serving): workgroup (local % nb, local / nb) of slot s.
@@ -250,7 +281,8 @@ __global__ __launch_bounds__(256) void cg_update2_grouped_kernel(SlotBatch B, in
   const ServeSlotDev& S = *B.slot[s];
   const int local = blockIdx.x - B.off[s];
   cg_update2_body(local % S.nb_upd, local / S.nb_upd, S.npix, S.R, S.P, S.ldv, S.rr_part, S.nb_upd, S.st[p],
-                  S.st[1 - p], S.bb, S.n_active + p, S.n_active + (1 - p), S.tol, S.max_iter, 0, S.n_lanczos, S.ab);
+                  S.st[1 - p], S.bb, S.n_active + p, S.n_active + (1 - p), S.tol, S.max_iter, 0, S.n_lanczos, S.ab,
+                  S.pmax);
 }
 
 __global__ void cg_snapshot_kernel(const int* n_active, volatile int* host_flag) {
@@ -295,10 +327,11 @@ int cg_update_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* con
 }
 
 int cg_init_launch(int npix, int nrhs, const float* Bm, int ldb, float* X, int ldx, float* R, float* P, int ldv,
-                   double* part, ColState* st0, ColState* st1, double* bb, int* n_active, int limit,
+                   double* part, ColState* st0, ColState* st1, double* bb, int* n_active, int limit, unsigned* pmax,
                    hipStream_t stream) {
   const int nb = cdiv(npix, 256);
-  hipLaunchKernelGGL(cg_init_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, Bm, ldb, X, ldx, R, P, ldv, part, nb);
+  hipLaunchKernelGGL(cg_init_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, Bm, ldb, X, ldx, R, P, ldv, part, nb,
+                     pmax);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(cg_init_state_kernel, dim3(1), dim3(256), 0, stream, nrhs, part, nb, st0, st1, bb, n_active,
                      limit);
@@ -429,11 +462,13 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
   MvmCtx mv;  // the points stay fixed for the whole solve: one tile plan
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid, nrhs,
                       prec, b.mvm_ws, b.mvm_ws_bytes, stream));
+  const RhsOut rhs_out{prec, mv.bufs.ldh, mv.bufs.Vh, mv.bufs.Vl, mv.bufs.Vp, mv.bufs.inv_scale, b.pmax, b.nb_upd};
+  const float sigma2 = (float)(prob->noise_sigma * prob->noise_sigma);
 
   const int nb = b.nb_upd;
   const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
   hipLaunchKernelGGL(cg_init_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, Bm, ldb, X, ldx, b.R, b.P, b.ldv,
-                     b.rr_part, nb);
+                     b.rr_part, nb, b.pmax);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(cg_init_state_kernel, dim3(1), dim3(256), 0, stream, nrhs, b.rr_part, nb, b.st[0], b.st[1], b.bb,
                      b.n_active, limit);
@@ -448,15 +483,19 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
       const int p = it & 1;
       CgGate gate;
       gate.n_active = b.n_active + p;
-      GPL_TRY(apply_A_into(prob, taps, mv, nrhs, b.P, b.ldv, b.T1, b.T2, b.ldf, b.AP, b.ldv, b.pap_part, gate,
-                           stream));
+      // AP = B K B^T P + sigma^2 P with p.Ap partials; B^T P goes straight into
+      // the product's RHS buffers
+      GPL_TRY(psf_adjoint_rhs_launch(n, ss, taps, nrhs, b.P, b.ldv, rhs_out, gate, stream));
+      GPL_TRY(mvm_run_prepared(mv, nrhs, b.T2, b.ldf, 0.f, gate, stream));
+      GPL_TRY(psf_forward_launch(n, ss, taps, nrhs, b.T2, b.ldf, b.AP, b.ldv, 1.f, 0.f, b.P, b.ldv, sigma2, b.P, b.ldv,
+                                 b.pap_part, gate, stream));
       hipLaunchKernelGGL(cg_update1_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, X, ldx, b.R, b.P, b.AP, b.ldv,
                          b.pap_part, b.ntiles, b.rr_part, nb, b.st[p], b.st[1 - p], b.n_active + p,
                          b.n_active + (1 - p));
       GPL_LAUNCH_CHECK();
       hipLaunchKernelGGL(cg_update2_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, b.R, b.P, b.ldv, b.rr_part,
                          nb, b.st[p], b.st[1 - p], b.bb, b.n_active + p, b.n_active + (1 - p), tol, max_iter,
-                         fixed_iters, n_lanczos, lanczos_ab);
+                         fixed_iters, n_lanczos, lanczos_ab, b.pmax);
       GPL_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(cg_snapshot_kernel, dim3(1), dim3(64), 0, stream, b.n_active + (end & 1),

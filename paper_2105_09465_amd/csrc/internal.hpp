@@ -43,10 +43,10 @@ struct ServeSlotDev {
   Taps taps;
   float sigma2, s2, amp2;
   const float *px, *py;
-  float *X, *R, *P, *AP, *T1, *T2;
+  float *X, *R, *P, *AP, *T2;
   int ldv, ldf;
   TilePlan plan;  // tile plan of the slot's points (grid Z-order)
-  unsigned* colmax;
+  unsigned* pmax;  // [nrhs][nb_upd] partial max |P| (float bits)
   float* inv_scale;
   _Float16 *Vh, *Vl;  // precision form: RHS block split in sorted order
   float* Vp;          // FP32 form: RHS block in sorted order
@@ -91,10 +91,20 @@ int psf_adjoint_launch(int n, int ss, const Taps& taps, int nrhs, const float* i
 // is prepared once per point set (tile plan) and run for any RHS block of at
 // most nrhs_max columns. `grid` (nullable) says the points are that grid's fine
 // pixels in row-major order.
+// Buffers of one product: the RHS block in the plan's sorted order (FP16 hi/lo
+// with per-column output scales, or FP32), column-max partials of the RHS, and
+// the partial rows of the waves.
+struct ProdBufs {
+  unsigned* colmax;
+  float* inv_scale;
+  _Float16 *Vh, *Vl;  // precision form
+  float* Vp;          // FP32 form
+  float* part;
+  int ldh, ncp;
+};
 struct MvmCtx {
   TilePlan plan;
-  void* scratch;
-  size_t scratch_bytes;
+  ProdBufs bufs;
   int prec, nrhs_max;
   float s2, amp2;
 };
@@ -103,6 +113,22 @@ int mvm_prepare(MvmCtx& m, double lengthscale, double amplitude, int n, const fl
                 const gpl_grid* grid, int nrhs, int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 int mvm_run(const MvmCtx& m, int nrhs, const float* V, int ldv, float* Y, int ldy, float beta, CgGate gate,
             hipStream_t stream);
+// The product from RHS buffers already written (by the fused PSF adjoint).
+int mvm_run_prepared(const MvmCtx& m, int nrhs, float* Y, int ldy, float beta, CgGate gate, hipStream_t stream);
+
+// Where the fused PSF adjoint writes B^T P: the product buffers of a grid-ordered
+// plan (fine point (fx, fy) at its Z-order rank), with per-column scales of the
+// precision form taken from partial maxima of |P| (|B^T P| <= max |P| / ss^2).
+struct RhsOut {
+  int prec;
+  int ldh;
+  _Float16 *Vh, *Vl;
+  float *Vp, *inv_scale;
+  const unsigned* pmax;  // [nrhs][npart] float bits of partial max |P|
+  int npart;
+};
+int psf_adjoint_rhs_launch(int n, int ss, const Taps& taps, int nrhs, const float* P, int ldp, const RhsOut& out,
+                           CgGate gate, hipStream_t stream);
 int mvm_launch(double lengthscale, double amplitude, int n, const float* px, const float* py, const gpl_grid* grid,
                int nrhs, const float* V, int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes,
                CgGate gate, hipStream_t stream);
@@ -120,7 +146,7 @@ int mvm_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* ds
 int cg_update_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
                       hipStream_t stream);
 int cg_init_launch(int npix, int nrhs, const float* Bm, int ldb, float* X, int ldx, float* R, float* P, int ldv,
-                   double* part, ColState* st0, ColState* st1, double* bb, int* n_active, int limit,
+                   double* part, ColState* st0, ColState* st1, double* bb, int* n_active, int limit, unsigned* pmax,
                    hipStream_t stream);
 int cg_finalize_launch(int nrhs, const ColState* st, const double* bb, double* bnorm2, int* iters, double* relres,
                        int* status, int n_lanczos, double* ab, hipStream_t stream);

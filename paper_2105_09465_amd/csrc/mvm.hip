@@ -38,20 +38,29 @@ int mvm_prepare(MvmCtx& m, double lengthscale, double amplitude, int n, const fl
                 const gpl_grid* grid, int nrhs, int prec, void* ws, size_t ws_bytes, hipStream_t stream) {
   GPL_TRY(check_ws(ws, ws_bytes, mvm_workspace(n, nrhs, prec)));
   Carver cv(ws, ws_bytes);
-  carve_mvm(cv, n, nrhs, prec, &m.plan, &m.scratch, &m.scratch_bytes);
+  void* scratch;
+  size_t scratch_bytes;
+  carve_mvm(cv, n, nrhs, prec, &m.plan, &scratch, &scratch_bytes);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
+  GPL_TRY(mfma_carve(m.plan, prec, nrhs, scratch, scratch_bytes, m.bufs));
   m.prec = prec;
   m.nrhs_max = nrhs;
   m.s2 = (float)kernel_scale2(lengthscale);
   m.amp2 = (float)(amplitude * amplitude);
+  GPL_TRY(mfma_zero_rhs(m.bufs, prec, stream));
   return plan_build(m.plan, n, px, py, grid, m.s2, plan_threshold(prec), stream);
+}
+
+int mvm_run_prepared(const MvmCtx& m, int nrhs, float* Y, int ldy, float beta, CgGate gate, hipStream_t stream) {
+  GPL_REQUIRE(nrhs <= m.nrhs_max, "product prepared for %d columns, %d given", m.nrhs_max, nrhs);
+  return mfma_product(m.plan, m.bufs, m.prec, m.s2, m.amp2, nrhs, Y, ldy, beta, gate, stream);
 }
 
 int mvm_run(const MvmCtx& m, int nrhs, const float* V, int ldv, float* Y, int ldy, float beta, CgGate gate,
             hipStream_t stream) {
   GPL_REQUIRE(nrhs <= m.nrhs_max, "product prepared for %d columns, %d given", m.nrhs_max, nrhs);
-  return mfma_launch(m.plan, m.prec, m.s2, m.amp2, nrhs, V, ldv, Y, ldy, beta, m.scratch, m.scratch_bytes, gate,
-                     stream);
+  GPL_TRY(mfma_prep_rhs(m.plan, m.bufs, m.prec, nrhs, V, ldv, gate, stream));
+  return mvm_run_prepared(m, nrhs, Y, ldy, beta, gate, stream);
 }
 
 int mvm_launch(double lengthscale, double amplitude, int n, const float* px, const float* py, const gpl_grid* grid,

@@ -380,21 +380,19 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(const TilePlan P, float s2
 
 // ---------------------------------------------------------------- reduction
 
-// Y[c][perm[j]] = (amp2 * colscale[c]) * sum_w part[slot(w, r)][c][row] + beta Y,
-// over the waves w that hold units of row tile r = j / 64, in wave order.
+// Y[c][perm[j]] = (amp2 * colscale[c]) * sum_q part[s0 + q][c][row] + beta Y over the
+// partial slots [s0, s0 + cnt) of row tile r = j / 64, in wave order.
 __device__ __forceinline__ void reduce_body(int bx, int c, const TilePlan& P, int nrhs, const float* __restrict__ part,
                                             int pcols, const float* __restrict__ colscale, float amp2, float* Y,
                                             int ldy, float beta) {
   const int j = bx * blockDim.x + threadIdx.x;
   if (j >= P.n || c >= nrhs) return;
   const int r = j / kRowTile, row = j - r * kRowTile;
-  const int2 wv = P.rwave[r];
+  const int2 sl = P.rslot[r];
+  const float* p0 = part + ((size_t)sl.x * pcols + c) * kRowTile + row;
+  const size_t stride = (size_t)pcols * kRowTile;
   float s = 0.f;
-  for (int w = wv.x; w <= wv.y; ++w) {
-    const int r0 = P.wrow[w];
-    if (r0 < 0) continue;  // a wave without units
-    s += part[((size_t)(P.wslot[w] + r - r0) * pcols + c) * kRowTile + row];
-  }
+  for (int q = 0; q < sl.y; ++q) s += p0[q * stride];
   const float f = colscale ? amp2 * colscale[c] : amp2;
   float* y = Y + (size_t)c * ldy + (P.perm ? P.perm[j] : j);
   const float res = f * s;
@@ -409,17 +407,6 @@ __global__ void reduce_kernel(const TilePlan P, int nrhs, const float* __restric
 }
 
 // ---------------------------------------------------------------- workspace
-
-// Buffers of one product: RHS block in sorted order (FP16 hi/lo or FP32), the
-// column scales and the partial rows of the waves.
-struct ProdBufs {
-  unsigned* colmax;
-  float* inv_scale;
-  _Float16 *Vh, *Vl;  // precision form
-  float* Vp;          // FP32 form
-  float* part;
-  int ldh, ncp;
-};
 
 template <class C>
 static void carve_prod(C& cv, int n, int nrhs, int prec, ProdBufs& b) {
@@ -461,16 +448,39 @@ static void launch_f32(const TilePlan& P, float s2, const float* Vp, int ldh, in
                      pcols, c0, gate);
 }
 
-int mfma_launch(const TilePlan& P, int prec, float s2, float amp2, int nrhs, const float* V, int ldv, float* Y,
-                int ldy, float beta, void* ws, size_t ws_bytes, CgGate gate, hipStream_t stream) {
-  const int n = P.n;
-  GPL_TRY(check_ws(ws, ws_bytes, mfma_workspace(n, nrhs, prec)));
+int mfma_carve(const TilePlan& P, int prec, int nrhs, void* ws, size_t ws_bytes, ProdBufs& b) {
+  GPL_TRY(check_ws(ws, ws_bytes, mfma_workspace(P.n, nrhs, prec)));
   Carver cv(ws, ws_bytes);
-  ProdBufs b;
-  carve_prod(cv, n, nrhs, prec, b);
+  carve_prod(cv, P.n, nrhs, prec, b);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
-  const bool f16 = prec == GPL_PREC_F16X3;
-  if (f16) {
+  return GPL_OK;
+}
+
+__global__ void zero_words_kernel(unsigned* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+static int zero_words(void* p, size_t words, hipStream_t stream) {
+  const int blocks = (int)std::min<size_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(zero_words_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, stream, static_cast<unsigned*>(p),
+                     words);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int mfma_zero_rhs(const ProdBufs& b, int prec, hipStream_t stream) {
+  const size_t elems = (size_t)b.ncp * b.ldh;  // ldh is a multiple of 64: whole words
+  if (prec == GPL_PREC_F16X3) {
+    GPL_TRY(zero_words(b.Vh, elems / 2, stream));
+    return zero_words(b.Vl, elems / 2, stream);
+  }
+  return zero_words(b.Vp, elems, stream);
+}
+
+int mfma_prep_rhs(const TilePlan& P, const ProdBufs& b, int prec, int nrhs, const float* V, int ldv, CgGate gate,
+                  hipStream_t stream) {
+  const int n = P.n;
+  if (prec == GPL_PREC_F16X3) {
     hipLaunchKernelGGL(colmax_kernel, dim3(kColmaxBlocks, nrhs), dim3(256), 0, stream, n, V, ldv, b.colmax, gate);
     GPL_LAUNCH_CHECK();
     hipLaunchKernelGGL(split_rhs_kernel, dim3(cdiv(b.ldh, 256), b.ncp), dim3(256), 0, stream, n, nrhs, V, ldv, P.perm,
@@ -480,6 +490,12 @@ int mfma_launch(const TilePlan& P, int prec, float s2, float amp2, int nrhs, con
                        b.Vp, b.ldh, gate);
   }
   GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float amp2, int nrhs, float* Y, int ldy,
+                 float beta, CgGate gate, hipStream_t stream) {
+  const bool f16 = prec == GPL_PREC_F16X3;
   // column blocks of up to 64 columns per pass; each pass writes its own columns
   for (int c0 = 0; c0 < b.ncp; c0 += kMaxCB * 16) {
     const int cb = std::min(kMaxCB, (b.ncp - c0) / 16);
@@ -506,7 +522,7 @@ int mfma_launch(const TilePlan& P, int prec, float s2, float amp2, int nrhs, con
     GPL_LAUNCH_CHECK();
     timing_end(t0, stream);
   }
-  hipLaunchKernelGGL(reduce_kernel, dim3(cdiv(n, 256), nrhs), dim3(256), 0, stream, P, nrhs, b.part, nrhs,
+  hipLaunchKernelGGL(reduce_kernel, dim3(cdiv(P.n, 256), nrhs), dim3(256), 0, stream, P, nrhs, b.part, nrhs,
                      f16 ? b.inv_scale : nullptr, amp2, Y, ldy, beta, gate);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
@@ -515,28 +531,8 @@ int mfma_launch(const TilePlan& P, int prec, float s2, float amp2, int nrhs, con
 // ---------------------------------------------------------------- grouped launches (serving)
 // One launch per stage over all slots of a batch; each slot uses up to 2 column
 // blocks (32 right-hand sides), its own tile plan and its own buffers, so its
-// result does not depend on the other slots.
-
-__global__ __launch_bounds__(256) void colmax_grouped_kernel(SlotBatch B, int p) {
-  const int s = B.find(blockIdx.x);
-  const ServeSlotDev& S = *B.slot[s];
-  if (S.n_active[p] == 0 || S.prec != GPL_PREC_F16X3) return;
-  const int local = blockIdx.x - B.off[s];
-  colmax_body(local % kColmaxBlocks, local / kColmaxBlocks, S.N, S.T1, S.ldf, S.colmax);
-}
-
-__global__ void prep_grouped_kernel(SlotBatch B, int p) {
-  const int s = B.find(blockIdx.x);
-  const ServeSlotDev& S = *B.slot[s];
-  if (S.n_active[p] == 0) return;
-  const int local = blockIdx.x - B.off[s];
-  const int per = cdiv(S.ldh, 256);
-  if (S.prec == GPL_PREC_F16X3)
-    split_rhs_body(local % per, local / per, S.N, S.nrhs, S.T1, S.ldf, S.plan.perm, S.colmax, S.Vh, S.Vl, S.ldh,
-                   S.inv_scale);
-  else
-    pack_rhs_body(local % per, local / per, S.N, S.nrhs, S.T1, S.ldf, S.plan.perm, S.Vp, S.ldh);
-}
+// result does not depend on the other slots. The slot's RHS block is written by
+// the grouped PSF adjoint.
 
 __global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
   const int s = B.find(blockIdx.x);
@@ -584,11 +580,6 @@ static int launch_grouped(void (*kern)(SlotBatch, int), const ServeSlotDev* cons
 
 int mvm_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
                 hipStream_t stream) {
-  GPL_TRY(launch_grouped(colmax_grouped_kernel, hslots, dslots, nslots, p,
-                         [](const ServeSlotDev& S) { return S.prec == GPL_PREC_F16X3 ? kColmaxBlocks * S.nrhs : 0; },
-                         stream));
-  GPL_TRY(launch_grouped(prep_grouped_kernel, hslots, dslots, nslots, p,
-                         [](const ServeSlotDev& S) { return cdiv(S.ldh, 256) * S.ncp; }, stream));
   hipEvent_t t0 = timing_begin(stream);
   GPL_TRY(launch_grouped(mvm_grouped_kernel, hslots, dslots, nslots, p,
                          [](const ServeSlotDev& S) { return S.plan.nw / kWaves; }, stream));

@@ -12,8 +12,15 @@ namespace gpl {
 size_t mfma_workspace(int n, int nrhs, int prec);
 // Skip threshold of the plan for a precision form.
 float plan_threshold(int prec);
-// Y = amp2 K V + beta Y over the plan P (points P.n, caller order of V and Y).
-int mfma_launch(const TilePlan& P, int prec, float s2, float amp2, int nrhs, const float* V, int ldv, float* Y,
-                int ldy, float beta, void* ws, size_t ws_bytes, CgGate gate, hipStream_t stream);
+// Carve the product buffers from a workspace of mfma_workspace bytes.
+int mfma_carve(const TilePlan& P, int prec, int nrhs, void* ws, size_t ws_bytes, ProdBufs& b);
+// Zero the RHS buffers (padding rows and columns must stay zero).
+int mfma_zero_rhs(const ProdBufs& b, int prec, hipStream_t stream);
+// RHS block V (caller order) into the product buffers (sorted order, split or packed).
+int mfma_prep_rhs(const TilePlan& P, const ProdBufs& b, int prec, int nrhs, const float* V, int ldv, CgGate gate,
+                  hipStream_t stream);
+// Y = amp2 K V + beta Y (caller order) from the prepared RHS buffers.
+int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float amp2, int nrhs, float* Y, int ldy,
+                 float beta, CgGate gate, hipStream_t stream);
 
 }  // namespace gpl

@@ -113,16 +113,18 @@ __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps ta
                    dotv, ld_dotv, partial, ntiles);
 }
 
-// Adjoint: out (fine) = alpha * P^T D^T in + beta * out; P^T is the correlation
-// with the taps: (P^T g)(y, x) = sum_{a,b} w_a w_b g(y + a, x + b).
-__device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss, const Taps& taps,
-                                                 const float* __restrict__ in, int ld_in, float* __restrict__ out,
-                                                 int ld_out, float alpha, float beta) {
+// Adjoint on one fine tile: v = (P^T D^T in)(fy, fx) for every fine point of the
+// tile, handed to store(fy, fx, v, z) with z the point's Z-order index within
+// the tile when ZWALK and the tile lies inside the grid (else -1). P^T is the correlation with the taps:
+// (P^T g)(y, x) = sum_{a,b} w_a w_b g(y + a, x + b).
+template <bool ZWALK, class Store>
+__device__ __forceinline__ void psf_adjoint_tile(int tile, int c, int n, int ss, const Taps& taps,
+                                                 const float* __restrict__ in, int ld_in, Store&& store) {
   __shared__ float S1[kMaxWin * kMaxWin];
-  __shared__ float S2[kMaxWin * kFineTile];
+  __shared__ float S2[kMaxWin * (kFineTile + 1)];  // padded rows: no bank conflicts in the Z-order walk
   __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
   const int M = n * ss, r = taps.r;
-  const int F = kFineTile, W = F + 2 * r;
+  const int F = kFineTile, W = F + 2 * r, LS = F + 1;
   if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
   const int tiles_x = (M + F - 1) / F;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
@@ -139,20 +141,93 @@ __device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss,
     const int wy = idx / F, x = idx - wy * F;
     float s = 0.f;
     for (int b = -r; b <= r; ++b) s += tw[b + r] * S1[wy * W + x + r + b];
-    S2[idx] = s;
+    S2[wy * LS + x] = s;
   }
   __syncthreads();
+  // A tile fully inside the grid can be walked in Z-order (its fine points hold
+  // consecutive Z-order ranks: the tile is an aligned power-of-two square).
+  const bool zwalk = ZWALK && fy0 + F <= M && fx0 + F <= M;
   for (int o = threadIdx.x; o < F * F; o += blockDim.x) {
-    const int y = o / F, x = o - y * F;
+    int y, x;
+    if (zwalk) {
+      x = y = 0;
+      for (int b = 0; (1 << b) < F; ++b) {
+        x |= ((o >> (2 * b)) & 1) << b;
+        y |= ((o >> (2 * b + 1)) & 1) << b;
+      }
+    } else {
+      y = o / F;
+      x = o - y * F;
+    }
     const int fy = fy0 + y, fx = fx0 + x;
     if (fy >= M || fx >= M) continue;
     float v = 0.f;
-    for (int a = -r; a <= r; ++a) v += tw[a + r] * S2[(y + r + a) * F + x];
+    for (int a = -r; a <= r; ++a) v += tw[a + r] * S2[(y + r + a) * LS + x];
+    store(fy, fx, v, zwalk ? o : -1);
+  }
+}
+
+// out (fine, row-major) = alpha * B^T in + beta * out.
+__device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss, const Taps& taps,
+                                                 const float* __restrict__ in, int ld_in, float* __restrict__ out,
+                                                 int ld_out, float alpha, float beta) {
+  const int M = n * ss;
+  psf_adjoint_tile<false>(tile, c, n, ss, taps, in, ld_in, [&](int fy, int fx, float v, int) {
     const size_t o_idx = (size_t)c * ld_out + (size_t)fy * M + fx;
     float res = alpha * v;
     if (beta != 0.f) res += beta * out[o_idx];
     out[o_idx] = res;
+  });
+}
+
+// B^T P written straight into the RHS buffers of a grid-ordered product: fine
+// point (fx, fy) goes to its Z-order rank; the precision form scales column c by
+// 2^e_c, chosen from the bound max |B^T P| <= max |P| / ss^2 (nonnegative taps
+// summing to one) so that the largest entry stays below 2^14, and splits it
+// into FP16 hi (nearest) and lo.
+__device__ __forceinline__ void psf_adjoint_rhs_body(int tile, int c, int n, int ss, const Taps& taps,
+                                                     const float* __restrict__ in, int ld_in, const RhsOut& o) {
+  __shared__ float red[4];
+  __shared__ float s_scale;
+  const int M = n * ss;
+  const int tiles_x = (M + kFineTile - 1) / kFineTile;
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int base = zorder_rank(tx * kFineTile, ty * kFineTile, M);  // first rank of an interior tile
+  const bool f16 = o.prec == GPL_PREC_F16X3;
+  if (f16) {
+    float m = 0.f;
+    for (int k = threadIdx.x; k < o.npart; k += blockDim.x) m = fmaxf(m, __uint_as_float(o.pmax[c * o.npart + k]));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])) / (float)(ss * ss);
+      int e = 0;
+      if (mx > 0.f && isfinite(mx)) e = 14 - ilogbf(mx) - 1;  // bound * 2^e in [2^13, 2^14)
+      s_scale = ldexpf(1.f, e);
+      if (tile == 0) o.inv_scale[c] = ldexpf(1.f, -e) / 2048.f;  // with the 2^11 of the exp tile
+    }
+    __syncthreads();
   }
+  const float scale = f16 ? s_scale : 1.f;
+  // one instantiation of the tile (its LDS buffers) for both forms
+  psf_adjoint_tile<true>(tile, c, n, ss, taps, in, ld_in, [&](int fy, int fx, float v, int z) {
+    const size_t j = (size_t)c * o.ldh + (z >= 0 ? base + z : zorder_rank(fx, fy, M));
+    if (f16) {
+      const float sv = v * scale;
+      const _Float16 h = (_Float16)sv;
+      o.Vh[j] = h;
+      o.Vl[j] = (_Float16)(sv - (float)h);
+    } else {
+      o.Vp[j] = v;
+    }
+  });
+}
+
+__global__ __launch_bounds__(256) void psf_adjoint_rhs_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
+                                                              int ld_in, RhsOut o, CgGate gate) {
+  if (gate.skip(blockIdx.y)) return;
+  psf_adjoint_rhs_body(blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, o);
 }
 
 __global__ __launch_bounds__(256) void psf_adjoint_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
@@ -172,7 +247,8 @@ __global__ __launch_bounds__(256) void psf_adjoint_grouped_kernel(SlotBatch B, i
   const int local = blockIdx.x - B.off[s];
   const int tile = local % S.ntiles_adj, c = local / S.ntiles_adj;
   if (S.st[p][c].active == 0) return;
-  psf_adjoint_body(tile, c, S.n, S.ss, S.taps, S.P, S.ldv, S.T1, S.ldf, 1.f, 0.f);
+  const RhsOut o{S.prec, S.ldh, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd};
+  psf_adjoint_rhs_body(tile, c, S.n, S.ss, S.taps, S.P, S.ldv, o);
 }
 
 __global__ __launch_bounds__(256) void psf_forward_grouped_kernel(SlotBatch B, int p) {
@@ -232,6 +308,14 @@ int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* i
   const int ntiles = psf_forward_tiles(n, ss);
   hipLaunchKernelGGL(psf_forward_kernel, dim3(ntiles, nrhs), dim3(256), 0, stream, n, ss, taps, in, ld_in, out,
                      ld_out, alpha, beta, extra, ld_extra, gamma, dotv, ld_dotv, partial, ntiles, gate);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int psf_adjoint_rhs_launch(int n, int ss, const Taps& taps, int nrhs, const float* P, int ldp, const RhsOut& out,
+                           CgGate gate, hipStream_t stream) {
+  const int M = n * ss, t = (M + kFineTile - 1) / kFineTile;
+  hipLaunchKernelGGL(psf_adjoint_rhs_kernel, dim3(t * t, nrhs), dim3(256), 0, stream, n, ss, taps, P, ldp, out, gate);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

@@ -25,9 +25,9 @@ static const ServeSlotDev& host_desc(const gpl_serve_slot* s) {
 // Buffers of one slot, in carving order. The descriptor sits first.
 struct SlotBufs {
   ServeSlotDev* desc;
-  float *px, *py, *mu, *rhs, *X, *R, *P, *AP, *T1, *T2, *w, *fhat_tmp;
+  float *px, *py, *mu, *rhs, *X, *R, *P, *AP, *T2, *w;
   TilePlan plan;
-  unsigned* colmax;
+  unsigned* pmax;
   float* inv_scale;
   _Float16 *Vh, *Vl;
   float *Vp, *part;
@@ -55,12 +55,10 @@ static void carve_slot(Cv& cv, int n, int ss, int nrhs, int n_lanczos, int prec,
   x.R = cv.template take<float>((size_t)ldv * nrhs);
   x.P = cv.template take<float>((size_t)ldv * nrhs);
   x.AP = cv.template take<float>((size_t)ldv * nrhs);
-  x.T1 = cv.template take<float>((size_t)ldf * nrhs);
   x.T2 = cv.template take<float>((size_t)ldf * nrhs);
   x.w = cv.template take<float>(N);
-  x.fhat_tmp = nullptr;
   plan_carve(cv, N, x.plan);
-  x.colmax = cv.template take<unsigned>(f16 ? (size_t)ncp * kColmaxBlocks : 1);
+  x.pmax = cv.template take<unsigned>((size_t)nrhs * nb);
   x.inv_scale = cv.template take<float>(ncp);
   x.Vh = cv.template take<_Float16>(f16 ? (size_t)ncp * ldh : 1);
   x.Vl = cv.template take<_Float16>(f16 ? (size_t)ncp * ldh : 1);
@@ -156,12 +154,11 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
   D.R = b.R;
   D.P = b.P;
   D.AP = b.AP;
-  D.T1 = b.T1;
   D.T2 = b.T2;
   D.ldv = round_up(npix, 64);
   D.ldf = round_up(N, 64);
   D.plan = b.plan;
-  D.colmax = b.colmax;
+  D.pmax = b.pmax;
   D.inv_scale = b.inv_scale;
   D.Vh = b.Vh;
   D.Vl = b.Vl;
@@ -188,6 +185,10 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
 
   hipLaunchKernelGGL(write_desc_kernel, dim3(1), dim3(64), 0, stream, D, b.desc);
   GPL_LAUNCH_CHECK();
+  // the grouped PSF adjoint writes only the slot's fine points and columns:
+  // the padding of the RHS buffers stays zero
+  const ProdBufs pb{nullptr, b.inv_scale, b.Vh, b.Vl, b.Vp, b.part, D.ldh, D.ncp};
+  GPL_TRY(mfma_zero_rhs(pb, prec, stream));
   GPL_TRY(gpl_lens_raytrace(g, lens, b.px, b.py, stream));
   TilePlan plan = b.plan;  // same buffers as the descriptor's copy
   GPL_TRY(plan_build(plan, N, b.px, b.py, g, D.s2, plan_threshold(prec), stream));
@@ -200,7 +201,7 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
   GPL_TRY(psf_forward_launch(n, ss, taps, 1, b.mu, N, b.rhs, D.ldv, -1.f, 1.f, nullptr, 0, 0.f, nullptr, 0, nullptr,
                              CgGate{}, stream));
   GPL_TRY(cg_init_launch(npix, nrhs, b.rhs, D.ldv, b.X, D.ldv, b.R, b.P, D.ldv, b.rr, b.st0, b.st1, b.bb, b.n_active,
-                         max_iter, stream));
+                         max_iter, b.pmax, stream));
   std::memcpy(slot->opaque, &D, sizeof(D));
   slot->dev = b.desc;
   slot->ws = ws;

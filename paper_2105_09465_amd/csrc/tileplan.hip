@@ -148,14 +148,23 @@ __global__ void plan_waves_kernel(int nrt, int nw, const int* unit_off, const in
   nrows[w] = r1 - r0 + 1;
 }
 
-// Per row tile: first and last wave holding its units.
-__global__ void plan_rowwaves_kernel(int nrt, int nw, const int* unit_off, const int* count, const int* total,
-                                     int2* rwave) {
+// Per row tile: its partial slots [s0, s0 + cnt), from the first and last wave
+// holding its units (waves in between start in this row tile, so their slots
+// for it are their first ones, and empty waves own no slot).
+__global__ void plan_rowslots_kernel(int nrt, int nw, const int* unit_off, const int* count, const int* total,
+                                     const int* wrow, const int* wslot, int2* rslot) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrt) return;
   const int T = *total;
   const int a = unit_off[r], c = count[r];
-  rwave[r] = c > 0 ? make_int2(wave_of_unit(a, T, nw), wave_of_unit(a + c - 1, T, nw)) : make_int2(0, -1);
+  if (c <= 0) {
+    rslot[r] = make_int2(0, 0);
+    return;
+  }
+  const int wf = wave_of_unit(a, T, nw), wl = wave_of_unit(a + c - 1, T, nw);
+  const int s0 = wslot[wf] + (r - wrow[wf]);
+  const int s1 = wslot[wl] + (r - wrow[wl]);
+  rslot[r] = make_int2(s0, s1 - s0 + 1);
 }
 
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
@@ -184,8 +193,8 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, p.nw, p.wslot, p.wslot, p.wslot + p.nw);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_rowwaves_kernel, dim3(cdiv(p.nrt, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.unit_off,
-                     p.count, p.total, p.rwave);
+  hipLaunchKernelGGL(plan_rowslots_kernel, dim3(cdiv(p.nrt, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.unit_off,
+                     p.count, p.total, p.wrow, p.wslot, p.rslot);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

@@ -33,8 +33,8 @@ constexpr float kSkipFp32 = 152.f;
 // row-tile order. A product launch of nw waves gives wave w the contiguous
 // units [w T / nw, (w + 1) T / nw) (T units in all), so every wave gets the same
 // work; a wave writes one partial row block per row tile it touches, into
-// consecutive slots starting at wslot[w], and the partials of a row tile are
-// summed in wave order.
+// consecutive slots starting at wslot[w]. The slots of one row tile are then
+// consecutive too, in wave order, and are summed in that order.
 struct TilePlan {
   int n;     // points
   int nrt;   // row tiles = ceil(n / 64)
@@ -50,7 +50,7 @@ struct TilePlan {
   int* total;       // [1] T
   int* wrow;        // [nw] row tile of each wave's first unit (-1: no units)
   int* wslot;       // [nw + 1] first partial slot of each wave
-  int2* rwave;      // [nrt] first and last wave holding units of each row tile
+  int2* rslot;      // [nrt] first partial slot of each row tile and their number
 };
 
 // Waves of a product launch for n points, and partial slots it may write.
@@ -81,7 +81,7 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.total = cv.template take<int>(1);
   p.wrow = cv.template take<int>((size_t)p.nw);
   p.wslot = cv.template take<int>((size_t)p.nw + 1);
-  p.rwave = cv.template take<int2>((size_t)p.nrt);
+  p.rslot = cv.template take<int2>((size_t)p.nrt);
 }
 
 // Build the plan on `stream`. With `grid` the points are the fine grid of that
