@@ -20,7 +20,7 @@ namespace gpl {
 
 constexpr int kRowTile = 64;     // rows per wave (four 16-row MFMA tiles)
 constexpr int kChunk = 32;       // source points per chunk
-constexpr int kMaxPlanWaves = 4096;    // waves of one product launch (4 per SIMD)
+constexpr int kMaxPlanWaves = 3072;    // waves of one product launch (3 per SIMD)
 constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
 
 // Skip thresholds on s2 g^2 (exp2 arguments: 11 - s2 d^2 <= -25 leaves the FP16
