@@ -147,9 +147,8 @@ __device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* 
   if (*n_active_in == 0) return;
   const ColState st = sin[c];
   if (!st.active) return;
+  const double pap = threadIdx.x < 64 ? wave_fold_sum(pap_part + (size_t)c * ntiles, ntiles) : 0.0;
   if (threadIdx.x == 0) {
-    double pap = 0.0;
-    for (int t = 0; t < ntiles; ++t) pap += pap_part[(size_t)c * ntiles + t];
     const double a = st.rr / pap;
     const int ok = (pap > 0.0) && isfinite(a);
     s_alpha = ok ? a : 0.0;
@@ -199,10 +198,9 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
     if (bx == 0 && threadIdx.x == 0) sout[c] = st;
     return;
   }
+  const double rr_new = threadIdx.x < 64 ? wave_fold_sum(rr_part + (size_t)c * nb, nb) : 0.0;
   if (threadIdx.x == 0) {
     const ColState half = sout[c];  // alpha and bad written by update1
-    double rr_new = 0.0;
-    for (int b = 0; b < nb; ++b) rr_new += rr_part[(size_t)c * nb + b];
     const double beta = rr_new / st.rr;
     ColState nx;
     nx.alpha = half.alpha;

@@ -103,6 +103,14 @@ __device__ inline T warp_sum(T v) {
   return v;
 }
 
+// Sum of p[0, cnt) over the 64 lanes of one wave in a fixed order (lane-strided
+// partial sums, then a butterfly); the result is the same in every lane.
+__device__ inline double wave_fold_sum(const double* __restrict__ p, int cnt) {
+  double s = 0.0;
+  for (int k = (int)(threadIdx.x & 63); k < cnt; k += 64) s += p[k];
+  return warp_sum(s);
+}
+
 // Deterministic block reduction of one double per thread (blockDim.x <= 1024,
 // multiple of 64). Result valid in thread 0.
 __device__ inline double block_sum_double(double v, double* smem) {

@@ -45,35 +45,44 @@ int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
 
 // Forward: out[I] = alpha * (B in)[I] + beta * out[I] + gamma * extra[I];
 // optional FP64 partial sums of dotv[I] * out[I] per (column, tile).
+// Integer division by the supersampling factor (1 and 2 without a divide).
+__device__ __forceinline__ int div_ss(int v, int ss) { return ss == 1 ? v : ss == 2 ? (v >> 1) : v / ss; }
+
 __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss, const Taps& taps,
                                                  const float* __restrict__ in, int ld_in, float* __restrict__ out,
                                                  int ld_out, float alpha, float beta, const float* __restrict__ extra,
                                                  int ld_extra, float gamma, const float* __restrict__ dotv,
                                                  int ld_dotv, double* __restrict__ partial, int ntiles) {
   __shared__ float S1[kMaxWin * kMaxWin];
-  __shared__ float S2[kMaxWin * kFineTile];
+  __shared__ float S2[kMaxWin * (kFineTile + 1)];
   __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
   __shared__ double red[4];
   const int M = n * ss, r = taps.r;
   if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
   const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;  // output pixels per tile side
-  const int F = TP * ss, W = F + 2 * r;
+  const int F = TP * ss, W = F + 2 * r, LS = F + 1;
   const int tiles_x = (n + TP - 1) / TP;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
-  for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-    const int wy = idx / W, wx = idx - wy * W;
-    const int fy = fy0 - r + wy, fx = fx0 - r + wx;
-    S1[idx] = (fy >= 0 && fy < M && fx >= 0 && fx < M) ? src[(size_t)fy * M + fx] : 0.f;
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int wy = ly; wy < W; wy += 8) {
+    const int fy = fy0 - r + wy;
+    const bool rowok = fy >= 0 && fy < M;
+    for (int wx = lx; wx < W; wx += 32) {
+      const int fx = fx0 - r + wx;
+      S1[wy * W + wx] = (rowok && fx >= 0 && fx < M) ? src[(size_t)fy * M + fx] : 0.f;
+    }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < W * F; idx += blockDim.x) {
-    const int wy = idx / F, x = idx - wy * F;
-    float s = 0.f;
-    for (int b = -r; b <= r; ++b) s += tw[b + r] * S1[wy * W + x + r - b];
-    S2[idx] = s;
-  }
+  for (int wy = ly; wy < W; wy += 8)
+    for (int x = lx; x < F; x += 32) {
+      const float* row = S1 + wy * W + x + r;
+      float s = 0.f;
+#pragma unroll 4
+      for (int b = -r; b <= r; ++b) s += tw[b + r] * row[-b];
+      S2[wy * LS + x] = s;
+    }
   __syncthreads();
   const float inv_ss2 = 1.f / (float)(ss * ss);
   double dot = 0.0;
@@ -85,8 +94,10 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
     for (int sy = 0; sy < ss; ++sy)
       for (int sx = 0; sx < ss; ++sx) {
         const int y = oy * ss + sy, x = ox * ss + sx;
+        const float* col = S2 + (y + r) * LS + x;
         float v = 0.f;
-        for (int a = -r; a <= r; ++a) v += tw[a + r] * S2[(y + r - a) * F + x];
+#pragma unroll 4
+        for (int a = -r; a <= r; ++a) v += tw[a + r] * col[-a * LS];
         acc += v;
       }
     const int I = Iy * n + Ix;
@@ -121,9 +132,10 @@ template <bool ZWALK, class Store>
 __device__ __forceinline__ void psf_adjoint_tile(int tile, int c, int n, int ss, const Taps& taps,
                                                  const float* __restrict__ in, int ld_in, Store&& store) {
   __shared__ float S1[kMaxWin * kMaxWin];
-  __shared__ float S2[kMaxWin * (kFineTile + 1)];  // padded rows: no bank conflicts in the Z-order walk
+  __shared__ float S2[kMaxWin * (kFineTile + 1)];
   __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
   const int M = n * ss, r = taps.r;
+  static_assert(kFineTile == 32, "the Z-order decode below takes 5 bits per axis");
   const int F = kFineTile, W = F + 2 * r, LS = F + 1;
   if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
   const int tiles_x = (M + F - 1) / F;
@@ -131,39 +143,48 @@ __device__ __forceinline__ void psf_adjoint_tile(int tile, int c, int n, int ss,
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
   const float inv_ss2 = 1.f / (float)(ss * ss);
-  for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
-    const int wy = idx / W, wx = idx - wy * W;
-    const int fy = fy0 - r + wy, fx = fx0 - r + wx;
-    S1[idx] = (fy >= 0 && fy < M && fx >= 0 && fx < M) ? src[(fy / ss) * n + fx / ss] * inv_ss2 : 0.f;
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int wy = ly; wy < W; wy += 8) {
+    const int fy = fy0 - r + wy;
+    const bool rowok = fy >= 0 && fy < M;
+    const float* srow = src + (size_t)div_ss(rowok ? fy : 0, ss) * n;
+    for (int wx = lx; wx < W; wx += 32) {
+      const int fx = fx0 - r + wx;
+      S1[wy * W + wx] = (rowok && fx >= 0 && fx < M) ? srow[div_ss(fx, ss)] * inv_ss2 : 0.f;
+    }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < W * F; idx += blockDim.x) {
-    const int wy = idx / F, x = idx - wy * F;
+  for (int wy = ly; wy < W; wy += 8) {
+    const float* row = S1 + wy * W + lx + r;
     float s = 0.f;
-    for (int b = -r; b <= r; ++b) s += tw[b + r] * S1[wy * W + x + r + b];
-    S2[wy * LS + x] = s;
+#pragma unroll 4
+    for (int b = -r; b <= r; ++b) s += tw[b + r] * row[b];
+    S2[wy * LS + lx] = s;
   }
   __syncthreads();
-  // A tile fully inside the grid can be walked in Z-order (its fine points hold
-  // consecutive Z-order ranks: the tile is an aligned power-of-two square).
+  // A tile fully inside the grid holds consecutive Z-order ranks (it is an
+  // aligned power-of-two square): z is the point's Z-order index in the tile.
   const bool zwalk = ZWALK && fy0 + F <= M && fx0 + F <= M;
   for (int o = threadIdx.x; o < F * F; o += blockDim.x) {
-    int y, x;
+    int x = 0, y = 0;
     if (zwalk) {
-      x = y = 0;
-      for (int b = 0; (1 << b) < F; ++b) {
-        x |= ((o >> (2 * b)) & 1) << b;
-        y |= ((o >> (2 * b + 1)) & 1) << b;
+#pragma unroll
+      for (int bit = 0; bit < 5; ++bit) {
+        x |= ((o >> (2 * bit)) & 1) << bit;
+        y |= ((o >> (2 * bit + 1)) & 1) << bit;
       }
     } else {
-      y = o / F;
-      x = o - y * F;
+      y = o >> 5;
+      x = o & 31;
     }
     const int fy = fy0 + y, fx = fx0 + x;
     if (fy >= M || fx >= M) continue;
+    const float* col = S2 + (y + r) * LS + x;
     float v = 0.f;
-    for (int a = -r; a <= r; ++a) v += tw[a + r] * S2[(y + r + a) * LS + x];
-    store(fy, fx, v, zwalk ? o : -1);
+#pragma unroll 4
+    for (int a = -r; a <= r; ++a) v += tw[a + r] * col[a * LS];
+    const int z = zwalk ? o : -1;
+    store(fy, fx, v, z);
   }
 }
 
