@@ -147,6 +147,16 @@ __device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* 
   if (*n_active_in == 0) return;
   const ColState st = sin[c];
   if (!st.active) return;
+  // this thread's vector entries, loaded while alpha is being formed
+  const int i = bx * blockDim.x + threadIdx.x;
+  const size_t iv = (size_t)c * ldv + i;
+  float xv = 0.f, pv = 0.f, apv = 0.f, rv = 0.f;
+  if (i < npix) {
+    xv = X[(size_t)c * ldx + i];
+    pv = P[iv];
+    apv = AP[iv];
+    rv = R[iv];
+  }
   const double pap = threadIdx.x < 64 ? wave_fold_sum(pap_part + (size_t)c * ntiles, ntiles) : 0.0;
   if (threadIdx.x == 0) {
     const double a = st.rr / pap;
@@ -160,13 +170,11 @@ __device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* 
   }
   __syncthreads();
   const double alpha = s_alpha;
-  const int i = bx * blockDim.x + threadIdx.x;
   double s = 0.0;
   if (s_ok && i < npix) {
     const float af = (float)alpha;
-    const size_t iv = (size_t)c * ldv + i;
-    X[(size_t)c * ldx + i] = fmaf(af, P[iv], X[(size_t)c * ldx + i]);
-    const float r = fmaf(-af, AP[iv], R[iv]);
+    X[(size_t)c * ldx + i] = fmaf(af, pv, xv);
+    const float r = fmaf(-af, apv, rv);
     R[iv] = r;
     s = (double)r * r;
   }
@@ -197,6 +205,13 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
   if (*n_active_in == 0 || !st.active) {  // carry the state into the other parity
     if (bx == 0 && threadIdx.x == 0) sout[c] = st;
     return;
+  }
+  const int i = bx * blockDim.x + threadIdx.x;
+  const size_t iv = (size_t)c * ldv + i;
+  float rv = 0.f, pv = 0.f;
+  if (i < npix) {  // loaded while beta is being formed
+    rv = R[iv];
+    pv = P[iv];
   }
   const double rr_new = threadIdx.x < 64 ? wave_fold_sum(rr_part + (size_t)c * nb, nb) : 0.0;
   if (threadIdx.x == 0) {
@@ -243,11 +258,9 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
   }
   __syncthreads();
   if (!s_go) return;
-  const int i = bx * blockDim.x + threadIdx.x;
   float m = 0.f;
   if (i < npix) {
-    const size_t iv = (size_t)c * ldv + i;
-    const float pn = fmaf((float)s_beta, P[iv], R[iv]);
+    const float pn = fmaf((float)s_beta, pv, rv);
     P[iv] = pn;
     m = fabsf(pn);
   }

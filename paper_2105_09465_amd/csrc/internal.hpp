@@ -18,10 +18,11 @@ struct CgGate {
   const int* n_active = nullptr;   // device scalar
   const int* col_active = nullptr; // device [nrhs], stride `stride` ints
   int stride = 1;
+  // both flags are loaded together (one memory round trip, not two)
   __device__ bool skip(int c) const {
-    if (n_active && *n_active == 0) return true;
-    if (col_active && col_active[c * stride] == 0) return true;
-    return false;
+    const int na = n_active ? *n_active : 1;
+    const int ca = col_active ? col_active[c * stride] : 1;
+    return na == 0 || ca == 0;
   }
   __device__ bool skip_all() const { return n_active && *n_active == 0; }
 };

@@ -391,8 +391,24 @@ __device__ __forceinline__ void reduce_body(int bx, int c, const TilePlan& P, in
   const int2 sl = P.rslot[r];
   const float* p0 = part + ((size_t)sl.x * pcols + c) * kRowTile + row;
   const size_t stride = (size_t)pcols * kRowTile;
+  // in slot order; the loads of each group of 8 are issued together
   float s = 0.f;
-  for (int q = 0; q < sl.y; ++q) s += p0[q * stride];
+  int q = 0;
+  for (; q + 8 <= sl.y; q += 8) {
+    float t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p0[(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += t[u];
+  }
+  {
+    float t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = q + u < sl.y ? p0[(q + u) * stride] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q + u < sl.y) s += t[u];
+  }
   const float f = colscale ? amp2 * colscale[c] : amp2;
   float* y = Y + (size_t)c * ldy + (P.perm ? P.perm[j] : j);
   const float res = f * s;

@@ -17,6 +17,56 @@ namespace gpl {
 constexpr int kFineTile = 32;  // fine-grid tile side
 constexpr int kMaxWin = kFineTile + 2 * GPL_PSF_MAX_RADIUS;
 
+// Row stride of the adjoint's x-convolved buffer: 40 = 8 (mod 32), so the 8 x 8
+// pixel block a wave reads in the Z-order walk falls on distinct LDS banks.
+constexpr int kAdjStride = 40;
+constexpr int kOutPer = kFineTile * kFineTile / 256;  // output pixels per thread of a forward tile
+
+// A W x W window (W <= kMaxWin) staged into LDS through registers: thread
+// (lx, ly) of the 32 x 8 workgroup holds rows ly + 8k and columns lx + 32m, and
+// every global load of the window is issued before the first LDS store, so the
+// loads overlap instead of each waiting for the previous one.
+constexpr int kWinRows = (kMaxWin + 7) / 8, kWinCols = (kMaxWin + 31) / 32;
+static_assert(kWinRows * kWinCols <= 32, "one mask bit per window slot");
+struct WinRegs {
+  float v[kWinRows][kWinCols];
+  unsigned ok;  // bit k * kWinCols + m: slot inside the window and the grid
+};
+
+__device__ __forceinline__ int clamp_idx(int v, int m) { return min(max(v, 0), m - 1); }
+
+// at(wy, wx, ok) returns the value at window position (wy, wx) read from the
+// nearest grid pixel, always at a valid address, and sets ok when the position
+// lies inside the window and the grid. Slots that are not ok are stored as 0 in
+// win_store: keeping the selection out of the load blocks lets all loads be in
+// flight together.
+template <class At>
+__device__ __forceinline__ void win_load(WinRegs& R, int W, At&& at) {
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  R.ok = 0u;
+#pragma unroll
+  for (int k = 0; k < kWinRows; ++k)
+#pragma unroll
+    for (int m = 0; m < kWinCols; ++m)
+      if (8 * k < W && 32 * m < W) {
+        bool ok;
+        R.v[k][m] = at(ly + 8 * k, lx + 32 * m, ok);
+        R.ok |= (ok ? 1u : 0u) << (k * kWinCols + m);
+      }
+}
+
+__device__ __forceinline__ void win_store(const WinRegs& R, int W, float* S) {
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+#pragma unroll
+  for (int k = 0; k < kWinRows; ++k)
+#pragma unroll
+    for (int m = 0; m < kWinCols; ++m)
+      if (8 * k < W && 32 * m < W) {
+        const int wy = ly + 8 * k, wx = lx + 32 * m;
+        if (wy < W && wx < W) S[wy * W + wx] = (R.ok >> (k * kWinCols + m)) & 1u ? R.v[k][m] : 0.f;
+      }
+}
+
 int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
   GPL_REQUIRE(psf != nullptr, "psf is NULL");
   GPL_REQUIRE(psf->fwhm >= 0 && std::isfinite(psf->fwhm), "psf fwhm must be >= 0");
@@ -45,10 +95,16 @@ int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
 
 // Forward: out[I] = alpha * (B in)[I] + beta * out[I] + gamma * extra[I];
 // optional FP64 partial sums of dotv[I] * out[I] per (column, tile).
-// Integer division by the supersampling factor (1 and 2 without a divide).
-__device__ __forceinline__ int div_ss(int v, int ss) { return ss == 1 ? v : ss == 2 ? (v >> 1) : v / ss; }
+// floor(v / ss) for 0 <= v < 2^15 and 1 <= ss <= 32, rss = 1 / ss in FP32:
+// (v + 1/2) / ss stays at least 1/64 away from an integer, far more than the
+// FP32 rounding of the product. Branch-free, so the loads it addresses are not
+// split into separately waited blocks.
+__device__ __forceinline__ int div_ss(int v, float rss) { return (int)(((float)v + 0.5f) * rss); }
 
-__device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss, const Taps& taps,
+// `skip()` (uniform over the workgroup) is evaluated once the window loads are in
+// flight; when it is true the workgroup leaves without writing anything.
+template <class Skip>
+__device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
                                                  const float* __restrict__ in, int ld_in, float* __restrict__ out,
                                                  int ld_out, float alpha, float beta, const float* __restrict__ extra,
                                                  int ld_extra, float gamma, const float* __restrict__ dotv,
@@ -58,7 +114,6 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
   __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
   __shared__ double red[4];
   const int M = n * ss, r = taps.r;
-  if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
   const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;  // output pixels per tile side
   const int F = TP * ss, W = F + 2 * r, LS = F + 1;
   const int tiles_x = (n + TP - 1) / TP;
@@ -66,13 +121,36 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
-  for (int wy = ly; wy < W; wy += 8) {
-    const int fy = fy0 - r + wy;
-    const bool rowok = fy >= 0 && fy < M;
-    for (int wx = lx; wx < W; wx += 32) {
-      const int fx = fx0 - r + wx;
-      S1[wy * W + wx] = (rowok && fx >= 0 && fx < M) ? src[(size_t)fy * M + fx] : 0.f;
-    }
+  // this thread's output pixels (at most kOutPer) and their operands, loaded
+  // together with the window
+  int I[kOutPer];
+  float o_old[kOutPer], o_ext[kOutPer], o_dot[kOutPer];
+#pragma unroll
+  for (int u = 0; u < kOutPer; ++u) {
+    const int o = threadIdx.x + u * 256;
+    const int oy = o / TP, ox = o - oy * TP;
+    const int Iy = ty * TP + oy, Ix = tx * TP + ox;
+    I[u] = (o < TP * TP && Iy < n && Ix < n) ? Iy * n + Ix : -1;
+    // unconditional loads at valid addresses (pixel 0, or this column of `in`
+    // for an absent operand), selected afterwards
+    const int Ic = I[u] >= 0 ? I[u] : 0;
+    const float a = out[(size_t)c * ld_out + Ic];
+    const float e = extra ? extra[(size_t)c * ld_extra + Ic] : src[Ic];
+    const float d = dotv ? dotv[(size_t)c * ld_dotv + Ic] : src[Ic];
+    o_old[u] = beta != 0.f ? a : 0.f;
+    o_ext[u] = extra ? e : 0.f;
+    o_dot[u] = dotv ? d : 0.f;
+  }
+  {
+    WinRegs R;
+    win_load(R, W, [&](int wy, int wx, bool& ok) {
+      const int fy = fy0 - r + wy, fx = fx0 - r + wx;
+      ok = wy < W && wx < W && fy >= 0 && fy < M && fx >= 0 && fx < M;
+      return src[(size_t)clamp_idx(fy, M) * M + clamp_idx(fx, M)];
+    });
+    if (skip()) return;
+    if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
+    win_store(R, W, S1);
   }
   __syncthreads();
   for (int wy = ly; wy < W; wy += 8)
@@ -86,10 +164,11 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
   __syncthreads();
   const float inv_ss2 = 1.f / (float)(ss * ss);
   double dot = 0.0;
-  for (int o = threadIdx.x; o < TP * TP; o += blockDim.x) {
+#pragma unroll
+  for (int u = 0; u < kOutPer; ++u) {
+    if (I[u] < 0) continue;
+    const int o = threadIdx.x + u * 256;
     const int oy = o / TP, ox = o - oy * TP;
-    const int Iy = ty * TP + oy, Ix = tx * TP + ox;
-    if (Iy >= n || Ix >= n) continue;
     float acc = 0.f;
     for (int sy = 0; sy < ss; ++sy)
       for (int sx = 0; sx < ss; ++sx) {
@@ -100,12 +179,11 @@ __device__ __forceinline__ void psf_forward_body(int tile, int c, int n, int ss,
         for (int a = -r; a <= r; ++a) v += tw[a + r] * col[-a * LS];
         acc += v;
       }
-    const int I = Iy * n + Ix;
     float res = alpha * (acc * inv_ss2);
-    if (beta != 0.f) res += beta * out[(size_t)c * ld_out + I];
-    if (extra) res += gamma * extra[(size_t)c * ld_extra + I];
-    out[(size_t)c * ld_out + I] = res;
-    if (dotv) dot += (double)dotv[(size_t)c * ld_dotv + I] * (double)res;
+    if (beta != 0.f) res += beta * o_old[u];
+    if (extra) res += gamma * o_ext[u];
+    out[(size_t)c * ld_out + I[u]] = res;
+    if (dotv) dot += (double)o_dot[u] * (double)res;
   }
   if (partial) {
     const double s = block_sum_double(dot, red);
@@ -119,8 +197,7 @@ __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps ta
                                                           int ld_extra, float gamma, const float* __restrict__ dotv,
                                                           int ld_dotv, double* __restrict__ partial, int ntiles,
                                                           CgGate gate) {
-  if (gate.skip(blockIdx.y)) return;
-  psf_forward_body(blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out, alpha, beta, extra, ld_extra, gamma,
+  psf_forward_body([&] { return gate.skip(blockIdx.y); }, blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out, alpha, beta, extra, ld_extra, gamma,
                    dotv, ld_dotv, partial, ntiles);
 }
 
@@ -128,30 +205,33 @@ __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps ta
 // tile, handed to store(fy, fx, v, z) with z the point's Z-order index within
 // the tile when ZWALK and the tile lies inside the grid (else -1). P^T is the correlation with the taps:
 // (P^T g)(y, x) = sum_{a,b} w_a w_b g(y + a, x + b).
-template <bool ZWALK, class Store>
-__device__ __forceinline__ void psf_adjoint_tile(int tile, int c, int n, int ss, const Taps& taps,
-                                                 const float* __restrict__ in, int ld_in, Store&& store) {
+template <bool ZWALK, class Skip, class Pre, class Store>
+__device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
+                                                 const float* __restrict__ in, int ld_in, Pre&& pre, Store&& store) {
   __shared__ float S1[kMaxWin * kMaxWin];
-  __shared__ float S2[kMaxWin * (kFineTile + 1)];
+  __shared__ float S2[kMaxWin * kAdjStride];
   __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
   const int M = n * ss, r = taps.r;
   static_assert(kFineTile == 32, "the Z-order decode below takes 5 bits per axis");
-  const int F = kFineTile, W = F + 2 * r, LS = F + 1;
-  if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
+  const int F = kFineTile, W = F + 2 * r, LS = kAdjStride;
   const int tiles_x = (M + F - 1) / F;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
-  const float inv_ss2 = 1.f / (float)(ss * ss);
+  const float inv_ss2 = 1.f / (float)(ss * ss), rss = 1.f / (float)ss;
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
-  for (int wy = ly; wy < W; wy += 8) {
-    const int fy = fy0 - r + wy;
-    const bool rowok = fy >= 0 && fy < M;
-    const float* srow = src + (size_t)div_ss(rowok ? fy : 0, ss) * n;
-    for (int wx = lx; wx < W; wx += 32) {
-      const int fx = fx0 - r + wx;
-      S1[wy * W + wx] = (rowok && fx >= 0 && fx < M) ? srow[div_ss(fx, ss)] * inv_ss2 : 0.f;
-    }
+  {
+    WinRegs R;
+    win_load(R, W, [&](int wy, int wx, bool& ok) {
+      const int fy = fy0 - r + wy, fx = fx0 - r + wx;
+      ok = wy < W && wx < W && fy >= 0 && fy < M && fx >= 0 && fx < M;
+      // the 1 / ss^2 of D^T is applied to the convolved value
+      return src[(size_t)div_ss(clamp_idx(fy, M), rss) * n + div_ss(clamp_idx(fx, M), rss)];
+    });
+    if (skip()) return;
+    if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
+    pre();  // runs while the window loads are in flight
+    win_store(R, W, S1);
   }
   __syncthreads();
   for (int wy = ly; wy < W; wy += 8) {
@@ -184,16 +264,17 @@ __device__ __forceinline__ void psf_adjoint_tile(int tile, int c, int n, int ss,
 #pragma unroll 4
     for (int a = -r; a <= r; ++a) v += tw[a + r] * col[a * LS];
     const int z = zwalk ? o : -1;
-    store(fy, fx, v, z);
+    store(fy, fx, v * inv_ss2, z);
   }
 }
 
 // out (fine, row-major) = alpha * B^T in + beta * out.
-__device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss, const Taps& taps,
+template <class Skip>
+__device__ __forceinline__ void psf_adjoint_body(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
                                                  const float* __restrict__ in, int ld_in, float* __restrict__ out,
                                                  int ld_out, float alpha, float beta) {
   const int M = n * ss;
-  psf_adjoint_tile<false>(tile, c, n, ss, taps, in, ld_in, [&](int fy, int fx, float v, int) {
+  psf_adjoint_tile<false>(skip, tile, c, n, ss, taps, in, ld_in, [] {}, [&](int fy, int fx, float v, int) {
     const size_t o_idx = (size_t)c * ld_out + (size_t)fy * M + fx;
     float res = alpha * v;
     if (beta != 0.f) res += beta * out[o_idx];
@@ -206,7 +287,8 @@ __device__ __forceinline__ void psf_adjoint_body(int tile, int c, int n, int ss,
 // 2^e_c, chosen from the bound max |B^T P| <= max |P| / ss^2 (nonnegative taps
 // summing to one) so that the largest entry stays below 2^14, and splits it
 // into FP16 hi (nearest) and lo.
-__device__ __forceinline__ void psf_adjoint_rhs_body(int tile, int c, int n, int ss, const Taps& taps,
+template <class Skip>
+__device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
                                                      const float* __restrict__ in, int ld_in, const RhsOut& o) {
   __shared__ float red[4];
   __shared__ float s_scale;
@@ -215,7 +297,10 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(int tile, int c, int n, int
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int base = zorder_rank(tx * kFineTile, ty * kFineTile, M);  // first rank of an interior tile
   const bool f16 = o.prec == GPL_PREC_F16X3;
-  if (f16) {
+  // column scale, folded while the tile's window loads are in flight (the tile
+  // synchronises the workgroup before its first use of s_scale)
+  auto fold_scale = [&] {
+    if (!f16) return;
     float m = 0.f;
     for (int k = threadIdx.x; k < o.npart; k += blockDim.x) m = fmaxf(m, __uint_as_float(o.pmax[c * o.npart + k]));
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
@@ -228,11 +313,10 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(int tile, int c, int n, int
       s_scale = ldexpf(1.f, e);
       if (tile == 0) o.inv_scale[c] = ldexpf(1.f, -e) / 2048.f;  // with the 2^11 of the exp tile
     }
-    __syncthreads();
-  }
-  const float scale = f16 ? s_scale : 1.f;
+  };
   // one instantiation of the tile (its LDS buffers) for both forms
-  psf_adjoint_tile<true>(tile, c, n, ss, taps, in, ld_in, [&](int fy, int fx, float v, int z) {
+  psf_adjoint_tile<true>(skip, tile, c, n, ss, taps, in, ld_in, fold_scale, [&](int fy, int fx, float v, int z) {
+    const float scale = f16 ? s_scale : 1.f;
     const size_t j = (size_t)c * o.ldh + (z >= 0 ? base + z : zorder_rank(fx, fy, M));
     if (f16) {
       const float sv = v * scale;
@@ -247,15 +331,14 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(int tile, int c, int n, int
 
 __global__ __launch_bounds__(256) void psf_adjoint_rhs_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
                                                               int ld_in, RhsOut o, CgGate gate) {
-  if (gate.skip(blockIdx.y)) return;
-  psf_adjoint_rhs_body(blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, o);
+  psf_adjoint_rhs_body([&] { return gate.skip(blockIdx.y); }, blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, o);
 }
 
 __global__ __launch_bounds__(256) void psf_adjoint_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
                                                           int ld_in, float* __restrict__ out, int ld_out,
                                                           float alpha, float beta, CgGate gate) {
-  if (gate.skip(blockIdx.y)) return;
-  psf_adjoint_body(blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out, alpha, beta);
+  psf_adjoint_body([&] { return gate.skip(blockIdx.y); }, blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out,
+                   alpha, beta);
 }
 
 // ---- grouped launches (serving): workgroup b of slot s handles (tile, column) =
@@ -264,22 +347,18 @@ __global__ __launch_bounds__(256) void psf_adjoint_kernel(int n, int ss, Taps ta
 __global__ __launch_bounds__(256) void psf_adjoint_grouped_kernel(SlotBatch B, int p) {
   const int s = B.find(blockIdx.x);
   const ServeSlotDev& S = *B.slot[s];
-  if (S.n_active[p] == 0) return;
   const int local = blockIdx.x - B.off[s];
   const int tile = local % S.ntiles_adj, c = local / S.ntiles_adj;
-  if (S.st[p][c].active == 0) return;
   const RhsOut o{S.prec, S.ldh, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd};
-  psf_adjoint_rhs_body(tile, c, S.n, S.ss, S.taps, S.P, S.ldv, o);
+  psf_adjoint_rhs_body([&] { return S.n_active[p] == 0 || S.st[p][c].active == 0; }, tile, c, S.n, S.ss, S.taps, S.P, S.ldv, o);
 }
 
 __global__ __launch_bounds__(256) void psf_forward_grouped_kernel(SlotBatch B, int p) {
   const int s = B.find(blockIdx.x);
   const ServeSlotDev& S = *B.slot[s];
-  if (S.n_active[p] == 0) return;
   const int local = blockIdx.x - B.off[s];
   const int tile = local % S.ntiles_fwd, c = local / S.ntiles_fwd;
-  if (S.st[p][c].active == 0) return;
-  psf_forward_body(tile, c, S.n, S.ss, S.taps, S.T2, S.ldf, S.AP, S.ldv, 1.f, 0.f, S.P, S.ldv, S.sigma2, S.P, S.ldv,
+  psf_forward_body([&] { return S.n_active[p] == 0 || S.st[p][c].active == 0; }, tile, c, S.n, S.ss, S.taps, S.T2, S.ldf, S.AP, S.ldv, 1.f, 0.f, S.P, S.ldv, S.sigma2, S.P, S.ldv,
                    S.pap_part, S.ntiles_fwd);
 }
 
@@ -316,6 +395,14 @@ int psf_forward_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* c
                         [](const ServeSlotDev& S) { return S.ntiles_fwd * S.nrhs; }, stream);
 }
 
+// Grid limits of the PSF tiles: ss <= kFineTile and a fine side below 2^15 (the
+// range of the branch-free division by ss).
+static int check_psf_grid(int n, int ss) {
+  GPL_REQUIRE(ss >= 1 && ss <= kFineTile, "ss=%d outside [1, %d]", ss, kFineTile);
+  GPL_REQUIRE(n >= 1 && (long)n * ss < 32768, "fine grid side %ld exceeds 32767", (long)n * ss);
+  return GPL_OK;
+}
+
 int psf_forward_tiles(int n, int ss) {
   const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;
   const int t = (n + TP - 1) / TP;
@@ -325,7 +412,7 @@ int psf_forward_tiles(int n, int ss) {
 int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* in, int ld_in, float* out, int ld_out,
                        float alpha, float beta, const float* extra, int ld_extra, float gamma, const float* dotv,
                        int ld_dotv, double* partial, CgGate gate, hipStream_t stream) {
-  GPL_REQUIRE(ss <= kFineTile, "ss=%d exceeds %d", ss, kFineTile);
+  GPL_TRY(check_psf_grid(n, ss));
   const int ntiles = psf_forward_tiles(n, ss);
   hipLaunchKernelGGL(psf_forward_kernel, dim3(ntiles, nrhs), dim3(256), 0, stream, n, ss, taps, in, ld_in, out,
                      ld_out, alpha, beta, extra, ld_extra, gamma, dotv, ld_dotv, partial, ntiles, gate);
@@ -335,6 +422,7 @@ int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* i
 
 int psf_adjoint_rhs_launch(int n, int ss, const Taps& taps, int nrhs, const float* P, int ldp, const RhsOut& out,
                            CgGate gate, hipStream_t stream) {
+  GPL_TRY(check_psf_grid(n, ss));
   const int M = n * ss, t = (M + kFineTile - 1) / kFineTile;
   hipLaunchKernelGGL(psf_adjoint_rhs_kernel, dim3(t * t, nrhs), dim3(256), 0, stream, n, ss, taps, P, ldp, out, gate);
   GPL_LAUNCH_CHECK();
@@ -343,6 +431,7 @@ int psf_adjoint_rhs_launch(int n, int ss, const Taps& taps, int nrhs, const floa
 
 int psf_adjoint_launch(int n, int ss, const Taps& taps, int nrhs, const float* in, int ld_in, float* out, int ld_out,
                        float alpha, float beta, CgGate gate, hipStream_t stream) {
+  GPL_TRY(check_psf_grid(n, ss));
   const int M = n * ss, t = (M + kFineTile - 1) / kFineTile;
   hipLaunchKernelGGL(psf_adjoint_kernel, dim3(t * t, nrhs), dim3(256), 0, stream, n, ss, taps, in, ld_in, out, ld_out,
                      alpha, beta, gate);

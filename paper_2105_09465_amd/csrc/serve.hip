@@ -129,6 +129,7 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
   Taps taps;
   GPL_TRY(make_taps(g, &prob->psf, taps));
   const int n = g->n, ss = g->ss, npix = n * n, N = npix * ss * ss;
+  GPL_REQUIRE(n >= 1 && ss >= 1 && ss <= 32 && (long)n * ss < 32768, "grid n=%d ss=%d out of range", n, ss);
   GPL_REQUIRE(nrhs == 1 || ldz >= npix, "ldz must be >= n*n");
   GPL_TRY(check_ws(ws, ws_bytes, gpl_serve_slot_workspace(g, nrhs, n_lanczos, prec)));
   Carver cv(ws, ws_bytes);
