@@ -244,11 +244,13 @@ def main():
     cg_launches = sum(iters)
     post_ms = 0.0
     avg_ms = (mvm_ms - post_ms) / max(cg_launches, 1)
-    # work of one launch: the kernel values the product evaluates, 2048 per live
-    # (row tile, chunk) pair of its tile plan; every other pair is exactly zero
-    # in this precision and is not evaluated (the result is the all-pairs one)
-    live_tiles = G.ops.kernel_mvm_live_tiles(prob.kernel, recs[-1].px, recs[-1].py, prec=args.prec, grid=prob.grid)
-    evaluated = live_tiles * 64 * 32
+    # work of one launch: the kernel values the product evaluates, 512 per live
+    # (16-point subtile, 32-point chunk) pair of its tile plan; every other pair
+    # is exactly zero in this precision and is not evaluated (the result is the
+    # all-pairs one)
+    live_tiles, live_subtiles = G.ops.kernel_mvm_live_tiles(prob.kernel, recs[-1].px, recs[-1].py, prec=args.prec,
+                                                            grid=prob.grid)
+    evaluated = live_subtiles * 16 * 32
     achieved = evaluated / (avg_ms * 1e-3) / 1e9
 
     # ---- the dominant kernel alone, same shape and stream, for the rocprof cross-check

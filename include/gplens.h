@@ -138,7 +138,7 @@ int gpl_psf_conv(const gpl_grid* grid, const gpl_psf* psf, int nrhs, const float
  * formed on demand, never stored, as in Sec. 3.3), over n points, nrhs columns
  * (V, Y column-major with ld >= n, device memory, must not overlap).
  * prec = GPL_PREC_FP32 or GPL_PREC_F16X3. beta is 0 (overwrite) or any float.
- * Pairs of 64-point row tiles and 32-point chunks whose bounding boxes are so far
+ * Pairs of 16-point subtiles and 32-point chunks whose bounding boxes are so far
  * apart that every kernel value is exactly zero in the chosen precision are not
  * evaluated, so the result equals the all-pairs product up to FP32 summation
  * order. grid (nullable): the points are that grid's fine points in row-major
@@ -150,14 +150,15 @@ int gpl_gp_kernel_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const
                       const float* V, int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes,
                       hipStream_t stream);
 
-/* Work of the product above for these points: the number of (64-point row tile,
- * 32-point chunk) pairs it evaluates, each 2048 kernel values (the rest are
- * exactly zero). Writes *live_tiles (host memory) and synchronises `stream`;
- * a measurement helper, not needed for the product itself. */
+/* Work of the product above for these points: *live_tiles = the (64-point row
+ * tile, 32-point chunk) pairs it visits, *live_subtiles (nullable) = the
+ * (16-point subtile, 32-point chunk) pairs it evaluates, 512 kernel values each
+ * (the rest are exactly zero). Host outputs; synchronises `stream`. A
+ * measurement helper, not needed for the product itself. */
 size_t gpl_gp_kernel_mvm_plan_workspace(int n);
 int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px,
-                                 const float* py, int prec, long long* live_tiles, void* ws, size_t ws_bytes,
-                                 hipStream_t stream);
+                                 const float* py, int prec, long long* live_tiles, long long* live_subtiles,
+                                 void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Y = A X with A = B K B^T + noise_sigma^2 I (image pixels, nrhs columns). */
 size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int prec);

@@ -76,7 +76,7 @@ SIGNATURES = {
                                _P, _Z, _P]),
     "gpl_gp_kernel_mvm_plan_workspace": (_Z, [_I]),
     "gpl_gp_kernel_mvm_plan_stats": (_I, [C.POINTER(gpl_kernel), C.POINTER(gpl_grid), _I, _P, _P, _I,
-                                          C.POINTER(C.c_longlong), _P, _Z, _P]),
+                                          C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), _P, _Z, _P]),
     "gpl_apply_A_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I]),
     "gpl_apply_A": (_I, [C.POINTER(gpl_problem), _I, _P, _I, _P, _I, _I, _P, _Z, _P]),
     "gpl_cg_solve_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I]),

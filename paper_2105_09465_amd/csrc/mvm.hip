@@ -71,14 +71,27 @@ int mvm_launch(double lengthscale, double amplitude, int n, const float* px, con
   return mvm_run(m, nrhs, V, ldv, Y, ldy, beta, gate, stream);
 }
 
-__global__ void plan_live_sum_kernel(int nrt, const int* count, long long* out) {
-  __shared__ long long red[4];
-  long long s = 0;
-  for (int r = threadIdx.x; r < nrt; r += blockDim.x) s += count[r];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+// out[0] = listed (row tile, chunk) pairs, out[1] = listed (subtile, chunk) pairs.
+__global__ void plan_live_sum_kernel(int nrt, int nch, const int* count, const uint32_t* list, long long* out) {
+  __shared__ long long red[2][4];
+  long long u = 0, t = 0;
+  for (int r = blockIdx.x; r < nrt; r += gridDim.x) {
+    if (threadIdx.x == 0) u += count[r];
+    for (int k = threadIdx.x; k < count[r]; k += blockDim.x) t += __popc(entry_mask(list[(size_t)r * nch + k]));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    u += __shfl_xor(u, off, 64);
+    t += __shfl_xor(t, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = u;
+    red[1][threadIdx.x >> 6] = t;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    out[1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
 }
 
 int check_kernel(const gpl_kernel* k) {
@@ -115,12 +128,13 @@ extern "C" int gpl_gp_kernel_mvm(const gpl_kernel* kern, const gpl_grid* grid, i
 }
 
 extern "C" size_t gpl_gp_kernel_mvm_plan_workspace(int n) {
-  return n > 0 ? align_up(plan_workspace(n)) + kAlign : 0;
+  return n > 0 ? align_up(plan_workspace(n)) + 2 * kAlign : 0;
 }
 
 extern "C" int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px,
-                                            const float* py, int prec, long long* live_tiles, void* ws,
-                                            size_t ws_bytes, hipStream_t stream) {
+                                            const float* py, int prec, long long* live_tiles,
+                                            long long* live_subtiles, void* ws, size_t ws_bytes,
+                                            hipStream_t stream) {
   GPL_TRY(check_kernel(kern));
   GPL_REQUIRE(prec == GPL_PREC_FP32 || prec == GPL_PREC_F16X3, "unknown precision %d", prec);
   GPL_REQUIRE(n >= 1 && px && py && live_tiles, "bad arguments");
@@ -130,12 +144,15 @@ extern "C" int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_gr
   Carver cv(ws, ws_bytes);
   TilePlan p;
   plan_carve(cv, n, p);
-  long long* dsum = cv.take<long long>(1);
+  long long* dsum = cv.take<long long>(2);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   GPL_TRY(plan_build(p, n, px, py, grid, (float)kernel_scale2(kern->lengthscale), plan_threshold(prec), stream));
-  hipLaunchKernelGGL(plan_live_sum_kernel, dim3(1), dim3(256), 0, stream, p.nrt, p.count, dsum);
+  hipLaunchKernelGGL(plan_live_sum_kernel, dim3(1), dim3(256), 0, stream, p.nrt, p.nch, p.count, p.list, dsum);
   GPL_LAUNCH_CHECK();
-  GPL_HIP(hipMemcpyAsync(live_tiles, dsum, sizeof(long long), hipMemcpyDeviceToHost, stream));
+  long long h[2];
+  GPL_HIP(hipMemcpyAsync(h, dsum, sizeof(h), hipMemcpyDeviceToHost, stream));
   GPL_HIP(hipStreamSynchronize(stream));
+  *live_tiles = h[0];
+  if (live_subtiles) *live_subtiles = h[1];
   return GPL_OK;
 }

@@ -5,8 +5,9 @@
 //
 // Work decomposition: the points are taken in the order of a tile plan
 // (tileplan.hpp), which lists for every row tile of 64 points the chunks of 32
-// points that can give a non-zero kernel value; every other pair contributes
-// exact zeros and is not evaluated. The listed (row tile, chunk) pairs are split
+// points that can give a non-zero kernel value, each with the mask of the row
+// tile's four 16-point subtiles that can; every other pair contributes exact
+// zeros and is not evaluated (a masked-out subtile skips its exp tile and MFMAs). The listed (row tile, chunk) pairs are split
 // evenly over the waves of the launch, each wave taking a contiguous run of them
 // (so the work is balanced however unevenly the live pairs fall on row tiles).
 // A wave computes 64 rows (four 16-row MFMA tiles) at a time, with each chunk's
@@ -154,39 +155,52 @@ __device__ __forceinline__ void store_partial(const f32x4 (&acc)[kRT][CB], int s
     }
 }
 
-// Runs `body(chunk)` for the chunks at positions [kb, ke) of a row tile's list;
-// the chunk indices are read 64 at a time, one per lane, and broadcast with
-// readlane so that the chunk is uniform across the wave.
+// Runs `body(entry)` for the list entries at positions [kb, ke) of a row tile's
+// list; the entries are read 64 at a time, one per lane, and broadcast with
+// readlane so that the chunk and its subtile mask are uniform across the wave.
 template <class F>
-__device__ __forceinline__ void for_chunks(const uint16_t* lst, int kb, int ke, int lane, F&& body) {
+__device__ __forceinline__ void for_chunks(const uint32_t* lst, int kb, int ke, int lane, F&& body) {
 #pragma unroll 1
   for (int k0 = kb; k0 < ke; k0 += 64) {
     const int m = min(64, ke - k0);
     const int vidx = lane < m ? (int)lst[k0 + lane] : 0;
 #pragma unroll 1
-    for (int t = 0; t < m; ++t) body(__builtin_amdgcn_readlane(vidx, t));
+    for (int t = 0; t < m; ++t) body((uint32_t)__builtin_amdgcn_readlane(vidx, t));
   }
+}
+
+// Waits until at most N vector-memory loads of this wave are outstanding (vmcnt
+// only; the expcnt and lgkmcnt fields are left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
 // As for_chunks with two operand buffers: the next chunk's loads are issued
 // before the current chunk is computed (a load past the end repeats the last
-// chunk and is not used).
+// chunk and is not used). Before each compute the wave waits explicitly for the
+// current buffer, leaving exactly the next buffer's Buf::kLoads loads in flight;
+// without it, the compiler's conservative waits at the subtile branches also
+// waited for the next buffer and serialised every chunk on its loads.
 template <class Buf, class L, class C>
-__device__ __forceinline__ void for_chunks_pf(const uint16_t* lst, int kb, int ke, int lane, L&& load, C&& compute) {
+__device__ __forceinline__ void for_chunks_pf(const uint32_t* lst, int kb, int ke, int lane, L&& load, C&& compute) {
 #pragma unroll 1
   for (int k0 = kb; k0 < ke; k0 += 64) {
     const int m = min(64, ke - k0);
     const int vidx = lane < m ? (int)lst[k0 + lane] : 0;
     Buf a, b;
-    load(a, __builtin_amdgcn_readlane(vidx, 0));
+    load(a, (uint32_t)__builtin_amdgcn_readlane(vidx, 0));
 #pragma unroll 1
     for (int t = 0; t < m; t += 2) {
-      load(b, __builtin_amdgcn_readlane(vidx, min(t + 1, m - 1)));
+      load(b, (uint32_t)__builtin_amdgcn_readlane(vidx, min(t + 1, m - 1)));
       __builtin_amdgcn_sched_barrier(0);  // keep the next chunk's loads ahead of this compute
+      wait_vmcnt<Buf::kLoads>();
       compute(a);
       if (t + 1 >= m) break;
-      load(a, __builtin_amdgcn_readlane(vidx, min(t + 2, m - 1)));
+      load(a, (uint32_t)__builtin_amdgcn_readlane(vidx, min(t + 2, m - 1)));
       __builtin_amdgcn_sched_barrier(0);
+      wait_vmcnt<Buf::kLoads>();
       compute(b);
     }
   }
@@ -228,18 +242,22 @@ __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __
 
 // ---------------------------------------------------------------- precision form
 
-// Operands of one chunk for one lane: its 8 consecutive source points and the
-// hi/lo RHS fragments of every column block (columns past nrhs are zero).
+// Operands of one chunk for one lane: its 8 consecutive source points, the
+// hi/lo RHS fragments of every column block (columns past nrhs are zero) and
+// the (uniform) mask of the subtiles that see the chunk.
 template <int CB>
 struct F16Chunk {
+  static constexpr int kLoads = 4 + 2 * CB;  // vector loads issued by f16_load
   f32x4 x0, x1, y0, y1;
   half8 bh[CB], bl[CB];
+  unsigned mask;
 };
 
 template <int CB>
 __device__ __forceinline__ void f16_load(F16Chunk<CB>& c, const TilePlan& P, const _Float16* __restrict__ Vh,
-                                         const _Float16* __restrict__ Vl, int ldh, int ch, int ri, int g) {
-  const int j0 = ch * kChunk + g * 8;
+                                         const _Float16* __restrict__ Vl, int ldh, uint32_t entry, int ri, int g) {
+  c.mask = entry_mask(entry);
+  const int j0 = entry_chunk(entry) * kChunk + g * 8;
   c.x0 = *reinterpret_cast<const f32x4*>(&P.xs[j0]);
   c.x1 = *reinterpret_cast<const f32x4*>(&P.xs[j0 + 4]);
   c.y0 = *reinterpret_cast<const f32x4*>(&P.ys[j0]);
@@ -259,6 +277,7 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
   const float yj[8] = {c.y0[0], c.y0[1], c.y0[2], c.y0[3], c.y1[0], c.y1[1], c.y1[2], c.y1[3]};
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
+    if (!((c.mask >> rt) & 1u)) continue;  // every exp of this 16 x 32 tile is exactly zero
     float hf[8], lf[8], dx[8], dy[8], d2[8], k2[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) dx[e] = xi[rt] - xj[e];
@@ -304,10 +323,10 @@ __device__ __forceinline__ void mvm_f16x3_wave(int w, const TilePlan& P, float s
                                                float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
   wave_product<CB>(w, P, part, pcols, c0, ncols,
-                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint16_t* lst,
+                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
                      for_chunks_pf<F16Chunk<CB>>(lst, kb, ke, lane,
-                         [&](F16Chunk<CB>& c, int ch) { f16_load(c, P, Vh, Vl, ldh, ch, ri, g); },
+                         [&](F16Chunk<CB>& c, uint32_t e) { f16_load(c, P, Vh, Vl, ldh, e, ri, g); },
                          [&](const F16Chunk<CB>& c) { f16_compute(acc, c, xi, yi, s2); });
                    });
 }
@@ -326,10 +345,11 @@ __global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, float 
 
 template <int CB>
 __device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT],
-                                          const TilePlan& P, float s2, const float* __restrict__ Vp, int ldh, int ch,
-                                          int ri, int g) {
+                                          const TilePlan& P, float s2, const float* __restrict__ Vp, int ldh,
+                                          uint32_t entry, int ri, int g) {
   // two groups of 16 points; in each, this lane's 4 consecutive points
-  const int jc = ch * kChunk + g * 4;
+  const unsigned mask = entry_mask(entry);
+  const int jc = entry_chunk(entry) * kChunk + g * 4;
   float xj[8], yj[8];
   *reinterpret_cast<f32x4*>(&xj[0]) = *reinterpret_cast<const f32x4*>(&P.xs[jc]);
   *reinterpret_cast<f32x4*>(&xj[4]) = *reinterpret_cast<const f32x4*>(&P.xs[jc + 16]);
@@ -343,6 +363,7 @@ __device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&x
       b[cb][h] = *reinterpret_cast<const f32x4*>(&Vp[(size_t)(cb * 16 + ri) * ldh + jc + 16 * h]);
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
+    if (!((mask >> rt) & 1u)) continue;  // every exp of this 16 x 32 tile is exactly zero
     float kv[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -363,9 +384,10 @@ __device__ __forceinline__ void mvm_f32_wave(int w, const TilePlan& P, float s2,
                                              int ldh, int ncols, float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
   wave_product<CB>(w, P, part, pcols, c0, ncols,
-                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint16_t* lst,
+                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
-                     for_chunks(lst, kb, ke, lane, [&](int ch) { f32_chunk<CB>(acc, xi, yi, P, s2, Vp, ldh, ch, ri, g); });
+                     for_chunks(lst, kb, ke, lane,
+                                [&](uint32_t e) { f32_chunk<CB>(acc, xi, yi, P, s2, Vp, ldh, e, ri, g); });
                    });
 }
 

@@ -93,14 +93,46 @@ int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
   return GPL_OK;
 }
 
-// Forward: out[I] = alpha * (B in)[I] + beta * out[I] + gamma * extra[I];
-// optional FP64 partial sums of dotv[I] * out[I] per (column, tile).
 // floor(v / ss) for 0 <= v < 2^15 and 1 <= ss <= 32, rss = 1 / ss in FP32:
 // (v + 1/2) / ss stays at least 1/64 away from an integer, far more than the
 // FP32 rounding of the product. Branch-free, so the loads it addresses are not
 // split into separately waited blocks.
 __device__ __forceinline__ int div_ss(int v, float rss) { return (int)(((float)v + 0.5f) * rss); }
 
+// x-convolution of the staged window, S2[wy * LS + x] = sum_b w_b S1[wy * W + x + r + SGN b]
+// for wy < W, x < F <= 32 (SGN = -1: convolution, +1: correlation). Thread
+// (lx, ly) takes column lx and rows ly + 8k, three rows at a time so that three
+// independent FMA chains share each tap (a row past the window reads the last
+// row and is not stored).
+template <int SGN>
+__device__ __forceinline__ void conv_x(const float* S1, float* S2, const float* tw, int W, int F, int LS, int r) {
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  if (lx >= F) return;
+  const int nk = (W + 7) / 8;
+#pragma unroll 1
+  for (int k0 = 0; k0 < nk; k0 += 3) {
+    int wy[3];
+    const float* row[3];
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      wy[i] = ly + 8 * (k0 + i);
+      row[i] = S1 + min(wy[i], W - 1) * W + lx + r;
+    }
+#pragma unroll 2
+    for (int b = -r; b <= r; ++b) {
+      const float w = tw[b + r];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[i] = fmaf(w, row[i][SGN * b], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (wy[i] < W) S2[wy[i] * LS + lx] = acc[i];
+  }
+}
+
+// Forward: out[I] = alpha * (B in)[I] + beta * out[I] + gamma * extra[I];
+// optional FP64 partial sums of dotv[I] * out[I] per (column, tile).
 // `skip()` (uniform over the workgroup) is evaluated once the window loads are in
 // flight; when it is true the workgroup leaves without writing anything.
 template <class Skip>
@@ -153,33 +185,48 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
     win_store(R, W, S1);
   }
   __syncthreads();
-  for (int wy = ly; wy < W; wy += 8)
-    for (int x = lx; x < F; x += 32) {
-      const float* row = S1 + wy * W + x + r;
-      float s = 0.f;
-#pragma unroll 4
-      for (int b = -r; b <= r; ++b) s += tw[b + r] * row[-b];
-      S2[wy * LS + x] = s;
-    }
+  conv_x<-1>(S1, S2, tw, W, F, LS, r);
   __syncthreads();
-  const float inv_ss2 = 1.f / (float)(ss * ss);
+  // y-convolution of this thread's fine points, four independent chains at a
+  // time: chain q is fine point q % ss^2 of output u = q / ss^2.
+  const int ss2 = ss * ss;
+  const float inv_ss2 = 1.f / (float)ss2;
+  float acc[kOutPer] = {};
+  int nq = 0;
+#pragma unroll
+  for (int u = 0; u < kOutPer; ++u) nq += I[u] >= 0 ? ss2 : 0;  // outputs of a thread come first
+#pragma unroll 1
+  for (int q0 = 0; q0 < nq; q0 += 4) {
+    const float* col[4];
+    int uq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = min(q0 + i, nq - 1);
+      const int u = q / ss2, f = q - u * ss2;
+      const int sy = f / ss, sx = f - sy * ss;
+      const int o = threadIdx.x + u * 256;
+      const int oy = o / TP, ox = o - oy * TP;
+      col[i] = S2 + (oy * ss + sy + r) * LS + ox * ss + sx;
+      uq[i] = q0 + i < nq ? u : -1;
+    }
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int a = -r; a <= r; ++a) {
+      const float w = tw[a + r];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = fmaf(w, col[i][-a * LS], v[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int u = 0; u < kOutPer; ++u)
+        if (uq[i] == u) acc[u] += v[i];
+  }
   double dot = 0.0;
 #pragma unroll
   for (int u = 0; u < kOutPer; ++u) {
     if (I[u] < 0) continue;
-    const int o = threadIdx.x + u * 256;
-    const int oy = o / TP, ox = o - oy * TP;
-    float acc = 0.f;
-    for (int sy = 0; sy < ss; ++sy)
-      for (int sx = 0; sx < ss; ++sx) {
-        const int y = oy * ss + sy, x = ox * ss + sx;
-        const float* col = S2 + (y + r) * LS + x;
-        float v = 0.f;
-#pragma unroll 4
-        for (int a = -r; a <= r; ++a) v += tw[a + r] * col[-a * LS];
-        acc += v;
-      }
-    float res = alpha * (acc * inv_ss2);
+    float res = alpha * (acc[u] * inv_ss2);
     if (beta != 0.f) res += beta * o_old[u];
     if (extra) res += gamma * o_ext[u];
     out[(size_t)c * ld_out + I[u]] = res;
@@ -234,18 +281,18 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
     win_store(R, W, S1);
   }
   __syncthreads();
-  for (int wy = ly; wy < W; wy += 8) {
-    const float* row = S1 + wy * W + lx + r;
-    float s = 0.f;
-#pragma unroll 4
-    for (int b = -r; b <= r; ++b) s += tw[b + r] * row[b];
-    S2[wy * LS + lx] = s;
-  }
+  conv_x<1>(S1, S2, tw, W, F, LS, r);
   __syncthreads();
   // A tile fully inside the grid holds consecutive Z-order ranks (it is an
   // aligned power-of-two square): z is the point's Z-order index in the tile.
+  // Each thread takes the points o = tid + 256 u, u < 4, as four chains.
   const bool zwalk = ZWALK && fy0 + F <= M && fx0 + F <= M;
-  for (int o = threadIdx.x; o < F * F; o += blockDim.x) {
+  constexpr int kPer = kFineTile * kFineTile / 256;
+  int px[kPer], py[kPer];
+  const float* col[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int o = threadIdx.x + u * 256;
     int x = 0, y = 0;
     if (zwalk) {
 #pragma unroll
@@ -257,14 +304,21 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
       y = o >> 5;
       x = o & 31;
     }
-    const int fy = fy0 + y, fx = fx0 + x;
-    if (fy >= M || fx >= M) continue;
-    const float* col = S2 + (y + r) * LS + x;
-    float v = 0.f;
-#pragma unroll 4
-    for (int a = -r; a <= r; ++a) v += tw[a + r] * col[a * LS];
-    const int z = zwalk ? o : -1;
-    store(fy, fx, v * inv_ss2, z);
+    px[u] = x;
+    py[u] = y;
+    col[u] = S2 + (y + r) * LS + x;
+  }
+  float v[kPer] = {};
+#pragma unroll 2
+  for (int a = -r; a <= r; ++a) {
+    const float w = tw[a + r];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) v[u] = fmaf(w, col[u][a * LS], v[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int fy = fy0 + py[u], fx = fx0 + px[u];
+    if (fy < M && fx < M) store(fy, fx, v[u] * inv_ss2, zwalk ? (int)threadIdx.x + u * 256 : -1);
   }
 }
 

@@ -37,16 +37,13 @@ __global__ void plan_points_kernel(int n, int npad, const float* __restrict__ px
   ys[r] = py[i];
 }
 
-// Bounding box of each chunk of 32 sorted points (valid points only). A chunk
-// holding a non-finite coordinate gets an infinite box so it is never dropped.
-__global__ void plan_boxes_kernel(int n, int nch, const float* __restrict__ xs, const float* __restrict__ ys,
-                                  float4* cbox) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nch) return;
+// Bounding box of the valid points in [j0, j1); a non-finite coordinate gives
+// an infinite box (never dropped), no valid point an empty one (always dropped).
+__device__ __forceinline__ float4 point_box(const float* __restrict__ xs, const float* __restrict__ ys, int j0,
+                                            int j1) {
   float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
   bool bad = false;
-  const int jend = min(n, (c + 1) * kChunk);
-  for (int j = c * kChunk; j < jend; ++j) {
+  for (int j = j0; j < j1; ++j) {
     const float x = xs[j], y = ys[j];
     bad |= !(isfinite(x) && isfinite(y));
     x0 = fminf(x0, x);
@@ -54,31 +51,58 @@ __global__ void plan_boxes_kernel(int n, int nch, const float* __restrict__ xs, 
     y0 = fminf(y0, y);
     y1 = fmaxf(y1, y);
   }
-  cbox[c] = bad ? make_float4(-INFINITY, INFINITY, -INFINITY, INFINITY) : make_float4(x0, x1, y0, y1);
+  return bad ? make_float4(-INFINITY, INFINITY, -INFINITY, INFINITY) : make_float4(x0, x1, y0, y1);
 }
 
-// One wave per row tile: ascending list of live chunks by ballot compaction.
-__global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const float4* __restrict__ cbox, float s2,
-                                                        float threshold, int* count, uint16_t* list) {
+// Boxes of each chunk of 32 sorted points and of its two 16-point subtiles.
+__global__ void plan_boxes_kernel(int n, int nch, const float* __restrict__ xs, const float* __restrict__ ys,
+                                  float4* cbox, float4* sbox) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  const int j0 = c * kChunk, jm = min(n, j0 + kSubTile), j1 = min(n, j0 + kChunk);
+  const float4 a = point_box(xs, ys, j0, jm), b = point_box(xs, ys, jm, j1);
+  sbox[2 * c] = a;
+  sbox[2 * c + 1] = b;
+  cbox[c] = make_float4(fminf(a.x, b.x), fmaxf(a.y, b.y), fminf(a.z, b.z), fmaxf(a.w, b.w));
+}
+
+// s2 g^2 < threshold for the gap g between two boxes (NaN-free: an infinite box
+// gives a zero gap, an empty one an infinite gap).
+__device__ __forceinline__ bool boxes_live(const float4& a, const float4& q, float s2, float threshold) {
+  const float gx = fmaxf(0.f, fmaxf(q.x - a.y, a.x - q.y));
+  const float gy = fmaxf(0.f, fmaxf(q.z - a.w, a.z - q.w));
+  return !(s2 * fmaf(gx, gx, gy * gy) >= threshold);
+}
+
+// One wave per row tile: ascending list of live chunks by ballot compaction,
+// each entry with the mask of the subtiles that see the chunk.
+__global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const float4* __restrict__ cbox,
+                                                        const float4* __restrict__ sbox, float s2, float threshold,
+                                                        int* count, uint32_t* list) {
   const int r = blockIdx.x;
   if (r >= nrt) return;
   const int lane = threadIdx.x;
+  float4 sb[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) sb[t] = sbox[4 * r + t];
   const float4 a = cbox[2 * r], b = cbox[2 * r + 1];
-  const float rx0 = fminf(a.x, b.x), rx1 = fmaxf(a.y, b.y), ry0 = fminf(a.z, b.z), ry1 = fmaxf(a.w, b.w);
-  uint16_t* out = list + (size_t)r * nch;
+  const float4 rb = make_float4(fminf(a.x, b.x), fmaxf(a.y, b.y), fminf(a.z, b.z), fmaxf(a.w, b.w));
+  uint32_t* out = list + (size_t)r * nch;
   int base = 0;
   for (int c0 = 0; c0 < nch; c0 += 64) {
     const int c = c0 + lane;
-    bool live = false;
+    unsigned mask = 0u;
     if (c < nch) {
       const float4 q = cbox[c];
-      const float gx = fmaxf(0.f, fmaxf(q.x - rx1, rx0 - q.y));
-      const float gy = fmaxf(0.f, fmaxf(q.z - ry1, ry0 - q.w));
-      live = !(s2 * fmaf(gx, gx, gy * gy) >= threshold);
+      if (boxes_live(rb, q, s2, threshold)) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) mask |= (boxes_live(sb[t], q, s2, threshold) ? 1u : 0u) << t;
+      }
     }
-    const unsigned long long mask = __ballot(live);
-    if (live) out[base + __popcll(mask & ((1ull << lane) - 1ull))] = (uint16_t)c;
-    base += __popcll(mask);
+    const bool live = mask != 0u;
+    const unsigned long long bal = __ballot(live);
+    if (live) out[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)c | (mask << 16);
+    base += __popcll(bal);
   }
   if (lane == 0) count[r] = base;
 }
@@ -181,10 +205,11 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   hipLaunchKernelGGL(plan_points_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, n, p.npad, px, py, m,
                      grid ? perm : nullptr, p.xs, p.ys);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_boxes_kernel, dim3(cdiv(p.nch, 256)), dim3(256), 0, stream, n, p.nch, p.xs, p.ys, p.cbox);
+  hipLaunchKernelGGL(plan_boxes_kernel, dim3(cdiv(p.nch, 256)), dim3(256), 0, stream, n, p.nch, p.xs, p.ys, p.cbox,
+                     p.sbox);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_lists_kernel, dim3(p.nrt), dim3(64), 0, stream, p.nrt, p.nch, p.cbox, s2, threshold,
-                     p.count, p.list);
+  hipLaunchKernelGGL(plan_lists_kernel, dim3(p.nrt), dim3(64), 0, stream, p.nrt, p.nch, p.cbox, p.sbox, s2,
+                     threshold, p.count, p.list);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, p.nrt, p.count, p.unit_off, p.total);
   GPL_LAUNCH_CHECK();

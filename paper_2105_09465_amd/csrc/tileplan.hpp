@@ -1,9 +1,10 @@
 // Tile plan of the matrix-free kernel product: the points in a spatially
-// coherent order, the bounding box of every row tile (64 points) and column
-// chunk (32 points), and for every row tile the ascending list of chunks that
-// can hold a non-zero kernel value in the chosen precision.
+// coherent order, the bounding box of every 16-point subtile and 32-point
+// chunk, and for every row tile (64 points, four subtiles) the ascending list of
+// chunks that can hold a non-zero kernel value in the chosen precision, each
+// with a mask of the subtiles that can.
 //
-// A (row tile, chunk) pair is dropped only when the box gap g satisfies
+// A (subtile, chunk) pair is dropped only when the box gap g satisfies
 // s2 g^2 >= threshold, with s2 = log2(e)/(2 l^2) the exp2 scale of the RBF
 // kernel (Sec. 3.1, eq. "grbf"): then every exp tile entry of the pair is
 // exactly zero in the form that evaluates it (below the smallest FP16
@@ -19,6 +20,7 @@
 namespace gpl {
 
 constexpr int kRowTile = 64;     // rows per wave (four 16-row MFMA tiles)
+constexpr int kSubTile = 16;     // rows of one MFMA tile
 constexpr int kChunk = 32;       // source points per chunk
 constexpr int kMaxPlanWaves = 3072;    // waves of one product launch (3 per SIMD)
 constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
@@ -28,6 +30,11 @@ constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
 // margin for the FP32 rounding of the box gap and of d^2).
 constexpr float kSkipF16x3 = 36.f;
 constexpr float kSkipFp32 = 152.f;
+
+// List entries: chunk index in the low 16 bits, bit 16 + t set when subtile t of
+// the row tile can see the chunk (entries with no such bit are not listed).
+__host__ __device__ inline int entry_chunk(uint32_t e) { return (int)(e & 0xffffu); }
+__host__ __device__ inline unsigned entry_mask(uint32_t e) { return e >> 16; }
 
 // The evaluated work is a sequence of units, the live (row tile, chunk) pairs in
 // row-tile order. A product launch of nw waves gives wave w the contiguous
@@ -44,8 +51,9 @@ struct TilePlan {
   const int* perm;  // sorted position -> caller index; nullptr = identity
   float *xs, *ys;   // [npad] points in sorted order, zero padded
   float4* cbox;     // [nch] (xmin, xmax, ymin, ymax); empty chunks have xmin = +inf
-  int* count;       // [nrt] live chunks of each row tile (>= 1)
-  uint16_t* list;   // [nrt][nch] live chunks of each row tile, ascending
+  float4* sbox;     // [4 nrt] the same for every 16-point subtile
+  int* count;       // [nrt] live chunks of each row tile
+  uint32_t* list;   // [nrt][nch] entries of the live chunks of each row tile, ascending
   int* unit_off;    // [nrt] first unit of each row tile (exclusive prefix of count)
   int* total;       // [1] T
   int* wrow;        // [nw] row tile of each wave's first unit (-1: no units)
@@ -75,8 +83,9 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.xs = cv.template take<float>((size_t)p.npad);
   p.ys = cv.template take<float>((size_t)p.npad);
   p.cbox = cv.template take<float4>((size_t)p.nch);
+  p.sbox = cv.template take<float4>((size_t)p.nrt * 4);
   p.count = cv.template take<int>((size_t)p.nrt);
-  p.list = cv.template take<uint16_t>((size_t)p.nrt * p.nch);
+  p.list = cv.template take<uint32_t>((size_t)p.nrt * p.nch);
   p.unit_off = cv.template take<int>((size_t)p.nrt);
   p.total = cv.template take<int>(1);
   p.wrow = cv.template take<int>((size_t)p.nw);

@@ -124,17 +124,18 @@ def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0, grid:
     return out[0] if (squeeze and out.dim() == 2) else out
 
 
-def kernel_mvm_live_tiles(kernel: Kernel, px, py, prec="fp32", grid: Grid | None = None) -> int:
-    """Number of (64-point row tile, 32-point chunk) pairs the product evaluates
-    for these points (2048 kernel values each); synchronises the stream."""
+def kernel_mvm_live_tiles(kernel: Kernel, px, py, prec="fp32", grid: Grid | None = None) -> tuple[int, int]:
+    """Work of the product for these points: (64-point row tile, 32-point chunk)
+    pairs visited and (16-point subtile, 32-point chunk) pairs evaluated (512
+    kernel values each); synchronises the stream."""
     n = px.numel()
     ws, wsb = workspace(_lib.lib.gpl_gp_kernel_mvm_plan_workspace(n), px.device)
-    out = C.c_longlong(0)
+    tiles, subtiles = C.c_longlong(0), C.c_longlong(0)
     k = kernel.c()
     g = C.byref(grid.c()) if grid is not None else None
-    _lib.call("gpl_gp_kernel_mvm_plan_stats", C.byref(k), g, n, _ptr(px), _ptr(py), prec_code(prec), C.byref(out),
-              _wsptr(ws), wsb, _stream())
-    return int(out.value)
+    _lib.call("gpl_gp_kernel_mvm_plan_stats", C.byref(k), g, n, _ptr(px), _ptr(py), prec_code(prec), C.byref(tiles),
+              C.byref(subtiles), _wsptr(ws), wsb, _stream())
+    return int(tiles.value), int(subtiles.value)
 
 
 def problem_c(problem: Problem, px, py):

@@ -265,12 +265,14 @@ def test_kernel_mvm_grid_tiles(G, prec):
     Vt = cuda32(V)
     Yg = G.ops.kernel_mvm(prob.kernel, pts[0], pts[1], Vt, prec=prec, grid=prob.grid)
     Yc = G.ops.kernel_mvm(prob.kernel, pts[0], pts[1], Vt, prec=prec)
-    live_g = G.ops.kernel_mvm_live_tiles(prob.kernel, pts[0], pts[1], prec=prec, grid=prob.grid)
-    live_c = G.ops.kernel_mvm_live_tiles(prob.kernel, pts[0], pts[1], prec=prec)
+    live_g, sub_g = G.ops.kernel_mvm_live_tiles(prob.kernel, pts[0], pts[1], prec=prec, grid=prob.grid)
+    live_c, sub_c = G.ops.kernel_mvm_live_tiles(prob.kernel, pts[0], pts[1], prec=prec)
     total = (w.N // 64) * (w.N // 32)
-    print(f"evaluated tile pairs: grid order {live_g / total:.3f}, row-major {live_c / total:.3f}")
+    print(f"visited tile pairs: grid order {live_g / total:.3f}, row-major {live_c / total:.3f}; "
+          f"evaluated subtile pairs {sub_g / (4 * total):.3f}, {sub_c / (4 * total):.3f}")
     assert live_g < live_c < total
     assert live_g < 0.5 * total
+    assert live_g <= sub_g <= 4 * live_g and sub_g < 4 * live_g  # some subtiles of visited pairs are skipped
     px, py = t64(pts[0]), t64(pts[1])
     rows = rng.choice(w.N, 300, replace=False)
     V64 = V.astype(np.float64).T
