@@ -122,7 +122,7 @@ int mvm_run_prepared(const MvmCtx& m, int nrhs, float* Y, int ldy, float beta, C
 // precision form taken from partial maxima of |P| (|B^T P| <= max |P| / ss^2).
 struct RhsOut {
   int prec;
-  int ldh;
+  int ncp;  // columns of the buffers (rhs_at layout)
   _Float16 *Vh, *Vl;
   float *Vp, *inv_scale;
   const unsigned* pmax;  // [nrhs][npart] float bits of partial max |P|

@@ -82,7 +82,7 @@ __device__ __forceinline__ float gather_rhs(int j, int c, int n, int nrhs, const
 // inv_scale[c] = 2^-e_c / 2^11 folds both scales for the output.
 __device__ __forceinline__ void split_rhs_body(int bx, int c, int n, int nrhs, const float* __restrict__ V, int ldv,
                                                const int* perm, const unsigned* colmax, _Float16* Vh, _Float16* Vl,
-                                               int ldh, float* inv_scale) {
+                                               int ldh, int ncp, float* inv_scale) {
   const int j = bx * blockDim.x + threadIdx.x;
   if (j >= ldh) return;
   int e = 0;
@@ -97,29 +97,29 @@ __device__ __forceinline__ void split_rhs_body(int bx, int c, int n, int nrhs, c
   const float v = gather_rhs(j, c, n, nrhs, perm, V, ldv) * scale;
   const _Float16 h = (_Float16)v;
   const _Float16 l = (_Float16)(v - (float)h);
-  Vh[(size_t)c * ldh + j] = h;
-  Vl[(size_t)c * ldh + j] = l;
+  Vh[rhs_at(c, j, ncp)] = h;
+  Vl[rhs_at(c, j, ncp)] = l;
 }
 
 __global__ void split_rhs_kernel(int n, int nrhs, const float* __restrict__ V, int ldv, const int* perm,
-                                 const unsigned* colmax, _Float16* Vh, _Float16* Vl, int ldh, float* inv_scale,
+                                 const unsigned* colmax, _Float16* Vh, _Float16* Vl, int ldh, int ncp, float* inv_scale,
                                  CgGate gate) {
   if (gate.skip_all()) return;
-  split_rhs_body(blockIdx.x, blockIdx.y, n, nrhs, V, ldv, perm, colmax, Vh, Vl, ldh, inv_scale);
+  split_rhs_body(blockIdx.x, blockIdx.y, n, nrhs, V, ldv, perm, colmax, Vh, Vl, ldh, ncp, inv_scale);
 }
 
 // FP32 form: the RHS block in sorted order, zero padded.
 __device__ __forceinline__ void pack_rhs_body(int bx, int c, int n, int nrhs, const float* __restrict__ V, int ldv,
-                                              const int* perm, float* Vp, int ldh) {
+                                              const int* perm, float* Vp, int ldh, int ncp) {
   const int j = bx * blockDim.x + threadIdx.x;
   if (j >= ldh) return;
-  Vp[(size_t)c * ldh + j] = gather_rhs(j, c, n, nrhs, perm, V, ldv);
+  Vp[rhs_at(c, j, ncp)] = gather_rhs(j, c, n, nrhs, perm, V, ldv);
 }
 
 __global__ void pack_rhs_kernel(int n, int nrhs, const float* __restrict__ V, int ldv, const int* perm, float* Vp,
-                                int ldh, CgGate gate) {
+                                int ldh, int ncp, CgGate gate) {
   if (gate.skip_all()) return;
-  pack_rhs_body(blockIdx.x, blockIdx.y, n, nrhs, V, ldv, perm, Vp, ldh);
+  pack_rhs_body(blockIdx.x, blockIdx.y, n, nrhs, V, ldv, perm, Vp, ldh, ncp);
 }
 
 // ---------------------------------------------------------------- work of one wave
@@ -255,7 +255,7 @@ struct F16Chunk {
 
 template <int CB>
 __device__ __forceinline__ void f16_load(F16Chunk<CB>& c, const TilePlan& P, const _Float16* __restrict__ Vh,
-                                         const _Float16* __restrict__ Vl, int ldh, uint32_t entry, int ri, int g) {
+                                         const _Float16* __restrict__ Vl, int ncp, uint32_t entry, int ri, int g) {
   c.mask = entry_mask(entry);
   const int j0 = entry_chunk(entry) * kChunk + g * 8;
   c.x0 = *reinterpret_cast<const f32x4*>(&P.xs[j0]);
@@ -264,7 +264,7 @@ __device__ __forceinline__ void f16_load(F16Chunk<CB>& c, const TilePlan& P, con
   c.y1 = *reinterpret_cast<const f32x4*>(&P.ys[j0 + 4]);
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
-    const size_t o = (size_t)(cb * 16 + ri) * ldh + j0;
+    const size_t o = ((size_t)entry_chunk(entry) * ncp + cb * 16 + ri) * kChunk + g * 8;
     c.bh[cb] = *reinterpret_cast<const half8*>(&Vh[o]);
     c.bl[cb] = *reinterpret_cast<const half8*>(&Vl[o]);
   }
@@ -319,14 +319,14 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
 
 template <int CB>
 __device__ __forceinline__ void mvm_f16x3_wave(int w, const TilePlan& P, float s2, const _Float16* __restrict__ Vh,
-                                               const _Float16* __restrict__ Vl, int ldh, int ncols,
+                                               const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
   wave_product<CB>(w, P, part, pcols, c0, ncols,
                    [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
                      for_chunks_pf<F16Chunk<CB>>(lst, kb, ke, lane,
-                         [&](F16Chunk<CB>& c, uint32_t e) { f16_load(c, P, Vh, Vl, ldh, e, ri, g); },
+                         [&](F16Chunk<CB>& c, uint32_t e) { f16_load(c, P, Vh, Vl, ncp, e, ri, g); },
                          [&](const F16Chunk<CB>& c) { f16_compute(acc, c, xi, yi, s2); });
                    });
 }
@@ -334,18 +334,18 @@ __device__ __forceinline__ void mvm_f16x3_wave(int w, const TilePlan& P, float s
 // One wave per share of the plan's units; 4 independent waves per workgroup.
 template <int CB>
 __global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, float s2, const _Float16* __restrict__ Vh,
-                                                        const _Float16* __restrict__ Vl, int ldh, int ncols,
+                                                        const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                         float* __restrict__ part, int pcols, int c0, CgGate gate) {
   if (gate.skip_all()) return;
   const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  mvm_f16x3_wave<CB>(w, P, s2, Vh, Vl, ldh, ncols, part, pcols, c0);
+  mvm_f16x3_wave<CB>(w, P, s2, Vh, Vl, ncp, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- FP32 form
 
 template <int CB>
 __device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT],
-                                          const TilePlan& P, float s2, const float* __restrict__ Vp, int ldh,
+                                          const TilePlan& P, float s2, const float* __restrict__ Vp, int ncp,
                                           uint32_t entry, int ri, int g) {
   // two groups of 16 points; in each, this lane's 4 consecutive points
   const unsigned mask = entry_mask(entry);
@@ -360,7 +360,8 @@ __device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&x
   for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
     for (int h = 0; h < 2; ++h)
-      b[cb][h] = *reinterpret_cast<const f32x4*>(&Vp[(size_t)(cb * 16 + ri) * ldh + jc + 16 * h]);
+      b[cb][h] = *reinterpret_cast<const f32x4*>(&Vp[((size_t)entry_chunk(entry) * ncp + cb * 16 + ri) * kChunk +
+                                                     g * 4 + 16 * h]);
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
     if (!((mask >> rt) & 1u)) continue;  // every exp of this 16 x 32 tile is exactly zero
@@ -381,23 +382,23 @@ __device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&x
 
 template <int CB>
 __device__ __forceinline__ void mvm_f32_wave(int w, const TilePlan& P, float s2, const float* __restrict__ Vp,
-                                             int ldh, int ncols, float* __restrict__ part, int pcols, int c0) {
+                                             int ncp, int ncols, float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
   wave_product<CB>(w, P, part, pcols, c0, ncols,
                    [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
                      for_chunks(lst, kb, ke, lane,
-                                [&](uint32_t e) { f32_chunk<CB>(acc, xi, yi, P, s2, Vp, ldh, e, ri, g); });
+                                [&](uint32_t e) { f32_chunk<CB>(acc, xi, yi, P, s2, Vp, ncp, e, ri, g); });
                    });
 }
 
 template <int CB>
 __global__ __launch_bounds__(256) void mvm_f32_kernel(const TilePlan P, float s2, const float* __restrict__ Vp,
-                                                      int ldh, int ncols, float* __restrict__ part, int pcols, int c0,
+                                                      int ncp, int ncols, float* __restrict__ part, int pcols, int c0,
                                                       CgGate gate) {
   if (gate.skip_all()) return;
   const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  mvm_f32_wave<CB>(w, P, s2, Vp, ldh, ncols, part, pcols, c0);
+  mvm_f32_wave<CB>(w, P, s2, Vp, ncp, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- reduction
@@ -473,16 +474,16 @@ float plan_threshold(int prec) { return prec == GPL_PREC_F16X3 ? kSkipF16x3 : kS
 // ---------------------------------------------------------------- launches
 
 template <int CB>
-static void launch_f16x3(const TilePlan& P, float s2, const _Float16* Vh, const _Float16* Vl, int ldh, int ncols,
+static void launch_f16x3(const TilePlan& P, float s2, const _Float16* Vh, const _Float16* Vl, int ncp, int ncols,
                          float* part, int pcols, int c0, CgGate gate, hipStream_t stream) {
-  hipLaunchKernelGGL((mvm_f16x3_kernel<CB>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ldh, ncols,
+  hipLaunchKernelGGL((mvm_f16x3_kernel<CB>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ncp, ncols,
                      part, pcols, c0, gate);
 }
 
 template <int CB>
-static void launch_f32(const TilePlan& P, float s2, const float* Vp, int ldh, int ncols, float* part, int pcols,
+static void launch_f32(const TilePlan& P, float s2, const float* Vp, int ncp, int ncols, float* part, int pcols,
                        int c0, CgGate gate, hipStream_t stream) {
-  hipLaunchKernelGGL((mvm_f32_kernel<CB>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vp, ldh, ncols, part,
+  hipLaunchKernelGGL((mvm_f32_kernel<CB>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vp, ncp, ncols, part,
                      pcols, c0, gate);
 }
 
@@ -522,10 +523,10 @@ int mfma_prep_rhs(const TilePlan& P, const ProdBufs& b, int prec, int nrhs, cons
     hipLaunchKernelGGL(colmax_kernel, dim3(kColmaxBlocks, nrhs), dim3(256), 0, stream, n, V, ldv, b.colmax, gate);
     GPL_LAUNCH_CHECK();
     hipLaunchKernelGGL(split_rhs_kernel, dim3(cdiv(b.ldh, 256), b.ncp), dim3(256), 0, stream, n, nrhs, V, ldv, P.perm,
-                       b.colmax, b.Vh, b.Vl, b.ldh, b.inv_scale, gate);
+                       b.colmax, b.Vh, b.Vl, b.ldh, b.ncp, b.inv_scale, gate);
   } else {
     hipLaunchKernelGGL(pack_rhs_kernel, dim3(cdiv(b.ldh, 256), b.ncp), dim3(256), 0, stream, n, nrhs, V, ldv, P.perm,
-                       b.Vp, b.ldh, gate);
+                       b.Vp, b.ldh, b.ncp, gate);
   }
   GPL_LAUNCH_CHECK();
   return GPL_OK;
@@ -540,21 +541,22 @@ int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float
     const int ncols = std::min(nrhs - c0, cb * 16);
     hipEvent_t t0 = timing_begin(stream);
     if (f16) {
-      const _Float16* vh = b.Vh + (size_t)c0 * b.ldh;
-      const _Float16* vl = b.Vl + (size_t)c0 * b.ldh;
+      // columns c0.. of each chunk (rhs_at layout)
+      const _Float16* vh = b.Vh + (size_t)c0 * kChunk;
+      const _Float16* vl = b.Vl + (size_t)c0 * kChunk;
       switch (cb) {
-        case 4: launch_f16x3<4>(P, s2, vh, vl, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 3: launch_f16x3<3>(P, s2, vh, vl, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 2: launch_f16x3<2>(P, s2, vh, vl, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
-        default: launch_f16x3<1>(P, s2, vh, vl, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 4: launch_f16x3<4>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 3: launch_f16x3<3>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 2: launch_f16x3<2>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        default: launch_f16x3<1>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
       }
     } else {
-      const float* vp = b.Vp + (size_t)c0 * b.ldh;
+      const float* vp = b.Vp + (size_t)c0 * kChunk;
       switch (cb) {
-        case 4: launch_f32<4>(P, s2, vp, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 3: launch_f32<3>(P, s2, vp, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 2: launch_f32<2>(P, s2, vp, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
-        default: launch_f32<1>(P, s2, vp, b.ldh, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 4: launch_f32<4>(P, s2, vp, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 3: launch_f32<3>(P, s2, vp, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 2: launch_f32<2>(P, s2, vp, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        default: launch_f32<1>(P, s2, vp, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
       }
     }
     GPL_LAUNCH_CHECK();
@@ -579,14 +581,14 @@ __global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
   const int w = (blockIdx.x - B.off[s]) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (S.prec == GPL_PREC_F16X3) {
     if (S.nrhs > 16)
-      mvm_f16x3_wave<2>(w, S.plan, S.s2, S.Vh, S.Vl, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f16x3_wave<2>(w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
     else
-      mvm_f16x3_wave<1>(w, S.plan, S.s2, S.Vh, S.Vl, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f16x3_wave<1>(w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
   } else {
     if (S.nrhs > 16)
-      mvm_f32_wave<2>(w, S.plan, S.s2, S.Vp, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f32_wave<2>(w, S.plan, S.s2, S.Vp, S.ncp, S.nrhs, S.part, S.nrhs, 0);
     else
-      mvm_f32_wave<1>(w, S.plan, S.s2, S.Vp, S.ldh, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f32_wave<1>(w, S.plan, S.s2, S.Vp, S.ncp, S.nrhs, S.part, S.nrhs, 0);
   }
 }
 

@@ -371,7 +371,7 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int 
   // one instantiation of the tile (its LDS buffers) for both forms
   psf_adjoint_tile<true>(skip, tile, c, n, ss, taps, in, ld_in, fold_scale, [&](int fy, int fx, float v, int z) {
     const float scale = f16 ? s_scale : 1.f;
-    const size_t j = (size_t)c * o.ldh + (z >= 0 ? base + z : zorder_rank(fx, fy, M));
+    const size_t j = rhs_at(c, z >= 0 ? base + z : zorder_rank(fx, fy, M), o.ncp);
     if (f16) {
       const float sv = v * scale;
       const _Float16 h = (_Float16)sv;
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void psf_adjoint_grouped_kernel(SlotBatch B, i
   const ServeSlotDev& S = *B.slot[s];
   const int local = blockIdx.x - B.off[s];
   const int tile = local % S.ntiles_adj, c = local / S.ntiles_adj;
-  const RhsOut o{S.prec, S.ldh, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd};
+  const RhsOut o{S.prec, S.ncp, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd};
   psf_adjoint_rhs_body([&] { return S.n_active[p] == 0 || S.st[p][c].active == 0; }, tile, c, S.n, S.ss, S.taps, S.P, S.ldv, o);
 }
 

@@ -69,6 +69,14 @@ __host__ __device__ inline int plan_waves(int n) {
 }
 __host__ __device__ inline int plan_slots(int n) { return plan_waves(n) + (n + kRowTile - 1) / kRowTile; }
 
+// Position of entry (column c, sorted point j) in a right-hand-side buffer of ncp
+// columns: chunk-major, each chunk's columns of 32 consecutive points together,
+// so that the 16 columns of a column block of one chunk are 1 KB (FP16) or 2 KB
+// (FP32) of contiguous memory.
+__host__ __device__ inline size_t rhs_at(int c, int j, int ncp) {
+  return ((size_t)(j >> 5) * ncp + c) * kChunk + (j & (kChunk - 1));
+}
+
 // Bytes of the plan buffers for n points (0 for n <= 0).
 size_t plan_workspace(int n);
 // Carve the plan buffers (nullptr fields when the carver overflows).
