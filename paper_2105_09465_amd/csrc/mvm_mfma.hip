@@ -40,12 +40,12 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kRT = 4;                      // 16-row MFMA tiles per wave
+constexpr int kRT = kSubsPerTile;           // 16-row MFMA tiles per wave
 constexpr int kWaves = 4;                   // independent waves per workgroup
 constexpr float kKScale = 2048.f;           // 2^11 applied to the FP16 exp tile
 static constexpr int kMaxCB = 4;            // up to 64 columns per pass
 
-static_assert(kRT * 16 == kRowTile, "row tile is four MFMA tiles");
+static_assert(kRT * 16 == kRowTile, "row tile of 16-row MFMA tiles");
 
 // ---------------------------------------------------------------- RHS preparation
 

@@ -82,11 +82,15 @@ __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const 
   const int r = blockIdx.x;
   if (r >= nrt) return;
   const int lane = threadIdx.x;
-  float4 sb[4];
+  float4 sb[kSubsPerTile];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) sb[t] = sbox[4 * r + t];
-  const float4 a = cbox[2 * r], b = cbox[2 * r + 1];
-  const float4 rb = make_float4(fminf(a.x, b.x), fmaxf(a.y, b.y), fminf(a.z, b.z), fmaxf(a.w, b.w));
+  for (int t = 0; t < kSubsPerTile; ++t) sb[t] = sbox[kSubsPerTile * r + t];
+  float4 rb = cbox[kChunksPerTile * r];
+#pragma unroll
+  for (int t = 1; t < kChunksPerTile; ++t) {
+    const float4 c = cbox[kChunksPerTile * r + t];
+    rb = make_float4(fminf(rb.x, c.x), fmaxf(rb.y, c.y), fminf(rb.z, c.z), fmaxf(rb.w, c.w));
+  }
   uint32_t* out = list + (size_t)r * nch;
   int base = 0;
   for (int c0 = 0; c0 < nch; c0 += 64) {
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const 
       const float4 q = cbox[c];
       if (boxes_live(rb, q, s2, threshold)) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) mask |= (boxes_live(sb[t], q, s2, threshold) ? 1u : 0u) << t;
+        for (int t = 0; t < kSubsPerTile; ++t) mask |= (boxes_live(sb[t], q, s2, threshold) ? 1u : 0u) << t;
       }
     }
     const bool live = mask != 0u;

@@ -22,6 +22,8 @@ namespace gpl {
 constexpr int kRowTile = 64;     // rows per wave (four 16-row MFMA tiles)
 constexpr int kSubTile = 16;     // rows of one MFMA tile
 constexpr int kChunk = 32;       // source points per chunk
+constexpr int kSubsPerTile = kRowTile / kSubTile;
+constexpr int kChunksPerTile = kRowTile / kChunk;
 constexpr int kMaxPlanWaves = 3072;    // waves of one product launch (3 per SIMD)
 constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
 
@@ -45,13 +47,13 @@ __host__ __device__ inline unsigned entry_mask(uint32_t e) { return e >> 16; }
 struct TilePlan {
   int n;     // points
   int nrt;   // row tiles = ceil(n / 64)
-  int nch;   // chunks = 2 nrt
+  int nch;   // chunks = 2 nrt (kChunksPerTile nrt)
   int npad;  // 64 nrt
   int nw;    // waves of a product launch (multiple of 4)
   const int* perm;  // sorted position -> caller index; nullptr = identity
   float *xs, *ys;   // [npad] points in sorted order, zero padded
   float4* cbox;     // [nch] (xmin, xmax, ymin, ymax); empty chunks have xmin = +inf
-  float4* sbox;     // [4 nrt] the same for every 16-point subtile
+  float4* sbox;     // [kSubsPerTile nrt] the same for every 16-point subtile
   int* count;       // [nrt] live chunks of each row tile
   uint32_t* list;   // [nrt][nch] entries of the live chunks of each row tile, ascending
   int* unit_off;    // [nrt] first unit of each row tile (exclusive prefix of count)
@@ -84,14 +86,14 @@ template <class C>
 void plan_carve(C& cv, int n, TilePlan& p) {
   p.n = n;
   p.nrt = cdiv(n, kRowTile);
-  p.nch = 2 * p.nrt;
+  p.nch = kChunksPerTile * p.nrt;
   p.npad = p.nrt * kRowTile;
   p.nw = plan_waves(n);
   p.perm = cv.template take<int>((size_t)p.npad);
   p.xs = cv.template take<float>((size_t)p.npad);
   p.ys = cv.template take<float>((size_t)p.npad);
   p.cbox = cv.template take<float4>((size_t)p.nch);
-  p.sbox = cv.template take<float4>((size_t)p.nrt * 4);
+  p.sbox = cv.template take<float4>((size_t)p.nrt * kSubsPerTile);
   p.count = cv.template take<int>((size_t)p.nrt);
   p.list = cv.template take<uint32_t>((size_t)p.nrt * p.nch);
   p.unit_off = cv.template take<int>((size_t)p.nrt);
