@@ -7,9 +7,14 @@
 
 namespace gpl {
 
+// PSF taps on the fine grid and the composite filter of the PSF followed by the
+// ss x ss block sum: g[t + r] = sum_{s < ss} w[s - t] for t in [-r, ss - 1 + r]
+// (L = 2 r + ss entries; w taken as zero outside [-r, r]).
+constexpr int kMaxComposite = 2 * GPL_PSF_MAX_RADIUS + 32;
 struct Taps {
-  int r;
+  int r, L;
   float w[2 * GPL_PSF_MAX_RADIUS + 1];
+  float g[kMaxComposite];
 };
 
 // Early-exit gate used inside the CG loop: a kernel returns at once when no

@@ -2,11 +2,17 @@
 // image pixels) and its adjoint B^T = P^T D^T (Sec. 2 and Sec. 3.3 footnote on a
 // PSF as deterministic post-processing of the fluxes; Sec. 4.1 local averaging).
 //
-// One workgroup per (tile, column). The fine window of the tile plus the PSF
-// halo is staged in LDS, convolved along x into a second LDS buffer, then along
-// y; the forward direction averages each ss x ss block on the fly, the adjoint
-// generates D^T x while loading the window. The taps are a normalised 1-D
-// Gaussian (outer product in 2-D), computed on the host in FP64.
+// Both are applied through the composite 1-D filter g of the PSF taps and the
+// ss-point block sum (Taps::g): per axis, B maps fine index f to pixel I with
+// weight g(f - ss I) / ss, and B^T maps pixel I back to f with the same weight,
+// so B is a separable strided convolution with 2r + ss taps and B^T a polyphase
+// one with at most ceil((2r + ss) / ss) taps per output. This is the same linear
+// map as the PSF followed by the block mean; only the FP32 rounding order
+// differs. One workgroup per (tile, column): the input window of the tile (fine
+// values for B, pixel values for B^T) is staged in LDS, filtered along x into a
+// second LDS buffer, then along y. The taps are a normalised 1-D Gaussian,
+// computed on the host in FP64.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -21,6 +27,28 @@ constexpr int kMaxWin = kFineTile + 2 * GPL_PSF_MAX_RADIUS;
 // pixel block a wave reads in the Z-order walk falls on distinct LDS banks.
 constexpr int kAdjStride = 40;
 constexpr int kOutPer = kFineTile * kFineTile / 256;  // output pixels per thread of a forward tile
+
+// Dynamic LDS of the tiles (floats), sized for the PSF radius r and the
+// supersampling ss of the launch.
+__host__ __device__ inline int fwd_tile_dims(int r, int ss, int& TP, int& W) {
+  TP = kFineTile / ss > 0 ? kFineTile / ss : 1;
+  W = TP * ss + 2 * r;
+  return W * W + W * (TP + 1) + 2 * r + ss;
+}
+__host__ __device__ inline int adj_tile_dims(int r, int ss, int& WC, int& K) {
+  const int L = 2 * r + ss;
+  WC = (kFineTile + 2 * r + ss - 2) / ss + 1;
+  K = (L - 1) / ss + 1;
+  return WC * WC + (WC + K - 1) * kAdjStride + ss + L;
+}
+__host__ __device__ inline size_t fwd_lds_bytes(int r, int ss) {
+  int a, b;
+  return sizeof(float) * (size_t)fwd_tile_dims(r, ss, a, b);
+}
+__host__ __device__ inline size_t adj_lds_bytes(int r, int ss) {
+  int a, b;
+  return sizeof(float) * (size_t)adj_tile_dims(r, ss, a, b);
+}
 
 // A W x W window (W <= kMaxWin) staged into LDS through registers: thread
 // (lx, ly) of the 32 x 8 workgroup holds rows ly + 8k and columns lx + 32m, and
@@ -67,14 +95,31 @@ __device__ __forceinline__ void win_store(const WinRegs& R, int W, float* S) {
       }
 }
 
+// g[t + r] = sum_{s < ss} w[s - t] / sum for t in [-r, ss - 1 + r], in FP64.
+static void composite_taps(int ss, int r, const double* w, double sum, Taps& t) {
+  t.L = 2 * r + ss;
+  for (int k = 0; k < t.L; ++k) {
+    const int tt = k - r;
+    double a = 0.0;
+    for (int s = 0; s < ss; ++s) {
+      const int j = s - tt;
+      if (j >= -r && j <= r) a += w[j + r];
+    }
+    t.g[k] = (float)(a / sum);
+  }
+}
+
 int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
   GPL_REQUIRE(psf != nullptr, "psf is NULL");
   GPL_REQUIRE(psf->fwhm >= 0 && std::isfinite(psf->fwhm), "psf fwhm must be >= 0");
   GPL_REQUIRE(psf->radius >= 0 && psf->radius <= GPL_PSF_MAX_RADIUS, "psf radius must be in [0, %d]",
               GPL_PSF_MAX_RADIUS);
+  GPL_REQUIRE(g->ss >= 1 && g->ss <= kFineTile, "ss=%d outside [1, %d]", g->ss, kFineTile);
   if (psf->fwhm == 0.0) {
+    const double one[1] = {1.0};
     t.r = 0;
     t.w[0] = 1.f;
+    composite_taps(g->ss, 0, one, 1.0, t);
     return GPL_OK;
   }
   const double h = g->pix_scale / g->ss;
@@ -90,6 +135,7 @@ int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
   }
   t.r = r;
   for (int k = 0; k < 2 * r + 1; ++k) t.w[k] = (float)(w[k] / sum);
+  composite_taps(g->ss, r, w, sum, t);
   return GPL_OK;
 }
 
@@ -99,35 +145,27 @@ int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
 // split into separately waited blocks.
 __device__ __forceinline__ int div_ss(int v, float rss) { return (int)(((float)v + 0.5f) * rss); }
 
-// x-convolution of the staged window, S2[wy * LS + x] = sum_b w_b S1[wy * W + x + r + SGN b]
-// for wy < W, x < F <= 32 (SGN = -1: convolution, +1: correlation). Thread
-// (lx, ly) takes column lx and rows ly + 8k, three rows at a time so that three
-// independent FMA chains share each tap (a row past the window reads the last
-// row and is not stored).
-template <int SGN>
-__device__ __forceinline__ void conv_x(const float* S1, float* S2, const float* tw, int W, int F, int LS, int r) {
-  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
-  if (lx >= F) return;
-  const int nk = (W + 7) / 8;
-#pragma unroll 1
-  for (int k0 = 0; k0 < nk; k0 += 3) {
-    int wy[3];
-    const float* row[3];
-    float acc[3] = {0.f, 0.f, 0.f};
+// Floor and ceiling of a / b for b > 0 and any sign of a.
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+__device__ __forceinline__ int ceil_div(int a, int b) { return -floor_div(-a, b); }
+
+// Forward y pass for this thread's NU pixels o = tid + 256 u (a pixel past the
+// tile repeats the last one and is not used).
+template <int NU>
+__device__ __forceinline__ void forward_ypass(const float* S2, const float* tg, int L, int LS, int ss, int TP,
+                                              float (&acc)[kOutPer]) {
+  const float* col[NU];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      wy[i] = ly + 8 * (k0 + i);
-      row[i] = S1 + min(wy[i], W - 1) * W + lx + r;
-    }
+  for (int u = 0; u < NU; ++u) {
+    const int o = min((int)threadIdx.x + u * 256, TP * TP - 1);
+    const int oy = o / TP, ox = o - oy * TP;
+    col[u] = S2 + ss * oy * LS + ox;
+  }
 #pragma unroll 2
-    for (int b = -r; b <= r; ++b) {
-      const float w = tw[b + r];
+  for (int k = 0; k < L; ++k) {
+    const float w = tg[k];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) acc[i] = fmaf(w, row[i][SGN * b], acc[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      if (wy[i] < W) S2[wy[i] * LS + lx] = acc[i];
+    for (int u = 0; u < NU; ++u) acc[u] = fmaf(w, col[u][k * LS], acc[u]);
   }
 }
 
@@ -141,13 +179,15 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
                                                  int ld_out, float alpha, float beta, const float* __restrict__ extra,
                                                  int ld_extra, float gamma, const float* __restrict__ dotv,
                                                  int ld_dotv, double* __restrict__ partial, int ntiles) {
-  __shared__ float S1[kMaxWin * kMaxWin];
-  __shared__ float S2[kMaxWin * (kFineTile + 1)];
-  __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
+  extern __shared__ float psf_lds[];
   __shared__ double red[4];
-  const int M = n * ss, r = taps.r;
-  const int TP = kFineTile / ss > 0 ? kFineTile / ss : 1;  // output pixels per tile side
-  const int F = TP * ss, W = F + 2 * r, LS = F + 1;
+  const int M = n * ss, r = taps.r, L = taps.L;
+  int TP, W;  // output pixels per tile side, window side
+  fwd_tile_dims(r, ss, TP, W);
+  const int F = TP * ss, LS = TP + 1;
+  float* const S1 = psf_lds;           // [W][W] fine window
+  float* const S2 = S1 + W * W;        // [W][LS] filtered along x
+  float* const tg = S2 + W * LS;       // [L] composite taps
   const int tiles_x = (n + TP - 1) / TP;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
@@ -181,47 +221,44 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
       return src[(size_t)clamp_idx(fy, M) * M + clamp_idx(fx, M)];
     });
     if (skip()) return;
-    if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
+    if ((int)threadIdx.x < L) tg[threadIdx.x] = taps.g[threadIdx.x];
     win_store(R, W, S1);
   }
   __syncthreads();
-  conv_x<-1>(S1, S2, tw, W, F, LS, r);
-  __syncthreads();
-  // y-convolution of this thread's fine points, four independent chains at a
-  // time: chain q is fine point q % ss^2 of output u = q / ss^2.
-  const int ss2 = ss * ss;
-  const float inv_ss2 = 1.f / (float)ss2;
-  float acc[kOutPer] = {};
-  int nq = 0;
+  // x: S2[wy][ox] = sum_t g(t) S1[wy][ss ox + t + r], window rows wy < W, pixel
+  // columns ox < TP; three rows at a time share each tap
+  for (int o0 = threadIdx.x; o0 < W * TP; o0 += 3 * 256) {
+    int at[3];
+    float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-  for (int u = 0; u < kOutPer; ++u) nq += I[u] >= 0 ? ss2 : 0;  // outputs of a thread come first
-#pragma unroll 1
-  for (int q0 = 0; q0 < nq; q0 += 4) {
-    const float* col[4];
-    int uq[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = min(q0 + i, nq - 1);
-      const int u = q / ss2, f = q - u * ss2;
-      const int sy = f / ss, sx = f - sy * ss;
-      const int o = threadIdx.x + u * 256;
-      const int oy = o / TP, ox = o - oy * TP;
-      col[i] = S2 + (oy * ss + sy + r) * LS + ox * ss + sx;
-      uq[i] = q0 + i < nq ? u : -1;
+    for (int i = 0; i < 3; ++i) {
+      const int o = min(o0 + 256 * i, W * TP - 1);
+      const int wy = o / TP, ox = o - wy * TP;
+      at[i] = wy * W + ss * ox;
     }
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-    for (int a = -r; a <= r; ++a) {
-      const float w = tw[a + r];
+    for (int k = 0; k < L; ++k) {
+      const float w = tg[k];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = fmaf(w, col[i][-a * LS], v[i]);
+      for (int i = 0; i < 3; ++i) acc[i] = fmaf(w, S1[at[i] + k], acc[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int u = 0; u < kOutPer; ++u)
-        if (uq[i] == u) acc[u] += v[i];
+    for (int i = 0; i < 3; ++i) {
+      const int o = o0 + 256 * i;
+      if (o < W * TP) {
+        const int wy = o / TP, ox = o - wy * TP;
+        S2[wy * LS + ox] = acc[i];
+      }
+    }
   }
+  __syncthreads();
+  // y: pixel (oy, ox) = sum_t g(t) S2[ss oy + t + r][ox] / ss^2
+  const float inv_ss2 = 1.f / (float)(ss * ss);
+  float acc[kOutPer] = {};
+  if (TP * TP > 256)
+    forward_ypass<kOutPer>(S2, tg, L, LS, ss, TP, acc);
+  else
+    forward_ypass<1>(S2, tg, L, LS, ss, TP, acc);
   double dot = 0.0;
 #pragma unroll
   for (int u = 0; u < kOutPer; ++u) {
@@ -255,40 +292,71 @@ __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps ta
 template <bool ZWALK, class Skip, class Pre, class Store>
 __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
                                                  const float* __restrict__ in, int ld_in, Pre&& pre, Store&& store) {
-  __shared__ float S1[kMaxWin * kMaxWin];
-  __shared__ float S2[kMaxWin * kAdjStride];
-  __shared__ float tw[2 * GPL_PSF_MAX_RADIUS + 1];
-  const int M = n * ss, r = taps.r;
+  extern __shared__ float psf_lds[];
+  const int M = n * ss, r = taps.r, L = taps.L;
+  int WC, K;  // window side in pixels; pixels that reach one fine point along an axis
+  adj_tile_dims(r, ss, WC, K);
   static_assert(kFineTile == 32, "the Z-order decode below takes 5 bits per axis");
-  const int F = kFineTile, W = F + 2 * r, LS = kAdjStride;
+  const int F = kFineTile, LS = kAdjStride;
+  float* const S1 = psf_lds;                 // [WC][WC] pixel window
+  float* const S2 = S1 + WC * WC;            // [WC + K - 1][LS] filtered along x, zero rows at the end
+  float* const tz = S2 + (WC + K - 1) * LS;  // [ss + L]: ss zeros, then g
   const int tiles_x = (M + F - 1) / F;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
+  // pixels whose composite filter reaches the tile: from ceil((f0 - ss + 1 - r) / ss) on, WC of them
+  const int cy0 = ceil_div(fy0 - ss + 1 - r, ss), cx0 = ceil_div(fx0 - ss + 1 - r, ss);
   const float* src = in + (size_t)c * ld_in;
-  const float inv_ss2 = 1.f / (float)(ss * ss), rss = 1.f / (float)ss;
+  const float inv_ss2 = 1.f / (float)(ss * ss);
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
   {
     WinRegs R;
-    win_load(R, W, [&](int wy, int wx, bool& ok) {
-      const int fy = fy0 - r + wy, fx = fx0 - r + wx;
-      ok = wy < W && wx < W && fy >= 0 && fy < M && fx >= 0 && fx < M;
-      // the 1 / ss^2 of D^T is applied to the convolved value
-      return src[(size_t)div_ss(clamp_idx(fy, M), rss) * n + div_ss(clamp_idx(fx, M), rss)];
+    win_load(R, WC, [&](int wy, int wx, bool& ok) {
+      const int iy = cy0 + wy, ix = cx0 + wx;
+      ok = wy < WC && wx < WC && iy >= 0 && iy < n && ix >= 0 && ix < n;
+      return src[(size_t)clamp_idx(iy, n) * n + clamp_idx(ix, n)];
     });
     if (skip()) return;
-    if ((int)threadIdx.x <= 2 * r) tw[threadIdx.x] = taps.w[threadIdx.x];
+    if ((int)threadIdx.x < ss + L) tz[threadIdx.x] = (int)threadIdx.x < ss ? 0.f : taps.g[threadIdx.x - ss];
+    for (int i = threadIdx.x; i < (K - 1) * LS; i += 256) S2[WC * LS + i] = 0.f;
     pre();  // runs while the window loads are in flight
-    win_store(R, W, S1);
+    win_store(R, WC, S1);
   }
   __syncthreads();
-  conv_x<1>(S1, S2, tw, W, F, LS, r);
+  // x: S2[wy][x] = sum_k g(t0 - ss k) S1[wy][jlo + k], the pixels jlo.. that reach
+  // fine column fx0 + x (weights past the last one are the zeros in front of g)
+  {
+    const int fx = fx0 + lx;
+    const int jlo = ceil_div(fx - ss + 1 - r, ss) - cx0;
+    const int b0 = ss + (fx - ss * (cx0 + jlo)) + r;  // tz index of k = 0
+    const int nk = (WC + 7) / 8;
+#pragma unroll 1
+    for (int k0 = 0; k0 < nk; k0 += 3) {
+      int wy[3];
+      float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) wy[i] = min(ly + 8 * (k0 + i), WC - 1);
+#pragma unroll 2
+      for (int k = 0; k < K; ++k) {
+        const float w = tz[b0 - ss * k];
+        const int j = min(jlo + k, WC - 1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[i] = fmaf(w, S1[wy[i] * WC + j], acc[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int row = ly + 8 * (k0 + i);
+        if (row < WC) S2[row * LS + lx] = acc[i];
+      }
+    }
+  }
   __syncthreads();
-  // A tile fully inside the grid holds consecutive Z-order ranks (it is an
-  // aligned power-of-two square): z is the point's Z-order index in the tile.
-  // Each thread takes the points o = tid + 256 u, u < 4, as four chains.
+  // y, for the points o = tid + 256 u, u < 4 (four chains). A tile fully inside
+  // the grid holds consecutive Z-order ranks (it is an aligned power-of-two
+  // square): there z is the point's Z-order index in the tile.
   const bool zwalk = ZWALK && fy0 + F <= M && fx0 + F <= M;
   constexpr int kPer = kFineTile * kFineTile / 256;
-  int px[kPer], py[kPer];
+  int px[kPer], py[kPer], b0[kPer];
   const float* col[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -306,14 +374,16 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
     }
     px[u] = x;
     py[u] = y;
-    col[u] = S2 + (y + r) * LS + x;
+    const int fy = fy0 + y;
+    const int ilo = ceil_div(fy - ss + 1 - r, ss) - cy0;
+    b0[u] = ss + (fy - ss * (cy0 + ilo)) + r;
+    col[u] = S2 + ilo * LS + x;
   }
   float v[kPer] = {};
 #pragma unroll 2
-  for (int a = -r; a <= r; ++a) {
-    const float w = tw[a + r];
+  for (int k = 0; k < K; ++k) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) v[u] = fmaf(w, col[u][a * LS], v[u]);
+    for (int u = 0; u < kPer; ++u) v[u] = fmaf(tz[b0[u] - ss * k], col[u][k * LS], v[u]);
   }
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -423,16 +493,18 @@ int psf_adjoint_tiles(int n, int ss) {
 
 static int grouped_launch(void (*kern)(SlotBatch, int), const ServeSlotDev* const* hslots,
                           const ServeSlotDev* const* dslots, int nslots, int p, int (*tiles_of)(const ServeSlotDev&),
-                          hipStream_t stream) {
+                          size_t (*lds_of)(int, int), hipStream_t stream) {
   SlotBatch B;
   B.nslots = nslots;
   B.off[0] = 0;
+  size_t lds = 0;
   for (int s = 0; s < nslots; ++s) {
     B.slot[s] = dslots[s];
     B.off[s + 1] = B.off[s] + tiles_of(*hslots[s]);
+    lds = std::max(lds, lds_of(hslots[s]->taps.r, hslots[s]->ss));
   }
   if (B.off[nslots] == 0) return GPL_OK;
-  hipLaunchKernelGGL(kern, dim3(B.off[nslots]), dim3(256), 0, stream, B, p);
+  hipLaunchKernelGGL(kern, dim3(B.off[nslots]), dim3(256), lds, stream, B, p);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
@@ -440,13 +512,13 @@ static int grouped_launch(void (*kern)(SlotBatch, int), const ServeSlotDev* cons
 int psf_adjoint_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
                         hipStream_t stream) {
   return grouped_launch(psf_adjoint_grouped_kernel, hslots, dslots, nslots, p,
-                        [](const ServeSlotDev& S) { return S.ntiles_adj * S.nrhs; }, stream);
+                        [](const ServeSlotDev& S) { return S.ntiles_adj * S.nrhs; }, adj_lds_bytes, stream);
 }
 
 int psf_forward_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* const* dslots, int nslots, int p,
                         hipStream_t stream) {
   return grouped_launch(psf_forward_grouped_kernel, hslots, dslots, nslots, p,
-                        [](const ServeSlotDev& S) { return S.ntiles_fwd * S.nrhs; }, stream);
+                        [](const ServeSlotDev& S) { return S.ntiles_fwd * S.nrhs; }, fwd_lds_bytes, stream);
 }
 
 // Grid limits of the PSF tiles: ss <= kFineTile and a fine side below 2^15 (the
@@ -468,7 +540,8 @@ int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* i
                        int ld_dotv, double* partial, CgGate gate, hipStream_t stream) {
   GPL_TRY(check_psf_grid(n, ss));
   const int ntiles = psf_forward_tiles(n, ss);
-  hipLaunchKernelGGL(psf_forward_kernel, dim3(ntiles, nrhs), dim3(256), 0, stream, n, ss, taps, in, ld_in, out,
+  hipLaunchKernelGGL(psf_forward_kernel, dim3(ntiles, nrhs), dim3(256), fwd_lds_bytes(taps.r, ss), stream, n, ss, taps,
+                     in, ld_in, out,
                      ld_out, alpha, beta, extra, ld_extra, gamma, dotv, ld_dotv, partial, ntiles, gate);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
@@ -478,7 +551,8 @@ int psf_adjoint_rhs_launch(int n, int ss, const Taps& taps, int nrhs, const floa
                            CgGate gate, hipStream_t stream) {
   GPL_TRY(check_psf_grid(n, ss));
   const int M = n * ss, t = (M + kFineTile - 1) / kFineTile;
-  hipLaunchKernelGGL(psf_adjoint_rhs_kernel, dim3(t * t, nrhs), dim3(256), 0, stream, n, ss, taps, P, ldp, out, gate);
+  hipLaunchKernelGGL(psf_adjoint_rhs_kernel, dim3(t * t, nrhs), dim3(256), adj_lds_bytes(taps.r, ss), stream, n, ss,
+                     taps, P, ldp, out, gate);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
@@ -487,7 +561,8 @@ int psf_adjoint_launch(int n, int ss, const Taps& taps, int nrhs, const float* i
                        float alpha, float beta, CgGate gate, hipStream_t stream) {
   GPL_TRY(check_psf_grid(n, ss));
   const int M = n * ss, t = (M + kFineTile - 1) / kFineTile;
-  hipLaunchKernelGGL(psf_adjoint_kernel, dim3(t * t, nrhs), dim3(256), 0, stream, n, ss, taps, in, ld_in, out, ld_out,
+  hipLaunchKernelGGL(psf_adjoint_kernel, dim3(t * t, nrhs), dim3(256), adj_lds_bytes(taps.r, ss), stream, n, ss, taps,
+                     in, ld_in, out, ld_out,
                      alpha, beta, gate);
   GPL_LAUNCH_CHECK();
   return GPL_OK;

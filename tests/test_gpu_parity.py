@@ -133,7 +133,8 @@ def test_sersic_parity(G):
 
 # ------------------------------------------------------------------ a4 observation operator
 
-@pytest.mark.parametrize("n,ss,fwhm", [(24, 1, 0.1), (37, 2, 0.1), (20, 3, 0.1), (33, 2, 0.0), (50, 1, 0.3)])
+@pytest.mark.parametrize("n,ss,fwhm", [(24, 1, 0.1), (37, 2, 0.1), (20, 3, 0.1), (33, 2, 0.0), (50, 1, 0.3),
+                                       (9, 4, 0.12), (13, 5, 0.05)])
 def test_psf_conv_parity_and_adjoint(G, n, ss, fwhm):
     _say("psf", n, ss, fwhm)
     rng = np.random.default_rng(n * 10 + ss)
