@@ -130,24 +130,26 @@ def serving_requests(G, torch, synth, n_requests, rate_hz=1.0):
 
 
 def serve_section(G, torch, synth, n_requests):
-    """Poisson stream of reconstructions of uneven sizes (sides 48..160 px, 1x1 or
-    2x2 supersampling, lens and source from the priors, 16 probes each) through
-    the continuous-batching engine, for both arithmetic forms. The arrival rate is
-    0.8 x the plain FP32 capacity measured on the same requests."""
-    import numpy as np
-
+    """Reconstructions of uneven sizes (sides 48..160 px, 1x1 or 2x2
+    supersampling, lens and source from the priors, 16 probes each) through the
+    continuous-batching engine, for both arithmetic forms:
+    - capacity: every request available at once, reconstructions/s of the engine;
+    - stream: Poisson arrivals at 0.8 x the plain FP32 capacity, with p50/p99
+      latency from arrival to result."""
     reqs = serving_requests(G, torch, synth, n_requests)
     out = {"requests": n_requests, "hbm_budget_GiB": 8}
-    # capacity of the plain form with every request available at once
-    eng = G.serving.ServingEngine(prec="fp32", hbm_budget=8 << 30)
-    res = eng.run(reqs, realtime=False)
-    cap = len(res) / eng.stats["wall_s"]
-    rate = 0.8 * cap
+    for prec in ("fp32", "f16x3"):  # capacity: all present at the start, latency counted from there
+        eng = G.serving.ServingEngine(prec=prec, hbm_budget=8 << 30)
+        res = eng.run(reqs, realtime=False)
+        s = G.serving.summarize(res, eng.stats["wall_s"])
+        out[f"capacity_{prec}"] = {"reconstructions_per_s": s["reconstructions_per_s"], "wall_s": s["wall_s"],
+                                   "p50_latency_ms": s["p50_latency_ms"], "p99_latency_ms": s["p99_latency_ms"],
+                                   "max_active_slots": eng.stats["max_active"]}
+    rate = 0.8 * out["capacity_fp32"]["reconstructions_per_s"]
     trace = synth.serving_trace(n_requests, rate)
     for r, (t, _, _, _) in zip(reqs, trace):
         r.arrival = t
     out["arrival_rate_per_s"] = rate
-    out["plain_fp32_capacity_per_s"] = cap
     for prec in ("fp32", "f16x3"):
         eng = G.serving.ServingEngine(prec=prec, hbm_budget=8 << 30)
         res = eng.run(reqs, realtime=True)
@@ -155,6 +157,8 @@ def serve_section(G, torch, synth, n_requests):
         s.update(max_active_slots=eng.stats["max_active"], rounds=eng.stats["rounds"],
                  nonconverged=int(sum(any(st != 0 for st in r.status) for r in res)))
         out[prec] = s
+    out["capacity_ratio_f16x3_vs_fp32"] = (out["capacity_f16x3"]["reconstructions_per_s"] /
+                                           out["capacity_fp32"]["reconstructions_per_s"])
     return out
 
 
@@ -197,7 +201,7 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="run only the dominant kernel this many times at the bench shape, then a 1 GiB copy "
                          "(calibration of the HBM byte counters), and exit; for rocprofv3 counter runs")
-    ap.add_argument("--serve-requests", type=int, default=24,
+    ap.add_argument("--serve-requests", type=int, default=128,
                     help="requests in the serving trace (0: skip; the full trace has 512)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -175,7 +175,8 @@ class ServingEngine:
                 tnow = time.perf_counter() - t0
                 for s, (out, iters, relres, status, image) in done:
                     o = out.cpu().tolist()
-                    results.append(Result(s.req.rid, s.req.arrival, s.t_admit, tnow, o[0], o[1], o[2], o[3], o[4],
+                    arrival = s.req.arrival if realtime else 0.0
+                    results.append(Result(s.req.rid, arrival, s.t_admit, tnow, o[0], o[1], o[2], o[3], o[4],
                                           iters.cpu().tolist(), relres.cpu().tolist(), status.cpu().tolist(), image))
                     used -= s.footprint
             active = keep
