@@ -124,22 +124,6 @@ __global__ void pack_rhs_kernel(int n, int nrhs, const float* __restrict__ V, in
 
 // ---------------------------------------------------------------- work of one wave
 
-// The units [u0, u1) of wave w (row-tile order), and the first row tile and
-// partial slot they map to.
-struct WaveRange {
-  int u0, u1, r, slot;
-};
-
-__device__ __forceinline__ WaveRange wave_range(int w, const TilePlan& P) {
-  const int T = *P.total;
-  WaveRange wr;
-  wr.u0 = wave_unit(w, T, P.nw);
-  wr.u1 = wave_unit(w + 1, T, P.nw);
-  wr.r = P.wrow[w];
-  wr.slot = P.wslot[w];
-  return wr;
-}
-
 // Partial rows of one row tile from one wave: part[(slot * pcols + c0 + c) * 64 + row]
 // for c < ncols (MFMA D layout: column = lane % 16, rows 4 * (lane / 16) + v).
 template <int CB>
@@ -208,18 +192,20 @@ __device__ __forceinline__ void for_chunks_pf(const uint32_t* lst, int kb, int k
 
 // One wave's share of a product: for each row tile its units touch, load the
 // tile's 64 row coordinates, accumulate over the tile's chunks in the range, and
-// write the partial rows. `chunk_fn(acc, xi, yi, ch)` accumulates one chunk.
-template <int CB, class F>
+// write the partial rows. `chunk_fn(acc, xi, yi, lst, kb, ke, lane)` accumulates
+// list positions [kb, ke) of a row tile. The wave's range comes from one
+// descriptor load, issued together with the gate flag; `skip()` is evaluated
+// once both are in.
+template <int CB, class S, class F>
 __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __restrict__ part, int pcols, int c0,
-                                             int ncols, F&& chunk_fn) {
-  const WaveRange wr = wave_range(w, P);
-  if (wr.u0 >= wr.u1) return;
+                                             int ncols, S&& skip, F&& chunk_fn) {
+  const int4 d = P.wdesc[w];
+  int rest = P.wrest[w];
+  if (skip() || d.x < 0) return;
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
-  int u = wr.u0, r = wr.r, slot = wr.slot;
+  int r = d.x, slot = d.y, kb = d.z, ke = d.w;
 #pragma unroll 1
-  while (u < wr.u1) {
-    const int off = P.unit_off[r];
-    const int end = min(wr.u1, off + P.count[r]);
+  while (true) {
     float xi[kRT], yi[kRT];
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
@@ -232,11 +218,14 @@ __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __
     for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    chunk_fn(acc, xi, yi, P.list + (size_t)r * P.nch, u - off, end - off, lane);
+    chunk_fn(acc, xi, yi, P.list + (size_t)r * P.nch, kb, ke, lane);
     store_partial<CB>(acc, slot, part, pcols, c0, ncols, ri, g);
-    ++slot;
+    if (rest <= 0) break;
     ++r;
-    u = end;
+    ++slot;
+    kb = 0;
+    ke = min(rest, P.count[r]);
+    rest -= ke;
   }
 }
 
@@ -317,12 +306,12 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
   }
 }
 
-template <int CB>
-__device__ __forceinline__ void mvm_f16x3_wave(int w, const TilePlan& P, float s2, const _Float16* __restrict__ Vh,
+template <int CB, class Skip>
+__device__ __forceinline__ void mvm_f16x3_wave(Skip&& skip, int w, const TilePlan& P, float s2, const _Float16* __restrict__ Vh,
                                                const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
-  wave_product<CB>(w, P, part, pcols, c0, ncols,
+  wave_product<CB>(w, P, part, pcols, c0, ncols, skip,
                    [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
                      for_chunks_pf<F16Chunk<CB>>(lst, kb, ke, lane,
@@ -336,9 +325,8 @@ template <int CB>
 __global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, float s2, const _Float16* __restrict__ Vh,
                                                         const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                         float* __restrict__ part, int pcols, int c0, CgGate gate) {
-  if (gate.skip_all()) return;
   const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  mvm_f16x3_wave<CB>(w, P, s2, Vh, Vl, ncp, ncols, part, pcols, c0);
+  mvm_f16x3_wave<CB>([&] { return gate.skip_all(); }, w, P, s2, Vh, Vl, ncp, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- FP32 form
@@ -380,11 +368,11 @@ __device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&x
   }
 }
 
-template <int CB>
-__device__ __forceinline__ void mvm_f32_wave(int w, const TilePlan& P, float s2, const float* __restrict__ Vp,
+template <int CB, class Skip>
+__device__ __forceinline__ void mvm_f32_wave(Skip&& skip, int w, const TilePlan& P, float s2, const float* __restrict__ Vp,
                                              int ncp, int ncols, float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
-  wave_product<CB>(w, P, part, pcols, c0, ncols,
+  wave_product<CB>(w, P, part, pcols, c0, ncols, skip,
                    [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
                      for_chunks(lst, kb, ke, lane,
@@ -396,22 +384,26 @@ template <int CB>
 __global__ __launch_bounds__(256) void mvm_f32_kernel(const TilePlan P, float s2, const float* __restrict__ Vp,
                                                       int ncp, int ncols, float* __restrict__ part, int pcols, int c0,
                                                       CgGate gate) {
-  if (gate.skip_all()) return;
   const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  mvm_f32_wave<CB>(w, P, s2, Vp, ncp, ncols, part, pcols, c0);
+  mvm_f32_wave<CB>([&] { return gate.skip_all(); }, w, P, s2, Vp, ncp, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- reduction
 
 // Y[c][perm[j]] = (amp2 * colscale[c]) * sum_q part[s0 + q][c][row] + beta Y over the
 // partial slots [s0, s0 + cnt) of row tile r = j / 64, in wave order.
-__device__ __forceinline__ void reduce_body(int bx, int c, const TilePlan& P, int nrhs, const float* __restrict__ part,
-                                            int pcols, const float* __restrict__ colscale, float amp2, float* Y,
-                                            int ldy, float beta) {
+// `skip()` is evaluated once the slot range and the destination index are loaded.
+template <class Skip>
+__device__ __forceinline__ void reduce_body(Skip&& skip, int bx, int c, const TilePlan& P, int nrhs,
+                                            const float* __restrict__ part, int pcols,
+                                            const float* __restrict__ colscale, float amp2, float* Y, int ldy,
+                                            float beta) {
   const int j = bx * blockDim.x + threadIdx.x;
   if (j >= P.n || c >= nrhs) return;
   const int r = j / kRowTile, row = j - r * kRowTile;
   const int2 sl = P.rslot[r];
+  const int dst = P.perm ? P.perm[j] : j;
+  if (skip()) return;
   const float* p0 = part + ((size_t)sl.x * pcols + c) * kRowTile + row;
   const size_t stride = (size_t)pcols * kRowTile;
   // in slot order; the loads of each group of 8 are issued together
@@ -433,7 +425,7 @@ __device__ __forceinline__ void reduce_body(int bx, int c, const TilePlan& P, in
       if (q + u < sl.y) s += t[u];
   }
   const float f = colscale ? amp2 * colscale[c] : amp2;
-  float* y = Y + (size_t)c * ldy + (P.perm ? P.perm[j] : j);
+  float* y = Y + (size_t)c * ldy + dst;
   const float res = f * s;
   *y = beta != 0.f ? res + beta * *y : res;
 }
@@ -441,8 +433,8 @@ __device__ __forceinline__ void reduce_body(int bx, int c, const TilePlan& P, in
 __global__ void reduce_kernel(const TilePlan P, int nrhs, const float* __restrict__ part, int pcols,
                               const float* __restrict__ colscale, float amp2, float* Y, int ldy, float beta,
                               CgGate gate) {
-  if (gate.skip_all()) return;
-  reduce_body(blockIdx.x, blockIdx.y, P, nrhs, part, pcols, colscale, amp2, Y, ldy, beta);
+  reduce_body([&] { return gate.skip_all(); }, blockIdx.x, blockIdx.y, P, nrhs, part, pcols, colscale, amp2, Y, ldy,
+              beta);
 }
 
 // ---------------------------------------------------------------- workspace
@@ -577,28 +569,27 @@ int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float
 __global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
   const int s = B.find(blockIdx.x);
   const ServeSlotDev& S = *B.slot[s];
-  if (S.n_active[p] == 0) return;
   const int w = (blockIdx.x - B.off[s]) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  auto skip = [&] { return S.n_active[p] == 0; };
   if (S.prec == GPL_PREC_F16X3) {
     if (S.nrhs > 16)
-      mvm_f16x3_wave<2>(w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f16x3_wave<2>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
     else
-      mvm_f16x3_wave<1>(w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f16x3_wave<1>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
   } else {
     if (S.nrhs > 16)
-      mvm_f32_wave<2>(w, S.plan, S.s2, S.Vp, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f32_wave<2>(skip, w, S.plan, S.s2, S.Vp, S.ncp, S.nrhs, S.part, S.nrhs, 0);
     else
-      mvm_f32_wave<1>(w, S.plan, S.s2, S.Vp, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      mvm_f32_wave<1>(skip, w, S.plan, S.s2, S.Vp, S.ncp, S.nrhs, S.part, S.nrhs, 0);
   }
 }
 
 __global__ void reduce_grouped_kernel(SlotBatch B, int p) {
   const int s = B.find(blockIdx.x);
   const ServeSlotDev& S = *B.slot[s];
-  if (S.n_active[p] == 0) return;
   const int local = blockIdx.x - B.off[s];
   const int per = cdiv(S.N, 256);
-  reduce_body(local % per, local / per, S.plan, S.nrhs, S.part, S.nrhs,
+  reduce_body([&] { return S.n_active[p] == 0; }, local % per, local / per, S.plan, S.nrhs, S.part, S.nrhs,
               S.prec == GPL_PREC_F16X3 ? S.inv_scale : nullptr, S.amp2, S.T2, S.ldf, 0.f);
 }
 

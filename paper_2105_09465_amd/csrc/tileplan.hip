@@ -195,6 +195,27 @@ __global__ void plan_rowslots_kernel(int nrt, int nw, const int* unit_off, const
   rslot[r] = make_int2(s0, s1 - s0 + 1);
 }
 
+// Per wave, its range in one load: the first row tile r, its first partial
+// slot, the list positions [kb, ke) it takes in row tile r, and the number of
+// units it takes in the row tiles after r (-1 row tile: no units).
+__global__ void plan_wdesc_kernel(int nw, const int* unit_off, const int* count, const int* total, const int* wrow,
+                                  const int* wslot, int4* wdesc, int* wrest) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const int T = *total;
+  const int u0 = wave_unit(w, T, nw), u1 = wave_unit(w + 1, T, nw);
+  const int r = wrow[w];
+  if (u0 >= u1 || r < 0) {
+    wdesc[w] = make_int4(-1, wslot[w], 0, 0);
+    wrest[w] = 0;
+    return;
+  }
+  const int off = unit_off[r];
+  const int ke = min(u1, off + count[r]) - off;
+  wdesc[w] = make_int4(r, wslot[w], u0 - off, ke);
+  wrest[w] = u1 - (off + ke);
+}
+
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
                hipStream_t stream) {
   GPL_REQUIRE(n >= 1, "plan needs at least one point");
@@ -224,6 +245,9 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_rowslots_kernel, dim3(cdiv(p.nrt, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.unit_off,
                      p.count, p.total, p.wrow, p.wslot, p.rslot);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_wdesc_kernel, dim3(cdiv(p.nw, 256)), dim3(256), 0, stream, p.nw, p.unit_off, p.count,
+                     p.total, p.wrow, p.wslot, p.wdesc, p.wrest);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

@@ -61,6 +61,8 @@ struct TilePlan {
   int* wrow;        // [nw] row tile of each wave's first unit (-1: no units)
   int* wslot;       // [nw + 1] first partial slot of each wave
   int2* rslot;      // [nrt] first partial slot of each row tile and their number
+  int4* wdesc;      // [nw] per wave: first row tile, first slot, list range [kb, ke) in that row tile
+  int* wrest;       // [nw] the wave's units in later row tiles
 };
 
 // Waves of a product launch for n points, and partial slots it may write.
@@ -101,6 +103,8 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.wrow = cv.template take<int>((size_t)p.nw);
   p.wslot = cv.template take<int>((size_t)p.nw + 1);
   p.rslot = cv.template take<int2>((size_t)p.nrt);
+  p.wdesc = cv.template take<int4>((size_t)p.nw);
+  p.wrest = cv.template take<int>((size_t)p.nw);
 }
 
 // Build the plan on `stream`. With `grid` the points are the fine grid of that
