@@ -132,6 +132,7 @@ struct RhsOut {
   float *Vp, *inv_scale;
   const unsigned* pmax;  // [nrhs][npart] float bits of partial max |P|
   int npart;
+  const int* irank;  // fine point (row-major) -> sorted position of the product's plan
 };
 int psf_adjoint_rhs_launch(int n, int ss, const Taps& taps, int nrhs, const float* P, int ldp, const RhsOut& out,
                            CgGate gate, hipStream_t stream);

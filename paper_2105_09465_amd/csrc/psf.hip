@@ -419,7 +419,9 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int 
   const int M = n * ss;
   const int tiles_x = (M + kFineTile - 1) / kFineTile;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  const int base = zorder_rank(tx * kFineTile, ty * kFineTile, M);  // first rank of an interior tile
+  // sorted position of the tile's first fine point: an interior tile (an aligned
+  // power-of-two square of the Z-order) holds the next 1024 positions from there
+  const int base = o.irank[min(ty * kFineTile, M - 1) * M + min(tx * kFineTile, M - 1)];
   const bool f16 = o.prec == GPL_PREC_F16X3;
   // column scale, folded while the tile's window loads are in flight (the tile
   // synchronises the workgroup before its first use of s_scale)
@@ -441,7 +443,7 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int 
   // one instantiation of the tile (its LDS buffers) for both forms
   psf_adjoint_tile<true>(skip, tile, c, n, ss, taps, in, ld_in, fold_scale, [&](int fy, int fx, float v, int z) {
     const float scale = f16 ? s_scale : 1.f;
-    const size_t j = rhs_at(c, z >= 0 ? base + z : zorder_rank(fx, fy, M), o.ncp);
+    const size_t j = rhs_at(c, z >= 0 ? base + z : o.irank[fy * M + fx], o.ncp);
     if (f16) {
       const float sv = v * scale;
       const _Float16 h = (_Float16)sv;
@@ -473,7 +475,7 @@ __global__ __launch_bounds__(256) void psf_adjoint_grouped_kernel(SlotBatch B, i
   const ServeSlotDev& S = *B.slot[s];
   const int local = blockIdx.x - B.off[s];
   const int tile = local % S.ntiles_adj, c = local / S.ntiles_adj;
-  const RhsOut o{S.prec, S.ncp, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd};
+  const RhsOut o{S.prec, S.ncp, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd, S.plan.irank};
   psf_adjoint_rhs_body([&] { return S.n_active[p] == 0 || S.st[p][c].active == 0; }, tile, c, S.n, S.ss, S.taps, S.P, S.ldv, o);
 }
 

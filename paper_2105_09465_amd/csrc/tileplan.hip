@@ -18,7 +18,7 @@ size_t plan_workspace(int n) {
 // Sorted coordinates (and the permutation for a grid): thread i handles caller
 // index i < n and the padding position i in [n, npad).
 __global__ void plan_points_kernel(int n, int npad, const float* __restrict__ px, const float* __restrict__ py, int m,
-                                   int* perm, float* xs, float* ys) {
+                                   int* perm, int* irank, float* xs, float* ys) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npad) return;
   if (i >= n) {
@@ -32,6 +32,7 @@ __global__ void plan_points_kernel(int n, int npad, const float* __restrict__ px
     const int fy = i / m, fx = i - fy * m;
     r = zorder_rank(fx, fy, m);
     perm[r] = i;
+    irank[i] = r;
   }
   xs[r] = px[i];
   ys[r] = py[i];
@@ -226,9 +227,10 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
     GPL_REQUIRE(m > 0 && (long)m * m == n, "grid does not match n=%d", n);
   }
   int* perm = const_cast<int*>(p.perm);
-  if (!grid) p.perm = nullptr;  // identity: the buffer stays unused
+  int* irank = const_cast<int*>(p.irank);
+  if (!grid) p.perm = p.irank = nullptr;  // identity: the buffers stay unused
   hipLaunchKernelGGL(plan_points_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, n, p.npad, px, py, m,
-                     grid ? perm : nullptr, p.xs, p.ys);
+                     grid ? perm : nullptr, grid ? irank : nullptr, p.xs, p.ys);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_boxes_kernel, dim3(cdiv(p.nch, 256)), dim3(256), 0, stream, n, p.nch, p.xs, p.ys, p.cbox,
                      p.sbox);

@@ -51,6 +51,7 @@ struct TilePlan {
   int npad;  // 64 nrt
   int nw;    // waves of a product launch (multiple of 4)
   const int* perm;  // sorted position -> caller index; nullptr = identity
+  const int* irank; // caller index -> sorted position (with a grid; else unused)
   float *xs, *ys;   // [npad] points in sorted order, zero padded
   float4* cbox;     // [nch] (xmin, xmax, ymin, ymax); empty chunks have xmin = +inf
   float4* sbox;     // [kSubsPerTile nrt] the same for every 16-point subtile
@@ -92,6 +93,7 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.npad = p.nrt * kRowTile;
   p.nw = plan_waves(n);
   p.perm = cv.template take<int>((size_t)p.npad);
+  p.irank = cv.template take<int>((size_t)p.npad);
   p.xs = cv.template take<float>((size_t)p.npad);
   p.ys = cv.template take<float>((size_t)p.npad);
   p.cbox = cv.template take<float4>((size_t)p.nch);
