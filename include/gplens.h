@@ -141,10 +141,11 @@ int gpl_psf_conv(const gpl_grid* grid, const gpl_psf* psf, int nrhs, const float
  * Pairs of 16-point subtiles and 32-point chunks whose bounding boxes are so far
  * apart that every kernel value is exactly zero in the chosen precision are not
  * evaluated, so the result equals the all-pairs product up to FP32 summation
- * order. grid (nullable): the points are that grid's fine points in row-major
- * order (as gpl_lens_raytrace writes them) and are then taken in the grid's
- * Z-order, which keeps tiles compact; NULL keeps the caller's order, best when
- * consecutive points are close. n <= 2,097,120. */
+ * order. The points are taken along a Hilbert curve of their own positions
+ * (ties in caller order), so tiles are compact in the plane the kernel is
+ * evaluated in; Y is returned in the caller's order. grid (nullable): if given,
+ * n must equal its fine point count (the points are then its fine grid in
+ * row-major order, as gpl_lens_raytrace writes them). n <= 2,097,120. */
 size_t gpl_gp_kernel_mvm_workspace(int n, int nrhs, int prec);
 int gpl_gp_kernel_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px, const float* py, int nrhs,
                       const float* V, int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes,

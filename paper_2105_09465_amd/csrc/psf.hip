@@ -286,12 +286,15 @@ __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps ta
 }
 
 // Adjoint on one fine tile: v = (P^T D^T in)(fy, fx) for every fine point of the
-// tile, handed to store(fy, fx, v, z) with z the point's Z-order index within
-// the tile when ZWALK and the tile lies inside the grid (else -1). P^T is the correlation with the taps:
-// (P^T g)(y, x) = sum_{a,b} w_a w_b g(y + a, x + b).
-template <bool ZWALK, class Skip, class Pre, class Store>
+// tile. Thread t takes the points u = 0..3 of the tile's walk (position t + 256 u:
+// Z-order within the tile when ZWALK, else row-major); fetch(u, fy, fx) runs for
+// each while the window loads are in flight (coordinates clamped into the grid)
+// and store(fy, fx, v, u) at the end for the points inside the grid. P^T is the
+// correlation with the taps: (P^T g)(y, x) = sum_{a,b} w_a w_b g(y + a, x + b).
+template <bool ZWALK, class Skip, class Pre, class Fetch, class Store>
 __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
-                                                 const float* __restrict__ in, int ld_in, Pre&& pre, Store&& store) {
+                                                 const float* __restrict__ in, int ld_in, Pre&& pre, Fetch&& fetch,
+                                                 Store&& store) {
   extern __shared__ float psf_lds[];
   const int M = n * ss, r = taps.r, L = taps.L;
   int WC, K;  // window side in pixels; pixels that reach one fine point along an axis
@@ -309,6 +312,31 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
   const float* src = in + (size_t)c * ld_in;
   const float inv_ss2 = 1.f / (float)(ss * ss);
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
+  // the thread's points: position o = tid + 256 u of the walk
+  constexpr int kPer = kFineTile * kFineTile / 256;
+  int px[kPer], py[kPer], b0[kPer];
+  const float* col[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int o = threadIdx.x + u * 256;
+    int x = 0, y = 0;
+    if (ZWALK) {
+#pragma unroll
+      for (int bit = 0; bit < 5; ++bit) {
+        x |= ((o >> (2 * bit)) & 1) << bit;
+        y |= ((o >> (2 * bit + 1)) & 1) << bit;
+      }
+    } else {
+      y = o >> 5;
+      x = o & 31;
+    }
+    px[u] = x;
+    py[u] = y;
+    const int fy = fy0 + y;
+    const int ilo = ceil_div(fy - ss + 1 - r, ss) - cy0;
+    b0[u] = ss + (fy - ss * (cy0 + ilo)) + r;
+    col[u] = S2 + ilo * LS + x;
+  }
   {
     WinRegs R;
     win_load(R, WC, [&](int wy, int wx, bool& ok) {
@@ -320,6 +348,8 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
     if ((int)threadIdx.x < ss + L) tz[threadIdx.x] = (int)threadIdx.x < ss ? 0.f : taps.g[threadIdx.x - ss];
     for (int i = threadIdx.x; i < (K - 1) * LS; i += 256) S2[WC * LS + i] = 0.f;
     pre();  // runs while the window loads are in flight
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) fetch(u, min(fy0 + py[u], M - 1), min(fx0 + px[u], M - 1));
     win_store(R, WC, S1);
   }
   __syncthreads();
@@ -351,34 +381,7 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
     }
   }
   __syncthreads();
-  // y, for the points o = tid + 256 u, u < 4 (four chains). A tile fully inside
-  // the grid holds consecutive Z-order ranks (it is an aligned power-of-two
-  // square): there z is the point's Z-order index in the tile.
-  const bool zwalk = ZWALK && fy0 + F <= M && fx0 + F <= M;
-  constexpr int kPer = kFineTile * kFineTile / 256;
-  int px[kPer], py[kPer], b0[kPer];
-  const float* col[kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int o = threadIdx.x + u * 256;
-    int x = 0, y = 0;
-    if (zwalk) {
-#pragma unroll
-      for (int bit = 0; bit < 5; ++bit) {
-        x |= ((o >> (2 * bit)) & 1) << bit;
-        y |= ((o >> (2 * bit + 1)) & 1) << bit;
-      }
-    } else {
-      y = o >> 5;
-      x = o & 31;
-    }
-    px[u] = x;
-    py[u] = y;
-    const int fy = fy0 + y;
-    const int ilo = ceil_div(fy - ss + 1 - r, ss) - cy0;
-    b0[u] = ss + (fy - ss * (cy0 + ilo)) + r;
-    col[u] = S2 + ilo * LS + x;
-  }
+  // y, for the points of the walk, four chains per thread
   float v[kPer] = {};
 #pragma unroll 2
   for (int k = 0; k < K; ++k) {
@@ -388,7 +391,7 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int fy = fy0 + py[u], fx = fx0 + px[u];
-    if (fy < M && fx < M) store(fy, fx, v[u] * inv_ss2, zwalk ? (int)threadIdx.x + u * 256 : -1);
+    if (fy < M && fx < M) store(fy, fx, v[u] * inv_ss2, u);
   }
 }
 
@@ -398,7 +401,8 @@ __device__ __forceinline__ void psf_adjoint_body(Skip&& skip, int tile, int c, i
                                                  const float* __restrict__ in, int ld_in, float* __restrict__ out,
                                                  int ld_out, float alpha, float beta) {
   const int M = n * ss;
-  psf_adjoint_tile<false>(skip, tile, c, n, ss, taps, in, ld_in, [] {}, [&](int fy, int fx, float v, int) {
+  psf_adjoint_tile<false>(skip, tile, c, n, ss, taps, in, ld_in, [] {}, [](int, int, int) {},
+                          [&](int fy, int fx, float v, int) {
     const size_t o_idx = (size_t)c * ld_out + (size_t)fy * M + fx;
     float res = alpha * v;
     if (beta != 0.f) res += beta * out[o_idx];
@@ -406,8 +410,9 @@ __device__ __forceinline__ void psf_adjoint_body(Skip&& skip, int tile, int c, i
   });
 }
 
-// B^T P written straight into the RHS buffers of a grid-ordered product: fine
-// point (fx, fy) goes to its Z-order rank; the precision form scales column c by
+// B^T P written straight into the RHS buffers of the product: fine
+// point (fx, fy) goes to its sorted position in the product's plan (irank,
+// loaded while the window loads are in flight); the precision form scales column c by
 // 2^e_c, chosen from the bound max |B^T P| <= max |P| / ss^2 (nonnegative taps
 // summing to one) so that the largest entry stays below 2^14, and splits it
 // into FP16 hi (nearest) and lo.
@@ -417,11 +422,7 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int 
   __shared__ float red[4];
   __shared__ float s_scale;
   const int M = n * ss;
-  const int tiles_x = (M + kFineTile - 1) / kFineTile;
-  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  // sorted position of the tile's first fine point: an interior tile (an aligned
-  // power-of-two square of the Z-order) holds the next 1024 positions from there
-  const int base = o.irank[min(ty * kFineTile, M - 1) * M + min(tx * kFineTile, M - 1)];
+  int jr[kFineTile * kFineTile / 256];
   const bool f16 = o.prec == GPL_PREC_F16X3;
   // column scale, folded while the tile's window loads are in flight (the tile
   // synchronises the workgroup before its first use of s_scale)
@@ -441,9 +442,10 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int 
     }
   };
   // one instantiation of the tile (its LDS buffers) for both forms
-  psf_adjoint_tile<true>(skip, tile, c, n, ss, taps, in, ld_in, fold_scale, [&](int fy, int fx, float v, int z) {
+  auto fetch = [&](int u, int fy, int fx) { jr[u] = o.irank[fy * M + fx]; };
+  psf_adjoint_tile<true>(skip, tile, c, n, ss, taps, in, ld_in, fold_scale, fetch, [&](int, int, float v, int u) {
     const float scale = f16 ? s_scale : 1.f;
-    const size_t j = rhs_at(c, z >= 0 ? base + z : o.irank[fy * M + fx], o.ncp);
+    const size_t j = rhs_at(c, jr[u], o.ncp);
     if (f16) {
       const float sv = v * scale;
       const _Float16 h = (_Float16)sv;

@@ -2,6 +2,7 @@
 // points, chunk bounding boxes, and per row tile the list of chunks within the
 // exact-zero cutoff of the kernel (Sec. 3.1, eq. "grbf").
 #include <cmath>
+#include <utility>
 
 #include "tileplan.hpp"
 
@@ -15,25 +16,165 @@ size_t plan_workspace(int n) {
   return s.used;
 }
 
-// Sorted coordinates (and the permutation for a grid): thread i handles caller
-// index i < n and the padding position i in [n, npad).
-__global__ void plan_points_kernel(int n, int npad, const float* __restrict__ px, const float* __restrict__ py, int m,
-                                   int* perm, int* irank, float* xs, float* ys) {
+// ---- point order: Hilbert keys, then a stable LSD radix sort ----
+
+// Extent of the finite points (one workgroup): (xmin, ymin, side of the square
+// from there that holds them all, 0).
+__global__ __launch_bounds__(1024) void plan_extent_kernel(int n, const float* __restrict__ px,
+                                                           const float* __restrict__ py, float4* ext) {
+  __shared__ float red[4][16];
+  float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const float x = px[i], y = py[i];
+    if (!(isfinite(x) && isfinite(y))) continue;
+    x0 = fminf(x0, x);
+    x1 = fmaxf(x1, x);
+    y0 = fminf(y0, y);
+    y1 = fmaxf(y1, y);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    x0 = fminf(x0, __shfl_xor(x0, off, 64));
+    x1 = fmaxf(x1, __shfl_xor(x1, off, 64));
+    y0 = fminf(y0, __shfl_xor(y0, off, 64));
+    y1 = fmaxf(y1, __shfl_xor(y1, off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = x0;
+    red[1][w] = x1;
+    red[2][w] = y0;
+    red[3][w] = y1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      x0 = fminf(x0, red[0][k]);
+      x1 = fmaxf(x1, red[1][k]);
+      y0 = fminf(y0, red[2][k]);
+      y1 = fmaxf(y1, red[3][k]);
+    }
+    if (!(x0 <= x1)) *ext = make_float4(0.f, 0.f, 0.f, 0.f);  // no finite point
+    else *ext = make_float4(x0, y0, fmaxf(x1 - x0, y1 - y0), 0.f);
+  }
+}
+
+// Index of cell (x, y) along the Hilbert curve of a 2^kHilbertBits square grid:
+// at each level the quadrant contributes its position along the curve's U
+// (0 lower left, 1 upper left, 2 upper right, 3 lower right), and the cell is
+// mapped into the frame of that quadrant's copy of the curve.
+__device__ __forceinline__ uint32_t hilbert_index(uint32_t x, uint32_t y) {
+  constexpr uint32_t side = 1u << kHilbertBits;
+  uint32_t d = 0;
+  for (uint32_t s = side >> 1; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x ^= side - 1;
+        y ^= side - 1;
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
+
+// Sort key of every point: its Hilbert index on the grid over the extent; a
+// point with a non-finite coordinate takes the last key.
+__global__ void plan_keys_kernel(int n, const float* __restrict__ px, const float* __restrict__ py,
+                                 const float4* __restrict__ ext, uint32_t* __restrict__ key) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npad) return;
-  if (i >= n) {
-    xs[i] = 0.f;
-    ys[i] = 0.f;
-    if (perm) perm[i] = -1;
+  if (i >= n) return;
+  const float4 e = *ext;
+  const float x = px[i], y = py[i];
+  constexpr float kMaxCell = (float)((1u << kHilbertBits) - 1);
+  uint32_t k = (1u << (2 * kHilbertBits)) - 1;
+  if (isfinite(x) && isfinite(y)) {
+    const float sc = e.z > 0.f ? (float)(1u << kHilbertBits) / e.z : 0.f;
+    const float qx = fminf(fmaxf((x - e.x) * sc, 0.f), kMaxCell);
+    const float qy = fminf(fmaxf((y - e.y) * sc, 0.f), kMaxCell);
+    k = hilbert_index((uint32_t)qx, (uint32_t)qy);
+  }
+  key[i] = k;
+}
+
+// Digit counts of one radix pass: hist[d nsb + b] = points of sort block b with
+// digit d.
+__global__ __launch_bounds__(kSortBlock) void sort_count_kernel(int n, int nsb, int shift,
+                                                                const uint32_t* __restrict__ key,
+                                                                int* __restrict__ hist) {
+  __shared__ int h[kSortDigits];
+  for (int d = threadIdx.x; d < kSortDigits; d += kSortBlock) h[d] = 0;
+  __syncthreads();
+  const int e = blockIdx.x * kSortBlock + threadIdx.x;
+  if (e < n) atomicAdd(&h[(key[e] >> shift) & (kSortDigits - 1)], 1);
+  __syncthreads();
+  for (int d = threadIdx.x; d < kSortDigits; d += kSortBlock) hist[d * nsb + blockIdx.x] = h[d];
+}
+
+// Stable scatter of one radix pass. hist holds the exclusive scan of the counts
+// (digit-major), i.e. the first output position of each (digit, block). A
+// point's position adds the points of its block before it with the same digit:
+// those in earlier waves (per-wave digit counts in LDS) and those in lower lanes
+// of its own wave (the lanes that agree with it on all 8 digit bits, from 8
+// ballots). vin = nullptr stands for the identity.
+__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(int n, int nsb, int shift,
+                                                                  const uint32_t* __restrict__ kin,
+                                                                  const int* __restrict__ vin,
+                                                                  const int* __restrict__ hist,
+                                                                  uint32_t* __restrict__ kout,
+                                                                  int* __restrict__ vout) {
+  constexpr int kWaves = kSortBlock / 64;
+  __shared__ int wc[kWaves][kSortDigits];
+  for (int i = threadIdx.x; i < kWaves * kSortDigits; i += kSortBlock) (&wc[0][0])[i] = 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * kSortBlock + threadIdx.x;
+  const bool valid = e < n;
+  const uint32_t k = valid ? kin[e] : 0u;
+  const int v = valid ? (vin ? vin[e] : e) : 0;
+  const int d = (int)((k >> shift) & (kSortDigits - 1));
+  unsigned long long m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1;
+    const unsigned long long bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  const int lower = __popcll(m & ((1ull << lane) - 1ull));
+  __syncthreads();  // counts cleared
+  if (valid && lower == 0) wc[w][d] = __popcll(m);
+  __syncthreads();
+  if (!valid) return;
+  int r = hist[d * nsb + blockIdx.x] + lower;
+  for (int q = 0; q < w; ++q) r += wc[q][d];
+  kout[r] = k;
+  vout[r] = v;
+}
+
+// Sorted coordinates and both directions of the permutation: thread r handles
+// sorted position r < n (caller index sorted[r]) and padding position r in
+// [n, npad).
+__global__ void plan_points_kernel(int n, int npad, const float* __restrict__ px, const float* __restrict__ py,
+                                   const int* sorted, int* perm, int* __restrict__ irank, float* __restrict__ xs,
+                                   float* __restrict__ ys) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= npad) return;
+  if (r >= n) {
+    xs[r] = 0.f;
+    ys[r] = 0.f;
+    perm[r] = -1;
     return;
   }
-  int r = i;
-  if (m > 0) {
-    const int fy = i / m, fx = i - fy * m;
-    r = zorder_rank(fx, fy, m);
-    perm[r] = i;
-    irank[i] = r;
+  const int i = sorted[r];
+  if ((unsigned)i >= (unsigned)n) {  // not a permutation: leave a hole, never an out-of-range write
+    xs[r] = ys[r] = NAN;
+    perm[r] = -1;
+    return;
   }
+  perm[r] = i;
+  irank[i] = r;
   xs[r] = px[i];
   ys[r] = py[i];
 }
@@ -226,11 +367,33 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
     m = grid->n * grid->ss;
     GPL_REQUIRE(m > 0 && (long)m * m == n, "grid does not match n=%d", n);
   }
+  (void)m;
   int* perm = const_cast<int*>(p.perm);
   int* irank = const_cast<int*>(p.irank);
-  if (!grid) p.perm = p.irank = nullptr;  // identity: the buffers stay unused
-  hipLaunchKernelGGL(plan_points_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, n, p.npad, px, py, m,
-                     grid ? perm : nullptr, grid ? irank : nullptr, p.xs, p.ys);
+  const int nsb = sort_blocks(n);
+  hipLaunchKernelGGL(plan_extent_kernel, dim3(1), dim3(1024), 0, stream, n, px, py, p.sext);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_keys_kernel, dim3(cdiv(n, 256)), dim3(256), 0, stream, n, px, py, p.sext, p.skey0);
+  GPL_LAUNCH_CHECK();
+  // ping-pong: keys skey0 <-> skey1, caller indices (identity) -> sval <-> perm
+  uint32_t* kin = p.skey0;
+  uint32_t* kout = p.skey1;
+  const int* vin = nullptr;
+  int* vout = p.sval;
+  for (int pass = 0; pass < kSortPasses; ++pass) {
+    hipLaunchKernelGGL(sort_count_kernel, dim3(nsb), dim3(kSortBlock), 0, stream, n, nsb, 8 * pass, kin, p.shist);
+    GPL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, kSortDigits * nsb, p.shist, p.shist, p.ssum);
+    GPL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nsb), dim3(kSortBlock), 0, stream, n, nsb, 8 * pass, kin, vin,
+                       p.shist, kout, vout);
+    GPL_LAUNCH_CHECK();
+    std::swap(kin, kout);
+    vin = vout;
+    vout = vout == p.sval ? perm : p.sval;
+  }
+  hipLaunchKernelGGL(plan_points_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, n, p.npad, px, py, vin, perm,
+                     irank, p.xs, p.ys);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_boxes_kernel, dim3(cdiv(p.nch, 256)), dim3(256), 0, stream, n, p.nch, p.xs, p.ys, p.cbox,
                      p.sbox);

@@ -1,5 +1,6 @@
-// Tile plan of the matrix-free kernel product: the points in a spatially
-// coherent order, the bounding box of every 16-point subtile and 32-point
+// Tile plan of the matrix-free kernel product: the points sorted along a Hilbert
+// curve of their own positions (the ray-traced source-plane points, so that the
+// images of one source region share tiles), the bounding box of every 16-point subtile and 32-point
 // chunk, and for every row tile (64 points, four subtiles) the ascending list of
 // chunks that can hold a non-zero kernel value in the chosen precision, each
 // with a mask of the subtiles that can.
@@ -50,8 +51,8 @@ struct TilePlan {
   int nch;   // chunks = 2 nrt (kChunksPerTile nrt)
   int npad;  // 64 nrt
   int nw;    // waves of a product launch (multiple of 4)
-  const int* perm;  // sorted position -> caller index; nullptr = identity
-  const int* irank; // caller index -> sorted position (with a grid; else unused)
+  const int* perm;  // [npad] sorted position -> caller index (-1 past n)
+  const int* irank; // [npad] caller index -> sorted position (first n entries)
   float *xs, *ys;   // [npad] points in sorted order, zero padded
   float4* cbox;     // [nch] (xmin, xmax, ymin, ymax); empty chunks have xmin = +inf
   float4* sbox;     // [kSubsPerTile nrt] the same for every 16-point subtile
@@ -64,7 +65,21 @@ struct TilePlan {
   int2* rslot;      // [nrt] first partial slot of each row tile and their number
   int4* wdesc;      // [nw] per wave: first row tile, first slot, list range [kb, ke) in that row tile
   int* wrest;       // [nw] the wave's units in later row tiles
+  // scratch of the sort that orders the points (used while the plan is built)
+  uint32_t *skey0, *skey1;  // [npad] Hilbert keys, ping-pong
+  int* sval;                // [npad] caller indices, ping-pong partner of perm
+  int* shist;               // [kSortDigits nsb] digit counts per sort block, then their offsets
+  float4* sext;             // [1] extent of the finite points
+  int* ssum;                // [1] scan total (unused)
 };
+
+// Sort of the points: Hilbert index of 12 bits per axis over the square that
+// holds every finite point, radix-sorted 8 bits a pass in blocks of 256 points.
+constexpr int kHilbertBits = 12;
+constexpr int kSortBlock = 256;
+constexpr int kSortDigits = 256;
+constexpr int kSortPasses = (2 * kHilbertBits + 7) / 8;
+__host__ __device__ inline int sort_blocks(int n) { return (n + kSortBlock - 1) / kSortBlock; }
 
 // Waves of a product launch for n points, and partial slots it may write.
 __host__ __device__ inline int plan_waves(int n) {
@@ -107,36 +122,23 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.rslot = cv.template take<int2>((size_t)p.nrt);
   p.wdesc = cv.template take<int4>((size_t)p.nw);
   p.wrest = cv.template take<int>((size_t)p.nw);
+  p.skey0 = cv.template take<uint32_t>((size_t)p.npad);
+  p.skey1 = cv.template take<uint32_t>((size_t)p.npad);
+  p.sval = cv.template take<int>((size_t)p.npad);
+  p.shist = cv.template take<int>((size_t)kSortDigits * sort_blocks(n));
+  p.sext = cv.template take<float4>(1);
+  p.ssum = cv.template take<int>(1);
 }
 
-// Build the plan on `stream`. With `grid` the points are the fine grid of that
-// grid in row-major order and are sorted along the Z-order curve of the fine
-// grid; without it they keep the caller's order. `s2` is the exp2 scale,
-// `threshold` one of kSkipF16x3 / kSkipFp32.
+// Build the plan on `stream`. The points are sorted along the Hilbert curve of
+// their positions (ties in caller order, so the plan depends only on the
+// points). `grid` (nullable) is checked against n: with one, the points are its
+// fine grid in row-major order, which is what irank is indexed by in the fused
+// PSF adjoint. `s2` is the exp2 scale, `threshold` one of kSkipF16x3 / kSkipFp32.
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
                hipStream_t stream);
 
 // Device: first unit of wave w of nw over T units.
 __device__ __forceinline__ int wave_unit(int w, int T, int nw) { return (int)((long long)w * T / nw); }
-
-// Device: Z-order rank of fine pixel (fx, fy) among the pixels of an m x m grid.
-__device__ __forceinline__ int zorder_rank(int fx, int fy, int m) {
-  int side = 1;
-  while (side < m) side <<= 1;
-  int rank = 0, x0 = 0, y0 = 0;
-  for (int s = side >> 1; s >= 1; s >>= 1) {
-    const int qx = fx >= x0 + s, qy = fy >= y0 + s;
-    const int q = qx + 2 * qy;
-    // valid pixels of the quadrants that precede q in Z-order
-    for (int t = 0; t < q; ++t) {
-      const int ax = x0 + (t & 1) * s, ay = y0 + (t >> 1) * s;
-      const int wx = min(max(m - ax, 0), s), wy = min(max(m - ay, 0), s);
-      rank += wx * wy;
-    }
-    x0 += qx * s;
-    y0 += qy * s;
-  }
-  return rank;
-}
 
 }  // namespace gpl

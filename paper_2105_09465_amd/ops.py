@@ -104,9 +104,8 @@ def psf_conv(grid: Grid, psf: PSF, inp, adjoint: bool, out=None, alpha=1.0, beta
 
 
 def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0, grid: Grid | None = None):
-    """Y = K V (+ beta Y) over the points (px, py); grid: the points are that
-    grid's fine points in row-major order (lets the product use the grid's
-    Z-order tiles)."""
+    """Y = K V (+ beta Y) over the points (px, py); grid (optional): the points
+    are that grid's fine points in row-major order (checked against n)."""
     n = px.numel()
     squeeze = V.dim() == 1
     V2 = V.unsqueeze(0) if squeeze else V
