@@ -215,13 +215,19 @@ int gpl_block_dot(int n, int ncols, const float* X, int ldx, const float* Y, int
                   hipStream_t stream);
 
 /* Opt-in timing of the kernel-product launches (main product kernel only, not
- * its preparation or reduction), for measuring achieved rates: while enabled,
- * every such launch on this host thread is bracketed by HIP events recorded on
- * its stream. gpl_timing_read waits for the recorded events (host wait, no
- * device synchronisation), returns the summed elapsed milliseconds and launch
- * count since the last reset, and resets them if `reset` is non-zero. */
-int gpl_timing_enable(int on);
+ * its preparation or reduction), for measuring achieved rates. With stride
+ * k >= 1, every k-th such launch on this host thread (counted from the enable
+ * call) is bracketed by HIP events recorded on its stream; 0 turns timing off.
+ * Each event pair delays the stream by a few microseconds, so a stride above 1
+ * keeps timed runs close to untimed ones. gpl_timing_read waits for the
+ * recorded events (host wait, no device synchronisation) and returns the summed
+ * elapsed milliseconds and number of timed launches since the last reset;
+ * gpl_timing_samples copies up to `cap` of the per-launch times (ms, in launch
+ * order) to host memory `ms` and sets *count to how many there are. Both reset
+ * the samples if `reset` is non-zero. */
+int gpl_timing_enable(int stride);
 int gpl_timing_read(double* total_ms, long* launches, int reset);
+int gpl_timing_samples(float* ms, int cap, int* count, int reset);
 
 /* ---------------------------------------------------------------- backward */
 

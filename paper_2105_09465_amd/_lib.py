@@ -101,6 +101,7 @@ SIGNATURES = {
     "gpl_serve_snapshot": (_I, [C.POINTER(C.POINTER(gpl_serve_slot)), _I, C.c_long, _P, _P]),
     "gpl_serve_slot_finish": (_I, [C.POINTER(gpl_serve_slot), C.c_long, _D, _P, _P, _P, _P, _P, _P, _P]),
     "gpl_timing_read": (_I, [C.POINTER(_D), C.POINTER(C.c_long), _I]),
+    "gpl_timing_samples": (_I, [C.POINTER(C.c_float), _I, C.POINTER(_I), _I]),
 }
 
 

@@ -220,7 +220,7 @@ __device__ __forceinline__ bool boxes_live(const float4& a, const float4& q, flo
 // each entry with the mask of the subtiles that see the chunk.
 __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const float4* __restrict__ cbox,
                                                         const float4* __restrict__ sbox, float s2, float threshold,
-                                                        int* count, uint32_t* list) {
+                                                        int* count, uint32_t* list, int* roww) {
   const int r = blockIdx.x;
   if (r >= nrt) return;
   const int lane = threadIdx.x;
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const 
     rb = make_float4(fminf(rb.x, c.x), fmaxf(rb.y, c.y), fminf(rb.z, c.z), fmaxf(rb.w, c.w));
   }
   uint32_t* out = list + (size_t)r * nch;
-  int base = 0;
+  int base = 0, cost = 0;
   for (int c0 = 0; c0 < nch; c0 += 64) {
     const int c = c0 + lane;
     unsigned mask = 0u;
@@ -247,31 +247,40 @@ __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const 
     }
     const bool live = mask != 0u;
     const unsigned long long bal = __ballot(live);
-    if (live) out[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)c | (mask << 16);
+    const uint32_t e = (uint32_t)c | (mask << 16);
+    if (live) {
+      out[base + __popcll(bal & ((1ull << lane) - 1ull))] = e;
+      cost += unit_cost(e);
+    }
     base += __popcll(bal);
   }
-  if (lane == 0) count[r] = base;
+  for (int off = 32; off > 0; off >>= 1) cost += __shfl_xor(cost, off, 64);
+  if (lane == 0) {
+    count[r] = base;
+    roww[r] = kCostRowTile + cost;
+  }
 }
 
 // Exclusive prefix sum of n ints in one workgroup of 1024 threads (in place
 // allowed); the sum goes to *sum.
-__global__ __launch_bounds__(1024) void plan_scan_kernel(int n, const int* in, int* out, int* sum) {
-  __shared__ int wsum[16];
-  __shared__ int carry_s;
+template <class T>
+__global__ __launch_bounds__(1024) void plan_scan_kernel(int n, const int* in, T* out, T* sum) {
+  __shared__ T wsum[16];
+  __shared__ T carry_s;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid == 0) carry_s = 0;
   __syncthreads();
   for (int base = 0; base < n; base += 1024) {
     const int i = base + tid;
-    const int v = i < n ? in[i] : 0;
-    int x = v;  // inclusive scan within the wave
+    const T v = i < n ? (T)in[i] : (T)0;
+    T x = v;  // inclusive scan within the wave
     for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(x, off, 64);
+      const T y = __shfl_up(x, off, 64);
       if (lane >= off) x += y;
     }
     if (lane == 63) wsum[wv] = x;
     __syncthreads();
-    int before = carry_s;
+    T before = carry_s;
     for (int k = 0; k < wv; ++k) before += wsum[k];
     if (i < n) out[i] = before + x - v;
     __syncthreads();
@@ -291,23 +300,57 @@ __device__ __forceinline__ int row_of_unit(const int* unit_off, int nrt, int u) 
   return lo;
 }
 
-// Largest wave w with wave_unit(w) <= u (the wave whose range holds unit u).
-__device__ __forceinline__ int wave_of_unit(int u, int T, int nw) {
+// Largest wave w with wunit[w] <= u (the wave whose range holds unit u).
+__device__ __forceinline__ int wave_of_unit(int u, const int* wunit, int nw) {
   int lo = 0, hi = nw - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (wave_unit(mid, T, nw) <= u) lo = mid; else hi = mid - 1;
+    if (wunit[mid] <= u) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
+// First unit of each wave b in [0, nw]: the first unit whose exclusive cost
+// prefix reaches the wave's target, wtot x (round weight of the waves below b)
+// / (that of all nw waves). A row tile's own cost counts before its first unit.
+// One wave per boundary: the row tile by binary search over the row prefixes,
+// then the units of that row tile 64 at a time.
+__global__ __launch_bounds__(256) void plan_wunit_kernel(int nrt, int nch, int nw, int wround, const int* count,
+                                                         const uint32_t* __restrict__ list, const int* unit_off,
+                                                         const long long* rowwoff, const long long* wtot, int* wunit) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (b > nw) return;
+  const long long t = *wtot * wave_weight_below(b, wround) / wave_weight_below(nw, wround);
+  int lo = 0, hi = nrt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rowwoff[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int r = lo, cnt = count[r];
+  const long long rem = t - rowwoff[r];
+  const uint32_t* L = list + (size_t)r * nch;
+  long long before = kCostRowTile;  // cost of the row tile up to the current group of 64 units
+  int k = 0;
+  for (int k0 = 0; k0 < cnt && before < rem; k0 += 64) {
+    const int kk = k0 + lane;
+    const int c = kk < cnt ? unit_cost(L[kk]) : 0;
+    int x = c;  // inclusive prefix within the group
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    k += __popcll(__ballot(kk < cnt && before + (x - c) < rem));
+    before += __shfl(x, 63, 64);
+  }
+  if (lane == 0) wunit[b] = unit_off[r] + k;
+}
+
 // Per wave: first row tile and number of row tiles its units touch (the count
 // goes to nrows[w], scanned into partial slots afterwards).
-__global__ void plan_waves_kernel(int nrt, int nw, const int* unit_off, const int* total, int* wrow, int* nrows) {
+__global__ void plan_waves_kernel(int nrt, int nw, const int* wunit, const int* unit_off, int* wrow, int* nrows) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
-  const int T = *total;
-  const int u0 = wave_unit(w, T, nw), u1 = wave_unit(w + 1, T, nw);
+  const int u0 = wunit[w], u1 = wunit[w + 1];
   if (u0 >= u1) {
     wrow[w] = -1;
     nrows[w] = 0;
@@ -321,17 +364,16 @@ __global__ void plan_waves_kernel(int nrt, int nw, const int* unit_off, const in
 // Per row tile: its partial slots [s0, s0 + cnt), from the first and last wave
 // holding its units (waves in between start in this row tile, so their slots
 // for it are their first ones, and empty waves own no slot).
-__global__ void plan_rowslots_kernel(int nrt, int nw, const int* unit_off, const int* count, const int* total,
+__global__ void plan_rowslots_kernel(int nrt, int nw, const int* wunit, const int* unit_off, const int* count,
                                      const int* wrow, const int* wslot, int2* rslot) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrt) return;
-  const int T = *total;
   const int a = unit_off[r], c = count[r];
   if (c <= 0) {
     rslot[r] = make_int2(0, 0);
     return;
   }
-  const int wf = wave_of_unit(a, T, nw), wl = wave_of_unit(a + c - 1, T, nw);
+  const int wf = wave_of_unit(a, wunit, nw), wl = wave_of_unit(a + c - 1, wunit, nw);
   const int s0 = wslot[wf] + (r - wrow[wf]);
   const int s1 = wslot[wl] + (r - wrow[wl]);
   rslot[r] = make_int2(s0, s1 - s0 + 1);
@@ -340,12 +382,11 @@ __global__ void plan_rowslots_kernel(int nrt, int nw, const int* unit_off, const
 // Per wave, its range in one load: the first row tile r, its first partial
 // slot, the list positions [kb, ke) it takes in row tile r, and the number of
 // units it takes in the row tiles after r (-1 row tile: no units).
-__global__ void plan_wdesc_kernel(int nw, const int* unit_off, const int* count, const int* total, const int* wrow,
+__global__ void plan_wdesc_kernel(int nw, const int* wunit, const int* unit_off, const int* count, const int* wrow,
                                   const int* wslot, int4* wdesc, int* wrest) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nw) return;
-  const int T = *total;
-  const int u0 = wave_unit(w, T, nw), u1 = wave_unit(w + 1, T, nw);
+  const int u0 = wunit[w], u1 = wunit[w + 1];
   const int r = wrow[w];
   if (u0 >= u1 || r < 0) {
     wdesc[w] = make_int4(-1, wslot[w], 0, 0);
@@ -358,6 +399,19 @@ __global__ void plan_wdesc_kernel(int nw, const int* unit_off, const int* count,
   wrest[w] = u1 - (off + ke);
 }
 
+// Compute units of the current device (queried once per device).
+static int compute_units() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] <= 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
                hipStream_t stream) {
   GPL_REQUIRE(n >= 1, "plan needs at least one point");
@@ -368,6 +422,7 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
     GPL_REQUIRE(m > 0 && (long)m * m == n, "grid does not match n=%d", n);
   }
   (void)m;
+  p.wround = 4 * compute_units();
   int* perm = const_cast<int*>(p.perm);
   int* irank = const_cast<int*>(p.irank);
   const int nsb = sort_blocks(n);
@@ -383,7 +438,8 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   for (int pass = 0; pass < kSortPasses; ++pass) {
     hipLaunchKernelGGL(sort_count_kernel, dim3(nsb), dim3(kSortBlock), 0, stream, n, nsb, 8 * pass, kin, p.shist);
     GPL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, kSortDigits * nsb, p.shist, p.shist, p.ssum);
+    hipLaunchKernelGGL(plan_scan_kernel<int>, dim3(1), dim3(1024), 0, stream, kSortDigits * nsb, p.shist, p.shist,
+                       p.ssum);
     GPL_LAUNCH_CHECK();
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(nsb), dim3(kSortBlock), 0, stream, n, nsb, 8 * pass, kin, vin,
                        p.shist, kout, vout);
@@ -399,20 +455,25 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
                      p.sbox);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_lists_kernel, dim3(p.nrt), dim3(64), 0, stream, p.nrt, p.nch, p.cbox, p.sbox, s2,
-                     threshold, p.count, p.list);
+                     threshold, p.count, p.list, p.roww);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, p.nrt, p.count, p.unit_off, p.total);
+  hipLaunchKernelGGL(plan_scan_kernel<int>, dim3(1), dim3(1024), 0, stream, p.nrt, p.count, p.unit_off, p.total);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_waves_kernel, dim3(cdiv(p.nw, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.unit_off, p.total,
-                     p.wrow, p.wslot);
+  hipLaunchKernelGGL(plan_scan_kernel<long long>, dim3(1), dim3(1024), 0, stream, p.nrt, p.roww, p.rowwoff, p.wtot);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, stream, p.nw, p.wslot, p.wslot, p.wslot + p.nw);
+  hipLaunchKernelGGL(plan_wunit_kernel, dim3(cdiv(p.nw + 1, 4)), dim3(256), 0, stream, p.nrt, p.nch, p.nw, p.wround,
+                     p.count, p.list, p.unit_off, p.rowwoff, p.wtot, p.wunit);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_rowslots_kernel, dim3(cdiv(p.nrt, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.unit_off,
-                     p.count, p.total, p.wrow, p.wslot, p.rslot);
+  hipLaunchKernelGGL(plan_waves_kernel, dim3(cdiv(p.nw, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.wunit,
+                     p.unit_off, p.wrow, p.wslot);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_wdesc_kernel, dim3(cdiv(p.nw, 256)), dim3(256), 0, stream, p.nw, p.unit_off, p.count,
-                     p.total, p.wrow, p.wslot, p.wdesc, p.wrest);
+  hipLaunchKernelGGL(plan_scan_kernel<int>, dim3(1), dim3(1024), 0, stream, p.nw, p.wslot, p.wslot, p.wslot + p.nw);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_rowslots_kernel, dim3(cdiv(p.nrt, 256)), dim3(256), 0, stream, p.nrt, p.nw, p.wunit,
+                     p.unit_off, p.count, p.wrow, p.wslot, p.rslot);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_wdesc_kernel, dim3(cdiv(p.nw, 256)), dim3(256), 0, stream, p.nw, p.wunit, p.unit_off,
+                     p.count, p.wrow, p.wslot, p.wdesc, p.wrest);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

@@ -40,17 +40,27 @@ __host__ __device__ inline int entry_chunk(uint32_t e) { return (int)(e & 0xffff
 __host__ __device__ inline unsigned entry_mask(uint32_t e) { return e >> 16; }
 
 // The evaluated work is a sequence of units, the live (row tile, chunk) pairs in
-// row-tile order. A product launch of nw waves gives wave w the contiguous
-// units [w T / nw, (w + 1) T / nw) (T units in all), so every wave gets the same
-// work; a wave writes one partial row block per row tile it touches, into
-// consecutive slots starting at wslot[w]. The slots of one row tile are then
-// consecutive too, in wave order, and are summed in that order.
+// row-tile order (T units in all). A product launch of nw waves gives each wave
+// a contiguous range of units; a wave writes one partial row block per row tile
+// it touches, into consecutive slots starting at wslot[w]. The slots of one row
+// tile are then consecutive too, in wave order, and are summed in that order.
+//
+// The ranges balance a cost estimate, not the unit count: a unit costs in
+// proportion to its live subtiles plus a fixed part, and a row tile has a fixed
+// cost of its own (row loads, the partial store). They are also sized for how
+// the waves share a SIMD. Workgroups are dispatched in order, one per compute
+// unit at a time, so the waves of the r-th group of wround = 4 x (compute
+// units) waves sit as the r-th wave on their SIMDs, and the SIMD issues for its
+// oldest wave first. With equal costs the first group ends early and the last
+// one runs on alone at the rate of a single wave; costs in the ratio of
+// kRoundWeight let the three waves of a SIMD end together.
 struct TilePlan {
   int n;     // points
   int nrt;   // row tiles = ceil(n / 64)
   int nch;   // chunks = 2 nrt (kChunksPerTile nrt)
   int npad;  // 64 nrt
   int nw;    // waves of a product launch (multiple of 4)
+  int wround;  // waves dispatched per round (4 per compute unit)
   const int* perm;  // [npad] sorted position -> caller index (-1 past n)
   const int* irank; // [npad] caller index -> sorted position (first n entries)
   float *xs, *ys;   // [npad] points in sorted order, zero padded
@@ -65,6 +75,10 @@ struct TilePlan {
   int2* rslot;      // [nrt] first partial slot of each row tile and their number
   int4* wdesc;      // [nw] per wave: first row tile, first slot, list range [kb, ke) in that row tile
   int* wrest;       // [nw] the wave's units in later row tiles
+  int* wunit;       // [nw + 1] first unit of each wave (wunit[nw] = T)
+  int* roww;        // [nrt] cost estimate of each row tile
+  long long* rowwoff;  // [nrt] exclusive prefix of roww
+  long long* wtot;     // [1] total cost
   // scratch of the sort that orders the points (used while the plan is built)
   uint32_t *skey0, *skey1;  // [npad] Hilbert keys, ping-pong
   int* sval;                // [npad] caller indices, ping-pong partner of perm
@@ -107,6 +121,7 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.nch = kChunksPerTile * p.nrt;
   p.npad = p.nrt * kRowTile;
   p.nw = plan_waves(n);
+  p.wround = 1024;
   p.perm = cv.template take<int>((size_t)p.npad);
   p.irank = cv.template take<int>((size_t)p.npad);
   p.xs = cv.template take<float>((size_t)p.npad);
@@ -122,6 +137,10 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.rslot = cv.template take<int2>((size_t)p.nrt);
   p.wdesc = cv.template take<int4>((size_t)p.nw);
   p.wrest = cv.template take<int>((size_t)p.nw);
+  p.wunit = cv.template take<int>((size_t)p.nw + 1);
+  p.roww = cv.template take<int>((size_t)p.nrt);
+  p.rowwoff = cv.template take<long long>((size_t)p.nrt);
+  p.wtot = cv.template take<long long>(1);
   p.skey0 = cv.template take<uint32_t>((size_t)p.npad);
   p.skey1 = cv.template take<uint32_t>((size_t)p.npad);
   p.sval = cv.template take<int>((size_t)p.npad);
@@ -138,7 +157,26 @@ void plan_carve(C& cv, int n, TilePlan& p) {
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
                hipStream_t stream);
 
-// Device: first unit of wave w of nw over T units.
-__device__ __forceinline__ int wave_unit(int w, int T, int nw) { return (int)((long long)w * T / nw); }
+// Relative work of a wave in the first, second and later dispatch rounds.
+constexpr int kRounds = 3;
+constexpr int kRoundWeight[kRounds] = {16, 9, 4};
+
+// Weight of waves [0, w): sum over rounds of the round's weight x its waves below w.
+__host__ __device__ inline long long wave_weight_below(int w, int wround) {
+  long long c = 0;
+  for (int k = 0; k < kRounds; ++k) {
+    const int lo = k * wround;
+    const int hi = k == kRounds - 1 ? w : min(w, (k + 1) * wround);
+    if (hi > lo) c += (long long)kRoundWeight[k] * (hi - lo);
+  }
+  return c;
+}
+
+// Cost estimate of a unit (per live subtile and fixed) and of a row tile, in the
+// ratio measured for the precision form.
+constexpr int kCostSubtile = 4;
+constexpr int kCostUnit = 5;
+constexpr int kCostRowTile = 36;
+__host__ __device__ inline int unit_cost(uint32_t e) { return kCostSubtile * __builtin_popcount(entry_mask(e)) + kCostUnit; }
 
 }  // namespace gpl

@@ -253,8 +253,11 @@ def sersic_backward(src: Sersic, px, py, gmu, gpx, gpy):
 
 # ------------------------------------------------------------------ timing
 
-def timing_enable(on: bool = True):
-    _lib.call("gpl_timing_enable", 1 if on else 0)
+def timing_enable(on: bool | int = True):
+    """Time every kernel-product launch (True), every k-th one (an int k >= 1),
+    or none (False / 0)."""
+    stride = int(on) if not isinstance(on, bool) else (1 if on else 0)
+    _lib.call("gpl_timing_enable", stride)
 
 
 def timing_read(reset: bool = True):
@@ -262,3 +265,12 @@ def timing_read(reset: bool = True):
     ms, n = C.c_double(0.0), C.c_long(0)
     _lib.call("gpl_timing_read", C.byref(ms), C.byref(n), 1 if reset else 0)
     return ms.value, n.value
+
+
+def timing_samples(reset: bool = True):
+    """Per-launch milliseconds of the timed kernel-product launches, in order."""
+    n = C.c_int(0)
+    _lib.call("gpl_timing_samples", None, 0, C.byref(n), 0)
+    buf = (C.c_float * max(n.value, 1))()
+    _lib.call("gpl_timing_samples", buf, n.value, C.byref(n), 1 if reset else 0)
+    return [float(buf[k]) for k in range(n.value)]

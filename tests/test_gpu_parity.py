@@ -520,3 +520,23 @@ def test_evidence_full_size_vs_stored_oracle(G, prec):
     assert abs(ld_err) <= 4 * h["stderr"]
     im = t64(rec.image)
     assert np.max(np.abs(im - z["image"])) <= 1e-4 * np.max(np.abs(z["image"]))
+
+
+def test_timing_stride(G):
+    """Event timing of the product launches: stride k times launches 0, k, 2k, ...
+    of those made while enabled; nothing is timed when off."""
+    _say("timing stride")
+    rng = np.random.default_rng(31)
+    px, py = cuda32(rng.uniform(0, 1, 3000)), cuda32(rng.uniform(0, 1, 3000))
+    V = cuda32(rng.standard_normal((5, 3000)))
+    k = G.Kernel(0.05, 1.0)
+    G.ops.timing_samples(reset=True)
+    G.ops.timing_enable(3)
+    for _ in range(7):
+        G.ops.kernel_mvm(k, px, py, V, prec="f16x3")
+    G.ops.timing_enable(False)
+    s = G.ops.timing_samples(reset=True)
+    assert len(s) == 3 and all(v > 0 for v in s)
+    for _ in range(2):
+        G.ops.kernel_mvm(k, px, py, V, prec="f16x3")
+    assert G.ops.timing_read(reset=True) == (0.0, 0)
