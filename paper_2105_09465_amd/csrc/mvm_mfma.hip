@@ -18,8 +18,8 @@
 // reproducible. Exact coordinate differences are formed before scaling.
 //
 // Precision form (GPL_PREC_F16X3): exp tiles computed in FP32 as 2^11 k (the
-// factor enters through the exp2 argument) and split into FP16 hi (the top 11
-// significant bits) and lo = k - hi; the RHS block is split the same way after
+// factor enters through the exp2 argument) and split into FP16 hi (truncated
+// toward zero) and lo = k - hi (exact in FP32); the RHS block is split after
 // a per-column power-of-two scale that puts its largest entry near 2^14. Each
 // 16x16x32 tile takes three MFMAs (hi.hi + hi.lo + lo.hi) into FP32
 // accumulators; the dropped lo.lo term is ~2^-22 relative.
@@ -267,7 +267,7 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
     if (!((c.mask >> rt) & 1u)) continue;  // every exp of this 16 x 32 tile is exactly zero
-    float hf[8], lf[8], dx[8], dy[8], d2[8], k2[8];
+    float lf[8], dx[8], dy[8], d2[8], k2[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) dx[e] = xi[rt] - xj[e];
 #pragma unroll
@@ -280,14 +280,15 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
     for (int e = 0; e < 8; ++e) d2[e] = fmaf(d2[e], -s2, 11.f);
 #pragma unroll
     for (int e = 0; e < 8; ++e) k2[e] = exp2_fast(d2[e]);  // 2^11 k
-#pragma unroll
-    for (int e = 0; e < 8; ++e) hf[e] = __uint_as_float(__float_as_uint(k2[e]) & 0xffffe000u);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) lf[e] = k2[e] - hf[e];
     half8 hi, lo;
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
-      const half2v h = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(hf[e], hf[e + 1]));
+      // hi = 2^11 k truncated to FP16; lo = 2^11 k - hi exactly, formed from the
+      // FP16 half in one v_fma_mix_f32 (no compiler builtin selects it)
+      const auto hp = __builtin_amdgcn_cvt_pkrtz(k2[e], k2[e + 1]);
+      const half2v h = __builtin_bit_cast(half2v, hp);
+      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lf[e]) : "v"(hp), "v"(k2[e]));
+      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(lf[e + 1]) : "v"(hp), "v"(k2[e + 1]));
       const half2v l = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(lf[e], lf[e + 1]));
       hi[e] = h[0];
       hi[e + 1] = h[1];
