@@ -407,20 +407,16 @@ __device__ __forceinline__ void reduce_body(Skip&& skip, int bx, int c, const Ti
   if (skip()) return;
   const float* p0 = part + ((size_t)sl.x * pcols + c) * kRowTile + row;
   const size_t stride = (size_t)pcols * kRowTile;
-  // in slot order; the loads of each group of 8 are issued together
+  // in slot order; the loads of each group of 8 are issued together. Past the
+  // last slot a load repeats it (always a valid address) and its value is not
+  // added: a load under a condition would be branched around and waited for on
+  // its own.
   float s = 0.f;
-  int q = 0;
-  for (; q + 8 <= sl.y; q += 8) {
+  const int last = max(sl.y - 1, 0);
+  for (int q = 0; q < sl.y; q += 8) {
     float t[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = p0[(q + u) * stride];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s += t[u];
-  }
-  {
-    float t[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = q + u < sl.y ? p0[(q + u) * stride] : 0.f;
+    for (int u = 0; u < 8; ++u) t[u] = p0[(size_t)min(q + u, last) * stride];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (q + u < sl.y) s += t[u];

@@ -251,6 +251,33 @@ def test_kernel_mvm_f16x3_wide_dynamic_range(G):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_kernel_mvm_ties_and_outliers(G, prec):
+    """Points that the plan's Hilbert sort must order by caller index (groups of
+    exact duplicates, so equal keys), a dense clump inside one grid cell of the
+    sort, and far outliers that stretch the sorted extent (N = 2309: a ragged last
+    sort block and row tile). All rows against the FP64 oracle, and the same
+    product over the points handed over in reverse order."""
+    _say("mvm ties and outliers", prec)
+    rng = np.random.default_rng(41)
+    base = rng.uniform(-0.3, 0.3, (700, 2))
+    dup = np.repeat(base[:300], 4, axis=0)             # 1200 points in 300 groups of 4 identical ones
+    clump = 1e-6 * rng.standard_normal((500, 2)) + 0.1  # closer than one cell of the sort's grid
+    far = rng.uniform(-50, 50, (9, 2))
+    pts = np.concatenate([base[300:], dup, clump, far, base[:200]]).astype(np.float32)
+    n = len(pts)
+    px, py = pts[:, 0].copy(), pts[:, 1].copy()
+    V = rng.standard_normal((3, n)).astype(np.float32)
+    k = G.Kernel(0.05, 0.7)
+    Y = t64(G.ops.kernel_mvm(k, cuda32(px), cuda32(py), cuda32(V), prec=prec))
+    Yr = t64(G.ops.kernel_mvm(k, cuda32(px[::-1]), cuda32(py[::-1]), cuda32(V[:, ::-1]), prec=prec))[:, ::-1]
+    P64 = (px.astype(np.float64), py.astype(np.float64))
+    want = okernel.kernel_mvm(*P64, V.astype(np.float64).T, 0.05, 0.7)
+    scale = okernel.kernel_abs_mvm_rows(*P64, np.arange(n), V.astype(np.float64).T, 0.05, 0.7)
+    assert np.max(np.abs(Y.T - want) / scale) <= 1e-5
+    assert np.max(np.abs(Yr.T - want) / scale) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
 def test_kernel_mvm_grid_tiles(G, prec):
     """Lensed points of the 100x100, ss = 2 workload (N = 40,000), which the
     product sorts along a Hilbert curve of their source-plane positions: most
