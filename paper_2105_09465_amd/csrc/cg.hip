@@ -473,7 +473,7 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
   MvmCtx mv;  // the points stay fixed for the whole solve: one tile plan
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid, nrhs,
                       prec, b.mvm_ws, b.mvm_ws_bytes, stream));
-  const RhsOut rhs_out{prec, mv.bufs.ncp, mv.bufs.Vh, mv.bufs.Vl, mv.bufs.Vp, mv.bufs.inv_scale, b.pmax, b.nb_upd,
+  const RhsOut rhs_out{prec, nrhs, mv.bufs.ncp, mv.bufs.Vh, mv.bufs.Vl, mv.bufs.Vp, mv.bufs.inv_scale, b.pmax, b.nb_upd,
                        mv.plan.irank};
   const float sigma2 = (float)(prob->noise_sigma * prob->noise_sigma);
 

@@ -127,7 +127,8 @@ int mvm_run_prepared(const MvmCtx& m, int nrhs, float* Y, int ldy, float beta, C
 // precision form taken from partial maxima of |P| (|B^T P| <= max |P| / ss^2).
 struct RhsOut {
   int prec;
-  int ncp;  // columns of the buffers (rhs_at layout)
+  int nrhs;  // columns of the product (their FP16 parts are placed by hi_slot)
+  int ncp;   // column slots of the buffers (rhs_at layout)
   _Float16 *Vh, *Vl;
   float *Vp, *inv_scale;
   const unsigned* pmax;  // [nrhs][npart] float bits of partial max |P|

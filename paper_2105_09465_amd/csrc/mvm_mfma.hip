@@ -80,11 +80,16 @@ __device__ __forceinline__ float gather_rhs(int j, int c, int n, int nrhs, const
 
 // V' = V * 2^e_c split into FP16 hi (nearest) and lo, in sorted order;
 // inv_scale[c] = 2^-e_c / 2^11 folds both scales for the output.
-__device__ __forceinline__ void split_rhs_body(int bx, int c, int n, int nrhs, const float* __restrict__ V, int ldv,
-                                               const int* perm, const unsigned* colmax, _Float16* Vh, _Float16* Vl,
-                                               int ldh, int ncp, float* inv_scale) {
+__device__ __forceinline__ void split_rhs_body(int bx, int slot, int n, int nrhs, const float* __restrict__ V,
+                                               int ldv, const int* perm, const unsigned* colmax, _Float16* Vh,
+                                               _Float16* Vl, int ldh, int ncp, float* inv_scale) {
   const int j = bx * blockDim.x + threadIdx.x;
   if (j >= ldh) return;
+  // slot `slot` of the buffers: column `slot`, or in a packed last block one
+  // FP16 part (lo in odd slots) of column b0 + (slot - b0) / 2
+  const int b0 = packed_block_start(nrhs);
+  const bool packed = last_block_packed(nrhs) && slot >= b0;
+  const int c = packed ? b0 + (slot - b0) / 2 : slot;
   int e = 0;
   if (c < nrhs) {
     unsigned mb = 0u;
@@ -93,12 +98,16 @@ __device__ __forceinline__ void split_rhs_body(int bx, int c, int n, int nrhs, c
     if (mx > 0.f && isfinite(mx)) e = 14 - ilogbf(mx) - 1;  // mx * 2^e in [2^13, 2^14)
   }
   const float scale = ldexpf(1.f, e);
-  if (j == 0) inv_scale[c] = ldexpf(1.f, -e) / kKScale;
+  if (j == 0 && c < ncp && (!packed || ((slot - b0) & 1) == 0)) inv_scale[c] = ldexpf(1.f, -e) / kKScale;
   const float v = gather_rhs(j, c, n, nrhs, perm, V, ldv) * scale;
   const _Float16 h = (_Float16)v;
   const _Float16 l = (_Float16)(v - (float)h);
-  Vh[rhs_at(c, j, ncp)] = h;
-  Vl[rhs_at(c, j, ncp)] = l;
+  if (packed) {
+    Vh[rhs_at(slot, j, ncp)] = ((slot - b0) & 1) ? l : h;
+  } else {
+    Vh[rhs_at(c, j, ncp)] = h;
+    Vl[rhs_at(c, j, ncp)] = l;
+  }
 }
 
 __global__ void split_rhs_kernel(int n, int nrhs, const float* __restrict__ V, int ldv, const int* perm,
@@ -125,17 +134,25 @@ __global__ void pack_rhs_kernel(int n, int nrhs, const float* __restrict__ V, in
 // ---------------------------------------------------------------- work of one wave
 
 // Partial rows of one row tile from one wave: part[(slot * pcols + c0 + c) * 64 + row]
-// for c < ncols (MFMA D layout: column = lane % 16, rows 4 * (lane / 16) + v).
-template <int CB>
+// for c < ncols (MFMA D layout: column = lane % 16, rows 4 * (lane / 16) + v). In a
+// packed last block (PK) accumulator columns 2t and 2t + 1 (lanes ri, ri + 1) are
+// the two parts of column 16 (CB - 1) + t and are added.
+template <int CB, bool PK>
 __device__ __forceinline__ void store_partial(const f32x4 (&acc)[kRT][CB], int slot, float* __restrict__ part,
                                               int pcols, int c0, int ncols, int ri, int g) {
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-      const int c = cb * 16 + ri;
+      f32x4 v = acc[rt][cb];
+      int c = cb * 16 + ri;
+      if (PK && cb == CB - 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += __shfl_down(v[k], 1, 64);
+        c = (ri & 1) ? ncols : cb * 16 + ri / 2;  // odd lanes hold the second parts
+      }
       if (c < ncols)
-        *reinterpret_cast<f32x4*>(&part[((size_t)slot * pcols + c0 + c) * kRowTile + rt * 16 + g * 4]) = acc[rt][cb];
+        *reinterpret_cast<f32x4*>(&part[((size_t)slot * pcols + c0 + c) * kRowTile + rt * 16 + g * 4]) = v;
     }
 }
 
@@ -196,7 +213,7 @@ __device__ __forceinline__ void for_chunks_pf(const uint32_t* lst, int kb, int k
 // list positions [kb, ke) of a row tile. The wave's range comes from one
 // descriptor load, issued together with the gate flag; `skip()` is evaluated
 // once both are in.
-template <int CB, class S, class F>
+template <int CB, bool PK, class S, class F>
 __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __restrict__ part, int pcols, int c0,
                                              int ncols, S&& skip, F&& chunk_fn) {
   const int4 d = P.wdesc[w];
@@ -219,7 +236,7 @@ __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     chunk_fn(acc, xi, yi, P.list + (size_t)r * P.nch, kb, ke, lane);
-    store_partial<CB>(acc, slot, part, pcols, c0, ncols, ri, g);
+    store_partial<CB, PK>(acc, slot, part, pcols, c0, ncols, ri, g);
     if (rest <= 0) break;
     ++r;
     ++slot;
@@ -234,16 +251,17 @@ __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __
 // Operands of one chunk for one lane: its 8 consecutive source points, the
 // hi/lo RHS fragments of every column block (columns past nrhs are zero) and
 // the (uniform) mask of the subtiles that see the chunk.
-template <int CB>
+template <int CB, bool PK>
 struct F16Chunk {
-  static constexpr int kLoads = 4 + 2 * CB;  // vector loads issued by f16_load
+  static constexpr int kLo = CB - (PK ? 1 : 0);  // blocks with a separate lo fragment
+  static constexpr int kLoads = 4 + CB + kLo;    // vector loads issued by f16_load
   f32x4 x0, x1, y0, y1;
-  half8 bh[CB], bl[CB];
+  half8 bh[CB], bl[kLo > 0 ? kLo : 1];
   unsigned mask;
 };
 
-template <int CB>
-__device__ __forceinline__ void f16_load(F16Chunk<CB>& c, const TilePlan& P, const _Float16* __restrict__ Vh,
+template <int CB, bool PK>
+__device__ __forceinline__ void f16_load(F16Chunk<CB, PK>& c, const TilePlan& P, const _Float16* __restrict__ Vh,
                                          const _Float16* __restrict__ Vl, int ncp, uint32_t entry, int ri, int g) {
   c.mask = entry_mask(entry);
   const int j0 = entry_chunk(entry) * kChunk + g * 8;
@@ -255,12 +273,12 @@ __device__ __forceinline__ void f16_load(F16Chunk<CB>& c, const TilePlan& P, con
   for (int cb = 0; cb < CB; ++cb) {
     const size_t o = ((size_t)entry_chunk(entry) * ncp + cb * 16 + ri) * kChunk + g * 8;
     c.bh[cb] = *reinterpret_cast<const half8*>(&Vh[o]);
-    c.bl[cb] = *reinterpret_cast<const half8*>(&Vl[o]);
+    if (cb < F16Chunk<CB, PK>::kLo) c.bl[cb] = *reinterpret_cast<const half8*>(&Vl[o]);
   }
 }
 
-template <int CB>
-__device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chunk<CB>& c, const float (&xi)[kRT],
+template <int CB, bool PK>
+__device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chunk<CB, PK>& c, const float (&xi)[kRT],
                                             const float (&yi)[kRT], float s2) {
   const float xj[8] = {c.x0[0], c.x0[1], c.x0[2], c.x0[3], c.x1[0], c.x1[1], c.x1[2], c.x1[3]};
   const float yj[8] = {c.y0[0], c.y0[1], c.y0[2], c.y0[3], c.y1[0], c.y1[1], c.y1[2], c.y1[3]};
@@ -299,7 +317,7 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
     for (int cb = 0; cb < CB; ++cb)
       acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, c.bh[cb], acc[rt][cb], 0, 0, 0);
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
+    for (int cb = 0; cb < F16Chunk<CB, PK>::kLo; ++cb)
       acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, c.bl[cb], acc[rt][cb], 0, 0, 0);
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
@@ -307,27 +325,27 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
   }
 }
 
-template <int CB, class Skip>
+template <int CB, bool PK, class Skip>
 __device__ __forceinline__ void mvm_f16x3_wave(Skip&& skip, int w, const TilePlan& P, float s2, const _Float16* __restrict__ Vh,
                                                const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
-  wave_product<CB>(w, P, part, pcols, c0, ncols, skip,
+  wave_product<CB, PK>(w, P, part, pcols, c0, ncols, skip,
                    [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
-                     for_chunks_pf<F16Chunk<CB>>(lst, kb, ke, lane,
-                         [&](F16Chunk<CB>& c, uint32_t e) { f16_load(c, P, Vh, Vl, ncp, e, ri, g); },
-                         [&](const F16Chunk<CB>& c) { f16_compute(acc, c, xi, yi, s2); });
+                     for_chunks_pf<F16Chunk<CB, PK>>(lst, kb, ke, lane,
+                         [&](F16Chunk<CB, PK>& c, uint32_t e) { f16_load(c, P, Vh, Vl, ncp, e, ri, g); },
+                         [&](const F16Chunk<CB, PK>& c) { f16_compute(acc, c, xi, yi, s2); });
                    });
 }
 
 // One wave per share of the plan's units; 4 independent waves per workgroup.
-template <int CB>
+template <int CB, bool PK>
 __global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, float s2, const _Float16* __restrict__ Vh,
                                                         const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                         float* __restrict__ part, int pcols, int c0, CgGate gate) {
   const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  mvm_f16x3_wave<CB>([&] { return gate.skip_all(); }, w, P, s2, Vh, Vl, ncp, ncols, part, pcols, c0);
+  mvm_f16x3_wave<CB, PK>([&] { return gate.skip_all(); }, w, P, s2, Vh, Vl, ncp, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- FP32 form
@@ -373,7 +391,7 @@ template <int CB, class Skip>
 __device__ __forceinline__ void mvm_f32_wave(Skip&& skip, int w, const TilePlan& P, float s2, const float* __restrict__ Vp,
                                              int ncp, int ncols, float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
-  wave_product<CB>(w, P, part, pcols, c0, ncols, skip,
+  wave_product<CB, false>(w, P, part, pcols, c0, ncols, skip,
                    [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
                        int kb, int ke, int lane) {
                      for_chunks(lst, kb, ke, lane,
@@ -463,10 +481,14 @@ float plan_threshold(int prec) { return prec == GPL_PREC_F16X3 ? kSkipF16x3 : kS
 // ---------------------------------------------------------------- launches
 
 template <int CB>
-static void launch_f16x3(const TilePlan& P, float s2, const _Float16* Vh, const _Float16* Vl, int ncp, int ncols,
-                         float* part, int pcols, int c0, CgGate gate, hipStream_t stream) {
-  hipLaunchKernelGGL((mvm_f16x3_kernel<CB>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ncp, ncols,
-                     part, pcols, c0, gate);
+static void launch_f16x3(bool packed, const TilePlan& P, float s2, const _Float16* Vh, const _Float16* Vl, int ncp,
+                         int ncols, float* part, int pcols, int c0, CgGate gate, hipStream_t stream) {
+  if (packed)
+    hipLaunchKernelGGL((mvm_f16x3_kernel<CB, true>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ncp,
+                       ncols, part, pcols, c0, gate);
+  else
+    hipLaunchKernelGGL((mvm_f16x3_kernel<CB, false>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ncp,
+                       ncols, part, pcols, c0, gate);
 }
 
 template <int CB>
@@ -530,14 +552,16 @@ int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float
     const int ncols = std::min(nrhs - c0, cb * 16);
     hipEvent_t t0 = timing_begin(stream);
     if (f16) {
-      // columns c0.. of each chunk (rhs_at layout)
+      // columns c0.. of each chunk (rhs_at layout); the pass with the last block
+      // may have it packed
       const _Float16* vh = b.Vh + (size_t)c0 * kChunk;
       const _Float16* vl = b.Vl + (size_t)c0 * kChunk;
+      const bool pk = c0 + cb * 16 >= nrhs && last_block_packed(nrhs);
       switch (cb) {
-        case 4: launch_f16x3<4>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 3: launch_f16x3<3>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 2: launch_f16x3<2>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
-        default: launch_f16x3<1>(P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 4: launch_f16x3<4>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 3: launch_f16x3<3>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 2: launch_f16x3<2>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        default: launch_f16x3<1>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
       }
     } else {
       const float* vp = b.Vp + (size_t)c0 * kChunk;
@@ -569,10 +593,14 @@ __global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
   const int w = (blockIdx.x - B.off[s]) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   auto skip = [&] { return S.n_active[p] == 0; };
   if (S.prec == GPL_PREC_F16X3) {
-    if (S.nrhs > 16)
-      mvm_f16x3_wave<2>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
-    else
-      mvm_f16x3_wave<1>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+    const bool pk = last_block_packed(S.nrhs);
+    if (S.nrhs > 16) {
+      if (pk) mvm_f16x3_wave<2, true>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      else mvm_f16x3_wave<2, false>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+    } else {
+      if (pk) mvm_f16x3_wave<1, true>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      else mvm_f16x3_wave<1, false>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+    }
   } else {
     if (S.nrhs > 16)
       mvm_f32_wave<2>(skip, w, S.plan, S.s2, S.Vp, S.ncp, S.nrhs, S.part, S.nrhs, 0);

@@ -443,16 +443,22 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int 
   };
   // one instantiation of the tile (its LDS buffers) for both forms
   auto fetch = [&](int u, int fy, int fx) { jr[u] = o.irank[fy * M + fx]; };
+  // FP16 parts of column c: hi at slot hs of Vh, lo at the same slot of Vl or,
+  // in a packed last block, at the next slot of Vh
+  const int hs = hi_slot(c, o.nrhs);
+  const bool packed = last_block_packed(o.nrhs) && c >= packed_block_start(o.nrhs);
   psf_adjoint_tile<true>(skip, tile, c, n, ss, taps, in, ld_in, fold_scale, fetch, [&](int, int, float v, int u) {
     const float scale = f16 ? s_scale : 1.f;
-    const size_t j = rhs_at(c, jr[u], o.ncp);
     if (f16) {
+      const size_t j = rhs_at(hs, jr[u], o.ncp);
       const float sv = v * scale;
       const _Float16 h = (_Float16)sv;
+      const _Float16 l = (_Float16)(sv - (float)h);
       o.Vh[j] = h;
-      o.Vl[j] = (_Float16)(sv - (float)h);
+      if (packed) o.Vh[j + kChunk] = l;  // slot hs + 1 of the same chunk
+      else o.Vl[j] = l;
     } else {
-      o.Vp[j] = v;
+      o.Vp[rhs_at(c, jr[u], o.ncp)] = v;
     }
   });
 }
@@ -477,7 +483,7 @@ __global__ __launch_bounds__(256) void psf_adjoint_grouped_kernel(SlotBatch B, i
   const ServeSlotDev& S = *B.slot[s];
   const int local = blockIdx.x - B.off[s];
   const int tile = local % S.ntiles_adj, c = local / S.ntiles_adj;
-  const RhsOut o{S.prec, S.ncp, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd, S.plan.irank};
+  const RhsOut o{S.prec, S.nrhs, S.ncp, S.Vh, S.Vl, S.Vp, S.inv_scale, S.pmax, S.nb_upd, S.plan.irank};
   psf_adjoint_rhs_body([&] { return S.n_active[p] == 0 || S.st[p][c].active == 0; }, tile, c, S.n, S.ss, S.taps, S.P, S.ldv, o);
 }
 

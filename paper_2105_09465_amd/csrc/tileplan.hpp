@@ -111,6 +111,20 @@ __host__ __device__ inline size_t rhs_at(int c, int j, int ncp) {
   return ((size_t)(j >> 5) * ncp + c) * kChunk + (j & (kChunk - 1));
 }
 
+// The precision form's last block of 16 columns, when it holds at most 8 of the
+// nrhs columns, is packed: column c of it keeps both FP16 parts in the hi buffer,
+// hi at column slot 16 b + 2 (c - 16 b) and lo in the slot after it (b the block),
+// so that two MFMAs (hi and lo of the exp tile, each times [hi, lo] of the RHS)
+// give the column's product instead of three; the lo buffer's block is unused.
+__host__ __device__ inline bool last_block_packed(int nrhs) { return nrhs > 0 && nrhs - 16 * ((nrhs - 1) / 16) <= 8; }
+__host__ __device__ inline int packed_block_start(int nrhs) { return 16 * ((nrhs - 1) / 16); }
+// Column slot of the hi part of column c (the lo part: the same slot of the lo
+// buffer, or the next slot of the hi buffer when c is in a packed block).
+__host__ __device__ inline int hi_slot(int c, int nrhs) {
+  const int b0 = packed_block_start(nrhs);
+  return last_block_packed(nrhs) && c >= b0 ? b0 + 2 * (c - b0) : c;
+}
+
 // Bytes of the plan buffers for n points (0 for n <= 0).
 size_t plan_workspace(int n);
 // Carve the plan buffers (nullptr fields when the carver overflows).
