@@ -51,7 +51,7 @@ struct ServeSlotDev {
   const float *px, *py;
   float *X, *R, *P, *AP, *T2;
   int ldv, ldf;
-  TilePlan plan;  // tile plan of the slot's points (grid Z-order)
+  TilePlan plan;  // tile plan of the slot's points
   unsigned* pmax;  // [nrhs][nb_upd] partial max |P| (float bits)
   float* inv_scale;
   _Float16 *Vh, *Vl;  // precision form: RHS block split in sorted order
@@ -122,9 +122,10 @@ int mvm_run(const MvmCtx& m, int nrhs, const float* V, int ldv, float* Y, int ld
 // The product from RHS buffers already written (by the fused PSF adjoint).
 int mvm_run_prepared(const MvmCtx& m, int nrhs, float* Y, int ldy, float beta, CgGate gate, hipStream_t stream);
 
-// Where the fused PSF adjoint writes B^T P: the product buffers of a grid-ordered
-// plan (fine point (fx, fy) at its Z-order rank), with per-column scales of the
-// precision form taken from partial maxima of |P| (|B^T P| <= max |P| / ss^2).
+// Where the fused PSF adjoint writes B^T P: the product's RHS buffers (fine point
+// (fx, fy) at its sorted position in the plan, the FP16 parts of column c at the
+// slots hi_slot gives), with per-column scales of the precision form taken from
+// partial maxima of |P| (|B^T P| <= max |P| / ss^2).
 struct RhsOut {
   int prec;
   int nrhs;  // columns of the product (their FP16 parts are placed by hi_slot)

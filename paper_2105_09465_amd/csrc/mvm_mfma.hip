@@ -7,8 +7,9 @@
 // (tileplan.hpp), which lists for every row tile of 64 points the chunks of 32
 // points that can give a non-zero kernel value, each with the mask of the row
 // tile's four 16-point subtiles that can; every other pair contributes exact
-// zeros and is not evaluated (a masked-out subtile skips its exp tile and MFMAs). The listed (row tile, chunk) pairs are split
-// evenly over the waves of the launch, each wave taking a contiguous run of them
+// zeros and is not evaluated (a masked-out subtile skips its exp tile and
+// MFMAs). The listed (row tile, chunk) pairs are split over the waves of the
+// launch by an estimate of their cost, each wave taking a contiguous run of them
 // (so the work is balanced however unevenly the live pairs fall on row tiles).
 // A wave computes 64 rows (four 16-row MFMA tiles) at a time, with each chunk's
 // coordinates and right-hand-side block loaded straight from global memory into
@@ -22,7 +23,9 @@
 // toward zero) and lo = k - hi (exact in FP32); the RHS block is split after
 // a per-column power-of-two scale that puts its largest entry near 2^14. Each
 // 16x16x32 tile takes three MFMAs (hi.hi + hi.lo + lo.hi) into FP32
-// accumulators; the dropped lo.lo term is ~2^-22 relative.
+// accumulators; the dropped lo.lo term is ~2^-22 relative. A last block of at
+// most 8 columns is packed (hi and lo of a column side by side, see hi_slot)
+// and takes two: hi.[hi lo] + lo.[hi lo].
 //
 // FP32 form (GPL_PREC_FP32): the exp tile and the RHS in FP32 on
 // v_mfma_f32_16x16x4_f32.
