@@ -212,10 +212,12 @@ def test_kernel_mvm_fp32_mfma_parity(G, n, nrhs):
 
 
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (257, 3), (1000, 1), (3001, 17), (4096, 16), (5003, 33), (2500, 64),
-                                    (1500, 65)])
+                                    (1500, 65), (1200, 8), (1200, 9), (2000, 24), (2000, 25)])
 def test_kernel_mvm_f16x3_parity(G, n, nrhs):
     """Precision form: FP16 hi/lo split of the exp tile and of the RHS, three MFMA
-    terms, FP32 accumulation. Bound: 1e-5 of |K||V| per entry, as the FP32 form."""
+    terms, FP32 accumulation. Bound: 1e-5 of |K||V| per entry, as the FP32 form.
+    A last column block of at most 8 columns is packed (two MFMAs): 8 and 24
+    columns are the largest packed cases, 9 and 25 the smallest unpacked ones."""
     _say("mvm f16x3", n, nrhs)
     err = _mvm_case(G, n, nrhs, "f16x3", seed=11)
     print(f"max |err| / (|K||V|) = {err:.2e}")
