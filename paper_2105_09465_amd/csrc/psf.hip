@@ -203,15 +203,22 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
     const int oy = o / TP, ox = o - oy * TP;
     const int Iy = ty * TP + oy, Ix = tx * TP + ox;
     I[u] = (o < TP * TP && Iy < n && Ix < n) ? Iy * n + Ix : -1;
-    // unconditional loads at valid addresses (pixel 0, or this column of `in`
-    // for an absent operand), selected afterwards
-    const int Ic = I[u] >= 0 ? I[u] : 0;
-    const float a = out[(size_t)c * ld_out + Ic];
-    const float e = extra ? extra[(size_t)c * ld_extra + Ic] : src[Ic];
-    const float d = dotv ? dotv[(size_t)c * ld_dotv + Ic] : src[Ic];
-    o_old[u] = beta != 0.f ? a : 0.f;
-    o_ext[u] = extra ? e : 0.f;
-    o_dot[u] = dotv ? d : 0.f;
+  }
+  // unconditional loads at valid addresses (pixel 0, or this column of `in` for
+  // an absent operand), all issued after the indices are known; the values are
+  // only looked at where they are used (a select here would wait for them
+  // before the window loads are issued)
+  {
+    const float* po = out + (size_t)c * ld_out;
+    const float* pe = extra ? extra + (size_t)c * ld_extra : src;
+    const float* pd = dotv ? dotv + (size_t)c * ld_dotv : src;
+#pragma unroll
+    for (int u = 0; u < kOutPer; ++u) {
+      const int Ic = max(I[u], 0);
+      o_old[u] = po[Ic];
+      o_ext[u] = pe[Ic];
+      o_dot[u] = pd[Ic];
+    }
   }
   {
     WinRegs R;
