@@ -192,7 +192,6 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
-  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
   // this thread's output pixels (at most kOutPer) and their operands, loaded
   // together with the window
   int I[kOutPer];

@@ -17,7 +17,6 @@ namespace gpl {
 
 static_assert(sizeof(ServeSlotDev) <= sizeof(((gpl_serve_slot*)nullptr)->opaque), "slot descriptor too large");
 
-static ServeSlotDev& host_desc(gpl_serve_slot* s) { return *reinterpret_cast<ServeSlotDev*>(s->opaque); }
 static const ServeSlotDev& host_desc(const gpl_serve_slot* s) {
   return *reinterpret_cast<const ServeSlotDev*>(s->opaque);
 }
