@@ -55,7 +55,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mvm_f16x3_traffic_N40000_17cols.t
 
 def _source_hash():
     h = hashlib.sha256()
-    for f in ("mvm_mfma.hip", "mvm_mfma.hpp"):
+    for f in ("mvm_mfma.hip", "mvm_mfma.hpp", "tileplan.hpp", "tileplan.hip"):
         with open(os.path.join(ROOT, "paper_2105_09465_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
