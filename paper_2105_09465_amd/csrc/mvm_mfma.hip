@@ -272,11 +272,15 @@ __device__ __forceinline__ void f16_load(F16Chunk<CB, PK>& c, const TilePlan& P,
   c.x1 = *reinterpret_cast<const f32x4*>(&P.xs[j0 + 4]);
   c.y0 = *reinterpret_cast<const f32x4*>(&P.ys[j0]);
   c.y1 = *reinterpret_cast<const f32x4*>(&P.ys[j0 + 4]);
+  // uniform chunk base plus a fixed lane offset: little per-chunk address arithmetic
+  const size_t cbase = (size_t)entry_chunk(entry) * ncp * kChunk;
+  const _Float16* vh = Vh + cbase;
+  const _Float16* vl = Vl + cbase;
+  const unsigned lo = ri * kChunk + g * 8;
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
-    const size_t o = ((size_t)entry_chunk(entry) * ncp + cb * 16 + ri) * kChunk + g * 8;
-    c.bh[cb] = *reinterpret_cast<const half8*>(&Vh[o]);
-    if (cb < F16Chunk<CB, PK>::kLo) c.bl[cb] = *reinterpret_cast<const half8*>(&Vl[o]);
+    c.bh[cb] = *reinterpret_cast<const half8*>(vh + cb * 16 * kChunk + lo);
+    if (cb < F16Chunk<CB, PK>::kLo) c.bl[cb] = *reinterpret_cast<const half8*>(vl + cb * 16 * kChunk + lo);
   }
 }
 
@@ -365,13 +369,13 @@ __device__ __forceinline__ void f32_chunk(f32x4 (&acc)[kRT][CB], const float (&x
   *reinterpret_cast<f32x4*>(&xj[4]) = *reinterpret_cast<const f32x4*>(&P.xs[jc + 16]);
   *reinterpret_cast<f32x4*>(&yj[0]) = *reinterpret_cast<const f32x4*>(&P.ys[jc]);
   *reinterpret_cast<f32x4*>(&yj[4]) = *reinterpret_cast<const f32x4*>(&P.ys[jc + 16]);
+  const float* vp = Vp + (size_t)entry_chunk(entry) * ncp * kChunk;  // uniform chunk base
+  const unsigned lo = ri * kChunk + g * 4;
   f32x4 b[CB][2];
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-      b[cb][h] = *reinterpret_cast<const f32x4*>(&Vp[((size_t)entry_chunk(entry) * ncp + cb * 16 + ri) * kChunk +
-                                                     g * 4 + 16 * h]);
+    for (int h = 0; h < 2; ++h) b[cb][h] = *reinterpret_cast<const f32x4*>(vp + cb * 16 * kChunk + 16 * h + lo);
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
     if (!((mask >> rt) & 1u)) continue;  // every exp of this 16 x 32 tile is exactly zero
