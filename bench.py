@@ -40,11 +40,12 @@ METRIC = "kernel-MVM Gpairs/s at N=40k; reconstructions/s + p99 latency vs plain
 
 # Peak of the plain ALUs for the exp tile: 256 CUs x
 # 128 FP32 lanes x 2.4 GHz = 78.6 T FP32 VALU lane-ops/s (157.3 TFLOP/s counting
-# an FMA as two); v_exp_f32 at a quarter of that rate. One kernel pair needs at
-# least 5 FP32 VALU ops (two differences, a square, an FMA, the scale) and one
-# exp, i.e. 5 + 4 = 9 FP32-op equivalents -> 78.6e12 / 9 pairs/s.
+# an FMA as two); v_exp_f32 at a quarter of that rate. With the exp2 scale folded
+# into the coordinates once per point, one kernel pair needs at least 4 FP32 VALU
+# ops (two differences, two FMAs) and one exp, i.e. 4 + 4 = 8 FP32-op
+# equivalents -> 78.6e12 / 8 pairs/s.
 VALU_LANE_OPS = 256 * 128 * 2.4e9
-PAIR_COST = 5 + 4
+PAIR_COST = 4 + 4
 ALU_PEAK_GPAIRS = VALU_LANE_OPS / PAIR_COST / 1e9
 
 # HBM traffic of the dominant kernel per launch at this workload, from rocprofv3

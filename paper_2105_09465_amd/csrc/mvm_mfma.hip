@@ -211,13 +211,14 @@ __device__ __forceinline__ void for_chunks_pf(const uint32_t* lst, int kb, int k
 }
 
 // One wave's share of a product: for each row tile its units touch, load the
-// tile's 64 row coordinates, accumulate over the tile's chunks in the range, and
-// write the partial rows. `chunk_fn(acc, xi, yi, lst, kb, ke, lane)` accumulates
-// list positions [kb, ke) of a row tile. The wave's range comes from one
+// tile's 64 row coordinates (from rx, ry), accumulate over the tile's chunks in
+// the range, and write the partial rows. `chunk_fn(acc, xi, yi, r, lst, kb, ke,
+// lane)` accumulates list positions [kb, ke) of row tile r. The wave's range comes from one
 // descriptor load, issued together with the gate flag; `skip()` is evaluated
 // once both are in.
 template <int CB, bool PK, class S, class F>
-__device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __restrict__ part, int pcols, int c0,
+__device__ __forceinline__ void wave_product(int w, const TilePlan& P, const float* __restrict__ rx,
+                                             const float* __restrict__ ry, float* __restrict__ part, int pcols, int c0,
                                              int ncols, S&& skip, F&& chunk_fn) {
   const int4 d = P.wdesc[w];
   int rest = P.wrest[w];
@@ -230,15 +231,15 @@ __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
       const int i = r * kRowTile + rt * 16 + ri;
-      xi[rt] = P.xs[i];
-      yi[rt] = P.ys[i];
+      xi[rt] = rx[i];
+      yi[rt] = ry[i];
     }
     f32x4 acc[kRT][CB];
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[rt][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    chunk_fn(acc, xi, yi, P.list + (size_t)r * P.nch, kb, ke, lane);
+    chunk_fn(acc, xi, yi, r, P.list + (size_t)r * P.nch, kb, ke, lane);
     store_partial<CB, PK>(acc, slot, part, pcols, c0, ncols, ri, g);
     if (rest <= 0) break;
     ++r;
@@ -251,15 +252,17 @@ __device__ __forceinline__ void wave_product(int w, const TilePlan& P, float* __
 
 // ---------------------------------------------------------------- precision form
 
-// Operands of one chunk for one lane: its 8 consecutive source points, the
-// hi/lo RHS fragments of every column block (columns past nrhs are zero) and
-// the (uniform) mask of the subtiles that see the chunk.
+// Operands of one chunk for one lane: its 8 consecutive source points (scaled
+// and block-centred), the hi/lo RHS fragments of every column block (columns
+// past nrhs are zero), and the (uniform) centre of the chunk's block and mask of
+// the subtiles that see the chunk.
 template <int CB, bool PK>
 struct F16Chunk {
   static constexpr int kLo = CB - (PK ? 1 : 0);  // blocks with a separate lo fragment
-  static constexpr int kLoads = 4 + CB + kLo;    // vector loads issued by f16_load
+  static constexpr int kLoads = 5 + CB + kLo;    // vector loads issued by f16_load
   f32x4 x0, x1, y0, y1;
   half8 bh[CB], bl[kLo > 0 ? kLo : 1];
+  float2 cen;
   unsigned mask;
 };
 
@@ -267,11 +270,12 @@ template <int CB, bool PK>
 __device__ __forceinline__ void f16_load(F16Chunk<CB, PK>& c, const TilePlan& P, const _Float16* __restrict__ Vh,
                                          const _Float16* __restrict__ Vl, int ncp, uint32_t entry, int ri, int g) {
   c.mask = entry_mask(entry);
+  c.cen = P.cen[entry_chunk(entry) / kChunksPerTile];  // uniform address, one vector load
   const int j0 = entry_chunk(entry) * kChunk + g * 8;
-  c.x0 = *reinterpret_cast<const f32x4*>(&P.xs[j0]);
-  c.x1 = *reinterpret_cast<const f32x4*>(&P.xs[j0 + 4]);
-  c.y0 = *reinterpret_cast<const f32x4*>(&P.ys[j0]);
-  c.y1 = *reinterpret_cast<const f32x4*>(&P.ys[j0 + 4]);
+  c.x0 = *reinterpret_cast<const f32x4*>(&P.xc[j0]);
+  c.x1 = *reinterpret_cast<const f32x4*>(&P.xc[j0 + 4]);
+  c.y0 = *reinterpret_cast<const f32x4*>(&P.yc[j0]);
+  c.y1 = *reinterpret_cast<const f32x4*>(&P.yc[j0 + 4]);
   // uniform chunk base plus a fixed lane offset: little per-chunk address arithmetic
   const size_t cbase = (size_t)entry_chunk(entry) * ncp * kChunk;
   const _Float16* vh = Vh + cbase;
@@ -286,25 +290,27 @@ __device__ __forceinline__ void f16_load(F16Chunk<CB, PK>& c, const TilePlan& P,
 
 template <int CB, bool PK>
 __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chunk<CB, PK>& c, const float (&xi)[kRT],
-                                            const float (&yi)[kRT], float s2) {
+                                            const float (&yi)[kRT], float2 rcen) {
+  // scaled differences: (xi + (centre_i - centre_j)) - xj, the centre
+  // difference exact (both multiples of 2^-12) and uniform over the chunk
+  const float ox = rcen.x - c.cen.x, oy = rcen.y - c.cen.y;
   const float xj[8] = {c.x0[0], c.x0[1], c.x0[2], c.x0[3], c.x1[0], c.x1[1], c.x1[2], c.x1[3]};
   const float yj[8] = {c.y0[0], c.y0[1], c.y0[2], c.y0[3], c.y1[0], c.y1[1], c.y1[2], c.y1[3]};
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
     if (!((c.mask >> rt) & 1u)) continue;  // every exp of this 16 x 32 tile is exactly zero
-    float lf[8], dx[8], dy[8], d2[8], k2[8];
+    float lf[8], dx[8], dy[8], a[8], k2[8];
+    const float xe = xi[rt] + ox, ye = yi[rt] + oy;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dx[e] = xi[rt] - xj[e];
+    for (int e = 0; e < 8; ++e) dx[e] = xe - xj[e];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dy[e] = yi[rt] - yj[e];
+    for (int e = 0; e < 8; ++e) dy[e] = ye - yj[e];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d2[e] = dy[e] * dy[e];
+    for (int e = 0; e < 8; ++e) a[e] = fmaf(-dy[e], dy[e], 11.f);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d2[e] = fmaf(dx[e], dx[e], d2[e]);
+    for (int e = 0; e < 8; ++e) a[e] = fmaf(-dx[e], dx[e], a[e]);  // 11 - s2 d^2
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d2[e] = fmaf(d2[e], -s2, 11.f);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) k2[e] = exp2_fast(d2[e]);  // 2^11 k
+    for (int e = 0; e < 8; ++e) k2[e] = exp2_fast(a[e]);  // 2^11 k
     half8 hi, lo;
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
@@ -333,26 +339,27 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
 }
 
 template <int CB, bool PK, class Skip>
-__device__ __forceinline__ void mvm_f16x3_wave(Skip&& skip, int w, const TilePlan& P, float s2, const _Float16* __restrict__ Vh,
+__device__ __forceinline__ void mvm_f16x3_wave(Skip&& skip, int w, const TilePlan& P, const _Float16* __restrict__ Vh,
                                                const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
-  wave_product<CB, PK>(w, P, part, pcols, c0, ncols, skip,
-                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
-                       int kb, int ke, int lane) {
+  wave_product<CB, PK>(w, P, P.xc, P.yc, part, pcols, c0, ncols, skip,
+                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], int r,
+                       const uint32_t* lst, int kb, int ke, int lane) {
+                     const float2 rcen = P.cen[r];
                      for_chunks_pf<F16Chunk<CB, PK>>(lst, kb, ke, lane,
                          [&](F16Chunk<CB, PK>& c, uint32_t e) { f16_load(c, P, Vh, Vl, ncp, e, ri, g); },
-                         [&](const F16Chunk<CB, PK>& c) { f16_compute(acc, c, xi, yi, s2); });
+                         [&](const F16Chunk<CB, PK>& c) { f16_compute(acc, c, xi, yi, rcen); });
                    });
 }
 
 // One wave per share of the plan's units; 4 independent waves per workgroup.
 template <int CB, bool PK>
-__global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, float s2, const _Float16* __restrict__ Vh,
+__global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, const _Float16* __restrict__ Vh,
                                                         const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                         float* __restrict__ part, int pcols, int c0, CgGate gate) {
   const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  mvm_f16x3_wave<CB, PK>([&] { return gate.skip_all(); }, w, P, s2, Vh, Vl, ncp, ncols, part, pcols, c0);
+  mvm_f16x3_wave<CB, PK>([&] { return gate.skip_all(); }, w, P, Vh, Vl, ncp, ncols, part, pcols, c0);
 }
 
 // ---------------------------------------------------------------- FP32 form
@@ -398,9 +405,9 @@ template <int CB, class Skip>
 __device__ __forceinline__ void mvm_f32_wave(Skip&& skip, int w, const TilePlan& P, float s2, const float* __restrict__ Vp,
                                              int ncp, int ncols, float* __restrict__ part, int pcols, int c0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
-  wave_product<CB, false>(w, P, part, pcols, c0, ncols, skip,
-                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], const uint32_t* lst,
-                       int kb, int ke, int lane) {
+  wave_product<CB, false>(w, P, P.xs, P.ys, part, pcols, c0, ncols, skip,
+                   [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], int,
+                       const uint32_t* lst, int kb, int ke, int lane) {
                      for_chunks(lst, kb, ke, lane,
                                 [&](uint32_t e) { f32_chunk<CB>(acc, xi, yi, P, s2, Vp, ncp, e, ri, g); });
                    });
@@ -488,13 +495,13 @@ float plan_threshold(int prec) { return prec == GPL_PREC_F16X3 ? kSkipF16x3 : kS
 // ---------------------------------------------------------------- launches
 
 template <int CB>
-static void launch_f16x3(bool packed, const TilePlan& P, float s2, const _Float16* Vh, const _Float16* Vl, int ncp,
+static void launch_f16x3(bool packed, const TilePlan& P, const _Float16* Vh, const _Float16* Vl, int ncp,
                          int ncols, float* part, int pcols, int c0, CgGate gate, hipStream_t stream) {
   if (packed)
-    hipLaunchKernelGGL((mvm_f16x3_kernel<CB, true>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ncp,
+    hipLaunchKernelGGL((mvm_f16x3_kernel<CB, true>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, Vh, Vl, ncp,
                        ncols, part, pcols, c0, gate);
   else
-    hipLaunchKernelGGL((mvm_f16x3_kernel<CB, false>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, s2, Vh, Vl, ncp,
+    hipLaunchKernelGGL((mvm_f16x3_kernel<CB, false>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, Vh, Vl, ncp,
                        ncols, part, pcols, c0, gate);
 }
 
@@ -565,10 +572,10 @@ int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float
       const _Float16* vl = b.Vl + (size_t)c0 * kChunk;
       const bool pk = c0 + cb * 16 >= nrhs && last_block_packed(nrhs);
       switch (cb) {
-        case 4: launch_f16x3<4>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 3: launch_f16x3<3>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
-        case 2: launch_f16x3<2>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
-        default: launch_f16x3<1>(pk, P, s2, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 4: launch_f16x3<4>(pk, P, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 3: launch_f16x3<3>(pk, P, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        case 2: launch_f16x3<2>(pk, P, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
+        default: launch_f16x3<1>(pk, P, vh, vl, b.ncp, ncols, b.part, nrhs, c0, gate, stream); break;
       }
     } else {
       const float* vp = b.Vp + (size_t)c0 * kChunk;
@@ -602,11 +609,11 @@ __global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
   if (S.prec == GPL_PREC_F16X3) {
     const bool pk = last_block_packed(S.nrhs);
     if (S.nrhs > 16) {
-      if (pk) mvm_f16x3_wave<2, true>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
-      else mvm_f16x3_wave<2, false>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      if (pk) mvm_f16x3_wave<2, true>(skip, w, S.plan, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      else mvm_f16x3_wave<2, false>(skip, w, S.plan, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
     } else {
-      if (pk) mvm_f16x3_wave<1, true>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
-      else mvm_f16x3_wave<1, false>(skip, w, S.plan, S.s2, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      if (pk) mvm_f16x3_wave<1, true>(skip, w, S.plan, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
+      else mvm_f16x3_wave<1, false>(skip, w, S.plan, S.Vh, S.Vl, S.ncp, S.nrhs, S.part, S.nrhs, 0);
     }
   } else {
     if (S.nrhs > 16)

@@ -179,6 +179,27 @@ __global__ void plan_points_kernel(int n, int npad, const float* __restrict__ px
   ys[r] = py[i];
 }
 
+// Scaled, block-centred coordinates (TilePlan::xc, yc, cen): thread r handles
+// sorted position r. The block centre is the middle of the block's box, scaled
+// and rounded to a multiple of 2^-12 (a float), and xc = sqrt(s2) x - centre is
+// formed in FP64 and rounded once.
+__global__ void plan_scaled_kernel(int npad, const float* __restrict__ xs, const float* __restrict__ ys,
+                                   const float4* __restrict__ cbox, float s2, float* __restrict__ xc,
+                                   float* __restrict__ yc, float2* __restrict__ cen) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= npad) return;
+  const int b = r / kRowTile;
+  const double sg = sqrt((double)s2);
+  const float4 u = cbox[kChunksPerTile * b], v = cbox[kChunksPerTile * b + 1];
+  const double mx = 0.5 * ((double)fminf(u.x, v.x) + (double)fmaxf(u.y, v.y));
+  const double my = 0.5 * ((double)fminf(u.z, v.z) + (double)fmaxf(u.w, v.w));
+  const float cx = isfinite(mx) ? (float)(rint(mx * sg * 4096.0) / 4096.0) : 0.f;
+  const float cy = isfinite(my) ? (float)(rint(my * sg * 4096.0) / 4096.0) : 0.f;
+  xc[r] = (float)((double)xs[r] * sg - (double)cx);
+  yc[r] = (float)((double)ys[r] * sg - (double)cy);
+  if (r == b * kRowTile) cen[b] = make_float2(cx, cy);
+}
+
 // Bounding box of the valid points in [j0, j1); a non-finite coordinate gives
 // an infinite box (never dropped), no valid point an empty one (always dropped).
 __device__ __forceinline__ float4 point_box(const float* __restrict__ xs, const float* __restrict__ ys, int j0,
@@ -426,20 +447,24 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   int* perm = const_cast<int*>(p.perm);
   int* irank = const_cast<int*>(p.irank);
   const int nsb = sort_blocks(n);
-  hipLaunchKernelGGL(plan_extent_kernel, dim3(1), dim3(1024), 0, stream, n, px, py, p.sext);
+  // sort scratch in buffers that are written only after the sort: the extent in
+  // cbox[0], the keys in xc and yc, the scan totals in total
+  float4* ext = p.cbox;
+  hipLaunchKernelGGL(plan_extent_kernel, dim3(1), dim3(1024), 0, stream, n, px, py, ext);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(plan_keys_kernel, dim3(cdiv(n, 256)), dim3(256), 0, stream, n, px, py, p.sext, p.skey0);
+  hipLaunchKernelGGL(plan_keys_kernel, dim3(cdiv(n, 256)), dim3(256), 0, stream, n, px, py, ext,
+                     reinterpret_cast<uint32_t*>(p.xc));
   GPL_LAUNCH_CHECK();
-  // ping-pong: keys skey0 <-> skey1, caller indices (identity) -> sval <-> perm
-  uint32_t* kin = p.skey0;
-  uint32_t* kout = p.skey1;
+  // ping-pong: keys xc <-> yc, caller indices (identity) -> sval <-> perm
+  uint32_t* kin = reinterpret_cast<uint32_t*>(p.xc);
+  uint32_t* kout = reinterpret_cast<uint32_t*>(p.yc);
   const int* vin = nullptr;
   int* vout = p.sval;
   for (int pass = 0; pass < kSortPasses; ++pass) {
     hipLaunchKernelGGL(sort_count_kernel, dim3(nsb), dim3(kSortBlock), 0, stream, n, nsb, 8 * pass, kin, p.shist);
     GPL_LAUNCH_CHECK();
     hipLaunchKernelGGL(plan_scan_kernel<int>, dim3(1), dim3(1024), 0, stream, kSortDigits * nsb, p.shist, p.shist,
-                       p.ssum);
+                       p.total);
     GPL_LAUNCH_CHECK();
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(nsb), dim3(kSortBlock), 0, stream, n, nsb, 8 * pass, kin, vin,
                        p.shist, kout, vout);
@@ -453,6 +478,9 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_boxes_kernel, dim3(cdiv(p.nch, 256)), dim3(256), 0, stream, n, p.nch, p.xs, p.ys, p.cbox,
                      p.sbox);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(plan_scaled_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, p.npad, p.xs, p.ys, p.cbox, s2,
+                     p.xc, p.yc, p.cen);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_lists_kernel, dim3(p.nrt), dim3(64), 0, stream, p.nrt, p.nch, p.cbox, p.sbox, s2,
                      threshold, p.count, p.list, p.roww);

@@ -64,6 +64,13 @@ struct TilePlan {
   const int* perm;  // [npad] sorted position -> caller index (-1 past n)
   const int* irank; // [npad] caller index -> sorted position (first n entries)
   float *xs, *ys;   // [npad] points in sorted order, zero padded
+  // The same points for the precision form's product: scaled by sqrt(s2) and
+  // taken relative to the scaled centre of their 64-point block, cen[j / 64]
+  // (a multiple of 2^-12, 0 for a block without a finite box), so that
+  // sqrt(s2) (p_i - p_j) = (xc_i + (cen_i - cen_j)) - xc_j with every term of
+  // the size of the blocks, not of the coordinates.
+  float *xc, *yc;   // [npad]
+  float2* cen;      // [nrt]
   float4* cbox;     // [nch] (xmin, xmax, ymin, ymax); empty chunks have xmin = +inf
   float4* sbox;     // [kSubsPerTile nrt] the same for every 16-point subtile
   int* count;       // [nrt] live chunks of each row tile
@@ -79,12 +86,10 @@ struct TilePlan {
   int* roww;        // [nrt] cost estimate of each row tile
   long long* rowwoff;  // [nrt] exclusive prefix of roww
   long long* wtot;     // [1] total cost
-  // scratch of the sort that orders the points (used while the plan is built)
-  uint32_t *skey0, *skey1;  // [npad] Hilbert keys, ping-pong
+  // scratch of the sort that orders the points (used while the plan is built;
+  // its Hilbert keys and extent live in xc, yc and cbox, written after the sort)
   int* sval;                // [npad] caller indices, ping-pong partner of perm
   int* shist;               // [kSortDigits nsb] digit counts per sort block, then their offsets
-  float4* sext;             // [1] extent of the finite points
-  int* ssum;                // [1] scan total (unused)
 };
 
 // Sort of the points: Hilbert index of 12 bits per axis over the square that
@@ -140,6 +145,9 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.irank = cv.template take<int>((size_t)p.npad);
   p.xs = cv.template take<float>((size_t)p.npad);
   p.ys = cv.template take<float>((size_t)p.npad);
+  p.xc = cv.template take<float>((size_t)p.npad);
+  p.yc = cv.template take<float>((size_t)p.npad);
+  p.cen = cv.template take<float2>((size_t)p.nrt);
   p.cbox = cv.template take<float4>((size_t)p.nch);
   p.sbox = cv.template take<float4>((size_t)p.nrt * kSubsPerTile);
   p.count = cv.template take<int>((size_t)p.nrt);
@@ -155,12 +163,8 @@ void plan_carve(C& cv, int n, TilePlan& p) {
   p.roww = cv.template take<int>((size_t)p.nrt);
   p.rowwoff = cv.template take<long long>((size_t)p.nrt);
   p.wtot = cv.template take<long long>(1);
-  p.skey0 = cv.template take<uint32_t>((size_t)p.npad);
-  p.skey1 = cv.template take<uint32_t>((size_t)p.npad);
   p.sval = cv.template take<int>((size_t)p.npad);
   p.shist = cv.template take<int>((size_t)kSortDigits * sort_blocks(n));
-  p.sext = cv.template take<float4>(1);
-  p.ssum = cv.template take<int>(1);
 }
 
 // Build the plan on `stream`. The points are sorted along the Hilbert curve of
