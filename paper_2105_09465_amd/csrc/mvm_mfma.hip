@@ -601,7 +601,10 @@ int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float
 // result does not depend on the other slots. The slot's RHS block is written by
 // the grouped PSF adjoint.
 
-__global__ __launch_bounds__(256) void mvm_grouped_kernel(SlotBatch B, int p) {
+// The grouped kernel holds every wave variant, so its register count is their
+// union; three waves per SIMD (at most 168 VGPRs) are asked for explicitly, as
+// a batch of slots usually has more waves than the SIMDs hold at once.
+__global__ __launch_bounds__(256, 3) void mvm_grouped_kernel(SlotBatch B, int p) {
   const int s = B.find(blockIdx.x);
   const ServeSlotDev& S = *B.slot[s];
   const int w = (blockIdx.x - B.off[s]) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
