@@ -280,6 +280,30 @@ def test_kernel_mvm_ties_and_outliers(G, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_kernel_mvm_offset_cloud(G, prec):
+    """A point cloud far from the origin (offset of ~900 lengthscales, N = 3001,
+    17 columns): every kernel value depends only on differences, so the product
+    must keep its accuracy. The precision form scales the coordinates by
+    sqrt(s2) once per point; taken relative to the origin, that rounding alone
+    gives ~2e-5 of |K||V| here (measured with the centres set to zero), relative
+    to each 64-point block's centre ~3e-7."""
+    _say("mvm offset cloud", prec)
+    rng = np.random.default_rng(43)
+    n = 3001
+    px = (rng.uniform(-0.6, 0.6, n) + 37.5).astype(np.float32)
+    py = (rng.uniform(-0.6, 0.6, n) - 21.25).astype(np.float32)
+    V = rng.standard_normal((17, n)).astype(np.float32)
+    Y = t64(G.ops.kernel_mvm(G.Kernel(0.04, 0.3), cuda32(px), cuda32(py), cuda32(V), prec=prec))
+    P64 = (px.astype(np.float64), py.astype(np.float64))
+    rows = np.arange(n)
+    want = okernel.kernel_mvm_rows(*P64, rows, V.astype(np.float64).T, 0.04, 0.3)
+    scale = okernel.kernel_abs_mvm_rows(*P64, rows, V.astype(np.float64).T, 0.04, 0.3)
+    err = np.max(np.abs(Y.T - want) / scale)
+    print(f"max |err| / (|K||V|) = {err:.2e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
 def test_kernel_mvm_grid_tiles(G, prec):
     """Lensed points of the 100x100, ss = 2 workload (N = 40,000), which the
     product sorts along a Hilbert curve of their source-plane positions: most
