@@ -263,13 +263,14 @@ struct F16Chunk {
   f32x4 x0, x1, y0, y1;
   half8 bh[CB], bl[kLo > 0 ? kLo : 1];
   float2 cen;
-  unsigned mask;
+  unsigned mask, lomask;
 };
 
 template <int CB, bool PK>
 __device__ __forceinline__ void f16_load(F16Chunk<CB, PK>& c, const TilePlan& P, const _Float16* __restrict__ Vh,
                                          const _Float16* __restrict__ Vl, int ncp, uint32_t entry, int ri, int g) {
   c.mask = entry_mask(entry);
+  c.lomask = entry_lomask(entry);
   c.cen = P.cen[entry_chunk(entry) / kChunksPerTile];  // uniform address, one vector load
   const int j0 = entry_chunk(entry) * kChunk + g * 8;
   c.x0 = *reinterpret_cast<const f32x4*>(&P.xc[j0]);
@@ -311,20 +312,15 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
     for (int e = 0; e < 8; ++e) a[e] = fmaf(-dx[e], dx[e], a[e]);  // 11 - s2 d^2
 #pragma unroll
     for (int e = 0; e < 8; ++e) k2[e] = exp2_fast(a[e]);  // 2^11 k
-    half8 hi, lo;
+    // hi = 2^11 k truncated to FP16
+    half8 hi;
+    decltype(__builtin_amdgcn_cvt_pkrtz(0.f, 0.f)) hp[4];
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
-      // hi = 2^11 k truncated to FP16; lo = 2^11 k - hi exactly, formed from the
-      // FP16 half in one v_fma_mix_f32 (no compiler builtin selects it)
-      const auto hp = __builtin_amdgcn_cvt_pkrtz(k2[e], k2[e + 1]);
-      const half2v h = __builtin_bit_cast(half2v, hp);
-      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lf[e]) : "v"(hp), "v"(k2[e]));
-      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(lf[e + 1]) : "v"(hp), "v"(k2[e + 1]));
-      const half2v l = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(lf[e], lf[e + 1]));
+      hp[e / 2] = __builtin_amdgcn_cvt_pkrtz(k2[e], k2[e + 1]);
+      const half2v h = __builtin_bit_cast(half2v, hp[e / 2]);
       hi[e] = h[0];
       hi[e + 1] = h[1];
-      lo[e] = l[0];
-      lo[e + 1] = l[1];
     }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
@@ -332,6 +328,20 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
 #pragma unroll
     for (int cb = 0; cb < F16Chunk<CB, PK>::kLo; ++cb)
       acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi, c.bl[cb], acc[rt][cb], 0, 0, 0);
+    if (!((c.lomask >> rt) & 1u)) continue;  // every k of the tile <= 2^-20: lo below 2^-30
+    // lo = 2^11 k - hi exactly, formed from the FP16 half in one v_fma_mix_f32
+    // (no compiler builtin selects it)
+    half8 lo;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lf[e]) : "v"(hp[e / 2]), "v"(k2[e]));
+      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+          : "=v"(lf[e + 1])
+          : "v"(hp[e / 2]), "v"(k2[e + 1]));
+      const half2v l = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(lf[e], lf[e + 1]));
+      lo[e] = l[0];
+      lo[e + 1] = l[1];
+    }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
       acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo, c.bh[cb], acc[rt][cb], 0, 0, 0);

@@ -238,10 +238,11 @@ __device__ __forceinline__ bool boxes_live(const float4& a, const float4& q, flo
 }
 
 // One wave per row tile: ascending list of live chunks by ballot compaction,
-// each entry with the mask of the subtiles that see the chunk.
+// each entry with the mask of the subtiles that see the chunk and the mask of
+// those that also need the lo part (gap below lo_threshold).
 __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const float4* __restrict__ cbox,
                                                         const float4* __restrict__ sbox, float s2, float threshold,
-                                                        int* count, uint32_t* list, int* roww) {
+                                                        float lo_threshold, int* count, uint32_t* list, int* roww) {
   const int r = blockIdx.x;
   if (r >= nrt) return;
   const int lane = threadIdx.x;
@@ -263,10 +264,13 @@ __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const 
       const float4 q = cbox[c];
       if (boxes_live(rb, q, s2, threshold)) {
 #pragma unroll
-        for (int t = 0; t < kSubsPerTile; ++t) mask |= (boxes_live(sb[t], q, s2, threshold) ? 1u : 0u) << t;
+        for (int t = 0; t < kSubsPerTile; ++t) {
+          mask |= (boxes_live(sb[t], q, s2, threshold) ? 1u : 0u) << t;
+          mask |= (boxes_live(sb[t], q, s2, lo_threshold) ? 1u : 0u) << (4 + t);
+        }
       }
     }
-    const bool live = mask != 0u;
+    const bool live = (mask & 0xfu) != 0u;
     const unsigned long long bal = __ballot(live);
     const uint32_t e = (uint32_t)c | (mask << 16);
     if (live) {
@@ -482,8 +486,9 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   hipLaunchKernelGGL(plan_scaled_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, p.npad, p.xs, p.ys, p.cbox, s2,
                      p.xc, p.yc, p.cen);
   GPL_LAUNCH_CHECK();
+  const float lo_threshold = threshold == kSkipF16x3 ? kLoF16x3 : threshold;
   hipLaunchKernelGGL(plan_lists_kernel, dim3(p.nrt), dim3(64), 0, stream, p.nrt, p.nch, p.cbox, p.sbox, s2,
-                     threshold, p.count, p.list, p.roww);
+                     threshold, lo_threshold, p.count, p.list, p.roww);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(plan_scan_kernel<int>, dim3(1), dim3(1024), 0, stream, p.nrt, p.count, p.unit_off, p.total);
   GPL_LAUNCH_CHECK();

@@ -33,11 +33,19 @@ constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
 // margin for the FP32 rounding of the box gap and of d^2).
 constexpr float kSkipF16x3 = 36.f;
 constexpr float kSkipFp32 = 152.f;
+// In the precision form a (subtile, chunk) pair with s2 g^2 >= kLoF16x3 has
+// every kernel value k <= 2^-20, so the lo part of its exp tile (below 2^-10 k)
+// is below 2^-30 per entry, under a 2^-20 share of the FP32 rounding of an
+// entry of size one: such pairs multiply the hi part only.
+constexpr float kLoF16x3 = 20.f;
 
 // List entries: chunk index in the low 16 bits, bit 16 + t set when subtile t of
-// the row tile can see the chunk (entries with no such bit are not listed).
+// the row tile can see the chunk (entries with no such bit are not listed), bit
+// 20 + t set when that pair also needs the lo part of the exp tile (the same
+// bits as the first mask in the FP32 form).
 __host__ __device__ inline int entry_chunk(uint32_t e) { return (int)(e & 0xffffu); }
-__host__ __device__ inline unsigned entry_mask(uint32_t e) { return e >> 16; }
+__host__ __device__ inline unsigned entry_mask(uint32_t e) { return (e >> 16) & 0xfu; }
+__host__ __device__ inline unsigned entry_lomask(uint32_t e) { return (e >> 20) & 0xfu; }
 
 // The evaluated work is a sequence of units, the live (row tile, chunk) pairs in
 // row-tile order (T units in all). A product launch of nw waves gives each wave
@@ -171,7 +179,8 @@ void plan_carve(C& cv, int n, TilePlan& p) {
 // their positions (ties in caller order, so the plan depends only on the
 // points). `grid` (nullable) is checked against n: with one, the points are its
 // fine grid in row-major order, which is what irank is indexed by in the fused
-// PSF adjoint. `s2` is the exp2 scale, `threshold` one of kSkipF16x3 / kSkipFp32.
+// PSF adjoint. `s2` is the exp2 scale, `threshold` one of kSkipF16x3 / kSkipFp32
+// (with kSkipF16x3 the lo masks use kLoF16x3).
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
                hipStream_t stream);
 
@@ -190,11 +199,15 @@ __host__ __device__ inline long long wave_weight_below(int w, int wround) {
   return c;
 }
 
-// Cost estimate of a unit (per live subtile and fixed) and of a row tile, in the
-// ratio measured for the precision form.
-constexpr int kCostSubtile = 4;
+// Cost estimate of a unit (per live subtile, per subtile that also needs the lo
+// part, and fixed) and of a row tile, in the ratio measured for the precision form.
+constexpr int kCostSubtile = 3;
+constexpr int kCostSubtileLo = 1;
 constexpr int kCostUnit = 5;
 constexpr int kCostRowTile = 36;
-__host__ __device__ inline int unit_cost(uint32_t e) { return kCostSubtile * __builtin_popcount(entry_mask(e)) + kCostUnit; }
+__host__ __device__ inline int unit_cost(uint32_t e) {
+  return kCostSubtile * __builtin_popcount(entry_mask(e)) + kCostSubtileLo * __builtin_popcount(entry_lomask(e)) +
+         kCostUnit;
+}
 
 }  // namespace gpl
