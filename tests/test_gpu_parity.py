@@ -280,6 +280,27 @@ def test_kernel_mvm_ties_and_outliers(G, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_kernel_mvm_constant_rhs(G, prec):
+    """V = 1 in every column (N = 3001, 3 columns): Y is a^2 times the row sums
+    of K, so the truncation errors of the exp tile all have the same sign and
+    add up instead of cancelling (the RTZ hi part, and the lo part the precision
+    form drops where every k of a tile is below 2^-20). Bound: 1e-5 of the row
+    sum, as for random V."""
+    _say("mvm constant rhs", prec)
+    rng = np.random.default_rng(44)
+    n = 3001
+    px = rng.uniform(-0.6, 0.6, n).astype(np.float32)
+    py = rng.uniform(-0.6, 0.6, n).astype(np.float32)
+    V = np.ones((3, n), np.float32)
+    Y = t64(G.ops.kernel_mvm(G.Kernel(0.04, 0.3), cuda32(px), cuda32(py), cuda32(V), prec=prec))
+    P64 = (px.astype(np.float64), py.astype(np.float64))
+    want = okernel.kernel_mvm_rows(*P64, np.arange(n), V.astype(np.float64).T, 0.04, 0.3)
+    err = np.max(np.abs(Y.T - want) / want)
+    print(f"max |err| / (K 1) = {err:.2e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
 def test_kernel_mvm_offset_cloud(G, prec):
     """A point cloud far from the origin (offset of ~900 lengthscales, N = 3001,
     17 columns): every kernel value depends only on differences, so the product
