@@ -193,6 +193,36 @@ def kernel_only(G, torch, prec, reps):
     print(json.dumps({"kernel_only": reps, "copy_bytes": src.numel() * 4}), flush=True)
 
 
+def gradient_only(G, torch, synth, prec, reps):
+    """Timing of the backward path at the bench shape: ray tracing of the
+    40,000 points, one reconstruction, then `reps` evaluations of the 12-component
+    gradients of ln p and L_VI (the adjoints of the product with its tiles
+    recomputed, of ray tracing and of the Sersic mean). Prints one JSON line."""
+    import time
+    prob, z = load_workload()
+    npix = prob.grid.n_pix
+    d = torch.as_tensor(z["d"], dtype=torch.float32, device="cuda")
+    probes = torch.as_tensor(synth.rademacher(npix, 16, 1).T.copy(), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        G.ops.lens_raytrace(prob.grid, prob.lens)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        G.ops.lens_raytrace(prob.grid, prob.lens)
+    torch.cuda.synchronize()
+    t_ray = (time.perf_counter() - t0) / 20
+    rec = G.reconstruct(prob, d, probes, prec=prec, tol=1e-6, max_iter=1000, n_lanczos=N_LANCZOS)
+    G.autograd.evidence_gradients(prob, rec)  # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = G.autograd.evidence_gradients(prob, rec)
+    torch.cuda.synchronize()
+    t_grad = (time.perf_counter() - t0) / reps
+    print(json.dumps({"gradient_only": reps, "prec": prec, "N": prob.grid.N, "raytrace_ms": t_ray * 1e3,
+                      "gradients_ms": t_grad * 1e3, "components": int(g["lnp"].numel())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +234,9 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="run only the dominant kernel this many times at the bench shape, then a 1 GiB copy "
                          "(calibration of the HBM byte counters), and exit; for rocprofv3 counter runs")
+    ap.add_argument("--gradient-only", type=int, default=0,
+                    help="time ray tracing and this many evaluations of the evidence gradients at the bench shape, "
+                         "print one JSON line and exit")
     ap.add_argument("--serve-requests", type=int, default=128,
                     help="requests in the serving trace (0: skip; the full trace has 512)")
     args = ap.parse_args()
@@ -221,6 +254,9 @@ def main():
     torch.cuda.set_device(0)
     if args.kernel_only > 0:
         kernel_only(G, torch, args.prec, args.kernel_only)
+        return
+    if args.gradient_only > 0:
+        gradient_only(G, torch, synth, args.prec, args.gradient_only)
         return
     prob, z = load_workload()
     N, npix = prob.grid.N, prob.grid.n_pix

@@ -235,7 +235,9 @@ int gpl_timing_samples(float* ms, int cap, int* count, int reset);
  * with respect to the points, the lengthscale and the amplitude, kernel tiles
  * recomputed: gpx[i] += dF/dpx_i, gpy[i] += dF/dpy_i (FP32, accumulated),
  * g_hyp[0] = dF/d lengthscale, g_hyp[1] = dF/d amplitude (FP64, overwritten).
- * w is a HOST array of npairs weights. */
+ * w is a HOST array of npairs weights. The points are sorted as for the product
+ * (a tile plan is built in the workspace, so n is bounded as there), and pairs
+ * whose FP32 kernel value is exactly zero are skipped. */
 size_t gpl_gp_kernel_mvm_backward_workspace(int n, int npairs);
 int gpl_gp_kernel_mvm_backward(const gpl_kernel* kern, int n, const float* px, const float* py, int npairs,
                                const float* A, int lda, const float* Bv, int ldb, const double* w, float* gpx,

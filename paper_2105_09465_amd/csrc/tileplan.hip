@@ -229,14 +229,6 @@ __global__ void plan_boxes_kernel(int n, int nch, const float* __restrict__ xs, 
   cbox[c] = make_float4(fminf(a.x, b.x), fmaxf(a.y, b.y), fminf(a.z, b.z), fmaxf(a.w, b.w));
 }
 
-// s2 g^2 < threshold for the gap g between two boxes (NaN-free: an infinite box
-// gives a zero gap, an empty one an infinite gap).
-__device__ __forceinline__ bool boxes_live(const float4& a, const float4& q, float s2, float threshold) {
-  const float gx = fmaxf(0.f, fmaxf(q.x - a.y, a.x - q.y));
-  const float gy = fmaxf(0.f, fmaxf(q.z - a.w, a.z - q.w));
-  return !(s2 * fmaf(gx, gx, gy * gy) >= threshold);
-}
-
 // One wave per row tile: ascending list of live chunks by ballot compaction,
 // each entry with the mask of the subtiles that see the chunk and the mask of
 // those that also need the lo part (gap below lo_threshold).
@@ -287,18 +279,33 @@ __global__ __launch_bounds__(64) void plan_lists_kernel(int nrt, int nch, const 
 }
 
 // Exclusive prefix sum of n ints in one workgroup of 1024 threads (in place
-// allowed); the sum goes to *sum.
+// allowed); the sum goes to *sum. A round covers 16384 entries: they are loaded
+// into LDS with coalesced loads, each thread scans 16 consecutive ones (row
+// stride 17 words, so the 64 lanes of a wave hit distinct banks), the thread
+// totals are scanned across the workgroup, and the results go back through LDS
+// to coalesced stores. T (the output type) is int or long long.
+constexpr int kScanIpt = 16;
+constexpr int kScanRound = 1024 * kScanIpt;
 template <class T>
 __global__ __launch_bounds__(1024) void plan_scan_kernel(int n, const int* in, T* out, T* sum) {
+  __shared__ T buf[1024 * (kScanIpt + 1)];
   __shared__ T wsum[16];
   __shared__ T carry_s;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid == 0) carry_s = 0;
-  __syncthreads();
-  for (int base = 0; base < n; base += 1024) {
-    const int i = base + tid;
-    const T v = i < n ? (T)in[i] : (T)0;
-    T x = v;  // inclusive scan within the wave
+  for (int base = 0; base < n; base += kScanRound) {
+    __syncthreads();  // the previous round's stores have read buf
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+      const int e = k * 1024 + tid;  // entry of the round, coalesced
+      buf[(e / kScanIpt) * (kScanIpt + 1) + e % kScanIpt] = base + e < n ? (T)in[base + e] : (T)0;
+    }
+    __syncthreads();
+    T* row = buf + tid * (kScanIpt + 1);
+    T tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) tot += row[k];
+    T x = tot;  // inclusive scan of the thread totals within the wave
     for (int off = 1; off < 64; off <<= 1) {
       const T y = __shfl_up(x, off, 64);
       if (lane >= off) x += y;
@@ -307,11 +314,22 @@ __global__ __launch_bounds__(1024) void plan_scan_kernel(int n, const int* in, T
     __syncthreads();
     T before = carry_s;
     for (int k = 0; k < wv; ++k) before += wsum[k];
-    if (i < n) out[i] = before + x - v;
+    T run = before + x - tot;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+      const T v = row[k];
+      row[k] = run;
+      run += v;
+    }
     __syncthreads();
     if (tid == 1023) carry_s = before + x;
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+      const int e = k * 1024 + tid;
+      if (base + e < n) out[base + e] = buf[(e / kScanIpt) * (kScanIpt + 1) + e % kScanIpt];
+    }
   }
+  __syncthreads();
   if (tid == 0) *sum = carry_s;
 }
 

@@ -39,6 +39,14 @@ constexpr float kSkipFp32 = 152.f;
 // entry of size one: such pairs multiply the hi part only.
 constexpr float kLoF16x3 = 20.f;
 
+// s2 g^2 < threshold for the gap g between two boxes (x0, x1, y0, y1) (NaN-free:
+// an infinite box gives a zero gap, an empty one an infinite gap).
+__device__ __forceinline__ bool boxes_live(const float4& a, const float4& q, float s2, float threshold) {
+  const float gx = fmaxf(0.f, fmaxf(q.x - a.y, a.x - q.y));
+  const float gy = fmaxf(0.f, fmaxf(q.z - a.w, a.z - q.w));
+  return !(s2 * fmaf(gx, gx, gy * gy) >= threshold);
+}
+
 // List entries: chunk index in the low 16 bits, bit 16 + t set when subtile t of
 // the row tile can see the chunk (entries with no such bit are not listed), bit
 // 20 + t set when that pair also needs the lo part of the exp tile (the same
