@@ -125,6 +125,21 @@ __global__ __launch_bounds__(256) void mvm_bwd_kernel(int n, const float* __rest
     const float4 q = source_tile_box(cbox, nch, row0 / kBJ + r);
     rb = make_float4(fminf(rb.x, q.x), fmaxf(rb.y, q.y), fminf(rb.z, q.z), fmaxf(rb.w, q.w));
   }
+  // this wave's rows: the 64-point row tiles row0/64 + w + 4r (r < R); their box
+  // (the same value in every lane) selects the chunks the wave computes
+  const int wv = tid >> 6;
+  float4 wb4 = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int k = 0; k < kChunksPerTile; ++k) {
+      const int c = (row0 / kRowTile + wv + 4 * r) * kChunksPerTile + k;
+      if (c < nch) {
+        const float4 q = cbox[c];
+        wb4 = make_float4(fminf(wb4.x, q.x), fmaxf(wb4.y, q.y), fminf(wb4.z, q.z), fmaxf(wb4.w, q.w));
+      }
+    }
+  }
   float xi[R], yi[R], wa[R][NC], wb[R][NC];
   double gx[R], gy[R];       // FP64 accumulation: the gradient terms partly cancel
   double hl = 0.0, hf = 0.0;  // per-lane sums of K s d^2 and K s
@@ -156,8 +171,9 @@ __global__ __launch_bounds__(256) void mvm_bwd_kernel(int n, const float* __rest
       sb[tid * NC + c] = ok ? Bs[(size_t)c * ldp + j] : 0.f;
     }
     __syncthreads();
+    const unsigned wlive = source_chunks_live(cbox, nch, jt / kBJ, wb4, s2);  // a subset of live
     for (int g = 0; g < kBJ / kChunk; ++g) {
-      if (!((live >> g) & 1u)) continue;
+      if (!((wlive >> g) & 1u)) continue;
 #pragma unroll 2
     for (int t = g * kChunk; t < (g + 1) * kChunk; ++t) {
       const float xj = sx[t], yj = sy[t];
