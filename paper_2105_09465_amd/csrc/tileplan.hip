@@ -24,13 +24,25 @@ __global__ __launch_bounds__(1024) void plan_extent_kernel(int n, const float* _
                                                            const float* __restrict__ py, float4* ext) {
   __shared__ float red[4][16];
   float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const float x = px[i], y = py[i];
-    if (!(isfinite(x) && isfinite(y))) continue;
-    x0 = fminf(x0, x);
-    x1 = fmaxf(x1, x);
-    y0 = fminf(y0, y);
-    y1 = fmaxf(y1, y);
+  // 8 points per thread and round, their loads issued together (an index past n
+  // reads point 0 and is not used)
+  constexpr int kU = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += kU * blockDim.x) {
+    float x[kU], y[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * blockDim.x;
+      x[u] = px[i < n ? i : 0];
+      y[u] = py[i < n ? i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (i0 + u * (int)blockDim.x >= n || !(isfinite(x[u]) && isfinite(y[u]))) continue;
+      x0 = fminf(x0, x[u]);
+      x1 = fmaxf(x1, x[u]);
+      y0 = fminf(y0, y[u]);
+      y1 = fmaxf(y1, y[u]);
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     x0 = fminf(x0, __shfl_xor(x0, off, 64));
