@@ -210,7 +210,7 @@ __host__ __device__ inline long long wave_weight_below(int w, int wround) {
 // Cost estimate of a unit (per live subtile, per subtile that also needs the lo
 // part, and fixed) and of a row tile, in the ratio measured for the precision form.
 constexpr int kCostSubtile = 3;
-constexpr int kCostSubtileLo = 1;
+constexpr int kCostSubtileLo = 2;
 constexpr int kCostUnit = 5;
 constexpr int kCostRowTile = 36;
 __host__ __device__ inline int unit_cost(uint32_t e) {
