@@ -22,13 +22,23 @@ import math
 import numpy as np
 
 
-def cg(Amul, Bm, tol=1e-6, max_iter=1000, n_lanczos=30, fixed_iters=0):
+def cg(Amul, Bm, tol=1e-6, max_iter=1000, n_lanczos=30, fixed_iters=0, vec_dtype=np.float64):
     """Column-independent CG on A X = B. Returns dict with X, iters, relres,
-    alpha/beta histories (first n_lanczos steps per column) and |b|^2."""
+    alpha/beta histories (first n_lanczos steps per column) and |b|^2.
+
+    vec_dtype = np.float32 keeps X, R, P and A P in single precision, the
+    arithmetic of the paper's GPU fits (Sec. 4.3 compares its posterior widths
+    with the machine precision of single-precision floats), while every dot
+    product and the alpha/beta scalars stay FP64;
+    each vector update is rounded to vec_dtype once. Amul then receives and
+    returns vec_dtype blocks."""
+    vt = np.dtype(vec_dtype)
     Bm = np.asarray(Bm, dtype=np.float64)
     if Bm.ndim == 1:
         Bm = Bm[:, None]
     n, m = Bm.shape
+    if vt != np.float64:
+        return _cg_lowprec(Amul, Bm.astype(vt), tol, max_iter, n_lanczos, fixed_iters, vt)
     X = np.zeros_like(Bm)
     R = Bm.copy()
     P = R.copy()
@@ -59,6 +69,41 @@ def cg(Amul, Bm, tol=1e-6, max_iter=1000, n_lanczos=30, fixed_iters=0):
             active &= np.sqrt(rr) > tol * np.sqrt(bb)
     relres = np.sqrt(rr / np.where(bb > 0, bb, 1.0))
     return dict(X=X, iters=iters, relres=relres, alphas=alphas, betas=betas, bnorm2=bb)
+
+
+def _cg_lowprec(Amul, Bm, tol, max_iter, n_lanczos, fixed_iters, vt):
+    """The recurrences of `cg` with vectors in vt and FP64 scalars."""
+    n, m = Bm.shape
+    X = np.zeros_like(Bm)
+    R = Bm.copy()
+    P = R.copy()
+    rr = np.sum(R.astype(np.float64) ** 2, axis=0)
+    bb = rr.copy()
+    active = bb > 0
+    iters = np.zeros(m, dtype=np.int64)
+    alphas = np.zeros((m, n_lanczos))
+    betas = np.zeros((m, n_lanczos))
+    limit = fixed_iters if fixed_iters > 0 else max_iter
+    for k in range(limit):
+        if not active.any():
+            break
+        AP = np.asarray(Amul(P), dtype=vt)
+        pAp = np.sum(P.astype(np.float64) * AP.astype(np.float64), axis=0)
+        alpha = np.where(active, rr / np.where(active, pAp, 1.0), 0.0)
+        X = (X + alpha.astype(vt) * P).astype(vt)
+        R = (R - alpha.astype(vt) * AP).astype(vt)
+        rr_new = np.sum(R.astype(np.float64) ** 2, axis=0)
+        beta = np.where(active, rr_new / np.where(active, rr, 1.0), 0.0)
+        if k < n_lanczos:
+            alphas[active, k] = alpha[active]
+            betas[active, k] = beta[active]
+        iters[active] += 1
+        P = np.where(active, (R + beta.astype(vt) * P).astype(vt), P)
+        rr = np.where(active, rr_new, rr)
+        if fixed_iters <= 0:
+            active &= np.sqrt(rr) > tol * np.sqrt(bb)
+    relres = np.sqrt(rr / np.where(bb > 0, bb, 1.0))
+    return dict(X=X.astype(np.float64), iters=iters, relres=relres, alphas=alphas, betas=betas, bnorm2=bb)
 
 
 def cg_tridiagonal(alphas, betas, k):

@@ -235,6 +235,26 @@ def test_psf_taps_and_adjoint():
         assert math.isclose(lhs, rhs, rel_tol=1e-13)
 
 
+def test_psf_sigma_is_half_maximum_width():
+    """The FWHM -> sigma conversion, pinned by the definition of the full width
+    at half maximum rather than by its closed form: with taps on a spacing that
+    puts a sample exactly at FWHM/2 from the centre, that sample is half the
+    central one; the half-maximum crossing of the continuous profile, found by
+    bisection, lies at FWHM/2."""
+    for fwhm, h, k in [(0.1, 0.01, 5), (0.12, 0.02, 3), (0.3, 0.025, 6)]:
+        taps = psf.psf_taps(fwhm, h)
+        r = (taps.size - 1) // 2
+        assert math.isclose(k * h, fwhm / 2, rel_tol=1e-12)
+        assert math.isclose(taps[r + k] / taps[r], 0.5, rel_tol=1e-12)
+        assert math.isclose(taps[r - k] / taps[r], 0.5, rel_tol=1e-12)
+        s = psf.psf_sigma(fwhm)
+        lo, hi = 0.0, 10 * fwhm
+        for _ in range(200):  # profile(x) = 1/2 by bisection on x
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if math.exp(-mid * mid / (2 * s * s)) > 0.5 else (lo, mid)
+        assert math.isclose(2 * lo, fwhm, rel_tol=1e-12)
+
+
 def test_psf_brute_force_and_constant():
     taps = psf.psf_taps(0.1, 0.05)
     r = (taps.size - 1) // 2
@@ -329,6 +349,28 @@ def test_cg_equals_direct_solve():
     res = krylov.cg(lambda X: A @ X, b, tol=1e-12, max_iter=500)
     assert np.allclose(res["X"], np.linalg.solve(A, b), rtol=1e-9, atol=1e-10)
     assert np.all(res["relres"] <= 1e-12)
+
+
+def test_cg_single_precision_vectors():
+    """The FP32-vector variant: on a well-conditioned system it reaches the
+    direct solve to FP32 accuracy, its vectors stay float32, and its first step
+    (x_1 = alpha b, alpha = b.b / b.Ab) matches the closed form."""
+    A = _spd()
+    b = np.random.default_rng(9).standard_normal((40, 3))
+    seen = []
+
+    def amul(X):
+        seen.append(X.dtype)
+        return (A.astype(np.float32) @ X).astype(np.float32)
+
+    res = krylov.cg(amul, b, tol=1e-6, max_iter=500, vec_dtype=np.float32)
+    assert all(t == np.float32 for t in seen)
+    x = np.linalg.solve(A, b)
+    assert np.all(np.linalg.norm(res["X"] - x, axis=0) <= 1e-5 * np.linalg.norm(x, axis=0))
+    one = krylov.cg(amul, b, fixed_iters=1, vec_dtype=np.float32)
+    b32 = b.astype(np.float32).astype(np.float64)
+    alpha = np.sum(b32 * b32, axis=0) / np.sum(b32 * (A @ b32), axis=0)
+    assert np.allclose(one["X"], alpha * b32, rtol=1e-6)
 
 
 def test_cg_tridiagonal_equals_explicit_lanczos():
