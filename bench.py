@@ -9,10 +9,13 @@ mean and predicted image. The observation comes from the stored oracle simulatio
 that workload; everything in the timed region runs in the HIP library with the
 inputs already in HBM.
 
-Prints one JSON line. `value` is the kernel-pair throughput of the whole step
-(N^2 pairs per product with K, summed over the step's products, over the step
-time). Extra fields: reconstructions/s of both arithmetic forms, the roofline
-of the dominant kernel, and the FP64 oracle timed on the host as a baseline.
+Prints one JSON line. `value` is the kernel-pair throughput of the whole step:
+the kernel values the step's products evaluate (pairs below the 2^-36 cutoff
+are not evaluated), over the step time; the dense equivalent (N^2 pairs per
+product) is reported beside it. Extra fields: reconstructions/s of both
+arithmetic forms, the roofline of the dominant kernel and of the FP32 form's
+product, the serving trace, and the FP64 oracle timed on the host as a
+baseline.
 
     python bench.py [--steps K] [--warmup W] [--prec f16x3|fp32]
 """
@@ -47,6 +50,8 @@ METRIC = "kernel-MVM Gpairs/s at N=40k; reconstructions/s + p99 latency vs plain
 VALU_LANE_OPS = 256 * 128 * 2.4e9
 PAIR_COST = 4 + 4
 ALU_PEAK_GPAIRS = VALU_LANE_OPS / PAIR_COST / 1e9
+# Dense FP32 MFMA peak of MI355X (the FP32 form's tile x RHS product).
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 # HBM traffic of the dominant kernel per launch at this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration (profiles/), valid
@@ -113,6 +118,25 @@ def cpu_baseline(prob, px, py, budget_s=15.0):
                       f"{os.cpu_count()} logical CPUs"}
 
 
+def mock_observation(G, torch, problem, noise, field):
+    """A mock lensed image for a serving request (input generation, outside any
+    timed region): the Sersic mean plus a smooth random field (the kernel
+    product of white noise `field` with a kernel of lengthscale l/sqrt(2),
+    rescaled to the kernel amplitude), observed through B, plus i.i.d. noise of
+    the problem's sigma. Large requests would take the FP64 oracle minutes each,
+    so the library draws these."""
+    import dataclasses
+    g = problem.grid
+    pts = G.ops.lens_raytrace(g, problem.lens)
+    mu = G.ops.sersic_eval(problem.source, pts[0], pts[1])
+    wn = torch.as_tensor(field, dtype=torch.float32, device="cuda")
+    k2 = dataclasses.replace(problem.kernel, lengthscale=problem.kernel.lengthscale / math.sqrt(2.0))
+    gf = G.ops.kernel_mvm(k2, pts[0], pts[1], wn, prec="fp32", grid=g)
+    gf = gf * (problem.kernel.amplitude / gf.std().clamp_min(1e-30))
+    d = G.ops.psf_conv(g, problem.psf, mu + gf, adjoint=False)
+    return d + problem.noise_sigma * torch.as_tensor(noise, dtype=torch.float32, device="cuda")
+
+
 def serving_requests(G, torch, synth, n_requests, rate_hz=1.0):
     """n_requests requests with sides and supersampling from the serving trace,
     lens and source from the priors, a mock observation made by library calls,
@@ -125,7 +149,7 @@ def serving_requests(G, torch, synth, n_requests, rate_hz=1.0):
         prob = G.Problem(G.Grid(w.n, w.ss, w.pix_scale), G.Lens(*w.lens.as_tuple()),
                          G.Sersic(s.peak, s.R_e, s.n_sersic, s.xs, s.ys), G.Kernel(w.ell, w.amp), G.PSF(w.psf_fwhm),
                          w.noise_sigma)
-        d = G.serving.mock_observation(prob, synth.noise_normals(w.n_pix, 4, seed), synth.gp_normals(w.N, 4, seed))
+        d = mock_observation(G, torch, prob, synth.noise_normals(w.n_pix, 4, seed), synth.gp_normals(w.N, 4, seed))
         Z = torch.as_tensor(synth.rademacher(w.n_pix, 16, 4, seed).T.copy(), dtype=torch.float32, device="cuda")
         reqs.append(G.serving.Request(k, t, prob, d, Z))
     torch.cuda.synchronize()
@@ -223,6 +247,41 @@ def gradient_only(G, torch, synth, prec, reps):
                       "gradients_ms": t_grad * 1e3, "components": int(g["lnp"].numel())}), flush=True)
 
 
+def mfma_flops_per_launch(prec, nrhs, live_subtiles, live_lo):
+    """MFMA FLOP one product launch executes, from the plan's counts of evaluated
+    (16-point subtile, 32-point chunk) pairs and of those that need the lo part.
+    Precision form (v_mfma_f32_16x16x32_f16, 16384 FLOP): per 16-column block 3
+    MFMAs (hi.hi + hi.lo + lo.hi), 2 where the lo part is skipped; a last block of
+    at most 8 columns packs hi and lo side by side: 2 MFMAs, 1 without lo. FP32
+    form (v_mfma_f32_16x16x4_f32, 2048 FLOP): 8 MFMAs per 16-column block."""
+    full, rem = divmod(nrhs, 16)
+    if prec == "f16x3":
+        packed = 1 if 0 < rem <= 8 else 0
+        blocks = full + (1 if rem > 8 else 0)
+        per_lo = 3 * blocks + 2 * packed
+        per_hi = 2 * blocks + 1 * packed
+        n_mfma = live_lo * per_lo + (live_subtiles - live_lo) * per_hi
+        return n_mfma * 2 * 16 * 16 * 32
+    blocks = full + (1 if rem else 0)
+    return live_subtiles * blocks * 8 * 2 * 16 * 16 * 4
+
+
+def product_alone(G, torch, prob, px, py, nrhs, prec, reps=10):
+    """Average event-timed launch of the product alone (same shape, same stream)."""
+    V = torch.randn(nrhs, px.numel(), device="cuda")
+    Y = torch.empty_like(V)
+    for _ in range(2):
+        G.ops.kernel_mvm(prob.kernel, px, py, V, prec=prec, out=Y, grid=prob.grid)
+    torch.cuda.synchronize()
+    G.ops.timing_read(reset=True)
+    G.ops.timing_enable(1)
+    for _ in range(reps):
+        G.ops.kernel_mvm(prob.kernel, px, py, V, prec=prec, out=Y, grid=prob.grid)
+    G.ops.timing_enable(False)
+    ms, n = G.ops.timing_read(reset=True)
+    return ms / max(n, 1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +289,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f16x3", choices=["f16x3", "fp32"])
     ap.add_argument("--plain-steps", type=int, default=3, help="timed steps of the plain FP32 form (0: skip)")
+    ap.add_argument("--async-steps", type=int, default=2,
+                    help="steps with the fully asynchronous CG call (no host wait; 0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0: skip)")
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="run only the dominant kernel this many times at the bench shape, then a 1 GiB copy "
@@ -237,8 +298,10 @@ def main():
     ap.add_argument("--gradient-only", type=int, default=0,
                     help="time ray tracing and this many evaluations of the evidence gradients at the bench shape, "
                          "print one JSON line and exit")
-    ap.add_argument("--serve-requests", type=int, default=128,
-                    help="requests in the serving trace (0: skip; the full trace has 512)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests in the serving trace (0: skip)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving section (both forms) and print its JSON; for kernel traces")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs on a single MI355X)",
@@ -258,8 +321,12 @@ def main():
     if args.gradient_only > 0:
         gradient_only(G, torch, synth, args.prec, args.gradient_only)
         return
+    if args.serve_only:
+        print(json.dumps(serve_section(G, torch, synth, args.serve_requests)), flush=True)
+        return
     prob, z = load_workload()
     N, npix = prob.grid.N, prob.grid.n_pix
+    nrhs = 17
     d = torch.as_tensor(z["d"], dtype=torch.float32, device="cuda")
     probes = torch.as_tensor(synth.rademacher(npix, 16, 1).T.copy(), dtype=torch.float32, device="cuda")
     ws = None
@@ -280,9 +347,6 @@ def main():
     samples = G.ops.timing_samples(reset=True)
     hosts = [r.host() for r in recs]
     iters = [max(h["iters"]) for h in hosts]
-    # products with K per step: one per CG iteration (all 17 columns) + the posterior mean
-    pairs_per_step = [(it + 1) * N * N for it in iters]
-    value = sum(pairs_per_step) / elapsed / 1e9
     ms_per_step = elapsed / args.steps * 1e3
     # the dominant kernel: the 17-column product inside CG. Launches queued past
     # a step's last active iteration exit at once (a few microseconds against
@@ -291,48 +355,70 @@ def main():
     avg_ms = float(np.mean(active)) if active else float("nan")
     # work of one launch: the kernel values the product evaluates, 512 per live
     # (16-point subtile, 32-point chunk) pair of its tile plan; every other pair
-    # is exactly zero in this precision and is not evaluated (the result is the
-    # all-pairs one)
-    live_tiles, live_subtiles = G.ops.kernel_mvm_live_tiles(prob.kernel, recs[-1].px, recs[-1].py, prec=args.prec,
-                                                            grid=prob.grid)
+    # is below 2^-36 a^2 (exactly zero in the precision form) and is not evaluated
+    px, py = recs[-1].px, recs[-1].py
+    live_tiles, live_subtiles, live_lo = G.ops.kernel_mvm_live_tiles(prob.kernel, px, py, prec=args.prec,
+                                                                     grid=prob.grid, with_lo=True)
     evaluated = live_subtiles * 16 * 32
     achieved = evaluated / (avg_ms * 1e-3) / 1e9
-
-    # ---- the dominant kernel alone, same shape and stream, for the rocprof cross-check
-    V = torch.randn(17, N, device="cuda")
-    px, py = recs[-1].px, recs[-1].py
-    Y = torch.empty_like(V)
-    for _ in range(2):
-        G.ops.kernel_mvm(prob.kernel, px, py, V, prec=args.prec, out=Y, grid=prob.grid)
-    torch.cuda.synchronize()
-    G.ops.timing_read(reset=True)
-    G.ops.timing_enable(1)
-    for _ in range(10):
-        G.ops.kernel_mvm(prob.kernel, px, py, V, prec=args.prec, out=Y, grid=prob.grid)
-    G.ops.timing_enable(False)
-    alone_ms, alone_n = G.ops.timing_read(reset=True)
-    alone_avg = alone_ms / max(alone_n, 1)
+    mfma_flop = mfma_flops_per_launch(args.prec, nrhs, live_subtiles, live_lo)
+    # products with K per step: one per CG iteration (all 17 columns), one for the
+    # true residual at exit and the posterior mean's
+    products = [it + 2 for it in iters]
+    value = sum(products) * evaluated / elapsed / 1e9
+    dense_equivalent = sum(products) * N * N / elapsed / 1e9
+    alone_avg = product_alone(G, torch, prob, px, py, nrhs, args.prec)
 
     # ---- accuracy of this run against the stored oracle evidence
     h = hosts[-1]
-    lnp_rel = abs(h["lnp"] - float(z["lnp"])) / abs(float(z["lnp"]))
+    lnp_ref = float(z["lnp"])
+    lnp_rel = abs(h["lnp"] - lnp_ref) / abs(lnp_ref)
     r = recs[-1]
     ld30, se30, _ = G.ops.lanczos_logdet(r.cg["ab"][1:, :30].contiguous(), r.cg["iters"][1:], r.cg["bnorm2"][1:],
                                          1.0 / 16)
     slq30 = {"logdet_err": ld30.item() - float(z["logdet"]), "stderr": se30.item()}
 
-    # ---- plain FP32 form, same step
+    # ---- the same step with the fully asynchronous CG call (every iteration up
+    # to the cap enqueued, no host wait inside the library)
+    async_ms = None
+    if args.async_steps > 0:
+        t_async = []
+        for k in range(args.async_steps + 1):  # the first is a warmup
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            G.reconstruct(prob, d, probes, prec=args.prec, tol=1e-6, max_iter=1000, n_lanczos=N_LANCZOS,
+                          check_every=0, ws=ws)
+            torch.cuda.synchronize()
+            if k:
+                t_async.append((time.perf_counter() - t) * 1e3)
+        async_ms = float(np.mean(t_async))
+
+    # ---- plain FP32 form, same step, and its product's own roofline
     plain = None
     if args.plain_steps > 0 and args.prec != "fp32":
         run_steps(G, torch, prob, d, probes, "fp32", 1, ws)
         t0 = time.perf_counter()
         precs, ptimes = run_steps(G, torch, prob, d, probes, "fp32", args.plain_steps, ws)
         pel = time.perf_counter() - t0
-        ph = [r.host() for r in precs]
+        ph = [x.host() for x in precs]
         pit = [max(x["iters"]) for x in ph]
-        plain = {"value": sum((it + 1) * N * N for it in pit) / pel / 1e9, "unit": "Gpairs/s",
+        _, p_sub, _ = G.ops.kernel_mvm_live_tiles(prob.kernel, px, py, prec="fp32", grid=prob.grid, with_lo=True)
+        p_ms = product_alone(G, torch, prob, px, py, nrhs, "fp32")
+        p_flop = mfma_flops_per_launch("fp32", nrhs, p_sub, p_sub)
+        p_alg = p_sub * 512 * 2 * nrhs
+        plain = {"value": sum(it + 2 for it in pit) * p_sub * 512 / pel / 1e9, "unit": "Gpairs/s (evaluated)",
                  "reconstructions_per_s": args.plain_steps / pel, "ms_per_step": pel / args.plain_steps * 1e3,
-                 "cg_iters": pit[-1], "lnp_rel_err_vs_oracle": abs(ph[-1]["lnp"] - float(z["lnp"])) / abs(float(z["lnp"]))}
+                 "cg_iters": pit[-1], "lnp_rel_err_vs_oracle": abs(ph[-1]["lnp"] - lnp_ref) / abs(lnp_ref),
+                 "true_relres_max": max(ph[-1]["true_relres"]),
+                 "roofline": {"bound": "mfma", "kernel": "mvm_f32_kernel", "unit": "TFLOP/s",
+                              "achieved": p_flop / (p_ms * 1e-3) / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS,
+                              "frac": p_flop / (p_ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+                              "executed_flop_per_launch": p_flop,
+                              "algorithmic_flop_per_launch": p_alg,
+                              "note": "17 columns run as two 16-column MFMA blocks (32 columns executed)",
+                              "avg_launch_ms_alone": p_ms,
+                              "evaluated_pairs_per_launch": p_sub * 512,
+                              "alu_frac": p_sub * 512 / (p_ms * 1e-3) / 1e9 / ALU_PEAK_GPAIRS}}
 
     serving = None
     if args.serve_requests > 0:
@@ -346,7 +432,7 @@ def main():
     out = {
         "metric": METRIC,
         "value": value,
-        "unit": "Gpairs/s",
+        "unit": "Gpairs/s (evaluated)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -358,10 +444,16 @@ def main():
         "data": "synthetic (oracle-simulated lensed Sersic + RBF-GP source, seeded)",
         "config": {"workload": "100x100 px image, 2x2 supersampling (N=40000 points), SPLE+shear lens prior draw, "
                                "Gaussian PSF FWHM 0.1\", 1 solve + 16 Rademacher probe columns, CG tol 1e-6, "
-                               "SLQ over all CG steps", "N": N, "n_pix": npix, "rhs": 17},
+                               "SLQ over all CG steps", "N": N, "n_pix": npix, "rhs": nrhs},
+        "value_note": "kernel values evaluated by the step's products per second (the pairs of every product "
+                      "whose kernel value is below 2^-36 a^2 are not evaluated)",
+        "dense_equivalent_gpairs_per_s": dense_equivalent,
         "reconstructions_per_s": args.steps / elapsed,
+        "async_ms_per_step": async_ms,
         "cg_iters": iters[-1],
+        "true_relres_max": max(h["true_relres"]),
         "lnp_rel_err_vs_oracle": lnp_rel,
+        "lnp_slq_stderr_rel": 0.5 * h["stderr"] / abs(lnp_ref),
         "logdet_err_vs_oracle": h["logdet"] - float(z["logdet"]),
         "quad_rel_err_vs_oracle": abs(h["quad"] - float(z["quad"])) / float(z["quad"]),
         "slq_stderr": h["stderr"],
@@ -371,15 +463,17 @@ def main():
                      "kernel": "mvm_f16x3_kernel" if args.prec == "f16x3" else "mvm_f32_kernel",
                      "evaluated_pairs_per_launch": evaluated, "all_pairs_per_launch": N * N,
                      "evaluated_fraction": evaluated / (N * N),
-                     "all_pairs_rate_gpairs": N * N / (avg_ms * 1e-3) / 1e9,
                      "avg_launch_ms_in_step": avg_ms, "timed_launches_in_step": len(active),
                      "timing_stride": TIMING_STRIDE, "avg_launch_ms_alone": alone_avg,
-                     "mfma_tflops_executed": 2.0 * evaluated * 32 * (3 if args.prec == "f16x3" else 1)
-                     / (avg_ms * 1e-3) / 1e12},
+                     "subtile_pairs_with_lo": live_lo, "subtile_pairs": live_subtiles,
+                     "mfma_flop_per_launch": mfma_flop,
+                     "mfma_tflops_executed": mfma_flop / (avg_ms * 1e-3) / 1e12},
         "plain_fp32": plain,
         "serving": serving,
         "cpu_baseline": cpu,
     }
+    if plain:
+        out["reconstructions_ratio_vs_fp32"] = out["reconstructions_per_s"] / plain["reconstructions_per_s"]
     print(json.dumps(out), flush=True)
 
 

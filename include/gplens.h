@@ -139,13 +139,15 @@ int gpl_psf_conv(const gpl_grid* grid, const gpl_psf* psf, int nrhs, const float
  * (V, Y column-major with ld >= n, device memory, must not overlap).
  * prec = GPL_PREC_FP32 or GPL_PREC_F16X3. beta is 0 (overwrite) or any float.
  * Pairs of 16-point subtiles and 32-point chunks whose bounding boxes are so far
- * apart that every kernel value is exactly zero in the chosen precision are not
- * evaluated, so the result equals the all-pairs product up to FP32 summation
- * order. The points are taken along a Hilbert curve of their own positions
- * (ties in caller order), so tiles are compact in the plane the kernel is
- * evaluated in; Y is returned in the caller's order. grid (nullable): if given,
- * n must equal its fine point count (the points are then its fine grid in
- * row-major order, as gpl_lens_raytrace writes them). n <= 2,097,120. */
+ * apart that every kernel value is at most 2^-36 amplitude^2 are not evaluated:
+ * in the precision form those values are exactly zero (the result equals the
+ * all-pairs product up to FP32 summation order); in the FP32 form each dropped
+ * term is below 2^-36 amplitude^2 |v_j|. The points are taken along a Hilbert
+ * curve of their own positions (ties in caller order), so tiles are compact in
+ * the plane the kernel is evaluated in; Y is returned in the caller's order.
+ * grid (nullable): if given, n must equal its fine point count (the points are
+ * then its fine grid in row-major order, as gpl_lens_raytrace writes them).
+ * n <= 2,097,120. */
 size_t gpl_gp_kernel_mvm_workspace(int n, int nrhs, int prec);
 int gpl_gp_kernel_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px, const float* py, int nrhs,
                       const float* V, int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes,
@@ -154,35 +156,50 @@ int gpl_gp_kernel_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const
 /* Work of the product above for these points: *live_tiles = the (64-point row
  * tile, 32-point chunk) pairs it visits, *live_subtiles (nullable) = the
  * (16-point subtile, 32-point chunk) pairs it evaluates, 512 kernel values each
- * (the rest are exactly zero). Host outputs; synchronises `stream`. A
+ * (the rest are below the cutoff), *live_lo (nullable) = those of the evaluated
+ * pairs whose exp tile also needs its lo part in the precision form (equal to
+ * *live_subtiles in the FP32 form). Host outputs; synchronises `stream`. A
  * measurement helper, not needed for the product itself. */
 size_t gpl_gp_kernel_mvm_plan_workspace(int n);
 int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px,
                                  const float* py, int prec, long long* live_tiles, long long* live_subtiles,
-                                 void* ws, size_t ws_bytes, hipStream_t stream);
+                                 long long* live_lo, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Y = A X with A = B K B^T + noise_sigma^2 I (image pixels, nrhs columns). */
 size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int prec);
 int gpl_apply_A(const gpl_problem* prob, int nrhs, const float* X, int ldx, float* Y, int ldy, int prec, void* ws,
                 size_t ws_bytes, hipStream_t stream);
 
-/* Conjugate gradients on A X = Bm, one independent recurrence per column
- * (x_0 = 0), all columns sharing each product with A. FP32 vectors; dot
- * products, alpha/beta recurrences and the recorded coefficients in FP64.
+/* Conjugate gradients on A X = Bm, A = B K B^T + noise^2 I: the solves of the
+ * evidence (Sec. 3.1, eq. "gp-mll": u = A^{-1} r for the quadratic term) and
+ * of the probe vectors of the stochastic log-determinant, by the conjugate
+ * gradient method Sec. 3.3 names for evaluating eq. "gp-mll" (as in GPyTorch,
+ * with the CG coefficients giving the Lanczos tridiagonal of each probe).
+ * One independent recurrence per column (x_0 = 0), all columns sharing each
+ * product with A. FP32 vectors; dot products, alpha/beta recurrences and the
+ * recorded coefficients in FP64.
  * Column c stops when |r|/|b| <= tol (recursive residual) or, if
  * fixed_iters > 0, after exactly fixed_iters steps; max_iter caps the count.
  * Outputs (device): X (n*n x nrhs, ld ldx), lanczos_ab [nrhs][n_lanczos][2]
  * (alpha_k, beta_k for the first n_lanczos steps; 0 beyond a column's count),
- * bnorm2[nrhs] = |b_c|^2, iters[nrhs], relres[nrhs], status[nrhs].
- * The host waits (on events, not the device) until every column has stopped;
- * it checks progress every `check_every` iterations (<= 0: 8). */
+ * bnorm2[nrhs] = |b_c|^2, iters[nrhs], relres[nrhs] (recursive residual at
+ * the stop), status[nrhs]; true_relres[nrhs] (nullable) = |b - A x|/|b| of the
+ * returned iterate, from one more product with A after the last iteration.
+ * check_every = 0: fully asynchronous; every iteration up to the cap is
+ * enqueued and those after the last column has stopped return at once.
+ * check_every > 0: the host waits (on events, never synchronising the device)
+ * every check_every iterations for the number of active columns and stops
+ * enqueueing once it is zero; this mode keeps two pinned host ints and two
+ * events per host thread, created on first use and kept until the process ends. */
 size_t gpl_cg_solve_workspace(const gpl_problem* prob, int nrhs, int prec);
 int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, int ldb, float* X, int ldx, double tol,
                  int max_iter, int fixed_iters, int n_lanczos, double* lanczos_ab, double* bnorm2, int* iters,
-                 double* relres, int* status, int prec, int check_every, void* ws, size_t ws_bytes,
-                 hipStream_t stream);
+                 double* relres, double* true_relres, int* status, int prec, int check_every, void* ws,
+                 size_t ws_bytes, hipStream_t stream);
 
-/* Stochastic Lanczos quadrature of ln|A| from CG coefficients. Probe j uses the
+/* Stochastic Lanczos quadrature of ln|A|: the stochastic log-determinant that
+ * Sec. 3.3 names for the ln|2 pi A| term of eq. "gp-mll" (Hutchinson probes,
+ * Gauss quadrature from the Lanczos tridiagonal of each probe). Probe j uses the
  * first k_j = min(iters[j], n_lanczos) steps: the tridiagonal
  * T_kk = 1/a_k + b_{k-1}/a_{k-1}, T_{k,k+1} = sqrt(b_k)/a_k, and
  * contrib[j] = bnorm2[j] * e_1^T ln(T) e_1 (Gauss quadrature on T's Ritz
@@ -207,6 +224,20 @@ int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, cons
  * r, u of length n_pix (device), logdet device scalar. */
 int gpl_evidence_scalars(int n_pix, int n_points, const float* r, const float* u, const double* logdet,
                          double amplitude, double noise_sigma, double* out, hipStream_t stream);
+
+/* Amplitude derivatives of the evidence and of the App. D.1 loss, from the
+ * identity alpha dA/dalpha = 2 (A - sigma^2 I) (K is proportional to alpha^2):
+ * out[0] = d ln p/d alpha = ((quad - sigma^2 u.u) - scale sum_j (|z_j|^2 - sigma^2 z_j.x_j)) / alpha,
+ * the second term the probe estimate of tr(A^{-1} B K B^T) (Sec. 3.1 eq.
+ * "gp-mll" differentiated; Sec. 3.3 stochastic trace), x_j = A^{-1} z_j;
+ * out[1] = d L_VI/d alpha = -2 (quad - sigma^2 u.u)/alpha + 2 n_points alpha/(alpha^2 + sigma^2)
+ * (App. D.1 eq. "hyper-loss"). u = A^{-1} r (n_pix), Z and X the probe columns
+ * and their solves (ld >= n_pix; nprobe may be 0), quad a device scalar
+ * (r.u, as gpl_evidence_scalars writes it), scale the probe weight (1/nprobe
+ * for Hutchinson probes, 1 for all unit vectors). FP64 dot products. */
+int gpl_evidence_amplitude_grad(int n_pix, int n_points, int nprobe, const float* u, const float* Z, int ldz,
+                                const float* X, int ldx, const double* quad, double scale, double amplitude,
+                                double noise_sigma, double* out, hipStream_t stream);
 
 /* Column-wise dot products in FP64: out[c] = sum_i X[c*ldx + i] * Y[c*ldy + i],
  * c < ncols, i < n. Used for quadratic forms and trace estimates

@@ -76,12 +76,13 @@ SIGNATURES = {
                                _P, _Z, _P]),
     "gpl_gp_kernel_mvm_plan_workspace": (_Z, [_I]),
     "gpl_gp_kernel_mvm_plan_stats": (_I, [C.POINTER(gpl_kernel), C.POINTER(gpl_grid), _I, _P, _P, _I,
-                                          C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), _P, _Z, _P]),
+                                          C.POINTER(C.c_longlong), C.POINTER(C.c_longlong),
+                                          C.POINTER(C.c_longlong), _P, _Z, _P]),
     "gpl_apply_A_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I]),
     "gpl_apply_A": (_I, [C.POINTER(gpl_problem), _I, _P, _I, _P, _I, _I, _P, _Z, _P]),
     "gpl_cg_solve_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I]),
-    "gpl_cg_solve": (_I, [C.POINTER(gpl_problem), _I, _P, _I, _P, _I, _D, _I, _I, _I, _P, _P, _P, _P, _P, _I, _I,
-                          _P, _Z, _P]),
+    "gpl_cg_solve": (_I, [C.POINTER(gpl_problem), _I, _P, _I, _P, _I, _D, _I, _I, _I, _P, _P, _P, _P, _P, _P, _I,
+                          _I, _P, _Z, _P]),
     "gpl_lanczos_logdet_workspace": (_Z, [_I, _I]),
     "gpl_lanczos_logdet": (_I, [_I, _I, _P, _P, _P, _D, _P, _P, _P, _P, _Z, _P]),
     "gpl_evidence_scalars": (_I, [_I, _I, _P, _P, _P, _D, _D, _P, _P]),
@@ -93,6 +94,7 @@ SIGNATURES = {
     "gpl_sersic_backward_workspace": (_Z, [_I]),
     "gpl_sersic_backward": (_I, [C.POINTER(gpl_source), _I, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "gpl_block_dot": (_I, [_I, _I, _P, _I, _P, _I, _P, _P]),
+    "gpl_evidence_amplitude_grad": (_I, [_I, _I, _I, _P, _P, _I, _P, _I, _P, _D, _D, _D, _P, _P]),
     "gpl_timing_enable": (_I, [_I]),
     "gpl_serve_slot_workspace": (_Z, [C.POINTER(gpl_grid), _I, _I, _I]),
     "gpl_serve_slot_init": (_I, [C.POINTER(gpl_serve_slot), C.POINTER(gpl_problem), C.POINTER(gpl_lens),

@@ -56,9 +56,59 @@ __global__ __launch_bounds__(256) void block_dot_kernel(int n, const float* __re
   if (threadIdx.x == 0) out[c] = s;
 }
 
+// Amplitude derivatives of ln p and of the App. D.1 loss. K is proportional to
+// alpha^2, so alpha dA/dalpha = 2 B K B^T = 2 (A - sigma^2 I) and
+//   alpha d ln p/d alpha = u^T B K B^T u - tr(A^{-1} B K B^T)
+//                        = (quad - sigma^2 u.u) - (n - sigma^2 tr(A^{-1})),
+// with tr(A^{-1}) and n = tr(I) estimated from the probes z_j and their solves
+// x_j = A^{-1} z_j as scale * sum_j (|z_j|^2 - sigma^2 z_j.x_j);
+//   d L_VI/d alpha = -2 (quad - sigma^2 u.u)/alpha + 2 N alpha/(alpha^2 + sigma^2).
+// One workgroup; every dot product in FP64 in a fixed order.
+__global__ __launch_bounds__(256) void amplitude_grad_kernel(int n_pix, int n_points, int nprobe,
+                                                             const float* __restrict__ u, const float* __restrict__ Z,
+                                                             int ldz, const float* __restrict__ X, int ldx,
+                                                             const double* quad, double scale, double amp,
+                                                             double sigma, double* out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n_pix; i += blockDim.x) s += (double)u[i] * (double)u[i];
+  const double uu = block_sum_double(s, red);
+  double tr = 0.0;  // thread 0: scale * sum_j (|z_j|^2 - sigma^2 z_j.x_j)
+  for (int j = 0; j < nprobe; ++j) {
+    double zz = 0.0, zx = 0.0;
+    for (int i = threadIdx.x; i < n_pix; i += blockDim.x) {
+      const double z = Z[(size_t)j * ldz + i];
+      zz += z * z;
+      zx += z * (double)X[(size_t)j * ldx + i];
+    }
+    zz = block_sum_double(zz, red);
+    zx = block_sum_double(zx, red);
+    tr += zz - sigma * sigma * zx;
+  }
+  if (threadIdx.x == 0) {
+    const double q = *quad - sigma * sigma * uu;  // u^T B K B^T u
+    out[0] = (q - scale * tr) / amp;
+    out[1] = -2.0 * q / amp + 2.0 * n_points * amp / (amp * amp + sigma * sigma);
+  }
+}
+
 }  // namespace gpl
 
 using namespace gpl;
+
+extern "C" int gpl_evidence_amplitude_grad(int n_pix, int n_points, int nprobe, const float* u, const float* Z,
+                                           int ldz, const float* X, int ldx, const double* quad, double scale,
+                                           double amplitude, double noise_sigma, double* out, hipStream_t stream) {
+  GPL_REQUIRE(n_pix >= 1 && n_points >= 1 && nprobe >= 0, "bad sizes");
+  GPL_REQUIRE(u && quad && out, "NULL argument");
+  GPL_REQUIRE(nprobe == 0 || (Z && X && ldz >= n_pix && ldx >= n_pix), "probe blocks NULL or ld < n_pix");
+  GPL_REQUIRE(amplitude > 0 && std::isfinite(amplitude), "amplitude must be > 0");
+  GPL_REQUIRE(noise_sigma >= 0 && std::isfinite(noise_sigma), "noise_sigma must be >= 0");
+  hipLaunchKernelGGL(amplitude_grad_kernel, dim3(1), dim3(256), 0, stream, n_pix, n_points, nprobe, u, Z, ldz, X, ldx,
+                     quad, scale, amplitude, noise_sigma, out);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
 
 extern "C" int gpl_block_dot(int n, int ncols, const float* X, int ldx, const float* Y, int ldy, double* out,
                              hipStream_t stream) {

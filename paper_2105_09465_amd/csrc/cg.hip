@@ -12,10 +12,12 @@
 //      column scales of the precision form).
 // Per-column state is double-buffered by iteration parity so that every block
 // of a kernel reads the same old values. Kernels return at once when no column
-// is active. The host enqueues iterations in chunks, keeps one chunk in flight
-// ahead, and after each chunk reads the number of active columns from a small
-// coherent host buffer written by a snapshot kernel (waiting on an event, never
-// synchronising the device).
+// is active. Either every iteration up to the cap is enqueued at once (fully
+// asynchronous), or the host enqueues iterations in chunks, keeps one chunk in
+// flight ahead, and after each chunk reads the number of active columns from a
+// small coherent host buffer written by a snapshot kernel (waiting on an event,
+// never synchronising the device). After the last iteration one more product
+// with A gives the true residual b - A x of the returned iterate.
 #include <cmath>
 #include <mutex>
 
@@ -296,6 +298,43 @@ __global__ __launch_bounds__(256) void cg_update2_grouped_kernel(SlotBatch B, in
                   S.pmax);
 }
 
+// Partial max |X| per block (float bits), for the column scales of the
+// precision form when A is applied to the iterate itself.
+__global__ __launch_bounds__(256) void cg_absmax_kernel(int npix, const float* __restrict__ X, int ldx,
+                                                        unsigned* pmax, int nb) {
+  __shared__ float redm[4];
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const float m = block_max(i < npix ? fabsf(X[(size_t)c * ldx + i]) : 0.f, redm);
+  if (threadIdx.x == 0) pmax[(size_t)c * nb + blockIdx.x] = __float_as_uint(m);
+}
+
+// Partial |b - A x|^2 per block, in FP64.
+__global__ __launch_bounds__(256) void cg_true_residual_kernel(int npix, const float* __restrict__ Bm, int ldb,
+                                                               const float* __restrict__ AX, int ldv,
+                                                               double* part, int nb) {
+  __shared__ double red[4];
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < npix) {
+    const double d = (double)Bm[(size_t)c * ldb + i] - (double)AX[(size_t)c * ldv + i];
+    s = d * d;
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) part[(size_t)c * nb + blockIdx.x] = s;
+}
+
+// true_relres[c] = |b - A x| / |b| from the partials, in block order.
+__global__ void cg_true_residual_fold_kernel(int nrhs, const double* part, int nb, const double* bb,
+                                             double* true_relres) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)c * nb + b];
+  true_relres[c] = bb[c] > 0.0 ? sqrt(s / bb[c]) : sqrt(s);
+}
+
 __global__ void cg_snapshot_kernel(const int* n_active, volatile int* host_flag) {
   if (threadIdx.x == 0) {
     *host_flag = *n_active;
@@ -452,8 +491,8 @@ extern "C" size_t gpl_cg_solve_workspace(const gpl_problem* prob, int nrhs, int 
 
 extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, int ldb, float* X, int ldx,
                             double tol, int max_iter, int fixed_iters, int n_lanczos, double* lanczos_ab,
-                            double* bnorm2, int* iters, double* relres, int* status, int prec, int check_every,
-                            void* ws, size_t ws_bytes, hipStream_t stream) {
+                            double* bnorm2, int* iters, double* relres, double* true_relres, int* status, int prec,
+                            int check_every, void* ws, size_t ws_bytes, hipStream_t stream) {
   Taps taps;
   GPL_TRY(check_problem(prob, taps));
   GPL_REQUIRE(nrhs >= 1 && nrhs <= 65535, "nrhs=%d out of range", nrhs);
@@ -463,13 +502,14 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
   GPL_REQUIRE(ldb >= npix && ldx >= npix, "ldb/ldx must be >= n*n");
   GPL_REQUIRE(tol >= 0 && max_iter >= 0 && fixed_iters >= 0 && n_lanczos >= 0, "negative tol/iteration counts");
   GPL_REQUIRE(n_lanczos == 0 || lanczos_ab != nullptr, "lanczos_ab is NULL");
+  GPL_REQUIRE(check_every >= 0, "check_every must be >= 0");
   GPL_TRY(check_ws(ws, ws_bytes, gpl_cg_solve_workspace(prob, nrhs, prec)));
   Carver cv(ws, ws_bytes);
   CgBuffers b;
   carve_cg(cv, npix, N, nrhs, prec, &b, nullptr, ss, n);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   PollSlots* poll = nullptr;
-  GPL_TRY(poll_slots(poll));
+  if (check_every > 0) GPL_TRY(poll_slots(poll));
   MvmCtx mv;  // the points stay fixed for the whole solve: one tile plan
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid, nrhs,
                       prec, b.mvm_ws, b.mvm_ws_bytes, stream));
@@ -486,7 +526,9 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
                      b.n_active, limit);
   GPL_LAUNCH_CHECK();
 
-  const int chunk = check_every > 0 ? check_every : 8;
+  // check_every = 0: every iteration up to the limit is enqueued at once, and
+  // those after the last column has stopped exit at their first load.
+  const int chunk = check_every > 0 ? check_every : std::max(limit, 1);
   const int nchunks = cdiv(limit, chunk);
   int last_end = 0;  // one past the last enqueued iteration
   auto enqueue_chunk = [&](int k) -> int {
@@ -510,15 +552,18 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
                          fixed_iters, n_lanczos, lanczos_ab, b.pmax);
       GPL_LAUNCH_CHECK();
     }
+    last_end = end;
+    if (!poll) return GPL_OK;
     hipLaunchKernelGGL(cg_snapshot_kernel, dim3(1), dim3(64), 0, stream, b.n_active + (end & 1),
                        poll->flags + (k & 1));
     GPL_LAUNCH_CHECK();
     GPL_HIP(hipEventRecord(poll->ev[k & 1], stream));
-    last_end = end;
     return GPL_OK;
   };
 
-  if (nchunks > 0) {
+  if (nchunks > 0 && !poll) {
+    GPL_TRY(enqueue_chunk(0));
+  } else if (nchunks > 0) {
     GPL_TRY(enqueue_chunk(0));
     for (int k = 0; k < nchunks; ++k) {
       if (k + 1 < nchunks) GPL_TRY(enqueue_chunk(k + 1));
@@ -530,5 +575,21 @@ extern "C" int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, 
   hipLaunchKernelGGL(cg_finalize_kernel, dim3(cdiv(nrhs, 256)), dim3(256), 0, stream, nrhs, b.st[final_parity], b.bb,
                      bnorm2, iters, relres, status, n_lanczos, lanczos_ab);
   GPL_LAUNCH_CHECK();
+  if (true_relres) {
+    // |b - A x| / |b| of the returned iterate: one more application of A, to X
+    // itself (the recursive residual R drifts from it in finite precision)
+    hipLaunchKernelGGL(cg_absmax_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, X, ldx, b.pmax, nb);
+    GPL_LAUNCH_CHECK();
+    GPL_TRY(psf_adjoint_rhs_launch(n, ss, taps, nrhs, X, ldx, rhs_out, CgGate{}, stream));
+    GPL_TRY(mvm_run_prepared(mv, nrhs, b.T2, b.ldf, 0.f, CgGate{}, stream));
+    GPL_TRY(psf_forward_launch(n, ss, taps, nrhs, b.T2, b.ldf, b.AP, b.ldv, 1.f, 0.f, X, ldx, sigma2, nullptr, 0,
+                               nullptr, CgGate{}, stream));
+    hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, Bm, ldb, b.AP, b.ldv,
+                       b.rr_part, nb);
+    GPL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(cg_true_residual_fold_kernel, dim3(cdiv(nrhs, 256)), dim3(256), 0, stream, nrhs, b.rr_part,
+                       nb, b.bb, true_relres);
+    GPL_LAUNCH_CHECK();
+  }
   return GPL_OK;
 }

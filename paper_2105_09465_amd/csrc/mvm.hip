@@ -48,7 +48,7 @@ int mvm_prepare(MvmCtx& m, double lengthscale, double amplitude, int n, const fl
   m.s2 = (float)kernel_scale2(lengthscale);
   m.amp2 = (float)(amplitude * amplitude);
   GPL_TRY(mfma_zero_rhs(m.bufs, prec, stream));
-  return plan_build(m.plan, n, px, py, grid, m.s2, plan_threshold(prec), stream);
+  return plan_build(m.plan, n, px, py, grid, m.s2, plan_threshold(prec), plan_lo_threshold(prec), stream);
 }
 
 int mvm_run_prepared(const MvmCtx& m, int nrhs, float* Y, int ldy, float beta, CgGate gate, hipStream_t stream) {
@@ -73,25 +73,29 @@ int mvm_launch(double lengthscale, double amplitude, int n, const float* px, con
 
 // out[0] = listed (row tile, chunk) pairs, out[1] = listed (subtile, chunk) pairs.
 __global__ void plan_live_sum_kernel(int nrt, int nch, const int* count, const uint32_t* list, long long* out) {
-  __shared__ long long red[2][4];
-  long long u = 0, t = 0;
+  __shared__ long long red[3][4];
+  long long u = 0, t = 0, l = 0;
   for (int r = blockIdx.x; r < nrt; r += gridDim.x) {
     if (threadIdx.x == 0) u += count[r];
-    for (int k = threadIdx.x; k < count[r]; k += blockDim.x) t += __popc(entry_mask(list[(size_t)r * nch + k]));
+    for (int k = threadIdx.x; k < count[r]; k += blockDim.x) {
+      const uint32_t e = list[(size_t)r * nch + k];
+      t += __popc(entry_mask(e));
+      l += __popc(entry_lomask(e));
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     u += __shfl_xor(u, off, 64);
     t += __shfl_xor(t, off, 64);
+    l += __shfl_xor(l, off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     red[0][threadIdx.x >> 6] = u;
     red[1][threadIdx.x >> 6] = t;
+    red[2][threadIdx.x >> 6] = l;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    out[0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    out[1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) out[q] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
 }
 
 int check_kernel(const gpl_kernel* k) {
@@ -133,8 +137,8 @@ extern "C" size_t gpl_gp_kernel_mvm_plan_workspace(int n) {
 
 extern "C" int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px,
                                             const float* py, int prec, long long* live_tiles,
-                                            long long* live_subtiles, void* ws, size_t ws_bytes,
-                                            hipStream_t stream) {
+                                            long long* live_subtiles, long long* live_lo, void* ws,
+                                            size_t ws_bytes, hipStream_t stream) {
   GPL_TRY(check_kernel(kern));
   GPL_REQUIRE(prec == GPL_PREC_FP32 || prec == GPL_PREC_F16X3, "unknown precision %d", prec);
   GPL_REQUIRE(n >= 1 && px && py && live_tiles, "bad arguments");
@@ -144,15 +148,17 @@ extern "C" int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_gr
   Carver cv(ws, ws_bytes);
   TilePlan p;
   plan_carve(cv, n, p);
-  long long* dsum = cv.take<long long>(2);
+  long long* dsum = cv.take<long long>(3);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
-  GPL_TRY(plan_build(p, n, px, py, grid, (float)kernel_scale2(kern->lengthscale), plan_threshold(prec), stream));
+  GPL_TRY(plan_build(p, n, px, py, grid, (float)kernel_scale2(kern->lengthscale), plan_threshold(prec),
+                     plan_lo_threshold(prec), stream));
   hipLaunchKernelGGL(plan_live_sum_kernel, dim3(1), dim3(256), 0, stream, p.nrt, p.nch, p.count, p.list, dsum);
   GPL_LAUNCH_CHECK();
-  long long h[2];
+  long long h[3];
   GPL_HIP(hipMemcpyAsync(h, dsum, sizeof(h), hipMemcpyDeviceToHost, stream));
   GPL_HIP(hipStreamSynchronize(stream));
   *live_tiles = h[0];
   if (live_subtiles) *live_subtiles = h[1];
+  if (live_lo) *live_lo = h[2];
   return GPL_OK;
 }

@@ -315,7 +315,7 @@ extern "C" int gpl_gp_kernel_mvm_backward(const gpl_kernel* kern, int n, const f
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   const float s2 = (float)kernel_scale2(kern->lengthscale);
   const float amp2 = (float)(kern->amplitude * kern->amplitude);
-  GPL_TRY(plan_build(b.plan, n, px, py, nullptr, s2, kSkipFp32, stream));
+  GPL_TRY(plan_build(b.plan, n, px, py, nullptr, s2, kSkipFp32Exact, kSkipFp32Exact, stream));
   int chunk = 0;
   for (int c0 = 0; c0 < npairs; ++chunk) {
     const int left = npairs - c0;

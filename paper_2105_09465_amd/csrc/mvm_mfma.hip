@@ -98,7 +98,9 @@ __device__ __forceinline__ void split_rhs_body(int bx, int slot, int n, int nrhs
     unsigned mb = 0u;
     for (int b = 0; b < kColmaxBlocks; ++b) mb = max(mb, colmax[c * kColmaxBlocks + b]);
     const float mx = __uint_as_float(mb);
-    if (mx > 0.f && isfinite(mx)) e = 14 - ilogbf(mx) - 1;  // mx * 2^e in [2^13, 2^14)
+    // mx * 2^e in [2^13, 2^14); e is capped so that 2^e stays a finite float
+    // (a column below 2^-113 then scales to less than 2^13, still normal in FP16)
+    if (mx > 0.f && isfinite(mx)) e = min(14 - ilogbf(mx) - 1, 126);
   }
   const float scale = ldexpf(1.f, e);
   if (j == 0 && c < ncp && (!packed || ((slot - b0) & 1) == 0)) inv_scale[c] = ldexpf(1.f, -e) / kKScale;
@@ -463,9 +465,12 @@ __device__ __forceinline__ void reduce_body(Skip&& skip, int bx, int c, const Ti
     for (int u = 0; u < 8; ++u)
       if (q + u < sl.y) s += t[u];
   }
-  const float f = colscale ? amp2 * colscale[c] : amp2;
+  // amp2 first, then the power-of-two column scale: the same bits as one
+  // multiplication by amp2 * colscale while both are normal, and no subnormal
+  // factor for a column whose scale is near the bottom of the float range
+  const float as = amp2 * s;
   float* y = Y + (size_t)c * ldy + dst;
-  const float res = f * s;
+  const float res = colscale ? as * colscale[c] : as;
   *y = beta != 0.f ? res + beta * *y : res;
 }
 
@@ -501,6 +506,7 @@ size_t mfma_workspace(int n, int nrhs, int prec) {
 }
 
 float plan_threshold(int prec) { return prec == GPL_PREC_F16X3 ? kSkipF16x3 : kSkipFp32; }
+float plan_lo_threshold(int prec) { return prec == GPL_PREC_F16X3 ? kLoF16x3 : kSkipFp32; }
 
 // ---------------------------------------------------------------- launches
 

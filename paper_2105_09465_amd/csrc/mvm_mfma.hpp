@@ -11,7 +11,8 @@ namespace gpl {
 // Scratch bytes of one product of n points and nrhs columns (plan excluded).
 size_t mfma_workspace(int n, int nrhs, int prec);
 // Skip threshold of the plan for a precision form.
-float plan_threshold(int prec);
+float plan_threshold(int prec);     // skip threshold on s2 g^2 of the form
+float plan_lo_threshold(int prec);  // threshold of the lo masks (the skip threshold in the FP32 form)
 // Carve the product buffers from a workspace of mfma_workspace bytes.
 int mfma_carve(const TilePlan& P, int prec, int nrhs, void* ws, size_t ws_bytes, ProdBufs& b);
 // Zero the RHS buffers (padding rows and columns must stay zero).

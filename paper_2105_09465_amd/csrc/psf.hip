@@ -442,7 +442,8 @@ __device__ __forceinline__ void psf_adjoint_rhs_body(Skip&& skip, int tile, int 
     if (threadIdx.x == 0) {
       const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])) / (float)(ss * ss);
       int e = 0;
-      if (mx > 0.f && isfinite(mx)) e = 14 - ilogbf(mx) - 1;  // bound * 2^e in [2^13, 2^14)
+      // bound * 2^e in [2^13, 2^14), e capped so that 2^e stays a finite float
+      if (mx > 0.f && isfinite(mx)) e = min(14 - ilogbf(mx) - 1, 126);
       s_scale = ldexpf(1.f, e);
       if (tile == 0) o.inv_scale[c] = ldexpf(1.f, -e) / 2048.f;  // with the 2^11 of the exp tile
     }

@@ -191,7 +191,7 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
   GPL_TRY(mfma_zero_rhs(pb, prec, stream));
   GPL_TRY(gpl_lens_raytrace(g, lens, b.px, b.py, stream));
   TilePlan plan = b.plan;  // same buffers as the descriptor's copy
-  GPL_TRY(plan_build(plan, N, b.px, b.py, g, D.s2, plan_threshold(prec), stream));
+  GPL_TRY(plan_build(plan, N, b.px, b.py, g, D.s2, plan_threshold(prec), plan_lo_threshold(prec), stream));
   GPL_TRY(gpl_sersic_eval(src, N, b.px, b.py, b.mu, stream));
   GPL_HIP(hipMemcpyAsync(b.rhs, d, sizeof(float) * npix, hipMemcpyDeviceToDevice, stream));
   if (nrhs > 1)

@@ -468,7 +468,7 @@ static int compute_units() {
 }
 
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
-               hipStream_t stream) {
+               float lo_threshold, hipStream_t stream) {
   GPL_REQUIRE(n >= 1, "plan needs at least one point");
   GPL_REQUIRE(p.nch <= kMaxPlanChunks, "n=%d exceeds the product's limit of %d points", n, kMaxPlanChunks * kChunk);
   int m = 0;
@@ -516,7 +516,6 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   hipLaunchKernelGGL(plan_scaled_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, p.npad, p.xs, p.ys, p.cbox, s2,
                      p.xc, p.yc, p.cen);
   GPL_LAUNCH_CHECK();
-  const float lo_threshold = threshold == kSkipF16x3 ? kLoF16x3 : threshold;
   hipLaunchKernelGGL(plan_lists_kernel, dim3(p.nrt), dim3(64), 0, stream, p.nrt, p.nch, p.cbox, p.sbox, s2,
                      threshold, lo_threshold, p.count, p.list, p.roww);
   GPL_LAUNCH_CHECK();

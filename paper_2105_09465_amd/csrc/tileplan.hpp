@@ -28,11 +28,17 @@ constexpr int kChunksPerTile = kRowTile / kChunk;
 constexpr int kMaxPlanWaves = 3072;    // waves of one product launch (3 per SIMD)
 constexpr int kMaxPlanChunks = 65535;  // chunk indices are 16-bit
 
-// Skip thresholds on s2 g^2 (exp2 arguments: 11 - s2 d^2 <= -25 leaves the FP16
-// hi and lo parts zero; -s2 d^2 <= -152 underflows FP32 to zero; each with
-// margin for the FP32 rounding of the box gap and of d^2).
+// Skip thresholds on s2 g^2. Precision form: the exp2 argument 11 - s2 d^2 <= -25
+// leaves the FP16 hi and lo parts exactly zero (margin for the FP32 rounding of
+// the box gap and of d^2), so nothing is dropped. FP32 form: the same cutoff
+// drops terms k_ij v_j with k_ij <= 2^-36 a^2, an error-bounded cutoff rather than
+// an exact zero: per row the dropped terms sum to at most 2^-36 a^2 sum_j |v_j|
+// (5.8e-7 a^2 max|v| at 40,000 points), and both forms evaluate the same pairs.
+// -s2 d^2 <= -152 underflows FP32 itself to zero (kept for the adjoint's plan,
+// whose own per-chunk cutoff is applied on top).
 constexpr float kSkipF16x3 = 36.f;
-constexpr float kSkipFp32 = 152.f;
+constexpr float kSkipFp32 = 36.f;
+constexpr float kSkipFp32Exact = 152.f;
 // In the precision form a (subtile, chunk) pair with s2 g^2 >= kLoF16x3 has
 // every kernel value k <= 2^-20, so the lo part of its exp tile (below 2^-10 k)
 // is below 2^-30 per entry, under a 2^-20 share of the FP32 rounding of an
@@ -187,10 +193,11 @@ void plan_carve(C& cv, int n, TilePlan& p) {
 // their positions (ties in caller order, so the plan depends only on the
 // points). `grid` (nullable) is checked against n: with one, the points are its
 // fine grid in row-major order, which is what irank is indexed by in the fused
-// PSF adjoint. `s2` is the exp2 scale, `threshold` one of kSkipF16x3 / kSkipFp32
-// (with kSkipF16x3 the lo masks use kLoF16x3).
+// PSF adjoint. `s2` is the exp2 scale, `threshold` the skip threshold of the
+// form and `lo_threshold` that of the lo masks (kLoF16x3 in the precision form;
+// equal to `threshold` where the form has no lo part).
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
-               hipStream_t stream);
+               float lo_threshold, hipStream_t stream);
 
 // Relative work of a wave in the first, second and later dispatch rounds.
 constexpr int kRounds = 3;

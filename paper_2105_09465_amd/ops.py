@@ -123,17 +123,20 @@ def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0, grid:
     return out[0] if (squeeze and out.dim() == 2) else out
 
 
-def kernel_mvm_live_tiles(kernel: Kernel, px, py, prec="fp32", grid: Grid | None = None) -> tuple[int, int]:
+def kernel_mvm_live_tiles(kernel: Kernel, px, py, prec="fp32", grid: Grid | None = None, with_lo=False):
     """Work of the product for these points: (64-point row tile, 32-point chunk)
     pairs visited and (16-point subtile, 32-point chunk) pairs evaluated (512
-    kernel values each); synchronises the stream."""
+    kernel values each), and with with_lo also those evaluated pairs that need
+    the lo part of the exp tile in the precision form; synchronises the stream."""
     n = px.numel()
     ws, wsb = workspace(_lib.lib.gpl_gp_kernel_mvm_plan_workspace(n), px.device)
-    tiles, subtiles = C.c_longlong(0), C.c_longlong(0)
+    tiles, subtiles, lo = C.c_longlong(0), C.c_longlong(0), C.c_longlong(0)
     k = kernel.c()
     g = C.byref(grid.c()) if grid is not None else None
     _lib.call("gpl_gp_kernel_mvm_plan_stats", C.byref(k), g, n, _ptr(px), _ptr(py), prec_code(prec), C.byref(tiles),
-              C.byref(subtiles), _wsptr(ws), wsb, _stream())
+              C.byref(subtiles), C.byref(lo), _wsptr(ws), wsb, _stream())
+    if with_lo:
+        return int(tiles.value), int(subtiles.value), int(lo.value)
     return int(tiles.value), int(subtiles.value)
 
 
@@ -154,8 +157,12 @@ def apply_A(problem: Problem, px, py, X, prec="fp32"):
 
 
 def cg_solve(problem: Problem, px, py, Bm, tol=1e-6, max_iter=1000, fixed_iters=0, n_lanczos=30, prec="fp32",
-             check_every=8, ws=None):
-    """CG on A X = Bm for every column of Bm (ncols, n_pix). Returns device tensors."""
+             check_every=8, ws=None, true_residual=True):
+    """CG on A X = Bm for every column of Bm (ncols, n_pix). Returns device tensors.
+    check_every = 0 enqueues every iteration up to the cap without any host
+    wait; k > 0 lets the library wait for the active count every k iterations
+    and stop enqueueing once all columns have stopped. true_residual adds
+    |b - A x|/|b| of the returned iterate (one more product with A)."""
     npix = problem.grid.n_pix
     ldb = _block(Bm, npix, "Bm")
     m = Bm.shape[0]
@@ -166,6 +173,7 @@ def cg_solve(problem: Problem, px, py, Bm, tol=1e-6, max_iter=1000, fixed_iters=
     bnorm2 = torch.empty(m, dtype=torch.float64, device=dev)
     iters = torch.empty(m, dtype=torch.int32, device=dev)
     relres = torch.empty(m, dtype=torch.float64, device=dev)
+    true_relres = torch.empty(m, dtype=torch.float64, device=dev) if true_residual else None
     status = torch.empty(m, dtype=torch.int32, device=dev)
     pc = prec_code(prec)
     pr = problem_c(problem, px, py)
@@ -173,9 +181,10 @@ def cg_solve(problem: Problem, px, py, Bm, tol=1e-6, max_iter=1000, fixed_iters=
     if ws is None or ws.numel() < need:
         ws, _ = workspace(need, dev)
     _lib.call("gpl_cg_solve", C.byref(pr), m, _ptr(Bm), ldb, _ptr(X), npix, float(tol), int(max_iter),
-              int(fixed_iters), nl, _ptr(ab), _ptr(bnorm2), _ptr(iters), _ptr(relres), _ptr(status), pc,
-              int(check_every), _wsptr(ws), int(need), _stream())
-    return dict(X=X, ab=ab[:, :nl], bnorm2=bnorm2, iters=iters, relres=relres, status=status, n_lanczos=nl)
+              int(fixed_iters), nl, _ptr(ab), _ptr(bnorm2), _ptr(iters), _ptr(relres), _ptr(true_relres),
+              _ptr(status), pc, int(check_every), _wsptr(ws), int(need), _stream())
+    return dict(X=X, ab=ab[:, :nl], bnorm2=bnorm2, iters=iters, relres=relres, true_relres=true_relres,
+                status=status, n_lanczos=nl)
 
 
 def lanczos_logdet(ab, iters, bnorm2, scale):
@@ -195,6 +204,20 @@ def lanczos_logdet(ab, iters, bnorm2, scale):
 def evidence_scalars(n_pix, n_points, r, u, logdet, amplitude, noise_sigma):
     out = torch.empty(3, dtype=torch.float64, device=r.device)
     _lib.call("gpl_evidence_scalars", n_pix, n_points, _ptr(r), _ptr(u), _ptr(logdet), float(amplitude),
+              float(noise_sigma), _ptr(out), _stream())
+    return out
+
+
+def evidence_amplitude_grad(n_points, u, Z, X, quad, scale, amplitude, noise_sigma):
+    """(d ln p/d alpha, d L_VI/d alpha) as a float64 2-vector on the device; Z, X:
+    (m, n_pix) probes and their solves (m may be 0), quad a device scalar."""
+    npix = u.numel()
+    m = 0 if Z is None else Z.shape[0]
+    ldz = _block(Z, npix, "Z") if m else npix
+    ldx = _block(X, npix, "X") if m else npix
+    out = torch.empty(2, dtype=torch.float64, device=u.device)
+    _lib.call("gpl_evidence_amplitude_grad", npix, int(n_points), m, _ptr(u), _ptr(Z) if m else None, ldz,
+              _ptr(X) if m else None, ldx, _ptr(quad, torch.float64), float(scale), float(amplitude),
               float(noise_sigma), _ptr(out), _stream())
     return out
 

@@ -34,8 +34,10 @@ class Reconstruction:
     def host(self):
         """Copy the scalar results to the host (one synchronisation)."""
         s = self.scalars.double().cpu().tolist()
+        tr = self.cg.get("true_relres")
         return dict(quad=s[0], lnp=s[1], vi=s[2], logdet=float(self.logdet.item()), stderr=float(self.stderr.item()),
                     iters=self.cg["iters"].cpu().tolist(), relres=self.cg["relres"].cpu().tolist(),
+                    true_relres=tr.cpu().tolist() if tr is not None else None,
                     status=self.cg["status"].cpu().tolist())
 
 

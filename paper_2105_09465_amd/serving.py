@@ -14,13 +14,12 @@ from __future__ import annotations
 import collections
 import ctypes as C
 import dataclasses
-import math
 import time
 
 import numpy as np
 import torch
 
-from . import _lib, ops
+from . import _lib
 from .params import Problem
 
 PREC = {"fp32": _lib.PREC_FP32, "f16x3": _lib.PREC_F16X3}
@@ -54,23 +53,6 @@ class Result:
     @property
     def latency(self):
         return self.finished - self.arrival
-
-
-def mock_observation(problem: Problem, noise: np.ndarray, field: np.ndarray):
-    """A mock lensed image from library calls only: the Sersic mean plus a smooth
-    random field (the kernel product of white noise `field` with a kernel of
-    lengthscale l/sqrt(2), rescaled to the kernel amplitude), observed through
-    B, plus i.i.d. noise of the problem's sigma."""
-    g = problem.grid
-    pts = ops.lens_raytrace(g, problem.lens)
-    mu = ops.sersic_eval(problem.source, pts[0], pts[1])
-    wn = torch.as_tensor(field, dtype=torch.float32, device="cuda")
-    k2 = dataclasses.replace(problem.kernel, lengthscale=problem.kernel.lengthscale / math.sqrt(2.0))
-    gf = ops.kernel_mvm(k2, pts[0], pts[1], wn, prec="fp32", grid=g)
-    gf = gf * (problem.kernel.amplitude / gf.std().clamp_min(1e-30))
-    f = mu + gf
-    d = ops.psf_conv(g, problem.psf, f, adjoint=False)
-    return d + problem.noise_sigma * torch.as_tensor(noise, dtype=torch.float32, device="cuda")
 
 
 class _Slot:

@@ -365,8 +365,17 @@ def test_kernel_mvm_grid_tiles(G, prec):
     assert err <= 1e-5
     Yback = np.empty_like(t64(Yg))
     Yback[:, sh] = t64(Ys)
-    diff = np.abs(t64(Yg) - Yback).max(axis=1) / np.abs(t64(Yg)).max(axis=1)
-    assert diff.max() <= 1e-5, diff.max()
+    # the shuffled input makes a plan of its own (ties break in caller order), so
+    # it is held to the same per-entry bound; the two then differ by at most the
+    # sum of the two bounds. The largest difference over all rows relative to
+    # the column's largest entry is reported.
+    err_s = np.max(np.abs(Yback.T[rows] - want) / scale)
+    dif = np.max(np.abs(t64(Yg).T[rows] - Yback.T[rows]) / scale)
+    rel_all = (np.abs(t64(Yg) - Yback).max(axis=1) / np.abs(t64(Yg)).max(axis=1)).max()
+    print(f"shuffled order: |err| / (|K||V|) {err_s:.2e}; difference {dif:.2e} of |K||V| on the sampled rows, "
+          f"{rel_all:.2e} of max |Y| over all rows")
+    assert err_s <= 1e-5
+    assert dif <= 2e-5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "f16x3"])
@@ -400,6 +409,37 @@ def test_kernel_mvm_isolated_points(G, prec):
     Y = G.ops.kernel_mvm(G.Kernel(1e-4, 0.3), cuda32(px), cuda32(py), cuda32(V), prec=prec)
     want = 0.09 * V.astype(np.float64)
     assert np.max(np.abs(t64(Y) - want) / np.abs(want).max()) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16x3"])
+def test_kernel_mvm_tiny_columns(G, prec):
+    """Columns whose largest entry is 1e-36 (below 2^-113) or subnormal (1e-40):
+    the precision form's power-of-two column scale is capped so that it stays a
+    finite float, and the result keeps the per-entry bound of the other cases."""
+    _say("mvm tiny columns", prec)
+    rng = np.random.default_rng(24)
+    n = 1500
+    px, py = rng.uniform(-0.4, 0.4, (2, n))
+    V = rng.standard_normal((3, n))
+    V[0] *= 1e-36
+    V[1] *= 1e-40 / np.abs(V[1]).max()  # largest entry subnormal in FP32
+    V32 = V.astype(np.float32)
+    Y = G.ops.kernel_mvm(G.Kernel(0.04, 0.3), cuda32(px), cuda32(py), torch.as_tensor(V32, device="cuda"),
+                         prec=prec)
+    X, Yp = px.astype(np.float32).astype(np.float64), py.astype(np.float32).astype(np.float64)
+    V64 = V32.astype(np.float64).T
+    want = okernel.kernel_mvm(X, Yp, V64, 0.04, 0.3)
+    scale = okernel.kernel_abs_mvm_rows(X, Yp, np.arange(n), V64, 0.04, 0.3)
+    got = t64(Y).T
+    assert np.all(np.isfinite(got))
+    err0 = np.max(np.abs(got[:, 0] - want[:, 0]) / scale[:, 0])
+    err2 = np.max(np.abs(got[:, 2] - want[:, 2]) / scale[:, 2])
+    print(f"{prec}: 1e-36 column {err0:.2e}, normal column {err2:.2e}")
+    assert err0 <= 1e-5 and err2 <= 1e-5
+    # the subnormal column: its results are subnormal too, where the device may
+    # flush to zero; what is asserted is that nothing overflows on the way
+    tiny = np.finfo(np.float32).smallest_subnormal
+    assert np.max(np.abs(got[:, 1])) <= 1.01 * scale[:, 1].max() + 64 * tiny
 
 
 def test_kernel_mvm_beta_accumulate(G):
@@ -463,30 +503,25 @@ def _oracle_solution(w, d):
     return oev.solve_problem(P, d)
 
 
-def _cg_fp32_replay(A, B, iters):
-    """The CG recurrences with FP32 vectors and products and FP64 scalars."""
-    A32 = A.astype(np.float32)
-    X = np.zeros(B.shape, dtype=np.float32)
-    R = B.astype(np.float32).copy()
-    P = R.copy()
-    rr = np.sum(R.astype(np.float64) ** 2, axis=0)
-    for _ in range(iters):
-        AP = (A32 @ P).astype(np.float32)
-        a = rr / np.sum(P.astype(np.float64) * AP, axis=0)
-        X = (X + a.astype(np.float32) * P).astype(np.float32)
-        R = (R - a.astype(np.float32) * AP).astype(np.float32)
-        rn = np.sum(R.astype(np.float64) ** 2, axis=0)
-        P = (R + (rn / rr).astype(np.float32) * P).astype(np.float32)
-        rr = rn
-    return X
+def _energy_error(A, Xs, X):
+    """|x* - x|_A per column (the error CG minimises over its Krylov space)."""
+    E = Xs - X
+    return np.sqrt(np.maximum(np.sum(E * (A @ E), axis=0), 0.0))
 
 
 def test_cg_fixed_50_iterations_plain_workload(G):
-    """24x24 workload: CG with exactly 50 iterations, as the workload asks, next to
-    the exact Cholesky solution. At condition ~1e4, 50 steps are far from
-    convergence and FP32 rounding moves the iterate by a few per cent from the
-    FP64 recurrence (an FP32 replay of the recurrences shows the same), so the
-    GPU iterate is checked against that replay and the gaps are reported."""
+    """24x24 workload: CG with exactly 50 iterations, as the workload asks, against
+    the oracle. At condition ~1.2e4, 50 steps are far from convergence and the
+    iterate depends on the order of FP32 rounding, so the bounds come from the
+    oracle itself:
+    - Krylov optimality: no iterate of 50 steps has a smaller energy-norm error
+      than the FP64 oracle CG's (up to 1%);
+    - rounding spread: the oracle's FP32-vector CG (FP64 scalars, the GPU's
+      arithmetic) on four orderings of the same pixels gives four valid FP32
+      iterates; the GPU iterate and its quad must lie within 3x their largest
+      pairwise spread of the identity-order run;
+    - the first Lanczos coefficients, still well determined, match the FP64
+      oracle's to 1e-3."""
     w, d, _ = observation(0)
     _say("cg 50 iterations", w.name)
     prob = gpu_problem(w)
@@ -497,24 +532,34 @@ def test_cg_fixed_50_iterations_plain_workload(G):
     ex = _oracle_solution(w, d)
     A = ex["A"]
     rhs = np.concatenate([ex["r"][:, None], Z], axis=1)
+    Xs = np.linalg.solve(A, rhs)
     ocg = okrylov.cg(lambda X: A @ X, rhs, fixed_iters=50, n_lanczos=30)
     X = t64(rec.X).T
-    X32 = _cg_fp32_replay(A, rhs, 50).astype(np.float64)
-    rel32 = np.linalg.norm(X - X32, axis=0) / np.linalg.norm(X32, axis=0)
-    rel64 = np.linalg.norm(X - ocg["X"], axis=0) / np.linalg.norm(ocg["X"], axis=0)
-    q50 = ex["r"] @ ocg["X"][:, 0]
-    print(f"vs FP32 replay {rel32.max():.2e}; vs FP64 CG {rel64.max():.2e}; quad(50) gpu {h['quad']:.4f} "
-          f"fp32-replay {ex['r'] @ X32[:, 0]:.4f} fp64 {q50:.4f} cholesky {ex['quad']:.4f}")
-    # at condition ~1e4 the 50-step iterate is sensitive to the order of FP32
-    # rounding (two FP32 evaluations of the same recurrence differ by ~1%);
-    # assert what is stable and report the rest
-    assert rel32.max() < 3e-2
-    assert math.isclose(h["quad"], ex["r"] @ X32[:, 0], rel_tol=3e-3)
+    runs = []
+    for seed in range(4):
+        p = np.arange(w.n_pix) if seed == 0 else np.random.default_rng(100 + seed).permutation(w.n_pix)
+        Ap32 = A[np.ix_(p, p)].astype(np.float32)
+        Xp = okrylov.cg(lambda V: (Ap32 @ V).astype(np.float32), rhs[p], fixed_iters=50, n_lanczos=0,
+                        vec_dtype=np.float32)["X"]
+        Xo = np.empty_like(Xp)
+        Xo[p] = Xp
+        runs.append(Xo)
+    spread_it = max(np.max(np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0))
+                    for k, a in enumerate(runs) for b in runs[k + 1:])
+    quads = [ex["r"] @ R[:, 0] for R in runs]
+    spread_q = (max(quads) - min(quads)) / abs(quads[0])
+    rel_it = np.max(np.linalg.norm(X - runs[0], axis=0) / np.linalg.norm(runs[0], axis=0))
+    rel_q = abs(h["quad"] - quads[0]) / abs(quads[0])
+    e_gpu, e_64 = _energy_error(A, Xs, X), _energy_error(A, Xs, ocg["X"])
     tr_gpu = np.linalg.norm(rhs - A @ X, axis=0) / np.linalg.norm(rhs, axis=0)
     tr_64 = np.linalg.norm(rhs - A @ ocg["X"], axis=0) / np.linalg.norm(rhs, axis=0)
-    print("true relative residual after 50 steps: gpu", tr_gpu.max(), "fp64", tr_64.max())
-    # the first Lanczos coefficients are still well determined (FP32 and FP64
-    # recurrences part ways after ~7 steps at this condition number)
+    print(f"iterate vs oracle FP32 {rel_it:.2e} (oracle FP32 spread {spread_it:.2e}); quad vs oracle FP32 "
+          f"{rel_q:.2e} (spread {spread_q:.2e}); energy error gpu/fp64 {np.min(e_gpu / e_64):.3f}.."
+          f"{np.max(e_gpu / e_64):.3f}; true residual gpu {tr_gpu.max():.3f} fp64 {tr_64.max():.3f}; quad(50) "
+          f"gpu {h['quad']:.4f} fp64 {ex['r'] @ ocg['X'][:, 0]:.4f} cholesky {ex['quad']:.4f}")
+    assert np.all(e_gpu >= 0.99 * e_64)
+    assert rel_it <= 3 * spread_it
+    assert rel_q <= 3 * spread_q
     ab = rec.cg["ab"].double().cpu().numpy()
     assert np.allclose(ab[:, :6, 0], ocg["alphas"][:, :6], rtol=1e-3)
     assert np.allclose(ab[:, :6, 1], ocg["betas"][:, :6], rtol=1e-3)
@@ -532,6 +577,17 @@ def test_evidence_converged_vs_cholesky(G, index, n, ss):
     ex = _oracle_solution(w, d)
     assert all(s == 0 for s in h["status"]), h["status"]
     assert max(h["relres"]) <= 1e-6
+    # true residual of the returned iterate, as the library recomputes it after
+    # the last iteration, against the oracle's FP64 |b - A x|/|b| of the same
+    # iterate: the library's product with A is accurate to ~2^-21 of A|X| per
+    # entry (A has no negative entries), which bounds the difference
+    X = t64(rec.X).T
+    rhs = np.concatenate([ex["r"][:, None], Z], axis=1)
+    tr64 = np.linalg.norm(rhs - ex["A"] @ X, axis=0) / np.linalg.norm(rhs, axis=0)
+    floor = np.linalg.norm(ex["A"] @ np.abs(X), axis=0) / np.linalg.norm(rhs, axis=0) * 2.0 ** -21
+    trg = np.array(h["true_relres"])
+    print(f"true residual: library {trg.max():.2e}, oracle FP64 {tr64.max():.2e}, product floor {floor.max():.2e}")
+    assert np.all(np.abs(trg - tr64) <= 4 * floor + 1e-3 * tr64)
     quad_rel = abs(h["quad"] - ex["quad"]) / ex["quad"]
     ld_err = h["logdet"] - ex["logdet"]
     print(f"quad rel {quad_rel:.2e}; logdet err {ld_err:.3f} (stderr {h['stderr']:.3f}); "

@@ -1,12 +1,17 @@
 """Continuous batching: each request's result is the same alone and in the mix
-(bitwise), equals the single-request path, admission respects the memory budget
-and stalled solves are reported rather than hung."""
+(bitwise), equals the single-request path and the FP64 oracle's evidence,
+admission respects the memory budget and stalled solves are reported rather
+than hung. Observations are simulated by the oracle."""
+import functools
+
 import numpy as np
 import pytest
 
 import synth
+from oracle import data as odata
+from oracle import evidence as oev
 
-from helpers import gpu_problem
+from helpers import gpu_problem, oracle_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -28,15 +33,28 @@ def _say(*a):
 SIZES = [(24, 1), (40, 2), (32, 1), (48, 2), (28, 2), (36, 1)]
 
 
+@functools.lru_cache(maxsize=32)
+def _observed(side, ss, seed):
+    """Serving request of this size and seed, its image simulated by the oracle
+    (exact GP draw up to 4096 points, random Fourier features above)."""
+    w = synth.serving_request(side, ss, seed)
+    P = oracle_problem(w)
+    noise = synth.noise_normals(w.n_pix, 4, seed)
+    if w.N <= 4096:
+        d, _ = odata.simulate(P, noise, gp_normals=synth.gp_normals(w.N, 4, seed))
+    else:
+        d, _ = odata.simulate(P, noise, rff=synth.rff_draws(8192, 4, seed))
+    return w, d
+
+
 def _requests(G, sizes=SIZES, m=16):
     reqs = []
     for k, (side, ss) in enumerate(sizes):
-        w = synth.serving_request(side, ss, 1000 + k)
+        w, d = _observed(side, ss, 1000 + k)
         prob = gpu_problem(w)
-        d = G.serving.mock_observation(prob, synth.noise_normals(w.n_pix, 4, 1000 + k),
-                                       synth.gp_normals(w.N, 4, 1000 + k))
+        dd = torch.as_tensor(d, dtype=torch.float32, device="cuda")
         Z = torch.as_tensor(synth.rademacher(w.n_pix, m, 4, 1000 + k).T.copy(), dtype=torch.float32, device="cuda")
-        reqs.append(G.serving.Request(k, 0.0, prob, d, Z))
+        reqs.append(G.serving.Request(k, 0.0, prob, dd, Z))
     return reqs
 
 
@@ -93,3 +111,33 @@ def test_stalled_solves_reported(G):
     for r in res:
         assert max(r.iters) <= 5
         assert all(s == 1 for s in r.status)  # max_iter reached, reported per column
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "fp32"])
+def test_served_results_vs_oracle(G, prec):
+    """Requests of three sizes served together, each against the oracle's exact
+    Cholesky evidence of the same observation, with the bounds of the
+    single-request evidence tests: quad and L_VI within 1e-5, the 16-probe SLQ
+    log-determinant within 4 standard errors, the predicted image within 1e-4 of
+    its maximum; the ln p error is reported beside the SLQ standard error."""
+    sizes = [(24, 1), (40, 2), (48, 1), (32, 2)]
+    _say("served vs oracle", prec, sizes)
+    reqs = _requests(G, sizes)
+    res = {r.rid: r for r in G.serving.ServingEngine(prec=prec, max_slots=4, want_image=True).run(reqs,
+                                                                                                 realtime=False)}
+    for k, (side, ss) in enumerate(sizes):
+        w, d = _observed(side, ss, 1000 + k)
+        ex = oev.solve_problem(oracle_problem(w), d)
+        r = res[k]
+        quad_rel = abs(r.quad - ex["quad"]) / ex["quad"]
+        ld_err = r.logdet - ex["logdet"]
+        lnp_rel = abs(r.lnp - ex["lnp"]) / abs(ex["lnp"])
+        vi_rel = abs(r.vi - ex["vi"]) / abs(ex["vi"])
+        im = r.image.double().cpu().numpy()
+        im_err = np.max(np.abs(im - ex["image"])) / np.max(np.abs(ex["image"]))
+        print(f"{side}px ss{ss}: quad rel {quad_rel:.2e}; logdet err {ld_err:.2f} (stderr {r.stderr:.2f}); lnp rel "
+              f"{lnp_rel:.2e} (stderr/|lnp| {0.5 * r.stderr / abs(ex['lnp']):.2e}); image {im_err:.2e}")
+        assert all(s == 0 for s in r.status)
+        assert quad_rel <= 1e-5 and vi_rel <= 1e-5
+        assert abs(ld_err) <= 4 * r.stderr
+        assert im_err <= 1e-4
