@@ -14,7 +14,7 @@ import scipy.integrate as si
 import scipy.stats as st
 
 import synth
-from oracle import data, evidence, gradients, grid, kernel, krylov, lens, psf, source
+from oracle import data, evidence, gradients, grid, kernel, krylov, lens, precond, psf, source
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -390,6 +390,82 @@ def test_slq_all_unit_probes_is_exact():
     res = krylov.cg(lambda X: A @ X, E, tol=0.0, fixed_iters=n, n_lanczos=n)
     est, _, _ = krylov.slq_logdet(res["alphas"], res["betas"], res["iters"], res["bnorm2"], n, scale=1.0)
     assert math.isclose(est, np.linalg.slogdet(A)[1], rel_tol=1e-10)
+
+
+# ---------------------------------------------------------------- preconditioned solves and log-det
+
+def test_pivoted_cholesky_exact_at_full_rank_and_greedy():
+    M = _spd(n=40, seed=11) - 0.05 * np.eye(40)  # the kernel part, PSD
+    L, piv = precond.pivoted_cholesky(M, 40)
+    assert np.allclose(L @ L.T, M, rtol=0, atol=1e-12 * np.abs(M).max())
+    # lower triangular in pivot order, first pivot the largest diagonal entry
+    Lp = L[piv]
+    assert np.allclose(np.triu(Lp, 1), 0.0)
+    assert piv[0] == int(np.argmax(np.diag(M)))
+    # a partial factor is exact on its pivot rows and columns and leaves a PSD rest
+    L6, piv6 = precond.pivoted_cholesky(M, 6)
+    assert np.allclose((L6 @ L6.T)[:, piv6], M[:, piv6], atol=1e-12)
+    assert np.linalg.eigvalsh(M - L6 @ L6.T).min() > -1e-12
+    # the second pivot maximises the residual diagonal after the first step
+    L1, _ = precond.pivoted_cholesky(M, 1)
+    assert piv6[1] == int(np.argmax(np.diag(M - L1 @ L1.T)))
+
+
+def test_lowrank_logdet_and_woodbury():
+    rng = np.random.default_rng(12)
+    L = rng.standard_normal((50, 7))
+    s = 0.3
+    P = L @ L.T + s * np.eye(50)
+    assert math.isclose(precond.logdet_lowrank_plus_shift(L, s), np.linalg.slogdet(P)[1], rel_tol=1e-12)
+    V = rng.standard_normal((50, 3))
+    assert np.allclose(P @ precond.woodbury_solver(L, s)(V), V, rtol=1e-10, atol=1e-10)
+
+
+def test_pcg_solves_and_reduces_to_cg():
+    A = _spd(n=60, seed=13)
+    b = np.random.default_rng(14).standard_normal((60, 2))
+    x = np.linalg.solve(A, b)
+    M = A - 0.05 * np.eye(60)
+    L, _ = precond.pivoted_cholesky(M, 10)
+    res = precond.pcg(lambda X: A @ X, precond.woodbury_solver(L, 0.05), b, tol=1e-12, max_iter=200)
+    assert np.allclose(res["X"], x, rtol=1e-9, atol=1e-10)
+    exact = precond.pcg(lambda X: A @ X, lambda R: np.linalg.solve(A, R), b, tol=1e-12, max_iter=5)
+    assert np.all(exact["iters"] == 1)  # M = A: one step
+    plain = krylov.cg(lambda X: A @ X, b, tol=1e-12, max_iter=200, n_lanczos=20)
+    ident = precond.pcg(lambda X: A @ X, lambda R: R.copy(), b, tol=1e-12, max_iter=200, n_lanczos=20)
+    assert np.allclose(ident["alphas"], plain["alphas"]) and np.allclose(ident["betas"], plain["betas"])
+    assert np.allclose(ident["rz0"], plain["bnorm2"])
+
+
+def test_preconditioned_slq_whitened_unit_probes_is_exact():
+    """Probes P^{1/2} e_j for every j with full-length PCG: the estimate is
+    ln|P| + tr ln(P^{-1/2} A P^{-1/2}) = ln|A| exactly."""
+    n = 30
+    A = _spd(n=n, seed=15)
+    s = 0.05
+    L, _ = precond.pivoted_cholesky(A - s * np.eye(n), 5)
+    P = L @ L.T + s * np.eye(n)
+    w, V = np.linalg.eigh(P)
+    Z = (V * np.sqrt(w)) @ V.T  # P^{1/2} e_j as columns
+    res = precond.pcg(lambda X: A @ X, precond.woodbury_solver(L, s), Z, tol=0.0, fixed_iters=n, n_lanczos=n)
+    est, _, _ = precond.preconditioned_slq_logdet(res["alphas"], res["betas"], res["iters"], res["rz0"], n,
+                                                  precond.logdet_lowrank_plus_shift(L, s))
+    # scale: slq_logdet averages over m probes; whitened unit probes sum, so times n
+    ld_rest = (est - precond.logdet_lowrank_plus_shift(L, s)) * n
+    assert math.isclose(precond.logdet_lowrank_plus_shift(L, s) + ld_rest, np.linalg.slogdet(A)[1], rel_tol=1e-10)
+
+
+def test_preconditioned_probes_have_covariance_P():
+    rng = np.random.default_rng(16)
+    n, k, m = 40, 6, 20000
+    L = rng.standard_normal((n, k))
+    s = 0.2
+    Z = precond.probes_from(L, s, rng.standard_normal((k, m)), rng.standard_normal((n, m)))
+    P = L @ L.T + s * np.eye(n)
+    C = Z @ Z.T / m
+    assert np.max(np.abs(C - P)) <= 5 * np.sqrt(2.0 / m) * np.max(np.diag(P))
+    q = np.sum(Z * np.linalg.solve(P, Z), axis=0)  # chi-square with n degrees of freedom
+    assert abs(q.mean() - n) <= 5 * math.sqrt(2 * n / m)
 
 
 def test_slq_rademacher_within_stderr():
