@@ -206,16 +206,63 @@ int gpl_cg_solve(const gpl_problem* prob, int nrhs, const float* Bm, int ldb, fl
  * values), evaluated in FP64 from the integral representation
  * ln x = int e^s (1/(1+e^s) - 1/(x+e^s)) ds with the trapezoidal rule and
  * continued-fraction resolvents of T.
- * logdet = scale * sum_j contrib[j] (scale 1/nprobe for Hutchinson probes,
- * 1 for all unit vectors); stderr = scale * sqrt(nprobe) * sd(contrib).
+ * logdet = scale * sum_j contrib[j] + *offset (scale 1/nprobe for Hutchinson
+ * probes, 1 for all unit vectors; offset a device scalar, nullable: ln|P| for
+ * the preconditioned estimate below); stderr = scale * sqrt(nprobe) * sd(contrib).
  * lanczos_ab, iters, bnorm2 as written by gpl_cg_solve (probe columns only);
  * n_lanczos <= 4096. Outputs (device): contrib[nprobe], logdet[1], stderr[1].
  * A probe whose tridiagonal is not positive definite contributes NaN.
  * The workspace size is 0 (ws may be NULL). */
 size_t gpl_lanczos_logdet_workspace(int nprobe, int n_lanczos);
 int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, const int* iters, const double* bnorm2,
-                       double scale, double* contrib, double* logdet, double* stderr_out, void* ws, size_t ws_bytes,
-                       hipStream_t stream);
+                       double scale, const double* offset, double* contrib, double* logdet, double* stderr_out,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- preconditioned evidence
+ * The stochastic log-determinant of eq. "gp-mll" carries a noise Sec. 3.3
+ * names as the reason the paper avoids it (1-2% in GPyTorch). GPyTorch, which
+ * Sec. 3.3 cites for CG and that estimate, lowers the noise and the iteration
+ * count with a preconditioner P = L L^T + sigma^2 I from a partial pivoted
+ * Cholesky factor L of M = B K B^T (Gardner et al. 2018): ln|A| = ln|P| +
+ * ln|P^{-1/2} A P^{-1/2}|, the first term exact by the determinant lemma, the
+ * second estimated by SLQ on preconditioned CG with probes z ~ N(0, P).
+ *
+ * gpl_pchol: L (n*n x k, FP64, column-major, ld ldl) with k a multiple of 64,
+ * built 64 pivots at a time. The candidates of a block are the 64 largest
+ * entries of the residual diagonal of M - L L^T (ranked in FP32, ties by lower
+ * pixel index); their columns of M come from the matrix-free product applied
+ * to unit vectors (in precision `prec`), minus L L^T; a pivoted Cholesky of
+ * the 64 x 64 residual block takes them largest-first while the residual
+ * pivot exceeds 1e-5 of the largest diagonal entry of M (below that the FP32
+ * columns are rounding noise). pivots[j] = the pixel
+ * of column j, -1 for a zero column (a candidate not taken). G (k x k, ld ldg)
+ * receives the lower Cholesky factor of sigma^2 I + L^T L; logdet_P (device
+ * scalar) = ln|P| = (n*n - k) ln sigma^2 + ln|sigma^2 I + L^T L|; info (device)
+ * = 0, or 1 + the column where that factorisation failed. noise_sigma > 0. */
+size_t gpl_pchol_workspace(const gpl_problem* prob, int k, int prec);
+int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, int ldl, double* G, int ldg, int* pivots,
+              double* logdet_P, int* info, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Probes z_j = L g_j + noise_sigma h_j, distributed as N(0, P) for standard
+ * normals g (k x m, FP64, ld ldg) and h (n*n x m, FP32, ld ldh) supplied by the
+ * caller; Z (n*n x m, FP32, ld ldz). */
+size_t gpl_pchol_probes_workspace(int npix, int m);
+int gpl_pchol_probes(int npix, int k, const double* L, int ldl, double noise_sigma, int m, const double* g, int ldg,
+                     const float* h, int ldh, float* Z, int ldz, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Preconditioned CG on A X = Bm with P from gpl_pchol (L, G as written there):
+ * z = P^{-1} r by the Woodbury identity (FP64 products), alpha = r.z/p.Ap,
+ * beta = r'.z'/r.z, p = z' + beta p; one recurrence per column, FP32 vectors,
+ * FP64 scalars. Outputs as gpl_cg_solve, with rz0[c] = b_c^T P^{-1} b_c (the
+ * quadrature weight of a probe column) in place of |b|^2: pass rz0 as
+ * `bnorm2`, scale 1/m and offset ln|P| to gpl_lanczos_logdet for the
+ * preconditioned estimate of ln|A|. Stops on the recursive residual |r|/|b|;
+ * check_every as in gpl_cg_solve. */
+size_t gpl_pcg_solve_workspace(const gpl_problem* prob, int k, int nrhs, int prec);
+int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, int ldl, const double* G, int ldg, int nrhs,
+                  const float* Bm, int ldb, float* X, int ldx, double tol, int max_iter, int fixed_iters,
+                  int n_lanczos, double* lanczos_ab, double* rz0, int* iters, double* relres, double* true_relres,
+                  int* status, int prec, int check_every, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Evidence scalars (Sec. 3.1 eq. "gp-mll" with the sign reading
  * -2 ln p = r^T A^{-1} r + ln|2 pi A|; App. D.1 eq. "hyper-loss"):

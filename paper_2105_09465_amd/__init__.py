@@ -8,4 +8,4 @@ package binds it for torch tensors.
 """
 from . import _lib, autograd, ops, params, pipeline, serving  # noqa: F401
 from .params import Grid, Kernel, Lens, Problem, PSF, Sersic  # noqa: F401
-from .pipeline import reconstruct  # noqa: F401
+from .pipeline import reconstruct, reconstruct_preconditioned  # noqa: F401

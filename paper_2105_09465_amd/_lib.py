@@ -84,7 +84,14 @@ SIGNATURES = {
     "gpl_cg_solve": (_I, [C.POINTER(gpl_problem), _I, _P, _I, _P, _I, _D, _I, _I, _I, _P, _P, _P, _P, _P, _P, _I,
                           _I, _P, _Z, _P]),
     "gpl_lanczos_logdet_workspace": (_Z, [_I, _I]),
-    "gpl_lanczos_logdet": (_I, [_I, _I, _P, _P, _P, _D, _P, _P, _P, _P, _Z, _P]),
+    "gpl_lanczos_logdet": (_I, [_I, _I, _P, _P, _P, _D, _P, _P, _P, _P, _P, _Z, _P]),
+    "gpl_pchol_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I]),
+    "gpl_pchol": (_I, [C.POINTER(gpl_problem), _I, _I, _P, _I, _P, _I, _P, _P, _P, _P, _Z, _P]),
+    "gpl_pchol_probes_workspace": (_Z, [_I, _I]),
+    "gpl_pchol_probes": (_I, [_I, _I, _P, _I, _D, _I, _P, _I, _P, _I, _P, _I, _P, _Z, _P]),
+    "gpl_pcg_solve_workspace": (_Z, [C.POINTER(gpl_problem), _I, _I, _I]),
+    "gpl_pcg_solve": (_I, [C.POINTER(gpl_problem), _I, _P, _I, _P, _I, _I, _P, _I, _P, _I, _D, _I, _I, _I, _P, _P,
+                           _P, _P, _P, _P, _I, _I, _P, _Z, _P]),
     "gpl_evidence_scalars": (_I, [_I, _I, _P, _P, _P, _D, _D, _P, _P]),
     "gpl_gp_kernel_mvm_backward_workspace": (_Z, [_I, _I]),
     "gpl_gp_kernel_mvm_backward": (_I, [C.POINTER(gpl_kernel), _I, _P, _P, _I, _P, _I, _P, _I, C.POINTER(_D), _P, _P,

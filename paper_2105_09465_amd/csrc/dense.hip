@@ -1,0 +1,123 @@
+// Dense FP64 linear algebra on small blocks for the preconditioner: a rocBLAS
+// handle per host thread and device (its scratch memory always taken from the
+// caller's workspace), and a blocked right-looking Cholesky factorisation: a
+// one-workgroup kernel factors each 64 x 64 diagonal block in LDS, rocBLAS
+// dtrsm forms the panel below it and dsyrk updates the trailing matrix. The
+// log-determinant is summed from the factor's diagonal in a fixed order.
+#include <cmath>
+
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace gpl {
+
+static thread_local rocblas_handle t_handle[16] = {};
+
+int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t scratch_bytes) {
+  int dev = 0;
+  GPL_HIP(hipGetDevice(&dev));
+  GPL_REQUIRE(dev >= 0 && dev < 16, "device index %d out of range for the BLAS handles", dev);
+  if (t_handle[dev] == nullptr) {
+    if (rocblas_create_handle(&t_handle[dev]) != rocblas_status_success) {
+      set_error("rocblas_create_handle failed");
+      return GPL_EHIP;
+    }
+  }
+  rocblas_handle h = t_handle[dev];
+  if (rocblas_set_stream(h, stream) != rocblas_status_success ||
+      rocblas_set_workspace(h, scratch, scratch_bytes) != rocblas_status_success ||
+      rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success) {
+    set_error("rocblas handle set-up failed");
+    return GPL_EHIP;
+  }
+  *out = h;
+  return GPL_OK;
+}
+
+// Factor the jb x jb diagonal block at A (leading dimension lda) in place:
+// lower Cholesky, column by column in LDS. A non-positive or non-finite pivot
+// sets *info to its global column + 1 (first one wins) and leaves the block
+// unfinished. logd[c] = ln of the diagonal entry of column c.
+constexpr int kDiag = 64;
+__global__ __launch_bounds__(256) void potf2_kernel(double* A, int lda, int jb, int col0, double* logd, int* info) {
+  __shared__ double T[kDiag][kDiag + 1];
+  __shared__ int s_bad;
+  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    T[i][j] = A[(size_t)j * lda + i];
+  }
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int c = 0; c < jb; ++c) {
+    if (threadIdx.x == 0) {
+      const double p = T[c][c];
+      if (!(p > 0.0) || !isfinite(p)) {
+        s_bad = 1;
+        atomicCAS(info, 0, col0 + c + 1);
+      } else {
+        T[c][c] = sqrt(p);
+        logd[col0 + c] = 0.5 * log(p);
+      }
+    }
+    __syncthreads();
+    if (s_bad) return;
+    const double piv = T[c][c];
+    for (int i = c + 1 + threadIdx.x; i < jb; i += blockDim.x) T[i][c] /= piv;
+    __syncthreads();
+    const int m = jb - c - 1;  // trailing lower triangle of order m
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int i = c + 1 + e % m, j = c + 1 + e / m;
+      if (j <= i) T[i][j] -= T[i][c] * T[j][c];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    A[(size_t)j * lda + i] = j <= i ? T[i][j] : 0.0;
+  }
+}
+
+// out[0] = sum of logd[0..n) in index order (one wave, lane-strided then a
+// butterfly), times two: ln|A| of the factored matrix.
+__global__ void logdet_fold_kernel(int n, const double* logd, double* out) {
+  const double s = wave_fold_sum(logd, n);
+  if (threadIdx.x == 0) *out = 2.0 * s;
+}
+
+__global__ void zero_int_kernel(int* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info,
+                   hipStream_t stream) {
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, stream, info);
+  GPL_LAUNCH_CHECK();
+  const double one = 1.0, minus_one = -1.0;
+  for (int j0 = 0; j0 < n; j0 += kDiag) {
+    const int jb = std::min(kDiag, n - j0);
+    double* Ajj = A + (size_t)j0 * lda + j0;
+    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(256), 0, stream, Ajj, lda, jb, j0, logd, info);
+    GPL_LAUNCH_CHECK();
+    const int m = n - j0 - jb;
+    if (m <= 0) break;
+    double* Aij = Ajj + jb;  // the panel below the diagonal block
+    if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                      rocblas_diagonal_non_unit, m, jb, &one, Ajj, lda, Aij, lda) != rocblas_status_success) {
+      set_error("rocblas_dtrsm failed (n=%d, column %d)", n, j0);
+      return GPL_EHIP;
+    }
+    double* Att = A + (size_t)(j0 + jb) * lda + (j0 + jb);
+    if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, m, jb, &minus_one, Aij, lda, &one, Att, lda) !=
+        rocblas_status_success) {
+      set_error("rocblas_dsyrk failed (n=%d, column %d)", n, j0);
+      return GPL_EHIP;
+    }
+  }
+  if (logdet) {
+    hipLaunchKernelGGL(logdet_fold_kernel, dim3(1), dim3(64), 0, stream, n, logd, logdet);
+    GPL_LAUNCH_CHECK();
+  }
+  return GPL_OK;
+}
+
+}  // namespace gpl

@@ -1,0 +1,24 @@
+// Dense FP64 helpers of the preconditioner (csrc/dense.hip).
+#pragma once
+
+#include <rocblas/rocblas.h>
+
+#include "common.hpp"
+
+namespace gpl {
+
+// rocBLAS handle of this host thread on the current device, set to `stream`,
+// host pointer mode, and the given scratch memory (rocBLAS allocates none).
+int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t scratch_bytes);
+
+// Scratch memory handed to rocBLAS by every call that uses it.
+constexpr size_t kBlasScratch = size_t(32) << 20;
+
+// In-place lower Cholesky of the n x n matrix A (column-major, lda >= n; only
+// the lower triangle is read; the strict upper triangle is zeroed block by
+// block). logd[n] receives ln of the factor's diagonal, *logdet (nullable) =
+// ln|A|, *info = 0 or the first failing column + 1 (device scalars).
+int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info,
+                   hipStream_t stream);
+
+}  // namespace gpl

@@ -80,14 +80,15 @@ __global__ __launch_bounds__(64) void slq_probe_kernel(int nprobe, int n_lanczos
   if (lane == 0) contrib[j] = bnorm2[j] * kSlqStep * acc;
 }
 
-__global__ void slq_sum_kernel(int nprobe, double scale, const double* contrib, double* logdet, double* stderr_out) {
+__global__ void slq_sum_kernel(int nprobe, double scale, const double* offset, const double* contrib, double* logdet,
+                               double* stderr_out) {
   if (threadIdx.x != 0) return;
   double s = 0.0;
   for (int j = 0; j < nprobe; ++j) s += contrib[j];
   const double mean = s / nprobe;
   double v = 0.0;
   for (int j = 0; j < nprobe; ++j) v += (contrib[j] - mean) * (contrib[j] - mean);
-  *logdet = scale * s;
+  *logdet = scale * s + (offset ? *offset : 0.0);
   // sample standard deviation of the contributions, scaled like the estimate
   *stderr_out = nprobe > 1 ? scale * sqrt(v / (nprobe - 1)) * sqrt((double)nprobe) : NAN;
 }
@@ -103,8 +104,9 @@ extern "C" size_t gpl_lanczos_logdet_workspace(int nprobe, int n_lanczos) {
 }
 
 extern "C" int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, const int* iters,
-                                  const double* bnorm2, double scale, double* contrib, double* logdet,
-                                  double* stderr_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+                                  const double* bnorm2, double scale, const double* offset, double* contrib,
+                                  double* logdet, double* stderr_out, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
   GPL_REQUIRE(nprobe >= 1 && n_lanczos >= 1, "nprobe=%d n_lanczos=%d must be >= 1", nprobe, n_lanczos);
   GPL_REQUIRE(lanczos_ab && iters && bnorm2 && contrib && logdet && stderr_out, "NULL argument");
   GPL_REQUIRE(std::isfinite(scale), "scale must be finite");
@@ -114,7 +116,8 @@ extern "C" int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lancz
   hipLaunchKernelGGL(slq_probe_kernel, dim3(nprobe), dim3(64), 0, stream, nprobe, n_lanczos, lanczos_ab, iters,
                      bnorm2, contrib);
   GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(slq_sum_kernel, dim3(1), dim3(64), 0, stream, nprobe, scale, contrib, logdet, stderr_out);
+  hipLaunchKernelGGL(slq_sum_kernel, dim3(1), dim3(64), 0, stream, nprobe, scale, offset, contrib, logdet,
+                     stderr_out);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

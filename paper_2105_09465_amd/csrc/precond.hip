@@ -1,0 +1,1066 @@
+// Low-rank preconditioner of A = B K B^T + sigma^2 I and the preconditioned CG
+// that uses it: the GPyTorch scheme Sec. 3.3 cites for CG solves and the
+// stochastic log-determinant (Gardner et al. 2018), which lowers the noise of
+// that estimate (the reason Sec. 3.3 gives for avoiding it).
+//
+// Build. A partial pivoted Cholesky factor L (n x k, FP64) of M = B K B^T, its
+// columns taken 64 at a time: the 64 largest remaining diagonal entries of
+// M - L L^T are the candidates; their columns of M come from one application of
+// B K B^T to unit vectors (the matrix-free product), minus L L^T on them
+// (rocBLAS dgemm); one workgroup runs a pivoted Cholesky on the 64 x 64
+// residual block (largest remaining diagonal first, stopping below a relative
+// threshold), and the block's columns of L follow by a triangular solve
+// (dtrsm). Candidates the block does not take leave zero columns, which change
+// neither L L^T nor the determinant identity below. Then
+//   G = sigma^2 I_k + L^T L = R R^T (dsyrk, blocked Cholesky),
+//   ln|P| = (n - k) ln sigma^2 + ln|G|,  P = L L^T + sigma^2 I_n.
+// Solve. Preconditioned CG, one recurrence per column, with
+//   P^{-1} v = (v - L G^{-1} L^T v) / sigma^2 (dgemm, two dtrsm, dgemm),
+// FP32 vectors, FP64 scalars and Woodbury products; the alpha/beta of the
+// first steps give the Lanczos tridiagonal of P^{-1/2} A P^{-1/2} with the
+// usual CG formulas, and rz0 = b^T P^{-1} b is each probe's quadrature weight.
+#include <cmath>
+
+#include "common.hpp"
+#include "dense.hpp"
+#include "internal.hpp"
+
+namespace gpl {
+
+constexpr int kPcBlock = 64;         // pivots per block
+// A residual pivot below this share of the largest diagonal entry of M is not
+// taken: the columns of M come from FP32 products (relative error ~5e-7), so
+// smaller residuals are rounding noise, and at the workloads' noise level
+// (sigma^2 ~ 6e-3 of the largest diagonal entry) they are far below what the
+// preconditioner needs to capture.
+constexpr double kPcRelTol = 1e-5;
+
+// ---------------------------------------------------------------- diagonal of B K B^T
+
+// d[I] = sum_{f, g in fp(I)} b_f b_g K(p_f, p_g) with b = B^T e_I: the fine
+// points within the composite filter's reach of pixel I (weights
+// g[ty] g[tx] / ss^2, zero outside the grid). One workgroup per pixel; the
+// footprint is staged in LDS and the pair sum is reduced in a fixed order.
+constexpr int kMaxFoot = (2 * GPL_PSF_MAX_RADIUS + 8) * (2 * GPL_PSF_MAX_RADIUS + 8);
+__global__ __launch_bounds__(256) void bkb_diag_kernel(int n, int ss, const Taps taps, float s2, double amp2,
+                                                       const float* __restrict__ px, const float* __restrict__ py,
+                                                       double* d) {
+  __shared__ float fx[kMaxFoot], fy[kMaxFoot], fw[kMaxFoot];
+  __shared__ double red[4];
+  __shared__ int s_cnt;
+  const int I = blockIdx.x, iy = I / n, ix = I - iy * n, M = n * ss, L = taps.L, r = taps.r;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  // compact the in-grid footprint in a fixed (row-major) order
+  if (threadIdx.x == 0) {
+    int c = 0;
+    const float inv = 1.f / (float)(ss * ss);
+    for (int ty = 0; ty < L; ++ty) {
+      const int gy = iy * ss + ty - r;
+      if (gy < 0 || gy >= M) continue;
+      for (int tx = 0; tx < L; ++tx) {
+        const int gx = ix * ss + tx - r;
+        if (gx < 0 || gx >= M) continue;
+        const int j = gy * M + gx;
+        fx[c] = px[j];
+        fy[c] = py[j];
+        fw[c] = taps.g[ty] * taps.g[tx] * inv;
+        ++c;
+      }
+    }
+    s_cnt = c;
+  }
+  __syncthreads();
+  const int c = s_cnt;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < c * c; e += blockDim.x) {
+    const int a = e / c, b = e - a * c;
+    const float dx = fx[a] - fx[b], dy = fy[a] - fy[b];
+    s += (double)fw[a] * (double)fw[b] * (double)exp2_fast(-(fmaf(dx, dx, dy * dy) * s2));
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) d[I] = amp2 * s;
+}
+
+// ---------------------------------------------------------------- candidate selection
+
+// The kPcBlock largest positive entries of d (ranked by their FP32 value, ties
+// by lower index), in index order, into cand[0..kPcBlock); missing slots get
+// -1. One workgroup: a three-pass radix select on the FP32 bit patterns (11, 11
+// and 10 bits), then an ordered compaction.
+constexpr int kSelThreads = 1024;
+__global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const double* __restrict__ d, int* cand) {
+  __shared__ int hist[2048];
+  __shared__ int s_scan[kSelThreads];
+  __shared__ unsigned s_prefix, s_mask;
+  __shared__ int s_need;
+  const int t = threadIdx.x;
+  const int per = cdiv(n, kSelThreads), i0 = t * per, i1 = min(n, i0 + per);
+  auto key = [&](int i) -> unsigned {
+    const double v = d[i];
+    return v > 0.0 ? __float_as_uint((float)v) : 0u;
+  };
+  if (t == 0) {
+    s_prefix = 0u;
+    s_mask = 0u;
+    s_need = kPcBlock;
+  }
+  __syncthreads();
+  const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
+  for (int pass = 0; pass < 3; ++pass) {
+    for (int b = t; b < 2048; b += kSelThreads) hist[b] = 0;
+    __syncthreads();
+    const unsigned prefix = s_prefix, mask = s_mask;
+    const int sh = shifts[pass], nb = 1 << widths[pass];
+    for (int i = i0; i < i1; ++i) {
+      const unsigned k = key(i);
+      if (k != 0u && (k & mask) == prefix) atomicAdd(&hist[(k >> sh) & (nb - 1)], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+      int need = s_need, b = nb - 1;
+      for (; b > 0; --b) {
+        if (hist[b] >= need) break;
+        need -= hist[b];
+      }
+      s_need = need;
+      s_prefix = prefix | ((unsigned)b << sh);
+      s_mask = mask | ((unsigned)(nb - 1) << sh);
+    }
+    __syncthreads();
+  }
+  // threshold key T = s_prefix: every key > T is taken, and the s_need lowest
+  // indices with key == T (fewer if there are not that many)
+  const unsigned T = s_prefix;
+  int above = 0, equal = 0;
+  for (int i = i0; i < i1; ++i) {
+    const unsigned k = key(i);
+    above += (k != 0u && k > T);
+    equal += (k != 0u && k == T);
+  }
+  // exclusive scans of both counts over the threads, in index order
+  s_scan[t] = equal;
+  __syncthreads();
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const int v = t >= off ? s_scan[t - off] : 0;
+    __syncthreads();
+    s_scan[t] += v;
+    __syncthreads();
+  }
+  int eq_before = s_scan[t] - equal;
+  const int eq_take_total = s_need;
+  __syncthreads();
+  s_scan[t] = above + max(0, min(equal, eq_take_total - eq_before));
+  __syncthreads();
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const int v = t >= off ? s_scan[t - off] : 0;
+    __syncthreads();
+    s_scan[t] += v;
+    __syncthreads();
+  }
+  int pos = s_scan[t] - (above + max(0, min(equal, eq_take_total - eq_before)));
+  const int total = s_scan[kSelThreads - 1];
+  for (int i = i0; i < i1; ++i) {
+    const unsigned k = key(i);
+    bool take = false;
+    if (k != 0u && k > T) {
+      take = true;
+    } else if (k != 0u && k == T) {
+      take = eq_before < eq_take_total;
+      ++eq_before;
+    }
+    if (take && pos < kPcBlock) cand[pos++] = i;
+  }
+  for (int q = total + t; q < kPcBlock; q += kSelThreads) cand[q] = -1;
+}
+
+// ---------------------------------------------------------------- small element-wise kernels
+
+// E (npix x kPcBlock, ld npix) = unit columns e_{cand[c]} (zero where cand < 0).
+__global__ void unit_cols_kernel(int npix, const int* cand, float* E) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  E[(size_t)c * npix + i] = cand[c] == i ? 1.f : 0.f;
+}
+
+// C (FP64) = Mc (FP32), npix x kPcBlock.
+__global__ void widen_kernel(int npix, const float* __restrict__ Mc, double* C) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npix) C[(size_t)c * npix + i] = (double)Mc[(size_t)c * npix + i];
+}
+
+// Lc (kPcBlock x j) = L[cand, 0..j): rows of the factor at the candidates (0 for
+// a missing candidate).
+__global__ void gather_rows_kernel(int j, const double* __restrict__ L, int ldl, const int* cand, double* Lc) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= kPcBlock * j) return;
+  const int c = q % kPcBlock, col = q / kPcBlock;
+  Lc[(size_t)col * kPcBlock + c] = cand[c] >= 0 ? L[(size_t)col * ldl + cand[c]] : 0.0;
+}
+
+// Pivoted Cholesky of the residual block S = C[cand, :] (kPcBlock x kPcBlock) in
+// one workgroup: repeatedly the largest remaining diagonal entry, while it
+// exceeds tol (a share of the largest initial diagonal entry, d_max[0]).
+// Outputs order[0..kPcBlock) (taken candidates in pivot order first, then the
+// rest), *taken, and R (kPcBlock x kPcBlock, lower, in pivot order; identity on
+// the untaken part).
+__global__ __launch_bounds__(256) void block_pivot_kernel(const double* __restrict__ C, int npix, const int* cand,
+                                                          const double* dmax, double rel_tol, int* order,
+                                                          int* taken, double* R) {
+  // S[a][b] = C[cand[a], b] is read from global memory where needed; only the
+  // block's factor lives in LDS
+  __shared__ double Lb[kPcBlock][kPcBlock + 1];
+  __shared__ double rd[kPcBlock];  // residual diagonal of S
+  __shared__ int s_perm[kPcBlock];
+  __shared__ int s_used[kPcBlock];
+  __shared__ int s_piv, s_stop, s_count;
+  const int t = threadIdx.x;
+  for (int e = t; e < kPcBlock * kPcBlock; e += blockDim.x) Lb[e % kPcBlock][e / kPcBlock] = 0.0;
+  for (int a = t; a < kPcBlock; a += blockDim.x) {
+    s_used[a] = cand[a] < 0;
+    rd[a] = cand[a] < 0 ? 0.0 : C[(size_t)a * npix + cand[a]];
+  }
+  if (t == 0) {
+    s_stop = 0;
+    s_count = 0;
+  }
+  __syncthreads();
+  const double tol = rel_tol * dmax[0];
+  for (int step = 0; step < kPcBlock; ++step) {
+    if (t == 0) {  // the largest remaining diagonal entry (lowest index on ties)
+      int best = -1;
+      double bv = 0.0;
+      for (int a = 0; a < kPcBlock; ++a)
+        if (!s_used[a] && rd[a] > bv) {
+          bv = rd[a];
+          best = a;
+        }
+      if (best < 0 || !(bv > tol)) {
+        s_stop = 1;
+      } else {
+        s_piv = best;
+        s_used[best] = 1;
+        s_perm[step] = best;
+        Lb[best][step] = sqrt(bv);
+        s_count = step + 1;
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int p = s_piv;
+    const double lpp = Lb[p][step];
+    for (int a = t; a < kPcBlock; a += blockDim.x) {
+      if (s_used[a]) continue;
+      double v = C[(size_t)p * npix + cand[a]];
+      for (int q = 0; q < step; ++q) v -= Lb[a][q] * Lb[p][q];
+      const double l = v / lpp;
+      Lb[a][step] = l;
+      rd[a] -= l * l;
+    }
+    __syncthreads();
+  }
+  const int cnt = s_count;
+  // order: taken pivots first, then the rest in candidate order
+  if (t == 0) {
+    int q = cnt;
+    for (int a = 0; a < kPcBlock; ++a) {
+      bool in_perm = false;
+      for (int u = 0; u < cnt; ++u) in_perm |= s_perm[u] == a;
+      if (!in_perm) s_perm[q++] = a;
+    }
+    *taken = cnt;
+  }
+  __syncthreads();
+  for (int a = t; a < kPcBlock; a += blockDim.x) order[a] = s_perm[a];
+  // R[u][v] = Lb[perm[u]][v] for v <= u < cnt; identity beyond
+  for (int e = t; e < kPcBlock * kPcBlock; e += blockDim.x) {
+    const int u = e % kPcBlock, v = e / kPcBlock;
+    double val = 0.0;
+    if (u < cnt && v < cnt) val = v <= u ? Lb[s_perm[u]][v] : 0.0;
+    else if (u == v) val = 1.0;
+    R[(size_t)v * kPcBlock + u] = val;
+  }
+}
+
+// Lnew[:, u] = C[:, order[u]] for u < taken, 0 beyond (before the solve with R).
+__global__ void gather_cols_kernel(int npix, const double* __restrict__ C, const int* order, const int* taken,
+                                   double* Lnew, int ldl) {
+  const int u = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  Lnew[(size_t)u * ldl + i] = u < *taken ? C[(size_t)order[u] * npix + i] : 0.0;
+}
+
+// Rows of the new columns that a pivoted Cholesky fixes exactly: zero at the
+// pivots of earlier blocks (their residual is zero; the computed one is
+// rounding noise that the triangular solve would amplify), and R's row u at the
+// block's u-th pivot (the computed columns of M are not exactly symmetric, so
+// the solve alone would not return it). Then d -= sum_u Lnew[i, u]^2 (in u
+// order), clamped at 0, exactly 0 at the new pivots, which are marked in
+// is_piv; pivots[j0 + u] = the pixel of pivot u (-1 where none was taken).
+__global__ void diag_update_kernel(int npix, double* d, double* __restrict__ Lnew, int ldl, const int* cand,
+                                   const int* order, const int* taken, const double* __restrict__ R, int* is_piv,
+                                   int* pivots, int j0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cnt = *taken;
+  if (i < kPcBlock && pivots) pivots[j0 + i] = i < cnt ? cand[order[i]] : -1;
+  if (i >= npix) return;
+  int pu = -1;
+  for (int u = 0; u < cnt; ++u)
+    if (cand[order[u]] == i) pu = u;
+  if (is_piv[i]) {
+    for (int u = 0; u < kPcBlock; ++u) Lnew[(size_t)u * ldl + i] = 0.0;
+  } else if (pu >= 0) {
+    for (int u = 0; u < kPcBlock; ++u) Lnew[(size_t)u * ldl + i] = u < cnt ? R[(size_t)u * kPcBlock + pu] : 0.0;
+  }
+  double v = d[i];
+  for (int u = 0; u < cnt; ++u) {
+    const double l = Lnew[(size_t)u * ldl + i];
+    v -= l * l;
+  }
+  if (pu >= 0) {
+    v = 0.0;
+    is_piv[i] = 1;
+  }
+  d[i] = v > 0.0 ? v : 0.0;
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// dmax[0] = max d (one workgroup).
+__global__ __launch_bounds__(1024) void dmax_kernel(int n, const double* d, double* dmax) {
+  __shared__ double red[16];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, d[i]);
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    *dmax = r;
+  }
+}
+
+__global__ void add_diag_kernel(int k, double* G, int ldg, double s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) G[(size_t)i * ldg + i] += s;
+}
+
+// ln|P| = (n - k) ln s + ln|G|.
+__global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, double* out) {
+  if (threadIdx.x == 0) *out = (double)(n - k) * log(s) + *logdet_g;
+}
+
+// ---------------------------------------------------------------- build workspace
+
+struct PcBuf {
+  float *E, *T1, *T2, *Mc;
+  double *C, *Lc, *R, *d, *dmax, *logd, *logdet_g;
+  int *cand, *order, *taken, *info, *is_piv;
+  void* mvm_ws;
+  size_t mvm_bytes;
+  void* blas;
+};
+
+template <class Cv>
+static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
+  const int ldf = round_up(N, 64);
+  b.E = c.template take<float>((size_t)npix * kPcBlock);
+  b.T1 = c.template take<float>((size_t)ldf * kPcBlock);
+  b.T2 = c.template take<float>((size_t)ldf * kPcBlock);
+  b.Mc = c.template take<float>((size_t)npix * kPcBlock);
+  b.C = c.template take<double>((size_t)npix * kPcBlock);
+  b.Lc = c.template take<double>((size_t)kPcBlock * std::max(k, 1));
+  b.R = c.template take<double>((size_t)kPcBlock * kPcBlock);
+  b.d = c.template take<double>(npix);
+  b.dmax = c.template take<double>(1);
+  b.logd = c.template take<double>(std::max(k, 1));
+  b.logdet_g = c.template take<double>(1);
+  b.cand = c.template take<int>(kPcBlock);
+  b.order = c.template take<int>(kPcBlock);
+  b.taken = c.template take<int>(1);
+  b.info = c.template take<int>(1);
+  b.is_piv = c.template take<int>(npix);
+  b.mvm_bytes = mvm_workspace(N, kPcBlock, prec);
+  b.mvm_ws = c.template take<char>(b.mvm_bytes);
+  b.blas = c.template take<char>(kBlasScratch);
+}
+
+static int check_pc_problem(const gpl_problem* prob, Taps& taps) {
+  GPL_REQUIRE(prob != nullptr, "problem is NULL");
+  const gpl_grid* g = &prob->grid;
+  GPL_REQUIRE(g->n >= 1 && g->ss >= 1 && g->pix_scale > 0, "bad grid");
+  GPL_REQUIRE(prob->px && prob->py, "problem points are NULL");
+  GPL_REQUIRE(prob->noise_sigma > 0 && std::isfinite(prob->noise_sigma), "noise_sigma must be > 0");
+  GPL_TRY(check_kernel(&prob->kernel));
+  GPL_TRY(make_taps(g, &prob->psf, taps));
+  GPL_REQUIRE((2 * taps.r + g->ss) * (2 * taps.r + g->ss) <= kMaxFoot, "PSF footprint too large");
+  return GPL_OK;
+}
+
+// ---------------------------------------------------------------- preconditioned CG
+
+struct PcgState {
+  double rz;     // r . P^{-1} r of the current residual
+  double rr;     // r . r of the current residual
+  double alpha;  // alpha of the step that produced this state
+  int active, iters, status, bad;
+};
+
+struct PcgBuf {
+  float *R, *P, *AP, *T2, *Z;
+  double *R64, *Z64, *W;
+  int ldv, ldf;
+  void* mvm_ws;
+  size_t mvm_bytes;
+  double *pap_part, *rr_part, *rz_part;
+  int ntiles, nb;
+  PcgState* st[2];
+  double* bb;
+  int* n_active;
+  unsigned* pmax;
+  void* blas;
+};
+
+template <class Cv>
+static void carve_pcg(Cv& c, int npix, int N, int n, int ss, int k, int nrhs, int prec, PcgBuf& b) {
+  b.ldv = round_up(npix, 64);
+  b.ldf = round_up(N, 64);
+  b.ntiles = psf_forward_tiles(n, ss);
+  b.nb = cdiv(npix, 256);
+  b.R = c.template take<float>((size_t)b.ldv * nrhs);
+  b.P = c.template take<float>((size_t)b.ldv * nrhs);
+  b.AP = c.template take<float>((size_t)b.ldv * nrhs);
+  b.Z = c.template take<float>((size_t)b.ldv * nrhs);
+  b.T2 = c.template take<float>((size_t)b.ldf * nrhs);
+  b.R64 = c.template take<double>((size_t)b.ldv * nrhs);
+  b.Z64 = c.template take<double>((size_t)b.ldv * nrhs);
+  b.W = c.template take<double>((size_t)std::max(k, 1) * nrhs);
+  b.mvm_bytes = mvm_workspace(N, nrhs, prec);
+  b.mvm_ws = c.template take<char>(b.mvm_bytes);
+  b.pap_part = c.template take<double>((size_t)b.ntiles * nrhs);
+  b.rr_part = c.template take<double>((size_t)b.nb * nrhs);
+  b.rz_part = c.template take<double>((size_t)b.nb * nrhs);
+  b.st[0] = c.template take<PcgState>(nrhs);
+  b.st[1] = c.template take<PcgState>(nrhs);
+  b.bb = c.template take<double>(nrhs);
+  b.n_active = c.template take<int>(2);
+  b.pmax = c.template take<unsigned>((size_t)b.nb * nrhs);
+  b.blas = c.template take<char>(kBlasScratch);
+}
+
+// Z64 = R64 = R (FP64 copies for the Woodbury products).
+__global__ __launch_bounds__(256) void pcg_widen_kernel(int npix, const float* __restrict__ R, int ldv, double* R64,
+                                                        double* Z64) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  const double v = R[(size_t)c * ldv + i];
+  R64[(size_t)c * ldv + i] = v;
+  Z64[(size_t)c * ldv + i] = v;
+}
+
+// P^{-1} R for every column: W = L^T R64; W = G^{-1} W (two triangular solves
+// with the factor of G); Z64 = R64 - L W. The caller finishes Z = Z64 / s.
+static int woodbury(rocblas_handle h, int npix, int k, const double* L, int ldl, const double* G, int ldg, int nrhs,
+                    const double* R64, double* Z64, int ldv, double* W) {
+  const double one = 1.0, zero = 0.0, minus_one = -1.0;
+  if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, nrhs, npix, &one, L, ldl, R64, ldv,
+                    &zero, W, k) != rocblas_status_success ||
+      rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, k,
+                    nrhs, &one, G, ldg, W, k) != rocblas_status_success ||
+      rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
+                    rocblas_diagonal_non_unit, k, nrhs, &one, G, ldg, W, k) != rocblas_status_success ||
+      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, npix, nrhs, k, &minus_one, L, ldl, W, k, &one,
+                    Z64, ldv) != rocblas_status_success) {
+    set_error("rocBLAS call of the preconditioner failed");
+    return GPL_EHIP;
+  }
+  return GPL_OK;
+}
+
+// Z = Z64 / s (FP32), partial r.z and (at init) partial |b|^2 and max |Z| per block.
+__global__ __launch_bounds__(256) void pcg_zfinish_kernel(int npix, const double* __restrict__ Z64, int ldv,
+                                                          double inv_s, const float* __restrict__ R, float* Z,
+                                                          double* rz_part, int nb, const PcgState* st,
+                                                          const int* n_active) {
+  __shared__ double red[4];
+  const int c = blockIdx.y;
+  if (n_active && (*n_active == 0 || !st[c].active)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < npix) {
+    const float z = (float)(Z64[(size_t)c * ldv + i] * inv_s);
+    Z[(size_t)c * ldv + i] = z;
+    s = (double)R[(size_t)c * ldv + i] * (double)z;
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) rz_part[(size_t)c * nb + blockIdx.x] = s;
+}
+
+// R = B, X = 0, partial |b|^2.
+__global__ __launch_bounds__(256) void pcg_init_kernel(int npix, const float* __restrict__ Bm, int ldb, float* X,
+                                                       int ldx, float* R, int ldv, double* part, int nb) {
+  __shared__ double red[4];
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < npix) {
+    const float b = Bm[(size_t)c * ldb + i];
+    R[(size_t)c * ldv + i] = b;
+    X[(size_t)c * ldx + i] = 0.f;
+    s = (double)b * b;
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) part[(size_t)c * nb + blockIdx.x] = s;
+}
+
+// P = Z and partial max |P|, after the initial preconditioner application.
+__global__ __launch_bounds__(256) void pcg_init_p_kernel(int npix, const float* __restrict__ Z, float* P, int ldv,
+                                                         unsigned* pmax, int nb) {
+  __shared__ float redm[4];
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float m = 0.f;
+  if (i < npix) {
+    const float z = Z[(size_t)c * ldv + i];
+    P[(size_t)c * ldv + i] = z;
+    m = fabsf(z);
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) pmax[(size_t)c * nb + blockIdx.x] =
+      __float_as_uint(fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3])));
+}
+
+// Initial state per column from the partials: rr = |b|^2, rz = b.P^{-1}b.
+__global__ void pcg_init_state_kernel(int nrhs, const double* rr_part, const double* rz_part, int nb, PcgState* s0,
+                                      PcgState* s1, double* bb, double* rz0, int* n_active, int limit) {
+  __shared__ int count;
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < nrhs; c += blockDim.x) {
+    double rr = 0.0, rz = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      rr += rr_part[(size_t)c * nb + b];
+      rz += rz_part[(size_t)c * nb + b];
+    }
+    PcgState z;
+    z.rr = rr;
+    z.rz = rz;
+    z.alpha = 0.0;
+    z.iters = 0;
+    z.bad = 0;
+    if (!isfinite(rr) || !isfinite(rz)) {
+      z.status = GPL_CG_NONFINITE;
+      z.active = 0;
+    } else if (rr == 0.0 || limit == 0) {
+      z.status = rr == 0.0 ? GPL_CG_CONVERGED : GPL_CG_MAXITER;
+      z.active = 0;
+    } else {
+      z.status = GPL_CG_CONVERGED;
+      z.active = 1;
+    }
+    s0[c] = z;
+    s1[c] = z;
+    bb[c] = rr;
+    if (rz0) rz0[c] = rz;
+    if (z.active) atomicAdd(&count, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    n_active[0] = count;
+    n_active[1] = count;
+  }
+}
+
+// alpha = rz / pAp; X += alpha P; R -= alpha AP; R64 = Z64 = R; partial r.r.
+__global__ __launch_bounds__(256) void pcg_update1_kernel(int npix, float* X, int ldx, float* R, const float* P,
+                                                          const float* AP, int ldv, double* R64, double* Z64,
+                                                          const double* pap_part, int ntiles, double* rr_part, int nb,
+                                                          const PcgState* sin, PcgState* sout,
+                                                          const int* n_active_in, int* n_active_out) {
+  __shared__ double red[4];
+  __shared__ double s_alpha;
+  __shared__ int s_ok;
+  const int c = blockIdx.y, bx = blockIdx.x;
+  if (bx == 0 && c == 0 && threadIdx.x == 0) *n_active_out = 0;
+  if (*n_active_in == 0) return;
+  const PcgState st = sin[c];
+  if (!st.active) return;
+  const int i = bx * blockDim.x + threadIdx.x;
+  const size_t iv = (size_t)c * ldv + i;
+  float xv = 0.f, pv = 0.f, apv = 0.f, rv = 0.f;
+  if (i < npix) {
+    xv = X[(size_t)c * ldx + i];
+    pv = P[iv];
+    apv = AP[iv];
+    rv = R[iv];
+  }
+  const double pap = threadIdx.x < 64 ? wave_fold_sum(pap_part + (size_t)c * ntiles, ntiles) : 0.0;
+  if (threadIdx.x == 0) {
+    const double a = st.rz / pap;
+    const int ok = (pap > 0.0) && isfinite(a);
+    s_alpha = ok ? a : 0.0;
+    s_ok = ok;
+    if (bx == 0) {
+      sout[c].alpha = s_alpha;
+      sout[c].bad = ok ? 0 : (isfinite(pap) ? 1 : 2);
+    }
+  }
+  __syncthreads();
+  double s = 0.0;
+  if (s_ok && i < npix) {
+    const float af = (float)s_alpha;
+    X[(size_t)c * ldx + i] = fmaf(af, pv, xv);
+    const float r = fmaf(-af, apv, rv);
+    R[iv] = r;
+    R64[iv] = r;
+    Z64[iv] = r;
+    s = (double)r * r;
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) rr_part[(size_t)c * nb + bx] = s;
+}
+
+// beta = rz_new / rz; P = Z + beta P; block 0 records the Lanczos coefficients
+// and decides the column's status (stop on the recursive residual |r|/|b|).
+__global__ __launch_bounds__(256) void pcg_update2_kernel(int npix, const float* Z, float* P, int ldv,
+                                                          const double* rr_part, const double* rz_part, int nb,
+                                                          const PcgState* sin, PcgState* sout, const double* bb,
+                                                          const int* n_active_in, int* n_active_out, double tol,
+                                                          int max_iter, int fixed_iters, int n_lanczos, double* ab,
+                                                          unsigned* pmax) {
+  __shared__ double s_beta;
+  __shared__ int s_go;
+  __shared__ float redm[4];
+  const int c = blockIdx.y, bx = blockIdx.x;
+  const PcgState st = sin[c];
+  if (*n_active_in == 0 || !st.active) {
+    if (bx == 0 && threadIdx.x == 0) sout[c] = st;
+    return;
+  }
+  const int i = bx * blockDim.x + threadIdx.x;
+  const size_t iv = (size_t)c * ldv + i;
+  float zv = 0.f, pv = 0.f;
+  if (i < npix) {
+    zv = Z[iv];
+    pv = P[iv];
+  }
+  double rr_new = 0.0, rz_new = 0.0;
+  if (threadIdx.x < 64) {
+    rr_new = wave_fold_sum(rr_part + (size_t)c * nb, nb);
+    rz_new = wave_fold_sum(rz_part + (size_t)c * nb, nb);
+  }
+  if (threadIdx.x == 0) {
+    const PcgState half = sout[c];
+    const double beta = rz_new / st.rz;
+    PcgState nx;
+    nx.alpha = half.alpha;
+    nx.bad = 0;
+    nx.iters = st.iters;
+    nx.rr = st.rr;
+    nx.rz = st.rz;
+    nx.status = GPL_CG_CONVERGED;
+    nx.active = 0;
+    int go = 0;
+    if (half.bad) {
+      nx.status = half.bad == 1 ? GPL_CG_BREAKDOWN : GPL_CG_NONFINITE;
+    } else if (!isfinite(rr_new) || !isfinite(rz_new) || !isfinite(beta)) {
+      nx.status = GPL_CG_NONFINITE;
+      nx.iters = st.iters + 1;
+    } else {
+      go = 1;
+      nx.rr = rr_new;
+      nx.rz = rz_new;
+      nx.iters = st.iters + 1;
+      if (bx == 0 && st.iters < n_lanczos) {
+        double* e = ab + ((size_t)c * n_lanczos + st.iters) * 2;
+        e[0] = half.alpha;
+        e[1] = beta;
+      }
+      if (fixed_iters > 0) {
+        nx.active = nx.iters < fixed_iters;
+      } else if (sqrt(rr_new) <= tol * sqrt(bb[c])) {
+        nx.active = 0;
+      } else if (nx.iters >= max_iter) {
+        nx.status = GPL_CG_MAXITER;
+      } else {
+        nx.active = 1;
+      }
+    }
+    s_beta = beta;
+    s_go = go;
+    if (bx == 0) {
+      sout[c] = nx;
+      if (nx.active) atomicAdd(n_active_out, 1);
+    }
+  }
+  __syncthreads();
+  if (!s_go) return;
+  float m = 0.f;
+  if (i < npix) {
+    const float pn = fmaf((float)s_beta, pv, zv);
+    P[iv] = pn;
+    m = fabsf(pn);
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    pmax[(size_t)c * nb + bx] = __float_as_uint(fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3])));
+}
+
+__global__ void pcg_finalize_kernel(int nrhs, const PcgState* st, const double* bb, int* iters, double* relres,
+                                    int* status, int n_lanczos, double* ab) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  const PcgState s = st[c];
+  if (iters) iters[c] = s.iters;
+  if (relres) relres[c] = bb[c] > 0.0 ? sqrt(s.rr / bb[c]) : 0.0;
+  if (status) status[c] = s.active ? GPL_CG_MAXITER : s.status;
+  if (ab)
+    for (int k = s.iters; k < n_lanczos; ++k) {
+      ab[((size_t)c * n_lanczos + k) * 2 + 0] = 0.0;
+      ab[((size_t)c * n_lanczos + k) * 2 + 1] = 0.0;
+    }
+}
+
+__global__ void pcg_snapshot_kernel(const int* n_active, volatile int* host_flag) {
+  if (threadIdx.x == 0) {
+    *host_flag = *n_active;
+    __threadfence_system();
+  }
+}
+
+// Partial |b - A x|^2 per block and its fold (the true residual at exit).
+__global__ __launch_bounds__(256) void pcg_true_residual_kernel(int npix, const float* __restrict__ Bm, int ldb,
+                                                                const float* __restrict__ AX, int ldv, double* part,
+                                                                int nb) {
+  __shared__ double red[4];
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < npix) {
+    const double d = (double)Bm[(size_t)c * ldb + i] - (double)AX[(size_t)c * ldv + i];
+    s = d * d;
+  }
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) part[(size_t)c * nb + blockIdx.x] = s;
+}
+
+__global__ void pcg_true_residual_fold_kernel(int nrhs, const double* part, int nb, const double* bb, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)c * nb + b];
+  out[c] = bb[c] > 0.0 ? sqrt(s / bb[c]) : sqrt(s);
+}
+
+__global__ __launch_bounds__(256) void pcg_absmax_kernel(int npix, const float* __restrict__ X, int ldx,
+                                                         unsigned* pmax, int nb) {
+  __shared__ float redm[4];
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float m = i < npix ? fabsf(X[(size_t)c * ldx + i]) : 0.f;
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    pmax[(size_t)c * nb + blockIdx.x] = __float_as_uint(fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3])));
+}
+
+// Probe block Z = L g + sqrt(s) h (FP32 output), FP64 accumulation.
+__global__ void probe_finish_kernel(int npix, const double* __restrict__ Lg, double sq, const float* __restrict__ h,
+                                    int ldh, float* Z, int ldz) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npix) Z[(size_t)c * ldz + i] = (float)(Lg[(size_t)c * npix + i] + sq * (double)h[(size_t)c * ldh + i]);
+}
+
+struct PollFlags {
+  int* flags = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int device = -1;
+};
+
+static int pcg_poll(PollFlags*& out) {
+  thread_local PollFlags f;
+  int dev = 0;
+  GPL_HIP(hipGetDevice(&dev));
+  if (f.flags == nullptr || f.device != dev) {
+    GPL_HIP(hipHostMalloc(reinterpret_cast<void**>(&f.flags), 2 * sizeof(int), hipHostMallocCoherent));
+    GPL_HIP(hipEventCreateWithFlags(&f.ev[0], hipEventDisableTiming));
+    GPL_HIP(hipEventCreateWithFlags(&f.ev[1], hipEventDisableTiming));
+    f.device = dev;
+  }
+  out = &f;
+  return GPL_OK;
+}
+
+}  // namespace gpl
+
+using namespace gpl;
+
+// ---------------------------------------------------------------- entry points
+
+extern "C" size_t gpl_pchol_workspace(const gpl_problem* prob, int k, int prec) {
+  if (prob == nullptr || k <= 0 || prob->grid.n <= 0 || prob->grid.ss <= 0) return 0;
+  const int npix = prob->grid.n * prob->grid.n, N = npix * prob->grid.ss * prob->grid.ss;
+  Sizer s;
+  PcBuf b;
+  carve_pc(s, npix, N, k, prec, b);
+  return s.used;
+}
+
+extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, int ldl, double* G, int ldg,
+                         int* pivots, double* logdet_P, int* info, void* ws, size_t ws_bytes, hipStream_t stream) {
+  Taps taps;
+  GPL_TRY(check_pc_problem(prob, taps));
+  GPL_REQUIRE(prec == GPL_PREC_FP32 || prec == GPL_PREC_F16X3, "unknown precision %d", prec);
+  const int n = prob->grid.n, ss = prob->grid.ss, npix = n * n, N = npix * ss * ss;
+  GPL_REQUIRE(k >= kPcBlock && k % kPcBlock == 0, "k=%d must be a positive multiple of %d", k, kPcBlock);
+  GPL_REQUIRE(L && G && logdet_P && info, "NULL argument");
+  GPL_REQUIRE(ldl >= npix && ldg >= k, "ldl=%d (>= %d) / ldg=%d (>= %d)", ldl, npix, ldg, k);
+  GPL_TRY(check_ws(ws, ws_bytes, gpl_pchol_workspace(prob, k, prec)));
+  Carver cv(ws, ws_bytes);
+  PcBuf b;
+  carve_pc(cv, npix, N, k, prec, b);
+  if (!cv.ok()) return check_ws(nullptr, 0, 1);
+  rocblas_handle h;
+  GPL_TRY(blas_handle(&h, stream, b.blas, kBlasScratch));
+  MvmCtx mv;
+  GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid,
+                      kPcBlock, prec, b.mvm_ws, b.mvm_bytes, stream));
+  const float s2 = (float)kernel_scale2(prob->kernel.lengthscale);
+  const double amp2 = prob->kernel.amplitude * prob->kernel.amplitude;
+  hipLaunchKernelGGL(bkb_diag_kernel, dim3(npix), dim3(256), 0, stream, n, ss, taps, s2, amp2, prob->px, prob->py,
+                     b.d);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(dmax_kernel, dim3(1), dim3(1024), 0, stream, npix, b.d, b.dmax);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, b.is_piv, npix);
+  GPL_LAUNCH_CHECK();
+  const int ldf = round_up(N, 64);
+  const dim3 gcol(cdiv(npix, 256), kPcBlock);
+  const double one = 1.0, minus_one = -1.0, zero = 0.0;
+  for (int j0 = 0; j0 < k; j0 += kPcBlock) {
+    hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
+    GPL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(unit_cols_kernel, gcol, dim3(256), 0, stream, npix, b.cand, b.E);
+    GPL_LAUNCH_CHECK();
+    // columns of B K B^T at the candidates (the matrix-free product)
+    GPL_TRY(psf_adjoint_launch(n, ss, taps, kPcBlock, b.E, npix, b.T1, ldf, 1.f, 0.f, CgGate{}, stream));
+    GPL_TRY(mvm_run(mv, kPcBlock, b.T1, ldf, b.T2, ldf, 0.f, CgGate{}, stream));
+    GPL_TRY(psf_forward_launch(n, ss, taps, kPcBlock, b.T2, ldf, b.Mc, npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr, 0,
+                               nullptr, CgGate{}, stream));
+    hipLaunchKernelGGL(widen_kernel, gcol, dim3(256), 0, stream, npix, b.Mc, b.C);
+    GPL_LAUNCH_CHECK();
+    if (j0 > 0) {  // residual columns: C -= L[:, :j0] L[cand, :j0]^T
+      hipLaunchKernelGGL(gather_rows_kernel, dim3(cdiv(kPcBlock * j0, 256)), dim3(256), 0, stream, j0, L, ldl, b.cand,
+                         b.Lc);
+      GPL_LAUNCH_CHECK();
+      if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, kPcBlock, j0, &minus_one, L,
+                        ldl, b.Lc, kPcBlock, &one, b.C, npix) != rocblas_status_success) {
+        set_error("rocblas_dgemm (residual columns) failed");
+        return GPL_EHIP;
+      }
+    }
+    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(256), 0, stream, b.C, npix, b.cand, b.dmax, kPcRelTol,
+                       b.order, b.taken, b.R);
+    GPL_LAUNCH_CHECK();
+    double* Lnew = L + (size_t)j0 * ldl;
+    hipLaunchKernelGGL(gather_cols_kernel, gcol, dim3(256), 0, stream, npix, b.C, b.order, b.taken, Lnew, ldl);
+    GPL_LAUNCH_CHECK();
+    if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                      rocblas_diagonal_non_unit, npix, kPcBlock, &one, b.R, kPcBlock, Lnew, ldl) !=
+        rocblas_status_success) {
+      set_error("rocblas_dtrsm (new columns) failed");
+      return GPL_EHIP;
+    }
+    hipLaunchKernelGGL(diag_update_kernel, dim3(cdiv(std::max(npix, kPcBlock), 256)), dim3(256), 0, stream, npix,
+                       b.d, Lnew, ldl, b.cand, b.order, b.taken, b.R, b.is_piv, pivots, j0);
+    GPL_LAUNCH_CHECK();
+  }
+  // G = s I + L^T L and its Cholesky factor; ln|P|
+  const double s = prob->noise_sigma * prob->noise_sigma;
+  if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, k, npix, &one, L, ldl, &zero, G, ldg) !=
+      rocblas_status_success) {
+    set_error("rocblas_dsyrk (L^T L) failed");
+    return GPL_EHIP;
+  }
+  hipLaunchKernelGGL(add_diag_kernel, dim3(cdiv(k, 256)), dim3(256), 0, stream, k, G, ldg, s);
+  GPL_LAUNCH_CHECK();
+  GPL_TRY(dense_cholesky(h, G, k, ldg, b.logd, b.logdet_g, info, stream));
+  hipLaunchKernelGGL(logdet_p_kernel, dim3(1), dim3(64), 0, stream, npix, k, s, b.logdet_g, logdet_P);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+extern "C" size_t gpl_pchol_probes_workspace(int npix, int m) {
+  if (npix <= 0 || m <= 0) return 0;
+  Sizer s;
+  s.take<double>((size_t)npix * m);
+  s.take<char>(kBlasScratch);
+  return s.used;
+}
+
+extern "C" int gpl_pchol_probes(int npix, int k, const double* L, int ldl, double noise_sigma, int m, const double* g,
+                                int ldg, const float* hn, int ldh, float* Z, int ldz, void* ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  GPL_REQUIRE(npix >= 1 && k >= 1 && m >= 0, "bad sizes");
+  if (m == 0) return GPL_OK;
+  GPL_REQUIRE(L && g && hn && Z, "NULL argument");
+  GPL_REQUIRE(ldl >= npix && ldg >= k && ldh >= npix && ldz >= npix, "leading dimension too small");
+  GPL_REQUIRE(noise_sigma > 0 && std::isfinite(noise_sigma), "noise_sigma must be > 0");
+  GPL_TRY(check_ws(ws, ws_bytes, gpl_pchol_probes_workspace(npix, m)));
+  Carver cv(ws, ws_bytes);
+  double* Lg = cv.take<double>((size_t)npix * m);
+  void* scratch = cv.take<char>(kBlasScratch);
+  if (!cv.ok()) return check_ws(nullptr, 0, 1);
+  rocblas_handle h;
+  GPL_TRY(blas_handle(&h, stream, scratch, kBlasScratch));
+  const double one = 1.0, zero = 0.0;
+  if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, npix, m, k, &one, L, ldl, g, ldg, &zero, Lg,
+                    npix) != rocblas_status_success) {
+    set_error("rocblas_dgemm (probes) failed");
+    return GPL_EHIP;
+  }
+  hipLaunchKernelGGL(probe_finish_kernel, dim3(cdiv(npix, 256), m), dim3(256), 0, stream, npix, Lg, noise_sigma, hn,
+                     ldh, Z, ldz);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+extern "C" size_t gpl_pcg_solve_workspace(const gpl_problem* prob, int k, int nrhs, int prec) {
+  if (prob == nullptr || nrhs <= 0 || prob->grid.n <= 0 || prob->grid.ss <= 0) return 0;
+  const int n = prob->grid.n, ss = prob->grid.ss, npix = n * n, N = npix * ss * ss;
+  Sizer s;
+  PcgBuf b;
+  carve_pcg(s, npix, N, n, ss, k, nrhs, prec, b);
+  return s.used;
+}
+
+extern "C" int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, int ldl, const double* G, int ldg,
+                             int nrhs, const float* Bm, int ldb, float* X, int ldx, double tol, int max_iter,
+                             int fixed_iters, int n_lanczos, double* lanczos_ab, double* rz0, int* iters,
+                             double* relres, double* true_relres, int* status, int prec, int check_every, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  Taps taps;
+  GPL_TRY(check_pc_problem(prob, taps));
+  GPL_REQUIRE(prec == GPL_PREC_FP32 || prec == GPL_PREC_F16X3, "unknown precision %d", prec);
+  GPL_REQUIRE(nrhs >= 1 && nrhs <= 65535, "nrhs=%d out of range", nrhs);
+  const int n = prob->grid.n, ss = prob->grid.ss, npix = n * n, N = npix * ss * ss;
+  GPL_REQUIRE(k >= 1 && L && G && ldl >= npix && ldg >= k, "bad preconditioner arguments");
+  GPL_REQUIRE(Bm && X && ldb >= npix && ldx >= npix, "bad right-hand side or solution arguments");
+  GPL_REQUIRE(tol >= 0 && max_iter >= 0 && fixed_iters >= 0 && n_lanczos >= 0 && check_every >= 0,
+              "negative tol/iteration counts");
+  GPL_REQUIRE(n_lanczos == 0 || lanczos_ab != nullptr, "lanczos_ab is NULL");
+  GPL_TRY(check_ws(ws, ws_bytes, gpl_pcg_solve_workspace(prob, k, nrhs, prec)));
+  Carver cv(ws, ws_bytes);
+  PcgBuf b;
+  carve_pcg(cv, npix, N, n, ss, k, nrhs, prec, b);
+  if (!cv.ok()) return check_ws(nullptr, 0, 1);
+  rocblas_handle h;
+  GPL_TRY(blas_handle(&h, stream, b.blas, kBlasScratch));
+  PollFlags* poll = nullptr;
+  if (check_every > 0) GPL_TRY(pcg_poll(poll));
+  MvmCtx mv;
+  GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid, nrhs,
+                      prec, b.mvm_ws, b.mvm_bytes, stream));
+  const RhsOut rhs_out{prec, nrhs, mv.bufs.ncp, mv.bufs.Vh, mv.bufs.Vl, mv.bufs.Vp, mv.bufs.inv_scale, b.pmax, b.nb,
+                       mv.plan.irank};
+  const float sigma2 = (float)(prob->noise_sigma * prob->noise_sigma);
+  const double inv_s = 1.0 / (prob->noise_sigma * prob->noise_sigma);
+  const int nb = b.nb;
+  const dim3 gv(nb, nrhs);
+  const int limit = fixed_iters > 0 ? fixed_iters : max_iter;
+
+  // R = b, Z = P^{-1} b, P = Z, states
+  hipLaunchKernelGGL(pcg_init_kernel, gv, dim3(256), 0, stream, npix, Bm, ldb, X, ldx, b.R, b.ldv, b.rr_part, nb);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(pcg_widen_kernel, gv, dim3(256), 0, stream, npix, b.R, b.ldv, b.R64, b.Z64);
+  GPL_LAUNCH_CHECK();
+  GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W));
+  hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z, b.rz_part,
+                     nb, (const PcgState*)nullptr, (const int*)nullptr);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(pcg_init_p_kernel, gv, dim3(256), 0, stream, npix, b.Z, b.P, b.ldv, b.pmax, nb);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(pcg_init_state_kernel, dim3(1), dim3(256), 0, stream, nrhs, b.rr_part, b.rz_part, nb, b.st[0],
+                     b.st[1], b.bb, rz0, b.n_active, limit);
+  GPL_LAUNCH_CHECK();
+
+  const int chunk = check_every > 0 ? check_every : std::max(limit, 1);
+  const int nchunks = cdiv(limit, chunk);
+  int last_end = 0;
+  auto enqueue_chunk = [&](int kc) -> int {
+    const int end = std::min(limit, (kc + 1) * chunk);
+    for (int it = kc * chunk; it < end; ++it) {
+      const int p = it & 1;
+      CgGate gate;
+      gate.n_active = b.n_active + p;
+      GPL_TRY(psf_adjoint_rhs_launch(n, ss, taps, nrhs, b.P, b.ldv, rhs_out, gate, stream));
+      GPL_TRY(mvm_run_prepared(mv, nrhs, b.T2, b.ldf, 0.f, gate, stream));
+      GPL_TRY(psf_forward_launch(n, ss, taps, nrhs, b.T2, b.ldf, b.AP, b.ldv, 1.f, 0.f, b.P, b.ldv, sigma2, b.P,
+                                 b.ldv, b.pap_part, gate, stream));
+      hipLaunchKernelGGL(pcg_update1_kernel, gv, dim3(256), 0, stream, npix, X, ldx, b.R, b.P, b.AP, b.ldv, b.R64,
+                         b.Z64, b.pap_part, b.ntiles, b.rr_part, nb, b.st[p], b.st[1 - p], b.n_active + p,
+                         b.n_active + (1 - p));
+      GPL_LAUNCH_CHECK();
+      GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W));
+      hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z,
+                         b.rz_part, nb, (const PcgState*)b.st[p], (const int*)(b.n_active + p));
+      GPL_LAUNCH_CHECK();
+      hipLaunchKernelGGL(pcg_update2_kernel, gv, dim3(256), 0, stream, npix, b.Z, b.P, b.ldv, b.rr_part, b.rz_part,
+                         nb, b.st[p], b.st[1 - p], b.bb, b.n_active + p, b.n_active + (1 - p), tol, max_iter,
+                         fixed_iters, n_lanczos, lanczos_ab, b.pmax);
+      GPL_LAUNCH_CHECK();
+    }
+    last_end = end;
+    if (!poll) return GPL_OK;
+    hipLaunchKernelGGL(pcg_snapshot_kernel, dim3(1), dim3(64), 0, stream, b.n_active + (end & 1),
+                       poll->flags + (kc & 1));
+    GPL_LAUNCH_CHECK();
+    GPL_HIP(hipEventRecord(poll->ev[kc & 1], stream));
+    return GPL_OK;
+  };
+  if (nchunks > 0 && !poll) {
+    GPL_TRY(enqueue_chunk(0));
+  } else if (nchunks > 0) {
+    GPL_TRY(enqueue_chunk(0));
+    for (int kc = 0; kc < nchunks; ++kc) {
+      if (kc + 1 < nchunks) GPL_TRY(enqueue_chunk(kc + 1));
+      GPL_HIP(hipEventSynchronize(poll->ev[kc & 1]));
+      if (poll->flags[kc & 1] == 0) break;
+    }
+  }
+  const int fp = last_end & 1;
+  hipLaunchKernelGGL(pcg_finalize_kernel, dim3(cdiv(nrhs, 256)), dim3(256), 0, stream, nrhs, b.st[fp], b.bb, iters,
+                     relres, status, n_lanczos, lanczos_ab);
+  GPL_LAUNCH_CHECK();
+  if (true_relres) {
+    hipLaunchKernelGGL(pcg_absmax_kernel, gv, dim3(256), 0, stream, npix, X, ldx, b.pmax, nb);
+    GPL_LAUNCH_CHECK();
+    GPL_TRY(psf_adjoint_rhs_launch(n, ss, taps, nrhs, X, ldx, rhs_out, CgGate{}, stream));
+    GPL_TRY(mvm_run_prepared(mv, nrhs, b.T2, b.ldf, 0.f, CgGate{}, stream));
+    GPL_TRY(psf_forward_launch(n, ss, taps, nrhs, b.T2, b.ldf, b.AP, b.ldv, 1.f, 0.f, X, ldx, sigma2, nullptr, 0,
+                               nullptr, CgGate{}, stream));
+    hipLaunchKernelGGL(pcg_true_residual_kernel, gv, dim3(256), 0, stream, npix, Bm, ldb, b.AP, b.ldv, b.rr_part, nb);
+    GPL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(pcg_true_residual_fold_kernel, dim3(cdiv(nrhs, 256)), dim3(256), 0, stream, nrhs, b.rr_part,
+                       nb, b.bb, true_relres);
+    GPL_LAUNCH_CHECK();
+  }
+  return GPL_OK;
+}

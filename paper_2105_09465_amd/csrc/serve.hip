@@ -259,7 +259,7 @@ extern "C" int gpl_serve_slot_finish(gpl_serve_slot* slot, long iter, double log
   const int m = D.nrhs - 1;
   if (m > 0 && D.n_lanczos > 0) {
     GPL_TRY(gpl_lanczos_logdet(m, D.n_lanczos, b.ab + (size_t)D.n_lanczos * 2, iters + 1, b.bnorm2 + 1, logdet_scale,
-                               b.contrib, logdet, stderr_, b.lz_ws, b.lz_bytes, stream));
+                               nullptr, b.contrib, logdet, stderr_, b.lz_ws, b.lz_bytes, stream));
   } else {
     hipLaunchKernelGGL(fill_nan_kernel, dim3(1), dim3(64), 0, stream, logdet, 2);  // no log-determinant requested
     GPL_LAUNCH_CHECK();

@@ -187,8 +187,9 @@ def cg_solve(problem: Problem, px, py, Bm, tol=1e-6, max_iter=1000, fixed_iters=
                 status=status, n_lanczos=nl)
 
 
-def lanczos_logdet(ab, iters, bnorm2, scale):
-    """SLQ log-determinant from CG coefficients of the probe columns."""
+def lanczos_logdet(ab, iters, bnorm2, scale, offset=None):
+    """SLQ log-determinant from CG coefficients of the probe columns (plus a
+    device scalar offset, e.g. ln|P| of a preconditioner)."""
     m, nl = ab.shape[0], ab.shape[1]
     ab = ab.contiguous()
     dev = ab.device
@@ -197,8 +198,71 @@ def lanczos_logdet(ab, iters, bnorm2, scale):
     stderr = torch.empty(1, dtype=torch.float64, device=dev)
     ws, wsb = workspace(_lib.lib.gpl_lanczos_logdet_workspace(m, nl), dev)
     _lib.call("gpl_lanczos_logdet", m, nl, _ptr(ab), _ptr(iters.contiguous()), _ptr(bnorm2.contiguous()),
-              float(scale), _ptr(contrib), _ptr(logdet), _ptr(stderr), _wsptr(ws), wsb, _stream())
+              float(scale), _ptr(offset, torch.float64) if offset is not None else None, _ptr(contrib),
+              _ptr(logdet), _ptr(stderr), _wsptr(ws), wsb, _stream())
     return logdet, stderr, contrib
+
+
+def pchol(problem: Problem, px, py, k, prec="f16x3"):
+    """Partial pivoted Cholesky preconditioner of A: dict with L (k, n_pix)
+    float64 (column j of L is row j), G (k, k) the factor of sigma^2 I + L^T L
+    (column-major: row j of the tensor is column j), pivots (k,), logdet_P and
+    info (device scalars)."""
+    npix = problem.grid.n_pix
+    dev = px.device
+    L = torch.empty(k, npix, dtype=torch.float64, device=dev)
+    Gm = torch.empty(k, k, dtype=torch.float64, device=dev)
+    piv = torch.empty(k, dtype=torch.int32, device=dev)
+    ldp = torch.empty(1, dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    pc = prec_code(prec)
+    pr = problem_c(problem, px, py)
+    ws, wsb = workspace(_lib.lib.gpl_pchol_workspace(C.byref(pr), k, pc), dev)
+    _lib.call("gpl_pchol", C.byref(pr), int(k), pc, _ptr(L), npix, _ptr(Gm), k, _ptr(piv), _ptr(ldp), _ptr(info),
+              _wsptr(ws), wsb, _stream())
+    return dict(L=L, G=Gm, pivots=piv, logdet_P=ldp, info=info, k=int(k))
+
+
+def pchol_probes(pc: dict, noise_sigma, g, h):
+    """Probes z = L g + sigma h for normals g (m, k) float64 and h (m, n_pix)
+    float32 on the device; returns (m, n_pix) float32."""
+    L = pc["L"]
+    k, npix = L.shape
+    m = g.shape[0]
+    Z = torch.empty(m, npix, dtype=torch.float32, device=L.device)
+    ws, wsb = workspace(_lib.lib.gpl_pchol_probes_workspace(npix, m), L.device)
+    _lib.call("gpl_pchol_probes", npix, k, _ptr(L), npix, float(noise_sigma), m, _ptr(g.contiguous(), torch.float64),
+              k, _ptr(h.contiguous(), torch.float32), npix, _ptr(Z), npix, _wsptr(ws), wsb, _stream())
+    return Z
+
+
+def pcg_solve(problem: Problem, px, py, pc: dict, Bm, tol=1e-6, max_iter=1000, fixed_iters=0, n_lanczos=30,
+              prec="f16x3", check_every=2, ws=None, true_residual=True):
+    """Preconditioned CG on A X = Bm (ncols, n_pix) with the factor from pchol().
+    Returns device tensors; rz0 = b^T P^{-1} b per column."""
+    npix = problem.grid.n_pix
+    ldb = _block(Bm, npix, "Bm")
+    m = Bm.shape[0]
+    dev = Bm.device
+    k = pc["k"]
+    X = torch.empty(m, npix, dtype=torch.float32, device=dev)
+    nl = max(int(n_lanczos), 0)
+    ab = torch.zeros(m, max(nl, 1), 2, dtype=torch.float64, device=dev)
+    rz0 = torch.empty(m, dtype=torch.float64, device=dev)
+    iters = torch.empty(m, dtype=torch.int32, device=dev)
+    relres = torch.empty(m, dtype=torch.float64, device=dev)
+    true_relres = torch.empty(m, dtype=torch.float64, device=dev) if true_residual else None
+    status = torch.empty(m, dtype=torch.int32, device=dev)
+    pcode = prec_code(prec)
+    pr = problem_c(problem, px, py)
+    need = _lib.lib.gpl_pcg_solve_workspace(C.byref(pr), k, m, pcode)
+    if ws is None or ws.numel() < need:
+        ws, _ = workspace(need, dev)
+    _lib.call("gpl_pcg_solve", C.byref(pr), k, _ptr(pc["L"]), npix, _ptr(pc["G"]), k, m, _ptr(Bm), ldb, _ptr(X),
+              npix, float(tol), int(max_iter), int(fixed_iters), nl, _ptr(ab), _ptr(rz0), _ptr(iters), _ptr(relres),
+              _ptr(true_relres), _ptr(status), pcode, int(check_every), _wsptr(ws), int(need), _stream())
+    return dict(X=X, ab=ab[:, :nl], bnorm2=rz0, rz0=rz0, iters=iters, relres=relres, true_relres=true_relres,
+                status=status, n_lanczos=nl)
 
 
 def evidence_scalars(n_pix, n_points, r, u, logdet, amplitude, noise_sigma):

@@ -30,6 +30,7 @@ class Reconstruction:
     scalars: torch.Tensor  # quad, ln p, L_VI (float64, device)
     fhat: torch.Tensor | None
     image: torch.Tensor | None
+    precond: dict | None = None  # the preconditioner of reconstruct_preconditioned
 
     def host(self):
         """Copy the scalar results to the host (one synchronisation)."""
@@ -75,3 +76,42 @@ def reconstruct(problem: Problem, d: torch.Tensor, probes: torch.Tensor, prec="f
         ops.kernel_mvm(problem.kernel, px, py, w, prec="fp32", out=fhat, beta=1.0, grid=g)  # mu + K B^T u
         image = ops.psf_conv(g, problem.psf, fhat, adjoint=False)
     return Reconstruction(px, py, mu, rhs, cg["X"], cg, logdet, stderr, contrib, scalars, fhat, image)
+
+
+def reconstruct_preconditioned(problem: Problem, d: torch.Tensor, g: torch.Tensor, h: torch.Tensor, rank=4096,
+                               prec="f16x3", tol=1e-6, max_iter=200, n_lanczos=200, want_image=True,
+                               check_every=2, ws=None):
+    """Evidence and posterior mean of one image with the partial pivoted
+    Cholesky preconditioner of rank `rank` (a multiple of 64): ln|A| = ln|P| +
+    the SLQ estimate of ln|P^{-1/2} A P^{-1/2}| from preconditioned CG on probes
+    z = L g + sigma h ~ N(0, P). g: (m, rank) float64 and h: (m, n_pix) float32
+    standard normals on the GPU."""
+    gr = problem.grid
+    dev = d.device
+    pts = ops.lens_raytrace(gr, problem.lens, device=dev)
+    px, py = pts[0], pts[1]
+    mu = ops.sersic_eval(problem.source, px, py)
+    pc = ops.pchol(problem, px, py, rank, prec=prec)
+    m = g.shape[0]
+    rhs = torch.empty(1 + m, gr.n_pix, dtype=torch.float32, device=dev)
+    rhs[0].copy_(d)
+    if m:
+        rhs[1:].copy_(ops.pchol_probes(pc, problem.noise_sigma, g, h))
+    ops.psf_conv(gr, problem.psf, mu, adjoint=False, out=rhs[0], alpha=-1.0, beta=1.0)  # r = d - B mu
+    cg = ops.pcg_solve(problem, px, py, pc, rhs, tol=tol, max_iter=max_iter, n_lanczos=n_lanczos, prec=prec,
+                       check_every=check_every, ws=ws)
+    if m and cg["n_lanczos"] > 0:
+        logdet, stderr, contrib = ops.lanczos_logdet(cg["ab"][1:], cg["iters"][1:], cg["rz0"][1:], 1.0 / m,
+                                                     offset=pc["logdet_P"])
+    else:
+        logdet = torch.full((1,), math.nan, dtype=torch.float64, device=dev)
+        stderr, contrib = logdet.clone(), torch.empty(0, dtype=torch.float64, device=dev)
+    u = cg["X"][0]
+    scalars = ops.evidence_scalars(gr.n_pix, gr.N, rhs[0], u, logdet, problem.kernel.amplitude, problem.noise_sigma)
+    fhat = image = None
+    if want_image:
+        w = ops.psf_conv(gr, problem.psf, u, adjoint=True)
+        fhat = mu.clone()
+        ops.kernel_mvm(problem.kernel, px, py, w, prec="fp32", out=fhat, beta=1.0, grid=gr)
+        image = ops.psf_conv(gr, problem.psf, fhat, adjoint=False)
+    return Reconstruction(px, py, mu, rhs, cg["X"], cg, logdet, stderr, contrib, scalars, fhat, image, pc)

@@ -151,6 +151,16 @@ def rademacher(n: int, m: int, index: int, sub: int = 0) -> np.ndarray:
     return (r.integers(0, 2, size=(n, m), dtype=np.int8) * 2 - 1).astype(np.float64)
 
 
+_TAG_PC_PROBE = 7
+
+
+def preconditioned_probe_normals(n: int, k: int, m: int, index: int, sub: int = 0):
+    """Standard normals for m probes of a rank-k preconditioner on n pixels:
+    g (m, k) and h (m, n), both float64."""
+    r = _rng(index, _TAG_PC_PROBE, sub)
+    return r.standard_normal((m, k)), r.standard_normal((m, n))
+
+
 def gp_normals(N: int, index: int, sub: int = 0) -> np.ndarray:
     """Standard normals for an exact (factorised) GP draw over N points."""
     return _rng(index, _TAG_GP, sub).standard_normal(N)

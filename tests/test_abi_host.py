@@ -70,7 +70,14 @@ def test_invalid_arguments_rejected_on_host():
     assert need > 0
     assert L.lib.gpl_gp_kernel_mvm(C.byref(k), None, 40000, p, p, 17, p, 40000, C.c_void_p(64), 40000, 0.0, 0, None, 0,
                                    None) == L.GPL_EWORKSPACE
-    assert L.lib.gpl_lanczos_logdet(0, 30, p, p, p, 1.0, p, p, p, None, 0, None) == L.GPL_EINVAL
+    assert L.lib.gpl_lanczos_logdet(0, 30, p, p, p, 1.0, None, p, p, p, None, 0, None) == L.GPL_EINVAL
+    # preconditioner: rank not a multiple of 64, zero noise
+    prob = L.gpl_problem(g, k, L.gpl_psf(0.1, 0), 0.02, p, p)
+    assert L.lib.gpl_pchol(C.byref(prob), 100, 1, p, 100, p, 100, p, p, p, None, 0, None) == L.GPL_EINVAL
+    assert b"multiple of 64" in L.lib.gpl_last_error()
+    prob0 = L.gpl_problem(g, k, L.gpl_psf(0.1, 0), 0.0, p, p)
+    assert L.lib.gpl_pchol(C.byref(prob0), 64, 1, p, 100, p, 64, p, p, p, None, 0, None) == L.GPL_EINVAL
+    assert L.lib.gpl_pchol(C.byref(prob), 64, 1, p, 100, p, 64, p, p, p, None, 0, None) == L.GPL_EWORKSPACE
 
 
 def test_workspace_sizes_monotone():
