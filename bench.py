@@ -39,6 +39,8 @@ FIXTURE = os.path.join(ROOT, "tests", "fixtures", "workload1_draw0.npz")
 N_LANCZOS = 1000
 # Every k-th product launch of the timed steps is timed with HIP events.
 TIMING_STRIDE = 16
+# Rank of the partial pivoted Cholesky preconditioner of the preconditioned step.
+PC_RANK = 4096
 METRIC = "kernel-MVM Gpairs/s at N=40k; reconstructions/s + p99 latency vs plain form"
 
 # Peak of the plain ALUs for the exp tile: 256 CUs x
@@ -289,6 +291,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f16x3", choices=["f16x3", "fp32"])
     ap.add_argument("--plain-steps", type=int, default=3, help="timed steps of the plain FP32 form (0: skip)")
+    ap.add_argument("--pc-steps", type=int, default=3,
+                    help="timed steps with the rank-%d partial pivoted Cholesky preconditioner (0: skip)" % 4096)
     ap.add_argument("--async-steps", type=int, default=2,
                     help="steps with the fully asynchronous CG call (no host wait; 0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0: skip)")
@@ -393,6 +397,34 @@ def main():
                 t_async.append((time.perf_counter() - t) * 1e3)
         async_ms = float(np.mean(t_async))
 
+    # ---- the same image with the partial pivoted Cholesky preconditioner
+    # (rank PC_RANK): ln|A| = ln|P| + SLQ of P^{-1/2} A P^{-1/2}, 16 probes N(0, P)
+    pcsec = None
+    if args.pc_steps > 0:
+        gn, hn = synth.preconditioned_probe_normals(npix, PC_RANK, 16, 1)
+        gn = torch.as_tensor(gn, dtype=torch.float64, device="cuda")
+        hn = torch.as_tensor(hn, dtype=torch.float32, device="cuda")
+        G.reconstruct_preconditioned(prob, d, gn, hn, rank=PC_RANK, prec=args.prec)  # warmup
+        pts_pc = G.ops.lens_raytrace(prob.grid, prob.lens)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.pc_steps):
+            rpc = G.reconstruct_preconditioned(prob, d, gn, hn, rank=PC_RANK, prec=args.prec)
+        torch.cuda.synchronize()
+        pc_el = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        G.ops.pchol(prob, pts_pc[0], pts_pc[1], PC_RANK, prec=args.prec)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        hp = rpc.host()
+        pcsec = {"rank": PC_RANK, "probes": 16, "ms_per_step": pc_el / args.pc_steps * 1e3,
+                 "reconstructions_per_s": args.pc_steps / pc_el, "preconditioner_build_ms": t_build * 1e3,
+                 "pcg_iters": max(hp["iters"]), "lnp_rel_err_vs_oracle": abs(hp["lnp"] - lnp_ref) / abs(lnp_ref),
+                 "lnp_slq_stderr_rel": 0.5 * hp["stderr"] / abs(lnp_ref),
+                 "logdet_err_vs_oracle": hp["logdet"] - float(z["logdet"]), "slq_stderr": hp["stderr"],
+                 "quad_rel_err_vs_oracle": abs(hp["quad"] - float(z["quad"])) / float(z["quad"]),
+                 "true_relres_max": max(hp["true_relres"])}
+
     # ---- plain FP32 form, same step, and its product's own roofline
     plain = None
     if args.plain_steps > 0 and args.prec != "fp32":
@@ -468,6 +500,7 @@ def main():
                      "subtile_pairs_with_lo": live_lo, "subtile_pairs": live_subtiles,
                      "mfma_flop_per_launch": mfma_flop,
                      "mfma_tflops_executed": mfma_flop / (avg_ms * 1e-3) / 1e12},
+        "preconditioned": pcsec,
         "plain_fp32": plain,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -35,46 +35,41 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
 }
 
 // Factor the jb x jb diagonal block at A (leading dimension lda) in place:
-// lower Cholesky, column by column in LDS. A non-positive or non-finite pivot
-// sets *info to its global column + 1 (first one wins) and leaves the block
-// unfinished. logd[c] = ln of the diagonal entry of column c.
+// lower Cholesky by one wave in LDS, lane a owning row a (right-looking: after
+// each column the lanes below it update their own rows). A non-positive or
+// non-finite pivot sets *info to its global column + 1 (first one wins) and
+// leaves the block unfinished. logd[c] = ln of the diagonal entry of column c.
 constexpr int kDiag = 64;
-__global__ __launch_bounds__(256) void potf2_kernel(double* A, int lda, int jb, int col0, double* logd, int* info) {
+__global__ __launch_bounds__(64) void potf2_kernel(double* A, int lda, int jb, int col0, double* logd, int* info) {
   __shared__ double T[kDiag][kDiag + 1];
-  __shared__ int s_bad;
-  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
-    const int i = e % jb, j = e / jb;
-    T[i][j] = A[(size_t)j * lda + i];
-  }
-  if (threadIdx.x == 0) s_bad = 0;
+  const int a = threadIdx.x;
+  for (int j = 0; j < jb; ++j)
+    if (a < jb) T[a][j] = A[(size_t)j * lda + a];
   __syncthreads();
   for (int c = 0; c < jb; ++c) {
-    if (threadIdx.x == 0) {
-      const double p = T[c][c];
-      if (!(p > 0.0) || !isfinite(p)) {
-        s_bad = 1;
-        atomicCAS(info, 0, col0 + c + 1);
-      } else {
-        T[c][c] = sqrt(p);
-        logd[col0 + c] = 0.5 * log(p);
-      }
+    const double p = T[c][c];
+    if (!(p > 0.0) || !isfinite(p)) {
+      if (a == 0) atomicCAS(info, 0, col0 + c + 1);
+      return;
+    }
+    const double piv = sqrt(p);
+    __syncthreads();
+    if (a == c) {
+      T[c][c] = piv;
+      logd[col0 + c] = 0.5 * log(p);
+    }
+    double l = 0.0;
+    if (a > c && a < jb) {
+      l = T[a][c] / piv;
+      T[a][c] = l;
     }
     __syncthreads();
-    if (s_bad) return;
-    const double piv = T[c][c];
-    for (int i = c + 1 + threadIdx.x; i < jb; i += blockDim.x) T[i][c] /= piv;
-    __syncthreads();
-    const int m = jb - c - 1;  // trailing lower triangle of order m
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-      const int i = c + 1 + e % m, j = c + 1 + e / m;
-      if (j <= i) T[i][j] -= T[i][c] * T[j][c];
-    }
+    if (a > c && a < jb)
+      for (int j = c + 1; j <= a; ++j) T[a][j] -= l * T[j][c];
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
-    const int i = e % jb, j = e / jb;
-    A[(size_t)j * lda + i] = j <= i ? T[i][j] : 0.0;
-  }
+  for (int j = 0; j < jb; ++j)
+    if (a < jb) A[(size_t)j * lda + a] = j <= a ? T[a][j] : 0.0;
 }
 
 // out[0] = sum of logd[0..n) in index order (one wave, lane-strided then a
@@ -96,7 +91,7 @@ int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, do
   for (int j0 = 0; j0 < n; j0 += kDiag) {
     const int jb = std::min(kDiag, n - j0);
     double* Ajj = A + (size_t)j0 * lda + j0;
-    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(256), 0, stream, Ajj, lda, jb, j0, logd, info);
+    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(kDiag), 0, stream, Ajj, lda, jb, j0, logd, info);
     GPL_LAUNCH_CHECK();
     const int m = n - j0 - jb;
     if (m <= 0) break;

@@ -12,10 +12,11 @@
 // threshold), and the block's columns of L follow by a triangular solve
 // (dtrsm). Candidates the block does not take leave zero columns, which change
 // neither L L^T nor the determinant identity below. Then
-//   G = sigma^2 I_k + L^T L = R R^T (dsyrk, blocked Cholesky),
+//   G = sigma^2 I_k + L^T L = R R^T (dgemm, blocked Cholesky),
 //   ln|P| = (n - k) ln sigma^2 + ln|G|,  P = L L^T + sigma^2 I_n.
 // Solve. Preconditioned CG, one recurrence per column, with
-//   P^{-1} v = (v - L G^{-1} L^T v) / sigma^2 (dgemm, two dtrsm, dgemm),
+//   P^{-1} v = (v - L G^{-1} L^T v) / sigma^2 (dgemm, two dtrsm, dgemm in
+//   transposed form),
 // FP32 vectors, FP64 scalars and Woodbury products; the alpha/beta of the
 // first steps give the Lanczos tridiagonal of P^{-1/2} A P^{-1/2} with the
 // usual CG formulas, and rz0 = b^T P^{-1} b is each probe's quadrature weight.
@@ -91,9 +92,10 @@ __global__ __launch_bounds__(256) void bkb_diag_kernel(int n, int ss, const Taps
 constexpr int kSelThreads = 1024;
 __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const double* __restrict__ d, int* cand) {
   __shared__ int hist[2048];
+  __shared__ int cnt2[2048];
   __shared__ int s_scan[kSelThreads];
   __shared__ unsigned s_prefix, s_mask;
-  __shared__ int s_need;
+  __shared__ int s_need, s_pick;
   const int t = threadIdx.x;
   const int per = cdiv(n, kSelThreads), i0 = t * per, i1 = min(n, i0 + per);
   auto key = [&](int i) -> unsigned {
@@ -117,13 +119,32 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
       if (k != 0u && (k & mask) == prefix) atomicAdd(&hist[(k >> sh) & (nb - 1)], 1);
     }
     __syncthreads();
+    // counts from the top bin down: incl[i] = sum of hist over the i+1 highest
+    // bins (bins nb-1-i' for i' <= i), by a parallel inclusive scan; the chosen
+    // bin is the highest whose inclusive count reaches the number still needed
+    // (bin 0 if none does), and that many minus the count above it remain.
+    const int need0 = s_need;
+    for (int q = t; q < nb; q += kSelThreads) cnt2[q] = hist[nb - 1 - q];
+    __syncthreads();
+    for (int off = 1; off < nb; off <<= 1) {
+      int v0 = 0, v1 = 0;
+      const int q0 = t, q1 = t + kSelThreads;
+      if (q0 < nb && q0 >= off) v0 = cnt2[q0 - off];
+      if (q1 < nb && q1 >= off) v1 = cnt2[q1 - off];
+      __syncthreads();
+      if (q0 < nb) cnt2[q0] += v0;
+      if (q1 < nb) cnt2[q1] += v1;
+      __syncthreads();
+    }
+    if (t == 0) s_pick = nb - 1;  // "none reached": bin 0
+    __syncthreads();
+    for (int q = t; q < nb; q += kSelThreads)
+      if (cnt2[q] >= need0 && (q == 0 || cnt2[q - 1] < need0)) s_pick = q;
+    __syncthreads();
     if (t == 0) {
-      int need = s_need, b = nb - 1;
-      for (; b > 0; --b) {
-        if (hist[b] >= need) break;
-        need -= hist[b];
-      }
-      s_need = need;
+      const int q = s_pick, b = nb - 1 - q;
+      const int above_cnt = cnt2[q] - hist[b];
+      s_need = need0 - above_cnt;
       s_prefix = prefix | ((unsigned)b << sh);
       s_mask = mask | ((unsigned)(nb - 1) << sh);
     }
@@ -200,87 +221,75 @@ __global__ void gather_rows_kernel(int j, const double* __restrict__ L, int ldl,
   Lc[(size_t)col * kPcBlock + c] = cand[c] >= 0 ? L[(size_t)col * ldl + cand[c]] : 0.0;
 }
 
-// Pivoted Cholesky of the residual block S = C[cand, :] (kPcBlock x kPcBlock) in
-// one workgroup: repeatedly the largest remaining diagonal entry, while it
-// exceeds tol (a share of the largest initial diagonal entry, d_max[0]).
-// Outputs order[0..kPcBlock) (taken candidates in pivot order first, then the
-// rest), *taken, and R (kPcBlock x kPcBlock, lower, in pivot order; identity on
-// the untaken part).
-__global__ __launch_bounds__(256) void block_pivot_kernel(const double* __restrict__ C, int npix, const int* cand,
-                                                          const double* dmax, double rel_tol, int* order,
-                                                          int* taken, double* R) {
-  // S[a][b] = C[cand[a], b] is read from global memory where needed; only the
-  // block's factor lives in LDS
-  __shared__ double Lb[kPcBlock][kPcBlock + 1];
-  __shared__ double rd[kPcBlock];  // residual diagonal of S
+// Pivoted Cholesky of the residual block S = C[cand, :] (kPcBlock x kPcBlock)
+// by one wave, lane a owning candidate a: each step takes the largest remaining
+// diagonal entry (lowest candidate index on ties) while it exceeds tol (a share
+// of the largest diagonal entry of M, dmax[0]), forms l = S[:, p] / sqrt(S[p][p])
+// and updates S -= l l^T in LDS; the l vectors go to lv (kPcBlock x kPcBlock,
+// global). Outputs order[0..kPcBlock) (taken candidates in pivot order first,
+// then the rest), *taken, and R (kPcBlock x kPcBlock, lower, R[u][v] = l of
+// step v at the u-th pivot; identity on the untaken part).
+__global__ __launch_bounds__(64) void block_pivot_kernel(const double* __restrict__ C, int npix, const int* cand,
+                                                         const double* dmax, double rel_tol, double* lv,
+                                                         int* order, int* taken, double* R) {
+  __shared__ double S[kPcBlock][kPcBlock + 1];
+  __shared__ double lcol[kPcBlock];
   __shared__ int s_perm[kPcBlock];
-  __shared__ int s_used[kPcBlock];
-  __shared__ int s_piv, s_stop, s_count;
-  const int t = threadIdx.x;
-  for (int e = t; e < kPcBlock * kPcBlock; e += blockDim.x) Lb[e % kPcBlock][e / kPcBlock] = 0.0;
-  for (int a = t; a < kPcBlock; a += blockDim.x) {
-    s_used[a] = cand[a] < 0;
-    rd[a] = cand[a] < 0 ? 0.0 : C[(size_t)a * npix + cand[a]];
+  const int a = threadIdx.x;
+  const int ca = cand[a];
+  for (int b = 0; b < kPcBlock; ++b) {
+    const int cb = cand[b];
+    S[a][b] = (ca >= 0 && cb >= 0) ? C[(size_t)b * npix + ca] : 0.0;
   }
-  if (t == 0) {
-    s_stop = 0;
-    s_count = 0;
-  }
-  __syncthreads();
+  bool used = ca < 0;
   const double tol = rel_tol * dmax[0];
+  int cnt = 0;
+  __syncthreads();
   for (int step = 0; step < kPcBlock; ++step) {
-    if (t == 0) {  // the largest remaining diagonal entry (lowest index on ties)
-      int best = -1;
-      double bv = 0.0;
-      for (int a = 0; a < kPcBlock; ++a)
-        if (!s_used[a] && rd[a] > bv) {
-          bv = rd[a];
-          best = a;
-        }
-      if (best < 0 || !(bv > tol)) {
-        s_stop = 1;
-      } else {
-        s_piv = best;
-        s_used[best] = 1;
-        s_perm[step] = best;
-        Lb[best][step] = sqrt(bv);
-        s_count = step + 1;
+    // wave argmax of the remaining diagonal, lowest index on ties
+    double v = used ? -1.0 : S[a][a];
+    int idx = a;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
       }
     }
+    const int p = idx;
+    if (!(v > tol)) break;
+    const double lpp = sqrt(v);
+    const double l = a == p ? lpp : (used ? 0.0 : S[a][p] / lpp);
+    lcol[a] = (a == p || used) ? 0.0 : l;
+    lv[(size_t)step * kPcBlock + a] = l;
+    if (a == 0) s_perm[step] = p;
     __syncthreads();
-    if (s_stop) break;
-    const int p = s_piv;
-    const double lpp = Lb[p][step];
-    for (int a = t; a < kPcBlock; a += blockDim.x) {
-      if (s_used[a]) continue;
-      double v = C[(size_t)p * npix + cand[a]];
-      for (int q = 0; q < step; ++q) v -= Lb[a][q] * Lb[p][q];
-      const double l = v / lpp;
-      Lb[a][step] = l;
-      rd[a] -= l * l;
-    }
+    if (!used && a != p)
+      for (int b = 0; b < kPcBlock; ++b) S[a][b] -= l * lcol[b];
+    used = used || a == p;
+    cnt = step + 1;
     __syncthreads();
   }
-  const int cnt = s_count;
   // order: taken pivots first, then the rest in candidate order
-  if (t == 0) {
+  if (a == 0) {
     int q = cnt;
-    for (int a = 0; a < kPcBlock; ++a) {
+    for (int b = 0; b < kPcBlock; ++b) {
       bool in_perm = false;
-      for (int u = 0; u < cnt; ++u) in_perm |= s_perm[u] == a;
-      if (!in_perm) s_perm[q++] = a;
+      for (int u = 0; u < cnt; ++u) in_perm |= s_perm[u] == b;
+      if (!in_perm) s_perm[q++] = b;
     }
     *taken = cnt;
   }
   __syncthreads();
-  for (int a = t; a < kPcBlock; a += blockDim.x) order[a] = s_perm[a];
-  // R[u][v] = Lb[perm[u]][v] for v <= u < cnt; identity beyond
-  for (int e = t; e < kPcBlock * kPcBlock; e += blockDim.x) {
-    const int u = e % kPcBlock, v = e / kPcBlock;
+  order[a] = s_perm[a];
+  // R[u][v] = lv[v][perm[u]] for v <= u < cnt; identity beyond (column a = v)
+  const int vcol = a;
+  for (int u = 0; u < kPcBlock; ++u) {
     double val = 0.0;
-    if (u < cnt && v < cnt) val = v <= u ? Lb[s_perm[u]][v] : 0.0;
-    else if (u == v) val = 1.0;
-    R[(size_t)v * kPcBlock + u] = val;
+    if (u < cnt && vcol < cnt) val = vcol <= u ? lv[(size_t)vcol * kPcBlock + s_perm[u]] : 0.0;
+    else if (u == vcol) val = 1.0;
+    R[(size_t)vcol * kPcBlock + u] = val;
   }
 }
 
@@ -361,7 +370,7 @@ __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, 
 
 struct PcBuf {
   float *E, *T1, *T2, *Mc;
-  double *C, *Lc, *R, *d, *dmax, *logd, *logdet_g;
+  double *C, *Lc, *R, *lv, *d, *dmax, *logd, *logdet_g;
   int *cand, *order, *taken, *info, *is_piv;
   void* mvm_ws;
   size_t mvm_bytes;
@@ -378,6 +387,7 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.C = c.template take<double>((size_t)npix * kPcBlock);
   b.Lc = c.template take<double>((size_t)kPcBlock * std::max(k, 1));
   b.R = c.template take<double>((size_t)kPcBlock * kPcBlock);
+  b.lv = c.template take<double>((size_t)kPcBlock * kPcBlock);
   b.d = c.template take<double>(npix);
   b.dmax = c.template take<double>(1);
   b.logd = c.template take<double>(std::max(k, 1));
@@ -466,19 +476,22 @@ __global__ __launch_bounds__(256) void pcg_widen_kernel(int npix, const float* _
   Z64[(size_t)c * ldv + i] = v;
 }
 
-// P^{-1} R for every column: W = L^T R64; W = G^{-1} W (two triangular solves
-// with the factor of G); Z64 = R64 - L W. The caller finishes Z = Z64 / s.
+// P^{-1} R for every column, with the products in transposed form (the long
+// dimension n as the reduction of the first and the rows of the second):
+// Wt = R64^T L (m x k); Wt = Wt G^{-1} (two triangular solves with the factor
+// of G from the right; G is symmetric); Z64 = R64 - L Wt^T. The caller finishes
+// Z = Z64 / s.
 static int woodbury(rocblas_handle h, int npix, int k, const double* L, int ldl, const double* G, int ldg, int nrhs,
-                    const double* R64, double* Z64, int ldv, double* W) {
+                    const double* R64, double* Z64, int ldv, double* Wt) {
   const double one = 1.0, zero = 0.0, minus_one = -1.0;
-  if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, nrhs, npix, &one, L, ldl, R64, ldv,
-                    &zero, W, k) != rocblas_status_success ||
-      rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, k,
-                    nrhs, &one, G, ldg, W, k) != rocblas_status_success ||
-      rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
-                    rocblas_diagonal_non_unit, k, nrhs, &one, G, ldg, W, k) != rocblas_status_success ||
-      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, npix, nrhs, k, &minus_one, L, ldl, W, k, &one,
-                    Z64, ldv) != rocblas_status_success) {
+  if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, nrhs, k, npix, &one, R64, ldv, L, ldl,
+                    &zero, Wt, nrhs) != rocblas_status_success ||
+      rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                    rocblas_diagonal_non_unit, nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success ||
+      rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit,
+                    nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success ||
+      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, nrhs, k, &minus_one, L, ldl, Wt,
+                    nrhs, &one, Z64, ldv) != rocblas_status_success) {
     set_error("rocBLAS call of the preconditioner failed");
     return GPL_EHIP;
   }
@@ -876,7 +889,7 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
         return GPL_EHIP;
       }
     }
-    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(256), 0, stream, b.C, npix, b.cand, b.dmax, kPcRelTol,
+    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64), 0, stream, b.C, npix, b.cand, b.dmax, kPcRelTol, b.lv,
                        b.order, b.taken, b.R);
     GPL_LAUNCH_CHECK();
     double* Lnew = L + (size_t)j0 * ldl;
@@ -894,9 +907,9 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   }
   // G = s I + L^T L and its Cholesky factor; ln|P|
   const double s = prob->noise_sigma * prob->noise_sigma;
-  if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, k, npix, &one, L, ldl, &zero, G, ldg) !=
-      rocblas_status_success) {
-    set_error("rocblas_dsyrk (L^T L) failed");
+  if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, k, npix, &one, L, ldl, L, ldl, &zero,
+                    G, ldg) != rocblas_status_success) {
+    set_error("rocblas_dgemm (L^T L) failed");
     return GPL_EHIP;
   }
   hipLaunchKernelGGL(add_diag_kernel, dim3(cdiv(k, 256)), dim3(256), 0, stream, k, G, ldg, s);
