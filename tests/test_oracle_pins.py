@@ -14,7 +14,7 @@ import scipy.integrate as si
 import scipy.stats as st
 
 import synth
-from oracle import data, evidence, gradients, grid, kernel, krylov, lens, precond, psf, source
+from oracle import data, evidence, gradients, grid, kernel, krylov, lens, precond, psf, source, window
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -518,3 +518,129 @@ def test_rff_draw_covariance_is_rbf():
         draws.append(data.gp_draw_rff(px, py, 0.04, 0.3, om, ph, w))
     cov = np.cov(np.array(draws).T)
     assert np.allclose(cov, kernel.rbf_matrix(px, py, 0.04, 0.3), atol=0.08 * 0.09)
+
+
+# ---------------------------------------------------------------- pixel shapes, transmission (Sec. 3.2, 3.4, 3.5)
+
+def test_windowed_kernel_reduces_to_rbf():
+    """Z -> 0: eq. "covariance" is the RBF kernel of eq. "grbf"."""
+    rng = np.random.default_rng(50)
+    px, py = rng.uniform(-0.3, 0.3, (2, 60))
+    K0 = window.windowed_kernel_matrix(px, py, np.zeros((60, 3)), 0.04, 0.3)
+    assert np.allclose(K0, kernel.rbf_matrix(px, py, 0.04, 0.3), rtol=1e-13, atol=0)
+    # and continuously: a tiny shape moves K by O(|Z| / l^2)
+    Zt = np.tile([1e-9, 0.0, 1e-9], (60, 1))
+    Kt = window.windowed_kernel_matrix(px, py, Zt, 0.04, 0.3)
+    assert np.max(np.abs(Kt - K0)) <= 1e-4 * 0.09
+
+
+def test_window_square_integral_is_inverse_area():
+    """App. C: int w^2 = 1/|a x b| for Z = (a a^T + b b^T)/(4 pi), by quadrature."""
+    rng = np.random.default_rng(51)
+    for _ in range(4):
+        a, b = rng.uniform(-1, 1, 2), rng.uniform(-1, 1, 2)
+        Z = window.shape_cov(a[None], b[None])[0]
+        area = abs(a[0] * b[1] - a[1] * b[0])
+        s = math.sqrt(max(Z[0], Z[2]))
+        t = np.linspace(-12 * s, 12 * s, 1601)
+        X, Y = np.meshgrid(t, t)
+        w = window.gauss2(X, Y, Z[0], Z[1], Z[2])
+        integral = np.sum(w * w) * (t[1] - t[0]) ** 2
+        assert math.isclose(integral, 1.0 / area, rel_tol=1e-6)
+
+
+def test_windowed_covariance_is_the_double_integral():
+    """Eq. "covariance" against its definition, eq. "windowing": the mean of the
+    RBF kernel over independent draws from the two indicator Gaussians (Monte
+    Carlo, 4e6 samples, within 5 standard errors)."""
+    rng = np.random.default_rng(52)
+    ell, amp = 0.04, 0.3
+    pi_, pj = np.array([0.01, -0.02]), np.array([0.05, 0.03])
+    Zi = window.shape_cov(np.array([[0.03, 0.01]]), np.array([[-0.005, 0.02]]))[0]
+    Zj = window.shape_cov(np.array([[0.02, -0.015]]), np.array([[0.01, 0.025]]))[0]
+    want = window.windowed_kernel_matrix(pi_[:1], pi_[1:], Zi[None], ell, amp, pj[:1], pj[1:], Zj[None])[0, 0]
+    m = 4_000_000
+
+    def draw(mu, Z):
+        Lc = np.linalg.cholesky(np.array([[Z[0], Z[1]], [Z[1], Z[2]]]))
+        return mu + rng.standard_normal((m, 2)) @ Lc.T
+
+    x1, x2 = draw(pi_, Zi), draw(pj, Zj)
+    k = amp * amp * np.exp(-np.sum((x1 - x2) ** 2, axis=1) / (2 * ell * ell))
+    assert abs(k.mean() - want) <= 5 * k.std() / math.sqrt(m)
+
+
+def test_pixel_axes_on_a_regular_grid():
+    """An undeflected grid of spacing h: a = (h, 0), b = (0, h) everywhere,
+    edges included; Z = h^2 I / (4 pi), whose indicator has area h^2."""
+    h, M = 0.025, 7
+    x, y = grid.fine_coords(M, 1, h)
+    a, b = window.pixel_axes(x, y, M)
+    assert np.allclose(a, [h, 0.0]) and np.allclose(b, [0.0, h])
+    Z = window.shape_cov(a, b)
+    assert np.allclose(Z, [h * h / (4 * math.pi), 0.0, h * h / (4 * math.pi)])
+    # a sheared grid: the central difference of a linear map is exact inside
+    J = np.array([[1.3, 0.4], [-0.2, 0.7]])
+    P = (J @ np.stack([x, y])).T
+    a2, b2 = window.pixel_axes(P[:, 0], P[:, 1], M)
+    assert np.allclose(a2, J @ [h, 0.0]) and np.allclose(b2, J @ [0.0, h])
+
+
+def test_windowed_kernel_symmetric_psd_on_lensed_grid():
+    w = synth.workload(0)
+    P = evidence.Problem(w.n, w.ss, w.pix_scale, w.lens.as_tuple(), (1.0, 0.1, 1.5, 0.0, 0.0), w.ell, w.amp,
+                         w.noise_sigma, 0.0)
+    px, py = P.points()
+    a, b = window.pixel_axes(px, py, w.n * w.ss)
+    K = window.windowed_kernel_matrix(px, py, window.shape_cov(a, b), w.ell, w.amp)
+    assert np.array_equal(K, K.T)
+    assert np.linalg.eigvalsh(K).min() >= -1e-12 * w.amp ** 2 * px.size
+    # the pixel shapes widen the kernel: K_ii = alpha^2 l^2 / sqrt|2 Z_i + l^2 I| <= alpha^2
+    assert np.all(np.diag(K) <= w.amp ** 2 * (1 + 1e-15))
+
+
+def test_transmission_factorises_the_windowed_kernel():
+    """Eq. "transmission": with inducing points on a dense regular grid of
+    spacing s (density 1/s^2) covering the points, alpha^2 T T^T reproduces the
+    windowed K (the sum over the grid is a converged Riemann sum of a Gaussian
+    product)."""
+    rng = np.random.default_rng(53)
+    ell, amp = 0.04, 0.3
+    px, py = rng.uniform(-0.05, 0.05, (2, 12))
+    Z = window.shape_cov(rng.uniform(-0.01, 0.01, (12, 2)), rng.uniform(-0.01, 0.01, (12, 2)))
+    s = ell / 5
+    g = np.arange(-0.35, 0.35 + s / 2, s)
+    qx, qy = [v.ravel() for v in np.meshgrid(g, g)]
+    A = window.transmission_weights(np.full(qx.size, 1.0 / (s * s)), ell)
+    T = window.transmission_matrix(px, py, Z, qx, qy, ell, A)
+    K = window.windowed_kernel_matrix(px, py, Z, ell, amp)
+    assert np.allclose(amp * amp * T @ T.T, K, rtol=1e-8, atol=1e-12)
+
+
+def test_knn_density():
+    """k-th neighbour density: a square lattice of spacing s has its 20th
+    closest other point at sqrt(5) s (4 + 4 + 4 + 8 neighbours), so the estimate
+    is 20 / (5 pi s^2) away from the edges; brute force on random points."""
+    s = 0.03
+    g = np.arange(15) * s
+    qx, qy = [v.ravel() for v in np.meshgrid(g, g)]
+    rho = window.knn_density(qx, qy, 20)
+    centre = 7 * 15 + 7
+    assert math.isclose(rho[centre], 20 / (5 * math.pi * s * s), rel_tol=1e-12)
+    rng = np.random.default_rng(54)
+    q = rng.uniform(0, 1, (2, 300))
+    r = window.knn_density(q[0], q[1], 5)
+    i = 17
+    d = np.sort(np.hypot(q[0] - q[0, i], q[1] - q[1, i]))[1:]
+    assert math.isclose(r[i], 5 / (math.pi * d[4] ** 2), rel_tol=1e-12)
+
+
+def test_reconstruction_is_transmission_without_shapes():
+    rng = np.random.default_rng(55)
+    qx, qy = rng.uniform(-0.2, 0.2, (2, 40))
+    A = window.transmission_weights(window.knn_density(qx, qy, 20), 0.04)
+    yk = rng.standard_normal(40)
+    x, y = rng.uniform(-0.2, 0.2, (2, 30))
+    want = np.array([sum(A[k] * math.exp(-((x[i] - qx[k]) ** 2 + (y[i] - qy[k]) ** 2) / (2 * 0.0008)) /
+                         (2 * math.pi * 0.0008) * yk[k] for k in range(40)) for i in range(30)])
+    assert np.allclose(window.reconstruct_brightness(x, y, qx, qy, yk, 0.04, A), want, rtol=1e-12)
