@@ -76,8 +76,16 @@ typedef struct {
   double I_e, R_e, n_sersic, b_n, xs, ys;
 } gpl_source;
 
-/* RBF kernel k = amplitude^2 exp(-|x1-x2|^2 / (2 lengthscale^2)) (eq. "grbf",
- * isotropic Sigma = lengthscale^2 I). kind must be 0. */
+/* kind 0: RBF kernel k = amplitude^2 exp(-|x1-x2|^2 / (2 lengthscale^2))
+ * (eq. "grbf", isotropic Sigma = lengthscale^2 I).
+ * kind 1: pixel-shape (windowed) kernel of Sec. 3.2, eq. "covariance":
+ * K_ij = amplitude^2 2 pi lengthscale^2 N(p_i - p_j, Z_i + Z_j + lengthscale^2 I),
+ * Z_i = (a a^T + b b^T) / (4 pi) from the pixel axes a, b (half the distance
+ * between the projected centres of the neighbouring grid points along each
+ * grid axis; one-sided at the grid edges; eq. "window-kernel" and its
+ * footnote); needs the grid (the points are its fine grid in row-major order),
+ * runs in the FP32 form, and is accepted by gpl_gp_kernel_mvm and gpl_apply_A
+ * (the other entry points take kind 0). */
 typedef struct {
   int kind;
   double lengthscale, amplitude;
@@ -164,6 +172,35 @@ size_t gpl_gp_kernel_mvm_plan_workspace(int n);
 int gpl_gp_kernel_mvm_plan_stats(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px,
                                  const float* py, int prec, long long* live_tiles, long long* live_subtiles,
                                  long long* live_lo, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Gaussian products with per-point shape covariances (Sec. 3.2 eq.
+ * "covariance", Sec. 3.4 eq. "transmission", Sec. 3.5 eq. "gp-reconstruction"):
+ *   Y[i][c] = beta Y[i][c] + norm wt_i sum_j ws_j |C_ij|^{-1/2} exp(-d^T C_ij^{-1} d / 2) V[j][c],
+ *   d = (tx_i - sx_j, ty_i - sy_j),  C_ij = Zt_i + Zs_j + base_var I.
+ * Targets (nt points tx, ty) and sources (ns points sx, sy) each take an
+ * optional shape covariance tz / sz (NULL or three device arrays of n floats
+ * stored one after another: zxx, zxy, zyy) and an optional weight tw / sw (NULL
+ * = 1). V (ns x nrhs, ld ldv) and Y (nt x nrhs, ld ldy) must not overlap. The
+ * windowed kernel is norm = amplitude^2 lengthscale^2, base_var =
+ * lengthscale^2 with Z on both sides; the transmission T_ik = A_k N(p_i - q_k,
+ * Z_i + lengthscale^2 I / 2) is norm = 1 / (2 pi), base_var = lengthscale^2 / 2,
+ * tz = Z, sw = A; its transpose swaps the sides. Every pair is evaluated in
+ * FP32. */
+typedef struct {
+  double base_var, norm;
+} gpl_gauss;
+int gpl_gauss_product(const gpl_gauss* g, int nt, const float* tx, const float* ty, const float* tz, const float* tw,
+                      int ns, const float* sx, const float* sy, const float* sz, const float* sw, int nrhs,
+                      const float* V, int ldv, float* Y, int ldy, float beta, hipStream_t stream);
+
+/* Pixel shapes Z (three arrays of (n*ss)^2 floats: zxx, zxy, zyy) of the
+ * ray-traced fine grid px, py (eq. "window-kernel", axes as for kind 1). */
+int gpl_pixel_shapes(const gpl_grid* grid, const float* px, const float* py, float* z, hipStream_t stream);
+
+/* Density of the inducing points q for the transmission weights (Sec. 3.4,
+ * footnote to eq. "transmission"): rho_i = k / (pi r_k^2), r_k the distance
+ * from q_i to its k-th closest other point (1 <= k <= 32, n > k); brute force. */
+int gpl_knn_density(int n, const float* qx, const float* qy, int k, float* rho, hipStream_t stream);
 
 /* Y = A X with A = B K B^T + noise_sigma^2 I (image pixels, nrhs columns). */
 size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int prec);

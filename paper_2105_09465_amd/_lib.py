@@ -41,6 +41,10 @@ class gpl_kernel(C.Structure):
     _fields_ = [("kind", C.c_int), ("lengthscale", C.c_double), ("amplitude", C.c_double)]
 
 
+class gpl_gauss(C.Structure):
+    _fields_ = [("base_var", C.c_double), ("norm", C.c_double)]
+
+
 class gpl_psf(C.Structure):
     _fields_ = [("fwhm", C.c_double), ("radius", C.c_int)]
 
@@ -101,6 +105,10 @@ SIGNATURES = {
     "gpl_sersic_backward_workspace": (_Z, [_I]),
     "gpl_sersic_backward": (_I, [C.POINTER(gpl_source), _I, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "gpl_block_dot": (_I, [_I, _I, _P, _I, _P, _I, _P, _P]),
+    "gpl_gauss_product": (_I, [C.POINTER(gpl_gauss), _I, _P, _P, _P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _P, _I,
+                               C.c_float, _P]),
+    "gpl_pixel_shapes": (_I, [C.POINTER(gpl_grid), _P, _P, _P, _P]),
+    "gpl_knn_density": (_I, [_I, _P, _P, _I, _P, _P]),
     "gpl_evidence_amplitude_grad": (_I, [_I, _I, _I, _P, _P, _I, _P, _I, _P, _D, _D, _D, _P, _P]),
     "gpl_timing_enable": (_I, [_I]),
     "gpl_serve_slot_workspace": (_Z, [C.POINTER(gpl_grid), _I, _I, _I]),

@@ -418,13 +418,13 @@ static int poll_slots(PollSlots*& out) {
   return GPL_OK;
 }
 
-static int check_problem(const gpl_problem* prob, Taps& taps) {
+static int check_problem(const gpl_problem* prob, Taps& taps, bool windowed_ok = false) {
   GPL_REQUIRE(prob != nullptr, "problem is NULL");
   const gpl_grid* g = &prob->grid;
   GPL_REQUIRE(g->n >= 1 && g->ss >= 1 && g->pix_scale > 0, "bad grid");
   GPL_REQUIRE(prob->px && prob->py, "problem points are NULL");
   GPL_REQUIRE(prob->noise_sigma >= 0 && std::isfinite(prob->noise_sigma), "noise_sigma must be >= 0");
-  GPL_TRY(check_kernel(&prob->kernel));
+  GPL_TRY(windowed_ok ? check_kernel_any(&prob->kernel) : check_kernel(&prob->kernel));
   GPL_TRY(make_taps(g, &prob->psf, taps));
   return GPL_OK;
 }
@@ -461,7 +461,7 @@ extern "C" size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int p
 extern "C" int gpl_apply_A(const gpl_problem* prob, int nrhs, const float* X, int ldx, float* Y, int ldy, int prec,
                            void* ws, size_t ws_bytes, hipStream_t stream) {
   Taps taps;
-  GPL_TRY(check_problem(prob, taps));
+  GPL_TRY(check_problem(prob, taps, true));
   GPL_REQUIRE(nrhs >= 0 && nrhs <= 65535, "nrhs out of range");
   if (nrhs == 0) return GPL_OK;
   const int npix = prob->grid.n * prob->grid.n, N = npix * prob->grid.ss * prob->grid.ss;
@@ -475,6 +475,19 @@ extern "C" int gpl_apply_A(const gpl_problem* prob, int nrhs, const float* X, in
   const size_t mb = mvm_workspace(N, nrhs, prec);
   char* mws = c.take<char>(mb);
   if (!c.ok()) return check_ws(nullptr, 0, 1);
+  if (prob->kernel.kind == 1) {  // windowed kernel: B^T, the Gaussian product with pixel shapes, B
+    if (prec != GPL_PREC_FP32) {
+      set_error("the windowed kernel (kind 1) runs in the FP32 form only");
+      return GPL_EUNSUPPORTED;
+    }
+    const int n = prob->grid.n, ss = prob->grid.ss;
+    const float s2 = (float)(prob->noise_sigma * prob->noise_sigma);
+    GPL_TRY(psf_adjoint_launch(n, ss, taps, nrhs, X, ldx, T1, ldf, 1.f, 0.f, CgGate{}, stream));
+    GPL_TRY(windowed_mvm(&prob->kernel, &prob->grid, N, prob->px, prob->py, nrhs, T1, ldf, T2, ldf, 0.f, mws, mb,
+                         stream));
+    return psf_forward_launch(n, ss, taps, nrhs, T2, ldf, Y, ldy, 1.f, 0.f, X, ldx, s2, nullptr, 0, nullptr,
+                              CgGate{}, stream);
+  }
   MvmCtx mv;
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid, nrhs,
                       prec, mws, mb, stream));

@@ -41,10 +41,14 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
 // leaves the block unfinished. logd[c] = ln of the diagonal entry of column c.
 constexpr int kDiag = 64;
 __global__ __launch_bounds__(64) void potf2_kernel(double* A, int lda, int jb, int col0, double* logd, int* info) {
+  // T[j][a] holds entry (a, j): lane a walks its row along j at consecutive
+  // LDS addresses across the lanes (no bank conflicts)
   __shared__ double T[kDiag][kDiag + 1];
+  __shared__ double ld[kDiag];  // written to logd after the loop (a global store before each barrier would
+                                // make every barrier wait for it)
   const int a = threadIdx.x;
   for (int j = 0; j < jb; ++j)
-    if (a < jb) T[a][j] = A[(size_t)j * lda + a];
+    if (a < jb) T[j][a] = A[(size_t)j * lda + a];
   __syncthreads();
   for (int c = 0; c < jb; ++c) {
     const double p = T[c][c];
@@ -56,20 +60,21 @@ __global__ __launch_bounds__(64) void potf2_kernel(double* A, int lda, int jb, i
     __syncthreads();
     if (a == c) {
       T[c][c] = piv;
-      logd[col0 + c] = 0.5 * log(p);
+      ld[c] = 0.5 * log(p);
     }
     double l = 0.0;
     if (a > c && a < jb) {
-      l = T[a][c] / piv;
-      T[a][c] = l;
+      l = T[c][a] / piv;
+      T[c][a] = l;
     }
     __syncthreads();
     if (a > c && a < jb)
-      for (int j = c + 1; j <= a; ++j) T[a][j] -= l * T[j][c];
+      for (int j = c + 1; j <= a; ++j) T[j][a] -= l * T[c][j];
     __syncthreads();
   }
   for (int j = 0; j < jb; ++j)
-    if (a < jb) A[(size_t)j * lda + a] = j <= a ? T[a][j] : 0.0;
+    if (a < jb) A[(size_t)j * lda + a] = j <= a ? T[j][a] : 0.0;
+  if (a < jb) logd[col0 + a] = ld[a];
 }
 
 // out[0] = sum of logd[0..n) in index order (one wave, lane-strided then a
@@ -112,6 +117,50 @@ int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, do
     hipLaunchKernelGGL(logdet_fold_kernel, dim3(1), dim3(64), 0, stream, n, logd, logdet);
     GPL_LAUNCH_CHECK();
   }
+  return GPL_OK;
+}
+
+// C (m x n, ld ldc) = alpha * sum_s Wp[s] + beta C, the splits in order.
+__global__ void split_sum_kernel(int m, int n, int nsplit, const double* __restrict__ Wp, double alpha, double beta,
+                                 double* C, int ldc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  const int r = e % m, c = e / m;
+  double v = 0.0;
+  for (int s = 0; s < nsplit; ++s) v += Wp[(size_t)s * m * n + e];
+  double* y = C + (size_t)c * ldc + r;
+  *y = beta == 0.0 ? alpha * v : alpha * v + beta * *y;
+}
+
+size_t split_gemm_scratch(int m, int n, int nsplit) { return (size_t)nsplit * m * n * sizeof(double); }
+
+int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int kdim, int nsplit,
+               double alpha, const double* A, int lda, const double* B, int ldb, double beta, double* C, int ldc,
+               double* scratch, hipStream_t stream) {
+  nsplit = std::max(1, std::min(nsplit, kdim));
+  const int kc = cdiv(kdim, nsplit);
+  nsplit = cdiv(kdim, kc);
+  const int last = kdim - (nsplit - 1) * kc;  // rows of the reduction in the last split
+  // element (i, l) of op(A) is A[l*lda + i] without transpose, A[i*lda + l] with it:
+  // a split of the reduction index l moves A by kc columns (no transpose) or
+  // kc rows (transpose); likewise for B with (l, j)
+  const rocblas_stride sa = ta == rocblas_operation_none ? (rocblas_stride)kc * lda : kc;
+  const rocblas_stride sb = tb == rocblas_operation_none ? kc : (rocblas_stride)kc * ldb;
+  const double one = 1.0, zero = 0.0;
+  if (nsplit > 1 &&
+      rocblas_dgemm_strided_batched(h, ta, tb, m, n, kc, &one, A, lda, sa, B, ldb, sb, &zero, scratch, m,
+                                    (rocblas_stride)m * n, nsplit - 1) != rocblas_status_success) {
+    set_error("rocblas_dgemm_strided_batched failed");
+    return GPL_EHIP;
+  }
+  if (rocblas_dgemm(h, ta, tb, m, n, last, &one, A + (size_t)(nsplit - 1) * sa, lda, B + (size_t)(nsplit - 1) * sb,
+                    ldb, &zero, scratch + (size_t)(nsplit - 1) * m * n, m) != rocblas_status_success) {
+    set_error("rocblas_dgemm (last split) failed");
+    return GPL_EHIP;
+  }
+  hipLaunchKernelGGL(split_sum_kernel, dim3(cdiv(m * n, 256)), dim3(256), 0, stream, m, n, nsplit, scratch, alpha,
+                     beta, C, ldc);
+  GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
 

@@ -21,4 +21,13 @@ constexpr size_t kBlasScratch = size_t(32) << 20;
 int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info,
                    hipStream_t stream);
 
+// C (m x n) = alpha op(A) op(B) + beta C with the reduction dimension kdim
+// split into nsplit parts (rocBLAS strided-batched products into scratch, then
+// a sum in split order): GEMMs with one short side use the whole device this
+// way. scratch: split_gemm_scratch(m, n, nsplit) bytes.
+size_t split_gemm_scratch(int m, int n, int nsplit);
+int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int kdim, int nsplit,
+               double alpha, const double* A, int lda, const double* B, int ldb, double beta, double* C, int ldc,
+               double* scratch, hipStream_t stream);
+
 }  // namespace gpl

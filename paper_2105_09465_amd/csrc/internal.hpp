@@ -142,7 +142,20 @@ int mvm_launch(double lengthscale, double amplitude, int n, const float* px, con
                int nrhs, const float* V, int ldv, float* Y, int ldy, float beta, int prec, void* ws, size_t ws_bytes,
                CgGate gate, hipStream_t stream);
 
-int check_kernel(const gpl_kernel* k);
+int check_kernel(const gpl_kernel* k);  // RBF only (kind 0)
+
+// Gaussian products with per-point shape covariances (csrc/gauss.hip).
+struct GSide {
+  const float *x, *y, *z, *w;  // z: SoA zxx[n], zxy[n], zyy[n] (nullable); w nullable
+  int n;
+};
+int gauss_product_launch(const GSide& T, const GSide& S, double base_var, double norm, int nrhs, const float* V,
+                         int ldv, float* Y, int ldy, float beta, hipStream_t stream);
+int pixel_shapes_launch(int M, const float* px, const float* py, float* z, hipStream_t stream);
+int check_kernel_any(const gpl_kernel* k);  // RBF or windowed (kind 1)
+int windowed_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px, const float* py, int nrhs,
+                 const float* V, int ldv, float* Y, int ldy, float beta, void* ws, size_t ws_bytes,
+                 hipStream_t stream);
 
 // Grouped launches of one CG iteration's kernels over the slots of a batch
 // (parity p selects the state buffers). Each returns GPL_OK or GPL_EHIP.

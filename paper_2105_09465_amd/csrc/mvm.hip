@@ -112,10 +112,50 @@ using namespace gpl;
 
 extern "C" size_t gpl_gp_kernel_mvm_workspace(int n, int nrhs, int prec) { return mvm_workspace(n, nrhs, prec); }
 
+namespace gpl {
+
+// The windowed kernel (kind 1) as a Gaussian product over the grid's points
+// with their pixel shapes, Z staged at the start of the workspace.
+int windowed_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px, const float* py, int nrhs,
+                 const float* V, int ldv, float* Y, int ldy, float beta, void* ws, size_t ws_bytes,
+                 hipStream_t stream) {
+  GPL_REQUIRE(grid != nullptr, "the windowed kernel (kind 1) needs the grid of the points");
+  GPL_REQUIRE((long)grid->n * grid->ss * grid->n * grid->ss == n, "grid does not match n=%d", n);
+  GPL_TRY(check_ws(ws, ws_bytes, (size_t)3 * n * sizeof(float)));
+  float* z = static_cast<float*>(ws);
+  GPL_TRY(pixel_shapes_launch(grid->n * grid->ss, px, py, z, stream));
+  const double l2 = kern->lengthscale * kern->lengthscale;
+  const GSide side{px, py, z, nullptr, n};
+  return gauss_product_launch(side, side, l2, kern->amplitude * kern->amplitude * l2, nrhs, V, ldv, Y, ldy, beta,
+                              stream);
+}
+
+int check_kernel_any(const gpl_kernel* k) {
+  GPL_REQUIRE(k != nullptr, "kernel is NULL");
+  GPL_REQUIRE(k->kind == 0 || k->kind == 1, "kernel kind %d not supported (0 = RBF, 1 = windowed)", k->kind);
+  GPL_REQUIRE(k->lengthscale > 0 && std::isfinite(k->lengthscale), "lengthscale must be > 0");
+  GPL_REQUIRE(std::isfinite(k->amplitude), "amplitude must be finite");
+  return GPL_OK;
+}
+
+}  // namespace gpl
+
 extern "C" int gpl_gp_kernel_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px,
                                  const float* py, int nrhs, const float* V, int ldv, float* Y, int ldy, float beta,
                                  int prec, void* ws, size_t ws_bytes, hipStream_t stream) {
-  GPL_TRY(check_kernel(kern));
+  GPL_TRY(check_kernel_any(kern));
+  if (kern->kind == 1) {
+    if (prec != GPL_PREC_FP32) {
+      set_error("the windowed kernel (kind 1) runs in the FP32 form only");
+      return GPL_EUNSUPPORTED;
+    }
+    GPL_REQUIRE(n >= 0 && nrhs >= 0 && nrhs <= 65535, "n=%d nrhs=%d out of range", n, nrhs);
+    if (n == 0 || nrhs == 0) return GPL_OK;
+    GPL_REQUIRE(px && py && V && Y, "NULL argument");
+    GPL_REQUIRE(ldv >= n && ldy >= n, "ldv=%d ldy=%d must be >= n=%d", ldv, ldy, n);
+    GPL_REQUIRE(V != Y, "V and Y must not overlap");
+    return windowed_mvm(kern, grid, n, px, py, nrhs, V, ldv, Y, ldy, beta, ws, ws_bytes, stream);
+  }
   GPL_REQUIRE(prec == GPL_PREC_FP32 || prec == GPL_PREC_F16X3, "unknown precision %d", prec);
   GPL_REQUIRE(n >= 0 && nrhs >= 0 && nrhs <= 65535, "n=%d nrhs=%d out of range", n, nrhs);
   if (n == 0 || nrhs == 0) return GPL_OK;

@@ -28,7 +28,8 @@
 
 namespace gpl {
 
-constexpr int kPcBlock = 64;         // pivots per block
+constexpr int kPcBlock = 64;   // pivots per block
+constexpr int kPcSplits = 16;  // most splits of the reduction of a product with the factor
 // A residual pivot below this share of the largest diagonal entry of M is not
 // taken: the columns of M come from FP32 products (relative error ~5e-7), so
 // smaller residuals are rounding noise, and at the workloads' noise level
@@ -225,21 +226,25 @@ __global__ void gather_rows_kernel(int j, const double* __restrict__ L, int ldl,
 // by one wave, lane a owning candidate a: each step takes the largest remaining
 // diagonal entry (lowest candidate index on ties) while it exceeds tol (a share
 // of the largest diagonal entry of M, dmax[0]), forms l = S[:, p] / sqrt(S[p][p])
-// and updates S -= l l^T in LDS; the l vectors go to lv (kPcBlock x kPcBlock,
-// global). Outputs order[0..kPcBlock) (taken candidates in pivot order first,
+// and updates S -= l l^T in LDS; the l vectors are kept in LDS too. Outputs order[0..kPcBlock) (taken candidates in pivot order first,
 // then the rest), *taken, and R (kPcBlock x kPcBlock, lower, R[u][v] = l of
 // step v at the u-th pivot; identity on the untaken part).
 __global__ __launch_bounds__(64) void block_pivot_kernel(const double* __restrict__ C, int npix, const int* cand,
-                                                         const double* dmax, double rel_tol, double* lv,
-                                                         int* order, int* taken, double* R) {
+                                                         const double* dmax, double rel_tol, int* order, int* taken,
+                                                         double* R) {
+  // everything in LDS (65 KB): a global store before each barrier would make
+  // every barrier wait for it
   __shared__ double S[kPcBlock][kPcBlock + 1];
+  __shared__ double lv[kPcBlock][kPcBlock];
   __shared__ double lcol[kPcBlock];
   __shared__ int s_perm[kPcBlock];
   const int a = threadIdx.x;
   const int ca = cand[a];
+  // S[b][a] holds entry (a, b) of the block: lane a walks its row along b at
+  // consecutive LDS addresses across the lanes (no bank conflicts)
   for (int b = 0; b < kPcBlock; ++b) {
     const int cb = cand[b];
-    S[a][b] = (ca >= 0 && cb >= 0) ? C[(size_t)b * npix + ca] : 0.0;
+    S[b][a] = (ca >= 0 && cb >= 0) ? C[(size_t)b * npix + ca] : 0.0;
   }
   bool used = ca < 0;
   const double tol = rel_tol * dmax[0];
@@ -260,13 +265,13 @@ __global__ __launch_bounds__(64) void block_pivot_kernel(const double* __restric
     const int p = idx;
     if (!(v > tol)) break;
     const double lpp = sqrt(v);
-    const double l = a == p ? lpp : (used ? 0.0 : S[a][p] / lpp);
+    const double l = a == p ? lpp : (used ? 0.0 : S[p][a] / lpp);
     lcol[a] = (a == p || used) ? 0.0 : l;
-    lv[(size_t)step * kPcBlock + a] = l;
+    lv[step][a] = l;
     if (a == 0) s_perm[step] = p;
     __syncthreads();
     if (!used && a != p)
-      for (int b = 0; b < kPcBlock; ++b) S[a][b] -= l * lcol[b];
+      for (int b = 0; b < kPcBlock; ++b) S[b][a] -= l * lcol[b];
     used = used || a == p;
     cnt = step + 1;
     __syncthreads();
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(64) void block_pivot_kernel(const double* __restric
   const int vcol = a;
   for (int u = 0; u < kPcBlock; ++u) {
     double val = 0.0;
-    if (u < cnt && vcol < cnt) val = vcol <= u ? lv[(size_t)vcol * kPcBlock + s_perm[u]] : 0.0;
+    if (u < cnt && vcol < cnt) val = vcol <= u ? lv[vcol][s_perm[u]] : 0.0;
     else if (u == vcol) val = 1.0;
     R[(size_t)vcol * kPcBlock + u] = val;
   }
@@ -370,7 +375,7 @@ __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, 
 
 struct PcBuf {
   float *E, *T1, *T2, *Mc;
-  double *C, *Lc, *R, *lv, *d, *dmax, *logd, *logdet_g;
+  double *C, *Lc, *R, *d, *dmax, *logd, *logdet_g, *split;
   int *cand, *order, *taken, *info, *is_piv;
   void* mvm_ws;
   size_t mvm_bytes;
@@ -387,7 +392,7 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.C = c.template take<double>((size_t)npix * kPcBlock);
   b.Lc = c.template take<double>((size_t)kPcBlock * std::max(k, 1));
   b.R = c.template take<double>((size_t)kPcBlock * kPcBlock);
-  b.lv = c.template take<double>((size_t)kPcBlock * kPcBlock);
+  b.split = c.template take<double>(split_gemm_scratch(npix, kPcBlock, kPcSplits) / sizeof(double));
   b.d = c.template take<double>(npix);
   b.dmax = c.template take<double>(1);
   b.logd = c.template take<double>(std::max(k, 1));
@@ -425,7 +430,7 @@ struct PcgState {
 
 struct PcgBuf {
   float *R, *P, *AP, *T2, *Z;
-  double *R64, *Z64, *W;
+  double *R64, *Z64, *W, *split;
   int ldv, ldf;
   void* mvm_ws;
   size_t mvm_bytes;
@@ -452,6 +457,9 @@ static void carve_pcg(Cv& c, int npix, int N, int n, int ss, int k, int nrhs, in
   b.R64 = c.template take<double>((size_t)b.ldv * nrhs);
   b.Z64 = c.template take<double>((size_t)b.ldv * nrhs);
   b.W = c.template take<double>((size_t)std::max(k, 1) * nrhs);
+  b.split = c.template take<double>(
+      std::max(split_gemm_scratch(nrhs, std::max(k, 1), kPcSplits), split_gemm_scratch(npix, nrhs, kPcSplits)) /
+      sizeof(double));
   b.mvm_bytes = mvm_workspace(N, nrhs, prec);
   b.mvm_ws = c.template take<char>(b.mvm_bytes);
   b.pap_part = c.template take<double>((size_t)b.ntiles * nrhs);
@@ -476,26 +484,24 @@ __global__ __launch_bounds__(256) void pcg_widen_kernel(int npix, const float* _
   Z64[(size_t)c * ldv + i] = v;
 }
 
-// P^{-1} R for every column, with the products in transposed form (the long
-// dimension n as the reduction of the first and the rows of the second):
-// Wt = R64^T L (m x k); Wt = Wt G^{-1} (two triangular solves with the factor
-// of G from the right; G is symmetric); Z64 = R64 - L Wt^T. The caller finishes
-// Z = Z64 / s.
+// P^{-1} R for every column: Wt = R64^T L (m x k); Wt = Wt G^{-1} (two
+// triangular solves with the factor of G from the right; G is symmetric);
+// Z64 = R64 - L Wt^T. Both products with L have one short side (m columns)
+// and run with their long reduction split. The caller finishes Z = Z64 / s.
 static int woodbury(rocblas_handle h, int npix, int k, const double* L, int ldl, const double* G, int ldg, int nrhs,
-                    const double* R64, double* Z64, int ldv, double* Wt) {
-  const double one = 1.0, zero = 0.0, minus_one = -1.0;
-  if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, nrhs, k, npix, &one, R64, ldv, L, ldl,
-                    &zero, Wt, nrhs) != rocblas_status_success ||
-      rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                    const double* R64, double* Z64, int ldv, double* Wt, double* split, hipStream_t stream) {
+  const double one = 1.0;
+  GPL_TRY(split_gemm(h, rocblas_operation_transpose, rocblas_operation_none, nrhs, k, npix, kPcSplits, 1.0, R64, ldv,
+                     L, ldl, 0.0, Wt, nrhs, split, stream));
+  if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                     rocblas_diagonal_non_unit, nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success ||
       rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit,
-                    nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success ||
-      rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, nrhs, k, &minus_one, L, ldl, Wt,
-                    nrhs, &one, Z64, ldv) != rocblas_status_success) {
-    set_error("rocBLAS call of the preconditioner failed");
+                    nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success) {
+    set_error("rocblas_dtrsm (preconditioner) failed");
     return GPL_EHIP;
   }
-  return GPL_OK;
+  return split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, nrhs, k, kPcSplits, -1.0, L, ldl, Wt,
+                    nrhs, 1.0, Z64, ldv, split, stream);
 }
 
 // Z = Z64 / s (FP32), partial r.z and (at init) partial |b|^2 and max |Z| per block.
@@ -883,13 +889,10 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
       hipLaunchKernelGGL(gather_rows_kernel, dim3(cdiv(kPcBlock * j0, 256)), dim3(256), 0, stream, j0, L, ldl, b.cand,
                          b.Lc);
       GPL_LAUNCH_CHECK();
-      if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, kPcBlock, j0, &minus_one, L,
-                        ldl, b.Lc, kPcBlock, &one, b.C, npix) != rocblas_status_success) {
-        set_error("rocblas_dgemm (residual columns) failed");
-        return GPL_EHIP;
-      }
+      GPL_TRY(split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, kPcBlock, j0,
+                         std::max(1, j0 / 256), -1.0, L, ldl, b.Lc, kPcBlock, 1.0, b.C, npix, b.split, stream));
     }
-    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64), 0, stream, b.C, npix, b.cand, b.dmax, kPcRelTol, b.lv,
+    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64), 0, stream, b.C, npix, b.cand, b.dmax, kPcRelTol,
                        b.order, b.taken, b.R);
     GPL_LAUNCH_CHECK();
     double* Lnew = L + (size_t)j0 * ldl;
@@ -1004,7 +1007,7 @@ extern "C" int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, in
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(pcg_widen_kernel, gv, dim3(256), 0, stream, npix, b.R, b.ldv, b.R64, b.Z64);
   GPL_LAUNCH_CHECK();
-  GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W));
+  GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, stream));
   hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z, b.rz_part,
                      nb, (const PcgState*)nullptr, (const int*)nullptr);
   GPL_LAUNCH_CHECK();
@@ -1031,7 +1034,7 @@ extern "C" int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, in
                          b.Z64, b.pap_part, b.ntiles, b.rr_part, nb, b.st[p], b.st[1 - p], b.n_active + p,
                          b.n_active + (1 - p));
       GPL_LAUNCH_CHECK();
-      GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W));
+      GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, stream));
       hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z,
                          b.rz_part, nb, (const PcgState*)b.st[p], (const int*)(b.n_active + p));
       GPL_LAUNCH_CHECK();

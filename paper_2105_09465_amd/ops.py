@@ -123,6 +123,42 @@ def kernel_mvm(kernel: Kernel, px, py, V, prec="fp32", out=None, beta=0.0, grid:
     return out[0] if (squeeze and out.dim() == 2) else out
 
 
+def gauss_product(base_var, norm, tx, ty, sx, sy, V, tz=None, tw=None, sz=None, sw=None, out=None, beta=0.0):
+    """Y[i] = beta Y[i] + norm wt_i sum_j ws_j |C_ij|^{-1/2} exp(-d^T C_ij^{-1} d / 2) V[j], C_ij = Zt_i + Zs_j +
+    base_var I, d = t_i - s_j: targets (tx, ty), sources (sx, sy); V (ncols, ns); shapes tz/sz as (3, n)
+    (zxx, zxy, zyy), weights tw/sw (n,), all float32 on the GPU."""
+    nt, ns = tx.numel(), sx.numel()
+    squeeze = V.dim() == 1
+    V2 = V.unsqueeze(0) if squeeze else V
+    ldv = _block(V2, ns, "V")
+    if out is None:
+        out = torch.zeros(V2.shape[0], nt, dtype=torch.float32, device=V.device)
+    out2 = out.unsqueeze(0) if out.dim() == 1 else out
+    ldy = _block(out2, nt, "Y")
+    g = _lib.gpl_gauss(float(base_var), float(norm))
+    for z, n in ((tz, nt), (sz, ns)):
+        if z is not None and (tuple(z.shape) != (3, n) or not z.is_contiguous()):
+            raise ValueError("shape covariances must be contiguous (3, n) tensors")
+    _lib.call("gpl_gauss_product", C.byref(g), nt, _ptr(tx), _ptr(ty), _ptr(tz), _ptr(tw), ns, _ptr(sx), _ptr(sy),
+              _ptr(sz), _ptr(sw), V2.shape[0], _ptr(V2), ldv, _ptr(out2), ldy, float(beta), _stream())
+    return out[0] if (squeeze and out.dim() == 2) else out
+
+
+def pixel_shapes(grid: Grid, px, py):
+    """Pixel-shape covariances (3, N): zxx, zxy, zyy of the ray-traced fine grid."""
+    z = torch.empty(3, grid.N, dtype=torch.float32, device=px.device)
+    g = grid.c()
+    _lib.call("gpl_pixel_shapes", C.byref(g), _ptr(px), _ptr(py), _ptr(z), _stream())
+    return z
+
+
+def knn_density(qx, qy, k=20):
+    """k-th closest neighbour density of the points (q_x, q_y)."""
+    rho = torch.empty(qx.numel(), dtype=torch.float32, device=qx.device)
+    _lib.call("gpl_knn_density", qx.numel(), _ptr(qx), _ptr(qy), int(k), _ptr(rho), _stream())
+    return rho
+
+
 def kernel_mvm_live_tiles(kernel: Kernel, px, py, prec="fp32", grid: Grid | None = None, with_lo=False):
     """Work of the product for these points: (64-point row tile, 32-point chunk)
     pairs visited and (16-point subtile, 32-point chunk) pairs evaluated (512

@@ -75,9 +75,10 @@ class Sersic:
 class Kernel:
     lengthscale: float
     amplitude: float
+    kind: int = 0  # 0: RBF (eq. "grbf"); 1: pixel-shape windowed kernel (eq. "covariance")
 
     def c(self):
-        return _lib.gpl_kernel(0, self.lengthscale, self.amplitude)
+        return _lib.gpl_kernel(self.kind, self.lengthscale, self.amplitude)
 
 
 @dataclasses.dataclass(frozen=True)
