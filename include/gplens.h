@@ -365,6 +365,18 @@ size_t gpl_lens_raytrace_backward_workspace(const gpl_grid* grid);
 int gpl_lens_raytrace_backward(const gpl_grid* grid, const gpl_lens* lens, const float* gpx, const float* gpy,
                                double* g_lens, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Allocation-free form of gpl_lens_raytrace_backward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same result
+ * (bitwise), with the partial sums in a static device array of 1 MiB that each
+ * device holds from its first call until the process ends. No workspace
+ * argument; nothing is allocated. Grids of more than 4,194,304 fine points
+ * ((n ss)^2) are rejected with GPL_EINVAL. Every call on one device shares that
+ * array and overwrites it completely before reading it, so calls that overlap
+ * in time on one device (different streams, several host threads) race. */
+int gpl_lens_raytrace_backward_noalloc(const gpl_grid* grid, const gpl_lens* lens, const float* gpx,
+                                       const float* gpy, double* g_lens, hipStream_t stream);
+
 /* Adjoint of the Sersic mean: gpx[i] += gmu[i] dmu_i/dpx, gpy[i] += gmu[i] dmu_i/dpy,
  * g_src[0..1] = d/d(xs, ys) of sum_i gmu[i] mu_i (FP64, overwritten). */
 size_t gpl_sersic_backward_workspace(int n);

@@ -102,6 +102,7 @@ SIGNATURES = {
                                         _P, _P, _Z, _P]),
     "gpl_lens_raytrace_backward_workspace": (_Z, [C.POINTER(gpl_grid)]),
     "gpl_lens_raytrace_backward": (_I, [C.POINTER(gpl_grid), C.POINTER(gpl_lens), _P, _P, _P, _P, _Z, _P]),
+    "gpl_lens_raytrace_backward_noalloc": (_I, [C.POINTER(gpl_grid), C.POINTER(gpl_lens), _P, _P, _P, _P]),
     "gpl_sersic_backward_workspace": (_Z, [_I]),
     "gpl_sersic_backward": (_I, [C.POINTER(gpl_source), _I, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "gpl_block_dot": (_I, [_I, _I, _P, _I, _P, _I, _P, _P]),

@@ -8,6 +8,7 @@
 // lens-frame deflection is rotated back by -phi. One thread per fine point;
 // the grid coordinates are generated in registers, never read from memory.
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 #include "dual.hpp"
@@ -210,6 +211,33 @@ static LensCore<float> lens_core_float(const gpl_lens* L) {
   return c;
 }
 
+// Scratch of the allocation-free adjoint: 8 partial sums per 256-point block,
+// for up to kNoAllocMaxBlocks blocks (grids of up to 4,194,304 fine points),
+// 1 MiB held by each device the library runs on until the process ends. Host
+// code uses it only through the device address recorded per device below.
+constexpr int kNoAllocMaxBlocks = 16384;
+static __device__ __align__(256) double scratch[kNoAllocMaxBlocks * 8];
+
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+static int scratch_address(double** out) {
+  int dev = 0;
+  GPL_HIP(hipGetDevice(&dev));
+  GPL_REQUIRE(dev >= 0 && dev < 64, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    GPL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    GPL_REQUIRE(ptr != nullptr, "no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return GPL_OK;
+}
+
 }  // namespace gpl
 
 using namespace gpl;
@@ -252,6 +280,26 @@ extern "C" int gpl_lens_raytrace_backward(const gpl_grid* grid, const gpl_lens* 
   const GridF g = make_grid(grid);
   const int N = g.M * g.M, nb = cdiv(N, 256);
   double* partial = static_cast<double*>(ws);
+  hipLaunchKernelGGL(raytrace_backward_kernel, dim3(nb), dim3(256), 0, stream, g, N, *lens, series_terms(lens->q),
+                     gpx, gpy, partial);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, stream, partial, nb, 8, g_lens);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+extern "C" int gpl_lens_raytrace_backward_noalloc(const gpl_grid* grid, const gpl_lens* lens, const float* gpx,
+                                                  const float* gpy, double* g_lens, hipStream_t stream) {
+  GPL_TRY(check_grid(grid));
+  GPL_TRY(check_lens(lens));
+  GPL_REQUIRE(gpx && gpy && g_lens, "gpx/gpy/g_lens are NULL");
+  const GridF g = make_grid(grid);
+  const int N = g.M * g.M, nb = cdiv(N, 256);
+  GPL_REQUIRE(nb <= kNoAllocMaxBlocks, "grid of %d fine points exceeds the %d the static scratch holds", N,
+              kNoAllocMaxBlocks * 256);
+  double* partial = nullptr;
+  GPL_TRY(scratch_address(&partial));
+  // every block writes its 8 partial sums before they are read: nothing to clear
   hipLaunchKernelGGL(raytrace_backward_kernel, dim3(nb), dim3(256), 0, stream, g, N, *lens, series_terms(lens->q),
                      gpx, gpy, partial);
   GPL_LAUNCH_CHECK();

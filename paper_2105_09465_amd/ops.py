@@ -364,6 +364,15 @@ def lens_raytrace_backward(grid: Grid, lens: Lens, gpx, gpy):
     return out
 
 
+def lens_raytrace_backward_noalloc(grid: Grid, lens: Lens, gpx, gpy, out):
+    """The adjoint into a caller-owned FP64 buffer of 8, with no allocation in
+    the library (its scratch is a static device array; calls on one device must
+    not overlap)."""
+    g, L = grid.c(), lens.c()
+    _lib.call("gpl_lens_raytrace_backward_noalloc", C.byref(g), C.byref(L), _ptr(gpx), _ptr(gpy), _ptr(out), _stream())
+    return out
+
+
 def sersic_backward(src: Sersic, px, py, gmu, gpx, gpy):
     n = px.numel()
     s = src.c()

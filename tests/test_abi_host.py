@@ -90,3 +90,14 @@ def test_workspace_sizes_monotone():
     assert a % 256 == 0
     assert L.lib.gpl_lanczos_logdet_workspace(16, 30) == 0  # the quadrature runs in LDS
     assert L.lib.gpl_gp_kernel_mvm_workspace(160000, 64, 1) > L.lib.gpl_gp_kernel_mvm_workspace(40000, 17, 1) > 0
+
+
+def test_noalloc_adjoint_size_limit_on_host():
+    """The allocation-free adjoint refuses grids beyond its static scratch
+    (4,194,304 fine points) before any device call."""
+    L = _lib()
+    p = C.c_void_p(16)  # never dereferenced: validation fails first
+    lens = L.gpl_lens(1.0, 0.8, 0.0, 2.0, 0.0, 0.0, 0.0, 0.0)
+    big = L.gpl_grid(2049, 1, 0.05, 0.0, 0.0)
+    assert L.lib.gpl_lens_raytrace_backward_noalloc(C.byref(big), C.byref(lens), p, p, p, None) == L.GPL_EINVAL
+    assert b"static scratch" in L.lib.gpl_last_error()
