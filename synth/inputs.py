@@ -179,6 +179,15 @@ def noise_normals(n_pix: int, index: int, sub: int = 0) -> np.ndarray:
     return _rng(index, _TAG_NOISE, sub).standard_normal(n_pix)
 
 
+def source_grid(n: int = 40, spacing: float = 0.03, cx: float = 0.0, cy: float = 0.0):
+    """Regular n x n grid of source-plane points (row-major, y increasing with
+    the row), `spacing` arcsec apart and centred on (cx, cy): the paper's
+    source-plane grid is 40 x 40 at 30 mas (Sec. 4.1). Returns (gx, gy) float64."""
+    o = (np.arange(n) - (n - 1) / 2.0) * spacing
+    gy, gx = np.meshgrid(o + cy, o + cx, indexing="ij")
+    return gx.ravel(), gy.ravel()
+
+
 SERVE_SIDES = (48, 64, 96, 128, 160)
 
 

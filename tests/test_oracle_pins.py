@@ -14,7 +14,7 @@ import scipy.integrate as si
 import scipy.stats as st
 
 import synth
-from oracle import data, evidence, gradients, grid, kernel, krylov, lens, precond, psf, source, window
+from oracle import data, evidence, gradients, grid, kernel, krylov, lens, posterior, precond, psf, source, window
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -644,3 +644,73 @@ def test_reconstruction_is_transmission_without_shapes():
     want = np.array([sum(A[k] * math.exp(-((x[i] - qx[k]) ** 2 + (y[i] - qy[k]) ** 2) / (2 * 0.0008)) /
                          (2 * math.pi * 0.0008) * yk[k] for k in range(40)) for i in range(30)])
     assert np.allclose(window.reconstruct_brightness(x, y, qx, qy, yk, 0.04, A), want, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- posterior at new points (f4)
+
+def _posterior_problem(n, ss, fwhm, theta_e=0.6, ell=0.04, peak=0.0):
+    return evidence.Problem(n, ss, 0.05, (theta_e, 0.8, 0.5, 2.0, 0.0, 0.0, 0.03, 0.0), (peak, 0.1, 1.5, 0.0, 0.0),
+                            ell, 0.3, 0.02, fwhm)
+
+
+def test_posterior_matches_sklearn_gp_regression():
+    """No PSF, no supersampling (B = I) and a zero mean: the posterior mean and
+    variance at new points are those of scikit-learn's Gaussian-process
+    regressor with the same fixed RBF kernel and noise (an independent
+    implementation of eqs. "gp-exact-mean" and "gp-exact-var")."""
+    from sklearn.gaussian_process import GaussianProcessRegressor
+    from sklearn.gaussian_process.kernels import RBF, ConstantKernel
+    P = _posterior_problem(8, 1, 0.0)
+    rng = np.random.default_rng(80)
+    d = 0.3 * rng.standard_normal(P.n_pix)
+    sol = evidence.solve_problem(P, d)
+    q = rng.uniform(-0.35, 0.35, (2, 25))
+    o = posterior.posterior_at(P, sol, q[0], q[1])
+    gp = GaussianProcessRegressor(ConstantKernel(P.amp ** 2, "fixed") * RBF(P.ell, "fixed"), alpha=P.sigma ** 2,
+                                  optimizer=None)
+    gp.fit(np.stack([sol["px"], sol["py"]], 1), d)
+    m, s = gp.predict(q.T, return_std=True)
+    assert np.max(np.abs(m - o["mean"])) <= 1e-12
+    assert np.max(np.abs(s * s - o["var"])) <= 1e-12
+    assert o["var"].min() < 0.5 * P.amp ** 2  # some query points are informed by the data
+
+
+def test_posterior_information_form_with_psf_and_supersampling():
+    """B = D o P (PSF, 2x2 supersampling) and a Sersic mean: the joint posterior
+    of the fluxes at the fitted points and the query points from the
+    information form Cov = (K_all^{-1} + H^T H / sigma^2)^{-1}, H = [B 0], mean
+    = mu_all + Cov H^T r / sigma^2 (Bayes' rule for a linear Gaussian model,
+    a different route from the Cholesky of A)."""
+    P = _posterior_problem(4, 2, 0.1, theta_e=0.02, ell=0.015, peak=0.2)
+    rng = np.random.default_rng(81)
+    d = 0.3 * rng.standard_normal(P.n_pix)
+    sol = evidence.solve_problem(P, d)
+    px, py = sol["px"], sol["py"]
+    q = np.array([[0.0125, -0.0375, 0.03], [0.0125, 0.0125, -0.06]])
+    o = posterior.posterior_at(P, sol, q[0], q[1])
+    ax, ay = np.concatenate([px, q[0]]), np.concatenate([py, q[1]])
+    Kall = kernel.rbf_matrix(ax, ay, P.ell, P.amp)
+    assert np.linalg.cond(Kall) < 1e8
+    Bm = psf.B_matrix(P.n, P.ss, P.taps())
+    H = np.hstack([Bm, np.zeros((P.n_pix, q.shape[1]))])
+    Lam = np.linalg.inv(Kall) + H.T @ H / P.sigma ** 2
+    Cov = np.linalg.inv(Lam)
+    mu_all = source.sersic(ax, ay, *P.src)
+    r = d - Bm @ mu_all[:px.size]
+    mean_all = mu_all + Cov @ H.T @ r / P.sigma ** 2
+    G = q.shape[1]
+    assert np.max(np.abs(mean_all[-G:] - o["mean"])) <= 1e-8 * np.max(np.abs(mean_all))
+    assert np.max(np.abs(np.diag(Cov)[-G:] - o["var"])) <= 1e-8 * P.amp ** 2
+
+
+def test_posterior_far_from_data_is_the_prior():
+    """Far from every fitted point (hundreds of lengthscales) the kernel
+    vanishes: the mean is the mean function and the variance is alpha^2."""
+    P = _posterior_problem(6, 2, 0.1, peak=0.5)
+    rng = np.random.default_rng(82)
+    d = 0.3 * rng.standard_normal(P.n_pix)
+    sol = evidence.solve_problem(P, d)
+    q = np.array([[20.0, -20.0], [20.0, 5.0]])
+    o = posterior.posterior_at(P, sol, q[0], q[1])
+    assert np.array_equal(o["var"], np.full(2, P.amp ** 2))
+    assert np.array_equal(o["mean"], source.sersic(q[0], q[1], *P.src))
