@@ -11,4 +11,4 @@ Each function cites the passage of Karchev, Coogan & Weniger (2021),
 processes", that it follows. Readings of passages the paper leaves open are
 stated where they are used.
 """
-from . import grid, lens, source, kernel, psf, evidence, krylov, precond, gradients, data, window, posterior  # noqa: F401,E501
+from . import grid, lens, source, kernel, psf, evidence, krylov, precond, gradients, data, window, posterior, vigp  # noqa: F401,E501

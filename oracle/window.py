@@ -124,6 +124,23 @@ def knn_density(qx, qy, k: int = 20):
     return rho
 
 
+def knn_radius(qx, qy, k: int = 20):
+    """(r_k, nn): distance from each point to its k-th closest other point and
+    that neighbour's index (brute force; the density of `knn_density` is
+    k / (pi r_k^2))."""
+    qx = np.asarray(qx, dtype=np.float64)
+    qy = np.asarray(qy, dtype=np.float64)
+    r = np.empty(qx.size)
+    nn = np.empty(qx.size, dtype=np.int64)
+    for s in range(0, qx.size, 1024):
+        d2 = (qx[s:s + 1024, None] - qx[None, :]) ** 2 + (qy[s:s + 1024, None] - qy[None, :]) ** 2
+        d2[np.arange(d2.shape[0]), np.arange(s, s + d2.shape[0])] = np.inf
+        idx = np.argsort(d2, axis=1, kind="stable")[:, k - 1]
+        nn[s:s + 1024] = idx
+        r[s:s + 1024] = np.sqrt(d2[np.arange(d2.shape[0]), idx])
+    return r, nn
+
+
 def transmission_weights(rho, ell):
     """A_k = |2 pi Sigma|^{1/4} / sqrt(rho_k) with Sigma = l^2 I (2-D)."""
     return math.sqrt(2.0 * math.pi * ell * ell) / np.sqrt(np.asarray(rho, dtype=np.float64))

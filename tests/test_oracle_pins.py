@@ -14,7 +14,8 @@ import scipy.integrate as si
 import scipy.stats as st
 
 import synth
-from oracle import data, evidence, gradients, grid, kernel, krylov, lens, posterior, precond, psf, source, window
+from oracle import (data, evidence, gradients, grid, kernel, krylov, lens, posterior, precond, psf, source, vigp,
+                    window)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -714,3 +715,132 @@ def test_posterior_far_from_data_is_the_prior():
     o = posterior.posterior_at(P, sol, q[0], q[1])
     assert np.array_equal(o["var"], np.full(2, P.amp ** 2))
     assert np.array_equal(o["mean"], source.sersic(q[0], q[1], *P.src))
+
+
+# ---------------------------------------------------------------- variational GP source (f2, f3)
+
+def _vigp_case(seed, n=6, ss=2, gn=8):
+    rng = np.random.default_rng(seed)
+    gx, gy = synth.source_grid(gn, 0.06)
+    m = vigp.Model(n, ss, 0.05, 2.0, (0.2, 0.1, 1.5, 0.01, -0.02), 0.02, 0.1,
+                   (("ip", 0.03), ("ip", 0.06), ("sp", 0.08)), gx, gy)
+    N, G = m.N, m.G
+    P = dict(lens_mean=np.array([0.6, 0.8, 0.5, 0.01, -0.02, 0.03, 0.01]) + 0.01 * rng.standard_normal(7),
+             lens_raw=np.tril(0.003 * rng.standard_normal((7, 7)), -1) + np.diag(np.log(0.01 * (1 + 0.1 * rng.random(7)))),
+             log_amp=np.log(np.array([0.02, 0.05, 0.2])),
+             sp_mean=0.05 * rng.standard_normal(G), sp_logs=np.log(0.01 * (1 + rng.random(G))),
+             sp_cross=0.01 * rng.standard_normal((G, 7)),
+             ip_mean=[0.01 * rng.standard_normal(N) for _ in range(2)],
+             ip_logs=[np.log(0.001 * (1 + rng.random(N))) for _ in range(2)])
+    eps = dict(e_l=rng.standard_normal(7), e_sp=rng.standard_normal(G), e_ip=[rng.standard_normal(N) for _ in range(2)])
+    d = 0.1 * rng.standard_normal(n * n) + 0.1
+    return m, P, eps, d
+
+
+def _perturbed(P, key, idx, h, li):
+    Q = {k: ([x.copy() for x in v] if isinstance(v, list) else v.copy()) for k, v in P.items()}
+    (Q[key][li] if li is not None else Q[key])[idx] += h
+    return Q
+
+
+def test_vigp_gradient_vs_finite_differences():
+    """The analytic ELBO gradient (through ray tracing, pixel shapes, k-NN
+    weights, both guide blocks and the amplitudes) against central differences
+    of the oracle's own ELBO sample (h = 1e-6)."""
+    m, P, eps, d = _vigp_case(0)
+    E, _, g = vigp.elbo(m, P, eps, d, want_grad=True)
+    assert np.isfinite(E)
+    rng = np.random.default_rng(1)
+    for key in ("lens_mean", "lens_raw", "log_amp", "sp_mean", "sp_logs", "sp_cross", "ip_mean", "ip_logs"):
+        for trial in range(3):
+            li = trial % 2 if key.startswith("ip_") else None
+            arr = P[key][li] if li is not None else P[key]
+            ga = g[key][li] if li is not None else g[key]
+            if key == "lens_raw":
+                a = int(rng.integers(0, 7))
+                idx = (a, int(rng.integers(0, a + 1)))
+            else:
+                idx = tuple(int(rng.integers(0, k)) for k in arr.shape)
+            h = 1e-6
+            fd = (vigp.elbo(m, _perturbed(P, key, idx, h, li), eps, d)[0]
+                  - vigp.elbo(m, _perturbed(P, key, idx, -h, li), eps, d)[0]) / (2 * h)
+            assert abs(fd - ga[idx]) <= 2e-6 * max(1.0, abs(ga[idx])), (key, idx, fd, ga[idx])
+    # every lens parameter, including x0, y0 (points near the lens centre)
+    for i in range(7):
+        h = 1e-6
+        fd = (vigp.elbo(m, _perturbed(P, "lens_mean", i, h, None), eps, d)[0]
+              - vigp.elbo(m, _perturbed(P, "lens_mean", i, -h, None), eps, d)[0]) / (2 * h)
+        assert abs(fd - g["lens_mean"][i]) <= 2e-6 * max(1.0, abs(g["lens_mean"][i])), (i, fd, g["lens_mean"][i])
+
+
+def test_vigp_sample_expectation_is_the_gaussian_elbo():
+    """With the lens noise fixed, the ELBO sample is a quadratic in the
+    source-parameter noise, so its mean over that noise follows exactly from
+    2n + 1 evaluations; it must equal the textbook Gaussian ELBO: the expected
+    log-likelihood of the linear model minus the KL divergence of the diagonal
+    guide from the prior."""
+    m, P, eps, d = _vigp_case(2, n=5, ss=1, gn=5)
+    e_l = eps["e_l"]
+    G, N = m.G, m.N
+
+    def sample(z):
+        e = dict(e_l=e_l, e_sp=z[:G], e_ip=[z[G:G + N], z[G + N:]])
+        return vigp.elbo(m, P, e, d)[0]
+
+    n = G + 2 * N
+    q0 = sample(np.zeros(n))
+    acc = q0
+    for j in range(n):
+        ej = np.zeros(n)
+        ej[j] = 1.0
+        acc += 0.5 * (sample(ej) + sample(-ej) - 2.0 * q0)
+    want = vigp.expected_elbo_fixed_lens(m, P, e_l, d)
+    assert abs(acc - want) <= 1e-9 * abs(want)
+
+
+def test_vigp_adam_matches_torch():
+    """Three Adam steps (torch's defaults, lr 1e-2) on changing gradients equal
+    torch.optim.Adam minimising -E."""
+    import torch
+    m, P, eps, d = _vigp_case(3)
+    rng = np.random.default_rng(4)
+    keys = ("lens_mean", "lens_raw", "sp_mean", "ip_mean")
+    params = {k: P[k] for k in keys}
+    state = vigp.adam_init(params)
+    tp = {k: ([torch.tensor(x, requires_grad=True) for x in v] if isinstance(v, list)
+              else torch.tensor(v, requires_grad=True)) for k, v in params.items()}
+    flat = [t for v in tp.values() for t in (v if isinstance(v, list) else [v])]
+    opt = torch.optim.Adam(flat, lr=1e-2)
+    for t in range(1, 4):
+        grads = {k: ([rng.standard_normal(x.shape) for x in v] if isinstance(v, list)
+                     else rng.standard_normal(v.shape)) for k, v in params.items()}
+        grads["lens_raw"] = np.tril(grads["lens_raw"])
+        params, state = vigp.adam_step(params, grads, state, t, 1e-2)
+        for k, v in tp.items():
+            for tv, gv in zip(v if isinstance(v, list) else [v], grads[k] if isinstance(v, list) else [grads[k]]):
+                tv.grad = torch.tensor(-gv)
+        opt.step()
+    for k, v in tp.items():
+        for tv, pv in zip(v if isinstance(v, list) else [v], params[k] if isinstance(v, list) else [params[k]]):
+            assert np.allclose(tv.detach().numpy(), pv, rtol=0, atol=1e-14)
+
+
+def test_pixel_axes_adjoint():
+    """axes_backward is the transpose of the linear map p -> (a, b):
+    <(a, b)(p), (ga, gb)> = <p, axes_backward(ga, gb)>."""
+    rng = np.random.default_rng(5)
+    for M in (1, 2, 3, 7):
+        p = rng.standard_normal((M * M, 2))
+        a, b = window.pixel_axes(p[:, 0], p[:, 1], M)
+        ga, gb = rng.standard_normal((2, M * M, 2))
+        lhs = np.sum(a * ga) + np.sum(b * gb)
+        rhs = np.sum(p * vigp.axes_backward(ga, gb, M))
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_knn_radius_matches_density():
+    rng = np.random.default_rng(6)
+    q = rng.uniform(-1, 1, (2, 300))
+    r, nn = window.knn_radius(q[0], q[1], 20)
+    assert np.allclose(20 / (math.pi * r * r), window.knn_density(q[0], q[1], 20), rtol=1e-12)
+    assert np.allclose(np.hypot(q[0] - q[0][nn], q[1] - q[1][nn]), r, rtol=1e-14)
