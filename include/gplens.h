@@ -193,9 +193,38 @@ int gpl_gauss_product(const gpl_gauss* g, int nt, const float* tx, const float* 
                       int ns, const float* sx, const float* sy, const float* sz, const float* sw, int nrhs,
                       const float* V, int ldv, float* Y, int ldy, float beta, hipStream_t stream);
 
+/* Adjoint of one column of gpl_gauss_product for sources without shape
+ * covariances: with F = sum_i U_i Y_i, Y = the product of V (one column, ns),
+ * accumulates (+=, FP32, device) the gradients gtx/gty (nt, nullable pair) of
+ * the target positions, gtz (3 x nt as for tz, nullable; needs tz) of the
+ * target shapes as the symmetric matrix gradient (entries xx, xy, yy of
+ * dF/dZ), gsx/gsy (ns, nullable pair) of the source positions and gsw (ns,
+ * nullable) of the source weights. The derivatives of the normal density:
+ * dN/dd = -N C^{-1} d, dN/dC = N (C^{-1} d d^T C^{-1} - C^{-1}) / 2. */
+int gpl_gauss_product_backward(const gpl_gauss* g, int nt, const float* tx, const float* ty, const float* tz,
+                               const float* tw, int ns, const float* sx, const float* sy, const float* sw,
+                               const float* V, const float* U, float* gtx, float* gty, float* gtz, float* gsx,
+                               float* gsy, float* gsw, hipStream_t stream);
+
+/* The same Gaussian entries as gpl_gauss_product written out as a dense
+ * nt x ns matrix M (column-major, ld ldm >= nt): M[j*ldm + i] = norm wt_i ws_j
+ * |C_ij|^{-1/2} exp(-d^T C_ij^{-1} d / 2). With the RBF parameters (norm =
+ * amplitude^2 lengthscale^2, base_var = lengthscale^2) and targets p, sources x,
+ * column j is K(p, x_j), the cross-covariance that the posterior variance at x_j
+ * (Sec. 3.7, eq. "gp-exact-var") needs. */
+int gpl_gauss_matrix(const gpl_gauss* g, int nt, const float* tx, const float* ty, const float* tz, const float* tw,
+                     int ns, const float* sx, const float* sy, const float* sz, const float* sw, float* M, int ldm,
+                     hipStream_t stream);
+
 /* Pixel shapes Z (three arrays of (n*ss)^2 floats: zxx, zxy, zyy) of the
  * ray-traced fine grid px, py (eq. "window-kernel", axes as for kind 1). */
 int gpl_pixel_shapes(const gpl_grid* grid, const float* px, const float* py, float* z, hipStream_t stream);
+
+/* Adjoint of gpl_pixel_shapes: gpx/gpy (+=) receive dF/dp from gz, the
+ * symmetric matrix gradient dF/dZ per point (3 arrays xx, xy, yy). Workspace:
+ * 16 (n ss)^2 bytes. */
+int gpl_pixel_shapes_backward(const gpl_grid* grid, const float* px, const float* py, const float* gz, float* gpx,
+                              float* gpy, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Density of the inducing points q for the transmission weights (Sec. 3.4,
  * footnote to eq. "transmission"): rho_i = k / (pi r_k^2), r_k the distance
@@ -323,6 +352,13 @@ int gpl_evidence_amplitude_grad(int n_pix, int n_points, int nprobe, const float
                                 const float* X, int ldx, const double* quad, double scale, double amplitude,
                                 double noise_sigma, double* out, hipStream_t stream);
 
+/* Posterior variance from solved columns (Sec. 3.7, eq. "gp-exact-var" with
+ * the observation operator): out[c] = prior - sum_i W[c*ldw + i] X[c*ldx + i]
+ * in FP64, c < ncols, i < n, for W = B K(p, x_c) and X = A^{-1} W; prior =
+ * k(x_c, x_c) (amplitude^2 for the RBF). */
+int gpl_posterior_variance(int n, int ncols, const float* W, int ldw, const float* X, int ldx, double prior,
+                           double* out, hipStream_t stream);
+
 /* Column-wise dot products in FP64: out[c] = sum_i X[c*ldx + i] * Y[c*ldy + i],
  * c < ncols, i < n. Used for quadratic forms and trace estimates
  * (z_j . A^{-1} z_j) of the evidence and its gradient. */
@@ -382,6 +418,77 @@ int gpl_lens_raytrace_backward_noalloc(const gpl_grid* grid, const gpl_lens* len
 size_t gpl_sersic_backward_workspace(int n);
 int gpl_sersic_backward(const gpl_source* src, int n, const float* px, const float* py, const float* gmu, float* gpx,
                         float* gpy, double* g_src, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- variational GP source
+ * The paper's fitting loop (Sec. 3.3-3.7, 4.2, 4.3): the source is a sum of
+ * GP layers written as transmission products (Sec. 3.3 eqs. "gp-gen2",
+ * "decomposition"; Sec. 3.4 eq. "transmission"):
+ *   f = mu(p) + sum_k T_k y_k,  T_k[i][j] = A_j N(p_i - q_j, Zt_i + l_k^2 I / 2),
+ *   A_j = sqrt(2 pi l_k^2) / sqrt(rho(q_j)),  rho = knn_k / (pi r^2),
+ * r the distance from q_j to its knn_k-th closest other inducing point. An
+ * image-plane layer (GPL_VIGP_IMAGE_PLANE) uses the traced points as inducing
+ * points (q = p) and their pixel shapes Zt (eq. "window-kernel"); the
+ * source-plane layer (GPL_VIGP_SOURCE_PLANE, at most one, Sec. 3.5) uses a
+ * fixed grid of G points and no shapes. Data d ~ N(B f, noise_sigma^2 I), prior
+ * y_k ~ N(0, alpha_k^2 I); lens prior: uniform boxes on theta_E, q, phi, x0, y0
+ * (prior_lo/hi) and N(0, shear_sd^2) on each shear component (Table
+ * "lens-params"). The slope, the Sersic mean and the noise are fixed.
+ *
+ * Guide (Sec. 4.2 eq. "guide", Table "gparams"): the 7 free lens parameters
+ * (theta_E, q, phi, x0, y0, gamma1, gamma2) and the source-plane parameters are
+ * jointly normal with scale [[L_l, 0], [C, diag(s_sp)]]; image-plane layers are
+ * diagonal normals; the amplitudes alpha_k are point estimates. Positive
+ * quantities are held as logarithms.
+ *
+ * Parameter blocks (device):
+ *   P64 (n64 = 56 + n_layers doubles): [0, 7) lens mean m_l; [7, 56) L_l raw,
+ *     row-major 7 x 7: entries below the diagonal as they are, diagonal entries
+ *     as ln L_l[a][a], entries above ignored; [56, 56 + n_layers) ln alpha_k.
+ *   P32 (n32 floats): the source-plane layer first (if any): m_sp (G), ln s_sp
+ *     (G), C (G x 7, column b at offset 2G + bG); then each image-plane layer
+ *     in layer order: m_k (N), ln s_k (N), N = (n ss)^2.
+ *   Noise of one sample (standard normals, drawn by the caller): e64 (7 doubles,
+ *     e_l) and e32 (ne32 floats: e_sp (G) first, then e_k (N) per image-plane
+ *     layer in layer order).
+ * gpl_vigp_elbo: one reparametrised sample (Sec. 3.6 eq. "reparam")
+ *   theta = m_l + L_l e_l, y_sp = m_sp + C e_l + s_sp e_sp, y_k = m_k + s_k e_k,
+ * and the ELBO sample (eq. "elbo") E = ln N(d | B f) + sum_k ln N(y_k | 0, alpha_k^2)
+ * + ln p(theta) - ln q(theta, y); out (device, 13 doubles): E, ln N(d | B f),
+ * sum_k ln p(y_k), ln p(theta) (-inf outside the boxes), -ln q, then the
+ * sampled 8-vector theta (gpl_lens order). G64 / G32 (device, shaped like
+ * P64 / P32) receive dE/dparameter (entries of L_l above the diagonal: 0),
+ * through the traced points, their pixel shapes and the k-NN weights of
+ * image-plane inducing points (each point's k-th neighbour held at its current
+ * index; its share is added with FP64 atomics, so the last FP32 bit of a
+ * gradient may vary between runs). All products are dense Gaussian products
+ * (every pair in FP32), FP64 sums for the scalars. */
+#define GPL_VIGP_IMAGE_PLANE 0
+#define GPL_VIGP_SOURCE_PLANE 1
+typedef struct {
+  int n_layers;              /* 1..8 */
+  int kind[8];               /* GPL_VIGP_IMAGE_PLANE or GPL_VIGP_SOURCE_PLANE */
+  double lengthscale[8];     /* l_k, arcsec */
+  int knn_k;                 /* neighbours of the density estimate (Sec. 3.4: 20), 1..32 */
+  double slope;              /* fixed SPLE slope */
+  double prior_lo[5], prior_hi[5]; /* boxes for theta_E, q, phi, x0, y0 */
+  double shear_sd;           /* prior standard deviation of gamma1, gamma2 */
+} gpl_vigp_model;
+int gpl_vigp_sizes(const gpl_vigp_model* model, const gpl_grid* grid, int G, size_t* n64, size_t* n32,
+                   size_t* ne32);
+size_t gpl_vigp_workspace(const gpl_vigp_model* model, const gpl_grid* grid, int G);
+int gpl_vigp_elbo(const gpl_vigp_model* model, const gpl_grid* grid, const gpl_psf* psf, const gpl_source* src,
+                  double noise_sigma, int G, const float* gx, const float* gy, const float* d, const double* P64,
+                  const float* P32, const double* e64, const float* e32, double* out, double* G64, float* G32,
+                  void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step (Sec. 4.3: torch's Adam; Kingma & Ba 2015) on both parameter
+ * blocks minimising -E, i.e. with loss gradient -G: m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * elementwise (FP64 for the P64 block, FP32 for P32); t >= 1 is the step
+ * number; M*, V* hold the moments (zero before the first step). */
+int gpl_vigp_adam(size_t n64, double* P64, const double* G64, double* M64, double* V64, size_t n32, float* P32,
+                  const float* G32, float* M32, float* V32, int t, double lr, double beta1, double beta2, double eps,
+                  hipStream_t stream);
 
 /* ---------------------------------------------------------------- serving
  * A continuous-batching request loop keeps every admitted reconstruction (a

@@ -127,15 +127,21 @@ def _layer_setup(model: Model, kind, ell, px, py, Z):
     return qx, qy, Zt, A, r, nn
 
 
-def elbo(model: Model, params, eps, d, want_grad: bool = False):
+def elbo(model: Model, params, eps, d, want_grad: bool = False, points=None):
     """Single-sample ELBO E (and, with want_grad, dE/d every parameter).
 
     Returns (E, pieces, grads) with pieces = dict(loglik, logprior_y,
-    logprior_theta, neg_logq) and grads a dict shaped like params."""
+    logprior_theta, neg_logq) and grads a dict shaped like params. `points`
+    (px, py), if given, replaces the traced points of the sampled lens (the
+    lens Jacobian is still that of the sampled lens): it lets a comparison
+    use another implementation's rounded points."""
     nl = len(model.layers)
     theta, L = lens_sample(model, params, eps["e_l"])
     xi_x, xi_y = grid.fine_coords(model.n, model.ss, model.pix_scale)
-    px, py = lensmod.raytrace(xi_x, xi_y, theta)
+    if points is None:
+        px, py = lensmod.raytrace(xi_x, xi_y, theta)
+    else:
+        px, py = (np.asarray(v, dtype=np.float64) for v in points)
     a, b = window.pixel_axes(px, py, model.M)
     Z = window.shape_cov(a, b)
     mu = source.sersic(px, py, *model.src)

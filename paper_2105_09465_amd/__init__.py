@@ -6,6 +6,6 @@ their adjoints, and a continuous-batching request loop.
 The computation lives in libgplens.so (C-ABI in include/gplens.h); this
 package binds it for torch tensors.
 """
-from . import _lib, autograd, ops, params, pipeline, serving  # noqa: F401
+from . import _lib, autograd, ops, params, pipeline, serving, vigp  # noqa: F401
 from .params import Grid, Kernel, Lens, Problem, PSF, Sersic  # noqa: F401
-from .pipeline import reconstruct, reconstruct_preconditioned  # noqa: F401
+from .pipeline import posterior_at, reconstruct, reconstruct_preconditioned  # noqa: F401

@@ -45,6 +45,12 @@ class gpl_gauss(C.Structure):
     _fields_ = [("base_var", C.c_double), ("norm", C.c_double)]
 
 
+class gpl_vigp_model(C.Structure):
+    _fields_ = [("n_layers", C.c_int), ("kind", C.c_int * 8), ("lengthscale", C.c_double * 8), ("knn_k", C.c_int),
+                ("slope", C.c_double), ("prior_lo", C.c_double * 5), ("prior_hi", C.c_double * 5),
+                ("shear_sd", C.c_double)]
+
+
 class gpl_psf(C.Structure):
     _fields_ = [("fwhm", C.c_double), ("radius", C.c_int)]
 
@@ -106,9 +112,20 @@ SIGNATURES = {
     "gpl_sersic_backward_workspace": (_Z, [_I]),
     "gpl_sersic_backward": (_I, [C.POINTER(gpl_source), _I, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "gpl_block_dot": (_I, [_I, _I, _P, _I, _P, _I, _P, _P]),
+    "gpl_posterior_variance": (_I, [_I, _I, _P, _I, _P, _I, _D, _P, _P]),
     "gpl_gauss_product": (_I, [C.POINTER(gpl_gauss), _I, _P, _P, _P, _P, _I, _P, _P, _P, _P, _I, _P, _I, _P, _I,
                                C.c_float, _P]),
+    "gpl_gauss_matrix": (_I, [C.POINTER(gpl_gauss), _I, _P, _P, _P, _P, _I, _P, _P, _P, _P, _P, _I, _P]),
     "gpl_pixel_shapes": (_I, [C.POINTER(gpl_grid), _P, _P, _P, _P]),
+    "gpl_gauss_product_backward": (_I, [C.POINTER(gpl_gauss), _I, _P, _P, _P, _P, _I, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        _P, _P, _P, _P]),
+    "gpl_pixel_shapes_backward": (_I, [C.POINTER(gpl_grid), _P, _P, _P, _P, _P, _P, _Z, _P]),
+    "gpl_vigp_sizes": (_I, [C.POINTER(gpl_vigp_model), C.POINTER(gpl_grid), _I, C.POINTER(_Z), C.POINTER(_Z),
+                            C.POINTER(_Z)]),
+    "gpl_vigp_workspace": (_Z, [C.POINTER(gpl_vigp_model), C.POINTER(gpl_grid), _I]),
+    "gpl_vigp_elbo": (_I, [C.POINTER(gpl_vigp_model), C.POINTER(gpl_grid), C.POINTER(gpl_psf), C.POINTER(gpl_source),
+                           _D, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
+    "gpl_vigp_adam": (_I, [_Z, _P, _P, _P, _P, _Z, _P, _P, _P, _P, _I, _D, _D, _D, _D, _P]),
     "gpl_knn_density": (_I, [_I, _P, _P, _I, _P, _P]),
     "gpl_evidence_amplitude_grad": (_I, [_I, _I, _I, _P, _P, _I, _P, _I, _P, _D, _D, _D, _P, _P]),
     "gpl_timing_enable": (_I, [_I]),

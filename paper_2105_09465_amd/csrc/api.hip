@@ -56,6 +56,18 @@ __global__ __launch_bounds__(256) void block_dot_kernel(int n, const float* __re
   if (threadIdx.x == 0) out[c] = s;
 }
 
+// out[c] = prior - sum_i W[c][i] X[c][i] (FP64, one workgroup per column).
+__global__ __launch_bounds__(256) void posterior_variance_kernel(int n, const float* __restrict__ W, int ldw,
+                                                                 const float* __restrict__ X, int ldx, double prior,
+                                                                 double* out) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += (double)W[(size_t)c * ldw + i] * (double)X[(size_t)c * ldx + i];
+  s = block_sum_double(s, red);
+  if (threadIdx.x == 0) out[c] = prior - s;
+}
+
 // Amplitude derivatives of ln p and of the App. D.1 loss. K is proportional to
 // alpha^2, so alpha dA/dalpha = 2 B K B^T = 2 (A - sigma^2 I) and
 //   alpha d ln p/d alpha = u^T B K B^T u - tr(A^{-1} B K B^T)
@@ -117,6 +129,18 @@ extern "C" int gpl_block_dot(int n, int ncols, const float* X, int ldx, const fl
   GPL_REQUIRE(X && Y && out, "NULL argument");
   GPL_REQUIRE(ldx >= n && ldy >= n, "ldx/ldy must be >= n");
   hipLaunchKernelGGL(block_dot_kernel, dim3(ncols), dim3(256), 0, stream, n, X, ldx, Y, ldy, out);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+extern "C" int gpl_posterior_variance(int n, int ncols, const float* W, int ldw, const float* X, int ldx,
+                                      double prior, double* out, hipStream_t stream) {
+  GPL_REQUIRE(n >= 0 && ncols >= 0, "negative size");
+  if (ncols == 0) return GPL_OK;
+  GPL_REQUIRE(W && X && out, "NULL argument");
+  GPL_REQUIRE(ldw >= n && ldx >= n, "ldw/ldx must be >= n");
+  GPL_REQUIRE(std::isfinite(prior), "prior variance must be finite");
+  hipLaunchKernelGGL(posterior_variance_kernel, dim3(ncols), dim3(256), 0, stream, n, W, ldw, X, ldx, prior, out);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

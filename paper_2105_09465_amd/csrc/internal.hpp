@@ -152,6 +152,20 @@ struct GSide {
 int gauss_product_launch(const GSide& T, const GSide& S, double base_var, double norm, int nrhs, const float* V,
                          int ldv, float* Y, int ldy, float beta, hipStream_t stream);
 int pixel_shapes_launch(int M, const float* px, const float* py, float* z, hipStream_t stream);
+int gauss_backward_launch(const GSide& T, const GSide& S, double base_var, double norm, const float* V, const float* U,
+                          float* gtx, float* gty, float* gtz, float* gsx, float* gsy, float* gsw, hipStream_t stream);
+int pixel_shapes_backward_launch(int M, const float* px, const float* py, const float* gz, float* gab, float* gpx,
+                                 float* gpy, hipStream_t stream);
+int knn_index_launch(int n, const float* qx, const float* qy, int k, float* rho, float* rk, int* nn,
+                     hipStream_t stream);
+int knn_weight_backward_launch(int n, const float* qx, const float* qy, const float* rk, const int* nn,
+                               const float* w, const float* gw, double* gq, float* gpx, float* gpy,
+                               hipStream_t stream);
+// Ray tracing and its adjoint with the 8 lens parameters in device memory.
+size_t raytrace_dev_backward_scratch(int N);
+int raytrace_dev_launch(const gpl_grid* grid, const double* lens, float* px, float* py, hipStream_t stream);
+int raytrace_dev_backward_launch(const gpl_grid* grid, const double* lens, const float* gpx, const float* gpy,
+                                 double* g_lens, double* scratch_partial, hipStream_t stream);
 int check_kernel_any(const gpl_kernel* k);  // RBF or windowed (kind 1)
 int windowed_mvm(const gpl_kernel* kern, const gpl_grid* grid, int n, const float* px, const float* py, int nrhs,
                  const float* V, int ldv, float* Y, int ldy, float beta, void* ws, size_t ws_bytes,

@@ -12,6 +12,7 @@
 
 #include "common.hpp"
 #include "dual.hpp"
+#include "internal.hpp"
 
 namespace gpl {
 
@@ -127,10 +128,8 @@ __global__ void grid_map_kernel(GridF g, int N, float* xi_x, float* xi_y, int* p
   if (pix) pix[j] = p;
 }
 
-__global__ void raytrace_kernel(GridF g, int N, LensCore<float> L, float g1, float g2, int nterms, float* px,
-                                float* py) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+__device__ inline void trace_point(const GridF& g, int j, const LensCore<float>& L, float g1, float g2, int nterms,
+                                   float* px, float* py) {
   float x, y;
   int p;
   fine_xy(g, j, x, y, p);
@@ -141,12 +140,67 @@ __global__ void raytrace_kernel(GridF g, int N, LensCore<float> L, float g1, flo
   py[j] = y - ay - sy;
 }
 
+__global__ void raytrace_kernel(GridF g, int N, LensCore<float> L, float g1, float g2, int nterms, float* px,
+                                float* py) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  trace_point(g, j, L, g1, g2, nterms, px, py);
+}
+
+// Lens parameters held in device memory (8 doubles in gpl_lens order), as a
+// sampled lens of the variational step keeps them: every thread derives the
+// constants itself. Parameters outside the lens model's range give non-finite
+// points, never an unbounded loop (the series length is capped).
+__device__ inline gpl_lens lens_from(const double* p) {
+  gpl_lens L;
+  L.theta_E = p[0];
+  L.q = p[1];
+  L.phi = p[2];
+  L.slope = p[3];
+  L.x0 = p[4];
+  L.y0 = p[5];
+  L.gamma1 = p[6];
+  L.gamma2 = p[7];
+  return L;
+}
+
+__device__ inline int series_terms_dev(double q) {
+  const double z = fabs((1.0 - q) / (1.0 + q));
+  if (!(z < 1.0)) return 512;
+  if (z < 1e-9) return 1;
+  const int K = (int)ceil(log(ldexp(1.0, -27) * (1.0 - z)) / log(z)) + 1;
+  return K < 1 ? 1 : (K > 512 ? 512 : K);
+}
+
+__device__ inline LensCore<float> lens_core_dev(const gpl_lens& L) {
+  LensCore<float> c;
+  c.cphi = (float)cos(L.phi);
+  c.sphi = (float)sin(L.phi);
+  c.sq = (float)sqrt(L.q);
+  c.isq = (float)(1.0 / sqrt(L.q));
+  c.pref = (float)(L.theta_E * 2.0 * sqrt(L.q) / (1.0 + L.q));
+  c.log2te = (float)log2(L.theta_E);
+  c.gm2 = (float)(L.slope - 2.0);
+  c.zmag = (float)((1.0 - L.q) / (1.0 + L.q));
+  c.b = (float)((L.slope - 1.0) / 2.0);
+  c.c = (float)((5.0 - L.slope) / 2.0);
+  c.x0 = (float)L.x0;
+  c.y0 = (float)L.y0;
+  return c;
+}
+
+__global__ void raytrace_dev_kernel(GridF g, int N, const double* __restrict__ lens, float* px, float* py) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const gpl_lens Lh = lens_from(lens);
+  trace_point(g, j, lens_core_dev(Lh), (float)Lh.gamma1, (float)Lh.gamma2, series_terms_dev(Lh.q), px, py);
+}
+
 // Adjoint: per point, dp/dtheta for (theta_E, q, phi, slope, x0, y0) by forward-mode
 // duals through sple_deflect; shear columns in closed form. Block partial sums in
 // FP64 go to `partial[block][8]`.
-__global__ __launch_bounds__(256) void raytrace_backward_kernel(GridF g, int N, gpl_lens Lh, int nterms,
-                                                                const float* gpx, const float* gpy,
-                                                                double* partial) {
+__device__ inline void raytrace_backward_body(const GridF& g, int N, const gpl_lens& Lh, int nterms,
+                                              const float* gpx, const float* gpy, double* partial) {
   using D6 = Dual<6>;
   __shared__ double red[4];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,6 +238,19 @@ __global__ __launch_bounds__(256) void raytrace_backward_kernel(GridF g, int N, 
     const double s = block_sum_double(acc[k], red);
     if (threadIdx.x == 0) partial[blockIdx.x * 8 + k] = s;
   }
+}
+
+__global__ __launch_bounds__(256) void raytrace_backward_kernel(GridF g, int N, gpl_lens Lh, int nterms,
+                                                                const float* gpx, const float* gpy,
+                                                                double* partial) {
+  raytrace_backward_body(g, N, Lh, nterms, gpx, gpy, partial);
+}
+
+__global__ __launch_bounds__(256) void raytrace_backward_dev_kernel(GridF g, int N, const double* __restrict__ lens,
+                                                                    const float* gpx, const float* gpy,
+                                                                    double* partial) {
+  const gpl_lens Lh = lens_from(lens);
+  raytrace_backward_body(g, N, Lh, series_terms_dev(Lh.q), gpx, gpy, partial);
 }
 
 __global__ void sum_partials_kernel(const double* partial, int nblocks, int width, double* out) {
@@ -235,6 +302,30 @@ static int scratch_address(double** out) {
     g_scratch_ptr[dev] = static_cast<double*>(ptr);
   }
   *out = g_scratch_ptr[dev];
+  return GPL_OK;
+}
+
+size_t raytrace_dev_backward_scratch(int N) { return align_up(sizeof(double) * 8 * (size_t)cdiv(N, 256)); }
+
+int raytrace_dev_launch(const gpl_grid* grid, const double* lens, float* px, float* py, hipStream_t stream) {
+  GPL_TRY(check_grid(grid));
+  const GridF g = make_grid(grid);
+  const int N = g.M * g.M;
+  hipLaunchKernelGGL(raytrace_dev_kernel, dim3(cdiv(N, 256)), dim3(256), 0, stream, g, N, lens, px, py);
+  GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int raytrace_dev_backward_launch(const gpl_grid* grid, const double* lens, const float* gpx, const float* gpy,
+                                 double* g_lens, double* scratch_partial, hipStream_t stream) {
+  GPL_TRY(check_grid(grid));
+  const GridF g = make_grid(grid);
+  const int N = g.M * g.M, nb = cdiv(N, 256);
+  hipLaunchKernelGGL(raytrace_backward_dev_kernel, dim3(nb), dim3(256), 0, stream, g, N, lens, gpx, gpy,
+                     scratch_partial);
+  GPL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, stream, scratch_partial, nb, 8, g_lens);
+  GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
 

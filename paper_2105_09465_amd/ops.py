@@ -144,6 +144,22 @@ def gauss_product(base_var, norm, tx, ty, sx, sy, V, tz=None, tw=None, sz=None, 
     return out[0] if (squeeze and out.dim() == 2) else out
 
 
+def gauss_matrix(base_var, norm, tx, ty, sx, sy, tz=None, tw=None, sz=None, sw=None, out=None):
+    """Dense Gaussian entries as a (ns, nt) float32 tensor: row j is column j of
+    the nt x ns matrix M_ij = norm wt_i ws_j |C_ij|^{-1/2} exp(-d^T C_ij^{-1} d / 2)."""
+    nt, ns = tx.numel(), sx.numel()
+    if out is None:
+        out = torch.empty(ns, nt, dtype=torch.float32, device=tx.device)
+    ldm = _block(out, nt, "M")
+    for z, n in ((tz, nt), (sz, ns)):
+        if z is not None and (tuple(z.shape) != (3, n) or not z.is_contiguous()):
+            raise ValueError("shape covariances must be contiguous (3, n) tensors")
+    g = _lib.gpl_gauss(float(base_var), float(norm))
+    _lib.call("gpl_gauss_matrix", C.byref(g), nt, _ptr(tx), _ptr(ty), _ptr(tz), _ptr(tw), ns, _ptr(sx), _ptr(sy),
+              _ptr(sz), _ptr(sw), _ptr(out), ldm, _stream())
+    return out
+
+
 def pixel_shapes(grid: Grid, px, py):
     """Pixel-shape covariances (3, N): zxx, zxy, zyy of the ray-traced fine grid."""
     z = torch.empty(3, grid.N, dtype=torch.float32, device=px.device)
@@ -330,6 +346,16 @@ def block_dot(X, Y):
     ldx, ldy = _block(X2, n, "X"), _block(Y2, n, "Y")
     out = torch.empty(X2.shape[0], dtype=torch.float64, device=X.device)
     _lib.call("gpl_block_dot", n, X2.shape[0], _ptr(X2), ldx, _ptr(Y2), ldy, _ptr(out), _stream())
+    return out
+
+
+def posterior_variance(W, X, prior):
+    """prior - W[c] . X[c] per column in FP64 (W, X as (ncols, n) blocks)."""
+    n = W.shape[-1]
+    ldw, ldx = _block(W, n, "W"), _block(X, n, "X")
+    out = torch.empty(W.shape[0], dtype=torch.float64, device=W.device)
+    _lib.call("gpl_posterior_variance", n, W.shape[0], _ptr(W), ldw, _ptr(X), ldx, float(prior), _ptr(out),
+              _stream())
     return out
 
 

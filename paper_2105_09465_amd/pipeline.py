@@ -115,3 +115,41 @@ def reconstruct_preconditioned(problem: Problem, d: torch.Tensor, g: torch.Tenso
         ops.kernel_mvm(problem.kernel, px, py, w, prec="fp32", out=fhat, beta=1.0, grid=gr)
         image = ops.psf_conv(gr, problem.psf, fhat, adjoint=False)
     return Reconstruction(px, py, mu, rhs, cg["X"], cg, logdet, stderr, contrib, scalars, fhat, image, pc)
+
+
+@dataclasses.dataclass
+class Posterior:
+    mean: torch.Tensor  # (G,) float32
+    var: torch.Tensor  # (G,) float64
+    W: torch.Tensor  # (G, n_pix): B K(p, x_g)
+    X: torch.Tensor  # (G, n_pix): A^{-1} W
+    cg: dict
+
+
+def posterior_at(problem: Problem, rec: Reconstruction, qx: torch.Tensor, qy: torch.Tensor, tol=1e-6,
+                 max_iter=None, prec=None, check_every=2, ws=None):
+    """Exact GP posterior mean and pointwise variance (Sec. 3.7, eqs.
+    "gp-exact-mean" and "gp-exact-var") at source-plane points q (float32 on
+    the GPU), from a finished reconstruction:
+        mean(x) = mu(x) + K(x, p) B^T u,   var(x) = alpha^2 - w_x^T A^{-1} w_x,
+    w_x = B K(p, x). The columns w_x are solved together, by preconditioned CG
+    with the reconstruction's preconditioner when it has one, else by CG."""
+    if problem.kernel.kind != 0:
+        raise ValueError("posterior_at supports the RBF kernel (kind 0)")
+    gr = problem.grid
+    ell, amp = problem.kernel.lengthscale, problem.kernel.amplitude
+    base, norm = ell * ell, amp * amp * ell * ell
+    w = ops.psf_conv(gr, problem.psf, rec.X[0], adjoint=True)  # B^T u
+    mean = ops.sersic_eval(problem.source, qx, qy)
+    ops.gauss_product(base, norm, qx, qy, rec.px, rec.py, w, out=mean, beta=1.0)
+    Kpq = ops.gauss_matrix(base, norm, rec.px, rec.py, qx, qy)  # (G, N): row g = K(p, x_g)
+    W = ops.psf_conv(gr, problem.psf, Kpq, adjoint=False)  # (G, n_pix)
+    del Kpq
+    if rec.precond is not None:
+        cg = ops.pcg_solve(problem, rec.px, rec.py, rec.precond, W, tol=tol, max_iter=max_iter or 200, n_lanczos=0,
+                           prec=prec or "f16x3", check_every=check_every, ws=ws)
+    else:
+        cg = ops.cg_solve(problem, rec.px, rec.py, W, tol=tol, max_iter=max_iter or 1000, n_lanczos=0,
+                          prec=prec or "fp32", check_every=max(check_every, 1), ws=ws)
+    var = ops.posterior_variance(W, cg["X"], amp * amp)
+    return Posterior(mean, var, W, cg["X"], cg)

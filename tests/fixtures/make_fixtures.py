@@ -3,7 +3,9 @@
 Runs only the FP64 oracle (and synth for the seeded draws). For the 100x100
 image with 2x2 supersampling (N = 40,000 source points, the first prior draw of
 that workload) it stores the simulated observation d, the exact Cholesky
-evidence terms, the variational objective and the predicted image.
+evidence terms, the variational objective, the predicted image, and the exact
+posterior mean and variance on the 40 x 40 source-plane grid at 30 mas centred
+on the origin.
 
     python tests/fixtures/make_fixtures.py
 """
@@ -17,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth  # noqa: E402
-from oracle import data, evidence  # noqa: E402
+from oracle import data, evidence, posterior  # noqa: E402
 
 
 def make(index=1, sub=0):
@@ -28,14 +30,17 @@ def make(index=1, sub=0):
     t = time.time()
     d, _ = data.simulate(P, synth.noise_normals(w.n_pix, index, sub), rff=synth.rff_draws(8192, index, sub))
     out = evidence.solve_problem(P, d)
+    gx, gy = synth.source_grid(40, 0.03)
+    post = posterior.posterior_at(P, out, gx, gy)
     path = os.path.join(HERE, f"workload{index}_draw{sub}.npz")
     np.savez_compressed(path, d=d, image=out["image"], lnp=out["lnp"], quad=out["quad"], logdet=out["logdet"],
                         vi=out["vi"], lens=np.array(w.lens.as_tuple()), source=np.array([s.peak, s.R_e, s.n_sersic,
                                                                                          s.xs, s.ys]),
                         n=w.n, ss=w.ss, pix_scale=w.pix_scale, ell=w.ell, amp=w.amp, sigma=w.noise_sigma,
-                        fwhm=w.psf_fwhm)
+                        fwhm=w.psf_fwhm, grid_n=40, grid_spacing=0.03, grid_mean=post["mean"],
+                        grid_var=post["var"])
     print(f"{path}: lnp {out['lnp']:.6f} quad {out['quad']:.6f} logdet {out['logdet']:.6f} "
-          f"({time.time() - t:.0f} s)")
+          f"var [{post['var'].min():.3e}, {post['var'].max():.3e}] ({time.time() - t:.0f} s)")
 
 
 if __name__ == "__main__":
