@@ -14,8 +14,10 @@ the kernel values the step's products evaluate (pairs below the 2^-36 cutoff
 are not evaluated), over the step time; the dense equivalent (N^2 pairs per
 product) is reported beside it. Extra fields: reconstructions/s of both
 arithmetic forms, the roofline of the dominant kernel and of the FP32 form's
-product, the serving trace, and the FP64 oracle timed on the host as a
-baseline.
+product, the preconditioned step, the exact posterior on a 40 x 40
+source-plane grid, the variational GP source fit (Adam steps) with the
+roofline of its transmission product, the serving trace, and the FP64 oracle
+timed on the host as a baseline.
 
     python bench.py [--steps K] [--warmup W] [--prec f16x3|fp32]
 """
@@ -284,6 +286,97 @@ def product_alone(G, torch, prob, px, py, nrhs, prec, reps=10):
     return ms / max(n, 1)
 
 
+# Variational GP source fit at the same workload: two image-plane layers on the
+# traced points and a source-plane layer on a 40 x 40 grid at 30 mas (Sec. 3.5,
+# Sec. 4.1), lengthscales in arcsec.
+VIGP_LAYERS = (("ip", 0.01), ("ip", 0.04), ("sp", 0.04))
+# FP32 slots per pair of a one-column transmission product with shapes on one
+# side: 2 differences, 6 for u = C^{-1} d and q = d.u, 1 scale, exp2 at a quarter
+# rate (4), 1 weight, 1 accumulate.
+GAUSS_PAIR_COST = 2 + 6 + 1 + 4 + 1 + 1
+GAUSS_PEAK_GPAIRS = VALU_LANE_OPS / GAUSS_PAIR_COST / 1e9
+
+
+def vigp_section(G, torch, synth, prob, d, steps, lens):
+    """Timed Adam steps of the variational fit (ELBO sample, gradient, update),
+    and the dense transmission product alone with its ALU roofline."""
+    import numpy as np
+    gx, gy = synth.source_grid(40, 0.03)
+    gxd = torch.as_tensor(gx, dtype=torch.float32, device="cuda")
+    gyd = torch.as_tensor(gy, dtype=torch.float32, device="cuda")
+    v = G.vigp.Vigp(G.vigp.VigpModel(VIGP_LAYERS, lens[3]), prob, d, gxd, gyd)
+    v.lens_mean.copy_(torch.as_tensor(np.asarray(lens)[[0, 1, 2, 4, 5, 6, 7]]))
+    v.lens_raw.copy_(torch.diag(torch.full((7,), math.log(0.01), dtype=torch.float64)))
+    v.log_amp.copy_(torch.log(torch.tensor([prob.noise_sigma, prob.noise_sigma, 10 * prob.noise_sigma],
+                                           dtype=torch.float64)))
+    v.sp["logs"].fill_(math.log(0.01))
+    for blk in v.ip:
+        blk["logs"].fill_(math.log(0.001))
+    noise = []
+    for t in range(steps + 2):
+        a, b = synth.vigp_normals(v.ne32, t)
+        noise.append((torch.as_tensor(a, device="cuda"), torch.as_tensor(b, dtype=torch.float32, device="cuda")))
+    for e64, e32 in noise[:2]:  # warmup
+        v.step(e64, e32, 1e-3)
+    torch.cuda.synchronize()
+    elbos = []
+    t0 = time.perf_counter()
+    for e64, e32 in noise[2:]:
+        elbos.append(v.step(e64, e32, 1e-3)[0].clone())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    elbos = [float(x.item()) for x in elbos]
+    # the image-plane layer's product alone: N targets with shapes, N weighted sources, one column
+    N = prob.grid.N
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    z = G.ops.pixel_shapes(prob.grid, pts[0], pts[1])
+    w = G.ops.knn_density(pts[0], pts[1], 20).rsqrt()
+    y = torch.randn(N, device="cuda")
+    out = torch.empty(N, device="cuda")
+    ell = VIGP_LAYERS[0][1]
+    args_ = (0.5 * ell * ell, math.sqrt(2 * math.pi * ell * ell) / (2 * math.pi), pts[0], pts[1], pts[0], pts[1], y)
+    G.ops.gauss_product(*args_, tz=z, sw=w, out=out)
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        G.ops.gauss_product(*args_, tz=z, sw=w, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    g_ms = e0.elapsed_time(e1) / reps
+    achieved = N * N / (g_ms * 1e-3) / 1e9
+    return {"layers": [list(x) for x in VIGP_LAYERS], "grid": "40x40 at 30 mas", "steps": steps,
+            "ms_per_step": el / steps * 1e3, "steps_per_s": steps / el, "lr": 1e-3,
+            "elbo_first": elbos[0], "elbo_last": elbos[-1],
+            "roofline": {"kernel": "gauss_product_kernel (image-plane layer, 1 column)", "bound": "alu",
+                         "unit": "Gpairs/s", "achieved": achieved, "peak": GAUSS_PEAK_GPAIRS,
+                         "frac": achieved / GAUSS_PEAK_GPAIRS, "pairs_per_launch": N * N,
+                         "avg_launch_ms_alone": g_ms}}
+
+
+def posterior_section(G, torch, synth, prob, rec, z):
+    """Exact posterior mean and variance on the 40 x 40 source-plane grid from
+    the preconditioned reconstruction, against the stored FP64 oracle."""
+    import numpy as np
+    gx, gy = synth.source_grid(int(z["grid_n"]), float(z["grid_spacing"]))
+    gxd = torch.as_tensor(gx, dtype=torch.float32, device="cuda")
+    gyd = torch.as_tensor(gy, dtype=torch.float32, device="cuda")
+    G.posterior_at(prob, rec, gxd, gyd)  # warmup
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        post = G.posterior_at(prob, rec, gxd, gyd)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    var = post.var.cpu().numpy()
+    mean = post.mean.double().cpu().numpy()
+    return {"points": int(gx.size), "ms": el * 1e3, "pcg_iters": int(post.cg["iters"].max().item()),
+            "var_max_abs_err_vs_oracle": float(np.max(np.abs(var - z["grid_var"]))),
+            "mean_max_abs_err_vs_oracle": float(np.max(np.abs(mean - z["grid_mean"]))),
+            "var_range_oracle": [float(z["grid_var"].min()), float(z["grid_var"].max())]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +395,8 @@ def main():
     ap.add_argument("--gradient-only", type=int, default=0,
                     help="time ray tracing and this many evaluations of the evidence gradients at the bench shape, "
                          "print one JSON line and exit")
+    ap.add_argument("--vigp-steps", type=int, default=10,
+                    help="timed steps of the variational GP source fit (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving trace (0: skip)")
     ap.add_argument("--serve-only", action="store_true",
@@ -425,6 +520,14 @@ def main():
                  "quad_rel_err_vs_oracle": abs(hp["quad"] - float(z["quad"])) / float(z["quad"]),
                  "true_relres_max": max(hp["true_relres"])}
 
+    post = None
+    if pcsec is not None:
+        post = posterior_section(G, torch, synth, prob, rpc, z)
+
+    vsec = None
+    if args.vigp_steps > 0:
+        vsec = vigp_section(G, torch, synth, prob, d, args.vigp_steps, prob.lens.as_tuple())
+
     # ---- plain FP32 form, same step, and its product's own roofline
     plain = None
     if args.plain_steps > 0 and args.prec != "fp32":
@@ -501,6 +604,8 @@ def main():
                      "mfma_flop_per_launch": mfma_flop,
                      "mfma_tflops_executed": mfma_flop / (avg_ms * 1e-3) / 1e12},
         "preconditioned": pcsec,
+        "posterior_grid": post,
+        "vigp": vsec,
         "plain_fp32": plain,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -228,8 +228,13 @@ int gpl_pixel_shapes_backward(const gpl_grid* grid, const float* px, const float
 
 /* Density of the inducing points q for the transmission weights (Sec. 3.4,
  * footnote to eq. "transmission"): rho_i = k / (pi r_k^2), r_k the distance
- * from q_i to its k-th closest other point (1 <= k <= 32, n > k); brute force. */
-int gpl_knn_density(int n, const float* qx, const float* qy, int k, float* rho, hipStream_t stream);
+ * from q_i to its k-th closest other point (1 <= k <= 32, n > k; squared
+ * distances ranked in FP32, equal ones by the lower index). The points are
+ * sorted along a Hilbert curve in the workspace and only 32-point chunks whose
+ * bounding box lies within reach are visited. n <= 2,097,120. */
+size_t gpl_knn_density_workspace(int n);
+int gpl_knn_density(int n, const float* qx, const float* qy, int k, float* rho, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
 
 /* Y = A X with A = B K B^T + noise_sigma^2 I (image pixels, nrhs columns). */
 size_t gpl_apply_A_workspace(const gpl_problem* prob, int nrhs, int prec);

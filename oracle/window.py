@@ -124,20 +124,22 @@ def knn_density(qx, qy, k: int = 20):
     return rho
 
 
-def knn_radius(qx, qy, k: int = 20):
-    """(r_k, nn): distance from each point to its k-th closest other point and
-    that neighbour's index (brute force; the density of `knn_density` is
-    k / (pi r_k^2))."""
+def knn_radius(qx, qy, k: int = 20, rows=None):
+    """(r_k, nn): distance from each point (or each point of `rows`) to its
+    k-th closest other point and that neighbour's index (brute force; the
+    density of `knn_density` is k / (pi r_k^2))."""
     qx = np.asarray(qx, dtype=np.float64)
     qy = np.asarray(qy, dtype=np.float64)
-    r = np.empty(qx.size)
-    nn = np.empty(qx.size, dtype=np.int64)
-    for s in range(0, qx.size, 1024):
-        d2 = (qx[s:s + 1024, None] - qx[None, :]) ** 2 + (qy[s:s + 1024, None] - qy[None, :]) ** 2
-        d2[np.arange(d2.shape[0]), np.arange(s, s + d2.shape[0])] = np.inf
+    rows = np.arange(qx.size) if rows is None else np.asarray(rows)
+    r = np.empty(rows.size)
+    nn = np.empty(rows.size, dtype=np.int64)
+    for s in range(0, rows.size, 1024):
+        rr = rows[s:s + 1024]
+        d2 = (qx[rr, None] - qx[None, :]) ** 2 + (qy[rr, None] - qy[None, :]) ** 2
+        d2[np.arange(rr.size), rr] = np.inf
         idx = np.argsort(d2, axis=1, kind="stable")[:, k - 1]
         nn[s:s + 1024] = idx
-        r[s:s + 1024] = np.sqrt(d2[np.arange(d2.shape[0]), idx])
+        r[s:s + 1024] = np.sqrt(d2[np.arange(rr.size), idx])
     return r, nn
 
 

@@ -126,7 +126,8 @@ SIGNATURES = {
     "gpl_vigp_elbo": (_I, [C.POINTER(gpl_vigp_model), C.POINTER(gpl_grid), C.POINTER(gpl_psf), C.POINTER(gpl_source),
                            _D, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _Z, _P]),
     "gpl_vigp_adam": (_I, [_Z, _P, _P, _P, _P, _Z, _P, _P, _P, _P, _I, _D, _D, _D, _D, _P]),
-    "gpl_knn_density": (_I, [_I, _P, _P, _I, _P, _P]),
+    "gpl_knn_density_workspace": (_Z, [_I]),
+    "gpl_knn_density": (_I, [_I, _P, _P, _I, _P, _P, _Z, _P]),
     "gpl_evidence_amplitude_grad": (_I, [_I, _I, _I, _P, _P, _I, _P, _I, _P, _D, _D, _D, _P, _P]),
     "gpl_timing_enable": (_I, [_I]),
     "gpl_serve_slot_workspace": (_Z, [C.POINTER(gpl_grid), _I, _I, _I]),

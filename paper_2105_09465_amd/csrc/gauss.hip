@@ -5,10 +5,13 @@
 //   Y[i][c] = beta Y[i][c] + norm * wt_i * sum_j ws_j |C_ij|^{-1/2} exp(-d^T C_ij^{-1} d / 2) V[j][c],
 //   d = t_i - s_j,  C_ij = Zt_i + Zs_j + base_var I  (2 x 2),
 // over target points t and source points s, each optionally with a shape
-// covariance Z (three floats: xx, xy, yy) and a weight w. One thread per target,
-// 256 targets per workgroup; source tiles of 256 points and their right-hand
-// side rows are staged in LDS; the exp tile is evaluated in FP32 on the fly and
-// never stored. Dense over all pairs (every pair is evaluated).
+// covariance Z (three floats: xx, xy, yy) and a weight w. A workgroup owns 64
+// targets (one per lane) and runs 8 waves, each over its own eighth of the
+// sources, staged 64 at a time in that wave's share of LDS with their
+// right-hand-side rows; the 8 partial sums are added in wave order at the end
+// (deterministic, and 8 waves per 64 targets fill the chip at tens of thousands
+// of points). The Gaussian entries are evaluated in FP32 on the fly and never
+// stored. Dense over all pairs (every pair is evaluated).
 #include <cmath>
 
 #include "common.hpp"
@@ -16,7 +19,9 @@
 
 namespace gpl {
 
-constexpr int kGTile = 256;  // sources per LDS tile = targets per workgroup
+constexpr int kGRows = 64;   // targets per workgroup (one per lane)
+constexpr int kGWaves = 8;   // waves per workgroup, each over its own share of the sources
+constexpr int kGThreads = kGRows * kGWaves;
 constexpr int kGCols = 8;    // right-hand-side columns per pass
 
 // |C|^{-1/2} exp(-d^T C^{-1} d / 2) for the 2 x 2 covariance (cxx, cxy; cxy, cyy).
@@ -26,42 +31,96 @@ __device__ inline float gauss_pair(float dx, float dy, float cxx, float cxy, flo
   return rsqrtf(det) * exp2_fast(-0.5f * 1.4426950408889634f * q);
 }
 
-__global__ __launch_bounds__(kGTile) void gauss_product_kernel(GSide T, GSide S, float base, float norm, int nc,
-                                                               const float* __restrict__ V, int ldv, float* Y,
-                                                               int ldy, float beta) {
-  __shared__ float sx[kGTile], sy[kGTile], sxx[kGTile], sxy[kGTile], syy[kGTile], sw[kGTile];
-  __shared__ float sv[kGCols][kGTile];
-  const int i = blockIdx.x * kGTile + threadIdx.x;
+// 64-point steps of each wave's share of n points: every wave runs the same
+// number of steps (so the workgroup barriers are uniform); steps past the end
+// are empty.
+__device__ inline int wave_steps(int n) { return cdiv(cdiv(n, 64), kGWaves); }
+
+// Shapes on at most one side (kMode 1: targets, or none; kMode 2: sources)
+// make C_ij a per-point constant whose inverse and determinant are formed once
+// per point; kMode 0 (shapes on both sides, the windowed kernel) forms them per
+// pair. NC: right-hand-side columns held per pass (1 or kGCols).
+template <int kMode, int NC>
+__global__ __launch_bounds__(kGThreads) void gauss_product_kernel(GSide T, GSide S, float base, float norm, int nc,
+                                                                  const float* __restrict__ V, int ldv, float* Y,
+                                                                  int ldy, float beta) {
+  // per source: x, y, then (kMode 0) zxx, zxy, zyy and w, or (kMode 2) the
+  // inverse ixx, ixy, iyy and w |C|^{-1/2}, or (kMode 1) w
+  __shared__ float sx[kGWaves][64], sy[kGWaves][64], sa[kGWaves][64], sb[kGWaves][64], sc[kGWaves][64],
+      sw[kGWaves][64];
+  __shared__ float sv[kGWaves][NC][64];
+  __shared__ float red[kGWaves - 1][NC][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * kGRows + lane;
   const bool live = i < T.n;
   const float xi = live ? T.x[i] : 0.f, yi = live ? T.y[i] : 0.f;
   const float txx = (live && T.z) ? T.z[i] : 0.f, txy = (live && T.z) ? T.z[T.n + i] : 0.f,
               tyy = (live && T.z) ? T.z[2 * T.n + i] : 0.f;
-  float acc[kGCols];
+  float ixx = 0.f, ixy = 0.f, iyy = 0.f, rdet = 1.f;
+  if (kMode == 1) {
+    const float cxx = txx + base, cxy = txy, cyy = tyy + base;
+    const float det = fmaf(cxx, cyy, -cxy * cxy), idet = 1.f / det;
+    ixx = cyy * idet;
+    ixy = -cxy * idet;
+    iyy = cxx * idet;
+    rdet = rsqrtf(det);
+  }
+  const float kq = -0.5f * 1.4426950408889634f;
+  float acc[NC];
 #pragma unroll
-  for (int c = 0; c < kGCols; ++c) acc[c] = 0.f;
-  for (int j0 = 0; j0 < S.n; j0 += kGTile) {
+  for (int c = 0; c < NC; ++c) acc[c] = 0.f;
+  const int steps = wave_steps(S.n);
+  for (int st = 0; st < steps; ++st) {
+    const int j0 = (wv * steps + st) * 64;
     __syncthreads();
-    const int j = j0 + threadIdx.x;
+    const int j = j0 + lane;
     const bool sj = j < S.n;
-    sx[threadIdx.x] = sj ? S.x[j] : 0.f;
-    sy[threadIdx.x] = sj ? S.y[j] : 0.f;
-    sxx[threadIdx.x] = (sj && S.z) ? S.z[j] : 0.f;
-    sxy[threadIdx.x] = (sj && S.z) ? S.z[S.n + j] : 0.f;
-    syy[threadIdx.x] = (sj && S.z) ? S.z[2 * S.n + j] : 0.f;
-    sw[threadIdx.x] = sj ? (S.w ? S.w[j] : 1.f) : 0.f;
+    const float zxx = (sj && S.z) ? S.z[j] : 0.f, zxy = (sj && S.z) ? S.z[S.n + j] : 0.f,
+                zyy = (sj && S.z) ? S.z[2 * S.n + j] : 0.f;
+    const float wj = sj ? (S.w ? S.w[j] : 1.f) : 0.f;
+    sx[wv][lane] = sj ? S.x[j] : 0.f;
+    sy[wv][lane] = sj ? S.y[j] : 0.f;
+    if (kMode == 2) {
+      const float cxx = zxx + base, cxy = zxy, cyy = zyy + base;
+      const float det = fmaf(cxx, cyy, -cxy * cxy), idet = 1.f / det;
+      sa[wv][lane] = cyy * idet;
+      sb[wv][lane] = -cxy * idet;
+      sc[wv][lane] = cxx * idet;
+      sw[wv][lane] = wj * rsqrtf(det);
+    } else {
+      sa[wv][lane] = zxx;
+      sb[wv][lane] = zxy;
+      sc[wv][lane] = zyy;
+      sw[wv][lane] = wj;
+    }
 #pragma unroll
-    for (int c = 0; c < kGCols; ++c) sv[c][threadIdx.x] = (sj && c < nc) ? V[(size_t)c * ldv + j] : 0.f;
+    for (int c = 0; c < NC; ++c) sv[wv][c][lane] = (sj && c < nc) ? V[(size_t)c * ldv + j] : 0.f;
     __syncthreads();
-    const int cnt = min(kGTile, S.n - j0);
+    const int cnt = max(0, min(64, S.n - j0));
     for (int jj = 0; jj < cnt; ++jj) {
-      const float val = sw[jj] * gauss_pair(xi - sx[jj], yi - sy[jj], txx + sxx[jj] + base, txy + sxy[jj],
-                                            tyy + syy[jj] + base);
+      const float dx = xi - sx[wv][jj], dy = yi - sy[wv][jj];
+      float val;
+      if (kMode == 0) {
+        val = sw[wv][jj] * gauss_pair(dx, dy, txx + sa[wv][jj] + base, txy + sb[wv][jj], tyy + sc[wv][jj] + base);
+      } else {
+        const float a = kMode == 2 ? sa[wv][jj] : ixx, b = kMode == 2 ? sb[wv][jj] : ixy,
+                    c = kMode == 2 ? sc[wv][jj] : iyy;
+        const float ux = fmaf(a, dx, b * dy), uy = fmaf(b, dx, c * dy);
+        val = sw[wv][jj] * exp2_fast(kq * fmaf(dx, ux, dy * uy));
+      }
 #pragma unroll
-      for (int c = 0; c < kGCols; ++c) acc[c] = fmaf(val, sv[c][jj], acc[c]);
+      for (int c = 0; c < NC; ++c) acc[c] = fmaf(val, sv[wv][c][jj], acc[c]);
     }
   }
-  if (!live) return;
-  const float f = norm * (T.w ? T.w[i] : 1.f);
+  if (wv > 0)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[wv - 1][c][lane] = acc[c];
+  __syncthreads();
+  if (wv > 0 || !live) return;
+  for (int w = 0; w < kGWaves - 1; ++w)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += red[w][c][lane];
+  const float f = norm * (T.w ? T.w[i] : 1.f) * rdet;
   for (int c = 0; c < nc; ++c) {
     float* y = Y + (size_t)c * ldy + i;
     *y = beta != 0.f ? f * acc[c] + beta * *y : f * acc[c];
@@ -110,69 +169,6 @@ __global__ void pixel_shapes_kernel(int M, const float* __restrict__ px, const f
   z[2 * N + j] = f * (a.y * a.y + b.y * b.y);
 }
 
-// rho_i = k / (pi r_k^2), r_k the distance from point i to its k-th closest
-// other point (brute force over LDS tiles; the k smallest squared distances of
-// each thread are kept sorted in registers).
-constexpr int kKnnMax = 32;
-// kIndex: also keep the neighbours' indices and write, per point, the distance
-// r_k and the index of its k-th closest other point (equal distances keep the
-// lower index first).
-template <bool kIndex>
-__global__ __launch_bounds__(256) void knn_kernel(int n, const float* __restrict__ qx, const float* __restrict__ qy,
-                                                  int k, float* rho, float* rk, int* nn) {
-  __shared__ float tx[256], ty[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const float xi = i < n ? qx[i] : 0.f, yi = i < n ? qy[i] : 0.f;
-  float best[kKnnMax];
-  int bidx[kIndex ? kKnnMax : 1];
-#pragma unroll
-  for (int q = 0; q < kKnnMax; ++q) best[q] = INFINITY;
-  if (kIndex)
-#pragma unroll
-    for (int q = 0; q < kKnnMax; ++q) bidx[kIndex ? q : 0] = -1;
-  float kth = INFINITY;  // best[k - 1], kept in a scalar (k is a runtime value)
-  int kidx = -1;
-  for (int j0 = 0; j0 < n; j0 += 256) {
-    __syncthreads();
-    const int j = j0 + threadIdx.x;
-    tx[threadIdx.x] = j < n ? qx[j] : 0.f;
-    ty[threadIdx.x] = j < n ? qy[j] : 0.f;
-    __syncthreads();
-    const int cnt = min(256, n - j0);
-    for (int jj = 0; jj < cnt; ++jj) {
-      if (j0 + jj == i) continue;
-      const float dx = xi - tx[jj], dy = yi - ty[jj];
-      float d2 = fmaf(dx, dx, dy * dy);
-      if (d2 >= kth) continue;
-      int id = j0 + jj;
-      // insertion into the sorted list (unrolled; entries beyond k stay unused)
-#pragma unroll
-      for (int q = 0; q < kKnnMax; ++q) {
-        if (q < k && d2 < best[q]) {
-          const float t = best[q];
-          best[q] = d2;
-          d2 = t;
-          if (kIndex) {
-            const int ti = bidx[kIndex ? q : 0];
-            bidx[kIndex ? q : 0] = id;
-            id = ti;
-          }
-        }
-        if (q == k - 1) {
-          kth = best[q];
-          if (kIndex) kidx = bidx[kIndex ? q : 0];
-        }
-      }
-    }
-  }
-  if (i >= n) return;
-  if (rho) rho[i] = (float)k / ((float)M_PI * kth);
-  if (kIndex) {
-    rk[i] = sqrtf(kth);
-    nn[i] = kidx;
-  }
-}
-
 // Adjoint of one column of the Gaussian product. With
 //   F = sum_i U_i norm wt_i sum_j ws_j V_j G_ij,  G_ij = |C_ij|^{-1/2} exp(-d^T C_ij^{-1} d / 2),
 // d = t_i - s_j, dG/dd = -G C^{-1} d and dG/dC = G (C^{-1} d d^T C^{-1} - C^{-1}) / 2:
@@ -181,12 +177,15 @@ __global__ __launch_bounds__(256) void knn_kernel(int n, const float* __restrict
 // accumulates gsx/gsy += dF/ds_j and gsw += dF/dws_j. Sources without shapes
 // only (their shape gradient is not formed).
 template <bool kShapes>
-__global__ __launch_bounds__(kGTile) void gauss_backward_target_kernel(GSide T, GSide S, float base, float norm,
-                                                                       const float* __restrict__ V,
-                                                                       const float* __restrict__ U, float* gtx,
-                                                                       float* gty, float* gtz) {
-  __shared__ float sx[kGTile], sy[kGTile], swv[kGTile];
-  const int i = blockIdx.x * kGTile + threadIdx.x;
+__global__ __launch_bounds__(kGThreads) void gauss_backward_target_kernel(GSide T, GSide S, float base, float norm,
+                                                                          const float* __restrict__ V,
+                                                                          const float* __restrict__ U, float* gtx,
+                                                                          float* gty, float* gtz) {
+  constexpr int kAcc = kShapes ? 6 : 2;
+  __shared__ float sx[kGWaves][64], sy[kGWaves][64], swv[kGWaves][64];
+  __shared__ float red[kGWaves - 1][kAcc][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * kGRows + lane;
   const bool live = i < T.n;
   const float xi = live ? T.x[i] : 0.f, yi = live ? T.y[i] : 0.f;
   const float txx = (live && T.z) ? T.z[i] : 0.f, txy = (live && T.z) ? T.z[T.n + i] : 0.f,
@@ -195,78 +194,107 @@ __global__ __launch_bounds__(kGTile) void gauss_backward_target_kernel(GSide T, 
   const float cxx = txx + base, cxy = txy, cyy = tyy + base;
   const float det = fmaf(cxx, cyy, -cxy * cxy), idet = 1.f / det, rdet = rsqrtf(det);
   const float ixx = cyy * idet, ixy = -cxy * idet, iyy = cxx * idet;
-  float ax = 0.f, ay = 0.f, zs = 0.f, zxx = 0.f, zxy = 0.f, zyy = 0.f;
-  for (int j0 = 0; j0 < S.n; j0 += kGTile) {
+  float acc[kAcc];  // ax, ay, then (shapes) sum g, zxx, zxy, zyy
+#pragma unroll
+  for (int a = 0; a < kAcc; ++a) acc[a] = 0.f;
+  const int steps = wave_steps(S.n);
+  for (int st = 0; st < steps; ++st) {
+    const int j0 = (wv * steps + st) * 64;
     __syncthreads();
-    const int j = j0 + threadIdx.x;
+    const int j = j0 + lane;
     const bool sj = j < S.n;
-    sx[threadIdx.x] = sj ? S.x[j] : 0.f;
-    sy[threadIdx.x] = sj ? S.y[j] : 0.f;
-    swv[threadIdx.x] = sj ? (S.w ? S.w[j] : 1.f) * V[j] : 0.f;
+    sx[wv][lane] = sj ? S.x[j] : 0.f;
+    sy[wv][lane] = sj ? S.y[j] : 0.f;
+    swv[wv][lane] = sj ? (S.w ? S.w[j] : 1.f) * V[j] : 0.f;
     __syncthreads();
-    const int cnt = min(kGTile, S.n - j0);
+    const int cnt = max(0, min(64, S.n - j0));
     for (int jj = 0; jj < cnt; ++jj) {
-      const float dx = xi - sx[jj], dy = yi - sy[jj];
+      const float dx = xi - sx[wv][jj], dy = yi - sy[wv][jj];
       const float ux = fmaf(ixx, dx, ixy * dy), uy = fmaf(ixy, dx, iyy * dy);
       const float q = fmaf(dx, ux, dy * uy);
-      const float gv = swv[jj] * exp2_fast(-0.5f * 1.4426950408889634f * q);
-      ax = fmaf(gv, ux, ax);
-      ay = fmaf(gv, uy, ay);
+      const float gv = swv[wv][jj] * exp2_fast(-0.5f * 1.4426950408889634f * q);
+      acc[0] = fmaf(gv, ux, acc[0]);
+      acc[1] = fmaf(gv, uy, acc[1]);
       if (kShapes) {
-        zs += gv;
-        zxx = fmaf(gv * ux, ux, zxx);
-        zxy = fmaf(gv * ux, uy, zxy);
-        zyy = fmaf(gv * uy, uy, zyy);
+        acc[2 % kAcc] += gv;
+        acc[3 % kAcc] = fmaf(gv * ux, ux, acc[3 % kAcc]);
+        acc[4 % kAcc] = fmaf(gv * ux, uy, acc[4 % kAcc]);
+        acc[5 % kAcc] = fmaf(gv * uy, uy, acc[5 % kAcc]);
       }
     }
   }
-  if (!live) return;
+  if (wv > 0)
+#pragma unroll
+    for (int a = 0; a < kAcc; ++a) red[wv - 1][a][lane] = acc[a];
+  __syncthreads();
+  if (wv > 0 || !live) return;
+  for (int w = 0; w < kGWaves - 1; ++w)
+#pragma unroll
+    for (int a = 0; a < kAcc; ++a) acc[a] += red[w][a][lane];
   const float c = norm * (T.w ? T.w[i] : 1.f) * U[i] * rdet;
-  gtx[i] -= c * ax;
-  gty[i] -= c * ay;
+  gtx[i] -= c * acc[0];
+  gty[i] -= c * acc[1];
   if (kShapes) {
     const float h = 0.5f * c;
-    gtz[i] += h * (zxx - ixx * zs);
-    gtz[T.n + i] += h * (zxy - ixy * zs);
-    gtz[2 * T.n + i] += h * (zyy - iyy * zs);
+    gtz[i] += h * (acc[3 % kAcc] - ixx * acc[2 % kAcc]);
+    gtz[T.n + i] += h * (acc[4 % kAcc] - ixy * acc[2 % kAcc]);
+    gtz[2 * T.n + i] += h * (acc[5 % kAcc] - iyy * acc[2 % kAcc]);
   }
 }
 
-__global__ __launch_bounds__(kGTile) void gauss_backward_source_kernel(GSide T, GSide S, float base, float norm,
-                                                                       const float* __restrict__ V,
-                                                                       const float* __restrict__ U, float* gsx,
-                                                                       float* gsy, float* gsw) {
-  __shared__ float tx[kGTile], ty[kGTile], txx[kGTile], txy[kGTile], tyy[kGTile], tc[kGTile];
-  const int j = blockIdx.x * kGTile + threadIdx.x;
+__global__ __launch_bounds__(kGThreads) void gauss_backward_source_kernel(GSide T, GSide S, float base, float norm,
+                                                                          const float* __restrict__ V,
+                                                                          const float* __restrict__ U, float* gsx,
+                                                                          float* gsy, float* gsw) {
+  // per target: position, the inverse of C_i = Zt_i + base I, and wt_i U_i |C_i|^{-1/2}
+  __shared__ float tx[kGWaves][64], ty[kGWaves][64], ta[kGWaves][64], tb[kGWaves][64], tcc[kGWaves][64],
+      tc[kGWaves][64];
+  __shared__ float red[kGWaves - 1][3][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.x * kGRows + lane;
   const bool live = j < S.n;
   const float xj = live ? S.x[j] : 0.f, yj = live ? S.y[j] : 0.f;
+  const float kq = -0.5f * 1.4426950408889634f;
   float ax = 0.f, ay = 0.f, aw = 0.f;
-  for (int i0 = 0; i0 < T.n; i0 += kGTile) {
+  const int steps = wave_steps(T.n);
+  for (int st = 0; st < steps; ++st) {
+    const int i0 = (wv * steps + st) * 64;
     __syncthreads();
-    const int i = i0 + threadIdx.x;
+    const int i = i0 + lane;
     const bool ti = i < T.n;
-    tx[threadIdx.x] = ti ? T.x[i] : 0.f;
-    ty[threadIdx.x] = ti ? T.y[i] : 0.f;
-    txx[threadIdx.x] = (ti && T.z) ? T.z[i] : 0.f;
-    txy[threadIdx.x] = (ti && T.z) ? T.z[T.n + i] : 0.f;
-    tyy[threadIdx.x] = (ti && T.z) ? T.z[2 * T.n + i] : 0.f;
-    tc[threadIdx.x] = ti ? (T.w ? T.w[i] : 1.f) * U[i] : 0.f;
+    const float cxx = ((ti && T.z) ? T.z[i] : 0.f) + base, cxy = (ti && T.z) ? T.z[T.n + i] : 0.f,
+                cyy = ((ti && T.z) ? T.z[2 * T.n + i] : 0.f) + base;
+    const float det = fmaf(cxx, cyy, -cxy * cxy), idet = 1.f / det;
+    tx[wv][lane] = ti ? T.x[i] : 0.f;
+    ty[wv][lane] = ti ? T.y[i] : 0.f;
+    ta[wv][lane] = cyy * idet;
+    tb[wv][lane] = -cxy * idet;
+    tcc[wv][lane] = cxx * idet;
+    tc[wv][lane] = ti ? (T.w ? T.w[i] : 1.f) * U[i] * rsqrtf(det) : 0.f;
     __syncthreads();
-    const int cnt = min(kGTile, T.n - i0);
+    const int cnt = max(0, min(64, T.n - i0));
     for (int ii = 0; ii < cnt; ++ii) {
-      const float cxx = txx[ii] + base, cxy = txy[ii], cyy = tyy[ii] + base;
-      const float idet = 1.f / fmaf(cxx, cyy, -cxy * cxy);
-      const float ixx = cyy * idet, ixy = -cxy * idet, iyy = cxx * idet;
-      const float dx = tx[ii] - xj, dy = ty[ii] - yj;
+      const float dx = tx[wv][ii] - xj, dy = ty[wv][ii] - yj;
+      const float ixx = ta[wv][ii], ixy = tb[wv][ii], iyy = tcc[wv][ii];
       const float ux = fmaf(ixx, dx, ixy * dy), uy = fmaf(ixy, dx, iyy * dy);
-      const float q = fmaf(dx, ux, dy * uy);
-      const float gv = tc[ii] * sqrtf(idet) * exp2_fast(-0.5f * 1.4426950408889634f * q);
+      const float gv = tc[wv][ii] * exp2_fast(kq * fmaf(dx, ux, dy * uy));
       ax = fmaf(gv, ux, ax);
       ay = fmaf(gv, uy, ay);
       aw += gv;
     }
   }
-  if (!live) return;
+  if (wv > 0) {
+    red[wv - 1][0][lane] = ax;
+    red[wv - 1][1][lane] = ay;
+    red[wv - 1][2][lane] = aw;
+  }
+  __syncthreads();
+  if (wv > 0 || !live) return;
+  for (int w = 0; w < kGWaves - 1; ++w) {
+    ax += red[w][0][lane];
+    ay += red[w][1][lane];
+    aw += red[w][2][lane];
+  }
   const float f = norm * V[j];
   const float fw = f * (S.w ? S.w[j] : 1.f);
   if (gsx) {
@@ -368,15 +396,15 @@ int gauss_backward_launch(const GSide& T, const GSide& S, double base_var, doubl
   if (T.n == 0 || S.n == 0) return GPL_OK;
   if (gtx) {
     if (gtz)
-      hipLaunchKernelGGL(gauss_backward_target_kernel<true>, dim3(cdiv(T.n, kGTile)), dim3(kGTile), 0, stream, T, S,
+      hipLaunchKernelGGL(gauss_backward_target_kernel<true>, dim3(cdiv(T.n, kGRows)), dim3(kGThreads), 0, stream, T, S,
                          (float)base_var, (float)norm, V, U, gtx, gty, gtz);
     else
-      hipLaunchKernelGGL(gauss_backward_target_kernel<false>, dim3(cdiv(T.n, kGTile)), dim3(kGTile), 0, stream, T,
+      hipLaunchKernelGGL(gauss_backward_target_kernel<false>, dim3(cdiv(T.n, kGRows)), dim3(kGThreads), 0, stream, T,
                          S, (float)base_var, (float)norm, V, U, gtx, gty, gtz);
     GPL_LAUNCH_CHECK();
   }
   if (gsx || gsw) {
-    hipLaunchKernelGGL(gauss_backward_source_kernel, dim3(cdiv(S.n, kGTile)), dim3(kGTile), 0, stream, T, S,
+    hipLaunchKernelGGL(gauss_backward_source_kernel, dim3(cdiv(S.n, kGRows)), dim3(kGThreads), 0, stream, T, S,
                        (float)base_var, (float)norm, V, U, gsx, gsy, gsw);
     GPL_LAUNCH_CHECK();
   }
@@ -389,14 +417,6 @@ int pixel_shapes_backward_launch(int M, const float* px, const float* py, const 
   hipLaunchKernelGGL(pixel_axes_grad_kernel, dim3(cdiv(N, 256)), dim3(256), 0, stream, M, px, py, gz, gab);
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(pixel_axes_gather_kernel, dim3(cdiv(N, 256)), dim3(256), 0, stream, M, gab, gpx, gpy);
-  GPL_LAUNCH_CHECK();
-  return GPL_OK;
-}
-
-int knn_index_launch(int n, const float* qx, const float* qy, int k, float* rho, float* rk, int* nn,
-                     hipStream_t stream) {
-  GPL_REQUIRE(k >= 1 && k <= kKnnMax && n > k, "k=%d must be in [1, %d] and below n=%d", k, kKnnMax, n);
-  hipLaunchKernelGGL(knn_kernel<true>, dim3(cdiv(n, 256)), dim3(256), 0, stream, n, qx, qy, k, rho, rk, nn);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
@@ -414,11 +434,25 @@ int knn_weight_backward_launch(int n, const float* qx, const float* qy, const fl
 
 int gauss_product_launch(const GSide& T, const GSide& S, double base_var, double norm, int nrhs, const float* V,
                          int ldv, float* Y, int ldy, float beta, hipStream_t stream) {
-  const dim3 grid(cdiv(T.n, kGTile));
+  const dim3 grid(cdiv(T.n, kGRows));
+  const int mode = S.z == nullptr ? 1 : (T.z == nullptr ? 2 : 0);
   for (int c0 = 0; c0 < nrhs; c0 += kGCols) {
     const int nc = std::min(kGCols, nrhs - c0);
-    hipLaunchKernelGGL(gauss_product_kernel, grid, dim3(kGTile), 0, stream, T, S, (float)base_var, (float)norm, nc,
-                       V + (size_t)c0 * ldv, ldv, Y + (size_t)c0 * ldy, ldy, beta);
+    const float *v = V + (size_t)c0 * ldv;
+    float* y = Y + (size_t)c0 * ldy;
+    const float b = (float)base_var, nm = (float)norm;
+#define GPL_GAUSS_LAUNCH(M, C) \
+  hipLaunchKernelGGL((gauss_product_kernel<M, C>), grid, dim3(kGThreads), 0, stream, T, S, b, nm, nc, v, ldv, y, ldy, beta)
+    if (nc == 1) {
+      if (mode == 0) GPL_GAUSS_LAUNCH(0, 1);
+      else if (mode == 1) GPL_GAUSS_LAUNCH(1, 1);
+      else GPL_GAUSS_LAUNCH(2, 1);
+    } else {
+      if (mode == 0) GPL_GAUSS_LAUNCH(0, kGCols);
+      else if (mode == 1) GPL_GAUSS_LAUNCH(1, kGCols);
+      else GPL_GAUSS_LAUNCH(2, kGCols);
+    }
+#undef GPL_GAUSS_LAUNCH
     GPL_LAUNCH_CHECK();
   }
   return GPL_OK;
@@ -497,14 +531,4 @@ extern "C" int gpl_pixel_shapes(const gpl_grid* grid, const float* px, const flo
   GPL_REQUIRE(grid != nullptr && grid->n >= 1 && grid->ss >= 1, "bad grid");
   GPL_REQUIRE(px && py && z, "NULL argument");
   return pixel_shapes_launch(grid->n * grid->ss, px, py, z, stream);
-}
-
-extern "C" int gpl_knn_density(int n, const float* qx, const float* qy, int k, float* rho, hipStream_t stream) {
-  GPL_REQUIRE(k >= 1 && k <= kKnnMax, "k=%d outside [1, %d]", k, kKnnMax);
-  GPL_REQUIRE(n > k, "need more than k=%d points, got %d", k, n);
-  GPL_REQUIRE(qx && qy && rho, "NULL argument");
-  hipLaunchKernelGGL(knn_kernel<false>, dim3(cdiv(n, 256)), dim3(256), 0, stream, n, qx, qy, k, rho, nullptr,
-                     nullptr);
-  GPL_LAUNCH_CHECK();
-  return GPL_OK;
 }

@@ -156,8 +156,9 @@ int gauss_backward_launch(const GSide& T, const GSide& S, double base_var, doubl
                           float* gtx, float* gty, float* gtz, float* gsx, float* gsy, float* gsw, hipStream_t stream);
 int pixel_shapes_backward_launch(int M, const float* px, const float* py, const float* gz, float* gab, float* gpx,
                                  float* gpy, hipStream_t stream);
-int knn_index_launch(int n, const float* qx, const float* qy, int k, float* rho, float* rk, int* nn,
-                     hipStream_t stream);
+size_t knn_workspace(int n);
+int knn_index_launch(int n, const float* qx, const float* qy, int k, float* rho, float* rk, int* nn, void* ws,
+                     size_t ws_bytes, hipStream_t stream);
 int knn_weight_backward_launch(int n, const float* qx, const float* qy, const float* rk, const int* nn,
                                const float* w, const float* gw, double* gq, float* gpx, float* gpy,
                                hipStream_t stream);

@@ -467,17 +467,9 @@ static int compute_units() {
   return cached[dev];
 }
 
-int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
-               float lo_threshold, hipStream_t stream) {
+int plan_sort(TilePlan& p, int n, const float* px, const float* py, hipStream_t stream) {
   GPL_REQUIRE(n >= 1, "plan needs at least one point");
   GPL_REQUIRE(p.nch <= kMaxPlanChunks, "n=%d exceeds the product's limit of %d points", n, kMaxPlanChunks * kChunk);
-  int m = 0;
-  if (grid) {
-    m = grid->n * grid->ss;
-    GPL_REQUIRE(m > 0 && (long)m * m == n, "grid does not match n=%d", n);
-  }
-  (void)m;
-  p.wround = 4 * compute_units();
   int* perm = const_cast<int*>(p.perm);
   int* irank = const_cast<int*>(p.irank);
   const int nsb = sort_blocks(n);
@@ -513,6 +505,17 @@ int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_g
   hipLaunchKernelGGL(plan_boxes_kernel, dim3(cdiv(p.nch, 256)), dim3(256), 0, stream, n, p.nch, p.xs, p.ys, p.cbox,
                      p.sbox);
   GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
+               float lo_threshold, hipStream_t stream) {
+  if (grid) {
+    const int m = grid->n * grid->ss;
+    GPL_REQUIRE(m > 0 && (long)m * m == n, "grid does not match n=%d", n);
+  }
+  p.wround = 4 * compute_units();
+  GPL_TRY(plan_sort(p, n, px, py, stream));
   hipLaunchKernelGGL(plan_scaled_kernel, dim3(cdiv(p.npad, 256)), dim3(256), 0, stream, p.npad, p.xs, p.ys, p.cbox, s2,
                      p.xc, p.yc, p.cen);
   GPL_LAUNCH_CHECK();

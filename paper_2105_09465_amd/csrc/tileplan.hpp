@@ -198,6 +198,9 @@ void plan_carve(C& cv, int n, TilePlan& p) {
 // equal to `threshold` where the form has no lo part).
 int plan_build(TilePlan& p, int n, const float* px, const float* py, const gpl_grid* grid, float s2, float threshold,
                float lo_threshold, hipStream_t stream);
+// The first part of plan_build alone: the Hilbert sort (perm, irank, xs, ys)
+// and the chunk and subtile boxes.
+int plan_sort(TilePlan& p, int n, const float* px, const float* py, hipStream_t stream);
 
 // Relative work of a wave in the first, second and later dispatch rounds.
 constexpr int kRounds = 3;

@@ -101,6 +101,8 @@ struct Bump {
 
 struct VBufs {
   double *lens, *g_lens, *g_src, *sums, *gq, *rt_partial, *se_partial;
+  void* knn_ws;
+  size_t knn_bytes;
   float *px, *py, *Z, *f, *resid, *g_f, *gpx, *gpy, *gZ, *gw, *gab, *r, *w, *w_sp, *r_sp, *y;
   int *nn, *nn_sp;
 };
@@ -133,6 +135,8 @@ static size_t vigp_carve(const VLayout& L, void* ws, VBufs& b) {
   b.r_sp = B.take<float>(G);
   b.nn_sp = B.take<int>(G);
   b.y = B.take<float>(L.ne32 ? L.ne32 : 1);
+  b.knn_bytes = knn_workspace(std::max(L.nip > 0 ? L.N : 0, L.sp >= 0 ? L.G : 0));
+  b.knn_ws = B.take<char>(std::max<size_t>(b.knn_bytes, 1));
   return B.used;
 }
 
@@ -357,12 +361,12 @@ extern "C" int gpl_vigp_elbo(const gpl_vigp_model* model, const gpl_grid* grid, 
   GPL_TRY(raytrace_dev_launch(grid, b.lens, b.px, b.py, stream));
   GPL_TRY(pixel_shapes_launch(L.M, b.px, b.py, b.Z, stream));
   if (L.nip > 0) {
-    GPL_TRY(knn_index_launch(N, b.px, b.py, model->knn_k, nullptr, b.r, b.nn, stream));
+    GPL_TRY(knn_index_launch(N, b.px, b.py, model->knn_k, nullptr, b.r, b.nn, b.knn_ws, b.knn_bytes, stream));
     hipLaunchKernelGGL(vigp_knn_weight_kernel, blocks_for(N), dim3(256), 0, stream, N, b.r, wscale, b.w);
     GPL_LAUNCH_CHECK();
   }
   if (L.sp >= 0) {
-    GPL_TRY(knn_index_launch(G, gx, gy, model->knn_k, nullptr, b.r_sp, b.nn_sp, stream));
+    GPL_TRY(knn_index_launch(G, gx, gy, model->knn_k, nullptr, b.r_sp, b.nn_sp, b.knn_ws, b.knn_bytes, stream));
     hipLaunchKernelGGL(vigp_knn_weight_kernel, blocks_for(G), dim3(256), 0, stream, G, b.r_sp, wscale, b.w_sp);
     GPL_LAUNCH_CHECK();
   }

@@ -170,8 +170,10 @@ def pixel_shapes(grid: Grid, px, py):
 
 def knn_density(qx, qy, k=20):
     """k-th closest neighbour density of the points (q_x, q_y)."""
-    rho = torch.empty(qx.numel(), dtype=torch.float32, device=qx.device)
-    _lib.call("gpl_knn_density", qx.numel(), _ptr(qx), _ptr(qy), int(k), _ptr(rho), _stream())
+    n = qx.numel()
+    rho = torch.empty(n, dtype=torch.float32, device=qx.device)
+    ws, wsb = workspace(_lib.lib.gpl_knn_density_workspace(n), qx.device)
+    _lib.call("gpl_knn_density", n, _ptr(qx), _ptr(qy), int(k), _ptr(rho), _wsptr(ws), wsb, _stream())
     return rho
 
 

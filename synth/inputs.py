@@ -152,6 +152,7 @@ def rademacher(n: int, m: int, index: int, sub: int = 0) -> np.ndarray:
 
 
 _TAG_PC_PROBE = 7
+_TAG_VIGP = 8
 
 
 def preconditioned_probe_normals(n: int, k: int, m: int, index: int, sub: int = 0):
@@ -159,6 +160,13 @@ def preconditioned_probe_normals(n: int, k: int, m: int, index: int, sub: int = 
     g (m, k) and h (m, n), both float64."""
     r = _rng(index, _TAG_PC_PROBE, sub)
     return r.standard_normal((m, k)), r.standard_normal((m, n))
+
+
+def vigp_normals(n32: int, step: int, index: int = 1):
+    """Standard normals of one reparametrised sample of the variational step:
+    the 7 lens-parameter normals (float64) and n32 source-parameter normals."""
+    r = _rng(index, _TAG_VIGP, step)
+    return r.standard_normal(7), r.standard_normal(n32)
 
 
 def gp_normals(N: int, index: int, sub: int = 0) -> np.ndarray:

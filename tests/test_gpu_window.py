@@ -112,6 +112,27 @@ def test_knn_density_vs_oracle(G):
     assert np.max(np.abs(rho - want) / want) <= 1e-5
 
 
+def test_knn_density_lensed_full_size(G):
+    """The traced 200 x 200 fine grid of the 100 x 100 workload (N = 40,000,
+    strongly non-uniform): density at 600 sampled points against brute force
+    on the same FP32 points, and a regular grid (many equal distances)."""
+    _say("knn density lensed full size")
+    w = synth.workload(1)
+    prob = gpu_problem(w)
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    rho = t64(G.ops.knn_density(pts[0], pts[1], 20))
+    rows = np.random.default_rng(65).choice(w.N, 600, replace=False)
+    r, _ = owin.knn_radius(t64(pts[0]), t64(pts[1]), 20, rows=rows)
+    want = 20 / (math.pi * r * r)
+    err = np.max(np.abs(rho[rows] - want) / want)
+    print(f"max rel err {err:.2e}")
+    assert err <= 1e-5
+    gx, gy = synth.source_grid(40, 0.03)
+    rho = t64(G.ops.knn_density(cuda32(gx), cuda32(gy), 20))
+    want = owin.knn_density(gx.astype(np.float32).astype(np.float64), gy.astype(np.float32).astype(np.float64), 20)
+    assert np.max(np.abs(rho - want) / want) <= 1e-5
+
+
 def test_transmission_products_vs_oracle(G):
     """T y and T^T v (eq. "transmission") for image-plane inducing points (q = p,
     the pixel shapes on the point side) and for a 40 x 40 source-plane grid
