@@ -136,8 +136,13 @@ size_t split_gemm_scratch(int m, int n, int nsplit) { return (size_t)nsplit * m 
 
 int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int kdim, int nsplit,
                double alpha, const double* A, int lda, const double* B, int ldb, double beta, double* C, int ldc,
-               double* scratch, hipStream_t stream) {
-  nsplit = std::max(1, std::min(nsplit, kdim));
+               double* scratch, size_t scratch_elems, hipStream_t stream) {
+  const size_t per = (size_t)m * n;
+  GPL_REQUIRE(m > 0 && n > 0 && kdim > 0, "split product of empty size");
+  GPL_REQUIRE(scratch_elems >= per, "split product scratch holds %zu doubles, one split needs %zu", scratch_elems,
+              per);
+  const size_t fit = scratch_elems / per;
+  nsplit = std::max(1, std::min(std::min(nsplit, kdim), (int)std::min<size_t>(fit, 1 << 20)));
   const int kc = cdiv(kdim, nsplit);
   nsplit = cdiv(kdim, kc);
   const int last = kdim - (nsplit - 1) * kc;  // rows of the reduction in the last split

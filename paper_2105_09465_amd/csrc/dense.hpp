@@ -24,10 +24,12 @@ int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, do
 // C (m x n) = alpha op(A) op(B) + beta C with the reduction dimension kdim
 // split into nsplit parts (rocBLAS strided-batched products into scratch, then
 // a sum in split order): GEMMs with one short side use the whole device this
-// way. scratch: split_gemm_scratch(m, n, nsplit) bytes.
+// way. scratch: split_gemm_scratch(m, n, nsplit) bytes; scratch_elems is the
+// number of doubles it holds, and nsplit is lowered to what fits (an error if
+// not even one split does).
 size_t split_gemm_scratch(int m, int n, int nsplit);
 int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int kdim, int nsplit,
                double alpha, const double* A, int lda, const double* B, int ldb, double beta, double* C, int ldc,
-               double* scratch, hipStream_t stream);
+               double* scratch, size_t scratch_elems, hipStream_t stream);
 
 }  // namespace gpl

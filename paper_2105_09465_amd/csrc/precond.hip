@@ -376,6 +376,7 @@ __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, 
 struct PcBuf {
   float *E, *T1, *T2, *Mc;
   double *C, *Lc, *R, *d, *dmax, *logd, *logdet_g, *split;
+  size_t split_elems;  // doubles of split
   int *cand, *order, *taken, *info, *is_piv;
   void* mvm_ws;
   size_t mvm_bytes;
@@ -392,7 +393,8 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.C = c.template take<double>((size_t)npix * kPcBlock);
   b.Lc = c.template take<double>((size_t)kPcBlock * std::max(k, 1));
   b.R = c.template take<double>((size_t)kPcBlock * kPcBlock);
-  b.split = c.template take<double>(split_gemm_scratch(npix, kPcBlock, kPcSplits) / sizeof(double));
+  b.split_elems = split_gemm_scratch(npix, kPcBlock, kPcSplits) / sizeof(double);
+  b.split = c.template take<double>(b.split_elems);
   b.d = c.template take<double>(npix);
   b.dmax = c.template take<double>(1);
   b.logd = c.template take<double>(std::max(k, 1));
@@ -431,6 +433,7 @@ struct PcgState {
 struct PcgBuf {
   float *R, *P, *AP, *T2, *Z;
   double *R64, *Z64, *W, *split;
+  size_t split_elems;  // doubles of split
   int ldv, ldf;
   void* mvm_ws;
   size_t mvm_bytes;
@@ -457,9 +460,10 @@ static void carve_pcg(Cv& c, int npix, int N, int n, int ss, int k, int nrhs, in
   b.R64 = c.template take<double>((size_t)b.ldv * nrhs);
   b.Z64 = c.template take<double>((size_t)b.ldv * nrhs);
   b.W = c.template take<double>((size_t)std::max(k, 1) * nrhs);
-  b.split = c.template take<double>(
+  b.split_elems =
       std::max(split_gemm_scratch(nrhs, std::max(k, 1), kPcSplits), split_gemm_scratch(npix, nrhs, kPcSplits)) /
-      sizeof(double));
+      sizeof(double);
+  b.split = c.template take<double>(b.split_elems);
   b.mvm_bytes = mvm_workspace(N, nrhs, prec);
   b.mvm_ws = c.template take<char>(b.mvm_bytes);
   b.pap_part = c.template take<double>((size_t)b.ntiles * nrhs);
@@ -489,10 +493,11 @@ __global__ __launch_bounds__(256) void pcg_widen_kernel(int npix, const float* _
 // Z64 = R64 - L Wt^T. Both products with L have one short side (m columns)
 // and run with their long reduction split. The caller finishes Z = Z64 / s.
 static int woodbury(rocblas_handle h, int npix, int k, const double* L, int ldl, const double* G, int ldg, int nrhs,
-                    const double* R64, double* Z64, int ldv, double* Wt, double* split, hipStream_t stream) {
+                    const double* R64, double* Z64, int ldv, double* Wt, double* split, size_t split_elems,
+                    hipStream_t stream) {
   const double one = 1.0;
   GPL_TRY(split_gemm(h, rocblas_operation_transpose, rocblas_operation_none, nrhs, k, npix, kPcSplits, 1.0, R64, ldv,
-                     L, ldl, 0.0, Wt, nrhs, split, stream));
+                     L, ldl, 0.0, Wt, nrhs, split, split_elems, stream));
   if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                     rocblas_diagonal_non_unit, nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success ||
       rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit,
@@ -501,7 +506,7 @@ static int woodbury(rocblas_handle h, int npix, int k, const double* L, int ldl,
     return GPL_EHIP;
   }
   return split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, nrhs, k, kPcSplits, -1.0, L, ldl, Wt,
-                    nrhs, 1.0, Z64, ldv, split, stream);
+                    nrhs, 1.0, Z64, ldv, split, split_elems, stream);
 }
 
 // Z = Z64 / s (FP32), partial r.z and (at init) partial |b|^2 and max |Z| per block.
@@ -890,7 +895,8 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
                          b.Lc);
       GPL_LAUNCH_CHECK();
       GPL_TRY(split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, kPcBlock, j0,
-                         std::max(1, j0 / 256), -1.0, L, ldl, b.Lc, kPcBlock, 1.0, b.C, npix, b.split, stream));
+                         std::min(kPcSplits, std::max(1, j0 / 256)), -1.0, L, ldl, b.Lc, kPcBlock, 1.0, b.C, npix,
+                         b.split, b.split_elems, stream));
     }
     hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64), 0, stream, b.C, npix, b.cand, b.dmax, kPcRelTol,
                        b.order, b.taken, b.R);
@@ -1007,7 +1013,7 @@ extern "C" int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, in
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(pcg_widen_kernel, gv, dim3(256), 0, stream, npix, b.R, b.ldv, b.R64, b.Z64);
   GPL_LAUNCH_CHECK();
-  GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, stream));
+  GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, b.split_elems, stream));
   hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z, b.rz_part,
                      nb, (const PcgState*)nullptr, (const int*)nullptr);
   GPL_LAUNCH_CHECK();
@@ -1034,7 +1040,7 @@ extern "C" int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, in
                          b.Z64, b.pap_part, b.ntiles, b.rr_part, nb, b.st[p], b.st[1 - p], b.n_active + p,
                          b.n_active + (1 - p));
       GPL_LAUNCH_CHECK();
-      GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, stream));
+      GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, b.split_elems, stream));
       hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z,
                          b.rz_part, nb, (const PcgState*)b.st[p], (const int*)(b.n_active + p));
       GPL_LAUNCH_CHECK();

@@ -137,6 +137,41 @@ def test_pchol_full_rank_is_the_matrix(G):
     assert max(res["iters"].cpu().tolist()) <= 8
 
 
+def test_pchol_rank_beyond_sixteen_splits(G):
+    """Rank 4480 on a 72 x 72 image (5184 pixels): from the 69th block on, the
+    residual columns' reduction over the earlier pivots (more than 16 x 256 of
+    them) is split at most as far as its scratch holds. The pivots taken still
+    reproduce their columns of M, the factor of sigma^2 I + L^T L is exact, and
+    ln|P| follows the determinant lemma."""
+    k = 4480
+    _say("pchol rank 4480", "72x72")
+    w, d, _ = observation(0)
+    w = w.replace(n=72)
+    prob = gpu_problem(w)
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    pc = G.ops.pchol(prob, pts[0], pts[1], k, prec="fp32")
+    torch.cuda.synchronize()
+    assert int(pc["info"].item()) == 0
+    P = oracle_problem(w)
+    A = oev.assemble_A(P, t64(pts[0]), t64(pts[1]))
+    M = A - w.noise_sigma ** 2 * np.eye(w.n_pix)
+    piv = pc["pivots"].cpu().numpy()
+    taken = piv >= 0
+    Lg = t64(pc["L"]).T[:, taken]
+    dmax = np.max(np.diag(M))
+    interp = np.max(np.abs(Lg @ Lg[piv[taken]].T - M[:, piv[taken]])) / dmax
+    print(f"taken {taken.sum()} of {k}; pivot columns {interp:.2e}")
+    # the last block starts at column 4416 > 16 x 256 whatever the candidates taken
+    assert k - 64 > 16 * 256 and taken.sum() > 4000
+    assert interp <= 2e-6
+    s = w.noise_sigma ** 2
+    Lall = t64(pc["L"]).T
+    Gf = t64(pc["G"]).T
+    Gm = s * np.eye(k) + Lall.T @ Lall
+    assert np.allclose(np.tril(Gf) @ np.tril(Gf).T, Gm, rtol=0, atol=1e-10 * np.abs(Gm).max())
+    assert math.isclose(float(pc["logdet_P"].item()), opc.logdet_lowrank_plus_shift(Lall, s), rel_tol=1e-10)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "f16x3"])
 def test_pcg_vs_oracle(G, prec):
     """Preconditioned CG with the GPU factor (rank 448) against the oracle's PCG
