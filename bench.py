@@ -14,8 +14,8 @@ the kernel values the step's products evaluate (pairs below the 2^-36 cutoff
 are not evaluated), over the step time; the dense equivalent (N^2 pairs per
 product) is reported beside it. Extra fields: reconstructions/s of both
 arithmetic forms, the roofline of the dominant kernel and of the FP32 form's
-product, the preconditioned step, the exact posterior on a 40 x 40
-source-plane grid, the variational GP source fit (Adam steps) with the
+product, the preconditioned step, the 200 x 200 image (N = 160,000) with 64
+columns in both forms, the exact posterior on a 40 x 40 source-plane grid, the variational GP source fit (Adam steps) with the
 roofline of its transmission product, the serving trace, and the FP64 oracle
 timed on the host as a baseline.
 
@@ -166,7 +166,10 @@ def serve_section(G, torch, synth, n_requests):
     continuous-batching engine, for both arithmetic forms:
     - capacity: every request available at once, reconstructions/s of the engine;
     - stream: Poisson arrivals at 0.8 x the plain FP32 capacity, with p50/p99
-      latency from arrival to result."""
+      latency from arrival to result.
+    The scheduling overhead is the share of the capacity run's wall time not
+    covered by the device time of the grouped CG steps (event pairs around each
+    round's step), i.e. host waits, admission, snapshots and retirement."""
     reqs = serving_requests(G, torch, synth, n_requests)
     out = {"requests": n_requests, "hbm_budget_GiB": 8}
     for prec in ("fp32", "f16x3"):  # capacity: all present at the start, latency counted from there
@@ -175,7 +178,11 @@ def serve_section(G, torch, synth, n_requests):
         s = G.serving.summarize(res, eng.stats["wall_s"])
         out[f"capacity_{prec}"] = {"reconstructions_per_s": s["reconstructions_per_s"], "wall_s": s["wall_s"],
                                    "p50_latency_ms": s["p50_latency_ms"], "p99_latency_ms": s["p99_latency_ms"],
-                                   "max_active_slots": eng.stats["max_active"]}
+                                   "max_active_slots": eng.stats["max_active"],
+                                   "device_step_fraction": eng.stats["step_s"] / s["wall_s"],
+                                   "scheduling_overhead": 1.0 - eng.stats["step_s"] / s["wall_s"],
+                                   "rounds": eng.stats["rounds"],
+                                   "lnp_slq_stderr_rel_median": s["lnp_slq_stderr_rel_median"]}
     rate = 0.8 * out["capacity_fp32"]["reconstructions_per_s"]
     trace = synth.serving_trace(n_requests, rate)
     for r, (t, _, _, _) in zip(reqs, trace):
@@ -186,6 +193,7 @@ def serve_section(G, torch, synth, n_requests):
         res = eng.run(reqs, realtime=True)
         s = G.serving.summarize(res, eng.stats["wall_s"])
         s.update(max_active_slots=eng.stats["max_active"], rounds=eng.stats["rounds"],
+                 device_step_s=eng.stats["step_s"],
                  nonconverged=int(sum(any(st != 0 for st in r.status) for r in res)))
         out[prec] = s
     out["capacity_ratio_f16x3_vs_fp32"] = (out["capacity_f16x3"]["reconstructions_per_s"] /
@@ -297,6 +305,57 @@ GAUSS_PAIR_COST = 2 + 6 + 1 + 4 + 1 + 1
 GAUSS_PEAK_GPAIRS = VALU_LANE_OPS / GAUSS_PAIR_COST / 1e9
 
 
+C3_FIXTURE = os.path.join(ROOT, "tests", "fixtures", "workload2_draw0_crop100.npz")
+
+
+def c3_section(G, torch, synth, steps):
+    """The 200 x 200 image with 2 x 2 supersampling (N = 160,000) and 64 columns
+    (1 solve + 63 probes): timed reconstructions in both forms, the product's
+    roofline at that size, and ln p with its SLQ standard error. Its observation
+    is the stored oracle simulation; the oracle's evidence exists for the central
+    100 x 100 crop only (the test suite compares against it)."""
+    import numpy as np
+    w = synth.workload(2)
+    s = w.source
+    prob = G.Problem(G.Grid(w.n, w.ss, w.pix_scale), G.Lens(*w.lens.as_tuple()),
+                     G.Sersic(s.peak, s.R_e, s.n_sersic, s.xs, s.ys), G.Kernel(w.ell, w.amp), G.PSF(w.psf_fwhm),
+                     w.noise_sigma)
+    z = np.load(C3_FIXTURE)
+    d = torch.as_tensor(z["d"], dtype=torch.float32, device="cuda")
+    Z = torch.as_tensor(synth.rademacher(w.n_pix, 63, 2).T.copy(), dtype=torch.float32, device="cuda")
+    out = {"workload": "200x200 px, 2x2 supersampling (N=160000), 64 columns (1 + 63 probes), CG tol 1e-6",
+           "N": w.N, "n_pix": w.n_pix}
+    for prec in ("f16x3", "fp32"):
+        G.reconstruct(prob, d, Z, prec=prec, tol=1e-6, max_iter=3000, n_lanczos=3000)  # warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rec = G.reconstruct(prob, d, Z, prec=prec, tol=1e-6, max_iter=3000, n_lanczos=3000)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        h = rec.host()
+        _, sub, lo = G.ops.kernel_mvm_live_tiles(prob.kernel, rec.px, rec.py, prec=prec, grid=prob.grid, with_lo=True)
+        ms = product_alone(G, torch, prob, rec.px, rec.py, 64, prec)
+        ev = sub * 512
+        sec = {"ms_per_reconstruction": el * 1e3, "reconstructions_per_s": 1.0 / el, "cg_iters": max(h["iters"]),
+               "lnp": h["lnp"], "lnp_slq_stderr_rel": 0.5 * h["stderr"] / abs(h["lnp"]),
+               "true_relres_max": max(h["true_relres"]), "product_ms_alone": ms,
+               "evaluated_pairs_per_launch": ev, "evaluated_fraction": ev / (w.N * w.N)}
+        if prec == "f16x3":
+            sec["roofline"] = {"bound": "alu", "unit": "Gpairs/s", "achieved": ev / (ms * 1e-3) / 1e9,
+                               "peak": ALU_PEAK_GPAIRS, "frac": ev / (ms * 1e-3) / 1e9 / ALU_PEAK_GPAIRS,
+                               "mfma_tflops_executed": mfma_flops_per_launch(prec, 64, sub, lo) / (ms * 1e-3) / 1e12}
+        else:
+            flop = mfma_flops_per_launch(prec, 64, sub, sub)
+            sec["roofline"] = {"bound": "mfma", "unit": "TFLOP/s", "achieved": flop / (ms * 1e-3) / 1e12,
+                               "peak": FP32_MFMA_PEAK_TFLOPS,
+                               "frac": flop / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS}
+        out[prec] = sec
+    out["reconstructions_ratio_f16x3_vs_fp32"] = (out["f16x3"]["reconstructions_per_s"] /
+                                                   out["fp32"]["reconstructions_per_s"])
+    return out
+
+
 def vigp_section(G, torch, synth, prob, d, steps, lens):
     """Timed Adam steps of the variational fit (ELBO sample, gradient, update),
     and the dense transmission product alone with its ALU roofline."""
@@ -395,6 +454,8 @@ def main():
     ap.add_argument("--gradient-only", type=int, default=0,
                     help="time ray tracing and this many evaluations of the evidence gradients at the bench shape, "
                          "print one JSON line and exit")
+    ap.add_argument("--c3-steps", type=int, default=2,
+                    help="timed reconstructions of the 200x200, N=160000 image per form (0: skip)")
     ap.add_argument("--vigp-steps", type=int, default=10,
                     help="timed steps of the variational GP source fit (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=512,
@@ -524,6 +585,10 @@ def main():
     if pcsec is not None:
         post = posterior_section(G, torch, synth, prob, rpc, z)
 
+    c3 = None
+    if args.c3_steps > 0:
+        c3 = c3_section(G, torch, synth, args.c3_steps)
+
     vsec = None
     if args.vigp_steps > 0:
         vsec = vigp_section(G, torch, synth, prob, d, args.vigp_steps, prob.lens.as_tuple())
@@ -605,6 +670,7 @@ def main():
                      "mfma_tflops_executed": mfma_flop / (avg_ms * 1e-3) / 1e12},
         "preconditioned": pcsec,
         "posterior_grid": post,
+        "c3_160k_64cols": c3,
         "vigp": vsec,
         "plain_fp32": plain,
         "serving": serving,

@@ -71,7 +71,7 @@ class ServingEngine:
         self.tol, self.max_iter, self.n_lanczos = float(tol), int(max_iter), int(n_lanczos)
         self.want_image = want_image
         self.snap = torch.zeros(64, dtype=torch.int32, pin_memory=True)
-        self.stats = dict(rounds=0, max_active=0, max_bytes=0, admitted=0, deferred_memory=0)
+        self.stats = dict(rounds=0, max_active=0, max_bytes=0, admitted=0, deferred_memory=0, step_s=0.0)
 
     def footprint(self, req: Request) -> int:
         g = req.problem.grid.c()
@@ -119,6 +119,8 @@ class ServingEngine:
         results = []
         used = 0
         it = 0
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while pending or active:
@@ -139,10 +141,15 @@ class ServingEngine:
             self.stats["max_active"] = max(self.stats["max_active"], len(active))
             self.stats["max_bytes"] = max(self.stats["max_bytes"], used)
             arr = (C.POINTER(_lib.gpl_serve_slot) * len(active))(*[C.pointer(s.c) for s in active])
+            ev0.record()
             _lib.call("gpl_serve_step", arr, len(active), self.chunk, it, stream)
+            ev1.record()
             it += self.chunk
             _lib.call("gpl_serve_snapshot", arr, len(active), it, C.c_void_p(self.snap.data_ptr()), stream)
             torch.cuda.current_stream().synchronize()
+            # device time of the round's grouped CG iterations (the rest of the
+            # round is the scheduler: snapshot, host wait, admission, retirement)
+            self.stats["step_s"] += ev0.elapsed_time(ev1) * 1e-3
             self.stats["rounds"] += 1
             snap = self.snap[:len(active)].tolist()
             keep = []
@@ -168,6 +175,8 @@ class ServingEngine:
 
 def summarize(results, wall_s):
     lat = np.array([r.latency for r in results])
+    se = np.array([0.5 * r.stderr / abs(r.lnp) for r in results if r.lnp != 0])
     return {"requests": len(results), "reconstructions_per_s": len(results) / wall_s,
             "p50_latency_ms": float(np.percentile(lat, 50) * 1e3), "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_latency_ms": float(lat.mean() * 1e3), "wall_s": wall_s}
+            "mean_latency_ms": float(lat.mean() * 1e3), "wall_s": wall_s,
+            "lnp_slq_stderr_rel_median": float(np.median(se)) if se.size else None}
