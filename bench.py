@@ -229,6 +229,24 @@ def kernel_only(G, torch, prec, reps):
     print(json.dumps({"kernel_only": reps, "copy_bytes": src.numel() * 4}), flush=True)
 
 
+def gauss_only(G, torch, reps):
+    """The variational step's image-plane transmission product alone (N =
+    40,000 traced points with their pixel shapes as targets, the same points with
+    k-NN weights as sources, one column, lengthscale 0.01"), `reps` launches."""
+    prob, _ = load_workload()
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    z = G.ops.pixel_shapes(prob.grid, pts[0], pts[1])
+    w = G.ops.knn_density(pts[0], pts[1], 20).rsqrt()
+    y = torch.randn(prob.grid.N, device="cuda")
+    out = torch.empty_like(y)
+    ell = VIGP_LAYERS[0][1]
+    for _ in range(reps):
+        G.ops.gauss_product(0.5 * ell * ell, math.sqrt(2 * math.pi * ell * ell) / (2 * math.pi), pts[0], pts[1],
+                            pts[0], pts[1], y, tz=z, sw=w, out=out)
+    torch.cuda.synchronize()
+    print(json.dumps({"gauss_only": reps, "pairs_per_launch": prob.grid.N ** 2}), flush=True)
+
+
 def gradient_only(G, torch, synth, prec, reps):
     """Timing of the backward path at the bench shape: ray tracing of the
     40,000 points, one reconstruction, then `reps` evaluations of the 12-component
@@ -451,6 +469,8 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0,
                     help="run only the dominant kernel this many times at the bench shape, then a 1 GiB copy "
                          "(calibration of the HBM byte counters), and exit; for rocprofv3 counter runs")
+    ap.add_argument("--gauss-only", type=int, default=0,
+                    help="run only the variational step's transmission product this many times (for counters)")
     ap.add_argument("--gradient-only", type=int, default=0,
                     help="time ray tracing and this many evaluations of the evidence gradients at the bench shape, "
                          "print one JSON line and exit")
@@ -477,6 +497,9 @@ def main():
     torch.cuda.set_device(0)
     if args.kernel_only > 0:
         kernel_only(G, torch, args.prec, args.kernel_only)
+        return
+    if args.gauss_only > 0:
+        gauss_only(G, torch, args.gauss_only)
         return
     if args.gradient_only > 0:
         gradient_only(G, torch, synth, args.prec, args.gradient_only)
