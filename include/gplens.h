@@ -307,9 +307,11 @@ int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, cons
  * pivot exceeds 1e-5 of the largest diagonal entry of M (below that the FP32
  * columns are rounding noise). pivots[j] = the pixel
  * of column j, -1 for a zero column (a candidate not taken). G (k x k, ld ldg)
- * receives the lower Cholesky factor of sigma^2 I + L^T L; logdet_P (device
- * scalar) = ln|P| = (n*n - k) ln sigma^2 + ln|sigma^2 I + L^T L|; info (device)
- * = 0, or 1 + the column where that factorisation failed. noise_sigma > 0. */
+ * receives, in its lower triangle, the inverse of sigma^2 I + L^T L (from its
+ * Cholesky factor; the strict upper triangle is not written);
+ * logdet_P (device scalar) = ln|P| = (n*n - k) ln sigma^2 + ln|sigma^2 I + L^T L|
+ * from that factor; info (device) = 0, or the order of the first leading minor
+ * of sigma^2 I + L^T L found not positive definite. noise_sigma > 0. */
 size_t gpl_pchol_workspace(const gpl_problem* prob, int k, int prec);
 int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, int ldl, double* G, int ldg, int* pivots,
               double* logdet_P, int* info, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -322,7 +324,8 @@ int gpl_pchol_probes(int npix, int k, const double* L, int ldl, double noise_sig
                      const float* h, int ldh, float* Z, int ldz, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Preconditioned CG on A X = Bm with P from gpl_pchol (L, G as written there):
- * z = P^{-1} r by the Woodbury identity (FP64 products), alpha = r.z/p.Ap,
+ * z = P^{-1} r by the Woodbury identity (FP64 products: L^T r, one symmetric
+ * product with G's lower triangle, L times that), alpha = r.z/p.Ap,
  * beta = r'.z'/r.z, p = z' + beta p; one recurrence per column, FP32 vectors,
  * FP64 scalars. Outputs as gpl_cg_solve, with rz0[c] = b_c^T P^{-1} b_c (the
  * quadrature weight of a probe column) in place of |b|^2: pass rz0 as

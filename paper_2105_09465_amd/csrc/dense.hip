@@ -1,9 +1,9 @@
-// Dense FP64 linear algebra on small blocks for the preconditioner: a rocBLAS
-// handle per host thread and device (its scratch memory always taken from the
-// caller's workspace), and a blocked right-looking Cholesky factorisation: a
-// one-workgroup kernel factors each 64 x 64 diagonal block in LDS, rocBLAS
-// dtrsm forms the panel below it and dsyrk updates the trailing matrix. The
-// log-determinant is summed from the factor's diagonal in a fixed order.
+// Dense FP64 linear algebra for the preconditioner: a rocBLAS handle per host
+// thread and device (its scratch memory always taken from the caller's
+// workspace), the Cholesky factor and inverse of a dense matrix by rocSOLVER
+// (the log-determinant summed from the factor's diagonal in a fixed order), a
+// row-parallel triangular solve with a 64 x 64 factor, and GEMMs with a long
+// reduction split over the device.
 #include <cmath>
 
 #include "common.hpp"
@@ -34,47 +34,10 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
   return GPL_OK;
 }
 
-// Factor the jb x jb diagonal block at A (leading dimension lda) in place:
-// lower Cholesky by one wave in LDS, lane a owning row a (right-looking: after
-// each column the lanes below it update their own rows). A non-positive or
-// non-finite pivot sets *info to its global column + 1 (first one wins) and
-// leaves the block unfinished. logd[c] = ln of the diagonal entry of column c.
-constexpr int kDiag = 64;
-__global__ __launch_bounds__(64) void potf2_kernel(double* A, int lda, int jb, int col0, double* logd, int* info) {
-  // T[j][a] holds entry (a, j): lane a walks its row along j at consecutive
-  // LDS addresses across the lanes (no bank conflicts)
-  __shared__ double T[kDiag][kDiag + 1];
-  __shared__ double ld[kDiag];  // written to logd after the loop (a global store before each barrier would
-                                // make every barrier wait for it)
-  const int a = threadIdx.x;
-  for (int j = 0; j < jb; ++j)
-    if (a < jb) T[j][a] = A[(size_t)j * lda + a];
-  __syncthreads();
-  for (int c = 0; c < jb; ++c) {
-    const double p = T[c][c];
-    if (!(p > 0.0) || !isfinite(p)) {
-      if (a == 0) atomicCAS(info, 0, col0 + c + 1);
-      return;
-    }
-    const double piv = sqrt(p);
-    __syncthreads();
-    if (a == c) {
-      T[c][c] = piv;
-      ld[c] = 0.5 * log(p);
-    }
-    double l = 0.0;
-    if (a > c && a < jb) {
-      l = T[c][a] / piv;
-      T[c][a] = l;
-    }
-    __syncthreads();
-    if (a > c && a < jb)
-      for (int j = c + 1; j <= a; ++j) T[j][a] -= l * T[c][j];
-    __syncthreads();
-  }
-  for (int j = 0; j < jb; ++j)
-    if (a < jb) A[(size_t)j * lda + a] = j <= a ? T[j][a] : 0.0;
-  if (a < jb) logd[col0 + a] = ld[a];
+// logd[c] = ln A[c][c] of a factor's diagonal.
+__global__ void diag_log_kernel(int n, const double* __restrict__ A, int lda, double* logd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) logd[c] = log(A[(size_t)c * lda + c]);
 }
 
 // out[0] = sum of logd[0..n) in index order (one wave, lane-strided then a
@@ -84,39 +47,58 @@ __global__ void logdet_fold_kernel(int n, const double* logd, double* out) {
   if (threadIdx.x == 0) *out = 2.0 * s;
 }
 
-__global__ void zero_int_kernel(int* p) {
-  if (threadIdx.x == 0) *p = 0;
-}
-
-int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info,
+int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info, bool inverse,
                    hipStream_t stream) {
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, stream, info);
-  GPL_LAUNCH_CHECK();
-  const double one = 1.0, minus_one = -1.0;
-  for (int j0 = 0; j0 < n; j0 += kDiag) {
-    const int jb = std::min(kDiag, n - j0);
-    double* Ajj = A + (size_t)j0 * lda + j0;
-    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(kDiag), 0, stream, Ajj, lda, jb, j0, logd, info);
-    GPL_LAUNCH_CHECK();
-    const int m = n - j0 - jb;
-    if (m <= 0) break;
-    double* Aij = Ajj + jb;  // the panel below the diagonal block
-    if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                      rocblas_diagonal_non_unit, m, jb, &one, Ajj, lda, Aij, lda) != rocblas_status_success) {
-      set_error("rocblas_dtrsm failed (n=%d, column %d)", n, j0);
-      return GPL_EHIP;
-    }
-    double* Att = A + (size_t)(j0 + jb) * lda + (j0 + jb);
-    if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, m, jb, &minus_one, Aij, lda, &one, Att, lda) !=
-        rocblas_status_success) {
-      set_error("rocblas_dsyrk failed (n=%d, column %d)", n, j0);
-      return GPL_EHIP;
-    }
+  if (rocsolver_dpotrf(h, rocblas_fill_lower, n, A, lda, info) != rocblas_status_success) {
+    set_error("rocsolver_dpotrf failed (n=%d)", n);
+    return GPL_EHIP;
   }
+  hipLaunchKernelGGL(diag_log_kernel, dim3(cdiv(n, 256)), dim3(256), 0, stream, n, A, lda, logd);
+  GPL_LAUNCH_CHECK();
   if (logdet) {
     hipLaunchKernelGGL(logdet_fold_kernel, dim3(1), dim3(64), 0, stream, n, logd, logdet);
     GPL_LAUNCH_CHECK();
   }
+  if (inverse && rocsolver_dpotri(h, rocblas_fill_lower, n, A, lda, info) != rocblas_status_success) {
+    set_error("rocsolver_dpotri failed (n=%d)", n);
+    return GPL_EHIP;
+  }
+  return GPL_OK;
+}
+
+// One row of B per thread: x R^T = b, i.e. x_v = (b_v - sum_{w<v} x_w R[v][w]) / R[v][v].
+// R is read from LDS at the same address by every lane (broadcast).
+constexpr int kTri = 64;
+__global__ __launch_bounds__(256) void trsm_rows64_kernel(int m, const double* __restrict__ R, double* B, int ldb) {
+  __shared__ double Rl[kTri][kTri];  // Rl[v][w] = R[v][w]
+  __shared__ double idg[kTri];
+  for (int e = threadIdx.x; e < kTri * kTri; e += blockDim.x) {
+    const int w = e / kTri, v = e - w * kTri;  // column-major: element (v, w) at w * 64 + v
+    Rl[v][w] = R[e];
+  }
+  __syncthreads();
+  if (threadIdx.x < kTri) idg[threadIdx.x] = 1.0 / Rl[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double x[kTri];
+#pragma unroll
+  for (int v = 0; v < kTri; ++v) x[v] = B[(size_t)v * ldb + i];
+#pragma unroll
+  for (int v = 0; v < kTri; ++v) {
+    double acc = x[v];
+#pragma unroll
+    for (int w = 0; w < v; ++w) acc = fma(-x[w], Rl[v][w], acc);
+    x[v] = acc * idg[v];
+  }
+#pragma unroll
+  for (int v = 0; v < kTri; ++v) B[(size_t)v * ldb + i] = x[v];
+}
+
+int trsm_rows64(int m, const double* R, double* B, int ldb, hipStream_t stream) {
+  if (m <= 0) return GPL_OK;
+  hipLaunchKernelGGL(trsm_rows64_kernel, dim3(cdiv(m, 256)), dim3(256), 0, stream, m, R, B, ldb);
+  GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include "common.hpp"
 
@@ -14,12 +15,23 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
 // Scratch memory handed to rocBLAS by every call that uses it.
 constexpr size_t kBlasScratch = size_t(32) << 20;
 
+// Scratch memory of the handle for the dense factorisations of the
+// preconditioner (rocSOLVER's Cholesky and inverse of a matrix of the rank's
+// size take their device memory from it).
+constexpr size_t kSolverScratch = size_t(256) << 20;
+
 // In-place lower Cholesky of the n x n matrix A (column-major, lda >= n; only
-// the lower triangle is read; the strict upper triangle is zeroed block by
-// block). logd[n] receives ln of the factor's diagonal, *logdet (nullable) =
-// ln|A|, *info = 0 or the first failing column + 1 (device scalars).
-int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info,
+// the lower triangle is read and written) by rocSOLVER, then, with `inverse`,
+// the lower triangle of A^{-1} in its place. logd[n] receives ln of the factor's
+// diagonal, *logdet (nullable) = ln|A| summed from it in index order, *info = 0
+// or the order of the first non-positive leading minor (device scalars).
+int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info, bool inverse,
                    hipStream_t stream);
+
+// B (m x 64, column-major, ld ldb) = B R^{-T} in place for the lower 64 x 64
+// factor R (column-major, ld 64): each row solves x R^T = b by forward
+// substitution, one row per thread, R in LDS.
+int trsm_rows64(int m, const double* R, double* B, int ldb, hipStream_t stream);
 
 // C (m x n) = alpha op(A) op(B) + beta C with the reduction dimension kdim
 // split into nsplit parts (rocBLAS strided-batched products into scratch, then

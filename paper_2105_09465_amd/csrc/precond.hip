@@ -223,29 +223,41 @@ __global__ void gather_rows_kernel(int j, const double* __restrict__ L, int ldl,
 }
 
 // Pivoted Cholesky of the residual block S = C[cand, :] (kPcBlock x kPcBlock)
-// by one wave, lane a owning candidate a: each step takes the largest remaining
-// diagonal entry (lowest candidate index on ties) while it exceeds tol (a share
-// of the largest diagonal entry of M, dmax[0]), forms l = S[:, p] / sqrt(S[p][p])
-// and updates S -= l l^T in LDS; the l vectors are kept in LDS too. Outputs order[0..kPcBlock) (taken candidates in pivot order first,
-// then the rest), *taken, and R (kPcBlock x kPcBlock, lower, R[u][v] = l of
-// step v at the u-th pivot; identity on the untaken part).
-__global__ __launch_bounds__(64) void block_pivot_kernel(const double* __restrict__ C, int npix, const int* cand,
-                                                         const double* dmax, double rel_tol, int* order, int* taken,
-                                                         double* R) {
+// in LDS by four waves: lane a of every wave owns candidate a, and wave q
+// updates the columns b of its quarter of the block. Each step takes the
+// largest remaining diagonal entry (lowest candidate index on ties; every wave
+// finds the same one from the same LDS state) while it exceeds tol (a share of
+// the largest diagonal entry of M, dmax[0]), forms l = S[:, p] / sqrt(S[p][p])
+// and updates S -= l l^T; the l vectors are kept in LDS too. Outputs
+// order[0..kPcBlock) (taken candidates in pivot order first, then the rest),
+// *taken, and R (kPcBlock x kPcBlock, lower, R[u][v] = l of step v at the u-th
+// pivot; identity on the untaken part).
+constexpr int kPivWaves = 4;
+constexpr int kPivCols = kPcBlock / kPivWaves;
+__global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const double* __restrict__ C, int npix,
+                                                                     const int* cand, const double* dmax,
+                                                                     double rel_tol, int* order, int* taken,
+                                                                     double* R) {
   // everything in LDS (65 KB): a global store before each barrier would make
   // every barrier wait for it
   __shared__ double S[kPcBlock][kPcBlock + 1];
   __shared__ double lv[kPcBlock][kPcBlock];
   __shared__ double lcol[kPcBlock];
   __shared__ int s_perm[kPcBlock];
-  const int a = threadIdx.x;
+  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int b0 = q * kPivCols;
   const int ca = cand[a];
   // S[b][a] holds entry (a, b) of the block: lane a walks its row along b at
-  // consecutive LDS addresses across the lanes (no bank conflicts)
-  for (int b = 0; b < kPcBlock; ++b) {
-    const int cb = cand[b];
-    S[b][a] = (ca >= 0 && cb >= 0) ? C[(size_t)b * npix + ca] : 0.0;
+  // consecutive LDS addresses across the lanes (no bank conflicts); the loads
+  // of a thread are independent and issued together
+  double ld[kPivCols];
+#pragma unroll
+  for (int u = 0; u < kPivCols; ++u) {
+    const int cb = cand[b0 + u];
+    ld[u] = (ca >= 0 && cb >= 0) ? C[(size_t)(b0 + u) * npix + ca] : 0.0;
   }
+#pragma unroll
+  for (int u = 0; u < kPivCols; ++u) S[b0 + u][a] = ld[u];
   bool used = ca < 0;
   const double tol = rel_tol * dmax[0];
   int cnt = 0;
@@ -266,31 +278,36 @@ __global__ __launch_bounds__(64) void block_pivot_kernel(const double* __restric
     if (!(v > tol)) break;
     const double lpp = sqrt(v);
     const double l = a == p ? lpp : (used ? 0.0 : S[p][a] / lpp);
-    lcol[a] = (a == p || used) ? 0.0 : l;
-    lv[step][a] = l;
-    if (a == 0) s_perm[step] = p;
+    if (q == 0) {
+      lcol[a] = (a == p || used) ? 0.0 : l;
+      lv[step][a] = l;
+      if (a == 0) s_perm[step] = p;
+    }
     __syncthreads();
     if (!used && a != p)
-      for (int b = 0; b < kPcBlock; ++b) S[b][a] -= l * lcol[b];
+#pragma unroll
+      for (int u = 0; u < kPivCols; ++u) S[b0 + u][a] -= l * lcol[b0 + u];
     used = used || a == p;
     cnt = step + 1;
     __syncthreads();
   }
   // order: taken pivots first, then the rest in candidate order
-  if (a == 0) {
-    int q = cnt;
+  if (threadIdx.x == 0) {
+    int qn = cnt;
     for (int b = 0; b < kPcBlock; ++b) {
       bool in_perm = false;
       for (int u = 0; u < cnt; ++u) in_perm |= s_perm[u] == b;
-      if (!in_perm) s_perm[q++] = b;
+      if (!in_perm) s_perm[qn++] = b;
     }
     *taken = cnt;
   }
   __syncthreads();
-  order[a] = s_perm[a];
+  if (q == 0) order[a] = s_perm[a];
   // R[u][v] = lv[v][perm[u]] for v <= u < cnt; identity beyond (column a = v)
   const int vcol = a;
-  for (int u = 0; u < kPcBlock; ++u) {
+#pragma unroll
+  for (int k = 0; k < kPivCols; ++k) {
+    const int u = b0 + k;
     double val = 0.0;
     if (u < cnt && vcol < cnt) val = vcol <= u ? lv[vcol][s_perm[u]] : 0.0;
     else if (u == vcol) val = 1.0;
@@ -406,7 +423,7 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.is_piv = c.template take<int>(npix);
   b.mvm_bytes = mvm_workspace(N, kPcBlock, prec);
   b.mvm_ws = c.template take<char>(b.mvm_bytes);
-  b.blas = c.template take<char>(kBlasScratch);
+  b.blas = c.template take<char>(kSolverScratch);
 }
 
 static int check_pc_problem(const gpl_problem* prob, Taps& taps) {
@@ -432,7 +449,7 @@ struct PcgState {
 
 struct PcgBuf {
   float *R, *P, *AP, *T2, *Z;
-  double *R64, *Z64, *W, *split;
+  double *R64, *Z64, *W, *W2, *split;
   size_t split_elems;  // doubles of split
   int ldv, ldf;
   void* mvm_ws;
@@ -460,6 +477,7 @@ static void carve_pcg(Cv& c, int npix, int N, int n, int ss, int k, int nrhs, in
   b.R64 = c.template take<double>((size_t)b.ldv * nrhs);
   b.Z64 = c.template take<double>((size_t)b.ldv * nrhs);
   b.W = c.template take<double>((size_t)std::max(k, 1) * nrhs);
+  b.W2 = c.template take<double>((size_t)std::max(k, 1) * nrhs);
   b.split_elems =
       std::max(split_gemm_scratch(nrhs, std::max(k, 1), kPcSplits), split_gemm_scratch(npix, nrhs, kPcSplits)) /
       sizeof(double);
@@ -488,24 +506,22 @@ __global__ __launch_bounds__(256) void pcg_widen_kernel(int npix, const float* _
   Z64[(size_t)c * ldv + i] = v;
 }
 
-// P^{-1} R for every column: Wt = R64^T L (m x k); Wt = Wt G^{-1} (two
-// triangular solves with the factor of G from the right; G is symmetric);
-// Z64 = R64 - L Wt^T. Both products with L have one short side (m columns)
+// P^{-1} R for every column: Wt = R64^T L (m x k); W2 = Wt G^{-1} (one
+// symmetric product with the inverse the build left in G's lower triangle);
+// Z64 = R64 - L W2^T. Both products with L have one short side (m columns)
 // and run with their long reduction split. The caller finishes Z = Z64 / s.
-static int woodbury(rocblas_handle h, int npix, int k, const double* L, int ldl, const double* G, int ldg, int nrhs,
-                    const double* R64, double* Z64, int ldv, double* Wt, double* split, size_t split_elems,
-                    hipStream_t stream) {
-  const double one = 1.0;
+static int woodbury(rocblas_handle h, int npix, int k, const double* L, int ldl, const double* Gi, int ldg, int nrhs,
+                    const double* R64, double* Z64, int ldv, double* Wt, double* W2, double* split,
+                    size_t split_elems, hipStream_t stream) {
+  const double one = 1.0, zero = 0.0;
   GPL_TRY(split_gemm(h, rocblas_operation_transpose, rocblas_operation_none, nrhs, k, npix, kPcSplits, 1.0, R64, ldv,
                      L, ldl, 0.0, Wt, nrhs, split, split_elems, stream));
-  if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                    rocblas_diagonal_non_unit, nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success ||
-      rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit,
-                    nrhs, k, &one, G, ldg, Wt, nrhs) != rocblas_status_success) {
-    set_error("rocblas_dtrsm (preconditioner) failed");
+  if (rocblas_dsymm(h, rocblas_side_right, rocblas_fill_lower, nrhs, k, &one, Gi, ldg, Wt, nrhs, &zero, W2, nrhs) !=
+      rocblas_status_success) {
+    set_error("rocblas_dsymm (preconditioner) failed");
     return GPL_EHIP;
   }
-  return split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, nrhs, k, kPcSplits, -1.0, L, ldl, Wt,
+  return split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, nrhs, k, kPcSplits, -1.0, L, ldl, W2,
                     nrhs, 1.0, Z64, ldv, split, split_elems, stream);
 }
 
@@ -862,7 +878,7 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   carve_pc(cv, npix, N, k, prec, b);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   rocblas_handle h;
-  GPL_TRY(blas_handle(&h, stream, b.blas, kBlasScratch));
+  GPL_TRY(blas_handle(&h, stream, b.blas, kSolverScratch));
   MvmCtx mv;
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid,
                       kPcBlock, prec, b.mvm_ws, b.mvm_bytes, stream));
@@ -898,32 +914,29 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
                          std::min(kPcSplits, std::max(1, j0 / 256)), -1.0, L, ldl, b.Lc, kPcBlock, 1.0, b.C, npix,
                          b.split, b.split_elems, stream));
     }
-    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64), 0, stream, b.C, npix, b.cand, b.dmax, kPcRelTol,
+    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64 * kPivWaves), 0, stream, b.C, npix, b.cand, b.dmax,
+                       kPcRelTol,
                        b.order, b.taken, b.R);
     GPL_LAUNCH_CHECK();
     double* Lnew = L + (size_t)j0 * ldl;
     hipLaunchKernelGGL(gather_cols_kernel, gcol, dim3(256), 0, stream, npix, b.C, b.order, b.taken, Lnew, ldl);
     GPL_LAUNCH_CHECK();
-    if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                      rocblas_diagonal_non_unit, npix, kPcBlock, &one, b.R, kPcBlock, Lnew, ldl) !=
-        rocblas_status_success) {
-      set_error("rocblas_dtrsm (new columns) failed");
-      return GPL_EHIP;
-    }
+    GPL_TRY(trsm_rows64(npix, b.R, Lnew, ldl, stream));  // Lnew = C[:, order] R^{-T}
     hipLaunchKernelGGL(diag_update_kernel, dim3(cdiv(std::max(npix, kPcBlock), 256)), dim3(256), 0, stream, npix,
                        b.d, Lnew, ldl, b.cand, b.order, b.taken, b.R, b.is_piv, pivots, j0);
     GPL_LAUNCH_CHECK();
   }
-  // G = s I + L^T L and its Cholesky factor; ln|P|
+  // G = s I + L^T L, its Cholesky factor (for ln|P|) and then its inverse
   const double s = prob->noise_sigma * prob->noise_sigma;
-  if (rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, k, npix, &one, L, ldl, L, ldl, &zero,
-                    G, ldg) != rocblas_status_success) {
-    set_error("rocblas_dgemm (L^T L) failed");
+  // lower triangle only (all the factorisation reads)
+  if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, k, npix, &one, L, ldl, &zero, G, ldg) !=
+      rocblas_status_success) {
+    set_error("rocblas_dsyrk (L^T L) failed");
     return GPL_EHIP;
   }
   hipLaunchKernelGGL(add_diag_kernel, dim3(cdiv(k, 256)), dim3(256), 0, stream, k, G, ldg, s);
   GPL_LAUNCH_CHECK();
-  GPL_TRY(dense_cholesky(h, G, k, ldg, b.logd, b.logdet_g, info, stream));
+  GPL_TRY(dense_cholesky(h, G, k, ldg, b.logd, b.logdet_g, info, true, stream));
   hipLaunchKernelGGL(logdet_p_kernel, dim3(1), dim3(64), 0, stream, npix, k, s, b.logdet_g, logdet_P);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
@@ -1013,7 +1026,7 @@ extern "C" int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, in
   GPL_LAUNCH_CHECK();
   hipLaunchKernelGGL(pcg_widen_kernel, gv, dim3(256), 0, stream, npix, b.R, b.ldv, b.R64, b.Z64);
   GPL_LAUNCH_CHECK();
-  GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, b.split_elems, stream));
+  GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.W2, b.split, b.split_elems, stream));
   hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z, b.rz_part,
                      nb, (const PcgState*)nullptr, (const int*)nullptr);
   GPL_LAUNCH_CHECK();
@@ -1040,7 +1053,7 @@ extern "C" int gpl_pcg_solve(const gpl_problem* prob, int k, const double* L, in
                          b.Z64, b.pap_part, b.ntiles, b.rr_part, nb, b.st[p], b.st[1 - p], b.n_active + p,
                          b.n_active + (1 - p));
       GPL_LAUNCH_CHECK();
-      GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.split, b.split_elems, stream));
+      GPL_TRY(woodbury(h, npix, k, L, ldl, G, ldg, nrhs, b.R64, b.Z64, b.ldv, b.W, b.W2, b.split, b.split_elems, stream));
       hipLaunchKernelGGL(pcg_zfinish_kernel, gv, dim3(256), 0, stream, npix, b.Z64, b.ldv, inv_s, b.R, b.Z,
                          b.rz_part, nb, (const PcgState*)b.st[p], (const int*)(b.n_active + p));
       GPL_LAUNCH_CHECK();

@@ -68,7 +68,7 @@ def test_pchol_factor_vs_oracle(G, prec):
     chose: L L^T reproduces the pivot columns of the exact M (interpolation, to
     the product's accuracy); the leading columns (largest pivots) match the
     oracle's factor for the same pivot order; ln|P| equals the determinant
-    lemma on the returned factor and nearly the oracle's; the factor of
+    lemma on the returned factor and nearly the oracle's; the inverse of
     sigma^2 I + L^T L is exact; the selection rule holds."""
     k = 128
     _say("pchol vs oracle", prec, k)
@@ -99,7 +99,8 @@ def test_pchol_factor_vs_oracle(G, prec):
     assert math.isclose(ldp, ld_o, rel_tol=1e-4)
     Gf = t64(pc["G"]).T
     Gm = s * np.eye(k) + Lg.T @ Lg
-    assert np.allclose(np.tril(Gf) @ np.tril(Gf).T, Gm, rtol=0, atol=1e-10 * np.abs(Gm).max())
+    Gi = np.tril(Gf) + np.tril(Gf, -1).T  # the inverse, from its lower triangle
+    assert np.allclose(Gi @ Gm, np.eye(k), rtol=0, atol=1e-9)
     # selection rule: the first block's pivots are among the 64 largest diagonal
     # entries of M (ranked in FP32; rounding may swap entries at the boundary),
     # the first pivot is the largest, and the first pivot of the second block is
@@ -141,7 +142,7 @@ def test_pchol_rank_beyond_sixteen_splits(G):
     """Rank 4480 on a 72 x 72 image (5184 pixels): from the 69th block on, the
     residual columns' reduction over the earlier pivots (more than 16 x 256 of
     them) is split at most as far as its scratch holds. The pivots taken still
-    reproduce their columns of M, the factor of sigma^2 I + L^T L is exact, and
+    reproduce their columns of M, the inverse of sigma^2 I + L^T L is exact, and
     ln|P| follows the determinant lemma."""
     k = 4480
     _say("pchol rank 4480", "72x72")
@@ -168,7 +169,8 @@ def test_pchol_rank_beyond_sixteen_splits(G):
     Lall = t64(pc["L"]).T
     Gf = t64(pc["G"]).T
     Gm = s * np.eye(k) + Lall.T @ Lall
-    assert np.allclose(np.tril(Gf) @ np.tril(Gf).T, Gm, rtol=0, atol=1e-10 * np.abs(Gm).max())
+    Gi = np.tril(Gf) + np.tril(Gf, -1).T  # the inverse, from its lower triangle
+    assert np.allclose(Gi @ Gm, np.eye(k), rtol=0, atol=1e-9)
     assert math.isclose(float(pc["logdet_P"].item()), opc.logdet_lowrank_plus_shift(Lall, s), rel_tol=1e-10)
 
 
