@@ -7,16 +7,16 @@
 // columns taken 64 at a time: the 64 largest remaining diagonal entries of
 // M - L L^T are the candidates; their columns of M come from one application of
 // B K B^T to unit vectors (the matrix-free product), minus L L^T on them
-// (rocBLAS dgemm); one workgroup runs a pivoted Cholesky on the 64 x 64
-// residual block (largest remaining diagonal first, stopping below a relative
-// threshold), and the block's columns of L follow by a triangular solve
-// (dtrsm). Candidates the block does not take leave zero columns, which change
-// neither L L^T nor the determinant identity below. Then
-//   G = sigma^2 I_k + L^T L = R R^T (dgemm, blocked Cholesky),
+// (split-K rocBLAS dgemm); one four-wave workgroup runs a pivoted Cholesky on
+// the 64 x 64 residual block (largest remaining diagonal first, stopping below
+// a relative threshold), and the block's columns of L follow by a row-parallel
+// triangular solve. Candidates the block does not take leave zero columns,
+// which change neither L L^T nor the determinant identity below. Then
+//   G = sigma^2 I_k + L^T L = R R^T (dsyrk, rocSOLVER dpotrf; dpotri leaves
+//   G^{-1} in the lower triangle),
 //   ln|P| = (n - k) ln sigma^2 + ln|G|,  P = L L^T + sigma^2 I_n.
 // Solve. Preconditioned CG, one recurrence per column, with
-//   P^{-1} v = (v - L G^{-1} L^T v) / sigma^2 (dgemm, two dtrsm, dgemm in
-//   transposed form),
+//   P^{-1} v = (v - L G^{-1} L^T v) / sigma^2 (dgemm, dsymm, dgemm),
 // FP32 vectors, FP64 scalars and Woodbury products; the alpha/beta of the
 // first steps give the Lanczos tridiagonal of P^{-1/2} A P^{-1/2} with the
 // usual CG formulas, and rz0 = b^T P^{-1} b is each probe's quadrature weight.
