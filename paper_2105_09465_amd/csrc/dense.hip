@@ -1,9 +1,8 @@
 // Dense FP64 linear algebra for the preconditioner: a rocBLAS handle per host
 // thread and device (its scratch memory always taken from the caller's
-// workspace), the Cholesky factor and inverse of a dense matrix by rocSOLVER
-// (the log-determinant summed from the factor's diagonal in a fixed order), a
-// row-parallel triangular solve with a 64 x 64 factor, and GEMMs with a long
-// reduction split over the device.
+// workspace), the inverse and log-determinant of a symmetric positive definite
+// matrix by bordering in 64 x 64 blocks, and GEMMs with a long reduction split
+// over the device.
 #include <cmath>
 
 #include "common.hpp"
@@ -34,70 +33,143 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
   return GPL_OK;
 }
 
-// logd[c] = ln A[c][c] of a factor's diagonal.
-__global__ void diag_log_kernel(int n, const double* __restrict__ A, int lda, double* logd) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) logd[c] = log(A[(size_t)c * lda + c]);
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
 }
 
-// out[0] = sum of logd[0..n) in index order (one wave, lane-strided then a
-// butterfly), times two: ln|A| of the factored matrix.
-__global__ void logdet_fold_kernel(int n, const double* logd, double* out) {
-  const double s = wave_fold_sum(logd, n);
-  if (threadIdx.x == 0) *out = 2.0 * s;
+// out[0] = sum of part[0..n) (one wave, lane-strided then a butterfly: a fixed
+// order).
+__global__ void fold_sum_kernel(int n, const double* part, double* out) {
+  const double s = wave_fold_sum(part, n);
+  if (threadIdx.x == 0) *out = s;
 }
 
-int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info, bool inverse,
-                   hipStream_t stream) {
-  if (rocsolver_dpotrf(h, rocblas_fill_lower, n, A, lda, info) != rocblas_status_success) {
-    set_error("rocsolver_dpotrf failed (n=%d)", n);
-    return GPL_EHIP;
+// One diagonal block of the bordered inverse. S = Gbb - T from the lower
+// triangle of Gbb (T = Y B^T, a 64 x 64 column-major block; null for the first
+// block); its Cholesky factor D by four waves in the layout of the block pivot
+// (lane a holds row a, wave q the columns [16q, 16q + 16) in registers, every
+// wave a copy of the diagonal; one barrier per step, the update vector
+// double-buffered by step parity); Dinv = D^{-1} by wave 0 (lane c solves
+// column c by forward substitution, the updates of a column's remaining rows
+// being independent); S^{-1} = Dinv^T Dinv written over Gbb (both triangles,
+// bitwise symmetric); *ld_part = ln|S|. A pivot that is not positive and finite
+// sets *info to its global index + 1 (when *info is still 0) and is replaced by
+// 1 so that every value stays finite.
+constexpr int kSpd = 64;
+__global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, const double* __restrict__ T,
+                                                        double* __restrict__ Dinv, double* ld_part, int* info,
+                                                        int j0) {
+  __shared__ double lv[kSpd][kSpd];      // lv[p][a] = D(a, p) (0 above the diagonal)
+  __shared__ double lz[2][kSpd];         // step p: D(a, p) for a > p, else 0
+  __shared__ double Di[kSpd][kSpd + 1];  // Di[r][c] = Dinv(r, c)
+  __shared__ double idg[kSpd];
+  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int b0 = q * 16;
+  double s[16];  // s[u] = S(a, b0 + u)
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int b = b0 + u, r = max(a, b), c = min(a, b);
+    s[u] = Gbb[(size_t)c * ldg + r] - (T ? T[(size_t)c * kSpd + r] : 0.0);
   }
-  hipLaunchKernelGGL(diag_log_kernel, dim3(cdiv(n, 256)), dim3(256), 0, stream, n, A, lda, logd);
+  double dg = Gbb[(size_t)a * ldg + a] - (T ? T[(size_t)a * kSpd + a] : 0.0);
+  double lsum = 0.0;
+  int bad = -1;
+  for (int p = 0; p < kSpd; ++p) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)__double_as_longlong(dg), p);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)__double_as_longlong(dg) >> 32), p);
+    const double dpp = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    const bool ok = dpp > 0.0 && isfinite(dpp);
+    if (!ok && bad < 0) bad = p;
+    const double pv = ok ? dpp : 1.0;
+    lsum += log(pv);  // ln D(p, p)^2
+    const int buf = p & 1;
+    if (q == p / 16) {  // this wave holds column p
+      const int pu = p - b0;
+      double sp = s[0];
+#pragma unroll
+      for (int u = 1; u < 16; ++u) sp = u == pu ? s[u] : sp;
+      const double lpp = sqrt(pv);
+      const double l = a == p ? lpp : (a > p ? sp / lpp : 0.0);
+      lv[p][a] = l;
+      lz[buf][a] = a > p ? l : 0.0;
+    }
+    __syncthreads();
+    const double la = lz[buf][a];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s[u] -= la * lz[buf][b0 + u];
+    dg -= la * la;
+  }
+  if (threadIdx.x < kSpd) idg[threadIdx.x] = 1.0 / lv[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  if (q == 0) {
+    double x[kSpd];
+#pragma unroll
+    for (int r = 0; r < kSpd; ++r) x[r] = r == a ? 1.0 : 0.0;
+#pragma unroll
+    for (int r = 0; r < kSpd; ++r) {
+      x[r] *= idg[r];
+#pragma unroll
+      for (int w = r + 1; w < kSpd; ++w) x[w] = fma(-lv[r][w], x[r], x[w]);
+    }
+#pragma unroll
+    for (int r = 0; r < kSpd; ++r) {
+      Di[r][a] = x[r];
+      Dinv[(size_t)a * kSpd + r] = x[r];
+    }
+  }
+  __syncthreads();
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  for (int r = 0; r < kSpd; ++r) {
+    const double xa = Di[r][a];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = fma(xa, Di[r][b0 + u], acc[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) Gbb[(size_t)(b0 + u) * ldg + a] = acc[u];
+  if (threadIdx.x == 0) {
+    *ld_part = lsum;
+    if (bad >= 0 && *info == 0) *info = j0 + bad + 1;
+  }
+}
+
+int spd_inverse(rocblas_handle h, double* G, int k, int ldg, const SpdScratch& w, double* logdet, int* info,
+                hipStream_t stream) {
+  GPL_REQUIRE(k > 0 && k % kSpd == 0, "order %d must be a positive multiple of %d", k, kSpd);
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, stream, info, 0);
   GPL_LAUNCH_CHECK();
-  if (logdet) {
-    hipLaunchKernelGGL(logdet_fold_kernel, dim3(1), dim3(64), 0, stream, n, logd, logdet);
+  const double one = 1.0, minus_one = -1.0, zero = 0.0;
+  const auto N = rocblas_operation_none, Tr = rocblas_operation_transpose;
+  for (int j0 = 0; j0 < k; j0 += kSpd) {
+    double* Gb = G + j0;                          // G[b, :b] (read), then Ginv[b, :b]
+    double* Gbb = G + (size_t)j0 * ldg + j0;      // G[b, b], then Ginv[b, b]
+    double* Gcol = G + (size_t)j0 * ldg;          // Ginv[:b, b]
+    if (j0 > 0) {
+      // Y = G[b, :b] Ginv[:b, :b];  T = Y G[b, :b]^T = G[b, :b] Ginv G[b, :b]^T
+      GPL_TRY(split_gemm(h, N, N, kSpd, j0, j0, std::max(1, std::min(16, j0 / 256)), 1.0, Gb, ldg, G, ldg, 0.0,
+                         w.Y, kSpd, w.split, w.split_elems, stream));
+      GPL_TRY(split_gemm(h, N, Tr, kSpd, kSpd, j0, std::max(1, j0 / 64), 1.0, w.Y, kSpd, Gb, ldg, 0.0, w.T, kSpd,
+                         w.split, w.split_elems, stream));
+    }
+    hipLaunchKernelGGL(spd_block_kernel, dim3(1), dim3(256), 0, stream, Gbb, ldg, j0 > 0 ? w.T : nullptr, w.Dinv,
+                       w.ld_part + j0 / kSpd, info, j0);
     GPL_LAUNCH_CHECK();
+    if (j0 > 0) {
+      // W = Dinv Y; Ginv[:b, :b] += W^T W (= Y^T S^{-1} Y); Ginv[b, :b] = -Dinv^T W (= -S^{-1} Y) and its transpose
+      if (rocblas_dgemm(h, N, N, kSpd, j0, kSpd, &one, w.Dinv, kSpd, w.Y, kSpd, &zero, w.W, kSpd) !=
+              rocblas_status_success ||
+          rocblas_dgemm(h, Tr, N, j0, j0, kSpd, &one, w.W, kSpd, w.W, kSpd, &one, G, ldg) != rocblas_status_success ||
+          rocblas_dgemm(h, Tr, N, kSpd, j0, kSpd, &minus_one, w.Dinv, kSpd, w.W, kSpd, &zero, Gb, ldg) !=
+              rocblas_status_success ||
+          rocblas_dgemm(h, Tr, N, j0, kSpd, kSpd, &minus_one, w.W, kSpd, w.Dinv, kSpd, &zero, Gcol, ldg) !=
+              rocblas_status_success) {
+        set_error("rocblas_dgemm (bordered inverse, block at %d) failed", j0);
+        return GPL_EHIP;
+      }
+    }
   }
-  if (inverse && rocsolver_dpotri(h, rocblas_fill_lower, n, A, lda, info) != rocblas_status_success) {
-    set_error("rocsolver_dpotri failed (n=%d)", n);
-    return GPL_EHIP;
-  }
-  return GPL_OK;
-}
-
-// One row of B per thread: x R^T = b, i.e. x_v = (b_v - sum_{w<v} x_w R[v][w]) / R[v][v].
-// R is read from LDS at the same address by every lane (broadcast).
-constexpr int kTri = 64;
-__global__ __launch_bounds__(256) void trsm_rows64_kernel(int m, const double* __restrict__ R, double* B, int ldb) {
-  __shared__ double Rl[kTri][kTri];  // Rl[v][w] = R[v][w]
-  __shared__ double idg[kTri];
-  for (int e = threadIdx.x; e < kTri * kTri; e += blockDim.x) {
-    const int w = e / kTri, v = e - w * kTri;  // column-major: element (v, w) at w * 64 + v
-    Rl[v][w] = R[e];
-  }
-  __syncthreads();
-  if (threadIdx.x < kTri) idg[threadIdx.x] = 1.0 / Rl[threadIdx.x][threadIdx.x];
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  double x[kTri];
-#pragma unroll
-  for (int v = 0; v < kTri; ++v) x[v] = B[(size_t)v * ldb + i];
-#pragma unroll
-  for (int v = 0; v < kTri; ++v) {
-    double acc = x[v];
-#pragma unroll
-    for (int w = 0; w < v; ++w) acc = fma(-x[w], Rl[v][w], acc);
-    x[v] = acc * idg[v];
-  }
-#pragma unroll
-  for (int v = 0; v < kTri; ++v) B[(size_t)v * ldb + i] = x[v];
-}
-
-int trsm_rows64(int m, const double* R, double* B, int ldb, hipStream_t stream) {
-  if (m <= 0) return GPL_OK;
-  hipLaunchKernelGGL(trsm_rows64_kernel, dim3(cdiv(m, 256)), dim3(256), 0, stream, m, R, B, ldb);
+  hipLaunchKernelGGL(fold_sum_kernel, dim3(1), dim3(64), 0, stream, k / kSpd, w.ld_part, logdet);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

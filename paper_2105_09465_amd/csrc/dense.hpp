@@ -2,7 +2,6 @@
 #pragma once
 
 #include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include "common.hpp"
 
@@ -15,23 +14,25 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
 // Scratch memory handed to rocBLAS by every call that uses it.
 constexpr size_t kBlasScratch = size_t(32) << 20;
 
-// Scratch memory of the handle for the dense factorisations of the
-// preconditioner (rocSOLVER's Cholesky and inverse of a matrix of the rank's
-// size take their device memory from it).
-constexpr size_t kSolverScratch = size_t(256) << 20;
-
-// In-place lower Cholesky of the n x n matrix A (column-major, lda >= n; only
-// the lower triangle is read and written) by rocSOLVER, then, with `inverse`,
-// the lower triangle of A^{-1} in its place. logd[n] receives ln of the factor's
-// diagonal, *logdet (nullable) = ln|A| summed from it in index order, *info = 0
-// or the order of the first non-positive leading minor (device scalars).
-int dense_cholesky(rocblas_handle h, double* A, int n, int lda, double* logd, double* logdet, int* info, bool inverse,
-                   hipStream_t stream);
-
-// B (m x 64, column-major, ld ldb) = B R^{-T} in place for the lower 64 x 64
-// factor R (column-major, ld 64): each row solves x R^T = b by forward
-// substitution, one row per thread, R in LDS.
-int trsm_rows64(int m, const double* R, double* B, int ldb, hipStream_t stream);
+// Inverse and log-determinant of a symmetric positive definite k x k matrix
+// (k a multiple of 64) by bordering: with Ginv the inverse of the leading
+// block A already formed, the next 64 rows B and diagonal block C give
+// Y = B A^{-1}, the Schur complement S = C - Y B^T (its Cholesky factor D and
+// D^{-1} in one workgroup), W = D^{-1} Y and
+//   inverse = [[A^{-1} + W^T W, -(D^{-T} W)^T], [-D^{-T} W, S^{-1}]],
+//   ln|G| = ln|A| + ln|S|.
+// G (column-major, ldg) is read from its lower triangle and receives the whole
+// inverse in place (both triangles); *logdet = ln|G| (the blocks' parts summed
+// in a fixed order); *info = 0, or 1 + the index of the first pivot of a
+// diagonal block that was not positive (the inverse is then meaningless).
+// Scratch (device, doubles): Y and W 64 x k, T and Dinv 64 x 64, ld_part k / 64,
+// split for the split products (split_elems doubles, at least 64 x k).
+struct SpdScratch {
+  double *Y, *W, *T, *Dinv, *ld_part, *split;
+  size_t split_elems;
+};
+int spd_inverse(rocblas_handle h, double* G, int k, int ldg, const SpdScratch& w, double* logdet, int* info,
+                hipStream_t stream);
 
 // C (m x n) = alpha op(A) op(B) + beta C with the reduction dimension kdim
 // split into nsplit parts (rocBLAS strided-batched products into scratch, then

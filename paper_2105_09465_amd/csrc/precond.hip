@@ -12,8 +12,8 @@
 // a relative threshold), and the block's columns of L follow by a row-parallel
 // triangular solve. Candidates the block does not take leave zero columns,
 // which change neither L L^T nor the determinant identity below. Then
-//   G = sigma^2 I_k + L^T L = R R^T (dsyrk, rocSOLVER dpotrf; dpotri leaves
-//   G^{-1} in the lower triangle),
+//   G = sigma^2 I_k + L^T L (dsyrk), then G^{-1} and ln|G| by bordering in
+//   64 x 64 blocks (Schur complements, their Cholesky factors and inverses),
 //   ln|P| = (n - k) ln sigma^2 + ln|G|,  P = L L^T + sigma^2 I_n.
 // Solve. Preconditioned CG, one recurrence per column, with
 //   P^{-1} v = (v - L G^{-1} L^T v) / sigma^2 (dgemm, dsymm, dgemm),
@@ -223,86 +223,111 @@ __global__ void gather_rows_kernel(int j, const double* __restrict__ L, int ldl,
 }
 
 // Pivoted Cholesky of the residual block S = C[cand, :] (kPcBlock x kPcBlock)
-// in LDS by four waves: lane a of every wave owns candidate a, and wave q
-// updates the columns b of its quarter of the block. Each step takes the
-// largest remaining diagonal entry (lowest candidate index on ties; every wave
-// finds the same one from the same LDS state) while it exceeds tol (a share of
-// the largest diagonal entry of M, dmax[0]), forms l = S[:, p] / sqrt(S[p][p])
-// and updates S -= l l^T; the l vectors are kept in LDS too. Outputs
-// order[0..kPcBlock) (taken candidates in pivot order first, then the rest),
-// *taken, and R (kPcBlock x kPcBlock, lower, R[u][v] = l of step v at the u-th
-// pivot; identity on the untaken part).
+// by four waves: lane a of every wave owns candidate a, and wave q holds the
+// entries (a, b) of its quarter of the columns b in registers. Every wave also
+// keeps the residual diagonal (lane a: entry (a, a)) and finds each step's
+// pivot itself: the largest remaining diagonal entry (lowest candidate index on
+// ties), while it exceeds tol (a share of the largest diagonal entry of M,
+// dmax[0]). The wave holding column p forms l = S[:, p] / sqrt(S[p][p]) and
+// publishes it in LDS; after one barrier every wave applies S -= l l^T to its
+// registers and to its copy of the diagonal (l is double-buffered by step
+// parity, so one barrier per step suffices). Outputs order[0..kPcBlock) (taken
+// candidates in pivot order first, then the rest), *taken, and R (kPcBlock x
+// kPcBlock, lower, R[u][v] = l of step v at the u-th pivot; identity on the
+// untaken part).
 constexpr int kPivWaves = 4;
 constexpr int kPivCols = kPcBlock / kPivWaves;
+
+// A 64-bit value of another lane of the same row of 16 lanes (DPP control CTRL).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long k) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)k, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(k >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Largest 64-bit key of the wave (every lane active), in every lane: the
+// maximum within each row of 16 lanes by DPP (exchanges inside quads, then
+// rotations of the row by 4 and 8 lanes), then the four row maxima as scalars.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  unsigned long long o;
+  o = dpp_u64<0xB1>(k);  // quad_perm [1, 0, 3, 2]
+  k = o > k ? o : k;
+  o = dpp_u64<0x4E>(k);  // quad_perm [2, 3, 0, 1]
+  k = o > k ? o : k;
+  o = dpp_u64<0x124>(k);  // row_ror:4
+  k = o > k ? o : k;
+  o = dpp_u64<0x128>(k);  // row_ror:8
+  k = o > k ? o : k;
+  unsigned long long m = 0ull;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)k, 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k >> 32), 16 * r);
+    const unsigned long long x = ((unsigned long long)hi << 32) | lo;
+    m = x > m ? x : m;
+  }
+  return m;
+}
+
 __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const double* __restrict__ C, int npix,
                                                                      const int* cand, const double* dmax,
                                                                      double rel_tol, int* order, int* taken,
                                                                      double* R) {
-  // everything in LDS (65 KB): a global store before each barrier would make
-  // every barrier wait for it
-  __shared__ double S[kPcBlock][kPcBlock + 1];
-  __shared__ double lv[kPcBlock][kPcBlock];
-  __shared__ double lcol[kPcBlock];
+  __shared__ double lv[kPcBlock][kPcBlock];  // lv[step][a]: l of each step
+  __shared__ double lc[2][kPcBlock];         // l with the pivot's and used entries zeroed
   __shared__ int s_perm[kPcBlock];
   const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int b0 = q * kPivCols;
   const int ca = cand[a];
-  // S[b][a] holds entry (a, b) of the block: lane a walks its row along b at
-  // consecutive LDS addresses across the lanes (no bank conflicts); the loads
-  // of a thread are independent and issued together
-  double ld[kPivCols];
+  double s[kPivCols];  // s[u] = entry (a, b0 + u)
 #pragma unroll
   for (int u = 0; u < kPivCols; ++u) {
     const int cb = cand[b0 + u];
-    ld[u] = (ca >= 0 && cb >= 0) ? C[(size_t)(b0 + u) * npix + ca] : 0.0;
+    s[u] = (ca >= 0 && cb >= 0) ? C[(size_t)(b0 + u) * npix + ca] : 0.0;
   }
-#pragma unroll
-  for (int u = 0; u < kPivCols; ++u) S[b0 + u][a] = ld[u];
-  bool used = ca < 0;
+  double dg = ca >= 0 ? C[(size_t)a * npix + ca] : 0.0;  // entry (a, a)
+  bool used = ca < 0, piv = false;
   const double tol = rel_tol * dmax[0];
   int cnt = 0;
-  __syncthreads();
   for (int step = 0; step < kPcBlock; ++step) {
-    // wave argmax of the remaining diagonal, lowest index on ties
-    double v = used ? -1.0 : S[a][a];
-    int idx = a;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off, 64);
-      const int oi = __shfl_xor(idx, off, 64);
-      if (ov > v || (ov == v && oi < idx)) {
-        v = ov;
-        idx = oi;
-      }
-    }
-    const int p = idx;
+    // wave argmax of the remaining diagonal, lowest index on ties: positive
+    // doubles order as their bit patterns; entries <= 0 never exceed tol >= 0
+    const unsigned long long key = (!used && dg > 0.0) ? (unsigned long long)__double_as_longlong(dg) : 0ull;
+    const unsigned long long kmax = wave_max_u64(key);
+    const double v = __longlong_as_double((long long)kmax);
     if (!(v > tol)) break;
-    const double lpp = sqrt(v);
-    const double l = a == p ? lpp : (used ? 0.0 : S[p][a] / lpp);
-    if (q == 0) {
-      lcol[a] = (a == p || used) ? 0.0 : l;
+    const int p = __ffsll((unsigned long long)__ballot(key == kmax)) - 1;
+    const int buf = step & 1;
+    if (q == p / kPivCols) {  // this wave holds column p
+      const int pu = p - b0;
+      double sp = s[0];
+#pragma unroll
+      for (int u = 1; u < kPivCols; ++u) sp = u == pu ? s[u] : sp;
+      const double lpp = sqrt(v);
+      const double l = a == p ? lpp : (used ? 0.0 : sp / lpp);
       lv[step][a] = l;
+      lc[buf][a] = (a == p || used) ? 0.0 : l;
       if (a == 0) s_perm[step] = p;
     }
     __syncthreads();
-    if (!used && a != p)
+    if (!used && a != p) {
+      const double la = lc[buf][a];
 #pragma unroll
-      for (int u = 0; u < kPivCols; ++u) S[b0 + u][a] -= l * lcol[b0 + u];
-    used = used || a == p;
-    cnt = step + 1;
-    __syncthreads();
-  }
-  // order: taken pivots first, then the rest in candidate order
-  if (threadIdx.x == 0) {
-    int qn = cnt;
-    for (int b = 0; b < kPcBlock; ++b) {
-      bool in_perm = false;
-      for (int u = 0; u < cnt; ++u) in_perm |= s_perm[u] == b;
-      if (!in_perm) s_perm[qn++] = b;
+      for (int u = 0; u < kPivCols; ++u) s[u] -= la * lc[buf][b0 + u];
+      dg -= la * la;
     }
-    *taken = cnt;
+    used = used || a == p;
+    piv = piv || a == p;
+    cnt = step + 1;
   }
-  __syncthreads();
-  if (q == 0) order[a] = s_perm[a];
+  // order: taken pivots first (pivot order), then the rest in candidate order
+  const unsigned long long rest = __ballot(!piv);
+  if (q == 0) {
+    if (a < cnt) order[a] = s_perm[a];
+    if (!piv) order[cnt + __popcll(rest & ((1ull << a) - 1ull))] = a;
+    if (a == 0) *taken = cnt;
+  }
   // R[u][v] = lv[v][perm[u]] for v <= u < cnt; identity beyond (column a = v)
   const int vcol = a;
 #pragma unroll
@@ -315,47 +340,74 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
   }
 }
 
-// Lnew[:, u] = C[:, order[u]] for u < taken, 0 beyond (before the solve with R).
-__global__ void gather_cols_kernel(int npix, const double* __restrict__ C, const int* order, const int* taken,
-                                   double* Lnew, int ldl) {
-  const int u = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npix) return;
-  Lnew[(size_t)u * ldl + i] = u < *taken ? C[(size_t)order[u] * npix + i] : 0.0;
-}
-
-// Rows of the new columns that a pivoted Cholesky fixes exactly: zero at the
-// pivots of earlier blocks (their residual is zero; the computed one is
-// rounding noise that the triangular solve would amplify), and R's row u at the
-// block's u-th pivot (the computed columns of M are not exactly symmetric, so
-// the solve alone would not return it). Then d -= sum_u Lnew[i, u]^2 (in u
-// order), clamped at 0, exactly 0 at the new pivots, which are marked in
-// is_piv; pivots[j0 + u] = the pixel of pivot u (-1 where none was taken).
-__global__ void diag_update_kernel(int npix, double* d, double* __restrict__ Lnew, int ldl, const int* cand,
-                                   const int* order, const int* taken, const double* __restrict__ R, int* is_piv,
-                                   int* pivots, int j0) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// The block's new columns of L and the residual diagonal, one thread per pixel
+// row i:
+//   x[u] = C[i, order[u]] for u < taken (0 beyond), then x R^{-T}: forward
+//   substitution taken column by column, so that the updates of a row's
+//   remaining entries are independent (each entry still receives its updates
+//   in the same order as in the row-by-row form);
+//   rows that a pivoted Cholesky fixes exactly: zero at the pivots of earlier
+//   blocks (their residual is zero; the computed one is rounding noise that
+//   the solve would amplify), and R's row u at the block's u-th pivot (the
+//   computed columns of M are not exactly symmetric, so the solve alone would
+//   not return it);
+//   d -= sum_u x[u]^2 (in u order), clamped at 0, exactly 0 at the new pivots,
+//   which are marked in is_piv; pivots[j0 + u] = the pixel of pivot u (-1 where
+//   none was taken).
+__global__ __launch_bounds__(256) void new_columns_kernel(int npix, const double* __restrict__ C, const int* order,
+                                                          const int* taken, const double* __restrict__ R,
+                                                          const int* cand, double* d, int* is_piv,
+                                                          double* __restrict__ Lnew, int ldl, int* pivots, int j0) {
+  __shared__ double Rt[kPcBlock][kPcBlock];  // Rt[v][w] = entry (w, v) of R
+  __shared__ double idg[kPcBlock];
+  __shared__ int s_ord[kPcBlock], s_pix[kPcBlock];
+  const int t = threadIdx.x;
   const int cnt = *taken;
-  if (i < kPcBlock && pivots) pivots[j0 + i] = i < cnt ? cand[order[i]] : -1;
+  for (int e = t; e < kPcBlock * kPcBlock; e += blockDim.x) (&Rt[0][0])[e] = R[e];
+  if (t < kPcBlock) {
+    const int o = order[t];
+    const int pix = t < cnt ? cand[o] : -1;
+    s_ord[t] = o;
+    s_pix[t] = pix;
+    if (blockIdx.x == 0 && pivots) pivots[j0 + t] = pix;
+  }
+  __syncthreads();
+  if (t < kPcBlock) idg[t] = 1.0 / Rt[t][t];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + t;
   if (i >= npix) return;
+  double x[kPcBlock];
+#pragma unroll
+  for (int u = 0; u < kPcBlock; ++u) x[u] = C[(size_t)s_ord[u] * npix + i];  // order[] is a permutation
+#pragma unroll
+  for (int u = 0; u < kPcBlock; ++u) x[u] = u < cnt ? x[u] : 0.0;
+#pragma unroll
+  for (int v = 0; v < kPcBlock; ++v) {
+    x[v] *= idg[v];
+#pragma unroll
+    for (int w = v + 1; w < kPcBlock; ++w) x[w] = fma(-x[v], Rt[v][w], x[w]);
+  }
   int pu = -1;
-  for (int u = 0; u < cnt; ++u)
-    if (cand[order[u]] == i) pu = u;
+#pragma unroll
+  for (int u = 0; u < kPcBlock; ++u) pu = s_pix[u] == i ? u : pu;
   if (is_piv[i]) {
-    for (int u = 0; u < kPcBlock; ++u) Lnew[(size_t)u * ldl + i] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPcBlock; ++u) x[u] = 0.0;
   } else if (pu >= 0) {
-    for (int u = 0; u < kPcBlock; ++u) Lnew[(size_t)u * ldl + i] = u < cnt ? R[(size_t)u * kPcBlock + pu] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kPcBlock; ++u) x[u] = u < cnt ? Rt[u][pu] : 0.0;
   }
   double v = d[i];
-  for (int u = 0; u < cnt; ++u) {
-    const double l = Lnew[(size_t)u * ldl + i];
-    v -= l * l;
-  }
+#pragma unroll
+  for (int u = 0; u < kPcBlock; ++u)
+    if (u < cnt) v -= x[u] * x[u];
   if (pu >= 0) {
     v = 0.0;
     is_piv[i] = 1;
   }
   d[i] = v > 0.0 ? v : 0.0;
+#pragma unroll
+  for (int u = 0; u < kPcBlock; ++u) Lnew[(size_t)u * ldl + i] = x[u];
 }
 
 __global__ void zero_ints_kernel(int* p, int n) {
@@ -392,7 +444,8 @@ __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, 
 
 struct PcBuf {
   float *E, *T1, *T2, *Mc;
-  double *C, *Lc, *R, *d, *dmax, *logd, *logdet_g, *split;
+  double *C, *Lc, *R, *d, *dmax, *logdet_g, *split;
+  double *Y, *W, *T, *Dinv, *ld_part;  // the bordered inverse of sigma^2 I + L^T L
   size_t split_elems;  // doubles of split
   int *cand, *order, *taken, *info, *is_piv;
   void* mvm_ws;
@@ -414,8 +467,12 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.split = c.template take<double>(b.split_elems);
   b.d = c.template take<double>(npix);
   b.dmax = c.template take<double>(1);
-  b.logd = c.template take<double>(std::max(k, 1));
   b.logdet_g = c.template take<double>(1);
+  b.Y = c.template take<double>((size_t)kPcBlock * std::max(k, 1));
+  b.W = c.template take<double>((size_t)kPcBlock * std::max(k, 1));
+  b.T = c.template take<double>((size_t)kPcBlock * kPcBlock);
+  b.Dinv = c.template take<double>((size_t)kPcBlock * kPcBlock);
+  b.ld_part = c.template take<double>(std::max(k / kPcBlock, 1));
   b.cand = c.template take<int>(kPcBlock);
   b.order = c.template take<int>(kPcBlock);
   b.taken = c.template take<int>(1);
@@ -423,7 +480,7 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.is_piv = c.template take<int>(npix);
   b.mvm_bytes = mvm_workspace(N, kPcBlock, prec);
   b.mvm_ws = c.template take<char>(b.mvm_bytes);
-  b.blas = c.template take<char>(kSolverScratch);
+  b.blas = c.template take<char>(kBlasScratch);
 }
 
 static int check_pc_problem(const gpl_problem* prob, Taps& taps) {
@@ -878,7 +935,7 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   carve_pc(cv, npix, N, k, prec, b);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
   rocblas_handle h;
-  GPL_TRY(blas_handle(&h, stream, b.blas, kSolverScratch));
+  GPL_TRY(blas_handle(&h, stream, b.blas, kBlasScratch));
   MvmCtx mv;
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid,
                       kPcBlock, prec, b.mvm_ws, b.mvm_bytes, stream));
@@ -893,7 +950,7 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   GPL_LAUNCH_CHECK();
   const int ldf = round_up(N, 64);
   const dim3 gcol(cdiv(npix, 256), kPcBlock);
-  const double one = 1.0, minus_one = -1.0, zero = 0.0;
+  const double one = 1.0, zero = 0.0;
   for (int j0 = 0; j0 < k; j0 += kPcBlock) {
     hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
     GPL_LAUNCH_CHECK();
@@ -918,17 +975,13 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
                        kPcRelTol,
                        b.order, b.taken, b.R);
     GPL_LAUNCH_CHECK();
-    double* Lnew = L + (size_t)j0 * ldl;
-    hipLaunchKernelGGL(gather_cols_kernel, gcol, dim3(256), 0, stream, npix, b.C, b.order, b.taken, Lnew, ldl);
-    GPL_LAUNCH_CHECK();
-    GPL_TRY(trsm_rows64(npix, b.R, Lnew, ldl, stream));  // Lnew = C[:, order] R^{-T}
-    hipLaunchKernelGGL(diag_update_kernel, dim3(cdiv(std::max(npix, kPcBlock), 256)), dim3(256), 0, stream, npix,
-                       b.d, Lnew, ldl, b.cand, b.order, b.taken, b.R, b.is_piv, pivots, j0);
+    double* Lnew = L + (size_t)j0 * ldl;  // = C[:, order] R^{-T}, fixed rows, and the new residual diagonal
+    hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, npix, b.C, b.order, b.taken,
+                       b.R, b.cand, b.d, b.is_piv, Lnew, ldl, pivots, j0);
     GPL_LAUNCH_CHECK();
   }
-  // G = s I + L^T L, its Cholesky factor (for ln|P|) and then its inverse
+  // G = s I + L^T L (lower triangle), then in place its inverse and ln|G|
   const double s = prob->noise_sigma * prob->noise_sigma;
-  // lower triangle only (all the factorisation reads)
   if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, k, npix, &one, L, ldl, &zero, G, ldg) !=
       rocblas_status_success) {
     set_error("rocblas_dsyrk (L^T L) failed");
@@ -936,7 +989,8 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   }
   hipLaunchKernelGGL(add_diag_kernel, dim3(cdiv(k, 256)), dim3(256), 0, stream, k, G, ldg, s);
   GPL_LAUNCH_CHECK();
-  GPL_TRY(dense_cholesky(h, G, k, ldg, b.logd, b.logdet_g, info, true, stream));
+  GPL_TRY(spd_inverse(h, G, k, ldg, SpdScratch{b.Y, b.W, b.T, b.Dinv, b.ld_part, b.split, b.split_elems},
+                      b.logdet_g, info, stream));
   hipLaunchKernelGGL(logdet_p_kernel, dim3(1), dim3(64), 0, stream, npix, k, s, b.logdet_g, logdet_P);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
