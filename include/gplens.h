@@ -307,11 +307,14 @@ int gpl_lanczos_logdet(int nprobe, int n_lanczos, const double* lanczos_ab, cons
  * pivot exceeds 1e-5 of the largest diagonal entry of M (below that the FP32
  * columns are rounding noise). pivots[j] = the pixel
  * of column j, -1 for a zero column (a candidate not taken). G (k x k, ld ldg)
- * receives, in its lower triangle, the inverse of sigma^2 I + L^T L (from its
- * Cholesky factor; the strict upper triangle is not written);
+ * receives the inverse of sigma^2 I + L^T L (both triangles), built by
+ * bordering in 64 x 64 blocks (Schur complements and their Cholesky factors);
  * logdet_P (device scalar) = ln|P| = (n*n - k) ln sigma^2 + ln|sigma^2 I + L^T L|
- * from that factor; info (device) = 0, or the order of the first leading minor
- * of sigma^2 I + L^T L found not positive definite. noise_sigma > 0. */
+ * from those factors; info (device) = 0, or 1 + the index of the first pivot of
+ * a Schur complement found not positive (the outputs are then meaningless).
+ * noise_sigma > 0. Part of the work runs on a second stream of the calling
+ * thread; it starts after the work already enqueued on `stream` and `stream`
+ * waits for it before anything enqueued after this call. */
 size_t gpl_pchol_workspace(const gpl_problem* prob, int k, int prec);
 int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, int ldl, double* G, int ldg, int* pivots,
               double* logdet_P, int* info, void* ws, size_t ws_bytes, hipStream_t stream);

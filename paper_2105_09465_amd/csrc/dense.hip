@@ -10,19 +10,22 @@
 
 namespace gpl {
 
-static thread_local rocblas_handle t_handle[16] = {};
+static thread_local rocblas_handle t_handle[16][2] = {};
 
-int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t scratch_bytes) {
+int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t scratch_bytes, int slot) {
   int dev = 0;
   GPL_HIP(hipGetDevice(&dev));
   GPL_REQUIRE(dev >= 0 && dev < 16, "device index %d out of range for the BLAS handles", dev);
-  if (t_handle[dev] == nullptr) {
-    if (rocblas_create_handle(&t_handle[dev]) != rocblas_status_success) {
+  GPL_REQUIRE(slot == 0 || slot == 1, "BLAS handle slot %d", slot);
+  rocblas_handle& hs = t_handle[dev][slot];
+  if (hs == nullptr) {
+    if (rocblas_create_handle(&hs) != rocblas_status_success) {
+      hs = nullptr;
       set_error("rocblas_create_handle failed");
       return GPL_EHIP;
     }
   }
-  rocblas_handle h = t_handle[dev];
+  rocblas_handle h = hs;
   if (rocblas_set_stream(h, stream) != rocblas_status_success ||
       rocblas_set_workspace(h, scratch, scratch_bytes) != rocblas_status_success ||
       rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success) {
@@ -30,6 +33,27 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
     return GPL_EHIP;
   }
   *out = h;
+  return GPL_OK;
+}
+
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+static thread_local SideStream t_side[16];
+
+int side_stream(hipStream_t* s, hipEvent_t* ev0, hipEvent_t* ev1) {
+  int dev = 0;
+  GPL_HIP(hipGetDevice(&dev));
+  GPL_REQUIRE(dev >= 0 && dev < 16, "device index %d out of range for the side streams", dev);
+  SideStream& t = t_side[dev];
+  if (t.s == nullptr) {
+    GPL_HIP(hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking));
+    for (auto& e : t.ev) GPL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  *s = t.s;
+  *ev0 = t.ev[0];
+  *ev1 = t.ev[1];
   return GPL_OK;
 }
 
@@ -44,9 +68,9 @@ __global__ void fold_sum_kernel(int n, const double* part, double* out) {
   if (threadIdx.x == 0) *out = s;
 }
 
-// One diagonal block of the bordered inverse. S = Gbb - T from the lower
-// triangle of Gbb (T = Y B^T, a 64 x 64 column-major block; null for the first
-// block); its Cholesky factor D by four waves in the layout of the block pivot
+// One diagonal block of the bordered inverse. S = Gbb + shift I - T from the
+// lower triangle of Gbb (T = Y B^T, a 64 x 64 column-major block; null for the
+// first block); its Cholesky factor D by four waves in the layout of the block pivot
 // (lane a holds row a, wave q the columns [16q, 16q + 16) in registers, every
 // wave a copy of the diagonal; one barrier per step, the update vector
 // double-buffered by step parity); Dinv = D^{-1} by wave 0 (lane c solves
@@ -56,9 +80,9 @@ __global__ void fold_sum_kernel(int n, const double* part, double* out) {
 // sets *info to its global index + 1 (when *info is still 0) and is replaced by
 // 1 so that every value stays finite.
 constexpr int kSpd = 64;
-__global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, const double* __restrict__ T,
-                                                        double* __restrict__ Dinv, double* ld_part, int* info,
-                                                        int j0) {
+__global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, double shift,
+                                                        const double* __restrict__ T, double* __restrict__ Dinv,
+                                                        double* ld_part, int* info, int j0) {
   __shared__ double lv[kSpd][kSpd];      // lv[p][a] = D(a, p) (0 above the diagonal)
   __shared__ double lz[2][kSpd];         // step p: D(a, p) for a > p, else 0
   __shared__ double Di[kSpd][kSpd + 1];  // Di[r][c] = Dinv(r, c)
@@ -69,9 +93,9 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, co
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int b = b0 + u, r = max(a, b), c = min(a, b);
-    s[u] = Gbb[(size_t)c * ldg + r] - (T ? T[(size_t)c * kSpd + r] : 0.0);
+    s[u] = (Gbb[(size_t)c * ldg + r] + (b == a ? shift : 0.0)) - (T ? T[(size_t)c * kSpd + r] : 0.0);
   }
-  double dg = Gbb[(size_t)a * ldg + a] - (T ? T[(size_t)a * kSpd + a] : 0.0);
+  double dg = (Gbb[(size_t)a * ldg + a] + shift) - (T ? T[(size_t)a * kSpd + a] : 0.0);
   double lsum = 0.0;
   int bad = -1;
   for (int p = 0; p < kSpd; ++p) {
@@ -134,41 +158,47 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, co
   }
 }
 
-int spd_inverse(rocblas_handle h, double* G, int k, int ldg, const SpdScratch& w, double* logdet, int* info,
-                hipStream_t stream) {
-  GPL_REQUIRE(k > 0 && k % kSpd == 0, "order %d must be a positive multiple of %d", k, kSpd);
+int border_begin(int* info, hipStream_t stream) {
   hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, stream, info, 0);
   GPL_LAUNCH_CHECK();
+  return GPL_OK;
+}
+
+int border_step(rocblas_handle h, double* G, int ldg, int j0, double shift, const SpdScratch& w, int* info,
+                hipStream_t stream) {
+  GPL_REQUIRE(j0 >= 0 && j0 % kSpd == 0, "block start %d must be a multiple of %d", j0, kSpd);
   const double one = 1.0, minus_one = -1.0, zero = 0.0;
   const auto N = rocblas_operation_none, Tr = rocblas_operation_transpose;
-  for (int j0 = 0; j0 < k; j0 += kSpd) {
-    double* Gb = G + j0;                          // G[b, :b] (read), then Ginv[b, :b]
-    double* Gbb = G + (size_t)j0 * ldg + j0;      // G[b, b], then Ginv[b, b]
-    double* Gcol = G + (size_t)j0 * ldg;          // Ginv[:b, b]
-    if (j0 > 0) {
-      // Y = G[b, :b] Ginv[:b, :b];  T = Y G[b, :b]^T = G[b, :b] Ginv G[b, :b]^T
-      GPL_TRY(split_gemm(h, N, N, kSpd, j0, j0, std::max(1, std::min(16, j0 / 256)), 1.0, Gb, ldg, G, ldg, 0.0,
-                         w.Y, kSpd, w.split, w.split_elems, stream));
-      GPL_TRY(split_gemm(h, N, Tr, kSpd, kSpd, j0, std::max(1, j0 / 64), 1.0, w.Y, kSpd, Gb, ldg, 0.0, w.T, kSpd,
-                         w.split, w.split_elems, stream));
-    }
-    hipLaunchKernelGGL(spd_block_kernel, dim3(1), dim3(256), 0, stream, Gbb, ldg, j0 > 0 ? w.T : nullptr, w.Dinv,
-                       w.ld_part + j0 / kSpd, info, j0);
-    GPL_LAUNCH_CHECK();
-    if (j0 > 0) {
-      // W = Dinv Y; Ginv[:b, :b] += W^T W (= Y^T S^{-1} Y); Ginv[b, :b] = -Dinv^T W (= -S^{-1} Y) and its transpose
-      if (rocblas_dgemm(h, N, N, kSpd, j0, kSpd, &one, w.Dinv, kSpd, w.Y, kSpd, &zero, w.W, kSpd) !=
-              rocblas_status_success ||
-          rocblas_dgemm(h, Tr, N, j0, j0, kSpd, &one, w.W, kSpd, w.W, kSpd, &one, G, ldg) != rocblas_status_success ||
-          rocblas_dgemm(h, Tr, N, kSpd, j0, kSpd, &minus_one, w.Dinv, kSpd, w.W, kSpd, &zero, Gb, ldg) !=
-              rocblas_status_success ||
-          rocblas_dgemm(h, Tr, N, j0, kSpd, kSpd, &minus_one, w.W, kSpd, w.Dinv, kSpd, &zero, Gcol, ldg) !=
-              rocblas_status_success) {
-        set_error("rocblas_dgemm (bordered inverse, block at %d) failed", j0);
-        return GPL_EHIP;
-      }
+  double* Gb = G + j0;                      // G[b, :b] (read), then Ginv[b, :b]
+  double* Gbb = G + (size_t)j0 * ldg + j0;  // G[b, b], then Ginv[b, b]
+  double* Gcol = G + (size_t)j0 * ldg;      // Ginv[:b, b]
+  if (j0 > 0) {
+    // Y = G[b, :b] Ginv[:b, :b];  T = Y G[b, :b]^T = G[b, :b] Ginv G[b, :b]^T
+    GPL_TRY(split_gemm(h, N, N, kSpd, j0, j0, std::max(1, std::min(16, j0 / 256)), 1.0, Gb, ldg, G, ldg, 0.0, w.Y,
+                       kSpd, w.split, w.split_elems, stream));
+    GPL_TRY(split_gemm(h, N, Tr, kSpd, kSpd, j0, std::max(1, j0 / 64), 1.0, w.Y, kSpd, Gb, ldg, 0.0, w.T, kSpd,
+                       w.split, w.split_elems, stream));
+  }
+  hipLaunchKernelGGL(spd_block_kernel, dim3(1), dim3(256), 0, stream, Gbb, ldg, shift, j0 > 0 ? w.T : nullptr,
+                     w.Dinv, w.ld_part + j0 / kSpd, info, j0);
+  GPL_LAUNCH_CHECK();
+  if (j0 > 0) {
+    // W = Dinv Y; Ginv[:b, :b] += W^T W (= Y^T S^{-1} Y); Ginv[b, :b] = -Dinv^T W (= -S^{-1} Y) and its transpose
+    if (rocblas_dgemm(h, N, N, kSpd, j0, kSpd, &one, w.Dinv, kSpd, w.Y, kSpd, &zero, w.W, kSpd) !=
+            rocblas_status_success ||
+        rocblas_dgemm(h, Tr, N, j0, j0, kSpd, &one, w.W, kSpd, w.W, kSpd, &one, G, ldg) != rocblas_status_success ||
+        rocblas_dgemm(h, Tr, N, kSpd, j0, kSpd, &minus_one, w.Dinv, kSpd, w.W, kSpd, &zero, Gb, ldg) !=
+            rocblas_status_success ||
+        rocblas_dgemm(h, Tr, N, j0, kSpd, kSpd, &minus_one, w.W, kSpd, w.Dinv, kSpd, &zero, Gcol, ldg) !=
+            rocblas_status_success) {
+      set_error("rocblas_dgemm (bordered inverse, block at %d) failed", j0);
+      return GPL_EHIP;
     }
   }
+  return GPL_OK;
+}
+
+int border_finish(int k, const SpdScratch& w, double* logdet, hipStream_t stream) {
   hipLaunchKernelGGL(fold_sum_kernel, dim3(1), dim3(64), 0, stream, k / kSpd, w.ld_part, logdet);
   GPL_LAUNCH_CHECK();
   return GPL_OK;

@@ -11,10 +11,13 @@
 // the 64 x 64 residual block (largest remaining diagonal first, stopping below
 // a relative threshold), and the block's columns of L follow by a row-parallel
 // triangular solve. Candidates the block does not take leave zero columns,
-// which change neither L L^T nor the determinant identity below. Then
-//   G = sigma^2 I_k + L^T L (dsyrk), then G^{-1} and ln|G| by bordering in
-//   64 x 64 blocks (Schur complements, their Cholesky factors and inverses),
-//   ln|P| = (n - k) ln sigma^2 + ln|G|,  P = L L^T + sigma^2 I_n.
+// which change neither L L^T nor the determinant identity below. With
+//   G = sigma^2 I_k + L^T L,
+//   ln|P| = (n - k) ln sigma^2 + ln|G|,  P = L L^T + sigma^2 I_n,
+// G^{-1} and ln|G| are built by bordering in 64 x 64 blocks (Schur
+// complements, their Cholesky factors and inverses) on a second stream: as soon
+// as a block of L is in, its rows of L^T L and its bordering step run there
+// while the caller's stream builds the next block.
 // Solve. Preconditioned CG, one recurrence per column, with
 //   P^{-1} v = (v - L G^{-1} L^T v) / sigma^2 (dgemm, dsymm, dgemm),
 // FP32 vectors, FP64 scalars and Woodbury products; the alpha/beta of the
@@ -430,11 +433,6 @@ __global__ __launch_bounds__(1024) void dmax_kernel(int n, const double* d, doub
   }
 }
 
-__global__ void add_diag_kernel(int k, double* G, int ldg, double s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < k) G[(size_t)i * ldg + i] += s;
-}
-
 // ln|P| = (n - k) ln s + ln|G|.
 __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, double* out) {
   if (threadIdx.x == 0) *out = (double)(n - k) * log(s) + *logdet_g;
@@ -445,12 +443,13 @@ __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, 
 struct PcBuf {
   float *E, *T1, *T2, *Mc;
   double *C, *Lc, *R, *d, *dmax, *logdet_g, *split;
-  double *Y, *W, *T, *Dinv, *ld_part;  // the bordered inverse of sigma^2 I + L^T L
+  double *Y, *W, *T, *Dinv, *ld_part, *split2;  // G and its bordered inverse (on the side stream)
+  size_t split2_elems;
   size_t split_elems;  // doubles of split
   int *cand, *order, *taken, *info, *is_piv;
   void* mvm_ws;
   size_t mvm_bytes;
-  void* blas;
+  void *blas, *blas2;
 };
 
 template <class Cv>
@@ -473,6 +472,9 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.T = c.template take<double>((size_t)kPcBlock * kPcBlock);
   b.Dinv = c.template take<double>((size_t)kPcBlock * kPcBlock);
   b.ld_part = c.template take<double>(std::max(k / kPcBlock, 1));
+  b.split2_elems = split_gemm_scratch(kPcBlock, std::max(k, 1), kPcSplits) / sizeof(double);
+  b.split2 = c.template take<double>(b.split2_elems);
+  b.blas2 = c.template take<char>(kBlasScratch);
   b.cand = c.template take<int>(kPcBlock);
   b.order = c.template take<int>(kPcBlock);
   b.taken = c.template take<int>(1);
@@ -934,66 +936,78 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   PcBuf b;
   carve_pc(cv, npix, N, k, prec, b);
   if (!cv.ok()) return check_ws(nullptr, 0, 1);
-  rocblas_handle h;
+  rocblas_handle h, h2;
   GPL_TRY(blas_handle(&h, stream, b.blas, kBlasScratch));
+  hipStream_t s2;
+  hipEvent_t ev_l, ev_join;
+  GPL_TRY(side_stream(&s2, &ev_l, &ev_join));
+  GPL_TRY(blas_handle(&h2, s2, b.blas2, kBlasScratch, 1));
   MvmCtx mv;
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid,
                       kPcBlock, prec, b.mvm_ws, b.mvm_bytes, stream));
-  const float s2 = (float)kernel_scale2(prob->kernel.lengthscale);
+  const float s2s = (float)kernel_scale2(prob->kernel.lengthscale);
   const double amp2 = prob->kernel.amplitude * prob->kernel.amplitude;
-  hipLaunchKernelGGL(bkb_diag_kernel, dim3(npix), dim3(256), 0, stream, n, ss, taps, s2, amp2, prob->px, prob->py,
-                     b.d);
-  GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(dmax_kernel, dim3(1), dim3(1024), 0, stream, npix, b.d, b.dmax);
-  GPL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, b.is_piv, npix);
-  GPL_LAUNCH_CHECK();
-  const int ldf = round_up(N, 64);
-  const dim3 gcol(cdiv(npix, 256), kPcBlock);
-  const double one = 1.0, zero = 0.0;
-  for (int j0 = 0; j0 < k; j0 += kPcBlock) {
-    hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
+  const double sig2 = prob->noise_sigma * prob->noise_sigma;
+  // the side stream starts after everything the caller enqueued so far, and
+  // the caller's stream waits for it at the end, error or not
+  GPL_HIP(hipEventRecord(ev_l, stream));
+  GPL_HIP(hipStreamWaitEvent(s2, ev_l, 0));
+  const int rc = [&]() -> int {
+    GPL_TRY(border_begin(info, s2));
+    hipLaunchKernelGGL(bkb_diag_kernel, dim3(npix), dim3(256), 0, stream, n, ss, taps, s2s, amp2, prob->px, prob->py,
+                       b.d);
     GPL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(unit_cols_kernel, gcol, dim3(256), 0, stream, npix, b.cand, b.E);
+    hipLaunchKernelGGL(dmax_kernel, dim3(1), dim3(1024), 0, stream, npix, b.d, b.dmax);
     GPL_LAUNCH_CHECK();
-    // columns of B K B^T at the candidates (the matrix-free product)
-    GPL_TRY(psf_adjoint_launch(n, ss, taps, kPcBlock, b.E, npix, b.T1, ldf, 1.f, 0.f, CgGate{}, stream));
-    GPL_TRY(mvm_run(mv, kPcBlock, b.T1, ldf, b.T2, ldf, 0.f, CgGate{}, stream));
-    GPL_TRY(psf_forward_launch(n, ss, taps, kPcBlock, b.T2, ldf, b.Mc, npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr, 0,
-                               nullptr, CgGate{}, stream));
-    hipLaunchKernelGGL(widen_kernel, gcol, dim3(256), 0, stream, npix, b.Mc, b.C);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, b.is_piv, npix);
     GPL_LAUNCH_CHECK();
-    if (j0 > 0) {  // residual columns: C -= L[:, :j0] L[cand, :j0]^T
-      hipLaunchKernelGGL(gather_rows_kernel, dim3(cdiv(kPcBlock * j0, 256)), dim3(256), 0, stream, j0, L, ldl, b.cand,
-                         b.Lc);
+    const int ldf = round_up(N, 64);
+    const dim3 gcol(cdiv(npix, 256), kPcBlock);
+    const SpdScratch sw{b.Y, b.W, b.T, b.Dinv, b.ld_part, b.split2, b.split2_elems};
+    for (int j0 = 0; j0 < k; j0 += kPcBlock) {
+      hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
       GPL_LAUNCH_CHECK();
-      GPL_TRY(split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, kPcBlock, j0,
-                         std::min(kPcSplits, std::max(1, j0 / 256)), -1.0, L, ldl, b.Lc, kPcBlock, 1.0, b.C, npix,
-                         b.split, b.split_elems, stream));
+      hipLaunchKernelGGL(unit_cols_kernel, gcol, dim3(256), 0, stream, npix, b.cand, b.E);
+      GPL_LAUNCH_CHECK();
+      // columns of B K B^T at the candidates (the matrix-free product)
+      GPL_TRY(psf_adjoint_launch(n, ss, taps, kPcBlock, b.E, npix, b.T1, ldf, 1.f, 0.f, CgGate{}, stream));
+      GPL_TRY(mvm_run(mv, kPcBlock, b.T1, ldf, b.T2, ldf, 0.f, CgGate{}, stream));
+      GPL_TRY(psf_forward_launch(n, ss, taps, kPcBlock, b.T2, ldf, b.Mc, npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr,
+                                 0, nullptr, CgGate{}, stream));
+      hipLaunchKernelGGL(widen_kernel, gcol, dim3(256), 0, stream, npix, b.Mc, b.C);
+      GPL_LAUNCH_CHECK();
+      if (j0 > 0) {  // residual columns: C -= L[:, :j0] L[cand, :j0]^T
+        hipLaunchKernelGGL(gather_rows_kernel, dim3(cdiv(kPcBlock * j0, 256)), dim3(256), 0, stream, j0, L, ldl,
+                           b.cand, b.Lc);
+        GPL_LAUNCH_CHECK();
+        GPL_TRY(split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, kPcBlock, j0,
+                           std::min(kPcSplits, std::max(1, j0 / 256)), -1.0, L, ldl, b.Lc, kPcBlock, 1.0, b.C, npix,
+                           b.split, b.split_elems, stream));
+      }
+      hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64 * kPivWaves), 0, stream, b.C, npix, b.cand, b.dmax,
+                         kPcRelTol, b.order, b.taken, b.R);
+      GPL_LAUNCH_CHECK();
+      double* Lnew = L + (size_t)j0 * ldl;  // = C[:, order] R^{-T}, fixed rows, and the new residual diagonal
+      hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, npix, b.C, b.order,
+                         b.taken, b.R, b.cand, b.d, b.is_piv, Lnew, ldl, pivots, j0);
+      GPL_LAUNCH_CHECK();
+      // on the side stream, once these columns are in: rows j0 .. j0 + 63 of
+      // G = L^T L (up to column j0 + 63), then the bordered inverse of
+      // sigma^2 I + G up to that block, while the next block is built
+      GPL_HIP(hipEventRecord(ev_l, stream));
+      GPL_HIP(hipStreamWaitEvent(s2, ev_l, 0));
+      GPL_TRY(split_gemm(h2, rocblas_operation_transpose, rocblas_operation_none, kPcBlock, j0 + kPcBlock, npix,
+                         kPcSplits, 1.0, Lnew, ldl, L, ldl, 0.0, G + j0, ldg, b.split2, b.split2_elems, s2));
+      GPL_TRY(border_step(h2, G, ldg, j0, sig2, sw, info, s2));
     }
-    hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64 * kPivWaves), 0, stream, b.C, npix, b.cand, b.dmax,
-                       kPcRelTol,
-                       b.order, b.taken, b.R);
+    GPL_TRY(border_finish(k, sw, b.logdet_g, s2));
+    hipLaunchKernelGGL(logdet_p_kernel, dim3(1), dim3(64), 0, s2, npix, k, sig2, b.logdet_g, logdet_P);
     GPL_LAUNCH_CHECK();
-    double* Lnew = L + (size_t)j0 * ldl;  // = C[:, order] R^{-T}, fixed rows, and the new residual diagonal
-    hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, npix, b.C, b.order, b.taken,
-                       b.R, b.cand, b.d, b.is_piv, Lnew, ldl, pivots, j0);
-    GPL_LAUNCH_CHECK();
-  }
-  // G = s I + L^T L (lower triangle), then in place its inverse and ln|G|
-  const double s = prob->noise_sigma * prob->noise_sigma;
-  if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, k, npix, &one, L, ldl, &zero, G, ldg) !=
-      rocblas_status_success) {
-    set_error("rocblas_dsyrk (L^T L) failed");
-    return GPL_EHIP;
-  }
-  hipLaunchKernelGGL(add_diag_kernel, dim3(cdiv(k, 256)), dim3(256), 0, stream, k, G, ldg, s);
-  GPL_LAUNCH_CHECK();
-  GPL_TRY(spd_inverse(h, G, k, ldg, SpdScratch{b.Y, b.W, b.T, b.Dinv, b.ld_part, b.split, b.split_elems},
-                      b.logdet_g, info, stream));
-  hipLaunchKernelGGL(logdet_p_kernel, dim3(1), dim3(64), 0, stream, npix, k, s, b.logdet_g, logdet_P);
-  GPL_LAUNCH_CHECK();
-  return GPL_OK;
+    return GPL_OK;
+  }();
+  GPL_HIP(hipEventRecord(ev_join, s2));
+  GPL_HIP(hipStreamWaitEvent(stream, ev_join, 0));
+  return rc;
 }
 
 extern "C" size_t gpl_pchol_probes_workspace(int npix, int m) {
