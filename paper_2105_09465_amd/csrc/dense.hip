@@ -38,11 +38,11 @@ int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t s
 
 struct SideStream {
   hipStream_t s = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
 static thread_local SideStream t_side[16];
 
-int side_stream(hipStream_t* s, hipEvent_t* ev0, hipEvent_t* ev1) {
+int side_stream(hipStream_t* s, hipEvent_t ev[3]) {
   int dev = 0;
   GPL_HIP(hipGetDevice(&dev));
   GPL_REQUIRE(dev >= 0 && dev < 16, "device index %d out of range for the side streams", dev);
@@ -52,8 +52,7 @@ int side_stream(hipStream_t* s, hipEvent_t* ev0, hipEvent_t* ev1) {
     for (auto& e : t.ev) GPL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   *s = t.s;
-  *ev0 = t.ev[0];
-  *ev1 = t.ev[1];
+  for (int i = 0; i < 3; ++i) ev[i] = t.ev[i];
   return GPL_OK;
 }
 
@@ -112,8 +111,8 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, do
       double sp = s[0];
 #pragma unroll
       for (int u = 1; u < 16; ++u) sp = u == pu ? s[u] : sp;
-      const double lpp = sqrt(pv);
-      const double l = a == p ? lpp : (a > p ? sp / lpp : 0.0);
+      const double r = rsqrt_f64(pv), lpp = pv * r;
+      const double l = a == p ? lpp : (a > p ? sp * r : 0.0);
       lv[p][a] = l;
       lz[buf][a] = a > p ? l : 0.0;
     }

@@ -12,10 +12,23 @@ namespace gpl {
 // pointer mode, and the given scratch memory (rocBLAS allocates none).
 int blas_handle(rocblas_handle* out, hipStream_t stream, void* scratch, size_t scratch_bytes, int slot = 0);
 
+// 1 / sqrt(v) for a positive normal v to FP64 accuracy: the hardware estimate
+// refined by two Newton steps r <- r + r (1 - v r^2) / 2 (each about doubles
+// the number of correct bits).
+__device__ __forceinline__ double rsqrt_f64(double v) {
+  double r = __builtin_amdgcn_rsq(v);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(v * r), r, 1.0);
+    r = fma(0.5 * r, e, r);
+  }
+  return r;
+}
+
 // A second stream of this host thread on the current device (non-blocking,
-// default priority) and two events for joining it with the caller's stream,
-// created on first use and kept.
-int side_stream(hipStream_t* s, hipEvent_t* ev0, hipEvent_t* ev1);
+// default priority) and three events for ordering it against the caller's
+// stream, created on first use and kept.
+int side_stream(hipStream_t* s, hipEvent_t ev[3]);
 
 // Scratch memory handed to rocBLAS by every call that uses it.
 constexpr size_t kBlasScratch = size_t(32) << 20;

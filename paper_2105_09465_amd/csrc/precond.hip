@@ -89,19 +89,43 @@ __global__ __launch_bounds__(256) void bkb_diag_kernel(int n, int ss, const Taps
 
 // ---------------------------------------------------------------- candidate selection
 
+// Exclusive prefix sum of v over the workgroup in thread order (wave scans by
+// lane shuffles, then one combine of the wave totals through LDS); *total gets
+// the sum. Every thread of the workgroup must call it.
+__device__ __forceinline__ int block_excl_scan(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int u = 0; u < nw; ++u) {
+    const int c = wsum[u];
+    tot += c;
+    before += u < w ? c : 0;
+  }
+  __syncthreads();  // wsum may be reused
+  *total = tot;
+  return before + x - v;
+}
+
 // The kPcBlock largest positive entries of d (ranked by their FP32 value, ties
 // by lower index), in index order, into cand[0..kPcBlock); missing slots get
 // -1. One workgroup: a three-pass radix select on the FP32 bit patterns (11, 11
-// and 10 bits), then an ordered compaction.
+// and 10 bits; each pass a histogram of the keys that match the prefix so far,
+// and a top-down scan of the bins for the one where the count reaches the
+// number still needed), then an ordered compaction.
 constexpr int kSelThreads = 1024;
 __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const double* __restrict__ d, int* cand) {
   __shared__ int hist[2048];
-  __shared__ int cnt2[2048];
-  __shared__ int s_scan[kSelThreads];
+  __shared__ int wsum[kSelThreads / 64];
   __shared__ unsigned s_prefix, s_mask;
-  __shared__ int s_need, s_pick;
+  __shared__ int s_need, s_bin, s_above;
   const int t = threadIdx.x;
-  const int per = cdiv(n, kSelThreads), i0 = t * per, i1 = min(n, i0 + per);
   auto key = [&](int i) -> unsigned {
     const double v = d[i];
     return v > 0.0 ? __float_as_uint((float)v) : 0u;
@@ -111,87 +135,69 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
     s_mask = 0u;
     s_need = kPcBlock;
   }
-  __syncthreads();
   const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
   for (int pass = 0; pass < 3; ++pass) {
-    for (int b = t; b < 2048; b += kSelThreads) hist[b] = 0;
+    const int sh = shifts[pass], nb = 1 << widths[pass];
+    for (int q = t; q < nb; q += kSelThreads) hist[q] = 0;
     __syncthreads();
     const unsigned prefix = s_prefix, mask = s_mask;
-    const int sh = shifts[pass], nb = 1 << widths[pass];
-    for (int i = i0; i < i1; ++i) {
+    const int need = s_need;
+    for (int i = t; i < n; i += kSelThreads) {
       const unsigned k = key(i);
       if (k != 0u && (k & mask) == prefix) atomicAdd(&hist[(k >> sh) & (nb - 1)], 1);
     }
     __syncthreads();
-    // counts from the top bin down: incl[i] = sum of hist over the i+1 highest
-    // bins (bins nb-1-i' for i' <= i), by a parallel inclusive scan; the chosen
-    // bin is the highest whose inclusive count reaches the number still needed
-    // (bin 0 if none does), and that many minus the count above it remain.
-    const int need0 = s_need;
-    for (int q = t; q < nb; q += kSelThreads) cnt2[q] = hist[nb - 1 - q];
-    __syncthreads();
-    for (int off = 1; off < nb; off <<= 1) {
-      int v0 = 0, v1 = 0;
-      const int q0 = t, q1 = t + kSelThreads;
-      if (q0 < nb && q0 >= off) v0 = cnt2[q0 - off];
-      if (q1 < nb && q1 >= off) v1 = cnt2[q1 - off];
-      __syncthreads();
-      if (q0 < nb) cnt2[q0] += v0;
-      if (q1 < nb) cnt2[q1] += v1;
-      __syncthreads();
+    // thread t covers bins nb-1-2t and nb-2-2t (top down); the chosen bin is
+    // the highest whose count from the top reaches `need`, else bin 0 with
+    // everything above it
+    const int b1 = nb - 1 - 2 * t, b2 = nb - 2 - 2 * t;
+    const int h1 = b1 >= 0 ? hist[b1] : 0, h2 = b2 >= 0 ? hist[b2] : 0;
+    int total;
+    const int excl = block_excl_scan(h1 + h2, wsum, &total);
+    if (t == 0) {
+      s_bin = 0;
+      s_above = total - hist[0];
     }
-    if (t == 0) s_pick = nb - 1;  // "none reached": bin 0
     __syncthreads();
-    for (int q = t; q < nb; q += kSelThreads)
-      if (cnt2[q] >= need0 && (q == 0 || cnt2[q - 1] < need0)) s_pick = q;
+    if (excl < need && need <= excl + h1) {
+      s_bin = b1;
+      s_above = excl;
+    } else if (excl + h1 < need && need <= excl + h1 + h2) {
+      s_bin = b2;
+      s_above = excl + h1;
+    }
     __syncthreads();
     if (t == 0) {
-      const int q = s_pick, b = nb - 1 - q;
-      const int above_cnt = cnt2[q] - hist[b];
-      s_need = need0 - above_cnt;
-      s_prefix = prefix | ((unsigned)b << sh);
+      s_need = need - s_above;
+      s_prefix = prefix | ((unsigned)s_bin << sh);
       s_mask = mask | ((unsigned)(nb - 1) << sh);
     }
     __syncthreads();
   }
   // threshold key T = s_prefix: every key > T is taken, and the s_need lowest
-  // indices with key == T (fewer if there are not that many)
+  // indices with key == T (fewer if there are not that many); thread t scans
+  // the index range [i0, i1) so that positions follow index order
   const unsigned T = s_prefix;
+  const int eq_take = s_need;
+  const int per = cdiv(n, kSelThreads), i0 = min(n, t * per), i1 = min(n, i0 + per);
   int above = 0, equal = 0;
   for (int i = i0; i < i1; ++i) {
     const unsigned k = key(i);
     above += (k != 0u && k > T);
     equal += (k != 0u && k == T);
   }
-  // exclusive scans of both counts over the threads, in index order
-  s_scan[t] = equal;
-  __syncthreads();
-  for (int off = 1; off < kSelThreads; off <<= 1) {
-    const int v = t >= off ? s_scan[t - off] : 0;
-    __syncthreads();
-    s_scan[t] += v;
-    __syncthreads();
-  }
-  int eq_before = s_scan[t] - equal;
-  const int eq_take_total = s_need;
-  __syncthreads();
-  s_scan[t] = above + max(0, min(equal, eq_take_total - eq_before));
-  __syncthreads();
-  for (int off = 1; off < kSelThreads; off <<= 1) {
-    const int v = t >= off ? s_scan[t - off] : 0;
-    __syncthreads();
-    s_scan[t] += v;
-    __syncthreads();
-  }
-  int pos = s_scan[t] - (above + max(0, min(equal, eq_take_total - eq_before)));
-  const int total = s_scan[kSelThreads - 1];
+  int tot_eq;
+  int eq_before = block_excl_scan(equal, wsum, &tot_eq);
+  const int mine = above + max(0, min(equal, eq_take - eq_before));
+  int total;
+  int pos = block_excl_scan(mine, wsum, &total);
   for (int i = i0; i < i1; ++i) {
     const unsigned k = key(i);
     bool take = false;
     if (k != 0u && k > T) {
       take = true;
     } else if (k != 0u && k == T) {
-      take = eq_before < eq_take_total;
+      take = eq_before < eq_take;
       ++eq_before;
     }
     if (take && pos < kPcBlock) cand[pos++] = i;
@@ -201,19 +207,34 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
 
 // ---------------------------------------------------------------- small element-wise kernels
 
-// E (npix x kPcBlock, ld npix) = unit columns e_{cand[c]} (zero where cand < 0).
-__global__ void unit_cols_kernel(int npix, const int* cand, float* E) {
+// T (fine grid, row-major, column c at T + c * ldt) = B^T e_{cand[c]} (zero
+// where cand < 0): the adjoint of a unit pixel vector is the composite filter's
+// footprint around that pixel, g(fx - ss Ix) g(fy - ss Iy) / ss^2, formed here
+// with the same FP32 operations as the general adjoint applies to it.
+__global__ void unit_adjoint_kernel(int n, int ss, const Taps taps, const int* cand, float* T, int ldt) {
   const int c = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npix) return;
-  E[(size_t)c * npix + i] = cand[c] == i ? 1.f : 0.f;
+  const int M = n * ss;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= M * M) return;
+  const int I = cand[c];
+  float v = 0.f;
+  if (I >= 0) {
+    const int Iy = I / n, Ix = I - Iy * n;
+    const int fy = f / M, fx = f - fy * M;
+    const int ty = fy - ss * Iy + taps.r, tx = fx - ss * Ix + taps.r;
+    if (ty >= 0 && ty < taps.L && tx >= 0 && tx < taps.L)
+      v = (taps.g[ty] * taps.g[tx]) * (1.f / (float)(ss * ss));
+  }
+  T[(size_t)c * ldt + f] = v;
 }
 
-// C (FP64) = Mc (FP32), npix x kPcBlock.
-__global__ void widen_kernel(int npix, const float* __restrict__ Mc, double* C) {
-  const int c = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < npix) C[(size_t)c * npix + i] = (double)Mc[(size_t)c * npix + i];
+// Ct (FP64, kPcBlock x npix, ld kPcBlock: the residual block stored by pixel
+// rows) = Mc^T (Mc FP32, npix x kPcBlock, ld npix). Thread (c, i) with c the
+// fastest index, so that the stores are contiguous.
+__global__ void widen_kernel(int npix, const float* __restrict__ Mc, double* Ct) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = e % kPcBlock, i = e / kPcBlock;
+  if (i < npix) Ct[e] = (double)Mc[(size_t)c * npix + i];
 }
 
 // Lc (kPcBlock x j) = L[cand, 0..j): rows of the factor at the candidates (0 for
@@ -225,14 +246,15 @@ __global__ void gather_rows_kernel(int j, const double* __restrict__ L, int ldl,
   Lc[(size_t)col * kPcBlock + c] = cand[c] >= 0 ? L[(size_t)col * ldl + cand[c]] : 0.0;
 }
 
-// Pivoted Cholesky of the residual block S = C[cand, :] (kPcBlock x kPcBlock)
+// Pivoted Cholesky of the residual block S = C[cand, :] (kPcBlock x kPcBlock;
+// C, the npix x kPcBlock residual columns, is stored by pixel rows in Ct)
 // by four waves: lane a of every wave owns candidate a, and wave q holds the
 // entries (a, b) of its quarter of the columns b in registers. Every wave also
 // keeps the residual diagonal (lane a: entry (a, a)) and finds each step's
 // pivot itself: the largest remaining diagonal entry (lowest candidate index on
 // ties), while it exceeds tol (a share of the largest diagonal entry of M,
-// dmax[0]). The wave holding column p forms l = S[:, p] / sqrt(S[p][p]) and
-// publishes it in LDS; after one barrier every wave applies S -= l l^T to its
+// dmax[0]). The wave holding column p forms l = S[:, p] / sqrt(S[p][p]) (the
+// reciprocal square root refined to FP64 accuracy) and publishes it in LDS; after one barrier every wave applies S -= l l^T to its
 // registers and to its copy of the diagonal (l is double-buffered by step
 // parity, so one barrier per step suffices). Outputs order[0..kPcBlock) (taken
 // candidates in pivot order first, then the rest), *taken, and R (kPcBlock x
@@ -273,7 +295,7 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k)
   return m;
 }
 
-__global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const double* __restrict__ C, int npix,
+__global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const double* __restrict__ Ct, int npix,
                                                                      const int* cand, const double* dmax,
                                                                      double rel_tol, int* order, int* taken,
                                                                      double* R) {
@@ -287,9 +309,9 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
 #pragma unroll
   for (int u = 0; u < kPivCols; ++u) {
     const int cb = cand[b0 + u];
-    s[u] = (ca >= 0 && cb >= 0) ? C[(size_t)(b0 + u) * npix + ca] : 0.0;
+    s[u] = (ca >= 0 && cb >= 0) ? Ct[(size_t)ca * kPcBlock + b0 + u] : 0.0;
   }
-  double dg = ca >= 0 ? C[(size_t)a * npix + ca] : 0.0;  // entry (a, a)
+  double dg = ca >= 0 ? Ct[(size_t)ca * kPcBlock + a] : 0.0;  // entry (a, a)
   bool used = ca < 0, piv = false;
   const double tol = rel_tol * dmax[0];
   int cnt = 0;
@@ -307,8 +329,8 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
       double sp = s[0];
 #pragma unroll
       for (int u = 1; u < kPivCols; ++u) sp = u == pu ? s[u] : sp;
-      const double lpp = sqrt(v);
-      const double l = a == p ? lpp : (used ? 0.0 : sp / lpp);
+      const double r = rsqrt_f64(v), lpp = v * r;
+      const double l = a == p ? lpp : (used ? 0.0 : sp * r);
       lv[step][a] = l;
       lc[buf][a] = (a == p || used) ? 0.0 : l;
       if (a == 0) s_perm[step] = p;
@@ -357,16 +379,35 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
 //   d -= sum_u x[u]^2 (in u order), clamped at 0, exactly 0 at the new pivots,
 //   which are marked in is_piv; pivots[j0 + u] = the pixel of pivot u (-1 where
 //   none was taken).
-__global__ __launch_bounds__(256) void new_columns_kernel(int npix, const double* __restrict__ C, const int* order,
-                                                          const int* taken, const double* __restrict__ R,
-                                                          const int* cand, double* d, int* is_piv,
-                                                          double* __restrict__ Lnew, int ldl, int* pivots, int j0) {
-  __shared__ double Rt[kPcBlock][kPcBlock];  // Rt[v][w] = entry (w, v) of R
+constexpr int kNcRows = 128;  // pixel rows per workgroup of the new-columns kernel
+__global__ __launch_bounds__(kNcRows) void new_columns_kernel(int npix, const double* __restrict__ Ct,
+                                                              const int* order, const int* taken,
+                                                              const double* __restrict__ R, const int* cand, double* d,
+                                                              int* is_piv, double* __restrict__ Lnew, int ldl,
+                                                              int* pivots, int j0) {
+  __shared__ double Rt[kPcBlock][kPcBlock];       // Rt[v][w] = entry (w, v) of R
+  __shared__ double rows[kNcRows][kPcBlock + 1];  // the workgroup's rows of the residual columns
   __shared__ double idg[kPcBlock];
   __shared__ int s_ord[kPcBlock], s_pix[kPcBlock];
   const int t = threadIdx.x;
   const int cnt = *taken;
-  for (int e = t; e < kPcBlock * kPcBlock; e += blockDim.x) (&Rt[0][0])[e] = R[e];
+  const int r0 = blockIdx.x * kNcRows;
+  // the workgroup's rows are one contiguous stretch of Ct: coalesced loads, all
+  // issued before the first LDS store (element t + kNcRows k is row
+  // t / 64 + 2k, column t % 64; rows past npix read the last row)
+  static_assert(kNcRows == 2 * kPcBlock, "two rows per pass of the workgroup");
+  {
+    double tmp[kPcBlock];
+    const int cc = t & (kPcBlock - 1), rb = t / kPcBlock;
+#pragma unroll
+    for (int k = 0; k < kPcBlock; ++k) {
+      const int rr = min(r0 + rb + 2 * k, npix - 1);
+      tmp[k] = Ct[(size_t)rr * kPcBlock + cc];
+    }
+#pragma unroll
+    for (int k = 0; k < kPcBlock; ++k) rows[rb + 2 * k][cc] = tmp[k];
+  }
+  for (int e = t; e < kPcBlock * kPcBlock; e += kNcRows) (&Rt[0][0])[e] = R[e];
   if (t < kPcBlock) {
     const int o = order[t];
     const int pix = t < cnt ? cand[o] : -1;
@@ -377,11 +418,11 @@ __global__ __launch_bounds__(256) void new_columns_kernel(int npix, const double
   __syncthreads();
   if (t < kPcBlock) idg[t] = 1.0 / Rt[t][t];
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + t;
+  const int i = r0 + t;
   if (i >= npix) return;
   double x[kPcBlock];
 #pragma unroll
-  for (int u = 0; u < kPcBlock; ++u) x[u] = C[(size_t)s_ord[u] * npix + i];  // order[] is a permutation
+  for (int u = 0; u < kPcBlock; ++u) x[u] = rows[t][s_ord[u]];  // order[] is a permutation
 #pragma unroll
   for (int u = 0; u < kPcBlock; ++u) x[u] = u < cnt ? x[u] : 0.0;
 #pragma unroll
@@ -441,7 +482,7 @@ __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, 
 // ---------------------------------------------------------------- build workspace
 
 struct PcBuf {
-  float *E, *T1, *T2, *Mc;
+  float *T1, *T2, *Mc;
   double *C, *Lc, *R, *d, *dmax, *logdet_g, *split;
   double *Y, *W, *T, *Dinv, *ld_part, *split2;  // G and its bordered inverse (on the side stream)
   size_t split2_elems;
@@ -455,7 +496,6 @@ struct PcBuf {
 template <class Cv>
 static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   const int ldf = round_up(N, 64);
-  b.E = c.template take<float>((size_t)npix * kPcBlock);
   b.T1 = c.template take<float>((size_t)ldf * kPcBlock);
   b.T2 = c.template take<float>((size_t)ldf * kPcBlock);
   b.Mc = c.template take<float>((size_t)npix * kPcBlock);
@@ -939,8 +979,8 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   rocblas_handle h, h2;
   GPL_TRY(blas_handle(&h, stream, b.blas, kBlasScratch));
   hipStream_t s2;
-  hipEvent_t ev_l, ev_join;
-  GPL_TRY(side_stream(&s2, &ev_l, &ev_join));
+  hipEvent_t ev[3];  // ev[0], ev[1]: block b of the factor is in (by parity of b); ev[2]: side stream done
+  GPL_TRY(side_stream(&s2, ev));
   GPL_TRY(blas_handle(&h2, s2, b.blas2, kBlasScratch, 1));
   MvmCtx mv;
   GPL_TRY(mvm_prepare(mv, prob->kernel.lengthscale, prob->kernel.amplitude, N, prob->px, prob->py, &prob->grid,
@@ -950,8 +990,8 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
   const double sig2 = prob->noise_sigma * prob->noise_sigma;
   // the side stream starts after everything the caller enqueued so far, and
   // the caller's stream waits for it at the end, error or not
-  GPL_HIP(hipEventRecord(ev_l, stream));
-  GPL_HIP(hipStreamWaitEvent(s2, ev_l, 0));
+  GPL_HIP(hipEventRecord(ev[1], stream));
+  GPL_HIP(hipStreamWaitEvent(s2, ev[1], 0));
   const int rc = [&]() -> int {
     GPL_TRY(border_begin(info, s2));
     hipLaunchKernelGGL(bkb_diag_kernel, dim3(npix), dim3(256), 0, stream, n, ss, taps, s2s, amp2, prob->px, prob->py,
@@ -962,51 +1002,56 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
     hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, b.is_piv, npix);
     GPL_LAUNCH_CHECK();
     const int ldf = round_up(N, 64);
-    const dim3 gcol(cdiv(npix, 256), kPcBlock);
     const SpdScratch sw{b.Y, b.W, b.T, b.Dinv, b.ld_part, b.split2, b.split2_elems};
+    // on the side stream, once block jb of the factor is in: rows jb .. jb + 63
+    // of G = L^T L (up to column jb + 63), then the bordered inverse of
+    // sigma^2 I + G up to that block. It is enqueued after the next block's
+    // work on the caller's stream, so that the host keeps that stream fed.
+    auto side_block = [&](int jb) -> int {
+      GPL_HIP(hipStreamWaitEvent(s2, ev[(jb / kPcBlock) & 1], 0));
+      GPL_TRY(split_gemm(h2, rocblas_operation_transpose, rocblas_operation_none, kPcBlock, jb + kPcBlock, npix,
+                         kPcSplits, 1.0, L + (size_t)jb * ldl, ldl, L, ldl, 0.0, G + jb, ldg, b.split2,
+                         b.split2_elems, s2));
+      return border_step(h2, G, ldg, jb, sig2, sw, info, s2);
+    };
     for (int j0 = 0; j0 < k; j0 += kPcBlock) {
       hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
       GPL_LAUNCH_CHECK();
-      hipLaunchKernelGGL(unit_cols_kernel, gcol, dim3(256), 0, stream, npix, b.cand, b.E);
-      GPL_LAUNCH_CHECK();
       // columns of B K B^T at the candidates (the matrix-free product)
-      GPL_TRY(psf_adjoint_launch(n, ss, taps, kPcBlock, b.E, npix, b.T1, ldf, 1.f, 0.f, CgGate{}, stream));
+      hipLaunchKernelGGL(unit_adjoint_kernel, dim3(cdiv(N, 256), kPcBlock), dim3(256), 0, stream, n, ss, taps,
+                         b.cand, b.T1, ldf);
+      GPL_LAUNCH_CHECK();
       GPL_TRY(mvm_run(mv, kPcBlock, b.T1, ldf, b.T2, ldf, 0.f, CgGate{}, stream));
       GPL_TRY(psf_forward_launch(n, ss, taps, kPcBlock, b.T2, ldf, b.Mc, npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr,
                                  0, nullptr, CgGate{}, stream));
-      hipLaunchKernelGGL(widen_kernel, gcol, dim3(256), 0, stream, npix, b.Mc, b.C);
+      hipLaunchKernelGGL(widen_kernel, dim3(cdiv(npix * kPcBlock, 256)), dim3(256), 0, stream, npix, b.Mc, b.C);
       GPL_LAUNCH_CHECK();
-      if (j0 > 0) {  // residual columns: C -= L[:, :j0] L[cand, :j0]^T
+      if (j0 > 0) {  // residual columns, by pixel rows: Ct -= L[cand, :j0] L[:, :j0]^T
         hipLaunchKernelGGL(gather_rows_kernel, dim3(cdiv(kPcBlock * j0, 256)), dim3(256), 0, stream, j0, L, ldl,
                            b.cand, b.Lc);
         GPL_LAUNCH_CHECK();
-        GPL_TRY(split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, npix, kPcBlock, j0,
-                           std::min(kPcSplits, std::max(1, j0 / 256)), -1.0, L, ldl, b.Lc, kPcBlock, 1.0, b.C, npix,
-                           b.split, b.split_elems, stream));
+        GPL_TRY(split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, kPcBlock, npix, j0,
+                           std::min(kPcSplits, std::max(1, j0 / 256)), -1.0, b.Lc, kPcBlock, L, ldl, 1.0, b.C,
+                           kPcBlock, b.split, b.split_elems, stream));
       }
       hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64 * kPivWaves), 0, stream, b.C, npix, b.cand, b.dmax,
                          kPcRelTol, b.order, b.taken, b.R);
       GPL_LAUNCH_CHECK();
       double* Lnew = L + (size_t)j0 * ldl;  // = C[:, order] R^{-T}, fixed rows, and the new residual diagonal
-      hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, npix, b.C, b.order,
+      hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, kNcRows)), dim3(kNcRows), 0, stream, npix, b.C, b.order,
                          b.taken, b.R, b.cand, b.d, b.is_piv, Lnew, ldl, pivots, j0);
       GPL_LAUNCH_CHECK();
-      // on the side stream, once these columns are in: rows j0 .. j0 + 63 of
-      // G = L^T L (up to column j0 + 63), then the bordered inverse of
-      // sigma^2 I + G up to that block, while the next block is built
-      GPL_HIP(hipEventRecord(ev_l, stream));
-      GPL_HIP(hipStreamWaitEvent(s2, ev_l, 0));
-      GPL_TRY(split_gemm(h2, rocblas_operation_transpose, rocblas_operation_none, kPcBlock, j0 + kPcBlock, npix,
-                         kPcSplits, 1.0, Lnew, ldl, L, ldl, 0.0, G + j0, ldg, b.split2, b.split2_elems, s2));
-      GPL_TRY(border_step(h2, G, ldg, j0, sig2, sw, info, s2));
+      GPL_HIP(hipEventRecord(ev[(j0 / kPcBlock) & 1], stream));
+      if (j0 > 0) GPL_TRY(side_block(j0 - kPcBlock));
     }
+    GPL_TRY(side_block(k - kPcBlock));
     GPL_TRY(border_finish(k, sw, b.logdet_g, s2));
     hipLaunchKernelGGL(logdet_p_kernel, dim3(1), dim3(64), 0, s2, npix, k, sig2, b.logdet_g, logdet_P);
     GPL_LAUNCH_CHECK();
     return GPL_OK;
   }();
-  GPL_HIP(hipEventRecord(ev_join, s2));
-  GPL_HIP(hipStreamWaitEvent(stream, ev_join, 0));
+  GPL_HIP(hipEventRecord(ev[2], s2));
+  GPL_HIP(hipStreamWaitEvent(stream, ev[2], 0));
   return rc;
 }
 
