@@ -49,7 +49,10 @@ int side_stream(hipStream_t* s, hipEvent_t ev[3]) {
   SideStream& t = t_side[dev];
   if (t.s == nullptr) {
     GPL_HIP(hipStreamCreateWithFlags(&t.s, hipStreamNonBlocking));
-    for (auto& e : t.ev) GPL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // the events only order work of two streams on this device: a device-scope
+    // release is enough (a system-scope one writes the caches back for the
+    // host at every record)
+    for (auto& e : t.ev) GPL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
   }
   *s = t.s;
   for (int i = 0; i < 3; ++i) ev[i] = t.ev[i];

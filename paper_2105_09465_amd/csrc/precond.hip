@@ -32,6 +32,7 @@
 namespace gpl {
 
 constexpr int kPcBlock = 64;   // pivots per block
+constexpr int kSideEvery = 2;  // blocks of the factor per event towards the side stream
 constexpr int kPcSplits = 16;  // most splits of the reduction of a product with the factor
 // A residual pivot below this share of the largest diagonal entry of M is not
 // taken: the columns of M come from FP32 products (relative error ~5e-7), so
@@ -120,6 +121,8 @@ __device__ __forceinline__ int block_excl_scan(int v, int* wsum, int* total) {
 // and a top-down scan of the bins for the one where the count reaches the
 // number still needed), then an ordered compaction.
 constexpr int kSelThreads = 1024;
+constexpr int kBinsPer = 2048 / kSelThreads;  // histogram bins per thread in the scans
+static_assert(kBinsPer * kSelThreads == 2048, "the threads cover the 2048 bins of a pass");
 __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const double* __restrict__ d, int* cand) {
   __shared__ int hist[2048];
   __shared__ int wsum[kSelThreads / 64];
@@ -147,24 +150,30 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
       if (k != 0u && (k & mask) == prefix) atomicAdd(&hist[(k >> sh) & (nb - 1)], 1);
     }
     __syncthreads();
-    // thread t covers bins nb-1-2t and nb-2-2t (top down); the chosen bin is
-    // the highest whose count from the top reaches `need`, else bin 0 with
-    // everything above it
-    const int b1 = nb - 1 - 2 * t, b2 = nb - 2 - 2 * t;
-    const int h1 = b1 >= 0 ? hist[b1] : 0, h2 = b2 >= 0 ? hist[b2] : 0;
+    // thread t covers bins nb-1-kBinsPer*t-j, j < kBinsPer (top down); the
+    // chosen bin is the highest whose count from the top reaches `need`, else
+    // bin 0 with everything above it
+    int h[kBinsPer], mine = 0;
+#pragma unroll
+    for (int j = 0; j < kBinsPer; ++j) {
+      const int bj = nb - 1 - kBinsPer * t - j;
+      h[j] = bj >= 0 ? hist[bj] : 0;
+      mine += h[j];
+    }
     int total;
-    const int excl = block_excl_scan(h1 + h2, wsum, &total);
+    int run = block_excl_scan(mine, wsum, &total);
     if (t == 0) {
       s_bin = 0;
       s_above = total - hist[0];
     }
     __syncthreads();
-    if (excl < need && need <= excl + h1) {
-      s_bin = b1;
-      s_above = excl;
-    } else if (excl + h1 < need && need <= excl + h1 + h2) {
-      s_bin = b2;
-      s_above = excl + h1;
+#pragma unroll
+    for (int j = 0; j < kBinsPer; ++j) {
+      if (run < need && need <= run + h[j]) {
+        s_bin = nb - 1 - kBinsPer * t - j;
+        s_above = run;
+      }
+      run += h[j];
     }
     __syncthreads();
     if (t == 0) {
@@ -1005,14 +1014,22 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
     const SpdScratch sw{b.Y, b.W, b.T, b.Dinv, b.ld_part, b.split2, b.split2_elems};
     // on the side stream, once block jb of the factor is in: rows jb .. jb + 63
     // of G = L^T L (up to column jb + 63), then the bordered inverse of
-    // sigma^2 I + G up to that block. It is enqueued after the next block's
-    // work on the caller's stream, so that the host keeps that stream fed.
+    // sigma^2 I + G up to that block. The caller's stream records an event
+    // after every kSideEvery-th block (a record drains that stream's queue, ~40
+    // us), and the side work of the blocks up to it is enqueued after the next
+    // block's work on the caller's stream, so that the host keeps that stream
+    // fed.
+    int pend_lo = 0, pend_hi = 0, pend_g = 0;  // blocks [pend_lo, pend_hi) are in, their side work not enqueued
     auto side_block = [&](int jb) -> int {
-      GPL_HIP(hipStreamWaitEvent(s2, ev[(jb / kPcBlock) & 1], 0));
       GPL_TRY(split_gemm(h2, rocblas_operation_transpose, rocblas_operation_none, kPcBlock, jb + kPcBlock, npix,
                          kPcSplits, 1.0, L + (size_t)jb * ldl, ldl, L, ldl, 0.0, G + jb, ldg, b.split2,
                          b.split2_elems, s2));
       return border_step(h2, G, ldg, jb, sig2, sw, info, s2);
+    };
+    auto side_group = [&]() -> int {
+      GPL_HIP(hipStreamWaitEvent(s2, ev[pend_g & 1], 0));
+      for (; pend_lo < pend_hi; ++pend_lo) GPL_TRY(side_block(pend_lo * kPcBlock));
+      return GPL_OK;
     };
     for (int j0 = 0; j0 < k; j0 += kPcBlock) {
       hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
@@ -1041,10 +1058,16 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
       hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, kNcRows)), dim3(kNcRows), 0, stream, npix, b.C, b.order,
                          b.taken, b.R, b.cand, b.d, b.is_piv, Lnew, ldl, pivots, j0);
       GPL_LAUNCH_CHECK();
-      GPL_HIP(hipEventRecord(ev[(j0 / kPcBlock) & 1], stream));
-      if (j0 > 0) GPL_TRY(side_block(j0 - kPcBlock));
+      // side work of a group whose event was recorded at an earlier block
+      if (pend_hi > pend_lo) GPL_TRY(side_group());
+      const int blk = j0 / kPcBlock;
+      if (blk % kSideEvery == kSideEvery - 1 || j0 + kPcBlock >= k) {
+        pend_g = blk / kSideEvery;
+        GPL_HIP(hipEventRecord(ev[pend_g & 1], stream));
+        pend_hi = blk + 1;
+      }
     }
-    GPL_TRY(side_block(k - kPcBlock));
+    if (pend_hi > pend_lo) GPL_TRY(side_group());
     GPL_TRY(border_finish(k, sw, b.logdet_g, s2));
     hipLaunchKernelGGL(logdet_p_kernel, dim3(1), dim3(64), 0, s2, npix, k, sig2, b.logdet_g, logdet_P);
     GPL_LAUNCH_CHECK();
