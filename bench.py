@@ -277,6 +277,36 @@ def gradient_only(G, torch, synth, prec, reps):
                       "gradients_ms": t_grad * 1e3, "components": int(g["lnp"].numel())}), flush=True)
 
 
+def pc_only(G, torch, synth, prec, reps):
+    """The preconditioned reconstruction alone at the bench shape (100x100 px,
+    2x2 supersampling, rank PC_RANK, 16 probes N(0, P)): two warmups, then
+    `reps` timed reconstructions and `reps` timed builds of the factor. Prints
+    one JSON line."""
+    import time
+    prob, z = load_workload()
+    npix = prob.grid.n_pix
+    d = torch.as_tensor(z["d"], dtype=torch.float32, device="cuda")
+    gn, hn = synth.preconditioned_probe_normals(npix, PC_RANK, 16, 1)
+    gn = torch.as_tensor(gn, dtype=torch.float64, device="cuda")
+    hn = torch.as_tensor(hn, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        G.reconstruct_preconditioned(prob, d, gn, hn, rank=PC_RANK, prec=prec)
+    pts = G.ops.lens_raytrace(prob.grid, prob.lens)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.reconstruct_preconditioned(prob, d, gn, hn, rank=PC_RANK, prec=prec)
+    torch.cuda.synchronize()
+    t_rec = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.ops.pchol(prob, pts[0], pts[1], PC_RANK, prec=prec)
+    torch.cuda.synchronize()
+    t_build = (time.perf_counter() - t0) / reps
+    print(json.dumps({"pc_only": reps, "prec": prec, "rank": PC_RANK, "reconstruction_ms": t_rec * 1e3,
+                      "build_ms": t_build * 1e3}), flush=True)
+
+
 def mfma_flops_per_launch(prec, nrhs, live_subtiles, live_lo):
     """MFMA FLOP one product launch executes, from the plan's counts of evaluated
     (16-point subtile, 32-point chunk) pairs and of those that need the lo part.
@@ -474,6 +504,8 @@ def main():
     ap.add_argument("--gradient-only", type=int, default=0,
                     help="time ray tracing and this many evaluations of the evidence gradients at the bench shape, "
                          "print one JSON line and exit")
+    ap.add_argument("--pc-only", type=int, default=0,
+                    help="time only the preconditioned reconstruction and its factor build, this many times")
     ap.add_argument("--c3-steps", type=int, default=2,
                     help="timed reconstructions of the 200x200, N=160000 image per form (0: skip)")
     ap.add_argument("--vigp-steps", type=int, default=10,
@@ -503,6 +535,9 @@ def main():
         return
     if args.gradient_only > 0:
         gradient_only(G, torch, synth, args.prec, args.gradient_only)
+        return
+    if args.pc_only > 0:
+        pc_only(G, torch, synth, args.prec, args.pc_only)
         return
     if args.serve_only:
         print(json.dumps(serve_section(G, torch, synth, args.serve_requests)), flush=True)
