@@ -216,25 +216,58 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
 
 // ---------------------------------------------------------------- small element-wise kernels
 
-// T (fine grid, row-major, column c at T + c * ldt) = B^T e_{cand[c]} (zero
-// where cand < 0): the adjoint of a unit pixel vector is the composite filter's
-// footprint around that pixel, g(fx - ss Ix) g(fy - ss Iy) / ss^2, formed here
-// with the same FP32 operations as the general adjoint applies to it.
-__global__ void unit_adjoint_kernel(int n, int ss, const Taps taps, const int* cand, float* T, int ldt) {
-  const int c = blockIdx.y;
-  const int M = n * ss;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= M * M) return;
-  const int I = cand[c];
-  float v = 0.f;
-  if (I >= 0) {
-    const int Iy = I / n, Ix = I - Iy * n;
-    const int fy = f / M, fx = f - fy * M;
-    const int ty = fy - ss * Iy + taps.r, tx = fx - ss * Ix + taps.r;
-    if (ty >= 0 && ty < taps.L && tx >= 0 && tx < taps.L)
-      v = (taps.g[ty] * taps.g[tx]) * (1.f / (float)(ss * ss));
+// The product's right-hand side for the unit pixel columns, written straight
+// into its buffers (the product then runs on them as prepared): column c is
+// B^T e_{cand[c]}, the composite filter's footprint g(fx - ss Ix) g(fy - ss Iy)
+// / ss^2 around that pixel, formed with the FP32 operations the general adjoint
+// applies to it and placed at the sorted positions of the product's plan. The
+// footprint of the previous block's candidate prev[c] is cleared first (the
+// buffers hold nothing else: they were zeroed when the product was prepared).
+// The precision form scales column c by 2^e from the bound max |B^T e| <= 1 /
+// ss^2 (non-negative taps summing to one) and splits it into FP16 hi (nearest)
+// and lo, as the CG loop's fused adjoint does. One workgroup per column.
+__global__ __launch_bounds__(256) void unit_rhs_kernel(int n, int ss, const Taps taps, const int* cand, int* prev,
+                                                       RhsOut o) {
+  const int c = blockIdx.x;
+  const int M = n * ss, L = taps.L, r = taps.r;
+  const bool f16 = o.prec == GPL_PREC_F16X3;
+  const int hs = hi_slot(c, o.nrhs);
+  const bool packed = last_block_packed(o.nrhs) && c >= packed_block_start(o.nrhs);
+  const float inv_ss2 = 1.f / (float)(ss * ss);
+  float scale = 1.f;
+  if (f16) {
+    const int e = min(14 - ilogbf(inv_ss2) - 1, 126);  // bound * 2^e in [2^13, 2^14)
+    scale = ldexpf(1.f, e);
+    if (threadIdx.x == 0) o.inv_scale[c] = ldexpf(1.f, -e) / 2048.f;  // with the 2^11 of the exp tile
   }
-  T[(size_t)c * ldt + f] = v;
+  auto put = [&](int j, float v) {
+    if (f16) {
+      const size_t at = rhs_at(hs, j, o.ncp);
+      const float sv = v * scale;
+      const _Float16 h = (_Float16)sv;
+      const _Float16 l = (_Float16)(sv - (float)h);
+      o.Vh[at] = h;
+      if (packed) o.Vh[at + kChunk] = l;  // slot hs + 1 of the same chunk
+      else o.Vl[at] = l;
+    } else {
+      o.Vp[rhs_at(c, j, o.ncp)] = v;
+    }
+  };
+  // the footprint of pixel I: fine point (ss Iy + ty - r, ss Ix + tx - r) has weight g[ty] g[tx] / ss^2
+  auto footprint = [&](int I, bool zero) {
+    const int Iy = I / n, Ix = I - Iy * n;
+    for (int t = threadIdx.x; t < L * L; t += blockDim.x) {
+      const int ty = t / L, tx = t - ty * L;
+      const int fy = ss * Iy + ty - r, fx = ss * Ix + tx - r;
+      if (fy < 0 || fy >= M || fx < 0 || fx >= M) continue;
+      put(o.irank[fy * M + fx], zero ? 0.f : (taps.g[ty] * taps.g[tx]) * inv_ss2);
+    }
+  };
+  const int old = prev[c], now = cand[c];
+  if (old >= 0) footprint(old, true);
+  __syncthreads();  // a footprint shared by both is written after it was cleared
+  if (now >= 0) footprint(now, false);
+  if (threadIdx.x == 0) prev[c] = now;
 }
 
 // Ct (FP64, kPcBlock x npix, ld kPcBlock: the residual block stored by pixel
@@ -463,6 +496,11 @@ __global__ __launch_bounds__(kNcRows) void new_columns_kernel(int npix, const do
   for (int u = 0; u < kPcBlock; ++u) Lnew[(size_t)u * ldl + i] = x[u];
 }
 
+__global__ void set_ints_kernel(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __global__ void zero_ints_kernel(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -491,12 +529,12 @@ __global__ void logdet_p_kernel(int n, int k, double s, const double* logdet_g, 
 // ---------------------------------------------------------------- build workspace
 
 struct PcBuf {
-  float *T1, *T2, *Mc;
+  float *T2, *Mc;
   double *C, *Lc, *R, *d, *dmax, *logdet_g, *split;
   double *Y, *W, *T, *Dinv, *ld_part, *split2;  // G and its bordered inverse (on the side stream)
   size_t split2_elems;
   size_t split_elems;  // doubles of split
-  int *cand, *order, *taken, *info, *is_piv;
+  int *cand, *prev, *order, *taken, *info, *is_piv;
   void* mvm_ws;
   size_t mvm_bytes;
   void *blas, *blas2;
@@ -505,7 +543,6 @@ struct PcBuf {
 template <class Cv>
 static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   const int ldf = round_up(N, 64);
-  b.T1 = c.template take<float>((size_t)ldf * kPcBlock);
   b.T2 = c.template take<float>((size_t)ldf * kPcBlock);
   b.Mc = c.template take<float>((size_t)npix * kPcBlock);
   b.C = c.template take<double>((size_t)npix * kPcBlock);
@@ -525,6 +562,7 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.split2 = c.template take<double>(b.split2_elems);
   b.blas2 = c.template take<char>(kBlasScratch);
   b.cand = c.template take<int>(kPcBlock);
+  b.prev = c.template take<int>(kPcBlock);
   b.order = c.template take<int>(kPcBlock);
   b.taken = c.template take<int>(1);
   b.info = c.template take<int>(1);
@@ -1011,6 +1049,10 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
     hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, b.is_piv, npix);
     GPL_LAUNCH_CHECK();
     const int ldf = round_up(N, 64);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(kPcBlock), 0, stream, b.prev, kPcBlock, -1);
+    GPL_LAUNCH_CHECK();
+    const RhsOut rhs{prec, kPcBlock, mv.bufs.ncp, mv.bufs.Vh, mv.bufs.Vl, mv.bufs.Vp, mv.bufs.inv_scale, nullptr, 0,
+                     mv.plan.irank};
     const SpdScratch sw{b.Y, b.W, b.T, b.Dinv, b.ld_part, b.split2, b.split2_elems};
     // on the side stream, once block jb of the factor is in: rows jb .. jb + 63
     // of G = L^T L (up to column jb + 63), then the bordered inverse of
@@ -1035,10 +1077,9 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
       hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
       GPL_LAUNCH_CHECK();
       // columns of B K B^T at the candidates (the matrix-free product)
-      hipLaunchKernelGGL(unit_adjoint_kernel, dim3(cdiv(N, 256), kPcBlock), dim3(256), 0, stream, n, ss, taps,
-                         b.cand, b.T1, ldf);
+      hipLaunchKernelGGL(unit_rhs_kernel, dim3(kPcBlock), dim3(256), 0, stream, n, ss, taps, b.cand, b.prev, rhs);
       GPL_LAUNCH_CHECK();
-      GPL_TRY(mvm_run(mv, kPcBlock, b.T1, ldf, b.T2, ldf, 0.f, CgGate{}, stream));
+      GPL_TRY(mvm_run_prepared(mv, kPcBlock, b.T2, ldf, 0.f, CgGate{}, stream));
       GPL_TRY(psf_forward_launch(n, ss, taps, kPcBlock, b.T2, ldf, b.Mc, npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr,
                                  0, nullptr, CgGate{}, stream));
       hipLaunchKernelGGL(widen_kernel, dim3(cdiv(npix * kPcBlock, 256)), dim3(256), 0, stream, npix, b.Mc, b.C);
