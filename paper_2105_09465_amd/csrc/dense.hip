@@ -171,14 +171,14 @@ int border_step(rocblas_handle h, double* G, int ldg, int j0, double shift, cons
   GPL_REQUIRE(j0 >= 0 && j0 % kSpd == 0, "block start %d must be a multiple of %d", j0, kSpd);
   const double one = 1.0, minus_one = -1.0, zero = 0.0;
   const auto N = rocblas_operation_none, Tr = rocblas_operation_transpose;
-  double* Gb = G + j0;                      // G[b, :b] (read), then Ginv[b, :b]
+  double* Gb = G + j0;                      // Ginv[b, :b]
   double* Gbb = G + (size_t)j0 * ldg + j0;  // G[b, b], then Ginv[b, b]
-  double* Gcol = G + (size_t)j0 * ldg;      // Ginv[:b, b]
+  double* Gcol = G + (size_t)j0 * ldg;      // G[:b, b] = G[b, :b]^T (read), then Ginv[:b, b]
   if (j0 > 0) {
     // Y = G[b, :b] Ginv[:b, :b];  T = Y G[b, :b]^T = G[b, :b] Ginv G[b, :b]^T
-    GPL_TRY(split_gemm(h, N, N, kSpd, j0, j0, std::max(1, std::min(16, j0 / 256)), 1.0, Gb, ldg, G, ldg, 0.0, w.Y,
+    GPL_TRY(split_gemm(h, Tr, N, kSpd, j0, j0, std::max(1, std::min(16, j0 / 256)), 1.0, Gcol, ldg, G, ldg, 0.0, w.Y,
                        kSpd, w.split, w.split_elems, stream));
-    GPL_TRY(split_gemm(h, N, Tr, kSpd, kSpd, j0, std::max(1, j0 / 64), 1.0, w.Y, kSpd, Gb, ldg, 0.0, w.T, kSpd,
+    GPL_TRY(split_gemm(h, N, N, kSpd, kSpd, j0, std::max(1, j0 / 64), 1.0, w.Y, kSpd, Gcol, ldg, 0.0, w.T, kSpd,
                        w.split, w.split_elems, stream));
   }
   hipLaunchKernelGGL(spd_block_kernel, dim3(1), dim3(256), 0, stream, Gbb, ldg, shift, j0 > 0 ? w.T : nullptr,

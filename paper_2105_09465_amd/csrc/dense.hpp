@@ -41,12 +41,12 @@ constexpr size_t kBlasScratch = size_t(32) << 20;
 // W = D^{-1} Y and
 //   inverse = [[A^{-1} + W^T W, -(D^{-T} W)^T], [-D^{-T} W, S^{-1}]],
 //   ln|G| = ln|A| + ln|S|.
-// G is column-major (ldg). border_step(j0) reads rows j0 .. j0 + 63 of G up to
-// column j0 + 63 (the diagonal block from its lower triangle) and the inverse of
-// the leading j0 x j0 block left in place by the earlier steps, and writes the
-// inverse of the leading (j0 + 64) block in place (both triangles); rows below
-// are neither read nor written, so they may be filled in while earlier steps
-// run. border_begin sets *info = 0; a step sets it (if still 0) to 1 + the index
+// G is column-major (ldg). border_step(j0) reads columns j0 .. j0 + 63 of G
+// down to row j0 + 63 (the diagonal block from its lower triangle) and the
+// inverse of the leading j0 x j0 block left in place by the earlier steps, and
+// writes the inverse of the leading (j0 + 64) block in place (both triangles);
+// later columns are neither read nor written, so they may be filled in while
+// earlier steps run. border_begin sets *info = 0; a step sets it (if still 0) to 1 + the index
 // of the first pivot of its diagonal block that was not positive (the inverse is
 // then meaningless); border_finish writes *logdet = ln|G + shift I| (the blocks'
 // parts summed in a fixed order).

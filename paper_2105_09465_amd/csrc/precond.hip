@@ -1054,8 +1054,8 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
     const RhsOut rhs{prec, kPcBlock, mv.bufs.ncp, mv.bufs.Vh, mv.bufs.Vl, mv.bufs.Vp, mv.bufs.inv_scale, nullptr, 0,
                      mv.plan.irank};
     const SpdScratch sw{b.Y, b.W, b.T, b.Dinv, b.ld_part, b.split2, b.split2_elems};
-    // on the side stream, once block jb of the factor is in: rows jb .. jb + 63
-    // of G = L^T L (up to column jb + 63), then the bordered inverse of
+    // on the side stream, once block jb of the factor is in: columns jb .. jb +
+    // 63 of G = L^T L (down to row jb + 63), then the bordered inverse of
     // sigma^2 I + G up to that block. The caller's stream records an event
     // after every kSideEvery-th block (a record drains that stream's queue, ~40
     // us), and the side work of the blocks up to it is enqueued after the next
@@ -1063,8 +1063,8 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
     // fed.
     int pend_lo = 0, pend_hi = 0, pend_g = 0;  // blocks [pend_lo, pend_hi) are in, their side work not enqueued
     auto side_block = [&](int jb) -> int {
-      GPL_TRY(split_gemm(h2, rocblas_operation_transpose, rocblas_operation_none, kPcBlock, jb + kPcBlock, npix,
-                         kPcSplits, 1.0, L + (size_t)jb * ldl, ldl, L, ldl, 0.0, G + jb, ldg, b.split2,
+      GPL_TRY(split_gemm(h2, rocblas_operation_transpose, rocblas_operation_none, jb + kPcBlock, kPcBlock, npix,
+                         kPcSplits, 1.0, L, ldl, L + (size_t)jb * ldl, ldl, 0.0, G + (size_t)jb * ldg, ldg, b.split2,
                          b.split2_elems, s2));
       return border_step(h2, G, ldg, jb, sig2, sw, info, s2);
     };
