@@ -146,20 +146,19 @@ __device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* 
   __shared__ double s_alpha;
   __shared__ int s_ok;
   if (bx == 0 && c == 0 && threadIdx.x == 0) *n_active_out = 0;
+  // this thread's vector entries and the p.Ap partials, loaded before the gate
+  // is read (always in bounds; unused when the column has stopped) so that the
+  // round trips overlap
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int ic = min(i, npix - 1);
+  const size_t iv = (size_t)c * ldv + ic;
+  const float xl = X[(size_t)c * ldx + ic], pl = P[iv], apl = AP[iv], rl = R[iv];
+  const double pap = threadIdx.x < 64 ? wave_fold_sum(pap_part + (size_t)c * ntiles, ntiles) : 0.0;
   if (*n_active_in == 0) return;
   const ColState st = sin[c];
   if (!st.active) return;
-  // this thread's vector entries, loaded while alpha is being formed
-  const int i = bx * blockDim.x + threadIdx.x;
-  const size_t iv = (size_t)c * ldv + i;
-  float xv = 0.f, pv = 0.f, apv = 0.f, rv = 0.f;
-  if (i < npix) {
-    xv = X[(size_t)c * ldx + i];
-    pv = P[iv];
-    apv = AP[iv];
-    rv = R[iv];
-  }
-  const double pap = threadIdx.x < 64 ? wave_fold_sum(pap_part + (size_t)c * ntiles, ntiles) : 0.0;
+  const bool in = i < npix;
+  const float xv = in ? xl : 0.f, pv = in ? pl : 0.f, apv = in ? apl : 0.f, rv = in ? rl : 0.f;
   if (threadIdx.x == 0) {
     const double a = st.rr / pap;
     const int ok = (pap > 0.0) && isfinite(a);
@@ -177,7 +176,7 @@ __device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* 
     const float af = (float)alpha;
     X[(size_t)c * ldx + i] = fmaf(af, pv, xv);
     const float r = fmaf(-af, apv, rv);
-    R[iv] = r;
+    R[(size_t)c * ldv + i] = r;
     s = (double)r * r;
   }
   s = block_sum_double(s, red);
@@ -203,19 +202,20 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
   __shared__ double s_beta;
   __shared__ int s_go;
   __shared__ float redm[4];
+  // this thread's vector entries and the r.r partials, loaded before the gate
+  // is read (always in bounds; unused when the column has stopped)
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int ic = min(i, npix - 1);
+  const float rl = R[(size_t)c * ldv + ic], pl = P[(size_t)c * ldv + ic];
+  const double rr_new = threadIdx.x < 64 ? wave_fold_sum(rr_part + (size_t)c * nb, nb) : 0.0;
   const ColState st = sin[c];
   if (*n_active_in == 0 || !st.active) {  // carry the state into the other parity
     if (bx == 0 && threadIdx.x == 0) sout[c] = st;
     return;
   }
-  const int i = bx * blockDim.x + threadIdx.x;
   const size_t iv = (size_t)c * ldv + i;
-  float rv = 0.f, pv = 0.f;
-  if (i < npix) {  // loaded while beta is being formed
-    rv = R[iv];
-    pv = P[iv];
-  }
-  const double rr_new = threadIdx.x < 64 ? wave_fold_sum(rr_part + (size_t)c * nb, nb) : 0.0;
+  const bool in = i < npix;
+  const float rv = in ? rl : 0.f, pv = in ? pl : 0.f;
   if (threadIdx.x == 0) {
     const ColState half = sout[c];  // alpha and bad written by update1
     const double beta = rr_new / st.rr;

@@ -50,6 +50,8 @@ static constexpr int kMaxCB = 4;            // up to 64 columns per pass
 
 static_assert(kRT * 16 == kRowTile, "row tile of 16-row MFMA tiles");
 
+static_assert(kWaves == kPlanWaves, "the plan orders workgroups of kPlanWaves waves");
+
 // ---------------------------------------------------------------- RHS preparation
 
 // Column-wise max |V| in two steps without atomics: kColmaxBlocks workgroups per
@@ -370,7 +372,8 @@ template <int CB, bool PK>
 __global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, const _Float16* __restrict__ Vh,
                                                         const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                         float* __restrict__ part, int pcols, int c0, CgGate gate) {
-  const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = plan_block(blockIdx.x, P.nw, P.wround) * kWaves +
+                __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   mvm_f16x3_wave<CB, PK>([&] { return gate.skip_all(); }, w, P, Vh, Vl, ncp, ncols, part, pcols, c0);
 }
 
@@ -429,7 +432,8 @@ template <int CB>
 __global__ __launch_bounds__(256) void mvm_f32_kernel(const TilePlan P, float s2, const float* __restrict__ Vp,
                                                       int ncp, int ncols, float* __restrict__ part, int pcols, int c0,
                                                       CgGate gate) {
-  const int w = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = plan_block(blockIdx.x, P.nw, P.wround) * kWaves +
+                __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   mvm_f32_wave<CB>([&] { return gate.skip_all(); }, w, P, s2, Vp, ncp, ncols, part, pcols, c0);
 }
 

@@ -203,14 +203,15 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
     const int Iy = ty * TP + oy, Ix = tx * TP + ox;
     I[u] = (o < TP * TP && Iy < n && Ix < n) ? Iy * n + Ix : -1;
   }
-  // unconditional loads at valid addresses (pixel 0, or this column of `in` for
-  // an absent operand), all issued after the indices are known; the values are
-  // only looked at where they are used (a select here would wait for them
-  // before the window loads are issued)
+  // unconditional loads at valid addresses (pixel 0 for a pixel past the grid),
+  // all issued after the indices are known; the values are only looked at where
+  // they are used (a select or a branch here would wait for them before the
+  // window loads are issued). An absent or unused operand (out when beta is 0)
+  // reads the same pixels of another, so it adds no memory traffic.
   {
-    const float* po = out + (size_t)c * ld_out;
     const float* pe = extra ? extra + (size_t)c * ld_extra : src;
-    const float* pd = dotv ? dotv + (size_t)c * ld_dotv : src;
+    const float* po = beta != 0.f ? out + (size_t)c * ld_out : pe;
+    const float* pd = dotv ? dotv + (size_t)c * ld_dotv : pe;
 #pragma unroll
     for (int u = 0; u < kOutPer; ++u) {
       const int Ic = max(I[u], 0);

@@ -205,8 +205,27 @@ int plan_sort(TilePlan& p, int n, const float* px, const float* py, hipStream_t 
 // Relative work of a wave in the first, second and later dispatch rounds.
 constexpr int kRounds = 3;
 constexpr int kRoundWeight[kRounds] = {16, 9, 4};
+constexpr int kPlanWaves = 4;  // waves per workgroup of a product launch
+constexpr int kXcds = 8;       // workgroup b of a launch runs on XCD b % kXcds
 
-// Weight of waves [0, w): sum over rounds of the round's weight x its waves below w.
+// Order of a launch's waves along the unit sequence. Workgroups are dispatched
+// in order, wround / kPlanWaves per round, round-robin over the XCDs. Within
+// each round the workgroups are permuted so that those an XCD takes hold one
+// contiguous eighth of the round's range: neighbouring row tiles then read
+// their right-hand-side chunks through one L2 instead of eight. A bijection on
+// every full group of kXcds workgroups of a round; the rest of a partial round
+// keeps its place. (One contiguous share of the whole sequence per XCD, the
+// rounds alternating in it, fetched more than this from HBM.)
+__host__ __device__ inline int plan_block(int b, int nw, int wround) {
+  const int R = wround / kPlanWaves;
+  const int r0 = b - b % R;
+  const int m = min(R, nw / kPlanWaves - r0) & ~(kXcds - 1);
+  const int i = b - r0;
+  return i < m ? r0 + (i % kXcds) * (m / kXcds) + i / kXcds : b;
+}
+
+// Weight of waves [0, w): sum over rounds of the round's weight x its waves below
+// w (the permutation of plan_block keeps every wave in its round).
 __host__ __device__ inline long long wave_weight_below(int w, int wround) {
   long long c = 0;
   for (int k = 0; k < kRounds; ++k) {
