@@ -26,28 +26,39 @@ constexpr int kMaxWin = kFineTile + 2 * GPL_PSF_MAX_RADIUS;
 // Row stride of the adjoint's x-convolved buffer: 40 = 8 (mod 32), so the 8 x 8
 // pixel block a wave reads in the Z-order walk falls on distinct LDS banks.
 constexpr int kAdjStride = 40;
-constexpr int kOutPer = kFineTile * kFineTile / 256;  // output pixels per thread of a forward tile
+constexpr int kOutPer = kFineTile * kFineTile / 256;  // output pixels per thread of a forward tile, at most
+// Output pixels per thread of a forward tile: (kFineTile / ss)^2 over 256 threads.
+__host__ __device__ inline int fwd_pixels_per_thread(int ss) { return ss == 1 ? kOutPer : 1; }
+static_assert(kFineTile * kFineTile / 4 <= 256, "a tile with ss >= 2 has at most 256 output pixels");
 
 // Dynamic LDS of the tiles (floats), sized for the PSF radius r and the
 // supersampling ss of the launch.
-__host__ __device__ inline int fwd_tile_dims(int r, int ss, int& TP, int& W) {
+// Forward: the composite taps (padded to a multiple of 4), the W x W fine window
+// and the x-filtered window stored transposed, [TP][LT] with an odd row stride.
+__host__ __device__ inline int fwd_tile_dims(int r, int ss, int& TP, int& W, int& LT) {
   TP = kFineTile / ss > 0 ? kFineTile / ss : 1;
   W = TP * ss + 2 * r;
-  return W * W + W * (TP + 1) + 2 * r + ss;
+  LT = W | 1;
+  return (2 * r + ss + 3) / 4 * 4 + W * W + TP * LT;
 }
-__host__ __device__ inline int adj_tile_dims(int r, int ss, int& WC, int& K) {
+// Adjoint: the taps by phase [ss][K4], the WC x WC pixel window with WCP = WC + 8
+// floats a row (the last 8 zero) and the x-filtered rows [WC + K4 - 1][kAdjStride]
+// (the last K4 - 1 zero). K = ceil(L / ss) pixels reach a fine point along an
+// axis, K4 is K rounded up to a multiple of 4.
+__host__ __device__ inline int adj_tile_dims(int r, int ss, int& WC, int& K4, int& WCP) {
   const int L = 2 * r + ss;
   WC = (kFineTile + 2 * r + ss - 2) / ss + 1;
-  K = (L - 1) / ss + 1;
-  return WC * WC + (WC + K - 1) * kAdjStride + ss + L;
+  K4 = ((L - 1) / ss + 4) / 4 * 4;
+  WCP = WC + 8;
+  return ss * K4 + WC * WCP + (WC + K4 - 1) * kAdjStride;
 }
 __host__ __device__ inline size_t fwd_lds_bytes(int r, int ss) {
-  int a, b;
-  return sizeof(float) * (size_t)fwd_tile_dims(r, ss, a, b);
+  int a, b, c;
+  return sizeof(float) * (size_t)fwd_tile_dims(r, ss, a, b, c);
 }
 __host__ __device__ inline size_t adj_lds_bytes(int r, int ss) {
-  int a, b;
-  return sizeof(float) * (size_t)adj_tile_dims(r, ss, a, b);
+  int a, b, c;
+  return sizeof(float) * (size_t)adj_tile_dims(r, ss, a, b, c);
 }
 
 // A W x W window (W <= kMaxWin) staged into LDS through registers: thread
@@ -63,27 +74,41 @@ struct WinRegs {
 
 __device__ __forceinline__ int clamp_idx(int v, int m) { return min(max(v, 0), m - 1); }
 
-// at(wy, wx, ok) returns the value at window position (wy, wx) read from the
-// nearest grid pixel, always at a valid address, and sets ok when the position
-// lies inside the window and the grid. Slots that are not ok are stored as 0 in
-// win_store: keeping the selection out of the load blocks lets all loads be in
-// flight together.
-template <class At>
-__device__ __forceinline__ void win_load(WinRegs& R, int W, At&& at) {
+// Window values are read from the nearest grid pixel, always at a valid
+// address; a slot's ok bit is set when its position lies inside the window and
+// the grid, and win_store stores the slots that are not ok as 0: keeping the
+// selection out of the load blocks lets all loads be in flight together. The
+// address and the in-grid test split into a row part row(wy, ok) (an element
+// offset from src) and a column part col(wx, ok), so that each slot costs one
+// address add; ok of a slot = ok of its row and of its column.
+template <class Row, class Col>
+__device__ __forceinline__ void win_load_sep(WinRegs& R, int W, const float* __restrict__ src, Row&& row, Col&& col) {
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  int coff[kWinCols];
+  unsigned cok = 0u;
+#pragma unroll
+  for (int m = 0; m < kWinCols; ++m) {
+    bool ok = false;
+    coff[m] = 32 * m < W ? col(lx + 32 * m, ok) : 0;
+    cok |= (ok ? 1u : 0u) << m;
+  }
   R.ok = 0u;
 #pragma unroll
   for (int k = 0; k < kWinRows; ++k)
+    if (8 * k < W) {
+      bool rok;
+      const float* p = src + row(ly + 8 * k, rok);
 #pragma unroll
-    for (int m = 0; m < kWinCols; ++m)
-      if (8 * k < W && 32 * m < W) {
-        bool ok;
-        R.v[k][m] = at(ly + 8 * k, lx + 32 * m, ok);
-        R.ok |= (ok ? 1u : 0u) << (k * kWinCols + m);
-      }
+      for (int m = 0; m < kWinCols; ++m)
+        if (32 * m < W) {
+          R.v[k][m] = p[coff[m]];
+          R.ok |= (rok && ((cok >> m) & 1u) ? 1u : 0u) << (k * kWinCols + m);
+        }
+    }
 }
 
-__device__ __forceinline__ void win_store(const WinRegs& R, int W, float* S) {
+// Row wy of the window goes to S + wy * stride.
+__device__ __forceinline__ void win_store(const WinRegs& R, int W, float* S, int stride) {
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
 #pragma unroll
   for (int k = 0; k < kWinRows; ++k)
@@ -91,7 +116,7 @@ __device__ __forceinline__ void win_store(const WinRegs& R, int W, float* S) {
     for (int m = 0; m < kWinCols; ++m)
       if (8 * k < W && 32 * m < W) {
         const int wy = ly + 8 * k, wx = lx + 32 * m;
-        if (wy < W && wx < W) S[wy * W + wx] = (R.ok >> (k * kWinCols + m)) & 1u ? R.v[k][m] : 0.f;
+        if (wy < W && wx < W) S[wy * stride + wx] = (R.ok >> (k * kWinCols + m)) & 1u ? R.v[k][m] : 0.f;
       }
 }
 
@@ -139,67 +164,79 @@ int make_taps(const gpl_grid* g, const gpl_psf* psf, Taps& t) {
   return GPL_OK;
 }
 
-// floor(v / ss) for 0 <= v < 2^15 and 1 <= ss <= 32, rss = 1 / ss in FP32:
-// (v + 1/2) / ss stays at least 1/64 away from an integer, far more than the
-// FP32 rounding of the product. Branch-free, so the loads it addresses are not
-// split into separately waited blocks.
-__device__ __forceinline__ int div_ss(int v, float rss) { return (int)(((float)v + 0.5f) * rss); }
-
-// Floor and ceiling of a / b for b > 0 and any sign of a.
-__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-__device__ __forceinline__ int ceil_div(int a, int b) { return -floor_div(-a, b); }
+// floor(v / d) for 0 <= v < 2^16 and 1 <= d <= 32, rd = 1 / d in FP32:
+// (v + 1/2) / d stays at least 1/64 away from an integer, more than the FP32
+// rounding of the product and of rd (together below 2^-7). Branch-free, so the
+// loads it addresses are not split into separately waited blocks.
+__device__ __forceinline__ int div_ss(int v, float rd) { return (int)(((float)v + 0.5f) * rd); }
 
 // Forward y pass for this thread's NU pixels o = tid + 256 u (a pixel past the
-// tile repeats the last one and is not used).
+// tile repeats the last one and is not used), from the transposed x-filtered
+// window S2T[ox][wy]: the taps of one pixel are consecutive, so four of them
+// are read with one base address.
 template <int NU>
-__device__ __forceinline__ void forward_ypass(const float* S2, const float* tg, int L, int LS, int ss, int TP,
-                                              float (&acc)[kOutPer]) {
-  const float* col[NU];
+__device__ __forceinline__ void forward_ypass(const float* S2T, const float* tg, int L, int LT, int ss, int TP,
+                                              float rTP, float (&acc)[NU]) {
+  int base[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
     const int o = min((int)threadIdx.x + u * 256, TP * TP - 1);
-    const int oy = o / TP, ox = o - oy * TP;
-    col[u] = S2 + ss * oy * LS + ox;
+    const int oy = div_ss(o, rTP), ox = o - oy * TP;
+    base[u] = ox * LT + ss * oy;
   }
-#pragma unroll 2
-  for (int k = 0; k < L; ++k) {
+  int k = 0;
+#pragma unroll 1
+  for (; k + 4 <= L; k += 4) {
+    const float4 w = *reinterpret_cast<const float4*>(tg + k);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const float* q = S2T + base[u] + k;
+      acc[u] = fmaf(w.x, q[0], acc[u]);
+      acc[u] = fmaf(w.y, q[1], acc[u]);
+      acc[u] = fmaf(w.z, q[2], acc[u]);
+      acc[u] = fmaf(w.w, q[3], acc[u]);
+    }
+  }
+  for (; k < L; ++k) {
     const float w = tg[k];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) acc[u] = fmaf(w, col[u][k * LS], acc[u]);
+    for (int u = 0; u < NU; ++u) acc[u] = fmaf(w, S2T[base[u] + k], acc[u]);
   }
 }
 
 // Forward: out[I] = alpha * (B in)[I] + beta * out[I] + gamma * extra[I];
 // optional FP64 partial sums of dotv[I] * out[I] per (column, tile).
 // `skip()` (uniform over the workgroup) is evaluated once the window loads are in
-// flight; when it is true the workgroup leaves without writing anything.
-template <class Skip>
+// flight; when it is true the workgroup leaves without writing anything. NU:
+// output pixels per thread, fwd_pixels_per_thread(ss).
+template <int NU, class Skip>
 __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
                                                  const float* __restrict__ in, int ld_in, float* __restrict__ out,
                                                  int ld_out, float alpha, float beta, const float* __restrict__ extra,
                                                  int ld_extra, float gamma, const float* __restrict__ dotv,
                                                  int ld_dotv, double* __restrict__ partial, int ntiles) {
-  extern __shared__ float psf_lds[];
+  extern __shared__ __align__(16) float psf_lds[];
   __shared__ double red[4];
   const int M = n * ss, r = taps.r, L = taps.L;
-  int TP, W;  // output pixels per tile side, window side
-  fwd_tile_dims(r, ss, TP, W);
-  const int F = TP * ss, LS = TP + 1;
-  float* const S1 = psf_lds;           // [W][W] fine window
-  float* const S2 = S1 + W * W;        // [W][LS] filtered along x
-  float* const tg = S2 + W * LS;       // [L] composite taps
+  int TP, W, LT;  // output pixels per tile side, window side, row stride of S2T
+  fwd_tile_dims(r, ss, TP, W, LT);
+  const int F = TP * ss;
+  const float rTP = 1.f / (float)TP;
+  float* const tg = psf_lds;                    // [L, padded to 4] composite taps
+  float* const S1 = tg + (L + 3) / 4 * 4;       // [W][W] fine window
+  float* const S2T = S1 + W * W;                // [TP][LT] filtered along x, transposed
   const int tiles_x = (n + TP - 1) / TP;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
   const float* src = in + (size_t)c * ld_in;
-  // this thread's output pixels (at most kOutPer) and their operands, loaded
-  // together with the window
-  int I[kOutPer];
-  float o_old[kOutPer], o_ext[kOutPer], o_dot[kOutPer];
+  // this thread's output pixels and their operands, loaded together with the
+  // window
+  int I[NU];
+  float o_old[NU], o_ext[NU], o_dot[NU];
 #pragma unroll
-  for (int u = 0; u < kOutPer; ++u) {
+  for (int u = 0; u < NU; ++u) {
     const int o = threadIdx.x + u * 256;
-    const int oy = o / TP, ox = o - oy * TP;
+    const int oy = div_ss(o, rTP), ox = o - oy * TP;
     const int Iy = ty * TP + oy, Ix = tx * TP + ox;
     I[u] = (o < TP * TP && Iy < n && Ix < n) ? Iy * n + Ix : -1;
   }
@@ -213,7 +250,7 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
     const float* po = beta != 0.f ? out + (size_t)c * ld_out : pe;
     const float* pd = dotv ? dotv + (size_t)c * ld_dotv : pe;
 #pragma unroll
-    for (int u = 0; u < kOutPer; ++u) {
+    for (int u = 0; u < NU; ++u) {
       const int Ic = max(I[u], 0);
       o_old[u] = po[Ic];
       o_ext[u] = pe[Ic];
@@ -222,29 +259,48 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
   }
   {
     WinRegs R;
-    win_load(R, W, [&](int wy, int wx, bool& ok) {
-      const int fy = fy0 - r + wy, fx = fx0 - r + wx;
-      ok = wy < W && wx < W && fy >= 0 && fy < M && fx >= 0 && fx < M;
-      return src[(size_t)clamp_idx(fy, M) * M + clamp_idx(fx, M)];
-    });
+    win_load_sep(
+        R, W, src,
+        [&](int wy, bool& ok) {
+          const int fy = fy0 - r + wy;
+          ok = wy < W && fy >= 0 && fy < M;
+          return clamp_idx(fy, M) * M;
+        },
+        [&](int wx, bool& ok) {
+          const int fx = fx0 - r + wx;
+          ok = wx < W && fx >= 0 && fx < M;
+          return clamp_idx(fx, M);
+        });
     if (skip()) return;
-    if ((int)threadIdx.x < L) tg[threadIdx.x] = taps.g[threadIdx.x];
-    win_store(R, W, S1);
+    if ((int)threadIdx.x < (L + 3) / 4 * 4) tg[threadIdx.x] = (int)threadIdx.x < L ? taps.g[threadIdx.x] : 0.f;
+    win_store(R, W, S1, W);
   }
   __syncthreads();
-  // x: S2[wy][ox] = sum_t g(t) S1[wy][ss ox + t + r], window rows wy < W, pixel
-  // columns ox < TP; three rows at a time share each tap
+  // x: S2T[ox][wy] = sum_t g(t) S1[wy][ss ox + t], window rows wy < W, pixel
+  // columns ox < TP; three outputs per thread share each group of four taps
   for (int o0 = threadIdx.x; o0 < W * TP; o0 += 3 * 256) {
     int at[3];
     float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int o = min(o0 + 256 * i, W * TP - 1);
-      const int wy = o / TP, ox = o - wy * TP;
+      const int wy = div_ss(o, rTP), ox = o - wy * TP;
       at[i] = wy * W + ss * ox;
     }
-#pragma unroll 2
-    for (int k = 0; k < L; ++k) {
+    int k = 0;
+#pragma unroll 1
+    for (; k + 4 <= L; k += 4) {
+      const float4 w = *reinterpret_cast<const float4*>(tg + k);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float* q = S1 + at[i] + k;
+        acc[i] = fmaf(w.x, q[0], acc[i]);
+        acc[i] = fmaf(w.y, q[1], acc[i]);
+        acc[i] = fmaf(w.z, q[2], acc[i]);
+        acc[i] = fmaf(w.w, q[3], acc[i]);
+      }
+    }
+    for (; k < L; ++k) {
       const float w = tg[k];
 #pragma unroll
       for (int i = 0; i < 3; ++i) acc[i] = fmaf(w, S1[at[i] + k], acc[i]);
@@ -253,22 +309,19 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
     for (int i = 0; i < 3; ++i) {
       const int o = o0 + 256 * i;
       if (o < W * TP) {
-        const int wy = o / TP, ox = o - wy * TP;
-        S2[wy * LS + ox] = acc[i];
+        const int wy = div_ss(o, rTP), ox = o - wy * TP;
+        S2T[ox * LT + wy] = acc[i];
       }
     }
   }
   __syncthreads();
-  // y: pixel (oy, ox) = sum_t g(t) S2[ss oy + t + r][ox] / ss^2
+  // y: pixel (oy, ox) = sum_t g(t) S2T[ox][ss oy + t] / ss^2
   const float inv_ss2 = 1.f / (float)(ss * ss);
-  float acc[kOutPer] = {};
-  if (TP * TP > 256)
-    forward_ypass<kOutPer>(S2, tg, L, LS, ss, TP, acc);
-  else
-    forward_ypass<1>(S2, tg, L, LS, ss, TP, acc);
+  float acc[NU] = {};
+  forward_ypass<NU>(S2T, tg, L, LT, ss, TP, rTP, acc);
   double dot = 0.0;
 #pragma unroll
-  for (int u = 0; u < kOutPer; ++u) {
+  for (int u = 0; u < NU; ++u) {
     if (I[u] < 0) continue;
     float res = alpha * (acc[u] * inv_ss2);
     if (beta != 0.f) res += beta * o_old[u];
@@ -282,13 +335,14 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
   }
 }
 
+template <int NU>
 __global__ __launch_bounds__(256) void psf_forward_kernel(int n, int ss, Taps taps, const float* __restrict__ in,
                                                           int ld_in, float* __restrict__ out, int ld_out,
                                                           float alpha, float beta, const float* __restrict__ extra,
                                                           int ld_extra, float gamma, const float* __restrict__ dotv,
                                                           int ld_dotv, double* __restrict__ partial, int ntiles,
                                                           CgGate gate) {
-  psf_forward_body([&] { return gate.skip(blockIdx.y); }, blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out, alpha, beta, extra, ld_extra, gamma,
+  psf_forward_body<NU>([&] { return gate.skip(blockIdx.y); }, blockIdx.x, blockIdx.y, n, ss, taps, in, ld_in, out, ld_out, alpha, beta, extra, ld_extra, gamma,
                    dotv, ld_dotv, partial, ntiles);
 }
 
@@ -302,26 +356,32 @@ template <bool ZWALK, class Skip, class Pre, class Fetch, class Store>
 __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, int n, int ss, const Taps& taps,
                                                  const float* __restrict__ in, int ld_in, Pre&& pre, Fetch&& fetch,
                                                  Store&& store) {
-  extern __shared__ float psf_lds[];
+  extern __shared__ __align__(16) float psf_lds[];
   const int M = n * ss, r = taps.r, L = taps.L;
-  int WC, K;  // window side in pixels; pixels that reach one fine point along an axis
-  adj_tile_dims(r, ss, WC, K);
+  int WC, K4, WCP;  // window side in pixels, taps per phase (padded), window row stride
+  adj_tile_dims(r, ss, WC, K4, WCP);
   static_assert(kFineTile == 32, "the Z-order decode below takes 5 bits per axis");
   const int F = kFineTile, LS = kAdjStride;
-  float* const S1 = psf_lds;                 // [WC][WC] pixel window
-  float* const S2 = S1 + WC * WC;            // [WC + K - 1][LS] filtered along x, zero rows at the end
-  float* const tz = S2 + (WC + K - 1) * LS;  // [ss + L]: ss zeros, then g
+  float* const T = psf_lds;           // [ss][K4] taps by phase
+  float* const S1 = T + ss * K4;      // [WC][WCP] pixel window
+  float* const S2 = S1 + WC * WCP;    // [WC + K4 - 1][LS] filtered along x
+  const float rss = 1.f / (float)ss;
+  // The pixels reaching fine point f along an axis are J(f) + k, k < K, with
+  // J(f) = floor((f - r) / ss); the weight of pixel J(f) + k is the composite
+  // tap g[q + 2r - ss k] (zero outside [0, L)), q = f - r - ss J(f) the phase.
+  // D, a multiple of ss above r, keeps the argument of the division positive.
+  const int D = ss * ((32 + ss - 1) / ss);
+  auto pix = [&](int f) { return div_ss(f - r + D, rss) - D / ss; };
   const int tiles_x = (M + F - 1) / F;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
-  // pixels whose composite filter reaches the tile: from ceil((f0 - ss + 1 - r) / ss) on, WC of them
-  const int cy0 = ceil_div(fy0 - ss + 1 - r, ss), cx0 = ceil_div(fx0 - ss + 1 - r, ss);
+  const int cy0 = pix(fy0), cx0 = pix(fx0);  // first pixel row and column of the window
   const float* src = in + (size_t)c * ld_in;
   const float inv_ss2 = 1.f / (float)(ss * ss);
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8 threads
   // the thread's points: position o = tid + 256 u of the walk
   constexpr int kPer = kFineTile * kFineTile / 256;
-  int px[kPer], py[kPer], b0[kPer];
+  int px[kPer], py[kPer], tb[kPer];
   const float* col[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -339,46 +399,61 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
     }
     px[u] = x;
     py[u] = y;
-    const int fy = fy0 + y;
-    const int ilo = ceil_div(fy - ss + 1 - r, ss) - cy0;
-    b0[u] = ss + (fy - ss * (cy0 + ilo)) + r;
-    col[u] = S2 + ilo * LS + x;
+    const int fy = fy0 + y, J = pix(fy);
+    tb[u] = (fy - r - ss * J) * K4;
+    col[u] = S2 + (J - cy0) * LS + x;
   }
   {
     WinRegs R;
-    win_load(R, WC, [&](int wy, int wx, bool& ok) {
-      const int iy = cy0 + wy, ix = cx0 + wx;
-      ok = wy < WC && wx < WC && iy >= 0 && iy < n && ix >= 0 && ix < n;
-      return src[(size_t)clamp_idx(iy, n) * n + clamp_idx(ix, n)];
-    });
+    win_load_sep(
+        R, WC, src,
+        [&](int wy, bool& ok) {
+          const int iy = cy0 + wy;
+          ok = wy < WC && iy >= 0 && iy < n;
+          return clamp_idx(iy, n) * n;
+        },
+        [&](int wx, bool& ok) {
+          const int ix = cx0 + wx;
+          ok = wx < WC && ix >= 0 && ix < n;
+          return clamp_idx(ix, n);
+        });
     if (skip()) return;
-    if ((int)threadIdx.x < ss + L) tz[threadIdx.x] = (int)threadIdx.x < ss ? 0.f : taps.g[threadIdx.x - ss];
-    for (int i = threadIdx.x; i < (K - 1) * LS; i += 256) S2[WC * LS + i] = 0.f;
+    for (int i = threadIdx.x; i < ss * K4; i += 256) {
+      const int q = i / K4, k = i - q * K4, t = q + 2 * r - ss * k;
+      T[i] = t >= 0 && t < L ? taps.g[t] : 0.f;
+    }
+    for (int i = threadIdx.x; i < WC * 8; i += 256) S1[(i >> 3) * WCP + WC + (i & 7)] = 0.f;
+    for (int i = threadIdx.x; i < (K4 - 1) * LS; i += 256) S2[WC * LS + i] = 0.f;
     pre();  // runs while the window loads are in flight
 #pragma unroll
     for (int u = 0; u < kPer; ++u) fetch(u, min(fy0 + py[u], M - 1), min(fx0 + px[u], M - 1));
-    win_store(R, WC, S1);
+    win_store(R, WC, S1, WCP);
   }
   __syncthreads();
-  // x: S2[wy][x] = sum_k g(t0 - ss k) S1[wy][jlo + k], the pixels jlo.. that reach
-  // fine column fx0 + x (weights past the last one are the zeros in front of g)
+  // x: S2[wy][x] = sum_k T[qx][k] S1[wy][jlo + k] for the pixels jlo + k that
+  // reach fine column fx0 + x (their reads stay inside the row's zero padding)
   {
-    const int fx = fx0 + lx;
-    const int jlo = ceil_div(fx - ss + 1 - r, ss) - cx0;
-    const int b0 = ss + (fx - ss * (cx0 + jlo)) + r;  // tz index of k = 0
+    const int fx = fx0 + lx, J = pix(fx);
+    const int jlo = J - cx0;
+    const float* tq = T + (fx - r - ss * J) * K4;
     const int nk = (WC + 7) / 8;
 #pragma unroll 1
     for (int k0 = 0; k0 < nk; k0 += 3) {
-      int wy[3];
+      int at[3];
       float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < 3; ++i) wy[i] = min(ly + 8 * (k0 + i), WC - 1);
-#pragma unroll 2
-      for (int k = 0; k < K; ++k) {
-        const float w = tz[b0 - ss * k];
-        const int j = min(jlo + k, WC - 1);
+      for (int i = 0; i < 3; ++i) at[i] = min(ly + 8 * (k0 + i), WC - 1) * WCP + jlo;
+#pragma unroll 1
+      for (int k = 0; k < K4; k += 4) {
+        const float4 w = *reinterpret_cast<const float4*>(tq + k);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) acc[i] = fmaf(w, S1[wy[i] * WC + j], acc[i]);
+        for (int i = 0; i < 3; ++i) {
+          const float* q = S1 + at[i] + k;
+          acc[i] = fmaf(w.x, q[0], acc[i]);
+          acc[i] = fmaf(w.y, q[1], acc[i]);
+          acc[i] = fmaf(w.z, q[2], acc[i]);
+          acc[i] = fmaf(w.w, q[3], acc[i]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -390,10 +465,17 @@ __device__ __forceinline__ void psf_adjoint_tile(Skip&& skip, int tile, int c, i
   __syncthreads();
   // y, for the points of the walk, four chains per thread
   float v[kPer] = {};
-#pragma unroll 2
-  for (int k = 0; k < K; ++k) {
+#pragma unroll 1
+  for (int k = 0; k < K4; k += 4) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) v[u] = fmaf(tz[b0[u] - ss * k], col[u][k * LS], v[u]);
+    for (int u = 0; u < kPer; ++u) {
+      const float4 w = *reinterpret_cast<const float4*>(T + tb[u] + k);
+      const float* q = col[u] + k * LS;
+      v[u] = fmaf(w.x, q[0], v[u]);
+      v[u] = fmaf(w.y, q[LS], v[u]);
+      v[u] = fmaf(w.z, q[2 * LS], v[u]);
+      v[u] = fmaf(w.w, q[3 * LS], v[u]);
+    }
   }
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -500,8 +582,13 @@ __global__ __launch_bounds__(256) void psf_forward_grouped_kernel(SlotBatch B, i
   const ServeSlotDev& S = *B.slot[s];
   const int local = blockIdx.x - B.off[s];
   const int tile = local % S.ntiles_fwd, c = local / S.ntiles_fwd;
-  psf_forward_body([&] { return S.n_active[p] == 0 || S.st[p][c].active == 0; }, tile, c, S.n, S.ss, S.taps, S.T2, S.ldf, S.AP, S.ldv, 1.f, 0.f, S.P, S.ldv, S.sigma2, S.P, S.ldv,
-                   S.pap_part, S.ntiles_fwd);
+  auto skip = [&] { return S.n_active[p] == 0 || S.st[p][c].active == 0; };
+  if (S.ss == 1)
+    psf_forward_body<kOutPer>(skip, tile, c, S.n, S.ss, S.taps, S.T2, S.ldf, S.AP, S.ldv, 1.f, 0.f, S.P, S.ldv,
+                              S.sigma2, S.P, S.ldv, S.pap_part, S.ntiles_fwd);
+  else
+    psf_forward_body<1>(skip, tile, c, S.n, S.ss, S.taps, S.T2, S.ldf, S.AP, S.ldv, 1.f, 0.f, S.P, S.ldv, S.sigma2,
+                        S.P, S.ldv, S.pap_part, S.ntiles_fwd);
 }
 
 int psf_adjoint_tiles(int n, int ss) {
@@ -558,9 +645,9 @@ int psf_forward_launch(int n, int ss, const Taps& taps, int nrhs, const float* i
                        int ld_dotv, double* partial, CgGate gate, hipStream_t stream) {
   GPL_TRY(check_psf_grid(n, ss));
   const int ntiles = psf_forward_tiles(n, ss);
-  hipLaunchKernelGGL(psf_forward_kernel, dim3(ntiles, nrhs), dim3(256), fwd_lds_bytes(taps.r, ss), stream, n, ss, taps,
-                     in, ld_in, out,
-                     ld_out, alpha, beta, extra, ld_extra, gamma, dotv, ld_dotv, partial, ntiles, gate);
+  auto kern = fwd_pixels_per_thread(ss) == 1 ? psf_forward_kernel<1> : psf_forward_kernel<kOutPer>;
+  hipLaunchKernelGGL(kern, dim3(ntiles, nrhs), dim3(256), fwd_lds_bytes(taps.r, ss), stream, n, ss, taps, in, ld_in,
+                     out, ld_out, alpha, beta, extra, ld_extra, gamma, dotv, ld_dotv, partial, ntiles, gate);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
