@@ -43,7 +43,7 @@ template <class C>
 static void carve_cg(C& c, int npix, int N, int nrhs, int prec, CgBuffers* b, size_t* mvm_bytes_out, int ss, int n) {
   const int ldv = round_up(npix, 64), ldf = round_up(N, 64);
   const size_t mvm_bytes = mvm_workspace(N, nrhs, prec);
-  const int ntiles = psf_forward_tiles(n, ss), nb_upd = cdiv(npix, 256);
+  const int ntiles = psf_forward_tiles(n, ss), nb_upd = cg_blocks(npix);
   float* R = c.template take<float>((size_t)ldv * nrhs);
   float* P = c.template take<float>((size_t)ldv * nrhs);
   float* AP = c.template take<float>((size_t)ldv * nrhs);
@@ -81,16 +81,19 @@ __global__ __launch_bounds__(256) void cg_init_kernel(int npix, const float* __r
   __shared__ double red[4];
   __shared__ float redm[4];
   const int c = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double s = 0.0;
   float m = 0.f;
-  if (i < npix) {
-    const float b = Bm[(size_t)c * ldb + i];
-    R[(size_t)c * ldv + i] = b;
-    P[(size_t)c * ldv + i] = b;
-    X[(size_t)c * ldx + i] = 0.f;
-    s = (double)b * b;
-    m = fabsf(b);
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e) {
+    const int i = blockIdx.x * kUpdSpan + e * 256 + threadIdx.x;
+    if (i < npix) {
+      const float b = Bm[(size_t)c * ldb + i];
+      R[(size_t)c * ldv + i] = b;
+      P[(size_t)c * ldv + i] = b;
+      X[(size_t)c * ldx + i] = 0.f;
+      s += (double)b * b;
+      m = fmaxf(m, fabsf(b));
+    }
   }
   s = block_sum_double(s, red);
   m = block_max(m, redm);
@@ -149,16 +152,22 @@ __device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* 
   // this thread's vector entries and the p.Ap partials, loaded before the gate
   // is read (always in bounds; unused when the column has stopped) so that the
   // round trips overlap
-  const int i = bx * blockDim.x + threadIdx.x;
-  const int ic = min(i, npix - 1);
-  const size_t iv = (size_t)c * ldv + ic;
-  const float xl = X[(size_t)c * ldx + ic], pl = P[iv], apl = AP[iv], rl = R[iv];
+  int i[kUpdPer];
+  float xv[kUpdPer], pv[kUpdPer], apv[kUpdPer], rv[kUpdPer];
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e) {
+    i[e] = bx * kUpdSpan + e * 256 + threadIdx.x;
+    const int ic = min(i[e], npix - 1);
+    const size_t iv = (size_t)c * ldv + ic;
+    xv[e] = X[(size_t)c * ldx + ic];
+    pv[e] = P[iv];
+    apv[e] = AP[iv];
+    rv[e] = R[iv];
+  }
   const double pap = threadIdx.x < 64 ? wave_fold_sum(pap_part + (size_t)c * ntiles, ntiles) : 0.0;
   if (*n_active_in == 0) return;
   const ColState st = sin[c];
   if (!st.active) return;
-  const bool in = i < npix;
-  const float xv = in ? xl : 0.f, pv = in ? pl : 0.f, apv = in ? apl : 0.f, rv = in ? rl : 0.f;
   if (threadIdx.x == 0) {
     const double a = st.rr / pap;
     const int ok = (pap > 0.0) && isfinite(a);
@@ -172,12 +181,16 @@ __device__ __forceinline__ void cg_update1_body(int bx, int c, int npix, float* 
   __syncthreads();
   const double alpha = s_alpha;
   double s = 0.0;
-  if (s_ok && i < npix) {
+  if (s_ok) {
     const float af = (float)alpha;
-    X[(size_t)c * ldx + i] = fmaf(af, pv, xv);
-    const float r = fmaf(-af, apv, rv);
-    R[(size_t)c * ldv + i] = r;
-    s = (double)r * r;
+#pragma unroll
+    for (int e = 0; e < kUpdPer; ++e)
+      if (i[e] < npix) {
+        X[(size_t)c * ldx + i[e]] = fmaf(af, pv[e], xv[e]);
+        const float r = fmaf(-af, apv[e], rv[e]);
+        R[(size_t)c * ldv + i[e]] = r;
+        s += (double)r * r;
+      }
   }
   s = block_sum_double(s, red);
   if (threadIdx.x == 0) rr_part[(size_t)c * nb + bx] = s;
@@ -204,18 +217,21 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
   __shared__ float redm[4];
   // this thread's vector entries and the r.r partials, loaded before the gate
   // is read (always in bounds; unused when the column has stopped)
-  const int i = bx * blockDim.x + threadIdx.x;
-  const int ic = min(i, npix - 1);
-  const float rl = R[(size_t)c * ldv + ic], pl = P[(size_t)c * ldv + ic];
+  int i[kUpdPer];
+  float rv[kUpdPer], pv[kUpdPer];
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e) {
+    i[e] = bx * kUpdSpan + e * 256 + threadIdx.x;
+    const size_t iv = (size_t)c * ldv + min(i[e], npix - 1);
+    rv[e] = R[iv];
+    pv[e] = P[iv];
+  }
   const double rr_new = threadIdx.x < 64 ? wave_fold_sum(rr_part + (size_t)c * nb, nb) : 0.0;
   const ColState st = sin[c];
   if (*n_active_in == 0 || !st.active) {  // carry the state into the other parity
     if (bx == 0 && threadIdx.x == 0) sout[c] = st;
     return;
   }
-  const size_t iv = (size_t)c * ldv + i;
-  const bool in = i < npix;
-  const float rv = in ? rl : 0.f, pv = in ? pl : 0.f;
   if (threadIdx.x == 0) {
     const ColState half = sout[c];  // alpha and bad written by update1
     const double beta = rr_new / st.rr;
@@ -261,11 +277,13 @@ __device__ __forceinline__ void cg_update2_body(int bx, int c, int npix, const f
   __syncthreads();
   if (!s_go) return;
   float m = 0.f;
-  if (i < npix) {
-    const float pn = fmaf((float)s_beta, pv, rv);
-    P[iv] = pn;
-    m = fabsf(pn);
-  }
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e)
+    if (i[e] < npix) {
+      const float pn = fmaf((float)s_beta, pv[e], rv[e]);
+      P[(size_t)c * ldv + i[e]] = pn;
+      m = fmaxf(m, fabsf(pn));
+    }
   m = block_max(m, redm);
   if (threadIdx.x == 0) pmax[(size_t)c * nb + bx] = __float_as_uint(m);
 }
@@ -304,8 +322,13 @@ __global__ __launch_bounds__(256) void cg_absmax_kernel(int npix, const float* _
                                                         unsigned* pmax, int nb) {
   __shared__ float redm[4];
   const int c = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const float m = block_max(i < npix ? fabsf(X[(size_t)c * ldx + i]) : 0.f, redm);
+  float m = 0.f;
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e) {
+    const int i = blockIdx.x * kUpdSpan + e * 256 + threadIdx.x;
+    if (i < npix) m = fmaxf(m, fabsf(X[(size_t)c * ldx + i]));
+  }
+  m = block_max(m, redm);
   if (threadIdx.x == 0) pmax[(size_t)c * nb + blockIdx.x] = __float_as_uint(m);
 }
 
@@ -315,11 +338,14 @@ __global__ __launch_bounds__(256) void cg_true_residual_kernel(int npix, const f
                                                                double* part, int nb) {
   __shared__ double red[4];
   const int c = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double s = 0.0;
-  if (i < npix) {
-    const double d = (double)Bm[(size_t)c * ldb + i] - (double)AX[(size_t)c * ldv + i];
-    s = d * d;
+#pragma unroll
+  for (int e = 0; e < kUpdPer; ++e) {
+    const int i = blockIdx.x * kUpdSpan + e * 256 + threadIdx.x;
+    if (i < npix) {
+      const double d = (double)Bm[(size_t)c * ldb + i] - (double)AX[(size_t)c * ldv + i];
+      s += d * d;
+    }
   }
   s = block_sum_double(s, red);
   if (threadIdx.x == 0) part[(size_t)c * nb + blockIdx.x] = s;
@@ -379,7 +405,7 @@ int cg_update_grouped(const ServeSlotDev* const* hslots, const ServeSlotDev* con
 int cg_init_launch(int npix, int nrhs, const float* Bm, int ldb, float* X, int ldx, float* R, float* P, int ldv,
                    double* part, ColState* st0, ColState* st1, double* bb, int* n_active, int limit, unsigned* pmax,
                    hipStream_t stream) {
-  const int nb = cdiv(npix, 256);
+  const int nb = cg_blocks(npix);
   hipLaunchKernelGGL(cg_init_kernel, dim3(nb, nrhs), dim3(256), 0, stream, npix, Bm, ldb, X, ldx, R, P, ldv, part, nb,
                      pmax);
   GPL_LAUNCH_CHECK();

@@ -70,6 +70,11 @@ struct ServeSlotDev {
 };
 
 constexpr int kMaxServeSlots = 64;
+// CG vector kernels: each workgroup of 256 threads takes kUpdPer entries per
+// thread, entries bx kUpdSpan + e 256 + t (e < kUpdPer), and writes one partial
+// (r.r, p.Ap, max |p|) per column.
+constexpr int kUpdPer = 4, kUpdSpan = 256 * kUpdPer;
+inline int cg_blocks(int npix) { return cdiv(npix, kUpdSpan); }
 constexpr int kColmaxBlocks = 32;  // workgroups per column of the column-max pass
 
 // Kernel argument naming the slots of one grouped launch: slot s owns the

@@ -43,7 +43,7 @@ static void carve_slot(Cv& cv, int n, int ss, int nrhs, int n_lanczos, int prec,
   const int ldv = round_up(npix, 64), ldf = round_up(N, 64);
   const int nrt = cdiv(N, kRowTile), ldh = nrt * kRowTile, ncp = cdiv(nrhs, 16) * 16;
   const bool f16 = prec == GPL_PREC_F16X3;
-  const int ntiles = psf_forward_tiles(n, ss), nb = cdiv(npix, 256);
+  const int ntiles = psf_forward_tiles(n, ss), nb = cg_blocks(npix);
   SlotBufs x;
   x.desc = cv.template take<ServeSlotDev>(1);
   x.px = cv.template take<float>(N);
@@ -174,7 +174,7 @@ extern "C" int gpl_serve_slot_init(gpl_serve_slot* slot, const gpl_problem* prob
   D.rr_part = b.rr;
   D.ntiles_fwd = psf_forward_tiles(n, ss);
   D.ntiles_adj = psf_adjoint_tiles(n, ss);
-  D.nb_upd = cdiv(npix, 256);
+  D.nb_upd = cg_blocks(npix);
   D.ab = b.ab;
   D.n_lanczos = n_lanczos;
   D.max_iter = max_iter;
