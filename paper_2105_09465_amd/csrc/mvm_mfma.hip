@@ -440,48 +440,83 @@ __global__ __launch_bounds__(256) void mvm_f32_kernel(const TilePlan P, float s2
 // ---------------------------------------------------------------- reduction
 
 // Y[c][perm[j]] = (amp2 * colscale[c]) * sum_q part[s0 + q][c][row] + beta Y over the
-// partial slots [s0, s0 + cnt) of row tile r = j / 64, in wave order.
+// partial slots [s0, s0 + cnt) of row tile r = j / 64, in wave order. A
+// workgroup takes 256 points and KC columns, c0 = cg KC on; each wave's 64
+// points are one row tile, so its slot range is uniform. KC = 4 halves the
+// instructions per entry of a large product; a small one, bound by latency,
+// runs faster with more waves (KC = 1).
 // `skip()` is evaluated once the slot range and the destination index are loaded.
-template <class Skip>
-__device__ __forceinline__ void reduce_body(Skip&& skip, int bx, int c, const TilePlan& P, int nrhs,
+template <int KC, class Skip>
+__device__ __forceinline__ void reduce_body(Skip&& skip, int bx, int cg, const TilePlan& P, int nrhs,
                                             const float* __restrict__ part, int pcols,
                                             const float* __restrict__ colscale, float amp2, float* Y, int ldy,
                                             float beta) {
-  const int j = bx * blockDim.x + threadIdx.x;
-  if (j >= P.n || c >= nrhs) return;
-  const int r = j / kRowTile, row = j - r * kRowTile;
+  const int j0 = bx * 256 + (int)(threadIdx.x & ~63u);  // the wave's first point
+  if (j0 >= P.n) return;
+  const int r = j0 / kRowTile, row = threadIdx.x & 63, j = j0 + row;
   const int2 sl = P.rslot[r];
-  const int dst = P.perm ? P.perm[j] : j;
+  const int dst = P.perm ? P.perm[min(j, P.n - 1)] : j;
+  const int c0 = cg * KC;
   if (skip()) return;
-  const float* p0 = part + ((size_t)sl.x * pcols + c) * kRowTile + row;
+  // the slot range is uniform over the wave; with one column a thread, the
+  // per-lane values keep the addresses independent of a wave-wide wait
+  const int s0 = KC > 1 ? __builtin_amdgcn_readfirstlane(sl.x) : sl.x;
+  const int cnt = KC > 1 ? __builtin_amdgcn_readfirstlane(sl.y) : sl.y;
   const size_t stride = (size_t)pcols * kRowTile;
-  // in slot order; the loads of each group of 8 are issued together. Past the
-  // last slot a load repeats it (always a valid address) and its value is not
-  // added: a load under a condition would be branched around and waited for on
-  // its own.
-  float s = 0.f;
-  const int last = max(sl.y - 1, 0);
-  for (int q = 0; q < sl.y; q += 8) {
-    float t[8];
+  const float* p0 = part + (size_t)s0 * stride + row;
+  int coff[KC];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = p0[(size_t)min(q + u, last) * stride];
+  for (int k = 0; k < KC; ++k) coff[k] = min(c0 + k, nrhs - 1) * kRowTile;
+  // in slot order; the loads of each group of 8 slots are issued together. Past
+  // the last slot (or column) a load repeats the last one (always a valid
+  // address) and its value is not added: a load under a condition would be
+  // branched around and waited for on its own.
+  float acc[KC] = {};
+  for (int q = 0; q < cnt; q += 8) {
+    float t[8][KC];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float* ps = p0 + (size_t)min(q + u, cnt - 1) * stride;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) t[u][k] = ps[coff[k]];
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (q + u < sl.y) s += t[u];
+      if (q + u < cnt)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc[k] += t[u][k];
   }
+  if (j >= P.n) return;
   // amp2 first, then the power-of-two column scale: the same bits as one
   // multiplication by amp2 * colscale while both are normal, and no subnormal
   // factor for a column whose scale is near the bottom of the float range
-  const float as = amp2 * s;
-  float* y = Y + (size_t)c * ldy + dst;
-  const float res = colscale ? as * colscale[c] : as;
-  *y = beta != 0.f ? res + beta * *y : res;
+  float res[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const float as = amp2 * acc[k];
+    res[k] = colscale ? as * colscale[min(c0 + k, nrhs - 1)] : as;
+  }
+  // Y is read only when beta is nonzero (two loops, so that the load is not
+  // speculated into the common beta = 0 case as an extra round trip)
+  if (beta == 0.f) {
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      if (c0 + k < nrhs) Y[(size_t)(c0 + k) * ldy + dst] = res[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      if (c0 + k < nrhs) {
+        float* y = Y + (size_t)(c0 + k) * ldy + dst;
+        *y = res[k] + beta * *y;
+      }
+  }
 }
 
+template <int KC>
 __global__ void reduce_kernel(const TilePlan P, int nrhs, const float* __restrict__ part, int pcols,
                               const float* __restrict__ colscale, float amp2, float* Y, int ldy, float beta,
                               CgGate gate) {
-  reduce_body([&] { return gate.skip_all(); }, blockIdx.x, blockIdx.y, P, nrhs, part, pcols, colscale, amp2, Y, ldy,
+  reduce_body<KC>([&] { return gate.skip_all(); }, blockIdx.x, blockIdx.y, P, nrhs, part, pcols, colscale, amp2, Y, ldy,
               beta);
 }
 
@@ -609,8 +644,11 @@ int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float
     GPL_LAUNCH_CHECK();
     timing_end(t0, stream);
   }
-  hipLaunchKernelGGL(reduce_kernel, dim3(cdiv(P.n, 256), nrhs), dim3(256), 0, stream, P, nrhs, b.part, nrhs,
-                     f16 ? b.inv_scale : nullptr, amp2, Y, ldy, beta, gate);
+  // four columns a thread when that still leaves eight workgroups per compute unit
+  const bool wide = (long)cdiv(P.n, 256) * cdiv(nrhs, 4) >= 8L * (P.wround / kWaves);
+  hipLaunchKernelGGL(wide ? reduce_kernel<4> : reduce_kernel<1>, dim3(cdiv(P.n, 256), cdiv(nrhs, wide ? 4 : 1)),
+                     dim3(256), 0, stream, P, nrhs, b.part, nrhs, f16 ? b.inv_scale : nullptr, amp2, Y, ldy, beta,
+                     gate);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }
@@ -651,7 +689,7 @@ __global__ void reduce_grouped_kernel(SlotBatch B, int p) {
   const ServeSlotDev& S = *B.slot[s];
   const int local = blockIdx.x - B.off[s];
   const int per = cdiv(S.N, 256);
-  reduce_body([&] { return S.n_active[p] == 0; }, local % per, local / per, S.plan, S.nrhs, S.part, S.nrhs,
+  reduce_body<1>([&] { return S.n_active[p] == 0; }, local % per, local / per, S.plan, S.nrhs, S.part, S.nrhs,
               S.prec == GPL_PREC_F16X3 ? S.inv_scale : nullptr, S.amp2, S.T2, S.ldf, 0.f);
 }
 
