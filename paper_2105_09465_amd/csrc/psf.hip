@@ -34,12 +34,13 @@ static_assert(kFineTile * kFineTile / 4 <= 256, "a tile with ss >= 2 has at most
 // Dynamic LDS of the tiles (floats), sized for the PSF radius r and the
 // supersampling ss of the launch.
 // Forward: the composite taps (padded to a multiple of 4), the W x W fine window
-// and the x-filtered window stored transposed, [TP][LT] with an odd row stride.
+// with rows of W rounded up to 4 floats, and the x-filtered window stored
+// transposed, [TP][LT] with an odd row stride.
 __host__ __device__ inline int fwd_tile_dims(int r, int ss, int& TP, int& W, int& LT) {
   TP = kFineTile / ss > 0 ? kFineTile / ss : 1;
   W = TP * ss + 2 * r;
   LT = W | 1;
-  return (2 * r + ss + 3) / 4 * 4 + W * W + TP * LT;
+  return (2 * r + ss + 3) / 4 * 4 + W * ((W + 3) / 4 * 4) + TP * LT;
 }
 // Adjoint: the taps by phase [ss][K4], the WC x WC pixel window with WCP = WC + 8
 // floats a row (the last 8 zero) and the x-filtered rows [WC + K4 - 1][kAdjStride]
@@ -223,8 +224,9 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
   const int F = TP * ss;
   const float rTP = 1.f / (float)TP;
   float* const tg = psf_lds;                    // [L, padded to 4] composite taps
-  float* const S1 = tg + (L + 3) / 4 * 4;       // [W][W] fine window
-  float* const S2T = S1 + W * W;                // [TP][LT] filtered along x, transposed
+  const int W4 = (W + 3) / 4 * 4;               // row stride of S1
+  float* const S1 = tg + (L + 3) / 4 * 4;       // [W][W4] fine window
+  float* const S2T = S1 + W * W4;               // [TP][LT] filtered along x, transposed
   const int tiles_x = (n + TP - 1) / TP;
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int fy0 = ty * F, fx0 = tx * F;
@@ -257,7 +259,30 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
       o_dot[u] = pd[Ic];
     }
   }
-  {
+  // A window inside the grid, W4 columns included, whose rows of W4 floats take
+  // at most four float4 loads a thread: staged by float4 (no clamps or masks).
+  // Any other window: by single floats with clamped addresses and masks.
+  const int wq = W4 >> 2, wtot = W * wq;
+  if (fy0 - r >= 0 && fy0 - r + W <= M && fx0 - r >= 0 && fx0 - r + W4 <= M && wtot <= 4 * 256) {
+    typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+    const float* base = src + (size_t)(fy0 - r) * M + (fx0 - r);
+    const float rq = 1.f / (float)wq;
+    f4u v[4];
+    int li[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u * 256 < wtot) {
+        const int i = min((int)threadIdx.x + u * 256, wtot - 1);
+        const int row = div_ss(i, rq), q = i - row * wq;
+        v[u] = *reinterpret_cast<const f4u*>(base + (size_t)row * M + 4 * q);
+        li[u] = row * W4 + 4 * q;
+      }
+    if (skip()) return;
+    if ((int)threadIdx.x < (L + 3) / 4 * 4) tg[threadIdx.x] = (int)threadIdx.x < L ? taps.g[threadIdx.x] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u * 256 < wtot) *reinterpret_cast<float4*>(S1 + li[u]) = float4{v[u][0], v[u][1], v[u][2], v[u][3]};
+  } else {
     WinRegs R;
     win_load_sep(
         R, W, src,
@@ -273,7 +298,7 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
         });
     if (skip()) return;
     if ((int)threadIdx.x < (L + 3) / 4 * 4) tg[threadIdx.x] = (int)threadIdx.x < L ? taps.g[threadIdx.x] : 0.f;
-    win_store(R, W, S1, W);
+    win_store(R, W, S1, W4);
   }
   __syncthreads();
   // x: S2T[ox][wy] = sum_t g(t) S1[wy][ss ox + t], window rows wy < W, pixel
@@ -285,7 +310,7 @@ __device__ __forceinline__ void psf_forward_body(Skip&& skip, int tile, int c, i
     for (int i = 0; i < 3; ++i) {
       const int o = min(o0 + 256 * i, W * TP - 1);
       const int wy = div_ss(o, rTP), ox = o - wy * TP;
-      at[i] = wy * W + ss * ox;
+      at[i] = wy * W4 + ss * ox;
     }
     int k = 0;
 #pragma unroll 1
