@@ -644,8 +644,10 @@ int mfma_product(const TilePlan& P, const ProdBufs& b, int prec, float s2, float
     GPL_LAUNCH_CHECK();
     timing_end(t0, stream);
   }
-  // four columns a thread when that still leaves eight workgroups per compute unit
-  const bool wide = (long)cdiv(P.n, 256) * cdiv(nrhs, 4) >= 8L * (P.wround / kWaves);
+  // four columns a thread when that still leaves sixteen workgroups per compute
+  // unit (measured: 64 columns at N = 160k 33.6 against 38.8 us with one column
+  // a thread; at N = 40k, where that gives ten, 24.5 against 22.9 us)
+  const bool wide = (long)cdiv(P.n, 256) * cdiv(nrhs, 4) >= 16L * (P.wround / kWaves);
   hipLaunchKernelGGL(wide ? reduce_kernel<4> : reduce_kernel<1>, dim3(cdiv(P.n, 256), cdiv(nrhs, wide ? 4 : 1)),
                      dim3(256), 0, stream, P, nrhs, b.part, nrhs, f16 ? b.inv_scale : nullptr, amp2, Y, ldy, beta,
                      gate);
