@@ -89,6 +89,7 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, do
   __shared__ double lz[2][kSpd];         // step p: D(a, p) for a > p, else 0
   __shared__ double Di[kSpd][kSpd + 1];  // Di[r][c] = Dinv(r, c)
   __shared__ double idg[kSpd];
+  __shared__ double pvs[kSpd];           // the pivots, for ln det after the loop
   const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int b0 = q * 16;
   double s[16];  // s[u] = S(a, b0 + u)
@@ -98,7 +99,6 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, do
     s[u] = (Gbb[(size_t)c * ldg + r] + (b == a ? shift : 0.0)) - (T ? T[(size_t)c * kSpd + r] : 0.0);
   }
   double dg = (Gbb[(size_t)a * ldg + a] + shift) - (T ? T[(size_t)a * kSpd + a] : 0.0);
-  double lsum = 0.0;
   int bad = -1;
   for (int p = 0; p < kSpd; ++p) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)__double_as_longlong(dg), p);
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, do
     const bool ok = dpp > 0.0 && isfinite(dpp);
     if (!ok && bad < 0) bad = p;
     const double pv = ok ? dpp : 1.0;
-    lsum += log(pv);  // ln D(p, p)^2
+    if (threadIdx.x == 0) pvs[p] = pv;  // ln D(p, p)^2 is summed after the loop
     const int buf = p & 1;
     if (q == p / 16) {  // this wave holds column p
       const int pu = p - b0;
@@ -127,6 +127,9 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, do
   }
   if (threadIdx.x < kSpd) idg[threadIdx.x] = 1.0 / lv[threadIdx.x][threadIdx.x];
   __syncthreads();
+  // sum over the pivots of ln D(p, p)^2: one logarithm a lane, a fixed-order
+  // butterfly over the wave
+  const double lsum = q == 0 ? warp_sum(log(pvs[a])) : 0.0;
   if (q == 0) {
     double x[kSpd];
 #pragma unroll
