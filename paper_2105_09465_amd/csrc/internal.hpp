@@ -23,6 +23,10 @@ struct CgGate {
   const int* n_active = nullptr;   // device scalar
   const int* col_active = nullptr; // device [nrhs], stride `stride` ints
   int stride = 1;
+  // products only: when set, a chunk c whose chunk_gen[c] differs from gen has
+  // a zero right-hand side in every column and is not evaluated
+  const int* chunk_gen = nullptr;
+  int gen = 0;
   // both flags are loaded together (one memory round trip, not two)
   __device__ bool skip(int c) const {
     const int na = n_active ? *n_active : 1;

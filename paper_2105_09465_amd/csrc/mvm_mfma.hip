@@ -270,10 +270,19 @@ struct F16Chunk {
   unsigned mask, lomask;
 };
 
-template <int CB, bool PK>
+// With FILT, a chunk whose generation differs from gen (its right-hand side is
+// zero in every column) gets an empty subtile mask, so its tiles are not
+// evaluated, and its loads read chunk 0 instead (they are still issued, which
+// keeps the wait counts exact, but hit in cache).
+template <int CB, bool PK, bool FILT = false>
 __device__ __forceinline__ void f16_load(F16Chunk<CB, PK>& c, const TilePlan& P, const _Float16* __restrict__ Vh,
-                                         const _Float16* __restrict__ Vl, int ncp, uint32_t entry, int ri, int g) {
+                                         const _Float16* __restrict__ Vl, int ncp, uint32_t entry, int ri, int g,
+                                         const int* __restrict__ cgen = nullptr, int gen = 0) {
   c.mask = entry_mask(entry);
+  if (FILT && cgen[entry_chunk(entry)] != gen) {
+    c.mask = 0u;
+    entry = 0u;
+  }
   c.lomask = entry_lomask(entry);
   c.cen = P.cen[entry_chunk(entry) / kChunksPerTile];  // uniform address, one vector load
   const int j0 = entry_chunk(entry) * kChunk + g * 8;
@@ -352,29 +361,33 @@ __device__ __forceinline__ void f16_compute(f32x4 (&acc)[kRT][CB], const F16Chun
   }
 }
 
-template <int CB, bool PK, class Skip>
+template <int CB, bool PK, bool FILT = false, class Skip>
 __device__ __forceinline__ void mvm_f16x3_wave(Skip&& skip, int w, const TilePlan& P, const _Float16* __restrict__ Vh,
                                                const _Float16* __restrict__ Vl, int ncp, int ncols,
-                                               float* __restrict__ part, int pcols, int c0) {
+                                               float* __restrict__ part, int pcols, int c0,
+                                               const int* __restrict__ cgen = nullptr, int gen = 0) {
   const int lane = threadIdx.x & 63, ri = lane & 15, g = lane >> 4;
   wave_product<CB, PK>(w, P, P.xc, P.yc, part, pcols, c0, ncols, skip,
                    [&](f32x4 (&acc)[kRT][CB], const float (&xi)[kRT], const float (&yi)[kRT], int r,
                        const uint32_t* lst, int kb, int ke, int lane) {
                      const float2 rcen = P.cen[r];
                      for_chunks_pf<F16Chunk<CB, PK>>(lst, kb, ke, lane,
-                         [&](F16Chunk<CB, PK>& c, uint32_t e) { f16_load(c, P, Vh, Vl, ncp, e, ri, g); },
+                         [&](F16Chunk<CB, PK>& c, uint32_t e) {
+                           f16_load<CB, PK, FILT>(c, P, Vh, Vl, ncp, e, ri, g, cgen, gen);
+                         },
                          [&](const F16Chunk<CB, PK>& c) { f16_compute(acc, c, xi, yi, rcen); });
                    });
 }
 
 // One wave per share of the plan's units; 4 independent waves per workgroup.
-template <int CB, bool PK>
+template <int CB, bool PK, bool FILT = false>
 __global__ __launch_bounds__(256) void mvm_f16x3_kernel(const TilePlan P, const _Float16* __restrict__ Vh,
                                                         const _Float16* __restrict__ Vl, int ncp, int ncols,
                                                         float* __restrict__ part, int pcols, int c0, CgGate gate) {
   const int w = plan_block(blockIdx.x, P.nw, P.wround) * kWaves +
                 __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  mvm_f16x3_wave<CB, PK>([&] { return gate.skip_all(); }, w, P, Vh, Vl, ncp, ncols, part, pcols, c0);
+  mvm_f16x3_wave<CB, PK, FILT>([&] { return gate.skip_all(); }, w, P, Vh, Vl, ncp, ncols, part, pcols, c0,
+                               gate.chunk_gen, gate.gen);
 }
 
 // ---------------------------------------------------------------- FP32 form
@@ -552,6 +565,13 @@ float plan_lo_threshold(int prec) { return prec == GPL_PREC_F16X3 ? kLoF16x3 : k
 template <int CB>
 static void launch_f16x3(bool packed, const TilePlan& P, const _Float16* Vh, const _Float16* Vl, int ncp,
                          int ncols, float* part, int pcols, int c0, CgGate gate, hipStream_t stream) {
+  if constexpr (CB == 4) {  // the chunk filter is built for the 64-column form only (elsewhere it is ignored)
+    if (gate.chunk_gen && !packed) {
+      hipLaunchKernelGGL((mvm_f16x3_kernel<4, false, true>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, Vh, Vl,
+                         ncp, ncols, part, pcols, c0, gate);
+      return;
+    }
+  }
   if (packed)
     hipLaunchKernelGGL((mvm_f16x3_kernel<CB, true>), dim3(P.nw / kWaves), dim3(256), 0, stream, P, Vh, Vl, ncp,
                        ncols, part, pcols, c0, gate);

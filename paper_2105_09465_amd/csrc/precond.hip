@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
 // ss^2 (non-negative taps summing to one) and splits it into FP16 hi (nearest)
 // and lo, as the CG loop's fused adjoint does. One workgroup per column.
 __global__ __launch_bounds__(256) void unit_rhs_kernel(int n, int ss, const Taps taps, const int* cand, int* prev,
-                                                       RhsOut o) {
+                                                       RhsOut o, int* chunk_gen, int gen) {
   const int c = blockIdx.x;
   const int M = n * ss, L = taps.L, r = taps.r;
   const bool f16 = o.prec == GPL_PREC_F16X3;
@@ -260,7 +260,9 @@ __global__ __launch_bounds__(256) void unit_rhs_kernel(int n, int ss, const Taps
       const int ty = t / L, tx = t - ty * L;
       const int fy = ss * Iy + ty - r, fx = ss * Ix + tx - r;
       if (fy < 0 || fy >= M || fx < 0 || fx >= M) continue;
-      put(o.irank[fy * M + fx], zero ? 0.f : (taps.g[ty] * taps.g[tx]) * inv_ss2);
+      const int j = o.irank[fy * M + fx];
+      put(j, zero ? 0.f : (taps.g[ty] * taps.g[tx]) * inv_ss2);
+      if (!zero) chunk_gen[j / kChunk] = gen;  // the product evaluates this chunk
     }
   };
   const int old = prev[c], now = cand[c];
@@ -535,6 +537,7 @@ struct PcBuf {
   size_t split2_elems;
   size_t split_elems;  // doubles of split
   int *cand, *prev, *order, *taken, *info, *is_piv;
+  int* chunk_gen;  // [chunks of the plan] the last block whose unit columns touch the chunk
   void* mvm_ws;
   size_t mvm_bytes;
   void *blas, *blas2;
@@ -567,6 +570,7 @@ static void carve_pc(Cv& c, int npix, int N, int k, int prec, PcBuf& b) {
   b.taken = c.template take<int>(1);
   b.info = c.template take<int>(1);
   b.is_piv = c.template take<int>(npix);
+  b.chunk_gen = c.template take<int>((size_t)kChunksPerTile * cdiv(N, kRowTile));
   b.mvm_bytes = mvm_workspace(N, kPcBlock, prec);
   b.mvm_ws = c.template take<char>(b.mvm_bytes);
   b.blas = c.template take<char>(kBlasScratch);
@@ -1048,6 +1052,9 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
     GPL_LAUNCH_CHECK();
     hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(npix, 256)), dim3(256), 0, stream, b.is_piv, npix);
     GPL_LAUNCH_CHECK();
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(mv.plan.nch, 256)), dim3(256), 0, stream, b.chunk_gen,
+                       mv.plan.nch);
+    GPL_LAUNCH_CHECK();
     const int ldf = round_up(N, 64);
     hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(kPcBlock), 0, stream, b.prev, kPcBlock, -1);
     GPL_LAUNCH_CHECK();
@@ -1077,9 +1084,15 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
       hipLaunchKernelGGL(select_top_kernel, dim3(1), dim3(kSelThreads), 0, stream, npix, b.d, b.cand);
       GPL_LAUNCH_CHECK();
       // columns of B K B^T at the candidates (the matrix-free product)
-      hipLaunchKernelGGL(unit_rhs_kernel, dim3(kPcBlock), dim3(256), 0, stream, n, ss, taps, b.cand, b.prev, rhs);
+      // the unit columns are zero outside their footprints: the product skips
+      // the chunks that no footprint of this block touches (generation j0 + 1)
+      hipLaunchKernelGGL(unit_rhs_kernel, dim3(kPcBlock), dim3(256), 0, stream, n, ss, taps, b.cand, b.prev, rhs,
+                         b.chunk_gen, j0 + 1);
       GPL_LAUNCH_CHECK();
-      GPL_TRY(mvm_run_prepared(mv, kPcBlock, b.T2, ldf, 0.f, CgGate{}, stream));
+      CgGate live;
+      live.chunk_gen = b.chunk_gen;
+      live.gen = j0 + 1;
+      GPL_TRY(mvm_run_prepared(mv, kPcBlock, b.T2, ldf, 0.f, live, stream));
       GPL_TRY(psf_forward_launch(n, ss, taps, kPcBlock, b.T2, ldf, b.Mc, npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr,
                                  0, nullptr, CgGate{}, stream));
       hipLaunchKernelGGL(widen_kernel, dim3(cdiv(npix * kPcBlock, 256)), dim3(256), 0, stream, npix, b.Mc, b.C);
