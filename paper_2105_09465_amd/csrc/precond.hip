@@ -24,6 +24,7 @@
 // first steps give the Lanczos tridiagonal of P^{-1/2} A P^{-1/2} with the
 // usual CG formulas, and rz0 = b^T P^{-1} b is each probe's quadrature weight.
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "dense.hpp"
@@ -409,8 +410,8 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
   }
 }
 
-// The block's new columns of L and the residual diagonal, one thread per pixel
-// row i:
+// The block's new columns of L and the residual diagonal, four lanes per pixel
+// row i (each holding 16 of the 64 entries):
 //   x[u] = C[i, order[u]] for u < taken (0 beyond), then x R^{-T}: forward
 //   substitution taken column by column, so that the updates of a row's
 //   remaining entries are independent (each entry still receives its updates
@@ -420,38 +421,44 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
 //   the solve would amplify), and R's row u at the block's u-th pivot (the
 //   computed columns of M are not exactly symmetric, so the solve alone would
 //   not return it);
-//   d -= sum_u x[u]^2 (in u order), clamped at 0, exactly 0 at the new pivots,
+//   d -= sum_u x[u]^2 (each lane's 16 in u order, then the quad in a fixed
+//   order), clamped at 0, exactly 0 at the new pivots,
 //   which are marked in is_piv; pivots[j0 + u] = the pixel of pivot u (-1 where
 //   none was taken).
-constexpr int kNcRows = 128;  // pixel rows per workgroup of the new-columns kernel
-__global__ __launch_bounds__(kNcRows) void new_columns_kernel(int npix, const double* __restrict__ Ct,
-                                                              const int* order, const int* taken,
-                                                              const double* __restrict__ R, const int* cand, double* d,
-                                                              int* is_piv, double* __restrict__ Lnew, int ldl,
-                                                              int* pivots, int j0) {
-  __shared__ double Rt[kPcBlock][kPcBlock];       // Rt[v][w] = entry (w, v) of R
-  __shared__ double rows[kNcRows][kPcBlock + 1];  // the workgroup's rows of the residual columns
-  __shared__ double idg[kPcBlock];
+constexpr int kNcPix = 64;  // pixels per workgroup of the new-columns kernel, four lanes each
+__global__ __launch_bounds__(256) void new_columns_kernel(int npix, const double* __restrict__ Ct,
+                                                          const int* order, const int* taken,
+                                                          const double* __restrict__ R, const int* cand, double* d,
+                                                          int* is_piv, double* __restrict__ Lnew, int ldl,
+                                                          int* pivots, int j0) {
+  __shared__ double Rz[kPcBlock][kPcBlock];       // Rz[v][w] = entry (w, v) of R for w > v, else 0
+  __shared__ double rows[kNcPix][kPcBlock + 1];   // the workgroup's rows of the residual columns
+  __shared__ double idg[kPcBlock], rdg[kPcBlock];  // 1 / R(v, v) and R(v, v)
   __shared__ int s_ord[kPcBlock], s_pix[kPcBlock];
   const int t = threadIdx.x;
   const int cnt = *taken;
-  const int r0 = blockIdx.x * kNcRows;
+  const int p0 = blockIdx.x * kNcPix;
   // the workgroup's rows are one contiguous stretch of Ct: coalesced loads, all
-  // issued before the first LDS store (element t + kNcRows k is row
-  // t / 64 + 2k, column t % 64; rows past npix read the last row)
-  static_assert(kNcRows == 2 * kPcBlock, "two rows per pass of the workgroup");
+  // issued before the first LDS store (element t + 256 k is row t / 64 + 4k,
+  // column t % 64; rows past npix read the last row)
+  static_assert(kNcPix * kPcBlock == 16 * 256, "sixteen elements a thread");
   {
-    double tmp[kPcBlock];
+    double tmp[16];
     const int cc = t & (kPcBlock - 1), rb = t / kPcBlock;
 #pragma unroll
-    for (int k = 0; k < kPcBlock; ++k) {
-      const int rr = min(r0 + rb + 2 * k, npix - 1);
-      tmp[k] = Ct[(size_t)rr * kPcBlock + cc];
-    }
+    for (int k = 0; k < 16; ++k) tmp[k] = Ct[(size_t)min(p0 + rb + 4 * k, npix - 1) * kPcBlock + cc];
 #pragma unroll
-    for (int k = 0; k < kPcBlock; ++k) rows[rb + 2 * k][cc] = tmp[k];
+    for (int k = 0; k < 16; ++k) rows[rb + 4 * k][cc] = tmp[k];
   }
-  for (int e = t; e < kPcBlock * kPcBlock; e += kNcRows) (&Rt[0][0])[e] = R[e];
+  for (int e = t; e < kPcBlock * kPcBlock; e += 256) {
+    const int v = e / kPcBlock, w = e - v * kPcBlock;
+    const double r = R[e];  // R is column-major: R[v * 64 + w] = entry (w, v)
+    (&Rz[0][0])[e] = w > v ? r : 0.0;
+    if (w == v) {
+      idg[v] = 1.0 / r;
+      rdg[v] = r;
+    }
+  }
   if (t < kPcBlock) {
     const int o = order[t];
     const int pix = t < cnt ? cand[o] : -1;
@@ -460,42 +467,67 @@ __global__ __launch_bounds__(kNcRows) void new_columns_kernel(int npix, const do
     if (blockIdx.x == 0 && pivots) pivots[j0 + t] = pix;
   }
   __syncthreads();
-  if (t < kPcBlock) idg[t] = 1.0 / Rt[t][t];
-  __syncthreads();
-  const int i = r0 + t;
-  if (i >= npix) return;
-  double x[kPcBlock];
+  // pixel i = p0 + t / 4; lane sub = t % 4 of its quad holds x[16 sub .. 16 sub + 15].
+  // Forward substitution x R = row (R upper triangular): at step v the owner
+  // lane of x[v] scales it by 1 / R(v, v), the quad takes it by a DPP broadcast,
+  // and every lane subtracts x[v] R(v, w) from its entries (zero for w <= v).
+  const int pl = t >> 2, sub = t & 3, i = p0 + pl;
+  double x[16];
 #pragma unroll
-  for (int u = 0; u < kPcBlock; ++u) x[u] = rows[t][s_ord[u]];  // order[] is a permutation
-#pragma unroll
-  for (int u = 0; u < kPcBlock; ++u) x[u] = u < cnt ? x[u] : 0.0;
-#pragma unroll
-  for (int v = 0; v < kPcBlock; ++v) {
-    x[v] *= idg[v];
-#pragma unroll
-    for (int w = v + 1; w < kPcBlock; ++w) x[w] = fma(-x[v], Rt[v][w], x[w]);
+  for (int k = 0; k < 16; ++k) {
+    const int u = 16 * sub + k;
+    x[k] = u < cnt ? rows[pl][s_ord[u]] : 0.0;  // order[] is a permutation
   }
+  // steps 16 ow .. 16 ow + 15, whose pivots lane ow holds (DPP quad_perm
+  // [ow, ow, ow, ow] is the control 0x55 ow)
+  auto steps = [&](auto owc) {
+    constexpr int ow = decltype(owc)::value;
+#pragma unroll
+    for (int vv = 0; vv < 16; ++vv) {
+      const int v = 16 * ow + vv;
+      if (sub == ow) x[vv] *= idg[v];
+      const unsigned long long xb = dpp_u64<0x55 * ow>((unsigned long long)__double_as_longlong(x[vv]));
+      const double xv = __longlong_as_double((long long)xb);
+      const double* rz = &Rz[v][16 * sub];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = fma(-xv, rz[k], x[k]);
+    }
+  };
+  steps(std::integral_constant<int, 0>{});
+  steps(std::integral_constant<int, 1>{});
+  steps(std::integral_constant<int, 2>{});
+  steps(std::integral_constant<int, 3>{});
   int pu = -1;
 #pragma unroll
   for (int u = 0; u < kPcBlock; ++u) pu = s_pix[u] == i ? u : pu;
-  if (is_piv[i]) {
+  const int ic = min(i, npix - 1);
+  if (is_piv[ic]) {
 #pragma unroll
-    for (int u = 0; u < kPcBlock; ++u) x[u] = 0.0;
+    for (int k = 0; k < 16; ++k) x[k] = 0.0;
   } else if (pu >= 0) {
 #pragma unroll
-    for (int u = 0; u < kPcBlock; ++u) x[u] = u < cnt ? Rt[u][pu] : 0.0;
+    for (int k = 0; k < 16; ++k) {
+      const int u = 16 * sub + k;
+      x[k] = u < cnt ? (u == pu ? rdg[u] : Rz[u][pu]) : 0.0;  // entry (pu, u) of R (zero for u > pu)
+    }
   }
-  double v = d[i];
+  double sq = 0.0;
 #pragma unroll
-  for (int u = 0; u < kPcBlock; ++u)
-    if (u < cnt) v -= x[u] * x[u];
-  if (pu >= 0) {
-    v = 0.0;
-    is_piv[i] = 1;
+  for (int k = 0; k < 16; ++k)
+    if (16 * sub + k < cnt) sq = fma(x[k], x[k], sq);
+  sq += __longlong_as_double((long long)dpp_u64<0xB1>((unsigned long long)__double_as_longlong(sq)));
+  sq += __longlong_as_double((long long)dpp_u64<0x4E>((unsigned long long)__double_as_longlong(sq)));
+  if (i >= npix) return;
+  if (sub == 0) {
+    double v = d[i] - sq;
+    if (pu >= 0) {
+      v = 0.0;
+      is_piv[i] = 1;
+    }
+    d[i] = v > 0.0 ? v : 0.0;
   }
-  d[i] = v > 0.0 ? v : 0.0;
 #pragma unroll
-  for (int u = 0; u < kPcBlock; ++u) Lnew[(size_t)u * ldl + i] = x[u];
+  for (int k = 0; k < 16; ++k) Lnew[(size_t)(16 * sub + k) * ldl + i] = x[k];
 }
 
 __global__ void set_ints_kernel(int* p, int n, int v) {
@@ -1109,7 +1141,7 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
                          kPcRelTol, b.order, b.taken, b.R);
       GPL_LAUNCH_CHECK();
       double* Lnew = L + (size_t)j0 * ldl;  // = C[:, order] R^{-T}, fixed rows, and the new residual diagonal
-      hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, kNcRows)), dim3(kNcRows), 0, stream, npix, b.C, b.order,
+      hipLaunchKernelGGL(new_columns_kernel, dim3(cdiv(npix, kNcPix)), dim3(256), 0, stream, npix, b.C, b.order,
                          b.taken, b.R, b.cand, b.d, b.is_piv, Lnew, ldl, pivots, j0);
       GPL_LAUNCH_CHECK();
       // side work of a group whose event was recorded at an earlier block
