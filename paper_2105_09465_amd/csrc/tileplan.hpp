@@ -212,10 +212,11 @@ constexpr int kXcds = 8;       // workgroup b of a launch runs on XCD b % kXcds
 // in order, wround / kPlanWaves per round, round-robin over the XCDs. Within
 // each round the workgroups are permuted so that those an XCD takes hold one
 // contiguous eighth of the round's range: neighbouring row tiles then read
-// their right-hand-side chunks through one L2 instead of eight. A bijection on
-// every full group of kXcds workgroups of a round; the rest of a partial round
-// keeps its place. (One contiguous share of the whole sequence per XCD, the
-// rounds alternating in it, fetched more than this from HBM.)
+// their right-hand-side chunks through one L2 instead of eight. The first
+// multiple of kXcds workgroups of a round are permuted among themselves; the
+// rest of a partial round keep their places. (One contiguous share of the whole
+// sequence per XCD, the rounds alternating in it, fetched more than this from
+// HBM.)
 __host__ __device__ inline int plan_block(int b, int nw, int wround) {
   const int R = wround / kPlanWaves;
   const int r0 = b - b % R;
