@@ -122,6 +122,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* wsum, int* total) {
 // and a top-down scan of the bins for the one where the count reaches the
 // number still needed), then an ordered compaction.
 constexpr int kSelThreads = 1024;
+constexpr int kSelCache = 16;  // keys a thread keeps in registers (n up to 16384)
 constexpr int kBinsPer = 2048 / kSelThreads;  // histogram bins per thread in the scans
 static_assert(kBinsPer * kSelThreads == 2048, "the threads cover the 2048 bins of a pass");
 __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const double* __restrict__ d, int* cand) {
@@ -134,6 +135,19 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
     const double v = d[i];
     return v > 0.0 ? __float_as_uint((float)v) : 0u;
   };
+  // thread t takes the index range [i0, i1) in every pass; with at most
+  // kSelCache indices a thread, their keys are loaded once, all together, and
+  // kept in registers (a loop of loads and LDS atomics would wait on each load)
+  const int per = cdiv(n, kSelThreads), i0 = min(n, t * per), i1 = min(n, i0 + per);
+  const bool cached = per <= kSelCache;
+  unsigned kc[kSelCache];
+  if (cached) {
+#pragma unroll
+    for (int e = 0; e < kSelCache; ++e) {
+      const double v = d[min(i0 + e, n - 1)];
+      kc[e] = (i0 + e < i1 && v > 0.0) ? __float_as_uint((float)v) : 0u;
+    }
+  }
   if (t == 0) {
     s_prefix = 0u;
     s_mask = 0u;
@@ -146,9 +160,17 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
     __syncthreads();
     const unsigned prefix = s_prefix, mask = s_mask;
     const int need = s_need;
-    for (int i = t; i < n; i += kSelThreads) {
-      const unsigned k = key(i);
-      if (k != 0u && (k & mask) == prefix) atomicAdd(&hist[(k >> sh) & (nb - 1)], 1);
+    if (cached) {
+#pragma unroll
+      for (int e = 0; e < kSelCache; ++e) {
+        const unsigned k = kc[e];
+        if (k != 0u && (k & mask) == prefix) atomicAdd(&hist[(k >> sh) & (nb - 1)], 1);
+      }
+    } else {
+      for (int i = i0; i < i1; ++i) {
+        const unsigned k = key(i);
+        if (k != 0u && (k & mask) == prefix) atomicAdd(&hist[(k >> sh) & (nb - 1)], 1);
+      }
     }
     __syncthreads();
     // thread t covers bins nb-1-kBinsPer*t-j, j < kBinsPer (top down); the
@@ -189,20 +211,27 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
   // the index range [i0, i1) so that positions follow index order
   const unsigned T = s_prefix;
   const int eq_take = s_need;
-  const int per = cdiv(n, kSelThreads), i0 = min(n, t * per), i1 = min(n, i0 + per);
   int above = 0, equal = 0;
-  for (int i = i0; i < i1; ++i) {
-    const unsigned k = key(i);
-    above += (k != 0u && k > T);
-    equal += (k != 0u && k == T);
+  if (cached) {
+#pragma unroll
+    for (int e = 0; e < kSelCache; ++e) {
+      const unsigned k = kc[e];  // 0 past i1
+      above += (k != 0u && k > T);
+      equal += (k != 0u && k == T);
+    }
+  } else {
+    for (int i = i0; i < i1; ++i) {
+      const unsigned k = key(i);
+      above += (k != 0u && k > T);
+      equal += (k != 0u && k == T);
+    }
   }
   int tot_eq;
   int eq_before = block_excl_scan(equal, wsum, &tot_eq);
   const int mine = above + max(0, min(equal, eq_take - eq_before));
   int total;
   int pos = block_excl_scan(mine, wsum, &total);
-  for (int i = i0; i < i1; ++i) {
-    const unsigned k = key(i);
+  auto emit = [&](int i, unsigned k) {
     bool take = false;
     if (k != 0u && k > T) {
       take = true;
@@ -211,6 +240,13 @@ __global__ __launch_bounds__(kSelThreads) void select_top_kernel(int n, const do
       ++eq_before;
     }
     if (take && pos < kPcBlock) cand[pos++] = i;
+  };
+  if (cached) {
+#pragma unroll
+    for (int e = 0; e < kSelCache; ++e)
+      if (i0 + e < i1) emit(i0 + e, kc[e]);
+  } else {
+    for (int i = i0; i < i1; ++i) emit(i, key(i));
   }
   for (int q = total + t; q < kPcBlock; q += kSelThreads) cand[q] = -1;
 }
@@ -350,13 +386,20 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
   const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int b0 = q * kPivCols;
   const int ca = cand[a];
+  // every load at a valid address (row 0 for a missing candidate) and issued
+  // together; a missing candidate's entries are zeroed afterwards (a load under
+  // a condition would be branched around and waited for on its own)
+  int cb[kPivCols];
+#pragma unroll
+  for (int u = 0; u < kPivCols; ++u) cb[u] = cand[b0 + u];
+  const double* crow = Ct + (size_t)max(ca, 0) * kPcBlock;
   double s[kPivCols];  // s[u] = entry (a, b0 + u)
 #pragma unroll
-  for (int u = 0; u < kPivCols; ++u) {
-    const int cb = cand[b0 + u];
-    s[u] = (ca >= 0 && cb >= 0) ? Ct[(size_t)ca * kPcBlock + b0 + u] : 0.0;
-  }
-  double dg = ca >= 0 ? Ct[(size_t)ca * kPcBlock + a] : 0.0;  // entry (a, a)
+  for (int u = 0; u < kPivCols; ++u) s[u] = crow[b0 + u];
+  double dg = crow[a];  // entry (a, a)
+#pragma unroll
+  for (int u = 0; u < kPivCols; ++u) s[u] = (ca >= 0 && cb[u] >= 0) ? s[u] : 0.0;
+  dg = ca >= 0 ? dg : 0.0;
   bool used = ca < 0, piv = false;
   const double tol = rel_tol * dmax[0];
   int cnt = 0;
