@@ -215,10 +215,21 @@ __global__ void split_sum_kernel(int m, int n, int nsplit, const double* __restr
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * n) return;
   const int r = e % m, c = e / m;
-  double v = 0.0;
-  for (int s = 0; s < nsplit; ++s) v += Wp[(size_t)s * m * n + e];
   double* y = C + (size_t)c * ldc + r;
-  *y = beta == 0.0 ? alpha * v : alpha * v + beta * *y;
+  const double y0 = beta == 0.0 ? 0.0 : *y;  // issued ahead of the split loads
+  // in split order; the loads of each group of 8 splits are issued together
+  // (past the last split a load repeats it, at a valid address, and is not added)
+  double v = 0.0;
+  const size_t mn = (size_t)m * n;
+  for (int s0 = 0; s0 < nsplit; s0 += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = Wp[(size_t)min(s0 + u, nsplit - 1) * mn + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s0 + u < nsplit) v += t[u];
+  }
+  *y = beta == 0.0 ? alpha * v : alpha * v + beta * y0;
 }
 
 size_t split_gemm_scratch(int m, int n, int nsplit) { return (size_t)nsplit * m * n * sizeof(double); }
