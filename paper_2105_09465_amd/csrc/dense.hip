@@ -252,14 +252,18 @@ int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int
   const rocblas_stride sa = ta == rocblas_operation_none ? (rocblas_stride)kc * lda : kc;
   const rocblas_stride sb = tb == rocblas_operation_none ? kc : (rocblas_stride)kc * ldb;
   const double one = 1.0, zero = 0.0;
-  if (nsplit > 1 &&
+  // splits of kc rows in one batched call; a shorter last split in a call of its own
+  const int nfull = last == kc ? nsplit : nsplit - 1;
+  if (nfull > 1 &&
       rocblas_dgemm_strided_batched(h, ta, tb, m, n, kc, &one, A, lda, sa, B, ldb, sb, &zero, scratch, m,
-                                    (rocblas_stride)m * n, nsplit - 1) != rocblas_status_success) {
+                                    (rocblas_stride)m * n, nfull) != rocblas_status_success) {
     set_error("rocblas_dgemm_strided_batched failed");
     return GPL_EHIP;
   }
-  if (rocblas_dgemm(h, ta, tb, m, n, last, &one, A + (size_t)(nsplit - 1) * sa, lda, B + (size_t)(nsplit - 1) * sb,
-                    ldb, &zero, scratch + (size_t)(nsplit - 1) * m * n, m) != rocblas_status_success) {
+  const int one_from = nfull > 1 ? nfull : 0;  // splits [one_from, nsplit) by plain calls
+  for (int s = one_from; s < nsplit; ++s)
+    if (rocblas_dgemm(h, ta, tb, m, n, s == nsplit - 1 ? last : kc, &one, A + (size_t)s * sa, lda, B + (size_t)s * sb,
+                      ldb, &zero, scratch + (size_t)s * m * n, m) != rocblas_status_success) {
     set_error("rocblas_dgemm (last split) failed");
     return GPL_EHIP;
   }
