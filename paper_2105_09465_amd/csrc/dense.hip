@@ -90,7 +90,9 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, do
   __shared__ double Di[kSpd][kSpd + 1];  // Di[r][c] = Dinv(r, c)
   __shared__ double idg[kSpd];
   __shared__ double pvs[kSpd];           // the pivots, for ln det after the loop
-  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
+  // the wave index as a scalar: the owner wave then picks its entry of column p
+  // by a register-relative move instead of a chain of selects
+  const int a = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b0 = q * 16;
   double s[16];  // s[u] = S(a, b0 + u)
 #pragma unroll
@@ -110,10 +112,7 @@ __global__ __launch_bounds__(256) void spd_block_kernel(double* Gbb, int ldg, do
     if (threadIdx.x == 0) pvs[p] = pv;  // ln D(p, p)^2 is summed after the loop
     const int buf = p & 1;
     if (q == p / 16) {  // this wave holds column p
-      const int pu = p - b0;
-      double sp = s[0];
-#pragma unroll
-      for (int u = 1; u < 16; ++u) sp = u == pu ? s[u] : sp;
+      const double sp = s[p - b0];
       const double r = rsqrt_f64(pv), lpp = pv * r;
       const double l = a == p ? lpp : (a > p ? sp * r : 0.0);
       lv[p][a] = l;

@@ -383,7 +383,9 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
   __shared__ double lv[kPcBlock][kPcBlock];  // lv[step][a]: l of each step
   __shared__ double lc[2][kPcBlock];         // l with the pivot's and used entries zeroed
   __shared__ int s_perm[kPcBlock];
-  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
+  // the wave index as a scalar: the owner wave then picks its entry of column p
+  // by a register-relative move instead of a chain of selects
+  const int a = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b0 = q * kPivCols;
   const int ca = cand[a];
   // every load at a valid address (row 0 for a missing candidate) and issued
@@ -413,10 +415,7 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
     const int p = __ffsll((unsigned long long)__ballot(key == kmax)) - 1;
     const int buf = step & 1;
     if (q == p / kPivCols) {  // this wave holds column p
-      const int pu = p - b0;
-      double sp = s[0];
-#pragma unroll
-      for (int u = 1; u < kPivCols; ++u) sp = u == pu ? s[u] : sp;
+      const double sp = s[p - b0];
       const double r = rsqrt_f64(v), lpp = v * r;
       const double l = a == p ? lpp : (used ? 0.0 : sp * r);
       lv[step][a] = l;
@@ -424,7 +423,7 @@ __global__ __launch_bounds__(64 * kPivWaves) void block_pivot_kernel(const doubl
       if (a == 0) s_perm[step] = p;
     }
     __syncthreads();
-    if (!used && a != p) {
+    {  // la = 0 at the pivot and the used rows: their entries stay as they are
       const double la = lc[buf][a];
 #pragma unroll
       for (int u = 0; u < kPivCols; ++u) s[u] -= la * lc[buf][b0 + u];
