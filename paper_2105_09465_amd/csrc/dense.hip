@@ -208,14 +208,16 @@ int border_finish(int k, const SpdScratch& w, double* logdet, hipStream_t stream
   return GPL_OK;
 }
 
-// C (m x n, ld ldc) = alpha * sum_s Wp[s] + beta C, the splits in order.
+// C (m x n, ld ldc) = alpha * sum_s Wp[s] + beta C, the splits in order; the
+// beta term's C(r, c) is Cf[r * n + c] widened when Cf is set.
 __global__ void split_sum_kernel(int m, int n, int nsplit, const double* __restrict__ Wp, double alpha, double beta,
-                                 double* C, int ldc) {
+                                 double* C, int ldc, const float* __restrict__ Cf) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * n) return;
   const int r = e % m, c = e / m;
   double* y = C + (size_t)c * ldc + r;
-  const double y0 = beta == 0.0 ? 0.0 : *y;  // issued ahead of the split loads
+  // issued ahead of the split loads
+  const double y0 = beta == 0.0 ? 0.0 : (Cf ? (double)Cf[(size_t)r * n + c] : *y);
   // in split order; the loads of each group of 8 splits are issued together
   // (past the last split a load repeats it, at a valid address, and is not added)
   double v = 0.0;
@@ -235,7 +237,7 @@ size_t split_gemm_scratch(int m, int n, int nsplit) { return (size_t)nsplit * m 
 
 int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int kdim, int nsplit,
                double alpha, const double* A, int lda, const double* B, int ldb, double beta, double* C, int ldc,
-               double* scratch, size_t scratch_elems, hipStream_t stream) {
+               double* scratch, size_t scratch_elems, hipStream_t stream, const float* Cf) {
   const size_t per = (size_t)m * n;
   GPL_REQUIRE(m > 0 && n > 0 && kdim > 0, "split product of empty size");
   GPL_REQUIRE(scratch_elems >= per, "split product scratch holds %zu doubles, one split needs %zu", scratch_elems,
@@ -267,7 +269,7 @@ int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int
     return GPL_EHIP;
   }
   hipLaunchKernelGGL(split_sum_kernel, dim3(cdiv(m * n, 256)), dim3(256), 0, stream, m, n, nsplit, scratch, alpha,
-                     beta, C, ldc);
+                     beta, C, ldc, Cf);
   GPL_LAUNCH_CHECK();
   return GPL_OK;
 }

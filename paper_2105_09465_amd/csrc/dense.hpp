@@ -66,10 +66,11 @@ int border_finish(int k, const SpdScratch& w, double* logdet, hipStream_t stream
 // a sum in split order): GEMMs with one short side use the whole device this
 // way. scratch: split_gemm_scratch(m, n, nsplit) bytes; scratch_elems is the
 // number of doubles it holds, and nsplit is lowered to what fits (an error if
-// not even one split does).
+// not even one split does). With Cf set, the beta term reads C's entry (i, j)
+// from Cf[i * n + j] as a float (C transposed and narrower) instead of from C.
 size_t split_gemm_scratch(int m, int n, int nsplit);
 int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int kdim, int nsplit,
                double alpha, const double* A, int lda, const double* B, int ldb, double beta, double* C, int ldc,
-               double* scratch, size_t scratch_elems, hipStream_t stream);
+               double* scratch, size_t scratch_elems, hipStream_t stream, const float* Cf = nullptr);
 
 }  // namespace gpl

@@ -1169,15 +1169,16 @@ extern "C" int gpl_pchol(const gpl_problem* prob, int k, int prec, double* L, in
       GPL_TRY(mvm_run_prepared(mv, kPcBlock, b.T2, ldf, 0.f, live, stream));
       GPL_TRY(psf_forward_launch(n, ss, taps, kPcBlock, b.T2, ldf, b.Mc, npix, 1.f, 0.f, nullptr, 0, 0.f, nullptr,
                                  0, nullptr, CgGate{}, stream));
-      hipLaunchKernelGGL(widen_kernel, dim3(cdiv(npix * kPcBlock, 256)), dim3(256), 0, stream, npix, b.Mc, b.C);
-      GPL_LAUNCH_CHECK();
-      if (j0 > 0) {  // residual columns, by pixel rows: Ct -= L[cand, :j0] L[:, :j0]^T
+      if (j0 == 0) {
+        hipLaunchKernelGGL(widen_kernel, dim3(cdiv(npix * kPcBlock, 256)), dim3(256), 0, stream, npix, b.Mc, b.C);
+        GPL_LAUNCH_CHECK();
+      } else {  // residual columns, by pixel rows: Ct = widened Mc^T - L[cand, :j0] L[:, :j0]^T
         hipLaunchKernelGGL(gather_rows_kernel, dim3(cdiv(kPcBlock * j0, 256)), dim3(256), 0, stream, j0, L, ldl,
                            b.cand, b.Lc);
         GPL_LAUNCH_CHECK();
         GPL_TRY(split_gemm(h, rocblas_operation_none, rocblas_operation_transpose, kPcBlock, npix, j0,
                            std::min(kPcSplits, std::max(1, j0 / 256)), -1.0, b.Lc, kPcBlock, L, ldl, 1.0, b.C,
-                           kPcBlock, b.split, b.split_elems, stream));
+                           kPcBlock, b.split, b.split_elems, stream, b.Mc));
       }
       hipLaunchKernelGGL(block_pivot_kernel, dim3(1), dim3(64 * kPivWaves), 0, stream, b.C, npix, b.cand, b.dmax,
                          kPcRelTol, b.order, b.taken, b.R);
