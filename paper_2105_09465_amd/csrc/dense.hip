@@ -265,7 +265,7 @@ int split_gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int
   for (int s = one_from; s < nsplit; ++s)
     if (rocblas_dgemm(h, ta, tb, m, n, s == nsplit - 1 ? last : kc, &one, A + (size_t)s * sa, lda, B + (size_t)s * sb,
                       ldb, &zero, scratch + (size_t)s * m * n, m) != rocblas_status_success) {
-    set_error("rocblas_dgemm (last split) failed");
+    set_error("rocblas_dgemm (split %d of %d) failed", s, nsplit);
     return GPL_EHIP;
   }
   hipLaunchKernelGGL(split_sum_kernel, dim3(cdiv(m * n, 256)), dim3(256), 0, stream, m, n, nsplit, scratch, alpha,
